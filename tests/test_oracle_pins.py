@@ -1,0 +1,601 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's formulas: each compares the oracle with an
+independent statement -- a textbook closed form, a value printed in the paper,
+Maxwell's definition of the fields from the potentials, an exact discrete
+propagator, or a hand-derived special case.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import extract as X
+from paper_2107_12437_amd import inputs as I
+
+C = 299792458.0
+EPS0 = 8.8541878128e-12
+K = 1.0 / (4.0 * math.pi * EPS0)
+E = I.E_CHARGE
+ME = I.M_E
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def gamma0(q, m, w0):
+    """Free-space energy decay rate of a Lorentz oscillator (Sec. 2.3)."""
+    return q * q * w0 * w0 / (6.0 * math.pi * EPS0 * C ** 3 * m)
+
+
+def one(kind, **kw):
+    ch = I.empty_charges(1)
+    ch["kind"][0] = kind
+    ch["q"][0] = kw.pop("q", E)
+    for k, v in kw.items():
+        ch[k][0] = v
+    return ch
+
+
+def pair(ch, x, t, kind=O.TOTAL):
+    return O.lw_pair(ch, 0, np.asarray(x, float), t, kind)
+
+
+# ----------------------------------------------------------------------------
+# printed constants
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("key", ["gamma0_q1_2pi200THz", "gamma0_q20_2pi200THz"])
+def test_gamma0_matches_printed(key):
+    g = GOLD[key]
+    s = g["setup"]
+    val = gamma0(s["q_e"] * E, s["m_over_me"] * ME, s["omega0"])
+    assert abs(val - g["value"]) <= 0.5 * 10 ** (math.floor(math.log10(g["value"])) - g["digits"] + 1)
+
+
+# ----------------------------------------------------------------------------
+# trajectories
+# ----------------------------------------------------------------------------
+
+def _families():
+    rng = np.random.default_rng(5)
+    w = I.workload_grid_mixed(grid_n=2, n_times=2)
+    ch = w["charges"]
+    uv = one(I.UNIFORM_VELOCITY, v=[0.2 * C, -0.1 * C, 0.05 * C], c0=[1e-9, 2e-9, 3e-9])
+    return [I.subset_charges(ch, [i]) for i in range(len(ch["kind"]))] + [uv]
+
+
+def test_kinematics_are_derivatives():
+    """v, a, jerk are the time derivatives of r, v, a (4th-order central differences)."""
+    for ch in _families():
+        w = ch["omega"][0] if ch["omega"][0] else 1e15
+        h = 1e-3 / w
+        for t in (0.3e-15, 0.71e-15):
+            f = [O.kinematics(ch, 0, t + k * h) for k in (-2, -1, 1, 2)]
+            r, v, a, j = O.kinematics(ch, 0, t)
+            for lvl, ref in ((0, v), (1, a), (2, j)):
+                fd = (8 * (f[2][lvl] - f[1][lvl]) - (f[3][lvl] - f[0][lvl])) / (12 * h)
+                scale = max(np.linalg.norm(ref), 1e-300)
+                assert np.linalg.norm(fd - ref) <= 1e-7 * scale + 1e-30, (ch["kind"][0], lvl)
+
+
+def test_circular_orbit_geometry():
+    ch = I.workload_tiny_orbit()["charges"]
+    R, w = ch["amp"][0], ch["omega"][0]
+    for t in np.linspace(0, 1e-15, 7):
+        r, v, a, _ = O.kinematics(ch, 0, t)
+        assert abs(np.linalg.norm(r) - R) < 1e-15 * R
+        assert abs(np.linalg.norm(v) - 0.3 * C) < 1e-12 * C
+        assert abs(np.linalg.norm(a) - R * w * w) < 1e-12 * R * w * w
+        assert abs(np.dot(r, v)) < 1e-12 * R * C
+
+
+# ----------------------------------------------------------------------------
+# retarded time, Eq. (ret_t)
+# ----------------------------------------------------------------------------
+
+def test_retarded_static():
+    ch = one(I.STATIONARY, c0=[1e-9, -2e-9, 0.5e-9])
+    x = np.array([30e-9, 10e-9, -5e-9])
+    D = np.linalg.norm(x - ch["c0"][0])
+    assert abs(O.retarded_tau(ch, 0, x, 1e-15) - D / C) <= 2 * np.spacing(D / C)
+
+
+def test_retarded_uniform_velocity_closed_form():
+    """|w + v tau| = c tau for the present offset w is a quadratic in tau."""
+    v = np.array([0.4 * C, 0.2 * C, -0.1 * C])
+    ch = one(I.UNIFORM_VELOCITY, v=v, c0=[2e-9, 0, 0])
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        x = rng.uniform(-50e-9, 50e-9, 3)
+        t = rng.uniform(0, 1e-15)
+        w = x - (ch["c0"][0] + v * t)
+        wv, vv, ww = w @ v, v @ v, w @ w
+        tau = (wv + math.sqrt(wv * wv + (C * C - vv) * ww)) / (C * C - vv)
+        assert abs(O.retarded_tau(ch, 0, x, t) - tau) <= 4e-15 * tau
+
+
+def test_retarded_circular_axis():
+    """On the orbit axis the distance to the orbit is constant, so tau = D / c."""
+    ch = I.workload_tiny_orbit()["charges"]
+    R = ch["amp"][0]
+    for z in (0.0, 3e-9, 40e-9):
+        tau = O.retarded_tau(ch, 0, [0, 0, z], 7.3e-16)
+        D = math.hypot(R, z)
+        assert abs(tau - D / C) <= 4e-15 * D / C
+
+
+def test_retarded_residual_invariant():
+    """c tau = |x - r(t - tau)| to within a few ulp for every family, including the
+    kink of the accelerating charge at t' = 0."""
+    w = I.workload_grid_mixed(grid_n=9, n_times=4)
+    ch = w["charges"]
+    pts = w["points"]
+    for i in range(len(ch["kind"])):
+        for t in w["times"][[0, -1]]:
+            for p in range(0, pts.shape[1], 7):
+                x = pts[:, p]
+                tau = O.retarded_tau(ch, i, x, t)
+                r, *_ = O.kinematics(ch, i, t - tau)
+                res = C * tau - np.linalg.norm(x - r)
+                assert abs(res) <= 8 * np.spacing(C * tau), (i, p)
+    # an observer whose retarded time straddles the start of the acceleration
+    acc = one(I.ACCEL, accel=0.6 * C / 1e-15, e1=[1, 0, 0])
+    x = np.array([0.0, 100e-9, 0.0])
+    for t in (0.2e-15, 0.33e-15, 0.4e-15, 0.9e-15):
+        tau = O.retarded_tau(acc, 0, x, t)
+        r, *_ = O.kinematics(acc, 0, t - tau)
+        assert abs(C * tau - np.linalg.norm(x - r)) <= 8 * np.spacing(C * tau)
+
+
+# ----------------------------------------------------------------------------
+# potentials and fields
+# ----------------------------------------------------------------------------
+
+def test_static_coulomb():
+    ch = one(I.STATIONARY, c0=[1e-9, 0, 0])
+    x = np.array([4e-9, 4e-9, 0])
+    out = pair(ch, x, 0.0)
+    d = x - ch["c0"][0]
+    D = np.linalg.norm(d)
+    np.testing.assert_allclose(out[0], K * E / D, rtol=1e-15)
+    np.testing.assert_allclose(out[4:7], K * E * d / D ** 3, rtol=1e-15, atol=0)
+    assert np.all(out[1:4] == 0) and np.all(out[7:10] == 0)
+
+
+def test_listing1_stationary_pair_superposition():
+    """Listing 1: +e at (10 nm, 0, 0) and -e at (-10 nm, 0, 0); Coulomb's law summed."""
+    ch = I.concat_charges([one(I.STATIONARY, c0=[10e-9, 0, 0]), one(I.STATIONARY, c0=[-10e-9, 0, 0], q=-E)])
+    pts = I.plane_grid(50e-9, 12)
+    out, flags = O.fields(ch, pts, [0.0])
+    ref_phi = np.zeros(pts.shape[1])
+    ref_E = np.zeros((3, pts.shape[1]))
+    for q, cx in ((E, 10e-9), (-E, -10e-9)):
+        d = pts - np.array([[cx], [0], [0]])
+        D = np.linalg.norm(d, axis=0)
+        ref_phi += K * q / D
+        ref_E += K * q * d / D ** 3
+    np.testing.assert_allclose(out[0, 0], ref_phi, rtol=1e-13, atol=1e-13 * np.abs(ref_phi).max())
+    np.testing.assert_allclose(out[0, 4:7], ref_E, rtol=1e-13, atol=1e-13 * np.abs(ref_E).max())
+    assert flags.sum() == 0
+
+
+def test_uniform_velocity_fields_closed_form():
+    """Field of a uniformly moving charge at its present position (Heaviside):
+    E = kq (1 - b^2) / (1 - b^2 sin^2 psi)^{3/2} w / |w|^3, B = v x E / c^2,
+    Phi = kq / (|w| sqrt(1 - b^2 sin^2 psi)), A = v Phi / c^2."""
+    v = np.array([0.3 * C, -0.35 * C, 0.1 * C])
+    ch = one(I.UNIFORM_VELOCITY, v=v, c0=[0, 1e-9, 0])
+    b2 = v @ v / C ** 2
+    rng = np.random.default_rng(1)
+    for _ in range(30):
+        x = rng.uniform(-40e-9, 40e-9, 3)
+        t = rng.uniform(-1e-15, 1e-15)
+        w = x - (ch["c0"][0] + v * t)
+        W = np.linalg.norm(w)
+        sin2 = 1 - (w @ v) ** 2 / (W * W * (v @ v))
+        fac = 1 - b2 * sin2
+        Eref = K * E * (1 - b2) / fac ** 1.5 * w / W ** 3
+        phi = K * E / (W * math.sqrt(fac))
+        out = pair(ch, x, t)
+        np.testing.assert_allclose(out[0], phi, rtol=1e-13)
+        np.testing.assert_allclose(out[1:4], v * phi / C ** 2, rtol=1e-13, atol=1e-13 * np.abs(v * phi / C ** 2).max())
+        np.testing.assert_allclose(out[4:7], Eref, rtol=1e-12, atol=1e-13 * np.abs(Eref).max())
+        Bref = np.cross(v, Eref) / C ** 2
+        np.testing.assert_allclose(out[7:10], Bref, rtol=1e-12, atol=1e-13 * np.abs(Bref).max())
+        # a uniformly moving charge does not radiate
+        assert np.all(pair(ch, x, t, O.RADIATION)[4:10] == 0)
+
+
+def test_circular_orbit_centre():
+    """At the centre of a circular orbit (radius R, speed b c): R is constant,
+    n . beta = 0 and beta_dot is parallel to n, which reduces Eq. (E) to
+    E = kq/R^2 [(1 - b^2) n - beta], with Phi = kq/R (derived by hand)."""
+    w = I.workload_tiny_orbit()
+    ch = w["charges"]
+    R, om = ch["amp"][0], ch["omega"][0]
+    for t in (w["times"][0], 1.234e-16, 0.0):
+        tau = R / C
+        r, v, *_ = O.kinematics(ch, 0, t - tau)
+        n = -r / R
+        beta = v / C
+        b2 = beta @ beta
+        Eref = K * E / R ** 2 * ((1 - b2) * n - beta)
+        out = pair(ch, [0, 0, 0], t)
+        np.testing.assert_allclose(out[0], K * E / R, rtol=1e-14)
+        np.testing.assert_allclose(out[1:4], K * E / R * beta / C, rtol=1e-12, atol=1e-14 * K * E / R / C)
+        np.testing.assert_allclose(out[4:7], Eref, rtol=1e-12, atol=1e-13 * np.linalg.norm(Eref))
+        np.testing.assert_allclose(out[7:10], np.cross(n, Eref) / C, rtol=1e-12,
+                                   atol=1e-13 * np.linalg.norm(Eref) / C)
+
+
+def _grad_curl(ch, x, t, hx):
+    """Central 4th-order differences of Phi and A in space and time."""
+    def f(dx, dt):
+        return pair(ch, x + dx, t + dt)
+    ht = hx / C
+    w = np.array([1, -8, 8, -1]) / 12.0
+    offs = (-2, -1, 1, 2)
+    dphi = np.zeros(3)
+    dA = np.zeros((3, 3))  # dA[i, j] = d A_j / d x_i
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = hx
+        vals = [f(k * e, 0.0) for k in offs]
+        d = sum(wk * v for wk, v in zip(w, vals)) / hx
+        dphi[i] = d[0]
+        dA[i] = d[1:4]
+    vals = [f(np.zeros(3), k * ht) for k in offs]
+    dt_ = sum(wk * v for wk, v in zip(w, vals)) / ht
+    return dphi, dA, dt_[0], dt_[1:4]
+
+
+@pytest.mark.parametrize("fam", ["circular", "linear", "accel"])
+def test_potentials_generate_fields(fam):
+    """E = -grad Phi - dA/dt and B = curl A (Maxwell), from the oracle's own Phi and A:
+    pins Eqs. (V), (A), (E), (B) and the retarded time together."""
+    if fam == "circular":
+        ch = one(I.CIRCULAR, amp=1e-9, omega=0.45 * C / 1e-9, phase=0.3, e1=[1, 0, 0], e2=[0, 0.6, 0.8])
+    elif fam == "linear":
+        ch = one(I.LINEAR_OSC, amp=2e-9, omega=0.4 * C / 2e-9, phase=1.1, e1=[0.6, 0.0, 0.8])
+    else:
+        ch = one(I.ACCEL, accel=0.5 * C / 1e-15, e1=[0, 0.8, 0.6])
+    rng = np.random.default_rng(7)
+    for _ in range(6):
+        x = rng.uniform(-12e-9, 12e-9, 3)
+        t = rng.uniform(0.6e-15, 0.9e-15)
+        out = pair(ch, x, t)
+        dphi, dA, dphit, dAt = _grad_curl(ch, x, t, 2e-12)
+        Efd = -dphi - dAt
+        Bfd = np.array([dA[1, 2] - dA[2, 1], dA[2, 0] - dA[0, 2], dA[0, 1] - dA[1, 0]])
+        En = np.linalg.norm(out[4:7])
+        assert np.linalg.norm(Efd - out[4:7]) <= 2e-7 * En, (fam, x, t)
+        assert np.linalg.norm(Bfd - out[7:10]) <= 2e-7 * En / C, (fam, x, t)
+        # Lorenz gauge: div A + (1/c^2) dPhi/dt = 0
+        divA = dA[0, 0] + dA[1, 1] + dA[2, 2]
+        assert abs(divA + dphit / C ** 2) <= 2e-7 * abs(dphit) / C ** 2 + 1e-30
+
+
+def test_structure_of_fields():
+    """Coulomb + radiation = total; the radiation fields are transverse with |E| = c|B|;
+    B is orthogonal to n at the retarded time; flipping q flips every output."""
+    w = I.workload_grid_mixed(grid_n=5, n_times=3)
+    ch = w["charges"]
+    for i in range(len(ch["kind"])):
+        s = I.subset_charges(ch, [i])
+        for p in range(0, 25, 6):
+            x, t = w["points"][:, p], w["times"][-1]
+            tot, co, ra = (O.lw_pair(s, 0, x, t, k) for k in (O.TOTAL, O.COULOMB, O.RADIATION))
+            tau = O.retarded_tau(s, 0, x, t)
+            r, *_ = O.kinematics(s, 0, t - tau)
+            n = (x - r) / np.linalg.norm(x - r)
+            sc = np.linalg.norm(tot[4:7])
+            np.testing.assert_allclose(co[4:7] + ra[4:7], tot[4:7], atol=1e-14 * sc)
+            np.testing.assert_allclose(co[:4], tot[:4], rtol=0)
+            assert abs(ra[4:7] @ n) <= 1e-12 * max(np.linalg.norm(ra[4:7]), 1e-300)
+            assert abs(np.linalg.norm(ra[4:7]) - C * np.linalg.norm(ra[7:10])) <= 1e-12 * np.linalg.norm(ra[4:7])
+            assert abs(tot[7:10] @ n) <= 1e-12 * np.linalg.norm(tot[7:10])
+            s2 = dict(s)
+            s2["q"] = -s["q"]
+            np.testing.assert_array_equal(O.lw_pair(s2, 0, x, t), -tot)
+
+
+def test_superposition_is_sum_of_singles():
+    w = I.workload_grid_mixed(grid_n=6, n_times=2)
+    ch = w["charges"]
+    tot, _ = O.fields(ch, w["points"], w["times"])
+    acc = np.zeros_like(tot)
+    for i in range(len(ch["kind"])):
+        o, _ = O.fields(I.subset_charges(ch, [i]), w["points"], w["times"])
+        acc += o
+    scale = np.abs(tot).max(axis=2, keepdims=True)
+    assert np.all(np.abs(tot - acc) <= 1e-13 * scale)
+
+
+def test_oscillating_dipole_matches_appendix_d():
+    """Two opposite charges q = 1e5 e oscillating 4e-14 m apart at 7e16 rad/s against the
+    ideal dipole field of App. D along the z axis, E_x = d0/(4 pi eps0) Re{e^{i(kz - wt)}
+    (k^2/z - 1/z^3 + i k/z^2)}; the paper reports < 1e-8 relative error outside the very
+    near field (Sec. 3.4, Fig. 8)."""
+    g = GOLD["app_d_rel_error"]["setup"]
+    w, q, s = g["omega"], g["q_over_e"] * E, g["separation"]
+    plus = one(I.LINEAR_OSC, q=q, amp=s / 2, omega=w, phase=0.0, e1=[1, 0, 0])
+    minus = one(I.LINEAR_OSC, q=-q, amp=s / 2, omega=w, phase=math.pi, e1=[1, 0, 0])
+    ch = I.concat_charges([plus, minus])
+    k = w / C
+    lam = 2 * math.pi / k
+    d0 = q * s
+    z = np.array([0.1, 0.3, 1.0, 3.0, 10.0]) * lam
+    pts = np.stack([np.zeros_like(z), np.zeros_like(z), z])
+    times = np.linspace(0, 2 * math.pi / w, 9)[:-1]
+    out, _ = O.fields(ch, pts, times)
+    amp = K * d0 * (k * k / z - 1 / z ** 3 + 1j * k / z ** 2)
+    for it, t in enumerate(times):
+        ref = np.real(np.exp(1j * (k * z - w * t)) * amp)
+        err = np.abs(out[it, 4] - ref) / np.abs(amp)
+        assert np.all(err < GOLD["app_d_rel_error"]["value"]), err
+
+
+def test_masking_rule():
+    w = I.workload_tiny_orbit()
+    out, flags = O.fields(w["charges"], w["points"], w["times"])
+    assert flags.sum() == 0 and np.isfinite(out).all()     # no 64x64 grid point is within 0.1 nm
+    t = w["times"][0]
+    r, *_ = O.kinematics(w["charges"], 0, t)
+    # 0.05 nm from the present position: the retarded distance is below 0.05/(1 - 0.3) nm
+    pts = np.stack([r + np.array([0, 0, 0.05e-9]), [5e-9, 0, 0]], axis=1)
+    out, flags = O.fields(w["charges"], pts, [t])
+    assert flags[0] & O.FLAG_MASKED and np.isnan(out[0, :, 0]).all()
+    assert flags[1] == 0 and np.isfinite(out[0, :, 1]).all()
+
+
+# ----------------------------------------------------------------------------
+# Lorentz oscillators
+# ----------------------------------------------------------------------------
+
+def _single(w0=2 * math.pi * 200e12, d0=E * 1e-12):
+    dip = I.empty_dipoles(1)
+    dip["omega0"][:] = w0
+    dip["d0"][:] = d0
+    return dip
+
+
+def test_isolated_oscillator_is_rk4_propagator():
+    """With no other source the drive vanishes, so every step is the exact RK4 propagator
+    P = sum_k (hA)^k / k! of y' = A y, A = [[0, 1], [-w0^2, -gamma0]] (Eq. (LO_equation))."""
+    w0 = 2 * math.pi * 200e12
+    dip = _single(w0)
+    dt = 1 / 200e12 / 200
+    steps = 3000
+    r = O.dipole_run(dip, [0, 1], dt, steps, out_stride=10)
+    g0 = gamma0(E, ME / 2, w0)
+    A = np.array([[0.0, 1.0], [-w0 * w0, -g0]]) * dt
+    P = np.eye(2) + A + A @ A / 2 + A @ A @ A / 6 + A @ A @ A @ A / 24
+    y = np.array([E * 1e-12, 0.0])
+    P10 = np.linalg.matrix_power(P, 10)
+    for row in range(steps // 10 + 1):
+        assert abs(r["d"][row, 0] - y[0]) <= 1e-11 * E * 1e-12
+        assert abs(r["d_dot"][row, 0] - y[1]) <= 1e-11 * E * 1e-12 * w0
+        y = P10 @ y
+    # energy of Eq. (dipoleE) decays at gamma0 up to the RK4 error
+    T = steps * dt
+    ratio = r["energy"][-1, 0] / r["energy"][0, 0]
+    assert abs(-math.log(ratio) / T / g0 - 1) < 0.05
+
+
+def test_rk4_fourth_order():
+    """Error of the isolated oscillator against the exact damped solution falls as dt^4."""
+    w0 = 2 * math.pi * 200e12
+    g0 = gamma0(E, ME / 2, w0)
+    lam = complex(-g0 / 2, math.sqrt(w0 * w0 - g0 * g0 / 4))
+    T = 2 / 200e12
+    errs = []
+    for n in (40, 80, 160):
+        r = O.dipole_run(_single(w0), [0, 1], T / n, n)
+        c1 = E * 1e-12 * (1 - 1j * lam.real / lam.imag) / 2    # d(0) = d0, d'(0) = 0
+        exact = 2 * (c1 * np.exp(lam * T)).real
+        exact_v = 2 * (c1 * lam * np.exp(lam * T)).real
+        # state error (d, d_dot/w0): the phase error shows at first order
+        errs.append(math.hypot(r["d"][-1, 0] - exact, (r["d_dot"][-1, 0] - exact_v) / w0))
+    o1, o2 = math.log2(errs[0] / errs[1]), math.log2(errs[1] / errs[2])
+    assert 3.8 < o1 < 4.2 and 3.8 < o2 < 4.2, (o1, o2)
+
+
+def test_static_prehistory_drive():
+    """At t = 0 every dipole is still static (Sec. 3.2), so the drive of dipole 1 is the
+    Coulomb field of dipole 2's two charges, placed by Eqs. (r_1), (r_2) with unequal masses."""
+    dip = I.empty_dipoles(2)
+    dip["axis"][0] = [0.6, 0.8, 0.0]
+    dip["axis"][1] = [0.0, 0.6, 0.8]
+    dip["origin"][1] = [7e-9, 2e-9, -3e-9]
+    dip["omega0"][:] = 2 * math.pi * 200e12
+    dip["m1"][1] = 3 * ME
+    dip["d0"][:] = [E * 2e-12, -E * 3e-12]
+    r = O.dipole_run(dip, [0, 2], 1e-18, 1)
+    m1, m2 = dip["m1"][1], dip["m2"][1]
+    rdip = dip["d0"][1] / E * dip["axis"][1]
+    rp = dip["origin"][1] + m2 / (m1 + m2) * rdip
+    rm = dip["origin"][1] - m1 / (m1 + m2) * rdip
+    x = dip["origin"][0]
+    Ef = K * E * ((x - rp) / np.linalg.norm(x - rp) ** 3 - (x - rm) / np.linalg.norm(x - rm) ** 3)
+    np.testing.assert_allclose(r["Ed"][0, 0], Ef @ dip["axis"][0], rtol=1e-9)
+
+
+def greens_ratios(orientation, R, w0):
+    """delta_12/gamma_0 and gamma_12/gamma_0 from the free-space dyadic Green's function
+    of App. A (the bracketed form with the k0^2 e^{ikR}/(4 pi R) prefactor; E = G d/eps0),
+    with gamma_0 from Im G(r, r) = k^3/(6 pi) (Eqs. (qed_gamma_ab), (qed_delta))."""
+    k = w0 / C
+    p = np.array([0.0, 1.0, 0.0]) if orientation == "s" else np.array([1.0, 0.0, 0.0])
+    Rh = np.array([1.0, 0.0, 0.0])
+    kR = k * R
+    pre = k * k * np.exp(1j * kR) / (4 * math.pi * R)
+    G = pre * ((1 + (1j * kR - 1) / kR ** 2) * np.eye(3) + (3 - 3j * kR - kR ** 2) / kR ** 2 * np.outer(Rh, Rh))
+    pGp = p @ G @ p
+    im_self = k ** 3 / (6 * math.pi)
+    return -pGp.real / (2 * im_self), pGp.imag / im_self
+
+
+def test_greens_function_matches_printed():
+    L2 = GOLD["listing2"]
+    d, g = greens_ratios("s", L2["setup"]["separation"], L2["setup"]["omega0"])
+    assert round(d, 3) == L2["delta12_th"] and round(g, 3) == L2["gamma12_th"]
+    f11 = GOLD["fig11_delta12_th"]
+    d11, _ = greens_ratios("s", f11["setup"]["separation"], f11["setup"]["omega0"])
+    assert round(d11, 2) == f11["value"]
+
+
+def test_listing2_coupled_s_dipoles():
+    """Listing 2: two in-phase s dipoles 80 nm apart, omega_0 = 2 pi 100 THz, 40,000 steps of
+    1e-18 s, fit from step 10,000.  The paper prints delta_12 = 156.919 and gamma^+ = 1.997
+    (theory 156.926 and 1 + 0.994, within 0.2 %)."""
+    L2 = GOLD["listing2"]
+    s = L2["setup"]
+    w0 = s["omega0"]
+    dip = I.empty_dipoles(2)
+    dip["axis"][:] = [0, 1, 0]
+    dip["origin"][1, 0] = s["separation"]
+    dip["omega0"][:] = w0
+    dip["d0"][:] = E * s["init_r"]
+    r = O.dipole_run(dip, [0, 2], s["dt"], s["steps"])
+    g0 = gamma0(E, ME / 2, w0)
+    m = X.pair_modes(r["d"][:, 0], r["d"][:, 1], s["dt"], 1, w0, s["first_index"])
+    delta12 = (m["omega_plus"] - w0) / g0
+    gplus = m["gamma_plus"] / g0
+    assert math.isnan(m["gamma_minus"])         # the anti-phase mode is not excited
+    assert abs(delta12 - L2["delta12_sim"]) < 1e-3           # matches the printed simulation
+    tol = GOLD["gf_rel_accuracy"]["value"]
+    assert abs(delta12 / L2["delta12_th"] - 1) < tol
+    assert abs(gplus / (1 + L2["gamma12_th"]) - 1) < tol
+    dth, gth = greens_ratios("s", s["separation"], w0)
+    assert abs(gplus / (1 + gth) - 1) < 1e-4
+
+
+def test_single_excitation_beats():
+    """One dipole excited, the other at rest (the Foerster case of Fig. 10 / Eqs. (rho_aa),
+    (rho_bb)): both normal modes appear, delta_omega = (w+ - w-)/2 matches delta_12 and
+    gamma^+- match gamma_0 +- gamma_12 of the Green's function (p dipoles, 30 nm)."""
+    w0 = 2 * math.pi * 200e12
+    R = 30e-9
+    dt = 1 / 200e12 / 2000
+    steps = 60000
+    dip = I.empty_dipoles(2)
+    dip["origin"][1, 0] = R
+    dip["omega0"][:] = w0
+    dip["d0"][0] = E * 1e-12
+    r = O.dipole_run(dip, [0, 2], dt, steps, out_stride=4)
+    g0 = gamma0(E, ME / 2, w0)
+    m = X.pair_modes(r["d"][:, 0], r["d"][:, 1], dt, 4, w0, X.default_skip(dt, R))
+    dth, gth = greens_ratios("p", R, w0)
+    assert abs(m["delta_omega"] / g0 / dth - 1) < 2e-3
+    assert abs(m["gamma_plus"] / g0 / (1 + gth) - 1) < 2e-3
+    # the subradiant rate is a small difference: compare it in units of gamma_0
+    assert abs(m["gamma_minus"] / g0 - (1 - gth)) < 2e-3
+    # populations (Eqs. (rho_aa), (rho_bb)): E1 + E2 decays, E1 - E2 starts at E1(0)
+    e1, e2 = r["energy"][:, 0], r["energy"][:, 1]
+    assert e2[0] == 0 and e1[0] > 0 and np.all(e1 + e2 <= (e1[0] + e2[0]) * (1 + 1e-9))
+
+
+def exact_modes(orientation, R, w0, q=E, m=ME / 2):
+    """Complex normal-mode frequencies of two identical oscillators without the Markov
+    approximation: with d(t) ~ e^{-i w t}, Eq. (LO_equation) and the exact dipole field of
+    App. D give w0^2 - w^2 - i gamma0 w = +-(q^2/m) g(w), where g is the field at the other
+    dipole along its axis per unit moment.  Solved by complex Newton from w0."""
+    g0 = gamma0(q, m, w0)
+    cos2 = 1.0 if orientation == "p" else 0.0
+
+    def g(w):
+        k = w / C
+        return K * np.exp(1j * k * R) * (k * k * (1 - cos2) / R + (3 * cos2 - 1) * (1 / R ** 3 - 1j * k / R ** 2))
+
+    res = []
+    for sgn in (1, -1):
+        def F(w):
+            return w0 * w0 - w * w - 1j * g0 * w - sgn * q * q / m * g(w)
+        w = complex(w0, -g0 / 2)
+        for _ in range(100):
+            h = 1e-7 * abs(w)
+            dw = F(w) / ((F(w + h) - F(w - h)) / (2 * h))
+            w -= dw
+            if abs(dw) < 1e-15 * abs(w):
+                break
+        res.append(w)
+    wp, wm = res
+    return {"gamma_plus": -2 * wp.imag, "gamma_minus": -2 * wm.imag, "delta_omega": (wp.real - wm.real) / 2}
+
+
+@pytest.mark.parametrize("R", [3e-9, 10e-9])
+def test_near_field_exact_modes(R):
+    """Near-field p dipoles, where the Green's-function rates (first order in the coupling)
+    no longer hold, against the exact classical mode roots."""
+    w0 = 2 * math.pi * 200e12
+    dt = 1 / 200e12 / 2000
+    dip = I.empty_dipoles(2)
+    dip["origin"][1, 0] = R
+    dip["omega0"][:] = w0
+    dip["d0"][0] = E * 1e-12
+    r = O.dipole_run(dip, [0, 2], dt, 40000, out_stride=4)
+    m = X.pair_modes(r["d"][:, 0], r["d"][:, 1], dt, 4, w0, X.default_skip(dt, R))
+    ex = exact_modes("p", R, w0)
+    g0 = gamma0(E, ME / 2, w0)
+    assert abs(m["delta_omega"] / ex["delta_omega"] - 1) < 2e-6
+    assert abs(m["gamma_plus"] - ex["gamma_plus"]) < 1e-3 * g0
+    assert abs(m["gamma_minus"] - ex["gamma_minus"]) < 1e-3 * g0
+
+
+def test_energy_balance_identity():
+    """dE_i/dt = d_dot E_d - (m gamma0/q^2) d_dot^2 follows from Eq. (LO_equation) and
+    Eq. (dipoleE); integrated with the trapezoid rule it must close to O(dt^2)."""
+    w0 = 2 * math.pi * 200e12
+    dt = 1 / 200e12 / 1000
+    steps = 4000
+    dip = I.empty_dipoles(3)
+    dip["origin"][1] = [12e-9, 0, 0]
+    dip["origin"][2] = [0, 15e-9, 4e-9]
+    dip["axis"][2] = [0, 0.6, 0.8]
+    dip["omega0"][:] = w0 * np.array([1.0, 1.001, 0.999])
+    dip["d0"][:] = E * 1e-12 * np.array([1.0, -0.5, 0.3])
+    r = O.dipole_run(dip, [0, 3], dt, steps)
+    m = ME / 2
+    for i in range(3):
+        g0 = gamma0(E, m, dip["omega0"][i])
+        p_in = r["d_dot"][:, i] * r["Ed"][:, i] - m * g0 / E ** 2 * r["d_dot"][:, i] ** 2
+        work = dt * (p_in.sum() - 0.5 * (p_in[0] + p_in[-1]))
+        dE = r["energy"][-1, i] - r["energy"][0, i]
+        scale = dt * np.abs(p_in).sum()
+        assert abs(dE - work) <= 1e-4 * scale, (i, dE, work, scale)
+
+
+def test_prony_recovers_damped_cosine():
+    dt = 1e-17
+    t = np.arange(20000) * dt
+    for g, w, ph in ((2e7, 1.3e15, 0.3), (5e12, 1.2e15, 2.0), (1e10, 9e14, -1.0)):
+        x = np.exp(-g * t / 2) * np.cos(w * t + ph)
+        gg, ww = X.prony2(x, int(round(math.pi / (2 * w * dt))), dt)
+        assert abs(gg / g - 1) < 1e-6 and abs(ww / w - 1) < 1e-12
+
+
+def test_error_paths():
+    dip = I.empty_dipoles(2)
+    dip["origin"][1, 0] = 5e-9
+    dip["omega0"][:] = 2 * math.pi * 200e12
+    dip["d0"][0] = E * 1e-12
+    with pytest.raises(O.OracleError) as ei:
+        O.dipole_run(dip, [0, 2], 2.5e-17, 10, policy=O.DT_STRICT)
+    assert ei.value.code == 3
+    O.dipole_run(dip, [0, 2], 2.5e-17, 10, policy=O.DT_EXTRAPOLATE)
+    dip["origin"][1, 0] = 20e-9
+    dip["d0"][0] = E * 1e-8       # a 10 nm swing at 200 THz exceeds c/100
+    with pytest.raises(O.OracleError) as ei:
+        O.dipole_run(dip, [0, 2], 2.5e-17, 200, policy=O.DT_STRICT)
+    assert ei.value.code == 4
+    O.dipole_run(dip, [0, 2], 2.5e-17, 200, policy=O.DT_STRICT, max_vel=0.1 * C)
+    dip["origin"][1, 0] = 5e-9    # the positive charge of dipole 1 sits on dipole 2's origin
+    with pytest.raises(O.OracleError) as ei:
+        O.dipole_run(dip, [0, 2], 2.5e-17, 5, policy=O.DT_EXTRAPOLATE, max_vel=0.1 * C)
+    assert ei.value.code == 8
+    fast = one(I.CIRCULAR, amp=1e-9, omega=1.2 * C / 1e-9)
+    with pytest.raises(O.OracleError) as ei:
+        O.fields(fast, np.zeros((3, 1)) + 5e-9, [0.0])
+    assert ei.value.code == 2
