@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Benchmark of the Lienard-Wiechert hot path on one MI355X.
+
+A step is one lw_fields call on the mixed-precision grid workload: 16 charges
+(linear oscillation, circular orbit, uniform acceleration; seeded), a 512x512
+plane over +-100 nm, 64 snapshots over the first femtosecond -- FP64 retarded
+times, FP32 field expressions with Kahan sums, FP32 outputs (671 MB per step).
+Inputs are resident in HBM before the timed region.
+
+The JSON line also carries the FP64 form of the same step, the oscillator
+throughput (256 two-dipole instances, 20,000 RK4 steps), the errors against the
+FP64 oracle on a sample, the roofline of the dominant kernel and the oracle's
+CPU throughput on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "charge·point LW evals/s (mixed vs FP64) + dipole-steps/s at stated error"
+
+# Algorithmic work per LW eval (one point, one charge, one time), counted from
+# the formulas: 86 FP32 flops for Phi, A, E, B of one charge (FMA = 2 flops)
+# and 150 FP64 flops for the retarded-time solve (3 Newton iterations of 50).
+FLOP_LW_FP32 = 86
+FLOP_SOLVE_FP64 = 150
+# Vector ALU peak of MI355X for FP64 and for unpacked FP32: 256 CUs x 4 SIMDs
+# x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def log(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed_calls(call, steps: int, warmup: int):
+    import torch
+    for _ in range(warmup):
+        call.launch()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        call.launch()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = [a.elapsed_time(b) for a, b in evs]
+    return wall, sum(kern) / len(kern)
+
+
+def errors(got, ref):
+    import numpy as np
+    res = {}
+    ok = np.isfinite(ref).all(axis=1)
+    for name, comps in (("phi", [0]), ("A", [1, 2, 3]), ("E", [4, 5, 6]), ("B", [7, 8, 9])):
+        g = got[:, comps, :].transpose(0, 2, 1)[ok]
+        r = ref[:, comps, :].transpose(0, 2, 1)[ok]
+        d = g - r
+        res[name] = {"relL2": float(np.sqrt((d * d).sum() / (r * r).sum())),
+                     "relmax": float(np.abs(d).max() / np.abs(r).max())}
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample-points", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dipole", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (each instance or "
+              "grid tile is independent, so N GPUs would shard the workload without exchange)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2107_12437_amd import inputs as I
+    from paper_2107_12437_amd import lw
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    w = I.workload_grid_mixed()
+    pts = torch.tensor(w["points"], dtype=torch.float64, device="cuda")
+    n_pts, n_ch, n_t = pts.shape[1], len(w["charges"]["kind"]), len(w["times"])
+    evals = n_pts * n_ch * n_t
+
+    log(f"[bench] mixed grid: {n_pts} points x {n_ch} charges x {n_t} times")
+    mixed = lw.FieldsCall(w["charges"], pts, w["times"], precision="mixed")
+    wall, kern_ms = timed_calls(mixed, args.steps, args.warmup)
+    ms_per_step = wall / args.steps * 1e3
+    value = evals / (wall / args.steps)
+    log(f"[bench] mixed: {ms_per_step:.3f} ms/step, kernel {kern_ms:.3f} ms, {value:.4e} evals/s")
+
+    fp64 = lw.FieldsCall(w["charges"], pts, w["times"], precision="fp64")
+    fsteps = max(3, args.steps // 4)
+    fwall, fkern_ms = timed_calls(fp64, fsteps, 1)
+    fp64_value = evals / (fwall / fsteps)
+    log(f"[bench] fp64: {fwall / fsteps * 1e3:.3f} ms/step, {fp64_value:.4e} evals/s")
+
+    achieved = evals * (FLOP_LW_FP32 + FLOP_SOLVE_FP64) / (kern_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TFLOPS, 1),
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_VALU_TFLOPS, 4), "traffic": None,
+                "kernel": "fields_kernel<float>", "flop_per_eval": FLOP_LW_FP32 + FLOP_SOLVE_FP64,
+                "kernel_ms": round(kern_ms, 4)}
+
+    # errors of both forms against the oracle on a sample of the same launch
+    out_m = mixed.out
+    out_f = fp64.out
+    rng = np.random.default_rng(5)
+    n_s = args.cpu_sample_points
+    pidx = np.sort(rng.choice(n_pts, size=min(n_s, n_pts), replace=False))
+    cpu = None
+    err = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        sub_pts = np.ascontiguousarray(w["points"][:, pidx])
+        log(f"[bench] oracle on {len(pidx)} points x {n_ch} charges x {n_t} times (1 core)")
+        t0 = time.perf_counter()
+        ref, _ = O.fields(w["charges"], sub_pts, w["times"])
+        cpu_s = time.perf_counter() - t0
+        cpu_evals = len(pidx) * n_ch * n_t
+        cpu = {"value": cpu_evals / cpu_s, "unit": "LW evals/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(pidx)} seeded grid points x {n_ch} charges x {n_t} times of the same "
+                         f"workload ({cpu_evals} evals, {cpu_s:.1f} s, serial FP64 C oracle)"}
+        gm = out_m[:, :, torch.tensor(pidx, device="cuda")].double().cpu().numpy()
+        gf = out_f[:, :, torch.tensor(pidx, device="cuda")].cpu().numpy()
+        err = {"mixed": errors(gm, ref), "fp64": errors(gf, ref)}
+        log(f"[bench] oracle {cpu['value']:.3e} evals/s; mixed E relmax {err['mixed']['E']['relmax']:.2e}")
+
+    dip = None
+    if not args.no_dipole:
+        pw = I.workload_dipole_pairs()
+        n_dip = len(pw["dipoles"]["omega0"])
+        lw.dipole_run(pw["dipoles"], pw["inst_off"], pw["dt"], 200, policy="extrapolate")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = lw.dipole_run(pw["dipoles"], pw["inst_off"], pw["dt"], pw["steps"], policy="extrapolate",
+                          out_stride=1, check=False)
+        torch.cuda.synchronize()
+        dsec = time.perf_counter() - t0
+        lw.sync_status()
+        dip = {"workload": pw["name"], "dipole_steps_per_s": n_dip * pw["steps"] / dsec,
+               "ms": round(dsec * 1e3, 3), "dtype": "f64"}
+        log(f"[bench] dipoles: {dsec * 1e3:.2f} ms, {dip['dipole_steps_per_s']:.3e} dipole-steps/s")
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "LW evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": w["name"], "precision": "mixed", "points": n_pts, "charges": n_ch,
+                   "times": n_t, "evals_per_step": evals},
+        "fp64_value": fp64_value, "mixed_over_fp64": value / fp64_value,
+        "roofline": roofline, "cpu_baseline": cpu, "errors_vs_oracle": err, "dipoles": dip,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * lw.h -- C ABI of the MI355X (gfx950) Lienard-Wiechert library (liblw.so).
+ *
+ * The library evaluates, for every (observation point, point charge) pair,
+ * the retarded time of Eq. (ret_t), t' = t - R(t')/c, on the charge's
+ * trajectory, then the Lienard-Wiechert potentials of Eqs. (V), (A) and the
+ * fields of Eqs. (E) / (ECoulomb) / (Eradiation) and (B), and sums them over
+ * charges (arXiv 2107.12437, Secs. 2.1-2.2).  It also runs the
+ * self-consistent Lorentz-oscillator loop of Algorithm 1 (Secs. 2.3, 3.2):
+ * dipoles driven by the retarded fields of the other dipoles' charges,
+ * integrated with RK4 from a device-resident history.
+ *
+ * Conventions
+ *   - SI units throughout.  Physical constants are CODATA 2018.
+ *   - "d_" arguments are device pointers (HIP device memory), "h_" arguments
+ *     are host pointers.  The caller owns every buffer it passes; the library
+ *     never frees or retains caller memory past the call (it keeps only its
+ *     own workspace, owned by the context).
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Every call enqueues
+ *     its work on that stream and returns without waiting, except where a
+ *     function says it synchronises.
+ *   - Errors are returned as lw_status codes; no C++ exception crosses the
+ *     ABI.  lw_last_error() gives a message for the last failure on the
+ *     calling thread.  Argument errors are detected on the host before any
+ *     launch; errors found by a kernel (a dipole charge above the speed limit,
+ *     a non-finite state, history overrun) are latched in the context and
+ *     returned by lw_sync_status().
+ *   - A context may be used from one host thread at a time.  Calls that share a
+ *     context must run on one stream (they share the context's workspace).
+ */
+#ifndef LW_H
+#define LW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* status                                                                    */
+/* ------------------------------------------------------------------------ */
+typedef int32_t lw_status;
+enum {
+    LW_OK = 0,
+    LW_E_INVALID = 1,       /* bad argument (size, pointer, non-finite or unnormalised input)   */
+    LW_E_SUPERLUMINAL = 2,  /* a trajectory reaches |v| >= c within the requested times         */
+    LW_E_DT_TOO_LARGE = 3,  /* c*dt >= the smallest dipole separation under LW_DT_STRICT
+                               (Sec. 3.2: radiation must not reach another dipole in one step) */
+    LW_E_VELOCITY = 4,      /* a dipole charge exceeded max_vel (Sec. 3.2, default c/100)      */
+    LW_E_NOCONV = 5,        /* retarded-time solve hit max_iter (fields: per-point flag bit 2)  */
+    LW_E_HIP = 6,           /* a HIP runtime call failed                                        */
+    LW_E_NOMEM = 7,         /* device or host allocation failed                                 */
+    LW_E_NONFINITE = 8,     /* an oscillator state became NaN or Inf                            */
+    LW_E_HISTORY = 9        /* a retarded time fell outside the stored history window           */
+};
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *lw_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* context                                                                   */
+/* ------------------------------------------------------------------------ */
+typedef struct lw_ctx lw_ctx;
+
+/* Creates a context on HIP device `device` (made current for the calls on the
+ * context).  The context owns device workspace, pinned staging memory and the
+ * tuning table; all are released by lw_destroy. */
+lw_status lw_create(lw_ctx **out, int32_t device);
+lw_status lw_destroy(lw_ctx *ctx);
+
+/* Waits for `stream`, then returns (and clears) the first error latched by a
+ * kernel of this context since the previous call; LW_OK if none. */
+lw_status lw_sync_status(lw_ctx *ctx, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* point charges with prescribed trajectories (Sec. 3.1)                     */
+/* ------------------------------------------------------------------------ */
+enum {
+    LW_STATIONARY = 0,       /* r(t) = c0                                                      */
+    LW_UNIFORM_VELOCITY = 1, /* r(t) = c0 + v t                                                */
+    LW_LINEAR_OSC = 2,       /* r(t) = c0 + amp cos(omega t + phase) e1                        */
+    LW_CIRCULAR = 3,         /* r(t) = c0 + amp (cos(omega t + phase) e1 + sin(... ) e2), e1 . e2 = 0 */
+    LW_ACCEL = 4             /* r(t) = c0 for t < 0, c0 + accel t^2 e1 / 2 for t >= 0          */
+};
+
+/* One point charge: its value q and parametric x(t), y(t), z(t) with exact
+ * derivatives (the paper's Charge subclasses, Sec. 3.1).  e1 and e2 must be
+ * unit vectors where the kind uses them.  Layout: 8-byte aligned, 144 bytes. */
+typedef struct {
+    int32_t kind;
+    int32_t pad_;
+    double q;          /* C            */
+    double c0[3];      /* m            */
+    double e1[3];
+    double e2[3];
+    double amp;        /* m            */
+    double omega;      /* rad/s        */
+    double phase;      /* rad          */
+    double accel;      /* m/s^2        */
+    double v[3];       /* m/s          */
+} lw_traj;
+
+enum { LW_FP64 = 0, LW_MIXED = 1 };
+enum { LW_FIELD_TOTAL = 0, LW_FIELD_COULOMB = 1, LW_FIELD_RADIATION = 2 };
+enum { LW_FLAG_MASKED = 1u, LW_FLAG_NOCONV = 2u };
+
+typedef struct {
+    int32_t precision;   /* LW_FP64: FP64 throughout.  LW_MIXED: FP64 retarded time and
+                            kinematics, FP32 field expressions with Kahan-compensated FP32
+                            sums over charges, FP32 outputs.                                */
+    int32_t field_kind;  /* E and B as the total field of Eq. (E) or its Coulomb or
+                            radiation part (Eqs. (ECoulomb), (Eradiation)); Phi and A
+                            are unaffected                                                  */
+    int32_t max_iter;    /* cap on retarded-time iterations per pair (0: 100)               */
+    int32_t reserved;    /* must be 0                                                       */
+    double mask_radius;  /* (point, time) with a retarded distance below this to any charge
+                            gets NaN outputs and LW_FLAG_MASKED (m; < 0: 1e-10)             */
+} lw_opts;
+
+/* Potentials and fields of n_charges point charges at n_pts points and n_times
+ * times (Secs. 2.1-2.2; the paper's calculate_V / calculate_A / calculate_E /
+ * calculate_B fused over outputs and times).
+ *   h_charges  host array of n_charges trajectories (n_charges >= 1)
+ *   d_pts      device FP64, SoA [3][n_pts]: x[], then y[], then z[]
+ *   h_times    host FP64 [n_times] observation times (s)
+ *   d_out      device, SoA [n_times][10][n_pts] with components
+ *              Phi, Ax, Ay, Az, Ex, Ey, Ez, Bx, By, Bz (V, V s/m, V/m, T);
+ *              FP64 for LW_FP64, FP32 for LW_MIXED
+ *   d_flags    device uint32 [n_pts] or NULL: LW_FLAG_* OR-ed over times
+ * Returns LW_E_SUPERLUMINAL if a charge moves at >= c at or before a requested
+ * time.  n_pts == 0 or n_times == 0 is a no-op.  Asynchronous. */
+lw_status lw_fields(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, const double *d_pts,
+                    int64_t n_pts, const double *h_times, int32_t n_times, const lw_opts *opts,
+                    void *d_out, uint32_t *d_flags, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Lorentz oscillators (Secs. 2.3, 3.2; Algorithm 1)                         */
+/* ------------------------------------------------------------------------ */
+
+/* One oscillator (the paper's Dipole): two charges +q (mass m1) and -q (mass
+ * m2) about the centre of mass `origin`, displaced along the unit axis p by
+ * r_dip = (d/q) p (Eqs. (r_1), (r_2)); d0 is the signed initial moment along p
+ * (C m).  Layout: 88 bytes. */
+typedef struct {
+    double origin[3];
+    double axis[3];
+    double omega0;     /* rad/s */
+    double q;          /* C, > 0 */
+    double m1, m2;     /* kg    */
+    double d0;         /* C m   */
+} lw_dipole;
+
+enum { LW_DT_STRICT = 0, LW_DT_EXTRAPOLATE = 1 };
+
+typedef struct {
+    int32_t precision;   /* LW_FP64 (the only value accepted for oscillator runs)           */
+    int32_t dt_policy;   /* LW_DT_STRICT: require c*dt < smallest separation (Sec. 3.2).
+                            LW_DT_EXTRAPOLATE: allow it; a source read beyond its newest
+                            stored step is a second-order Taylor step from that sample     */
+    int64_t out_stride;  /* outputs every out_stride steps (>= 1)                            */
+    double max_vel;      /* charge speed limit, m/s (<= 0: c/100)                            */
+    int32_t ring_depth;  /* stored steps per dipole (0: automatic, power of two)             */
+    int32_t reserved;    /* must be 0                                                       */
+} lw_run_opts;
+
+/* Runs `steps` RK4 steps of Eq. (LO_equation) for n_inst independent
+ * instances; instance k holds dipoles [h_inst_off[k], h_inst_off[k+1]) of
+ * h_dip.  Each dipole is driven by the component along its axis of the total
+ * field at its origin of the other dipoles' charges in its instance, read at
+ * their retarded times from the stored history (linear interpolation between
+ * steps; static at d0 before t = 0).  All dipoles advance together.
+ * Outputs (device FP64, [steps/out_stride + 1][n_dip], row k = step k*stride):
+ *   d_moment  moment d along the axis (required)
+ *   d_ddot    d d/dt                    (nullable)
+ *   d_energy  energy of Eq. (dipoleE)   (nullable)
+ *   d_drive   drive field E_d           (nullable)
+ * Asynchronous: speed-limit, non-finite and history errors are reported by
+ * lw_sync_status(). */
+lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
+                        int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts,
+                        double *d_moment, double *d_ddot, double *d_energy, double *d_drive,
+                        void *stream);
+
+/* Collective decay rates and frequency shift of two-dipole instances from a
+ * finished run's moments (Sec. 2.4, Eq. (KE)): the sum and difference of the
+ * two moments are the in-phase and anti-phase normal modes; each is fitted,
+ * after skipping `skip_steps` steps, by order-2 linear prediction with a lag of
+ * a quarter period of omega_ref, giving its complex frequency.
+ *   h_moment  host FP64 [n_rows][n_dip] (the d_moment output copied back)
+ *   h_out     host FP64 [n_inst][5]: gamma+, gamma-, omega+, omega-,
+ *             delta_omega = (omega+ - omega-)/2.  A mode whose RMS is below
+ *             1e-6 of the other's is NaN, and delta_omega then falls back to
+ *             omega+ - omega_ref (or omega_ref - omega-).  Instances that do
+ *             not hold exactly two dipoles get NaN.
+ * Host only; synchronous. */
+lw_status lw_pair_modes(const double *h_moment, int64_t n_rows, int32_t n_dip, const int32_t *h_inst_off,
+                        int32_t n_inst, double dt, int64_t out_stride, const double *h_omega_ref,
+                        const int64_t *h_skip_steps, double *h_out);
+
+/* Free-space energy decay rate gamma_0 = q^2 omega0^2 / (6 pi eps0 c^3 m)
+ * (Sec. 2.3) of an oscillator with reduced mass m. */
+double lw_gamma0(double q, double m, double omega0);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LW_H */

@@ -1,0 +1,452 @@
+// lw_api.cpp -- host runtime and C ABI of liblw.so (see include/lw.h).
+//
+// The context owns a growable device workspace, a pinned staging buffer for
+// the small host-side inputs (trajectories, times, oscillator records) and a
+// device error word that oscillator kernels latch errors into.  Every call
+// validates its arguments on the host, stages its inputs, and enqueues the
+// preparation and compute kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lw_device.hpp"
+#include "lw_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lw_status fail(lw_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+#define LW_HIP(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess) return fail(LW_E_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr double C_LIGHT = 299792458.0;
+constexpr double EPS0 = 8.8541878128e-12;
+constexpr double PI = 3.14159265358979323846;
+
+bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+double norm3(const double *v) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+bool unit3(const double *v) { return std::fabs(norm3(v) - 1.0) <= 1e-9; }
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+struct lw_ctx {
+    int device = 0;
+    void *d_work = nullptr;
+    size_t work_cap = 0;
+    void *h_stage = nullptr;
+    size_t stage_cap = 0;
+    hipEvent_t stage_evt = nullptr;
+    bool stage_pending = false;
+    uint32_t *d_err = nullptr;
+    lw::FieldLaunch field_launch{256, 4};
+};
+
+namespace {
+
+// Device workspace of at least `bytes`; reallocation waits for the stream so
+// no enqueued kernel still reads the old buffer.
+lw_status ensure_work(lw_ctx *ctx, size_t bytes, hipStream_t s)
+{
+    if (bytes <= ctx->work_cap) return LW_OK;
+    LW_HIP(hipStreamSynchronize(s));
+    if (ctx->d_work) LW_HIP(hipFree(ctx->d_work));
+    ctx->d_work = nullptr;
+    ctx->work_cap = 0;
+    size_t cap = align_up(std::max(bytes, (size_t)1 << 20), (size_t)1 << 20);
+    if (hipMalloc(&ctx->d_work, cap) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LW_E_NOMEM, "device workspace allocation of " + std::to_string(cap) + " bytes failed");
+    }
+    ctx->work_cap = cap;
+    return LW_OK;
+}
+
+// Pinned staging of at least `bytes`, free for writing (the previous upload
+// from it has completed).
+lw_status acquire_stage(lw_ctx *ctx, size_t bytes)
+{
+    if (ctx->stage_pending) {
+        LW_HIP(hipEventSynchronize(ctx->stage_evt));
+        ctx->stage_pending = false;
+    }
+    if (bytes <= ctx->stage_cap) return LW_OK;
+    if (ctx->h_stage) LW_HIP(hipHostFree(ctx->h_stage));
+    ctx->h_stage = nullptr;
+    ctx->stage_cap = 0;
+    size_t cap = align_up(std::max(bytes, (size_t)1 << 16), (size_t)1 << 16);
+    if (hipHostMalloc(&ctx->h_stage, cap, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LW_E_NOMEM, "pinned staging allocation failed");
+    }
+    ctx->stage_cap = cap;
+    return LW_OK;
+}
+
+lw_status upload(lw_ctx *ctx, void *d_dst, size_t bytes, hipStream_t s)
+{
+    LW_HIP(hipMemcpyAsync(d_dst, ctx->h_stage, bytes, hipMemcpyHostToDevice, s));
+    LW_HIP(hipEventRecord(ctx->stage_evt, s));
+    ctx->stage_pending = true;
+    return LW_OK;
+}
+
+lw_status check_traj(const lw_traj &T, int idx, double t_max)
+{
+    const std::string who = "charge " + std::to_string(idx) + ": ";
+    if (T.kind < LW_STATIONARY || T.kind > LW_ACCEL) return fail(LW_E_INVALID, who + "unknown trajectory kind");
+    if (!std::isfinite(T.q) || !finite3(T.c0)) return fail(LW_E_INVALID, who + "non-finite q or c0");
+    switch (T.kind) {
+    case LW_UNIFORM_VELOCITY:
+        if (!finite3(T.v)) return fail(LW_E_INVALID, who + "non-finite velocity");
+        if (!(norm3(T.v) < C_LIGHT)) return fail(LW_E_SUPERLUMINAL, who + "|v| >= c");
+        break;
+    case LW_LINEAR_OSC:
+    case LW_CIRCULAR:
+        if (!std::isfinite(T.amp) || !std::isfinite(T.omega) || !std::isfinite(T.phase) || T.amp < 0.0)
+            return fail(LW_E_INVALID, who + "bad amplitude, frequency or phase");
+        if (!unit3(T.e1)) return fail(LW_E_INVALID, who + "e1 is not a unit vector");
+        if (T.kind == LW_CIRCULAR) {
+            if (!unit3(T.e2)) return fail(LW_E_INVALID, who + "e2 is not a unit vector");
+            const double d = T.e1[0] * T.e2[0] + T.e1[1] * T.e2[1] + T.e1[2] * T.e2[2];
+            if (std::fabs(d) > 1e-9) return fail(LW_E_INVALID, who + "e1 and e2 are not orthogonal");
+        }
+        if (!(std::fabs(T.amp * T.omega) < C_LIGHT)) return fail(LW_E_SUPERLUMINAL, who + "amp*omega >= c");
+        break;
+    case LW_ACCEL:
+        if (!std::isfinite(T.accel) || T.accel < 0.0) return fail(LW_E_INVALID, who + "bad acceleration");
+        if (!unit3(T.e1)) return fail(LW_E_INVALID, who + "e1 is not a unit vector");
+        if (!(T.accel * std::max(t_max, 0.0) < C_LIGHT))
+            return fail(LW_E_SUPERLUMINAL, who + "speed reaches c before the last time");
+        break;
+    default:
+        break;
+    }
+    return LW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lw_last_error(void) { return g_last_error.c_str(); }
+
+double lw_gamma0(double q, double m, double omega0)
+{
+    return q * q * omega0 * omega0 / (6.0 * PI * EPS0 * C_LIGHT * C_LIGHT * C_LIGHT * m);
+}
+
+lw_status lw_create(lw_ctx **out, int32_t device)
+{
+    if (!out) return fail(LW_E_INVALID, "lw_create: null output pointer");
+    *out = nullptr;
+    int n = 0;
+    LW_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(LW_E_INVALID, "lw_create: no such device");
+    LW_HIP(hipSetDevice(device));
+    lw_ctx *c = new (std::nothrow) lw_ctx;
+    if (!c) return fail(LW_E_NOMEM, "lw_create: out of host memory");
+    c->device = device;
+    if (hipMalloc(&c->d_err, 256) != hipSuccess) {
+        delete c;
+        return fail(LW_E_NOMEM, "lw_create: error word allocation failed");
+    }
+    if (hipMemset(c->d_err, 0, 256) != hipSuccess || hipEventCreateWithFlags(&c->stage_evt, hipEventDisableTiming) != hipSuccess) {
+        (void)hipFree(c->d_err);
+        delete c;
+        return fail(LW_E_HIP, "lw_create: HIP initialisation failed");
+    }
+    *out = c;
+    return LW_OK;
+}
+
+lw_status lw_destroy(lw_ctx *ctx)
+{
+    if (!ctx) return LW_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->stage_evt) (void)hipEventDestroy(ctx->stage_evt);
+    if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+    if (ctx->d_work) (void)hipFree(ctx->d_work);
+    if (ctx->d_err) (void)hipFree(ctx->d_err);
+    delete ctx;
+    return LW_OK;
+}
+
+lw_status lw_sync_status(lw_ctx *ctx, void *stream)
+{
+    if (!ctx) return fail(LW_E_INVALID, "lw_sync_status: null context");
+    LW_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    LW_HIP(hipStreamSynchronize(s));
+    uint32_t e = 0;
+    LW_HIP(hipMemcpy(&e, ctx->d_err, sizeof(e), hipMemcpyDeviceToHost));
+    if (e) LW_HIP(hipMemset(ctx->d_err, 0, sizeof(uint32_t)));
+    if (e & 8u) return fail(LW_E_NONFINITE, "an oscillator state became non-finite");
+    if (e & 4u) return fail(LW_E_VELOCITY, "a dipole charge exceeded the speed limit");
+    if (e & 1u) return fail(LW_E_HISTORY, "a retarded time fell outside the stored history");
+    if (e & 2u) return fail(LW_E_NOCONV, "a retarded-time solve did not converge");
+    return LW_OK;
+}
+
+lw_status lw_fields(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, const double *d_pts, int64_t n_pts,
+                    const double *h_times, int32_t n_times, const lw_opts *opts, void *d_out, uint32_t *d_flags,
+                    void *stream)
+{
+    if (!ctx || !opts) return fail(LW_E_INVALID, "lw_fields: null context or options");
+    if (n_charges < 1 || !h_charges) return fail(LW_E_INVALID, "lw_fields: need at least one charge");
+    if (n_pts < 0 || n_times < 0) return fail(LW_E_INVALID, "lw_fields: negative size");
+    if (opts->precision != LW_FP64 && opts->precision != LW_MIXED)
+        return fail(LW_E_INVALID, "lw_fields: unknown precision");
+    if (opts->field_kind < LW_FIELD_TOTAL || opts->field_kind > LW_FIELD_RADIATION)
+        return fail(LW_E_INVALID, "lw_fields: unknown field kind");
+    if (opts->max_iter < 0 || opts->max_iter > 100000 || opts->reserved != 0 || std::isnan(opts->mask_radius))
+        return fail(LW_E_INVALID, "lw_fields: bad options");
+    if (n_pts == 0 || n_times == 0) return LW_OK;
+    if (!d_pts || !d_out || !h_times) return fail(LW_E_INVALID, "lw_fields: null buffer");
+    if (n_times > 65535 * 64) return fail(LW_E_INVALID, "lw_fields: too many times");
+    double t_max = -INFINITY;
+    for (int i = 0; i < n_times; ++i) {
+        if (!std::isfinite(h_times[i])) return fail(LW_E_INVALID, "lw_fields: non-finite time");
+        t_max = std::max(t_max, h_times[i]);
+    }
+    for (int c = 0; c < n_charges; ++c) {
+        lw_status st = check_traj(h_charges[c], c, t_max);
+        if (st != LW_OK) return st;
+    }
+    LW_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+
+    const size_t ch_bytes = align_up(sizeof(lw_traj) * (size_t)n_charges, 256);
+    const size_t tm_bytes = align_up(sizeof(double) * (size_t)n_times, 256);
+    const size_t rec_bytes = align_up(lw::src_rec_bytes() * (size_t)n_charges * (size_t)n_times, 256);
+    lw_status st = ensure_work(ctx, ch_bytes + tm_bytes + rec_bytes, s);
+    if (st != LW_OK) return st;
+    st = acquire_stage(ctx, ch_bytes + tm_bytes);
+    if (st != LW_OK) return st;
+    char *stage = (char *)ctx->h_stage;
+    std::memcpy(stage, h_charges, sizeof(lw_traj) * (size_t)n_charges);
+    std::memcpy(stage + ch_bytes, h_times, sizeof(double) * (size_t)n_times);
+    char *work = (char *)ctx->d_work;
+    st = upload(ctx, work, ch_bytes + tm_bytes, s);
+    if (st != LW_OK) return st;
+    const lw_traj *d_ch = (const lw_traj *)work;
+    const double *d_times = (const double *)(work + ch_bytes);
+    lw::SrcRec *d_recs = (lw::SrcRec *)(work + ch_bytes + tm_bytes);
+
+    const double mask_r = opts->mask_radius < 0.0 ? 1e-10 : opts->mask_radius;
+    const double tol_rel = opts->precision == LW_FP64 ? 4.0 * 2.220446049250313e-16 : 2.3283064365386963e-10;
+    LW_HIP(lw::launch_prep(d_ch, n_charges, d_times, n_times, d_recs, d_flags, n_pts, s));
+    LW_HIP(lw::launch_fields(d_recs, n_charges, d_pts, n_pts, n_times, *opts, tol_rel, mask_r, d_out, d_flags,
+                             ctx->field_launch, s));
+    return LW_OK;
+}
+
+lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
+                        int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts, double *d_moment,
+                        double *d_ddot, double *d_energy, double *d_drive, void *stream)
+{
+    if (!ctx || !opts || !h_dip || !h_inst_off || !d_moment) return fail(LW_E_INVALID, "lw_dipole_run: null argument");
+    if (n_dip < 1 || n_inst < 1) return fail(LW_E_INVALID, "lw_dipole_run: need at least one dipole and instance");
+    if (h_inst_off[0] != 0 || h_inst_off[n_inst] != n_dip)
+        return fail(LW_E_INVALID, "lw_dipole_run: instance offsets must run from 0 to n_dip");
+    if (!(dt > 0.0) || !std::isfinite(dt) || steps < 0) return fail(LW_E_INVALID, "lw_dipole_run: bad dt or steps");
+    if (opts->precision != LW_FP64) return fail(LW_E_INVALID, "lw_dipole_run: oscillator runs are FP64 only");
+    if (opts->dt_policy != LW_DT_STRICT && opts->dt_policy != LW_DT_EXTRAPOLATE)
+        return fail(LW_E_INVALID, "lw_dipole_run: unknown dt policy");
+    if (opts->out_stride < 1 || opts->reserved != 0 || opts->ring_depth < 0 ||
+        (opts->ring_depth & (opts->ring_depth - 1)) != 0 || !std::isfinite(opts->max_vel))
+        return fail(LW_E_INVALID, "lw_dipole_run: bad options");
+    for (int i = 0; i < n_dip; ++i) {
+        const lw_dipole &D = h_dip[i];
+        if (!finite3(D.origin) || !unit3(D.axis) || !(D.omega0 > 0.0) || !std::isfinite(D.omega0) ||
+            !(D.q > 0.0) || !std::isfinite(D.q) || !(D.m1 > 0.0) || !(D.m2 > 0.0) || !std::isfinite(D.m1) ||
+            !std::isfinite(D.m2) || !std::isfinite(D.d0))
+            return fail(LW_E_INVALID, "lw_dipole_run: bad parameters for dipole " + std::to_string(i));
+    }
+    // separations inside each instance: distinct origins, the dt rule, and the
+    // longest light travel time (history depth)
+    double max_sep = 0.0;
+    int max_n = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const int a0 = h_inst_off[k], a1 = h_inst_off[k + 1];
+        if (a1 < a0) return fail(LW_E_INVALID, "lw_dipole_run: decreasing instance offsets");
+        max_n = std::max(max_n, a1 - a0);
+        for (int a = a0; a < a1; ++a)
+            for (int b = a + 1; b < a1; ++b) {
+                const double d[3] = {h_dip[a].origin[0] - h_dip[b].origin[0], h_dip[a].origin[1] - h_dip[b].origin[1],
+                                     h_dip[a].origin[2] - h_dip[b].origin[2]};
+                const double r = norm3(d);
+                if (!(r > 0.0)) return fail(LW_E_INVALID, "lw_dipole_run: two dipoles share an origin");
+                if (opts->dt_policy == LW_DT_STRICT && !(C_LIGHT * dt < r))
+                    return fail(LW_E_DT_TOO_LARGE, "lw_dipole_run: c*dt is not below the separation of dipoles " +
+                                                       std::to_string(a) + " and " + std::to_string(b));
+                max_sep = std::max(max_sep, r);
+            }
+    }
+    // depth: the longest retarded time (plus the charges' own excursion) in
+    // steps, two interpolation neighbours and one step of slack
+    const double need = std::ceil(2.0 * max_sep / C_LIGHT / dt) + 3.0;
+    if (need > (double)(1 << 24)) return fail(LW_E_INVALID, "lw_dipole_run: dt too small for the separations");
+    int ring = 4;
+    while (ring < (int)need) ring <<= 1;
+    if (opts->ring_depth) {
+        if (opts->ring_depth < (int)need)
+            return fail(LW_E_INVALID, "lw_dipole_run: ring_depth below the longest retarded time");
+        ring = opts->ring_depth;
+    }
+    if (steps == 0 && !d_moment) return LW_OK;
+    LW_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+
+    // instances whose ring fits in LDS run with an LDS ring, the others with
+    // their ring in the device workspace
+    const int lds_limit = 64 * 1024;
+    std::vector<int32_t> lds_list, glb_list;
+    std::vector<int64_t> glb_off;
+    int max_lds_n = 0, max_glb_n = 0;
+    int64_t glb_doubles = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const int n = h_inst_off[k + 1] - h_inst_off[k];
+        if (n == 0) continue;
+        if (lw::ring_lds_bytes(n, ring) <= lds_limit) {
+            lds_list.push_back(k);
+            max_lds_n = std::max(max_lds_n, n);
+        } else {
+            glb_list.push_back(k);
+            glb_off.push_back(glb_doubles);
+            glb_doubles += (int64_t)n * ring * 3;
+            max_glb_n = std::max(max_glb_n, n);
+        }
+    }
+    if (max_glb_n > 0 && lw::ring_lds_bytes(max_glb_n, 0) > lds_limit)
+        return fail(LW_E_INVALID, "lw_dipole_run: instance too large");
+
+    const size_t in_bytes = align_up(sizeof(lw_dipole) * (size_t)n_dip, 256);
+    const size_t off_bytes = align_up(sizeof(int32_t) * (size_t)(n_inst + 1), 256);
+    const size_t list_bytes = align_up(sizeof(int32_t) * (size_t)(lds_list.size() + glb_list.size() + 1), 256);
+    const size_t roff_bytes = align_up(sizeof(int64_t) * (glb_off.size() + 1), 256);
+    const size_t stage_bytes = in_bytes + off_bytes + list_bytes + roff_bytes;
+    const size_t dev_bytes = align_up(lw::dip_dev_bytes() * (size_t)n_dip, 256);
+    const size_t ring_bytes = align_up(sizeof(double) * (size_t)std::max<int64_t>(glb_doubles, 1), 256);
+    lw_status st = ensure_work(ctx, stage_bytes + dev_bytes + ring_bytes, s);
+    if (st != LW_OK) return st;
+    st = acquire_stage(ctx, stage_bytes);
+    if (st != LW_OK) return st;
+    char *stage = (char *)ctx->h_stage;
+    std::memcpy(stage, h_dip, sizeof(lw_dipole) * (size_t)n_dip);
+    std::memcpy(stage + in_bytes, h_inst_off, sizeof(int32_t) * (size_t)(n_inst + 1));
+    int32_t *lists = (int32_t *)(stage + in_bytes + off_bytes);
+    std::copy(lds_list.begin(), lds_list.end(), lists);
+    std::copy(glb_list.begin(), glb_list.end(), lists + lds_list.size());
+    int64_t *roff = (int64_t *)(stage + in_bytes + off_bytes + list_bytes);
+    std::copy(glb_off.begin(), glb_off.end(), roff);
+    char *work = (char *)ctx->d_work;
+    st = upload(ctx, work, stage_bytes, s);
+    if (st != LW_OK) return st;
+    const lw_dipole *d_in = (const lw_dipole *)work;
+    const int32_t *d_off = (const int32_t *)(work + in_bytes);
+    const int32_t *d_lists = (const int32_t *)(work + in_bytes + off_bytes);
+    const int64_t *d_roff = (const int64_t *)(work + in_bytes + off_bytes + list_bytes);
+    lw::DipDev *d_dev = (lw::DipDev *)(work + stage_bytes);
+    double *d_ring = (double *)(work + stage_bytes + dev_bytes);
+
+    const double max_vel = opts->max_vel > 0.0 ? opts->max_vel : C_LIGHT / 100.0;
+    const int max_iter = 60;
+    LW_HIP(lw::launch_dipole_prep(d_in, n_dip, d_dev, s));
+    LW_HIP(lw::launch_dipole_instances(d_dev, d_off, d_lists, (int)lds_list.size(), max_lds_n, true, d_roff, d_ring,
+                                       ring, steps, opts->out_stride, dt, max_vel, max_iter, d_moment, d_ddot,
+                                       d_energy, d_drive, n_dip, ctx->d_err, s));
+    LW_HIP(lw::launch_dipole_instances(d_dev, d_off, d_lists + lds_list.size(), (int)glb_list.size(), max_glb_n,
+                                       false, d_roff, d_ring, ring, steps, opts->out_stride, dt, max_vel, max_iter,
+                                       d_moment, d_ddot, d_energy, d_drive, n_dip, ctx->d_err, s));
+    return LW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// host-side mode extraction (Sec. 2.4)
+// ---------------------------------------------------------------------------
+
+static void prony2(const std::vector<double> &x, int lag, double delta, double &gamma, double &omega)
+{
+    gamma = omega = NAN;
+    const int64_t N = (int64_t)x.size();
+    const int64_t L = lag;
+    if (N < 2 * L + 2) return;
+    // least squares for x[k+2L] = c1 x[k+L] + c0 x[k] via the 2x2 normal equations
+    long double saa = 0, sab = 0, sbb = 0, say = 0, sby = 0;
+    for (int64_t k = 0; k + 2 * L < N; ++k) {
+        const long double a = x[k + L], b = x[k], y = x[k + 2 * L];
+        saa += a * a;
+        sab += a * b;
+        sbb += b * b;
+        say += a * y;
+        sby += b * y;
+    }
+    const long double det = saa * sbb - sab * sab;
+    if (!(det != 0)) return;
+    const long double c1 = (say * sbb - sby * sab) / det;
+    const long double c0 = (saa * sby - sab * say) / det;
+    const long double disc = c1 * c1 + 4 * c0;
+    if (!(disc < 0)) return;
+    const long double r = std::sqrt(-c0);
+    const long double th = std::atan2(std::sqrt(-disc) / 2, c1 / 2);
+    gamma = (double)(-2.0L * std::log(r) / (L * (long double)delta));
+    omega = (double)(th / (L * (long double)delta));
+}
+
+lw_status lw_pair_modes(const double *h_moment, int64_t n_rows, int32_t n_dip, const int32_t *h_inst_off,
+                        int32_t n_inst, double dt, int64_t out_stride, const double *h_omega_ref,
+                        const int64_t *h_skip_steps, double *h_out)
+{
+    if (!h_moment || !h_inst_off || !h_omega_ref || !h_skip_steps || !h_out || n_rows < 1 || n_dip < 1 ||
+        n_inst < 1 || !(dt > 0.0) || out_stride < 1)
+        return fail(LW_E_INVALID, "lw_pair_modes: bad argument");
+    const double delta = dt * (double)out_stride;
+    for (int k = 0; k < n_inst; ++k) {
+        double *o = h_out + 5 * k;
+        for (int q = 0; q < 5; ++q) o[q] = NAN;
+        const int a = h_inst_off[k];
+        if (h_inst_off[k + 1] - a != 2 || a < 0 || a + 1 >= n_dip) continue;
+        const int64_t k0 = (h_skip_steps[k] + out_stride - 1) / out_stride;
+        if (k0 >= n_rows) continue;
+        std::vector<double> sp, am;
+        sp.reserve(n_rows - k0);
+        am.reserve(n_rows - k0);
+        long double ss = 0, sa = 0;
+        for (int64_t r = k0; r < n_rows; ++r) {
+            const double d1 = h_moment[r * n_dip + a], d2 = h_moment[r * n_dip + a + 1];
+            sp.push_back(d1 + d2);
+            am.push_back(d1 - d2);
+            ss += (long double)sp.back() * sp.back();
+            sa += (long double)am.back() * am.back();
+        }
+        const double w0 = h_omega_ref[k];
+        int lag = (int)std::lround(PI / (2.0 * w0 * delta));
+        if (lag < 1) lag = 1;
+        const double rs = std::sqrt((double)(ss / sp.size())), ra = std::sqrt((double)(sa / am.size()));
+        if (rs > 1e-6 * ra) prony2(sp, lag, delta, o[0], o[2]);
+        if (ra > 1e-6 * rs) prony2(am, lag, delta, o[1], o[3]);
+        if (std::isfinite(o[2]) && std::isfinite(o[3])) o[4] = 0.5 * (o[2] - o[3]);
+        else if (std::isfinite(o[2])) o[4] = o[2] - w0;
+        else if (std::isfinite(o[3])) o[4] = w0 - o[3];
+    }
+    return LW_OK;
+}
+
+}  // extern "C"

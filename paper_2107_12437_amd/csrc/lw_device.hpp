@@ -1,0 +1,329 @@
+// lw_device.hpp -- device math of the Lienard-Wiechert path for gfx950.
+//
+// Retarded time (Eq. (ret_t)) by a safeguarded Newton iteration in FP64, the
+// retarded kinematics of each trajectory family, and the Lienard-Wiechert
+// potentials and fields (Eqs. (V), (A), (E), (ECoulomb), (Eradiation), (B)) in
+// the working precision F (float for the mixed path, double for the FP64 path).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lw {
+
+// CODATA 2018
+constexpr double C_LIGHT = 299792458.0;
+constexpr double INV_C = 1.0 / 299792458.0;
+constexpr double EPS0 = 8.8541878128e-12;
+constexpr double PI = 3.14159265358979323846;
+constexpr double K_COUL = 1.0 / (4.0 * PI * EPS0);
+
+enum { K_STATIONARY = 0, K_UNIFORM_VELOCITY = 1, K_LINEAR_OSC = 2, K_CIRCULAR = 3, K_ACCEL = 4 };
+enum { F_TOTAL = 0, F_COULOMB = 1, F_RADIATION = 2 };
+enum { FLAG_MASKED = 1u, FLAG_NOCONV = 2u };
+
+// Per (time, charge) source record, written by the preparation kernel and read
+// wave-uniformly (scalar loads) by the field kernels.
+struct alignas(16) SrcRec {
+    int32_t kind;
+    int32_t pad_;
+    double kq;        // q / (4 pi eps0)
+    double t;         // observation time
+    double c0[3];
+    double e1[3];
+    double e2[3];
+    double e3[3];     // e1 x e2
+    double amp, omega;
+    double cT, sT;    // cos, sin of Theta = omega t + phase
+    double accel;
+    double Lmax;      // accel: distance travelled along e1 by time t
+    double v[3];
+    double rt[3];     // uniform velocity: position at time t
+};
+
+// Retarded kinematics seen from the observation point: R = x - r(t'), its
+// length D, velocity and acceleration of the charge at t' (Sec. 2.1).
+struct Kin {
+    double R[3];
+    double D;
+    double v[3];
+    double a[3];
+    uint32_t flags;
+};
+
+// sin and cos of a small angle |x| <= 0.75 from their Taylor series (terms
+// through x^17 and x^16; the truncation error is below 1e-18).
+__device__ __forceinline__ void sincos_small(double x, double &s, double &c)
+{
+    const double x2 = x * x;
+    double ps = -1.0 / 355687428096000.0;          // -1/17!
+    ps = fma(ps, x2, 1.0 / 1307674368000.0);       //  1/15!
+    ps = fma(ps, x2, -1.0 / 6227020800.0);         // -1/13!
+    ps = fma(ps, x2, 1.0 / 39916800.0);            //  1/11!
+    ps = fma(ps, x2, -1.0 / 362880.0);             // -1/9!
+    ps = fma(ps, x2, 1.0 / 5040.0);                //  1/7! (sign below)
+    ps = fma(ps, x2, -1.0 / 120.0);
+    ps = fma(ps, x2, 1.0 / 6.0);
+    // ps now holds 1/3! - x^2/5! + ...; sin x = x - x^3 * ps
+    s = fma(-x * x2, ps, x);
+    double pc = 1.0 / 20922789888000.0;            //  1/16!
+    pc = fma(pc, x2, -1.0 / 87178291200.0);        // -1/14!
+    pc = fma(pc, x2, 1.0 / 479001600.0);           //  1/12!
+    pc = fma(pc, x2, -1.0 / 3628800.0);            // -1/10!
+    pc = fma(pc, x2, 1.0 / 40320.0);               //  1/8!
+    pc = fma(pc, x2, -1.0 / 720.0);                // -1/6!
+    pc = fma(pc, x2, 1.0 / 24.0);                  //  1/4!
+    pc = fma(pc, x2, -0.5);                        // -1/2!
+    c = fma(pc, x2, 1.0);
+}
+
+// Trig state (cos, sin) of theta' = Theta - omega*tau kept across Newton
+// updates: small changes rotate it, large ones recompute it.
+struct Phase {
+    double c, s;
+    __device__ __forceinline__ void set(const SrcRec &S, double tau)
+    {
+        double sw, cw;
+        sincos(S.omega * tau, &sw, &cw);
+        c = S.cT * cw + S.sT * sw;      // cos(Theta - w tau)
+        s = S.sT * cw - S.cT * sw;      // sin(Theta - w tau)
+    }
+    __device__ __forceinline__ void advance(const SrcRec &S, double tau_new, double dtau)
+    {
+        const double ang = -S.omega * dtau;    // theta' moves by -omega * dtau
+        if (fabs(ang) <= 0.75) {
+            double sa, ca;
+            sincos_small(ang, sa, ca);
+            const double cn = c * ca - s * sa;
+            const double sn = s * ca + c * sa;
+            c = cn;
+            s = sn;
+        } else {
+            set(S, tau_new);
+        }
+    }
+};
+
+// One safeguarded Newton update of g(tau) = c tau - D(tau), g' = c - dD/dtau,
+// inside the bracket [lo, hi] (g < 0 below the root, > 0 above it; g' >= c -
+// |v| > 0).  Returns the next iterate; a step leaving the bracket bisects it.
+__device__ __forceinline__ double newton_step(double tau, double D, double dD, double &lo, double &hi)
+{
+    const double g = C_LIGHT * tau - D;
+    if (g < 0.0) lo = tau; else hi = tau;
+    double tn = tau - g / (C_LIGHT - dD);
+    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    return tn;
+}
+
+__device__ __forceinline__ bool converged(double tn, double tau, double tol_rel)
+{
+    return fabs(tn - tau) <= tol_rel * tn;
+}
+
+// --- circular orbit: r = c0 + amp (cos th e1 + sin th e2), th = Theta - w tau ---
+__device__ __forceinline__ void solve_circular(const SrcRec &S, const double w[3], int max_iter,
+                                               double tol_rel, Kin &k)
+{
+    const double A = S.amp, om = S.omega;
+    const double w1 = w[0] * S.e1[0] + w[1] * S.e1[1] + w[2] * S.e1[2];
+    const double w2 = w[0] * S.e2[0] + w[1] * S.e2[1] + w[2] * S.e2[2];
+    const double w3 = w[0] * S.e3[0] + w[1] * S.e3[1] + w[2] * S.e3[2];
+    const double rho = sqrt(w1 * w1 + w2 * w2);
+    const double WA = w1 * w1 + w2 * w2 + w3 * w3 + A * A;
+    // the distance to the orbit lies between these, so c tau does too
+    double lo = sqrt(w3 * w3 + (rho - A) * (rho - A)) * INV_C;
+    double hi = sqrt(w3 * w3 + (rho + A) * (rho + A)) * INV_C;
+    double tau = fmin(fmax(sqrt(WA) * INV_C, lo), hi);
+    Phase ph;
+    ph.set(S, tau);
+    bool ok = (hi == lo);
+    for (int it = 0; it < max_iter && !ok; ++it) {
+        const double P = w1 * ph.c + w2 * ph.s;
+        const double D = sqrt(fmax(WA - 2.0 * A * P, 0.0));
+        const double Q = w2 * ph.c - w1 * ph.s;              // n . v = A w Q / D
+        const double dD = (D > 0.0) ? A * om * Q / D : 0.0;
+        const double tn = newton_step(tau, D, dD, lo, hi);
+        ph.advance(S, tn, tn - tau);
+        ok = converged(tn, tau, tol_rel);
+        tau = tn;
+    }
+    k.flags = ok ? 0u : FLAG_NOCONV;
+    double ro[3], vo[3];
+    for (int i = 0; i < 3; ++i) {
+        ro[i] = A * (ph.c * S.e1[i] + ph.s * S.e2[i]);
+        vo[i] = A * (-ph.s * S.e1[i] + ph.c * S.e2[i]);
+        k.R[i] = w[i] - ro[i];
+        k.v[i] = om * vo[i];
+        k.a[i] = -om * om * ro[i];
+    }
+    k.D = sqrt(k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2]);
+}
+
+// --- linear oscillation: r = c0 + amp cos th e1 ---
+__device__ __forceinline__ void solve_linear(const SrcRec &S, const double w[3], int max_iter,
+                                             double tol_rel, Kin &k)
+{
+    const double A = S.amp, om = S.omega;
+    const double w1 = w[0] * S.e1[0] + w[1] * S.e1[1] + w[2] * S.e1[2];
+    const double W2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    const double perp2 = fmax(W2 - w1 * w1, 0.0);
+    const double u = fmin(fmax(w1, -A), A);
+    double lo = sqrt(perp2 + (w1 - u) * (w1 - u)) * INV_C;
+    double hi = sqrt(W2 + A * A + 2.0 * A * fabs(w1)) * INV_C;
+    double tau = fmin(fmax(sqrt(W2 + 0.5 * A * A) * INV_C, lo), hi);
+    Phase ph;
+    ph.set(S, tau);
+    bool ok = (hi == lo);
+    for (int it = 0; it < max_iter && !ok; ++it) {
+        const double x1 = w1 - A * ph.c;                     // R . e1
+        const double D = sqrt(fmax(perp2 + x1 * x1, 0.0));
+        const double dD = (D > 0.0) ? -A * om * ph.s * x1 / D : 0.0;
+        const double tn = newton_step(tau, D, dD, lo, hi);
+        ph.advance(S, tn, tn - tau);
+        ok = converged(tn, tau, tol_rel);
+        tau = tn;
+    }
+    k.flags = ok ? 0u : FLAG_NOCONV;
+    for (int i = 0; i < 3; ++i) {
+        k.R[i] = w[i] - A * ph.c * S.e1[i];
+        k.v[i] = -A * om * ph.s * S.e1[i];
+        k.a[i] = -A * om * om * ph.c * S.e1[i];
+    }
+    k.D = sqrt(k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2]);
+}
+
+// --- uniform acceleration from rest at t = 0 along e1 ---
+__device__ __forceinline__ void solve_accel(const SrcRec &S, const double w[3], int max_iter,
+                                            double tol_rel, Kin &k)
+{
+    const double acc = S.accel, L = S.Lmax, t = S.t;
+    const double w1 = w[0] * S.e1[0] + w[1] * S.e1[1] + w[2] * S.e1[2];
+    const double W2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    const double perp2 = fmax(W2 - w1 * w1, 0.0);
+    // positions up to time t fill the segment [0, L] along e1
+    const double u = fmin(fmax(w1, 0.0), L);
+    double lo = sqrt(perp2 + (w1 - u) * (w1 - u)) * INV_C;
+    double hi = fmax(sqrt(W2), sqrt(perp2 + (w1 - L) * (w1 - L))) * INV_C;
+    double tau = fmin(fmax(sqrt(perp2 + (w1 - L) * (w1 - L)) * INV_C, lo), hi);
+    bool ok = (hi == lo);
+    for (int it = 0; it < max_iter && !ok; ++it) {
+        const double tp = t - tau;
+        const double s = (tp > 0.0) ? 0.5 * acc * tp * tp : 0.0;   // distance along e1
+        const double vel = (tp > 0.0) ? acc * tp : 0.0;
+        const double x1 = w1 - s;
+        const double D = sqrt(fmax(perp2 + x1 * x1, 0.0));
+        const double dD = (D > 0.0) ? vel * x1 / D : 0.0;
+        const double tn = newton_step(tau, D, dD, lo, hi);
+        ok = converged(tn, tau, tol_rel);
+        tau = tn;
+    }
+    k.flags = ok ? 0u : FLAG_NOCONV;
+    const double tp = t - tau;
+    const double s = (tp >= 0.0) ? 0.5 * acc * tp * tp : 0.0;
+    const double vel = (tp >= 0.0) ? acc * tp : 0.0;
+    const double ac = (tp >= 0.0) ? acc : 0.0;
+    for (int i = 0; i < 3; ++i) {
+        k.R[i] = w[i] - s * S.e1[i];
+        k.v[i] = vel * S.e1[i];
+        k.a[i] = ac * S.e1[i];
+    }
+    k.D = sqrt(k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2]);
+}
+
+// --- uniform velocity: |wt + v tau| = c tau has a closed-form root ---
+__device__ __forceinline__ void solve_uniform(const SrcRec &S, const double x[3], Kin &k)
+{
+    double wt[3];
+    for (int i = 0; i < 3; ++i) wt[i] = x[i] - S.rt[i];
+    const double vv = S.v[0] * S.v[0] + S.v[1] * S.v[1] + S.v[2] * S.v[2];
+    const double wv = wt[0] * S.v[0] + wt[1] * S.v[1] + wt[2] * S.v[2];
+    const double ww = wt[0] * wt[0] + wt[1] * wt[1] + wt[2] * wt[2];
+    const double den = C_LIGHT * C_LIGHT - vv;
+    const double sq = sqrt(wv * wv + den * ww);
+    // the two algebraically equal forms, chosen to avoid cancellation
+    const double tau = (wv >= 0.0) ? (wv + sq) / den : ww / (sq - wv);
+    for (int i = 0; i < 3; ++i) {
+        k.R[i] = wt[i] + S.v[i] * tau;
+        k.v[i] = S.v[i];
+        k.a[i] = 0.0;
+    }
+    k.D = sqrt(k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2]);
+    k.flags = 0u;
+}
+
+__device__ __forceinline__ void retarded(const SrcRec &S, const double x[3], int max_iter, double tol_rel,
+                                         Kin &k)
+{
+    double w[3] = {x[0] - S.c0[0], x[1] - S.c0[1], x[2] - S.c0[2]};
+    switch (S.kind) {
+    case K_CIRCULAR: solve_circular(S, w, max_iter, tol_rel, k); break;
+    case K_LINEAR_OSC: solve_linear(S, w, max_iter, tol_rel, k); break;
+    case K_ACCEL: solve_accel(S, w, max_iter, tol_rel, k); break;
+    case K_UNIFORM_VELOCITY: solve_uniform(S, x, k); break;
+    default:
+        for (int i = 0; i < 3; ++i) { k.R[i] = w[i]; k.v[i] = 0.0; k.a[i] = 0.0; }
+        k.D = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        k.flags = 0u;
+        break;
+    }
+}
+
+template <typename F> __device__ __forceinline__ F recip(F x);
+template <> __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
+
+// Lienard-Wiechert outputs of one charge from its retarded kinematics, in
+// precision F: out = (Phi, A, E, B).  With u = n - beta and kappa = 1 - n.beta,
+// the radiation term's double cross product expands (BAC-CAB, n.u = kappa) to
+//   n x (u x beta_dot) = u (n . beta_dot) - kappa beta_dot,
+// so E = kq / (kappa^3 R) [u ((1 - beta^2)/R + n.beta_dot / c) - kappa beta_dot / c]
+// for the total field (Eq. (E)); the Coulomb and radiation parts keep their
+// own terms.  B = n x E / c (Eq. (B)), Phi = kq / (kappa R) (Eq. (V)),
+// A = Phi beta / c (Eq. (A) in SI form).
+template <typename F>
+__device__ __forceinline__ void lw_terms(const Kin &k, double kq, int field_kind, F out[10])
+{
+    const F iD = recip<F>((F)k.D);
+    const F n0 = (F)k.R[0] * iD, n1 = (F)k.R[1] * iD, n2 = (F)k.R[2] * iD;
+    const F b0 = (F)(k.v[0] * INV_C), b1 = (F)(k.v[1] * INV_C), b2 = (F)(k.v[2] * INV_C);
+    const F d0 = (F)(k.a[0] * INV_C), d1 = (F)(k.a[1] * INV_C), d2 = (F)(k.a[2] * INV_C);
+    const F ic = (F)INV_C;
+    const F nb = n0 * b0 + n1 * b1 + n2 * b2;
+    const F kappa = (F)1 - nb;
+    const F bb = b0 * b0 + b1 * b1 + b2 * b2;
+    const F u0 = n0 - b0, u1 = n1 - b1, u2 = n2 - b2;
+    const F nd = n0 * d0 + n1 * d1 + n2 * d2;
+    const F ik = recip<F>(kappa);
+    const F kqD = (F)kq * iD;
+    const F phi = kqD * ik;
+    const F f = phi * ik * ik;                              // kq / (kappa^3 R)
+    F cu, cd;                                               // E = f (u cu - beta_dot cd)
+    if (field_kind == F_COULOMB) {
+        cu = ((F)1 - bb) * iD;
+        cd = (F)0;
+    } else if (field_kind == F_RADIATION) {
+        cu = nd * ic;
+        cd = kappa * ic;
+    } else {
+        cu = ((F)1 - bb) * iD + nd * ic;
+        cd = kappa * ic;
+    }
+    const F E0 = f * (u0 * cu - d0 * cd);
+    const F E1 = f * (u1 * cu - d1 * cd);
+    const F E2 = f * (u2 * cu - d2 * cd);
+    const F m0 = n0 * ic, m1 = n1 * ic, m2 = n2 * ic;     // n / c
+    const F pc = phi * ic;
+    out[0] = phi;
+    out[1] = pc * b0;
+    out[2] = pc * b1;
+    out[3] = pc * b2;
+    out[4] = E0;
+    out[5] = E1;
+    out[6] = E2;
+    out[7] = m1 * E2 - m2 * E1;
+    out[8] = m2 * E0 - m0 * E2;
+    out[9] = m0 * E1 - m1 * E0;
+}
+
+}  // namespace lw

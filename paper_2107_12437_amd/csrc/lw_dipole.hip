@@ -1,0 +1,338 @@
+// lw_dipole.hip -- self-consistent Lorentz-oscillator runs on gfx950.
+//
+// Algorithm 1 of the paper, one workgroup per independent instance, persistent
+// over all time steps.  Each step:
+//   1. every (target i, stage time, source dipole j != i, charge +/-) pair
+//      solves its retarded time against j's stored history and evaluates the
+//      Lienard-Wiechert field of Eq. (E) at R_i projected on p_i (FP64);
+//   2. the pairs of one (target, stage) are summed in a fixed order by a lane
+//      group and a shuffle tree (bitwise reproducible);
+//   3. one lane per dipole takes the RK4 step of Eq. (LO_equation), writes
+//      (d, d_dot, d_ddot) at t_{n+1} into the history ring and the outputs.
+// The history ring holds the last `ring` steps of every dipole of the
+// instance (in LDS when it fits); its depth covers the longest light travel
+// time inside the instance, so step n+1 overwrites a slot no retarded time can
+// reach any more.
+#include <math.h>
+
+#include "lw_device.hpp"
+#include "lw_internal.hpp"
+
+namespace lw {
+
+struct DipDev {
+    double origin[3];
+    double axis[3];
+    double omega0;
+    double q;
+    double f;        // q^2 / m  (m = m1 m2 / (m1 + m2), Eq. (eff_mass))
+    double gamma0;   // q^2 omega0^2 / (6 pi eps0 c^3 m)  (Sec. 2.3)
+    double cfp;      // offset of the +q charge per unit moment: m2 / (m1 + m2) / q   (Eq. (r_1))
+    double cfm;      // offset of the -q charge per unit moment: -m1 / (m1 + m2) / q  (Eq. (r_2))
+    double vfac;     // charge speed per unit d_dot: max(m1, m2) / (m1 + m2) / q
+    double d0;
+};
+
+size_t dip_dev_bytes() { return sizeof(DipDev); }
+
+__global__ void dipole_prep_kernel(const lw_dipole *__restrict__ in, int n, DipDev *__restrict__ dev)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const lw_dipole &D = in[i];
+    DipDev o;
+    for (int k = 0; k < 3; ++k) {
+        o.origin[k] = D.origin[k];
+        o.axis[k] = D.axis[k];
+    }
+    const double M = D.m1 + D.m2;
+    const double m = D.m1 * D.m2 / M;
+    o.omega0 = D.omega0;
+    o.q = D.q;
+    o.f = D.q * D.q / m;
+    o.gamma0 = D.q * D.q * D.omega0 * D.omega0 / (6.0 * PI * EPS0 * C_LIGHT * C_LIGHT * C_LIGHT * m);
+    o.cfp = D.m2 / M / D.q;
+    o.cfm = -D.m1 / M / D.q;
+    o.vfac = fmax(D.m1, D.m2) / M / D.q;
+    o.d0 = D.d0;
+    dev[i] = o;
+}
+
+hipError_t launch_dipole_prep(const lw_dipole *d_in, int n, DipDev *d_dev, hipStream_t s)
+{
+    hipLaunchKernelGGL(dipole_prep_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d_in, n, d_dev);
+    return hipGetLastError();
+}
+
+// Per-dipole constants of the instance, staged in LDS.
+struct DipLds {
+    double ox, oy, oz;
+    double px, py, pz;
+    double cfp, cfm;
+    double d0;
+};
+
+// Stored kinematics (d, d_dot, d_ddot) of source j at s steps after t = 0 (s
+// real).  Static at d0 before t = 0 (Sec. 3.2); linear interpolation between
+// stored steps (Sec. 3.1); beyond the newest step `nstep` a second-order
+// Taylor step from it (reached only when c dt exceeds a separation).
+struct Hist {
+    const double *ring;   // [ring][n][3]
+    int n;
+    int mask;             // ring - 1
+    double dt;
+};
+
+__device__ __forceinline__ void hist_at(const Hist &H, int j, double d0, int64_t nstep, double s, double out[3],
+                                        uint32_t &err)
+{
+    if (s < 0.0) {
+        out[0] = d0;
+        out[1] = 0.0;
+        out[2] = 0.0;
+        return;
+    }
+    const double fk = floor(s);
+    const int64_t k = (int64_t)fk;
+    if (k >= nstep) {
+        const double *h = H.ring + ((int64_t)(nstep & H.mask) * H.n + j) * 3;
+        const double tt = (s - (double)nstep) * H.dt;
+        out[0] = h[0] + h[1] * tt + 0.5 * h[2] * tt * tt;
+        out[1] = h[1] + h[2] * tt;
+        out[2] = h[2];
+        return;
+    }
+    if (k + H.mask < nstep) err |= 1u;          // the slot was overwritten: history too short
+    const double u = s - fk;
+    const double *h0 = H.ring + ((int64_t)(k & H.mask) * H.n + j) * 3;
+    const double *h1 = H.ring + ((int64_t)((k + 1) & H.mask) * H.n + j) * 3;
+    out[0] = (1.0 - u) * h0[0] + u * h1[0];
+    out[1] = (1.0 - u) * h0[1] + u * h1[1];
+    out[2] = (1.0 - u) * h0[2] + u * h1[2];
+}
+
+// p_i . E of charge (cf, q_signed) of source dipole j seen at the origin of
+// target i at time (nstep + theta) dt.
+__device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double cf, double kq,
+                             int64_t nstep, double theta, int max_iter, uint32_t &err)
+{
+    const double dx = Si.ox - Sj.ox, dy = Si.oy - Sj.oy, dz = Si.oz - Sj.oz;
+    const double L2 = dx * dx + dy * dy + dz * dz;
+    const double L = sqrt(L2);
+    const double sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;     // Delta . p_j
+    const double inv_dt = 1.0 / H.dt;
+    const double base = (double)nstep + theta;
+    double lo = 0.0, hi = 2.0 * L * INV_C;
+    double tau = L * INV_C;
+    double h[3];
+    bool ok = false;
+    for (int it = 0; it < max_iter; ++it) {
+        hist_at(H, j, Sj.d0, nstep, base - tau * inv_dt, h, err);
+        const double rho = cf * h[0];                            // charge offset along p_j
+        const double D = sqrt(fmax(L2 - 2.0 * rho * sD + rho * rho, 0.0));
+        const double dD = (D > 0.0) ? cf * h[1] * (sD - rho) / D : 0.0;
+        const double tn = newton_step(tau, D, dD, lo, hi);
+        ok = converged(tn, tau, 4.0 * 2.220446049250313e-16);
+        tau = tn;
+        if (ok) break;
+    }
+    if (!ok) err |= 2u;
+    hist_at(H, j, Sj.d0, nstep, base - tau * inv_dt, h, err);
+    Kin k;
+    const double rho = cf * h[0];
+    k.R[0] = dx - rho * Sj.px;
+    k.R[1] = dy - rho * Sj.py;
+    k.R[2] = dz - rho * Sj.pz;
+    k.D = sqrt(k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2]);
+    k.v[0] = cf * h[1] * Sj.px;
+    k.v[1] = cf * h[1] * Sj.py;
+    k.v[2] = cf * h[1] * Sj.pz;
+    k.a[0] = cf * h[2] * Sj.px;
+    k.a[1] = cf * h[2] * Sj.py;
+    k.a[2] = cf * h[2] * Sj.pz;
+    k.flags = 0u;
+    double o[10];
+    lw_terms<double>(k, kq, F_TOTAL, o);
+    return o[4] * Si.px + o[5] * Si.py + o[6] * Si.pz;
+}
+
+enum { ERR_HISTORY = 1u, ERR_NOCONV = 2u, ERR_VELOCITY = 4u, ERR_NONFINITE = 8u };
+
+// Drive fields of all targets of the instance at stage times theta in
+// `thetas[0..nth)` (in steps after nstep), written to Eout[th * n + i].
+template <int BLOCK>
+__device__ void drive_all(const Hist &H, const DipLds *S, const double *qv, int n, int64_t nstep,
+                          const double *thetas, int nth, double *Eout, int max_iter, uint32_t &err)
+{
+    const int M = 2 * (n - 1);                    // pairs per (target, stage)
+    const int G = nth * n;                        // (target, stage) groups
+    int Lg = 1;
+    while (Lg < M && Lg < 64) Lg <<= 1;
+    while (Lg > 1 && Lg * G > BLOCK) Lg >>= 1;
+    const int per_pass = BLOCK / Lg;
+    const int npass = (G + per_pass - 1) / per_pass;
+    const int tid = threadIdx.x;
+    const int sub = tid % Lg;
+    for (int pass = 0; pass < npass; ++pass) {
+        const int g = pass * per_pass + tid / Lg;
+        double acc = 0.0;
+        if (g < G && M > 0) {
+            const int th = g / n, i = g % n;
+            for (int m = sub; m < M; m += Lg) {
+                const int jj = m >> 1, w = m & 1;
+                const int j = jj < i ? jj : jj + 1;
+                const double cf = w ? S[j].cfm : S[j].cfp;
+                const double kq = (w ? -qv[j] : qv[j]) * K_COUL;
+                acc += pair_drive(H, S[i], S[j], j, cf, kq, nstep, thetas[th], max_iter, err);
+            }
+        }
+        for (int off = 1; off < Lg; off <<= 1) acc += __shfl_xor(acc, off, 64);
+        if (g < G && sub == 0) Eout[g] = acc;
+    }
+}
+
+template <int BLOCK, bool RING_LDS>
+__global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__restrict__ dev,
+                                                             const int32_t *__restrict__ off,
+                                                             const int32_t *__restrict__ inst_list, int ring,
+                                                             int64_t steps, int64_t stride, double dt,
+                                                             double max_vel, int max_iter,
+                                                             double *__restrict__ ring_global,
+                                                             const int64_t *__restrict__ ring_off,
+                                                             double *__restrict__ out_d, double *__restrict__ out_v,
+                                                             double *__restrict__ out_E, double *__restrict__ out_Ed,
+                                                             int n_dip, uint32_t *__restrict__ d_err)
+{
+    extern __shared__ double lds[];
+    const int inst = inst_list[blockIdx.x];
+    const int i0 = off[inst];
+    const int n = off[inst + 1] - i0;
+    const int tid = threadIdx.x;
+    if (n <= 0) return;
+
+    // LDS layout: constants, q, Ecur, Emid/Eend, (ring), error word
+    DipLds *S = (DipLds *)lds;
+    double *qv = (double *)(S + n);
+    double *Ecur = qv + n;
+    double *Enew = Ecur + n;                    // [2][n]: mid, end
+    double *ring_lds = Enew + 2 * n;
+    double *ringp = RING_LDS ? ring_lds : ring_global + ring_off[blockIdx.x];
+    __shared__ uint32_t s_err;
+
+    for (int j = tid; j < n; j += BLOCK) {
+        const DipDev &D = dev[i0 + j];
+        S[j] = DipLds{D.origin[0], D.origin[1], D.origin[2], D.axis[0], D.axis[1], D.axis[2], D.cfp, D.cfm, D.d0};
+        qv[j] = D.q;
+    }
+    if (tid == 0) s_err = 0u;
+    __syncthreads();
+
+    Hist H{ringp, n, ring - 1, dt};
+    uint32_t err = 0u;
+
+    // t = 0: drive from the static pre-history, then sample 0 = (d0, 0, d_ddot(0))
+    {
+        const double th0[1] = {0.0};
+        drive_all<BLOCK>(H, S, qv, n, 0, th0, 1, Ecur, max_iter, err);
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += BLOCK) {
+        const DipDev &D = dev[i0 + i];
+        double *h = ringp + (int64_t)i * 3;
+        h[0] = D.d0;
+        h[1] = 0.0;
+        h[2] = D.f * Ecur[i] - D.omega0 * D.omega0 * D.d0;
+        const int gi = i0 + i;
+        out_d[gi] = D.d0;
+        if (out_v) out_v[gi] = 0.0;
+        if (out_E) out_E[gi] = D.omega0 * D.omega0 * D.d0 * D.d0 / (2.0 * D.f);
+        if (out_Ed) out_Ed[gi] = Ecur[i];
+    }
+    __syncthreads();
+
+    const double thetas[2] = {0.5, 1.0};
+    for (int64_t nstep = 0; nstep < steps; ++nstep) {
+        drive_all<BLOCK>(H, S, qv, n, nstep, thetas, 2, Enew, max_iter, err);
+        __syncthreads();
+        for (int i = tid; i < n; i += BLOCK) {
+            const DipDev &D = dev[i0 + i];
+            const double *h = ringp + ((int64_t)(nstep & (ring - 1)) * n + i) * 3;
+            const double w2 = D.omega0 * D.omega0, g = D.gamma0, f = D.f;
+            const double Em = Enew[i], Ee = Enew[n + i], Ec = Ecur[i];
+            const double y0 = h[0], y1 = h[1];
+            // classic RK4 on y = (d, d_dot), y' = (d_dot, f E_d(t) - gamma0 d_dot - w0^2 d)
+            const double k1d = y1, k1v = f * Ec - g * y1 - w2 * y0;
+            const double y0b = y0 + 0.5 * dt * k1d, y1b = y1 + 0.5 * dt * k1v;
+            const double k2d = y1b, k2v = f * Em - g * y1b - w2 * y0b;
+            const double y0c = y0 + 0.5 * dt * k2d, y1c = y1 + 0.5 * dt * k2v;
+            const double k3d = y1c, k3v = f * Em - g * y1c - w2 * y0c;
+            const double y0d = y0 + dt * k3d, y1d = y1 + dt * k3v;
+            const double k4d = y1d, k4v = f * Ee - g * y1d - w2 * y0d;
+            const double dn = y0 + dt / 6.0 * (k1d + 2.0 * k2d + 2.0 * k3d + k4d);
+            const double vn = y1 + dt / 6.0 * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
+            const double an = f * Ee - g * vn - w2 * dn;
+            double *hn = ringp + ((int64_t)((nstep + 1) & (ring - 1)) * n + i) * 3;
+            hn[0] = dn;
+            hn[1] = vn;
+            hn[2] = an;
+            Ecur[i] = Ee;
+            if (!(isfinite(dn) && isfinite(vn) && isfinite(an))) err |= ERR_NONFINITE;
+            if (max_vel > 0.0 && D.vfac * fabs(vn) > max_vel) err |= ERR_VELOCITY;
+            if ((nstep + 1) % stride == 0) {
+                const int64_t row = (nstep + 1) / stride;
+                const int64_t o = row * n_dip + i0 + i;
+                out_d[o] = dn;
+                if (out_v) out_v[o] = vn;
+                if (out_E) out_E[o] = (w2 * dn * dn + vn * vn) / (2.0 * f);
+                if (out_Ed) out_Ed[o] = Ee;
+            }
+        }
+        if (err) atomicOr(&s_err, err);
+        __syncthreads();
+        if (s_err & (ERR_NONFINITE | ERR_VELOCITY | ERR_HISTORY)) break;
+    }
+    __syncthreads();
+    if (tid == 0 && s_err) atomicOr(d_err, s_err);
+}
+
+int ring_lds_bytes(int n, int ring)
+{
+    return (int)(sizeof(DipLds) * n + sizeof(double) * 4 * n + sizeof(double) * 3 * (size_t)ring * n);
+}
+
+template <int BLOCK>
+static hipError_t launch_lo(bool ring_lds, dim3 grid, size_t shmem, hipStream_t s, const DipDev *d_dev,
+                            const int32_t *d_off, const int32_t *d_list, int ring, int64_t steps, int64_t stride,
+                            double dt, double max_vel, int max_iter, double *d_ring_global,
+                            const int64_t *d_ring_off, double *d_moment, double *d_ddot, double *d_energy,
+                            double *d_drive, int n_dip, uint32_t *d_err)
+{
+    if (ring_lds)
+        hipLaunchKernelGGL((lo_instances_kernel<BLOCK, true>), grid, dim3(BLOCK), shmem, s, d_dev, d_off, d_list,
+                           ring, steps, stride, dt, max_vel, max_iter, d_ring_global, d_ring_off, d_moment,
+                           d_ddot, d_energy, d_drive, n_dip, d_err);
+    else
+        hipLaunchKernelGGL((lo_instances_kernel<BLOCK, false>), grid, dim3(BLOCK), shmem, s, d_dev, d_off,
+                           d_list, ring, steps, stride, dt, max_vel, max_iter, d_ring_global, d_ring_off,
+                           d_moment, d_ddot, d_energy, d_drive, n_dip, d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_dipole_instances(const DipDev *d_dev, const int32_t *d_off, const int32_t *d_list, int n_list,
+                                   int max_n, bool ring_lds, const int64_t *d_ring_off, double *d_ring_global,
+                                   int ring, int64_t steps, int64_t stride, double dt, double max_vel,
+                                   int max_iter, double *d_moment, double *d_ddot, double *d_energy,
+                                   double *d_drive, int n_dip, uint32_t *d_err, hipStream_t s)
+{
+    if (n_list <= 0) return hipSuccess;
+    const size_t shmem = (size_t)ring_lds_bytes(max_n, ring_lds ? ring : 0);
+    const dim3 grid((unsigned)n_list);
+    if (max_n <= 8)
+        return launch_lo<64>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, stride, dt, max_vel,
+                             max_iter, d_ring_global, d_ring_off, d_moment, d_ddot, d_energy, d_drive, n_dip,
+                             d_err);
+    return launch_lo<256>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, stride, dt, max_vel,
+                          max_iter, d_ring_global, d_ring_off, d_moment, d_ddot, d_energy, d_drive, n_dip, d_err);
+}
+
+}  // namespace lw

@@ -1,0 +1,43 @@
+// lw_internal.hpp -- declarations shared by the host runtime and the kernel
+// translation units of liblw.so (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lw.h"
+
+namespace lw {
+
+struct SrcRec;
+
+// Launch parameters of the grid-field kernel chosen by the tuner.
+struct FieldLaunch {
+    int block;       // threads per workgroup (multiple of 64)
+    int tchunk;      // observation times handled by one workgroup
+};
+
+// Grid fields: preparation of (time, charge) records, then the fused
+// retarded-solve / Lienard-Wiechert / superposition / store kernel.
+hipError_t launch_prep(const lw_traj *d_ch, int nch, const double *d_times, int nt, SrcRec *d_recs,
+                       uint32_t *d_flags, int64_t npts, hipStream_t s);
+hipError_t launch_fields(const SrcRec *d_recs, int nch, const double *d_pts, int64_t npts, int nt,
+                         const lw_opts &o, double tol_rel, double mask_r, void *d_out, uint32_t *d_flags,
+                         const FieldLaunch &L, hipStream_t s);
+size_t src_rec_bytes();
+
+// Lorentz-oscillator runs.
+struct DipDev;     // device-side oscillator constants
+size_t dip_dev_bytes();
+int ring_lds_bytes(int n, int ring);
+hipError_t launch_dipole_prep(const lw_dipole *d_in, int n, DipDev *d_dev, hipStream_t s);
+// One launch of the per-instance persistent kernel over the instances listed in
+// d_list[0..n_list); max_n is the largest of them.  With ring_lds the history
+// ring lives in LDS, otherwise at d_ring_global + d_ring_off[block].
+hipError_t launch_dipole_instances(const DipDev *d_dev, const int32_t *d_off, const int32_t *d_list, int n_list,
+                                   int max_n, bool ring_lds, const int64_t *d_ring_off, double *d_ring_global,
+                                   int ring, int64_t steps, int64_t stride, double dt, double max_vel,
+                                   int max_iter, double *d_moment, double *d_ddot, double *d_energy,
+                                   double *d_drive, int n_dip, uint32_t *d_err, hipStream_t s);
+
+}  // namespace lw

@@ -1,0 +1,256 @@
+"""Python binding of liblw.so (argument marshalling only).
+
+Every computation happens in the HIP library; this module converts the seeded
+input records (``inputs.py`` dicts) to the C structs of ``include/lw.h``,
+allocates outputs as torch tensors on the GPU and passes raw pointers and the
+current HIP stream through the C ABI.  There is no fallback: if the library
+is missing or no GPU is present the calls raise.
+
+torch is imported before the library is loaded so that both share the HIP
+runtime that torch ships (same SONAME).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblw.so")
+
+FP64, MIXED = 0, 1
+FIELD_KINDS = {"total": 0, "coulomb": 1, "radiation": 2}
+PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+DT_POLICIES = {"strict": 0, "extrapolate": 1}
+FLAG_MASKED, FLAG_NOCONV = 1, 2
+STATUS_NAMES = {0: "LW_OK", 1: "LW_E_INVALID", 2: "LW_E_SUPERLUMINAL", 3: "LW_E_DT_TOO_LARGE",
+                4: "LW_E_VELOCITY", 5: "LW_E_NOCONV", 6: "LW_E_HIP", 7: "LW_E_NOMEM",
+                8: "LW_E_NONFINITE", 9: "LW_E_HISTORY"}
+EXPORTS = ("lw_last_error", "lw_create", "lw_destroy", "lw_sync_status", "lw_fields", "lw_dipole_run",
+           "lw_pair_modes", "lw_gamma0")
+OUTPUT_NAMES = ("phi", "Ax", "Ay", "Az", "Ex", "Ey", "Ez", "Bx", "By", "Bz")
+
+
+class LWError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Traj(ct.Structure):
+    _fields_ = [("kind", ct.c_int32), ("pad_", ct.c_int32), ("q", ct.c_double),
+                ("c0", ct.c_double * 3), ("e1", ct.c_double * 3), ("e2", ct.c_double * 3),
+                ("amp", ct.c_double), ("omega", ct.c_double), ("phase", ct.c_double),
+                ("accel", ct.c_double), ("v", ct.c_double * 3)]
+
+
+class Opts(ct.Structure):
+    _fields_ = [("precision", ct.c_int32), ("field_kind", ct.c_int32), ("max_iter", ct.c_int32),
+                ("reserved", ct.c_int32), ("mask_radius", ct.c_double)]
+
+
+class Dipole(ct.Structure):
+    _fields_ = [("origin", ct.c_double * 3), ("axis", ct.c_double * 3), ("omega0", ct.c_double),
+                ("q", ct.c_double), ("m1", ct.c_double), ("m2", ct.c_double), ("d0", ct.c_double)]
+
+
+class RunOpts(ct.Structure):
+    _fields_ = [("precision", ct.c_int32), ("dt_policy", ct.c_int32), ("out_stride", ct.c_int64),
+                ("max_vel", ct.c_double), ("ring_depth", ct.c_int32), ("reserved", ct.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads liblw.so and declares the C signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_2107_12437_amd.build`")
+    L = ct.CDLL(path)
+    vp, i32, i64, dbl = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_double
+    L.lw_last_error.restype = ct.c_char_p
+    L.lw_last_error.argtypes = []
+    L.lw_create.argtypes = [ct.POINTER(vp), i32]
+    L.lw_destroy.argtypes = [vp]
+    L.lw_sync_status.argtypes = [vp, vp]
+    L.lw_fields.argtypes = [vp, ct.POINTER(Traj), i32, vp, i64, ct.POINTER(dbl), i32, ct.POINTER(Opts), vp, vp, vp]
+    L.lw_dipole_run.argtypes = [vp, ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, i64,
+                                ct.POINTER(RunOpts), vp, vp, vp, vp, vp]
+    L.lw_pair_modes.argtypes = [ct.POINTER(dbl), i64, i32, ct.POINTER(i32), i32, dbl, i64,
+                                ct.POINTER(dbl), ct.POINTER(i64), ct.POINTER(dbl)]
+    L.lw_gamma0.restype = dbl
+    L.lw_gamma0.argtypes = [dbl, dbl, dbl]
+    for name in ("lw_create", "lw_destroy", "lw_sync_status", "lw_fields", "lw_dipole_run", "lw_pair_modes"):
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(code: int):
+    if code != 0:
+        raise LWError(code, load_library().lw_last_error().decode())
+
+
+class Context:
+    """Owns one lw_ctx (workspace, staging, error word) on a device."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the Lienard-Wiechert library needs an MI355X")
+        L = load_library()
+        self.device = int(device)
+        h = ct.c_void_p()
+        _check(L.lw_create(ct.byref(h), self.device))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            load_library().lw_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx: dict[int, Context] = {}
+
+
+def default_context(device: int | None = None) -> Context:
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _default_ctx:
+        _default_ctx[dev] = Context(dev)
+    return _default_ctx[dev]
+
+
+def _stream_ptr(device) -> ct.c_void_p:
+    return ct.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def pack_charges(charges: dict):
+    n = len(charges["kind"])
+    arr = (Traj * max(n, 1))()
+    for i in range(n):
+        t = arr[i]
+        t.kind = int(charges["kind"][i])
+        t.q = float(charges["q"][i])
+        t.c0[:] = [float(v) for v in charges["c0"][i]]
+        t.e1[:] = [float(v) for v in charges["e1"][i]]
+        t.e2[:] = [float(v) for v in charges["e2"][i]]
+        t.v[:] = [float(v) for v in charges["v"][i]]
+        t.amp = float(charges["amp"][i])
+        t.omega = float(charges["omega"][i])
+        t.phase = float(charges["phase"][i])
+        t.accel = float(charges["accel"][i])
+    return arr, n
+
+
+def pack_dipoles(dipoles: dict):
+    n = len(dipoles["omega0"])
+    arr = (Dipole * max(n, 1))()
+    for i in range(n):
+        d = arr[i]
+        d.origin[:] = [float(v) for v in dipoles["origin"][i]]
+        d.axis[:] = [float(v) for v in dipoles["axis"][i]]
+        d.omega0 = float(dipoles["omega0"][i])
+        d.q = float(dipoles["q"][i])
+        d.m1 = float(dipoles["m1"][i])
+        d.m2 = float(dipoles["m2"][i])
+        d.d0 = float(dipoles["d0"][i])
+    return arr, n
+
+
+class FieldsCall:
+    """A prepared lw_fields call: packed charges, times and options plus output
+    buffers, so repeated launches (benchmarks) pay no Python packing cost."""
+
+    def __init__(self, charges: dict, points: torch.Tensor, times, precision: str = "mixed",
+                 field_kind: str = "total", mask_radius: float = 1e-10, max_iter: int = 0,
+                 with_flags: bool = True, ctx: Context | None = None):
+        if not (isinstance(points, torch.Tensor) and points.is_cuda and points.dtype == torch.float64
+                and points.dim() == 2 and points.shape[0] == 3):
+            raise ValueError("points must be a [3, n] float64 tensor on the GPU")
+        self.points = points.contiguous()
+        self.ctx = ctx or default_context(points.device.index)
+        self.charges, self.n_charges = pack_charges(charges)
+        self.times = np.ascontiguousarray(np.atleast_1d(times), dtype=np.float64)
+        self.opts = Opts(PRECISIONS[precision], FIELD_KINDS[field_kind], int(max_iter), 0, float(mask_radius))
+        n_pts = self.points.shape[1]
+        dtype = torch.float32 if precision == "mixed" else torch.float64
+        self.out = torch.empty((len(self.times), 10, n_pts), dtype=dtype, device=points.device)
+        self.flags = torch.empty(n_pts, dtype=torch.int32, device=points.device) if with_flags else None
+        self.n_pts = n_pts
+
+    def launch(self):
+        L = load_library()
+        _check(L.lw_fields(self.ctx.handle, self.charges, self.n_charges, ct.c_void_p(self.points.data_ptr()),
+                           self.n_pts, self.times.ctypes.data_as(ct.POINTER(ct.c_double)), len(self.times),
+                           ct.byref(self.opts), ct.c_void_p(self.out.data_ptr()),
+                           ct.c_void_p(self.flags.data_ptr()) if self.flags is not None else None,
+                           _stream_ptr(self.points.device)))
+        return self.out, self.flags
+
+
+def fields(charges: dict, points: torch.Tensor, times, precision: str = "mixed", field_kind: str = "total",
+           mask_radius: float = 1e-10, max_iter: int = 0, ctx: Context | None = None):
+    """Phi, A, E, B of the charges at points ([3, n] float64 on the GPU) and times.
+    Returns (out [n_times][10][n_pts], flags [n_pts] int32)."""
+    return FieldsCall(charges, points, times, precision, field_kind, mask_radius, max_iter, True, ctx).launch()
+
+
+def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "strict", out_stride: int = 1,
+               max_vel: float = 0.0, ring_depth: int = 0, device=None, check: bool = True,
+               ctx: Context | None = None):
+    """Self-consistent oscillator run (Algorithm 1).  Returns a dict of [n_out][n_dip]
+    float64 GPU tensors: d, d_dot, energy, Ed."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    ctx = ctx or default_context(dev.index)
+    arr, n = pack_dipoles(dipoles)
+    off = np.ascontiguousarray(inst_off, dtype=np.int32)
+    n_out = int(steps) // int(out_stride) + 1
+    res = {k: torch.empty((n_out, n), dtype=torch.float64, device=dev) for k in ("d", "d_dot", "energy", "Ed")}
+    opts = RunOpts(FP64, DT_POLICIES[policy], int(out_stride), float(max_vel), int(ring_depth), 0)
+    L = load_library()
+    _check(L.lw_dipole_run(ctx.handle, arr, n, off.ctypes.data_as(ct.POINTER(ct.c_int32)), len(off) - 1,
+                           float(dt), int(steps), ct.byref(opts), ct.c_void_p(res["d"].data_ptr()),
+                           ct.c_void_p(res["d_dot"].data_ptr()), ct.c_void_p(res["energy"].data_ptr()),
+                           ct.c_void_p(res["Ed"].data_ptr()), _stream_ptr(dev)))
+    if check:
+        sync_status(ctx, dev)
+    return res
+
+
+def sync_status(ctx: Context | None = None, device=None):
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    ctx = ctx or default_context(dev.index)
+    _check(load_library().lw_sync_status(ctx.handle, _stream_ptr(dev)))
+
+
+def pair_modes(moment, inst_off, dt: float, out_stride: int, omega_ref, skip_steps):
+    """gamma+, gamma-, omega+, omega-, delta_omega per two-dipole instance ([n_inst, 5])
+    from moments [n_rows][n_dip] (host copy of dipole_run's d)."""
+    m = np.ascontiguousarray(moment.cpu().numpy() if isinstance(moment, torch.Tensor) else moment,
+                             dtype=np.float64)
+    off = np.ascontiguousarray(inst_off, dtype=np.int32)
+    n_inst = len(off) - 1
+    w = np.ascontiguousarray(np.broadcast_to(np.asarray(omega_ref, dtype=np.float64), (n_inst,)))
+    sk = np.ascontiguousarray(np.broadcast_to(np.asarray(skip_steps, dtype=np.int64), (n_inst,)))
+    out = np.empty((n_inst, 5))
+    dp = ct.POINTER(ct.c_double)
+    _check(load_library().lw_pair_modes(m.ctypes.data_as(dp), m.shape[0], m.shape[1],
+                                        off.ctypes.data_as(ct.POINTER(ct.c_int32)), n_inst, float(dt),
+                                        int(out_stride), w.ctypes.data_as(dp),
+                                        sk.ctypes.data_as(ct.POINTER(ct.c_int64)), out.ctypes.data_as(dp)))
+    return out
+
+
+def gamma0(q: float, m: float, omega0: float) -> float:
+    return float(load_library().lw_gamma0(q, m, omega0))

@@ -1,0 +1,70 @@
+"""The C ABI library without a GPU: it loads, exports every declared entry point, its
+struct layouts match the header, and its host-only calls agree with the oracle."""
+import ctypes as ct
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2107_12437_amd import lw, inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lw.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lw_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lw.load_library()
+    names = declared_functions()
+    assert set(names) == set(lw.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_struct_layouts_match_header():
+    assert ct.sizeof(lw.Traj) == 144
+    assert ct.sizeof(lw.Dipole) == 88
+    assert ct.sizeof(lw.Opts) == 24
+    assert ct.sizeof(lw.RunOpts) == 32
+
+
+def test_gamma0_host_helper():
+    # Fig. 9 caption: 19.791 MHz for q = e, m = m_e/2 at omega_0 = 2 pi 200 THz
+    g = lw.gamma0(I.E_CHARGE, I.M_E / 2, 2 * math.pi * 200e12)
+    assert round(g / 1e6, 3) == 19.791
+
+
+def test_null_context_is_rejected_without_gpu():
+    L = lw.load_library()
+    opts = lw.Opts(0, 0, 0, 0, -1.0)
+    arr, n = lw.pack_charges(I.workload_tiny_orbit()["charges"])
+    t = (ct.c_double * 1)(0.0)
+    assert L.lw_fields(None, arr, n, None, 10, t, 1, ct.byref(opts), None, None, None) == 1
+    assert b"null" in L.lw_last_error()
+
+
+def test_pair_modes_matches_oracle_extraction():
+    """Host Prony fit of the library against the oracle's numpy fit on the same signal."""
+    import oracle as O
+    from oracle import extract as X
+    w = I.workload_dipole_pairs(n_inst=3, steps=6000, seps=[5e-9, 40e-9, 300e-9])
+    r = O.dipole_run(w["dipoles"], w["inst_off"], w["dt"], w["steps"], policy=O.DT_EXTRAPOLATE, out_stride=2)
+    w0 = w["dipoles"]["omega0"][0]
+    skips = [X.default_skip(w["dt"], s) for s in w["separations"]]
+    got = lw.pair_modes(r["d"], w["inst_off"], w["dt"], 2, w0, skips)
+    for k in range(3):
+        ref = X.pair_modes(r["d"][:, 2 * k], r["d"][:, 2 * k + 1], w["dt"], 2, w0, skips[k])
+        for j, key in enumerate(("gamma_plus", "gamma_minus", "omega_plus", "omega_minus", "delta_omega")):
+            assert abs(got[k, j] - ref[key]) <= 1e-6 * abs(ref[key]) + 1e-9 * w0, (k, key, got[k, j], ref[key])
+
+
+def test_pair_modes_rejects_bad_arguments():
+    with pytest.raises(lw.LWError) as ei:
+        lw.pair_modes(np.zeros((10, 2)), [0, 2], -1.0, 1, 1e15, 0)
+    assert ei.value.code == 1

@@ -1,0 +1,136 @@
+"""GPU parity of lw_dipole_run (Algorithm 1) against the FP64 oracle.
+
+Moments, energies and drive fields are compared element by element, relative to
+the largest magnitude of each output (the FP64 path to 1e-11: both sides are
+FP64, the difference comes from the retarded-time solver and the order of the
+pair sums); collective rates and shifts extracted from them to 1e-3.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import extract as X
+from paper_2107_12437_amd import inputs as I
+from tests.helpers import gpu_ready
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ready(), reason="needs a GPU")]
+
+TOL_STATE = 1e-11
+
+
+def gpu_run(w, policy, stride=1, **kw):
+    from paper_2107_12437_amd import lw
+    r = lw.dipole_run(w["dipoles"], w["inst_off"], w["dt"], w["steps"], policy=policy, out_stride=stride, **kw)
+    return {k: v.cpu().numpy() for k, v in r.items()}
+
+
+def oracle_run(w, policy, stride=1):
+    return O.dipole_run(w["dipoles"], w["inst_off"], w["dt"], w["steps"],
+                        policy=O.DT_EXTRAPOLATE if policy == "extrapolate" else O.DT_STRICT, out_stride=stride)
+
+
+def assert_state_close(got, ref, keys=("d", "d_dot", "energy", "Ed"), tol=TOL_STATE, what=""):
+    for k in keys:
+        scale = np.abs(ref[k]).max(axis=0, keepdims=True)
+        scale = np.where(scale > 0, scale, 1.0)
+        err = np.abs(got[k] - ref[k]) / scale
+        assert err.max() <= tol, f"{what} {k}: max relative error {err.max():.3e} at {np.unravel_index(err.argmax(), err.shape)}"
+
+
+def test_pairs_extrapolate_parity():
+    """24 two-dipole instances of the pair recipe (log-uniform 1 nm - 1 um, dt = T0/200,
+    a third of them closer than c dt) for 1,500 steps."""
+    w = I.workload_dipole_pairs(n_inst=24, steps=1500)
+    got = gpu_run(w, "extrapolate")
+    ref = oracle_run(w, "extrapolate")
+    assert_state_close(got, ref, what="pairs")
+
+
+def test_pairs_strided_outputs():
+    w = I.workload_dipole_pairs(n_inst=6, steps=1000)
+    got = gpu_run(w, "extrapolate", stride=7)
+    ref = oracle_run(w, "extrapolate", stride=7)
+    assert got["d"].shape == (1000 // 7 + 1, 12)
+    assert_state_close(got, ref, what="strided")
+
+
+def test_cluster_strict_parity():
+    """A 6-dipole cluster with random axes and omega_0 spread (STRICT dt) and a 3-dipole one."""
+    rng = I.rng_for(71)
+    a = I.cluster_dipoles(rng, 6, 25e-9, 10e-9, 2 * math.pi * 200e12, 0.01, True)
+    b = I.cluster_dipoles(rng, 3, 25e-9, 10e-9, 2 * math.pi * 200e12, 0.01, True)
+    w = {"dipoles": I.concat_dipoles([a, b]), "inst_off": np.array([0, 6, 9], np.int32),
+         "dt": 1 / 200e12 / 200, "steps": 800}
+    got = gpu_run(w, "strict")
+    ref = oracle_run(w, "strict")
+    assert_state_close(got, ref, what="cluster")
+
+
+def test_large_cluster_global_ring():
+    """A 40-dipole cluster whose history ring does not fit in LDS (ring in device memory)."""
+    rng = I.rng_for(72)
+    d = I.cluster_dipoles(rng, 40, 60e-9, 10e-9, 2 * math.pi * 200e12, 0.01, True)
+    w = {"dipoles": d, "inst_off": np.array([0, 40], np.int32), "dt": 1 / 200e12 / 200, "steps": 150}
+    got = gpu_run(w, "strict")
+    ref = oracle_run(w, "strict")
+    assert_state_close(got, ref, what="large cluster")
+
+
+def test_gamma_domega_parity():
+    """Collective rates and shift of 8 pairs extracted on the host from the GPU moments and
+    from the oracle's moments: within 1e-3."""
+    from paper_2107_12437_amd import lw
+    w = I.workload_dipole_pairs(n_inst=8, steps=8000)
+    got = gpu_run(w, "extrapolate", stride=2)
+    ref = oracle_run(w, "extrapolate", stride=2)
+    w0 = w["dipoles"]["omega0"][0]
+    skips = [X.default_skip(w["dt"], s) for s in w["separations"]]
+    modes = lw.pair_modes(got["d"], w["inst_off"], w["dt"], 2, w0, skips)
+    g0 = lw.gamma0(I.E_CHARGE, I.M_E / 2, w0)
+    for k in range(8):
+        r = X.pair_modes(ref["d"][:, 2 * k], ref["d"][:, 2 * k + 1], w["dt"], 2, w0, skips[k])
+        for j, key in enumerate(("gamma_plus", "gamma_minus", "delta_omega")):
+            jj = (0, 1, 4)[j]
+            scale = max(abs(r[key]), g0)
+            assert abs(modes[k, jj] - r[key]) <= 1e-3 * scale, (k, key, modes[k, jj], r[key])
+
+
+def test_batch_equals_single_instances():
+    """A batched run equals the same instances run one by one, bitwise, and permuting the
+    instances permutes the outputs."""
+    w = I.workload_dipole_pairs(n_inst=5, steps=300)
+    full = gpu_run(w, "extrapolate")
+    for k in range(5):
+        one = dict(w, dipoles={kk: v[2 * k:2 * k + 2] for kk, v in w["dipoles"].items()},
+                   inst_off=np.array([0, 2], np.int32))
+        g = gpu_run(one, "extrapolate")
+        for key in ("d", "d_dot", "energy", "Ed"):
+            assert np.array_equal(g[key], full[key][:, 2 * k:2 * k + 2])
+    perm = [3, 0, 4, 1, 2]
+    idx = np.concatenate([[2 * p, 2 * p + 1] for p in perm])
+    pw = dict(w, dipoles={kk: v[idx] for kk, v in w["dipoles"].items()})
+    g = gpu_run(pw, "extrapolate")
+    assert np.array_equal(g["d"], full["d"][:, idx])
+
+
+def test_error_paths():
+    from paper_2107_12437_amd import lw
+    w = I.workload_dipole_pairs(n_inst=4, steps=10, seps=[2e-9, 5e-9, 20e-9, 100e-9])
+    with pytest.raises(lw.LWError) as ei:
+        gpu_run(w, "strict")
+    assert ei.value.code == 3
+    d = I.empty_dipoles(2)
+    d["origin"][1, 0] = 20e-9
+    d["omega0"][:] = 2 * math.pi * 200e12
+    d["d0"][0] = I.E_CHARGE * 1e-8        # charge speed reaches ~2c/100
+    w = {"dipoles": d, "inst_off": np.array([0, 2], np.int32), "dt": 2.5e-17, "steps": 200}
+    with pytest.raises(lw.LWError) as ei:
+        gpu_run(w, "strict")
+    assert ei.value.code == 4
+    gpu_run(w, "strict", max_vel=0.1 * I.C_LIGHT)
+    bad = dict(w, dipoles=dict(d, axis=np.array([[1.0, 0, 0], [0.5, 0, 0]])))
+    with pytest.raises(lw.LWError) as ei:
+        gpu_run(bad, "strict")
+    assert ei.value.code == 1
