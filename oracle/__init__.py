@@ -116,7 +116,7 @@ def lw_pair(charges: dict, i: int, x, t: float, kind: int = TOTAL, mask_r: float
     return None if f else out
 
 
-def fields(charges: dict, points, times, kind: int = TOTAL, mask_r: float = 1e-10):
+def fields(charges: dict, points, times, kind: int = TOTAL, mask_radius: float = 1e-10):
     """[n_times][10][n_pts] FP64 outputs and per-point flags."""
     arr, n = pack(charges)
     pts = _f64(points)
@@ -125,7 +125,7 @@ def fields(charges: dict, points, times, kind: int = TOTAL, mask_r: float = 1e-1
     npts = pts.shape[1]
     out = np.empty((len(tms), 10, npts))
     flags = np.zeros(npts, dtype=np.uint32)
-    st = lib().or_fields(arr, n, _dp(pts), npts, _dp(tms), len(tms), int(kind), float(mask_r),
+    st = lib().or_fields(arr, n, _dp(pts), npts, _dp(tms), len(tms), int(kind), float(mask_radius),
                          _dp(out), flags.ctypes.data_as(ct.POINTER(ct.c_uint32)))
     if st:
         raise OracleError(st, "fields")

@@ -131,6 +131,12 @@ def default_context(device: int | None = None) -> Context:
     return _default_ctx[dev]
 
 
+def _as_device(device) -> torch.device:
+    if isinstance(device, torch.device):
+        return device
+    return torch.device("cuda", torch.cuda.current_device() if device is None else int(device))
+
+
 def _stream_ptr(device) -> ct.c_void_p:
     return ct.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
@@ -211,7 +217,7 @@ def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "st
                ctx: Context | None = None):
     """Self-consistent oscillator run (Algorithm 1).  Returns a dict of [n_out][n_dip]
     float64 GPU tensors: d, d_dot, energy, Ed."""
-    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    dev = _as_device(device)
     ctx = ctx or default_context(dev.index)
     arr, n = pack_dipoles(dipoles)
     off = np.ascontiguousarray(inst_off, dtype=np.int32)
@@ -229,7 +235,7 @@ def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "st
 
 
 def sync_status(ctx: Context | None = None, device=None):
-    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    dev = _as_device(device)
     ctx = ctx or default_context(dev.index)
     _check(load_library().lw_sync_status(ctx.handle, _stream_ptr(dev)))
 
