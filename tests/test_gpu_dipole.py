@@ -1,9 +1,11 @@
 """GPU parity of lw_dipole_run (Algorithm 1) against the FP64 oracle.
 
-Moments, energies and drive fields are compared element by element, relative to
-the largest magnitude of each output (the FP64 path to 1e-11: both sides are
-FP64, the difference comes from the retarded-time solver and the order of the
-pair sums); collective rates and shifts extracted from them to 1e-3.
+Moments, velocities and energies are compared element by element relative to the
+largest magnitude of each output per dipole (1e-11: both sides are FP64 and
+differ by the retarded-time solver and the order of the pair sums).  The drive
+field is the near-cancelling sum of opposite charges' fields, so it is compared
+relative to the sum of the single-charge field magnitudes (1e-13, a few hundred
+ulp).  Collective rates and shifts extracted from the moments agree to 1e-3.
 """
 import math
 
@@ -18,6 +20,7 @@ from tests.helpers import gpu_ready
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ready(), reason="needs a GPU")]
 
 TOL_STATE = 1e-11
+TOL_DRIVE = 1e-13
 
 
 def gpu_run(w, policy, stride=1, **kw):
@@ -31,12 +34,35 @@ def oracle_run(w, policy, stride=1):
                         policy=O.DT_EXTRAPOLATE if policy == "extrapolate" else O.DT_STRICT, out_stride=stride)
 
 
-def assert_state_close(got, ref, keys=("d", "d_dot", "energy", "Ed"), tol=TOL_STATE, what=""):
+def single_charge_scale(w):
+    """Per target dipole, the sum over source charges of their Coulomb field magnitude
+    k q / L^2.  The drive field is the small difference of the two charges' fields of each
+    source dipole, so its FP64 rounding error is a few ulp of this scale, not of the net."""
+    dip, off = w["dipoles"], w["inst_off"]
+    k = 1 / (4 * math.pi * 8.8541878128e-12)
+    sc = np.zeros(len(dip["omega0"]))
+    for a0, a1 in zip(off[:-1], off[1:]):
+        for i in range(a0, a1):
+            for j in range(a0, a1):
+                if i != j:
+                    L2 = np.sum((dip["origin"][i] - dip["origin"][j]) ** 2)
+                    sc[i] += 2 * k * dip["q"][j] / L2
+    return sc
+
+
+def assert_state_close(got, ref, w, keys=("d", "d_dot", "energy", "Ed"), tol=TOL_STATE, what=""):
+    """d, d_dot, energy relative to their largest magnitude per dipole (tol); Ed relative
+    to the single-charge field scale (TOL_DRIVE)."""
     for k in keys:
-        scale = np.abs(ref[k]).max(axis=0, keepdims=True)
+        if k == "Ed":
+            scale = single_charge_scale(w)[None, :]
+            t = TOL_DRIVE
+        else:
+            scale = np.abs(ref[k]).max(axis=0, keepdims=True)
+            t = tol
         scale = np.where(scale > 0, scale, 1.0)
         err = np.abs(got[k] - ref[k]) / scale
-        assert err.max() <= tol, f"{what} {k}: max relative error {err.max():.3e} at {np.unravel_index(err.argmax(), err.shape)}"
+        assert err.max() <= t, f"{what} {k}: max relative error {err.max():.3e} at {np.unravel_index(err.argmax(), err.shape)}"
 
 
 def test_pairs_extrapolate_parity():
@@ -45,7 +71,7 @@ def test_pairs_extrapolate_parity():
     w = I.workload_dipole_pairs(n_inst=24, steps=1500)
     got = gpu_run(w, "extrapolate")
     ref = oracle_run(w, "extrapolate")
-    assert_state_close(got, ref, what="pairs")
+    assert_state_close(got, ref, w, what="pairs")
 
 
 def test_pairs_strided_outputs():
@@ -53,7 +79,7 @@ def test_pairs_strided_outputs():
     got = gpu_run(w, "extrapolate", stride=7)
     ref = oracle_run(w, "extrapolate", stride=7)
     assert got["d"].shape == (1000 // 7 + 1, 12)
-    assert_state_close(got, ref, what="strided")
+    assert_state_close(got, ref, w, what="strided")
 
 
 def test_cluster_strict_parity():
@@ -65,7 +91,7 @@ def test_cluster_strict_parity():
          "dt": 1 / 200e12 / 200, "steps": 800}
     got = gpu_run(w, "strict")
     ref = oracle_run(w, "strict")
-    assert_state_close(got, ref, what="cluster")
+    assert_state_close(got, ref, w, what="cluster")
 
 
 def test_large_cluster_global_ring():
@@ -75,7 +101,7 @@ def test_large_cluster_global_ring():
     w = {"dipoles": d, "inst_off": np.array([0, 40], np.int32), "dt": 1 / 200e12 / 200, "steps": 150}
     got = gpu_run(w, "strict")
     ref = oracle_run(w, "strict")
-    assert_state_close(got, ref, what="large cluster")
+    assert_state_close(got, ref, w, what="large cluster")
 
 
 def test_gamma_domega_parity():
