@@ -79,6 +79,11 @@ def main():
     ap.add_argument("--cpu-sample-points", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dipole", action="store_true")
+    ap.add_argument("--grid-only", action="store_true",
+                    help="time only the mixed grid step (for profiler runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="run one plain device-to-device copy of BYTES and exit (calibrates the "
+                         "profiler's byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (each instance or "
@@ -96,6 +101,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {4 * n} bytes")
+        return
     w = I.workload_grid_mixed()
     pts = torch.tensor(w["points"], dtype=torch.float64, device="cuda")
     n_pts, n_ch, n_t = pts.shape[1], len(w["charges"]["kind"]), len(w["times"])
@@ -107,6 +121,8 @@ def main():
     ms_per_step = wall / args.steps * 1e3
     value = evals / (wall / args.steps)
     log(f"[bench] mixed: {ms_per_step:.3f} ms/step, kernel {kern_ms:.3f} ms, {value:.4e} evals/s")
+    if args.grid_only:
+        return
 
     fp64 = lw.FieldsCall(w["charges"], pts, w["times"], precision="fp64")
     fsteps = max(3, args.steps // 4)

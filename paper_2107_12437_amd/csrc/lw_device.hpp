@@ -61,7 +61,7 @@ __device__ __forceinline__ void sincos_small(double x, double &s, double &c)
     ps = fma(ps, x2, -1.0 / 6227020800.0);         // -1/13!
     ps = fma(ps, x2, 1.0 / 39916800.0);            //  1/11!
     ps = fma(ps, x2, -1.0 / 362880.0);             // -1/9!
-    ps = fma(ps, x2, 1.0 / 5040.0);                //  1/7! (sign below)
+    ps = fma(ps, x2, 1.0 / 5040.0);                //  1/7!
     ps = fma(ps, x2, -1.0 / 120.0);
     ps = fma(ps, x2, 1.0 / 6.0);
     // ps now holds 1/3! - x^2/5! + ...; sin x = x - x^3 * ps
@@ -104,15 +104,34 @@ struct Phase {
     }
 };
 
-// One safeguarded Newton update of g(tau) = c tau - D(tau), g' = c - dD/dtau,
-// inside the bracket [lo, hi] (g < 0 below the root, > 0 above it; g' >= c -
-// |v| > 0).  Returns the next iterate; a step leaving the bracket bisects it.
-__device__ __forceinline__ double newton_step(double tau, double D, double dD, double &lo, double &hi)
+// Root bracket of g(tau) = c tau - D(tau): g < 0 below the root, g > 0 above
+// (g' >= c - |v| > 0).  The ends start as geometric bounds; an end is
+// "evaluated" once an iterate has landed there.
+struct Bracket {
+    double lo, hi;
+    bool lo_ev, hi_ev;
+    __device__ __forceinline__ Bracket(double l, double h) : lo(l), hi(h), lo_ev(false), hi_ev(false) {}
+};
+
+// One safeguarded Newton update.  An exact root, or a step below the rounding
+// of tau, returns tau itself (converged).  A step leaving the bracket goes to
+// the nearer end if that end has not been evaluated yet (the geometric bounds
+// are often close to the root), otherwise bisects.
+__device__ __forceinline__ double newton_step(double tau, double D, double dD, Bracket &b)
 {
     const double g = C_LIGHT * tau - D;
-    if (g < 0.0) lo = tau; else hi = tau;
+    if (g == 0.0) return tau;
+    if (g < 0.0) {
+        b.lo = tau;
+        b.lo_ev = true;
+    } else {
+        b.hi = tau;
+        b.hi_ev = true;
+    }
     double tn = tau - g / (C_LIGHT - dD);
-    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    if (tn == tau) return tau;
+    if (tn < b.lo) tn = b.lo_ev ? 0.5 * (b.lo + b.hi) : b.lo;
+    else if (tn > b.hi) tn = b.hi_ev ? 0.5 * (b.lo + b.hi) : b.hi;
     return tn;
 }
 
@@ -132,18 +151,17 @@ __device__ __forceinline__ void solve_circular(const SrcRec &S, const double w[3
     const double rho = sqrt(w1 * w1 + w2 * w2);
     const double WA = w1 * w1 + w2 * w2 + w3 * w3 + A * A;
     // the distance to the orbit lies between these, so c tau does too
-    double lo = sqrt(w3 * w3 + (rho - A) * (rho - A)) * INV_C;
-    double hi = sqrt(w3 * w3 + (rho + A) * (rho + A)) * INV_C;
-    double tau = fmin(fmax(sqrt(WA) * INV_C, lo), hi);
+    Bracket b(sqrt(w3 * w3 + (rho - A) * (rho - A)) * INV_C, sqrt(w3 * w3 + (rho + A) * (rho + A)) * INV_C);
+    double tau = fmin(fmax(sqrt(WA) * INV_C, b.lo), b.hi);
     Phase ph;
     ph.set(S, tau);
-    bool ok = (hi == lo);
+    bool ok = (b.hi == b.lo);
     for (int it = 0; it < max_iter && !ok; ++it) {
         const double P = w1 * ph.c + w2 * ph.s;
         const double D = sqrt(fmax(WA - 2.0 * A * P, 0.0));
         const double Q = w2 * ph.c - w1 * ph.s;              // n . v = A w Q / D
         const double dD = (D > 0.0) ? A * om * Q / D : 0.0;
-        const double tn = newton_step(tau, D, dD, lo, hi);
+        const double tn = newton_step(tau, D, dD, b);
         ph.advance(S, tn, tn - tau);
         ok = converged(tn, tau, tol_rel);
         tau = tn;
@@ -169,17 +187,16 @@ __device__ __forceinline__ void solve_linear(const SrcRec &S, const double w[3],
     const double W2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
     const double perp2 = fmax(W2 - w1 * w1, 0.0);
     const double u = fmin(fmax(w1, -A), A);
-    double lo = sqrt(perp2 + (w1 - u) * (w1 - u)) * INV_C;
-    double hi = sqrt(W2 + A * A + 2.0 * A * fabs(w1)) * INV_C;
-    double tau = fmin(fmax(sqrt(W2 + 0.5 * A * A) * INV_C, lo), hi);
+    Bracket b(sqrt(perp2 + (w1 - u) * (w1 - u)) * INV_C, sqrt(W2 + A * A + 2.0 * A * fabs(w1)) * INV_C);
+    double tau = fmin(fmax(sqrt(W2 + 0.5 * A * A) * INV_C, b.lo), b.hi);
     Phase ph;
     ph.set(S, tau);
-    bool ok = (hi == lo);
+    bool ok = (b.hi == b.lo);
     for (int it = 0; it < max_iter && !ok; ++it) {
         const double x1 = w1 - A * ph.c;                     // R . e1
         const double D = sqrt(fmax(perp2 + x1 * x1, 0.0));
         const double dD = (D > 0.0) ? -A * om * ph.s * x1 / D : 0.0;
-        const double tn = newton_step(tau, D, dD, lo, hi);
+        const double tn = newton_step(tau, D, dD, b);
         ph.advance(S, tn, tn - tau);
         ok = converged(tn, tau, tol_rel);
         tau = tn;
@@ -203,10 +220,9 @@ __device__ __forceinline__ void solve_accel(const SrcRec &S, const double w[3], 
     const double perp2 = fmax(W2 - w1 * w1, 0.0);
     // positions up to time t fill the segment [0, L] along e1
     const double u = fmin(fmax(w1, 0.0), L);
-    double lo = sqrt(perp2 + (w1 - u) * (w1 - u)) * INV_C;
-    double hi = fmax(sqrt(W2), sqrt(perp2 + (w1 - L) * (w1 - L))) * INV_C;
-    double tau = fmin(fmax(sqrt(perp2 + (w1 - L) * (w1 - L)) * INV_C, lo), hi);
-    bool ok = (hi == lo);
+    Bracket b(sqrt(perp2 + (w1 - u) * (w1 - u)) * INV_C, fmax(sqrt(W2), sqrt(perp2 + (w1 - L) * (w1 - L))) * INV_C);
+    double tau = fmin(fmax(sqrt(perp2 + (w1 - L) * (w1 - L)) * INV_C, b.lo), b.hi);
+    bool ok = (b.hi == b.lo);
     for (int it = 0; it < max_iter && !ok; ++it) {
         const double tp = t - tau;
         const double s = (tp > 0.0) ? 0.5 * acc * tp * tp : 0.0;   // distance along e1
@@ -214,7 +230,7 @@ __device__ __forceinline__ void solve_accel(const SrcRec &S, const double w[3], 
         const double x1 = w1 - s;
         const double D = sqrt(fmax(perp2 + x1 * x1, 0.0));
         const double dD = (D > 0.0) ? vel * x1 / D : 0.0;
-        const double tn = newton_step(tau, D, dD, lo, hi);
+        const double tn = newton_step(tau, D, dD, b);
         ok = converged(tn, tau, tol_rel);
         tau = tn;
     }

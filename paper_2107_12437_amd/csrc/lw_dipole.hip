@@ -122,7 +122,7 @@ __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, 
     const double sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;     // Delta . p_j
     const double inv_dt = 1.0 / H.dt;
     const double base = (double)nstep + theta;
-    double lo = 0.0, hi = 2.0 * L * INV_C;
+    Bracket b(0.0, 2.0 * L * INV_C);
     double tau = L * INV_C;
     double h[3];
     bool ok = false;
@@ -131,7 +131,7 @@ __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, 
         const double rho = cf * h[0];                            // charge offset along p_j
         const double D = sqrt(fmax(L2 - 2.0 * rho * sD + rho * rho, 0.0));
         const double dD = (D > 0.0) ? cf * h[1] * (sD - rho) / D : 0.0;
-        const double tn = newton_step(tau, D, dD, lo, hi);
+        const double tn = newton_step(tau, D, dD, b);
         ok = converged(tn, tau, 4.0 * 2.220446049250313e-16);
         tau = tn;
         if (ok) break;
