@@ -91,7 +91,16 @@ struct Phase {
     __device__ __forceinline__ void advance(const SrcRec &S, double tau_new, double dtau)
     {
         const double ang = -S.omega * dtau;    // theta' moves by -omega * dtau
-        if (fabs(ang) <= 0.75) {
+        if (fabs(ang) <= 0x1p-8) {
+            // |ang| <= 2^-8: Taylor through x^7 and x^6 (truncation below 5e-25)
+            const double a2 = ang * ang;
+            const double sa = fma(-ang * a2, fma(fma(-a2, 1.0 / 5040.0, 1.0 / 120.0), -a2, 1.0 / 6.0), ang);
+            const double ca = fma(a2, fma(a2, fma(-a2, 1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+            const double cn = c * ca - s * sa;
+            const double sn = s * ca + c * sa;
+            c = cn;
+            s = sn;
+        } else if (fabs(ang) <= 0.75) {
             double sa, ca;
             sincos_small(ang, sa, ca);
             const double cn = c * ca - s * sa;
@@ -113,11 +122,23 @@ struct Bracket {
     __device__ __forceinline__ Bracket(double l, double h) : lo(l), hi(h), lo_ev(false), hi_ev(false) {}
 };
 
-// One safeguarded Newton update.  An exact root, or a step below the rounding
-// of tau, returns tau itself (converged).  A step leaving the bracket goes to
-// the nearer end if that end has not been evaluated yet (the geometric bounds
-// are often close to the root), otherwise bisects.
-__device__ __forceinline__ double newton_step(double tau, double D, double dD, Bracket &b)
+// Reciprocal for derivative terms and step sizes (v_rcp_f64 refined by one
+// Newton-Raphson step): these only steer the iteration, the root itself is
+// decided by g = c tau - D, which is evaluated exactly.
+__device__ __forceinline__ double rcp_steer(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// One safeguarded Halley update of g(tau) = c tau - D(tau) with g' = c - D'
+// and g'' = -D''.  An exact root, or a step below the rounding of tau, returns
+// tau itself (converged).  The Halley step is used while its denominator stays
+// above g'^2 (the step is then at most twice Newton's), else Newton's.  A step
+// leaving the bracket goes to the nearer end if that end has not been
+// evaluated yet (the geometric bounds are often close to the root), otherwise
+// bisects.
+__device__ __forceinline__ double halley_step(double tau, double D, double dD, double ddD, Bracket &b)
 {
     const double g = C_LIGHT * tau - D;
     if (g == 0.0) return tau;
@@ -128,16 +149,27 @@ __device__ __forceinline__ double newton_step(double tau, double D, double dD, B
         b.hi = tau;
         b.hi_ev = true;
     }
-    double tn = tau - g / (C_LIGHT - dD);
+    const double gp = C_LIGHT - dD;
+    const double den = fma(2.0 * gp, gp, g * ddD);          // 2 g'^2 - g g''
+    double tn = (den > gp * gp) ? tau - 2.0 * g * gp * rcp_steer(den) : tau - g * rcp_steer(gp);
     if (tn == tau) return tau;
     if (tn < b.lo) tn = b.lo_ev ? 0.5 * (b.lo + b.hi) : b.lo;
     else if (tn > b.hi) tn = b.hi_ev ? 0.5 * (b.lo + b.hi) : b.hi;
     return tn;
 }
 
-__device__ __forceinline__ bool converged(double tn, double tau, double tol_rel)
+// Plain Newton update (same safeguards), for sources whose D'' is not tracked.
+__device__ __forceinline__ double newton_step(double tau, double D, double dD, Bracket &b)
 {
-    return fabs(tn - tau) <= tol_rel * tn;
+    return halley_step(tau, D, dD, 0.0, b);
+}
+
+// Converged when the last step is below tol_rel (relative), or when both
+// bracket ends have been evaluated and lie within 4 tol_rel of each other
+// (rounding noise in D can make the last steps alternate around the root).
+__device__ __forceinline__ bool converged(double tn, double tau, double tol_rel, const Bracket &b)
+{
+    return fabs(tn - tau) <= tol_rel * tn || (b.lo_ev && b.hi_ev && b.hi - b.lo <= 4.0 * tol_rel * tn);
 }
 
 // --- circular orbit: r = c0 + amp (cos th e1 + sin th e2), th = Theta - w tau ---
@@ -157,13 +189,17 @@ __device__ __forceinline__ void solve_circular(const SrcRec &S, const double w[3
     ph.set(S, tau);
     bool ok = (b.hi == b.lo);
     for (int it = 0; it < max_iter && !ok; ++it) {
-        const double P = w1 * ph.c + w2 * ph.s;
-        const double D = sqrt(fmax(WA - 2.0 * A * P, 0.0));
-        const double Q = w2 * ph.c - w1 * ph.s;              // n . v = A w Q / D
-        const double dD = (D > 0.0) ? A * om * Q / D : 0.0;
-        const double tn = newton_step(tau, D, dD, b);
+        // R = x - r(t') in the orbit frame (no cancellation near the orbit)
+        const double x1 = w1 - A * ph.c, x2 = w2 - A * ph.s;
+        const double D = sqrt(x1 * x1 + x2 * x2 + w3 * w3);
+        const double iD = (D > 0.0) ? rcp_steer(D) : 0.0;
+        const double Q = ph.c * x2 - ph.s * x1;              // D' = n . v = A w Q / D
+        const double P = w1 * ph.c + w2 * ph.s;              // D'' = (A w^2 P - D'^2) / D
+        const double dD = A * om * Q * iD;
+        const double ddD = (A * om * om * P - dD * dD) * iD;
+        const double tn = halley_step(tau, D, dD, ddD, b);
         ph.advance(S, tn, tn - tau);
-        ok = converged(tn, tau, tol_rel);
+        ok = converged(tn, tau, tol_rel, b);
         tau = tn;
     }
     k.flags = ok ? 0u : FLAG_NOCONV;
@@ -184,8 +220,9 @@ __device__ __forceinline__ void solve_linear(const SrcRec &S, const double w[3],
 {
     const double A = S.amp, om = S.omega;
     const double w1 = w[0] * S.e1[0] + w[1] * S.e1[1] + w[2] * S.e1[2];
-    const double W2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
-    const double perp2 = fmax(W2 - w1 * w1, 0.0);
+    const double p0 = w[0] - w1 * S.e1[0], p1 = w[1] - w1 * S.e1[1], p2 = w[2] - w1 * S.e1[2];
+    const double perp2 = p0 * p0 + p1 * p1 + p2 * p2;       // distance^2 from the axis line
+    const double W2 = perp2 + w1 * w1;
     const double u = fmin(fmax(w1, -A), A);
     Bracket b(sqrt(perp2 + (w1 - u) * (w1 - u)) * INV_C, sqrt(W2 + A * A + 2.0 * A * fabs(w1)) * INV_C);
     double tau = fmin(fmax(sqrt(W2 + 0.5 * A * A) * INV_C, b.lo), b.hi);
@@ -194,11 +231,14 @@ __device__ __forceinline__ void solve_linear(const SrcRec &S, const double w[3],
     bool ok = (b.hi == b.lo);
     for (int it = 0; it < max_iter && !ok; ++it) {
         const double x1 = w1 - A * ph.c;                     // R . e1
-        const double D = sqrt(fmax(perp2 + x1 * x1, 0.0));
-        const double dD = (D > 0.0) ? -A * om * ph.s * x1 / D : 0.0;
-        const double tn = newton_step(tau, D, dD, b);
+        const double D = sqrt(perp2 + x1 * x1);
+        const double iD = (D > 0.0) ? rcp_steer(D) : 0.0;
+        const double v1 = A * om * ph.s;                     // d x1 / d tau = -v1
+        const double dD = -v1 * x1 * iD;
+        const double ddD = (v1 * v1 + x1 * A * om * om * ph.c - dD * dD) * iD;
+        const double tn = halley_step(tau, D, dD, ddD, b);
         ph.advance(S, tn, tn - tau);
-        ok = converged(tn, tau, tol_rel);
+        ok = converged(tn, tau, tol_rel, b);
         tau = tn;
     }
     k.flags = ok ? 0u : FLAG_NOCONV;
@@ -216,8 +256,9 @@ __device__ __forceinline__ void solve_accel(const SrcRec &S, const double w[3], 
 {
     const double acc = S.accel, L = S.Lmax, t = S.t;
     const double w1 = w[0] * S.e1[0] + w[1] * S.e1[1] + w[2] * S.e1[2];
-    const double W2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
-    const double perp2 = fmax(W2 - w1 * w1, 0.0);
+    const double p0 = w[0] - w1 * S.e1[0], p1 = w[1] - w1 * S.e1[1], p2 = w[2] - w1 * S.e1[2];
+    const double perp2 = p0 * p0 + p1 * p1 + p2 * p2;       // distance^2 from the line of motion
+    const double W2 = perp2 + w1 * w1;
     // positions up to time t fill the segment [0, L] along e1
     const double u = fmin(fmax(w1, 0.0), L);
     Bracket b(sqrt(perp2 + (w1 - u) * (w1 - u)) * INV_C, fmax(sqrt(W2), sqrt(perp2 + (w1 - L) * (w1 - L))) * INV_C);
@@ -228,10 +269,12 @@ __device__ __forceinline__ void solve_accel(const SrcRec &S, const double w[3], 
         const double s = (tp > 0.0) ? 0.5 * acc * tp * tp : 0.0;   // distance along e1
         const double vel = (tp > 0.0) ? acc * tp : 0.0;
         const double x1 = w1 - s;
-        const double D = sqrt(fmax(perp2 + x1 * x1, 0.0));
-        const double dD = (D > 0.0) ? vel * x1 / D : 0.0;
-        const double tn = newton_step(tau, D, dD, b);
-        ok = converged(tn, tau, tol_rel);
+        const double D = sqrt(perp2 + x1 * x1);
+        const double iD = (D > 0.0) ? rcp_steer(D) : 0.0;
+        const double dD = vel * x1 * iD;                      // d x1 / d tau = vel
+        const double ddD = (vel * vel - ((tp > 0.0) ? acc * x1 : 0.0) - dD * dD) * iD;
+        const double tn = halley_step(tau, D, dD, ddD, b);
+        ok = converged(tn, tau, tol_rel, b);
         tau = tn;
     }
     k.flags = ok ? 0u : FLAG_NOCONV;

@@ -130,9 +130,9 @@ __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, 
         hist_at(H, j, Sj.d0, nstep, base - tau * inv_dt, h, err);
         const double rho = cf * h[0];                            // charge offset along p_j
         const double D = sqrt(fmax(L2 - 2.0 * rho * sD + rho * rho, 0.0));
-        const double dD = (D > 0.0) ? cf * h[1] * (sD - rho) / D : 0.0;
+        const double dD = (D > 0.0) ? cf * h[1] * (sD - rho) * rcp_steer(D) : 0.0;
         const double tn = newton_step(tau, D, dD, b);
-        ok = converged(tn, tau, 4.0 * 2.220446049250313e-16);
+        ok = converged(tn, tau, 4.0 * 2.220446049250313e-16, b);
         tau = tn;
         if (ok) break;
     }
