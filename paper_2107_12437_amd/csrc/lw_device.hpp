@@ -41,11 +41,10 @@ struct alignas(16) SrcRec {
     double rt[3];     // uniform velocity: position at time t
 };
 
-// Retarded kinematics seen from the observation point: R = x - r(t'), its
-// length D, velocity and acceleration of the charge at t' (Sec. 2.1).
+// Retarded kinematics seen from the observation point: R = x - r(t'),
+// velocity and acceleration of the charge at t' (Sec. 2.1).
 struct Kin {
     double R[3];
-    double D;
     double v[3];
     double a[3];
     uint32_t flags;
@@ -77,6 +76,31 @@ __device__ __forceinline__ void sincos_small(double x, double &s, double &c)
     c = fma(pc, x2, 1.0);
 }
 
+// sin and cos for |x| < 2^30: x = k pi/2 + r with pi/2 split into three
+// doubles (FMA Cody-Waite reduction, |r| <= pi/4), the Taylor kernel on r, then
+// the quadrant's swap and signs.
+__device__ __forceinline__ void sincos_reduced(double x, double &s, double &c)
+{
+    const double P1 = 0x1.921fb54442d18p+0;     // pi/2 = P1 + P2 + P3
+    const double P2 = 0x1.1a62633145c07p-54;
+    const double P3 = -0x1.f1976b7ed8fbcp-110;
+    const double k = rint(x * 0x1.45f306dc9c883p-1);   // x * 2/pi
+    double r = fma(-k, P1, x);
+    r = fma(-k, P2, r);
+    r = fma(-k, P3, r);
+    double sr, cr;
+    sincos_small(r, sr, cr);
+    const int q = (int)k & 3;
+    const double a = (q & 1) ? cr : sr;          // |sin x|, |cos x| up to sign
+    const double b = (q & 1) ? sr : cr;
+    s = (q & 2) ? -a : a;
+    c = ((q + 1) & 2) ? -b : b;
+}
+
+// Square root for bounds and starting values only (v_sqrt_f64, relative error
+// near 2^-22): callers widen what they derive from it.
+__device__ __forceinline__ double sqrt_rough(double x) { return __builtin_amdgcn_sqrt(x); }
+
 // Trig state (cos, sin) of theta' = Theta - omega*tau kept across Newton
 // updates: small changes rotate it, large ones recompute it.
 struct Phase {
@@ -84,7 +108,7 @@ struct Phase {
     __device__ __forceinline__ void set(const SrcRec &S, double tau)
     {
         double sw, cw;
-        sincos(S.omega * tau, &sw, &cw);
+        sincos_reduced(S.omega * tau, sw, cw);
         c = S.cT * cw + S.sT * sw;      // cos(Theta - w tau)
         s = S.sT * cw - S.cT * sw;      // sin(Theta - w tau)
     }
@@ -137,7 +161,7 @@ __device__ __forceinline__ double rcp_steer(double x)
 // above g'^2 (the step is then at most twice Newton's), else Newton's.  A step
 // leaving the bracket goes to the nearer end if that end has not been
 // evaluated yet (the geometric bounds are often close to the root), otherwise
-// bisects.
+// bisects; so does a step onto an end already evaluated.
 __device__ __forceinline__ double halley_step(double tau, double D, double dD, double ddD, Bracket &b)
 {
     const double g = C_LIGHT * tau - D;
@@ -153,8 +177,9 @@ __device__ __forceinline__ double halley_step(double tau, double D, double dD, d
     const double den = fma(2.0 * gp, gp, g * ddD);          // 2 g'^2 - g g''
     double tn = (den > gp * gp) ? tau - 2.0 * g * gp * rcp_steer(den) : tau - g * rcp_steer(gp);
     if (tn == tau) return tau;
-    if (tn < b.lo) tn = b.lo_ev ? 0.5 * (b.lo + b.hi) : b.lo;
-    else if (tn > b.hi) tn = b.hi_ev ? 0.5 * (b.lo + b.hi) : b.hi;
+    // landing on an evaluated end again would cycle: bisect instead
+    if (tn <= b.lo) tn = b.lo_ev ? 0.5 * (b.lo + b.hi) : b.lo;
+    else if (tn >= b.hi) tn = b.hi_ev ? 0.5 * (b.lo + b.hi) : b.hi;
     return tn;
 }
 
@@ -180,11 +205,13 @@ __device__ __forceinline__ void solve_circular(const SrcRec &S, const double w[3
     const double w1 = w[0] * S.e1[0] + w[1] * S.e1[1] + w[2] * S.e1[2];
     const double w2 = w[0] * S.e2[0] + w[1] * S.e2[1] + w[2] * S.e2[2];
     const double w3 = w[0] * S.e3[0] + w[1] * S.e3[1] + w[2] * S.e3[2];
-    const double rho = sqrt(w1 * w1 + w2 * w2);
+    const double rho = sqrt_rough(w1 * w1 + w2 * w2);
     const double WA = w1 * w1 + w2 * w2 + w3 * w3 + A * A;
     // the distance to the orbit lies between these, so c tau does too
-    Bracket b(sqrt(w3 * w3 + (rho - A) * (rho - A)) * INV_C, sqrt(w3 * w3 + (rho + A) * (rho + A)) * INV_C);
-    double tau = fmin(fmax(sqrt(WA) * INV_C, b.lo), b.hi);
+    // (widened by 1e-6 to cover the rough square roots)
+    Bracket b(sqrt_rough(w3 * w3 + (rho - A) * (rho - A)) * (INV_C * (1.0 - 1e-6)),
+              sqrt_rough(w3 * w3 + (rho + A) * (rho + A)) * (INV_C * (1.0 + 1e-6)));
+    double tau = fmin(fmax(sqrt_rough(WA) * INV_C, b.lo), b.hi);
     Phase ph;
     ph.set(S, tau);
     bool ok = (b.hi == b.lo);
@@ -211,7 +238,6 @@ __device__ __forceinline__ void solve_circular(const SrcRec &S, const double w[3
         k.v[i] = om * vo[i];
         k.a[i] = -om * om * ro[i];
     }
-    k.D = sqrt(k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2]);
 }
 
 // --- linear oscillation: r = c0 + amp cos th e1 ---
@@ -224,8 +250,9 @@ __device__ __forceinline__ void solve_linear(const SrcRec &S, const double w[3],
     const double perp2 = p0 * p0 + p1 * p1 + p2 * p2;       // distance^2 from the axis line
     const double W2 = perp2 + w1 * w1;
     const double u = fmin(fmax(w1, -A), A);
-    Bracket b(sqrt(perp2 + (w1 - u) * (w1 - u)) * INV_C, sqrt(W2 + A * A + 2.0 * A * fabs(w1)) * INV_C);
-    double tau = fmin(fmax(sqrt(W2 + 0.5 * A * A) * INV_C, b.lo), b.hi);
+    Bracket b(sqrt_rough(perp2 + (w1 - u) * (w1 - u)) * (INV_C * (1.0 - 1e-6)),
+              sqrt_rough(W2 + A * A + 2.0 * A * fabs(w1)) * (INV_C * (1.0 + 1e-6)));
+    double tau = fmin(fmax(sqrt_rough(W2 + 0.5 * A * A) * INV_C, b.lo), b.hi);
     Phase ph;
     ph.set(S, tau);
     bool ok = (b.hi == b.lo);
@@ -247,7 +274,6 @@ __device__ __forceinline__ void solve_linear(const SrcRec &S, const double w[3],
         k.v[i] = -A * om * ph.s * S.e1[i];
         k.a[i] = -A * om * om * ph.c * S.e1[i];
     }
-    k.D = sqrt(k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2]);
 }
 
 // --- uniform acceleration from rest at t = 0 along e1 ---
@@ -261,8 +287,10 @@ __device__ __forceinline__ void solve_accel(const SrcRec &S, const double w[3], 
     const double W2 = perp2 + w1 * w1;
     // positions up to time t fill the segment [0, L] along e1
     const double u = fmin(fmax(w1, 0.0), L);
-    Bracket b(sqrt(perp2 + (w1 - u) * (w1 - u)) * INV_C, fmax(sqrt(W2), sqrt(perp2 + (w1 - L) * (w1 - L))) * INV_C);
-    double tau = fmin(fmax(sqrt(perp2 + (w1 - L) * (w1 - L)) * INV_C, b.lo), b.hi);
+    const double Dnow = sqrt_rough(perp2 + (w1 - L) * (w1 - L));   // distance to the position at t
+    Bracket b(sqrt_rough(perp2 + (w1 - u) * (w1 - u)) * (INV_C * (1.0 - 1e-6)),
+              fmax(sqrt_rough(W2), Dnow) * (INV_C * (1.0 + 1e-6)));
+    double tau = fmin(fmax(Dnow * INV_C, b.lo), b.hi);
     bool ok = (b.hi == b.lo);
     for (int it = 0; it < max_iter && !ok; ++it) {
         const double tp = t - tau;
@@ -287,7 +315,6 @@ __device__ __forceinline__ void solve_accel(const SrcRec &S, const double w[3], 
         k.v[i] = vel * S.e1[i];
         k.a[i] = ac * S.e1[i];
     }
-    k.D = sqrt(k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2]);
 }
 
 // --- uniform velocity: |wt + v tau| = c tau has a closed-form root ---
@@ -307,7 +334,6 @@ __device__ __forceinline__ void solve_uniform(const SrcRec &S, const double x[3]
         k.v[i] = S.v[i];
         k.a[i] = 0.0;
     }
-    k.D = sqrt(k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2]);
     k.flags = 0u;
 }
 
@@ -322,7 +348,6 @@ __device__ __forceinline__ void retarded(const SrcRec &S, const double x[3], int
     case K_UNIFORM_VELOCITY: solve_uniform(S, x, k); break;
     default:
         for (int i = 0; i < 3; ++i) { k.R[i] = w[i]; k.v[i] = 0.0; k.a[i] = 0.0; }
-        k.D = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
         k.flags = 0u;
         break;
     }
@@ -340,11 +365,27 @@ template <> __device__ __forceinline__ double recip<double>(double x) { return 1
 // for the total field (Eq. (E)); the Coulomb and radiation parts keep their
 // own terms.  B = n x E / c (Eq. (B)), Phi = kq / (kappa R) (Eq. (V)),
 // A = Phi beta / c (Eq. (A) in SI form).
-template <typename F>
-__device__ __forceinline__ void lw_terms(const Kin &k, double kq, int field_kind, F out[10])
+// |R| and 1/|R| in precision F: FP32 through v_rsq_f32, FP64 correctly rounded.
+__device__ __forceinline__ void dist_inv(float R0, float R1, float R2, float &D, float &iD)
 {
-    const F iD = recip<F>((F)k.D);
-    const F n0 = (F)k.R[0] * iD, n1 = (F)k.R[1] * iD, n2 = (F)k.R[2] * iD;
+    const float D2 = R0 * R0 + R1 * R1 + R2 * R2;
+    iD = __builtin_amdgcn_rsqf(D2);
+    D = D2 * iD;
+}
+__device__ __forceinline__ void dist_inv(double R0, double R1, double R2, double &D, double &iD)
+{
+    D = sqrt(R0 * R0 + R1 * R1 + R2 * R2);
+    iD = 1.0 / D;
+}
+
+// Returns the retarded distance |R| in precision F (for masking).
+template <typename F>
+__device__ __forceinline__ F lw_terms(const Kin &k, double kq, int field_kind, F out[10])
+{
+    const F R0 = (F)k.R[0], R1 = (F)k.R[1], R2 = (F)k.R[2];
+    F D, iD;
+    dist_inv(R0, R1, R2, D, iD);
+    const F n0 = R0 * iD, n1 = R1 * iD, n2 = R2 * iD;
     const F b0 = (F)(k.v[0] * INV_C), b1 = (F)(k.v[1] * INV_C), b2 = (F)(k.v[2] * INV_C);
     const F d0 = (F)(k.a[0] * INV_C), d1 = (F)(k.a[1] * INV_C), d2 = (F)(k.a[2] * INV_C);
     const F ic = (F)INV_C;
@@ -383,6 +424,7 @@ __device__ __forceinline__ void lw_terms(const Kin &k, double kq, int field_kind
     out[7] = m1 * E2 - m2 * E1;
     out[8] = m2 * E0 - m0 * E2;
     out[9] = m0 * E1 - m1 * E0;
+    return D;
 }
 
 }  // namespace lw

@@ -143,7 +143,6 @@ __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, 
     k.R[0] = dx - rho * Sj.px;
     k.R[1] = dy - rho * Sj.py;
     k.R[2] = dz - rho * Sj.pz;
-    k.D = sqrt(k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2]);
     k.v[0] = cf * h[1] * Sj.px;
     k.v[1] = cf * h[1] * Sj.py;
     k.v[2] = cf * h[1] * Sj.pz;

@@ -83,9 +83,9 @@ __global__ __launch_bounds__(256) void fields_kernel(const SrcRec *__restrict__ 
             Kin k;
             retarded(R[c], x, max_iter, tol_rel, k);
             fl |= k.flags;
-            if (!(k.D >= mask_r)) fl |= FLAG_MASKED;
             F o[10];
-            lw_terms<F>(k, R[c].kq, field_kind, o);
+            const F D = lw_terms<F>(k, R[c].kq, field_kind, o);
+            if (!(D >= (F)mask_r)) fl |= FLAG_MASKED;
 #pragma unroll
             for (int j = 0; j < 10; ++j) {
                 if constexpr (sizeof(F) == 4) {
