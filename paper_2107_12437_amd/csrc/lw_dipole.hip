@@ -81,15 +81,17 @@ struct Hist {
     int n;
     int mask;             // ring - 1
     double dt;
+    double inv_dt;
 };
 
 __device__ __forceinline__ void hist_at(const Hist &H, int j, double d0, int64_t nstep, double s, double out[3],
-                                        uint32_t &err)
+                                        double &slope, uint32_t &err)
 {
     if (s < 0.0) {
         out[0] = d0;
         out[1] = 0.0;
         out[2] = 0.0;
+        slope = 0.0;
         return;
     }
     const double fk = floor(s);
@@ -100,6 +102,7 @@ __device__ __forceinline__ void hist_at(const Hist &H, int j, double d0, int64_t
         out[0] = h[0] + h[1] * tt + 0.5 * h[2] * tt * tt;
         out[1] = h[1] + h[2] * tt;
         out[2] = h[2];
+        slope = out[1];
         return;
     }
     if (k + H.mask < nstep) err |= 1u;          // the slot was overwritten: history too short
@@ -109,10 +112,13 @@ __device__ __forceinline__ void hist_at(const Hist &H, int j, double d0, int64_t
     out[0] = (1.0 - u) * h0[0] + u * h1[0];
     out[1] = (1.0 - u) * h0[1] + u * h1[1];
     out[2] = (1.0 - u) * h0[2] + u * h1[2];
+    slope = (h1[0] - h0[0]) * H.inv_dt;           // d/dt' of the interpolated moment
 }
 
 // p_i . E of charge (cf, q_signed) of source dipole j seen at the origin of
-// target i at time (nstep + theta) dt.
+// target i at time (nstep + theta) dt.  The retarded time uses the exact
+// slope of the interpolated position, so Newton converges quadratically; the
+// field uses the interpolated (d, d_dot, d_ddot) at the converged time.
 __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double cf, double kq,
                              int64_t nstep, double theta, int max_iter, uint32_t &err)
 {
@@ -120,24 +126,22 @@ __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, 
     const double L2 = dx * dx + dy * dy + dz * dz;
     const double L = sqrt(L2);
     const double sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;     // Delta . p_j
-    const double inv_dt = 1.0 / H.dt;
     const double base = (double)nstep + theta;
     Bracket b(0.0, 2.0 * L * INV_C);
     double tau = L * INV_C;
-    double h[3];
+    double h[3], slope;
     bool ok = false;
     for (int it = 0; it < max_iter; ++it) {
-        hist_at(H, j, Sj.d0, nstep, base - tau * inv_dt, h, err);
+        hist_at(H, j, Sj.d0, nstep, base - tau * H.inv_dt, h, slope, err);
         const double rho = cf * h[0];                            // charge offset along p_j
         const double D = sqrt(fmax(L2 - 2.0 * rho * sD + rho * rho, 0.0));
-        const double dD = (D > 0.0) ? cf * h[1] * (sD - rho) * rcp_steer(D) : 0.0;
+        const double dD = (D > 0.0) ? cf * slope * (sD - rho) * rcp_steer(D) : 0.0;
         const double tn = newton_step(tau, D, dD, b);
         ok = converged(tn, tau, 4.0 * 2.220446049250313e-16, b);
+        if (ok) break;                                           // keep h at the last evaluated tau
         tau = tn;
-        if (ok) break;
     }
     if (!ok) err |= 2u;
-    hist_at(H, j, Sj.d0, nstep, base - tau * inv_dt, h, err);
     Kin k;
     const double rho = cf * h[0];
     k.R[0] = dx - rho * Sj.px;
@@ -226,7 +230,7 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
     if (tid == 0) s_err = 0u;
     __syncthreads();
 
-    Hist H{ringp, n, ring - 1, dt};
+    Hist H{ringp, n, ring - 1, dt, 1.0 / dt};
     uint32_t err = 0u;
 
     // t = 0: drive from the static pre-history, then sample 0 = (d0, 0, d_ddot(0))
@@ -249,14 +253,31 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
     }
     __syncthreads();
 
+    // constants of the dipole this thread advances (the first BLOCK of the instance)
+    double own_w2 = 0.0, own_g = 0.0, own_f = 0.0, own_vfac = 0.0, own_ie = 0.0;
+    if (tid < n) {
+        const DipDev &D = dev[i0 + tid];
+        own_w2 = D.omega0 * D.omega0;
+        own_g = D.gamma0;
+        own_f = D.f;
+        own_vfac = D.vfac;
+        own_ie = 0.5 / D.f;
+    }
     const double thetas[2] = {0.5, 1.0};
     for (int64_t nstep = 0; nstep < steps; ++nstep) {
         drive_all<BLOCK>(H, S, qv, n, nstep, thetas, 2, Enew, max_iter, err);
         __syncthreads();
         for (int i = tid; i < n; i += BLOCK) {
-            const DipDev &D = dev[i0 + i];
+            double w2 = own_w2, g = own_g, f = own_f, vfac = own_vfac, ie = own_ie;
+            if (i != tid) {
+                const DipDev &D = dev[i0 + i];
+                w2 = D.omega0 * D.omega0;
+                g = D.gamma0;
+                f = D.f;
+                vfac = D.vfac;
+                ie = 0.5 / D.f;
+            }
             const double *h = ringp + ((int64_t)(nstep & (ring - 1)) * n + i) * 3;
-            const double w2 = D.omega0 * D.omega0, g = D.gamma0, f = D.f;
             const double Em = Enew[i], Ee = Enew[n + i], Ec = Ecur[i];
             const double y0 = h[0], y1 = h[1];
             // classic RK4 on y = (d, d_dot), y' = (d_dot, f E_d(t) - gamma0 d_dot - w0^2 d)
@@ -276,13 +297,13 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
             hn[2] = an;
             Ecur[i] = Ee;
             if (!(isfinite(dn) && isfinite(vn) && isfinite(an))) err |= ERR_NONFINITE;
-            if (max_vel > 0.0 && D.vfac * fabs(vn) > max_vel) err |= ERR_VELOCITY;
+            if (max_vel > 0.0 && vfac * fabs(vn) > max_vel) err |= ERR_VELOCITY;
             if ((nstep + 1) % stride == 0) {
                 const int64_t row = (nstep + 1) / stride;
                 const int64_t o = row * n_dip + i0 + i;
                 out_d[o] = dn;
                 if (out_v) out_v[o] = vn;
-                if (out_E) out_E[o] = (w2 * dn * dn + vn * vn) / (2.0 * f);
+                if (out_E) out_E[o] = (w2 * dn * dn + vn * vn) * ie;
                 if (out_Ed) out_Ed[o] = Ee;
             }
         }
