@@ -35,6 +35,21 @@ FLOP_SOLVE_FP64 = 150
 # Vector ALU peak of MI355X for FP64 and for unpacked FP32: 256 CUs x 4 SIMDs
 # x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# HBM bytes per launch of fields_kernel<float> on this workload from the profiler's
+# FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0) counters, calibrated on a plain 1 GiB copy
+# (profiles/fields_kernel_mixed_grid512x512x64t.md).  Valid only for the kernel
+# sources they were taken on; reported as null once those change.
+TRAFFIC_BYTES = 680.8e6
+TRAFFIC_SOURCES_SHA = "7b9e275bd8f93068"
+
+
+def kernel_sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("lw_fields.hip", "lw_device.hpp"):
+        with open(os.path.join(ROOT, "paper_2107_12437_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def log(msg: str):
@@ -132,7 +147,8 @@ def main():
 
     achieved = evals * (FLOP_LW_FP32 + FLOP_SOLVE_FP64) / (kern_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TFLOPS, 1),
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_VALU_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_VALU_TFLOPS, 4),
+                "traffic": TRAFFIC_BYTES if kernel_sources_sha() == TRAFFIC_SOURCES_SHA else None,
                 "kernel": "fields_kernel<float>", "flop_per_eval": FLOP_LW_FP32 + FLOP_SOLVE_FP64,
                 "kernel_ms": round(kern_ms, 4)}
 
