@@ -161,7 +161,10 @@ typedef struct {
     int64_t out_stride;  /* outputs every out_stride steps (>= 1)                            */
     double max_vel;      /* charge speed limit, m/s (<= 0: c/100)                            */
     int32_t ring_depth;  /* stored steps per dipole (0: automatic, power of two)             */
-    int32_t reserved;    /* must be 0                                                       */
+    int32_t stepped_min_n; /* instances of at least this many dipoles (or whose history does
+                              not fit in LDS) advance one launch per step with one workgroup
+                              per dipole; smaller ones run whole in one workgroup
+                              (0: 48; < 0: only when the history does not fit)             */
 } lw_run_opts;
 
 /* Runs `steps` RK4 steps of Eq. (LO_equation) for n_inst independent
@@ -175,6 +178,8 @@ typedef struct {
  *   d_ddot    d d/dt                    (nullable)
  *   d_energy  energy of Eq. (dipoleE)   (nullable)
  *   d_drive   drive field E_d           (nullable)
+ * Small instances run concurrently with the stepped ones on a second stream of
+ * the context that is joined back into `stream` before the call's work ends.
  * Asynchronous: speed-limit, non-finite and history errors are reported by
  * lw_sync_status(). */
 lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,

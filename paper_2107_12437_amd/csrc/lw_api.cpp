@@ -55,6 +55,12 @@ struct lw_ctx {
     bool stage_pending = false;
     uint32_t *d_err = nullptr;
     lw::FieldLaunch field_launch{256, 4};
+    hipStream_t side = nullptr;        // small instances run here, joined back into the caller's stream
+    hipStream_t capture = nullptr;     // graph capture of stepped runs
+    hipEvent_t join_a = nullptr, join_b = nullptr;
+    hipGraph_t graph = nullptr;        // last stepped run's graph, released once the stream passed it
+    hipGraphExec_t graph_exec = nullptr;
+    hipEvent_t graph_done = nullptr;
 };
 
 namespace {
@@ -180,6 +186,13 @@ lw_status lw_destroy(lw_ctx *ctx)
     if (!ctx) return LW_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->graph_done) (void)hipEventDestroy(ctx->graph_done);
+    if (ctx->join_a) (void)hipEventDestroy(ctx->join_a);
+    if (ctx->join_b) (void)hipEventDestroy(ctx->join_b);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     if (ctx->stage_evt) (void)hipEventDestroy(ctx->stage_evt);
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     if (ctx->d_work) (void)hipFree(ctx->d_work);
@@ -269,7 +282,7 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
     if (opts->precision != LW_FP64) return fail(LW_E_INVALID, "lw_dipole_run: oscillator runs are FP64 only");
     if (opts->dt_policy != LW_DT_STRICT && opts->dt_policy != LW_DT_EXTRAPOLATE)
         return fail(LW_E_INVALID, "lw_dipole_run: unknown dt policy");
-    if (opts->out_stride < 1 || opts->reserved != 0 || opts->ring_depth < 0 ||
+    if (opts->out_stride < 1 || opts->ring_depth < 0 ||
         (opts->ring_depth & (opts->ring_depth - 1)) != 0 || !std::isfinite(opts->max_vel))
         return fail(LW_E_INVALID, "lw_dipole_run: bad options");
     for (int i = 0; i < n_dip; ++i) {
@@ -314,67 +327,125 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
     LW_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
 
-    // instances whose ring fits in LDS run with an LDS ring, the others with
-    // their ring in the device workspace
+    // small instances whose ring fits in LDS run whole in one workgroup each;
+    // the others advance one launch per step with one workgroup per dipole
     const int lds_limit = 64 * 1024;
-    std::vector<int32_t> lds_list, glb_list;
-    std::vector<int64_t> glb_off;
-    int max_lds_n = 0, max_glb_n = 0;
-    int64_t glb_doubles = 0;
+    const int stepped_min = opts->stepped_min_n == 0 ? 48 : (opts->stepped_min_n < 0 ? (1 << 30) : opts->stepped_min_n);
+    std::vector<int32_t> lds_list, tgt, tgt_lo, tgt_n;
+    std::vector<int64_t> tgt_base;
+    int max_lds_n = 0;
+    int64_t ring_doubles = 0;
     for (int k = 0; k < n_inst; ++k) {
-        const int n = h_inst_off[k + 1] - h_inst_off[k];
+        const int a0 = h_inst_off[k], n = h_inst_off[k + 1] - a0;
         if (n == 0) continue;
-        if (lw::ring_lds_bytes(n, ring) <= lds_limit) {
+        if (n < stepped_min && lw::ring_lds_bytes(n, ring) <= lds_limit) {
             lds_list.push_back(k);
             max_lds_n = std::max(max_lds_n, n);
         } else {
-            glb_list.push_back(k);
-            glb_off.push_back(glb_doubles);
-            glb_doubles += (int64_t)n * ring * 3;
-            max_glb_n = std::max(max_glb_n, n);
+            for (int i = 0; i < n; ++i) {
+                tgt.push_back(a0 + i);
+                tgt_lo.push_back(a0);
+                tgt_n.push_back(n);
+                tgt_base.push_back(ring_doubles);
+            }
+            ring_doubles += (int64_t)n * ring * 3;
         }
     }
-    if (max_glb_n > 0 && lw::ring_lds_bytes(max_glb_n, 0) > lds_limit)
-        return fail(LW_E_INVALID, "lw_dipole_run: instance too large");
+    const size_t n_tgt = tgt.size();
 
     const size_t in_bytes = align_up(sizeof(lw_dipole) * (size_t)n_dip, 256);
     const size_t off_bytes = align_up(sizeof(int32_t) * (size_t)(n_inst + 1), 256);
-    const size_t list_bytes = align_up(sizeof(int32_t) * (size_t)(lds_list.size() + glb_list.size() + 1), 256);
-    const size_t roff_bytes = align_up(sizeof(int64_t) * (glb_off.size() + 1), 256);
-    const size_t stage_bytes = in_bytes + off_bytes + list_bytes + roff_bytes;
+    const size_t list_bytes = align_up(sizeof(int32_t) * (lds_list.size() + 1), 256);
+    const size_t t32_bytes = align_up(sizeof(int32_t) * (n_tgt + 1), 256);
+    const size_t t64_bytes = align_up(sizeof(int64_t) * (n_tgt + 1), 256);
+    const size_t stage_bytes = in_bytes + off_bytes + list_bytes + 3 * t32_bytes + t64_bytes;
     const size_t dev_bytes = align_up(lw::dip_dev_bytes() * (size_t)n_dip, 256);
-    const size_t ring_bytes = align_up(sizeof(double) * (size_t)std::max<int64_t>(glb_doubles, 1), 256);
-    lw_status st = ensure_work(ctx, stage_bytes + dev_bytes + ring_bytes, s);
+    const size_t ecur_bytes = align_up(sizeof(double) * (size_t)n_dip, 256);
+    const size_t step_bytes = 256;
+    const size_t ring_bytes = align_up(sizeof(double) * (size_t)std::max<int64_t>(ring_doubles, 1), 256);
+    lw_status st = ensure_work(ctx, stage_bytes + dev_bytes + ecur_bytes + step_bytes + ring_bytes, s);
     if (st != LW_OK) return st;
+    // the previous stepped run's graph is released once the stream has passed it
+    if (ctx->graph_exec || ctx->graph) {
+        LW_HIP(hipEventSynchronize(ctx->graph_done));
+        if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+        if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+        ctx->graph_exec = nullptr;
+        ctx->graph = nullptr;
+    }
     st = acquire_stage(ctx, stage_bytes);
     if (st != LW_OK) return st;
     char *stage = (char *)ctx->h_stage;
-    std::memcpy(stage, h_dip, sizeof(lw_dipole) * (size_t)n_dip);
-    std::memcpy(stage + in_bytes, h_inst_off, sizeof(int32_t) * (size_t)(n_inst + 1));
-    int32_t *lists = (int32_t *)(stage + in_bytes + off_bytes);
-    std::copy(lds_list.begin(), lds_list.end(), lists);
-    std::copy(glb_list.begin(), glb_list.end(), lists + lds_list.size());
-    int64_t *roff = (int64_t *)(stage + in_bytes + off_bytes + list_bytes);
-    std::copy(glb_off.begin(), glb_off.end(), roff);
+    size_t o = 0;
+    std::memcpy(stage + o, h_dip, sizeof(lw_dipole) * (size_t)n_dip);
+    o += in_bytes;
+    std::memcpy(stage + o, h_inst_off, sizeof(int32_t) * (size_t)(n_inst + 1));
+    o += off_bytes;
+    std::copy(lds_list.begin(), lds_list.end(), (int32_t *)(stage + o));
+    o += list_bytes;
+    std::copy(tgt.begin(), tgt.end(), (int32_t *)(stage + o));
+    o += t32_bytes;
+    std::copy(tgt_lo.begin(), tgt_lo.end(), (int32_t *)(stage + o));
+    o += t32_bytes;
+    std::copy(tgt_n.begin(), tgt_n.end(), (int32_t *)(stage + o));
+    o += t32_bytes;
+    std::copy(tgt_base.begin(), tgt_base.end(), (int64_t *)(stage + o));
     char *work = (char *)ctx->d_work;
     st = upload(ctx, work, stage_bytes, s);
     if (st != LW_OK) return st;
-    const lw_dipole *d_in = (const lw_dipole *)work;
-    const int32_t *d_off = (const int32_t *)(work + in_bytes);
-    const int32_t *d_lists = (const int32_t *)(work + in_bytes + off_bytes);
-    const int64_t *d_roff = (const int64_t *)(work + in_bytes + off_bytes + list_bytes);
-    lw::DipDev *d_dev = (lw::DipDev *)(work + stage_bytes);
-    double *d_ring = (double *)(work + stage_bytes + dev_bytes);
+    o = 0;
+    const lw_dipole *d_in = (const lw_dipole *)(work + o);
+    o += in_bytes;
+    const int32_t *d_off = (const int32_t *)(work + o);
+    o += off_bytes;
+    const int32_t *d_list = (const int32_t *)(work + o);
+    o += list_bytes;
+    const int32_t *d_tgt = (const int32_t *)(work + o);
+    o += t32_bytes;
+    const int32_t *d_tgt_lo = (const int32_t *)(work + o);
+    o += t32_bytes;
+    const int32_t *d_tgt_n = (const int32_t *)(work + o);
+    o += t32_bytes;
+    const int64_t *d_tgt_base = (const int64_t *)(work + o);
+    o += t64_bytes;
+    lw::DipDev *d_dev = (lw::DipDev *)(work + o);
+    o += dev_bytes;
+    double *d_Ecur = (double *)(work + o);
+    o += ecur_bytes;
+    int64_t *d_step = (int64_t *)(work + o);
+    o += step_bytes;
+    double *d_ring = (double *)(work + o);
 
     const double max_vel = opts->max_vel > 0.0 ? opts->max_vel : C_LIGHT / 100.0;
     const int max_iter = 60;
     LW_HIP(lw::launch_dipole_prep(d_in, n_dip, d_dev, s));
-    LW_HIP(lw::launch_dipole_instances(d_dev, d_off, d_lists, (int)lds_list.size(), max_lds_n, true, d_roff, d_ring,
+    const bool both = !lds_list.empty() && n_tgt > 0;
+    hipStream_t small_s = s;
+    if (both) {
+        if (!ctx->side) LW_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        if (!ctx->join_a) LW_HIP(hipEventCreateWithFlags(&ctx->join_a, hipEventDisableTiming));
+        if (!ctx->join_b) LW_HIP(hipEventCreateWithFlags(&ctx->join_b, hipEventDisableTiming));
+        LW_HIP(hipEventRecord(ctx->join_a, s));
+        LW_HIP(hipStreamWaitEvent(ctx->side, ctx->join_a, 0));
+        small_s = ctx->side;
+    }
+    LW_HIP(lw::launch_dipole_instances(d_dev, d_off, d_list, (int)lds_list.size(), max_lds_n, true, nullptr, nullptr,
                                        ring, steps, opts->out_stride, dt, max_vel, max_iter, d_moment, d_ddot,
-                                       d_energy, d_drive, n_dip, ctx->d_err, s));
-    LW_HIP(lw::launch_dipole_instances(d_dev, d_off, d_lists + lds_list.size(), (int)glb_list.size(), max_glb_n,
-                                       false, d_roff, d_ring, ring, steps, opts->out_stride, dt, max_vel, max_iter,
-                                       d_moment, d_ddot, d_energy, d_drive, n_dip, ctx->d_err, s));
+                                       d_energy, d_drive, n_dip, ctx->d_err, small_s));
+    if (n_tgt > 0) {
+        if (!ctx->capture) LW_HIP(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+        if (!ctx->graph_done) LW_HIP(hipEventCreateWithFlags(&ctx->graph_done, hipEventDisableTiming));
+        const int chunk = 256;
+        LW_HIP(lw::launch_dipole_steps(d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_tgt_base, (int)n_tgt, d_ring, d_Ecur, d_step,
+                                       ring, steps, opts->out_stride, dt, max_vel, max_iter, d_moment, d_ddot,
+                                       d_energy, d_drive, n_dip, ctx->d_err, chunk, s, ctx->capture, &ctx->graph,
+                                       &ctx->graph_exec));
+        LW_HIP(hipEventRecord(ctx->graph_done, s));
+    }
+    if (both) {
+        LW_HIP(hipEventRecord(ctx->join_b, ctx->side));
+        LW_HIP(hipStreamWaitEvent(s, ctx->join_b, 0));
+    }
     return LW_OK;
 }
 

@@ -315,6 +315,178 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
     if (tid == 0 && s_err) atomicOr(d_err, s_err);
 }
 
+// ---------------------------------------------------------------------------
+// Large instances: one workgroup per target dipole, one launch per step.
+// The step index comes from a device counter (advanced by step_advance_kernel)
+// so that a captured sequence of steps can be replayed.  Block b advances dipole
+// tgt[b]; its sources are the other dipoles of the same instance, whose history
+// ring sits at ring + ring_base[b] ([ring][n][3]).  Writing step n+1 of dipole
+// i touches the slot of step n+1-ring, which no retarded time of this step can
+// reach, so all blocks of a launch may run in any order.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ DipLds dip_lds(const DipDev &D)
+{
+    return DipLds{D.origin[0], D.origin[1], D.origin[2], D.axis[0], D.axis[1], D.axis[2], D.cfp, D.cfm, D.d0};
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict__ dev, const int32_t *__restrict__ tgt,
+                                                        const int32_t *__restrict__ tgt_lo,
+                                                        const int32_t *__restrict__ tgt_n,
+                                                        const int64_t *__restrict__ ring_base, double *__restrict__ ring,
+                                                        double *__restrict__ Ecur, const int64_t *__restrict__ step_ctr,
+                                                        int ring_depth, int64_t stride, double dt, double max_vel,
+                                                        int max_iter, int init, double *__restrict__ out_d,
+                                                        double *__restrict__ out_v, double *__restrict__ out_E,
+                                                        double *__restrict__ out_Ed, int n_dip,
+                                                        uint32_t *__restrict__ d_err)
+{
+    __shared__ double red[2][BLOCK];
+    const int tid = threadIdx.x;
+    const int gi = tgt[blockIdx.x];
+    const int i0 = tgt_lo[blockIdx.x];
+    const int n = tgt_n[blockIdx.x];
+    const int i = gi - i0;
+    const int64_t nstep = init ? 0 : *step_ctr;
+    double *rp = ring + ring_base[blockIdx.x];
+    Hist H{rp, n, ring_depth - 1, dt, 1.0 / dt};
+    uint32_t err = 0u;
+    const DipLds Si = dip_lds(dev[gi]);
+    const int M = 2 * (n - 1);                       // source charges
+    const int nth = init ? 1 : 2;
+    double acc0 = 0.0, acc1 = 0.0;                   // stage t_n + dt/2 (or t = 0), stage t_n + dt
+    for (int m = tid; m < nth * M; m += BLOCK) {
+        const int th = m / M, mm = m - th * M;
+        const int jj = mm >> 1, w = mm & 1;
+        const int j = jj < i ? jj : jj + 1;
+        const DipDev &Dj = dev[i0 + j];
+        const DipLds Sj = dip_lds(Dj);
+        const double cf = w ? Sj.cfm : Sj.cfp;
+        const double kq = (w ? -Dj.q : Dj.q) * K_COUL;
+        const double theta = init ? 0.0 : (th ? 1.0 : 0.5);
+        const double e = pair_drive(H, Si, Sj, j, cf, kq, nstep, theta, max_iter, err);
+        if (th) acc1 += e; else acc0 += e;
+    }
+    red[0][tid] = acc0;
+    red[1][tid] = acc1;
+    __syncthreads();
+    for (int off = BLOCK / 2; off > 0; off >>= 1) {
+        if (tid < off) {
+            red[0][tid] += red[0][tid + off];
+            red[1][tid] += red[1][tid + off];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const DipDev &D = dev[gi];
+        const double w2 = D.omega0 * D.omega0, g = D.gamma0, f = D.f;
+        if (init) {
+            // t = 0: drive from the static pre-history, sample 0 = (d0, 0, d_ddot(0))
+            const double E0 = red[0][0];
+            double *h = rp + (int64_t)i * 3;
+            h[0] = D.d0;
+            h[1] = 0.0;
+            h[2] = f * E0 - w2 * D.d0;
+            Ecur[gi] = E0;
+            out_d[gi] = D.d0;
+            if (out_v) out_v[gi] = 0.0;
+            if (out_E) out_E[gi] = w2 * D.d0 * D.d0 * (0.5 / f);
+            if (out_Ed) out_Ed[gi] = E0;
+        } else {
+            const double Em = red[0][0], Ee = red[1][0], Ec = Ecur[gi];
+            const double *h = rp + ((int64_t)(nstep & (ring_depth - 1)) * n + i) * 3;
+            const double y0 = h[0], y1 = h[1];
+            const double k1d = y1, k1v = f * Ec - g * y1 - w2 * y0;
+            const double y0b = y0 + 0.5 * dt * k1d, y1b = y1 + 0.5 * dt * k1v;
+            const double k2d = y1b, k2v = f * Em - g * y1b - w2 * y0b;
+            const double y0c = y0 + 0.5 * dt * k2d, y1c = y1 + 0.5 * dt * k2v;
+            const double k3d = y1c, k3v = f * Em - g * y1c - w2 * y0c;
+            const double y0d = y0 + dt * k3d, y1d = y1 + dt * k3v;
+            const double k4d = y1d, k4v = f * Ee - g * y1d - w2 * y0d;
+            const double dn = y0 + dt / 6.0 * (k1d + 2.0 * k2d + 2.0 * k3d + k4d);
+            const double vn = y1 + dt / 6.0 * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
+            const double an = f * Ee - g * vn - w2 * dn;
+            double *hn = rp + ((int64_t)((nstep + 1) & (ring_depth - 1)) * n + i) * 3;
+            hn[0] = dn;
+            hn[1] = vn;
+            hn[2] = an;
+            Ecur[gi] = Ee;
+            if (!(isfinite(dn) && isfinite(vn) && isfinite(an))) err |= ERR_NONFINITE;
+            if (max_vel > 0.0 && D.vfac * fabs(vn) > max_vel) err |= ERR_VELOCITY;
+            if ((nstep + 1) % stride == 0) {
+                const int64_t o = (nstep + 1) / stride * n_dip + gi;
+                out_d[o] = dn;
+                if (out_v) out_v[o] = vn;
+                if (out_E) out_E[o] = (w2 * dn * dn + vn * vn) * (0.5 / f);
+                if (out_Ed) out_Ed[o] = Ee;
+            }
+        }
+    }
+    if (err) atomicOr(d_err, err);
+}
+
+__global__ void step_advance_kernel(int64_t *step_ctr)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step_ctr += 1;
+}
+
+__global__ void step_reset_kernel(int64_t *step_ctr)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step_ctr = 0;
+}
+
+hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const int32_t *d_tgt_lo, const int32_t *d_tgt_n,
+                               const int64_t *d_ring_base, int n_tgt, double *d_ring, double *d_Ecur, int64_t *d_step,
+                               int ring, int64_t steps, int64_t stride, double dt, double max_vel, int max_iter,
+                               double *d_moment, double *d_ddot, double *d_energy, double *d_drive, int n_dip,
+                               uint32_t *d_err, int graph_chunk, hipStream_t s, hipStream_t cap,
+                               hipGraph_t *graph_out, hipGraphExec_t *exec_out)
+{
+    constexpr int B = 256;
+    if (n_tgt <= 0) return hipSuccess;
+    const dim3 grid((unsigned)n_tgt), block(B);
+    hipLaunchKernelGGL(step_reset_kernel, dim3(1), dim3(1), 0, s, d_step);
+    hipLaunchKernelGGL(lo_step_kernel<B>, grid, block, 0, s, d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_ring_base, d_ring,
+                       d_Ecur, d_step, ring, stride, dt, max_vel, max_iter, 1, d_moment, d_ddot, d_energy, d_drive,
+                       n_dip, d_err);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || steps == 0) return e;
+    // a chunk of steps is captured once into a graph and replayed; the step
+    // index lives on the device, so every replay continues where the last ended
+    auto enqueue = [&](hipStream_t q, int64_t count) {
+        for (int64_t k = 0; k < count; ++k) {
+            hipLaunchKernelGGL(lo_step_kernel<B>, grid, block, 0, q, d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_ring_base,
+                               d_ring, d_Ecur, d_step, ring, stride, dt, max_vel, max_iter, 0, d_moment, d_ddot,
+                               d_energy, d_drive, n_dip, d_err);
+            hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(1), 0, q, d_step);
+        }
+    };
+    const int64_t chunk = graph_chunk > 0 ? graph_chunk : 0;
+    if (chunk == 0 || steps < chunk || !cap) {
+        enqueue(s, steps);
+        return hipGetLastError();
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        enqueue(cap, chunk);
+        e = hipStreamEndCapture(cap, &graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    const int64_t reps = steps / chunk;
+    for (int64_t r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(exec, s);
+    if (e == hipSuccess) {
+        enqueue(s, steps - reps * chunk);
+        e = hipGetLastError();
+    }
+    // handed to the caller, which releases them once the stream has passed them
+    *graph_out = graph;
+    *exec_out = exec;
+    return e;
+}
+
 int ring_lds_bytes(int n, int ring)
 {
     return (int)(sizeof(DipLds) * n + sizeof(double) * 4 * n + sizeof(double) * 3 * (size_t)ring * n);

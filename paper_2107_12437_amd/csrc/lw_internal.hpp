@@ -40,4 +40,13 @@ hipError_t launch_dipole_instances(const DipDev *d_dev, const int32_t *d_off, co
                                    int max_iter, double *d_moment, double *d_ddot, double *d_energy,
                                    double *d_drive, int n_dip, uint32_t *d_err, hipStream_t s);
 
+// Large instances: one launch per step (captured into a replayed graph when
+// graph_chunk > 0 and a capture stream is given), one workgroup per target.
+hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const int32_t *d_tgt_lo, const int32_t *d_tgt_n,
+                               const int64_t *d_ring_base, int n_tgt, double *d_ring, double *d_Ecur, int64_t *d_step,
+                               int ring, int64_t steps, int64_t stride, double dt, double max_vel, int max_iter,
+                               double *d_moment, double *d_ddot, double *d_energy, double *d_drive, int n_dip,
+                               uint32_t *d_err, int graph_chunk, hipStream_t s, hipStream_t cap,
+                               hipGraph_t *graph_out, hipGraphExec_t *exec_out);
+
 }  // namespace lw

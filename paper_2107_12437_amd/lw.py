@@ -59,7 +59,7 @@ class Dipole(ct.Structure):
 
 class RunOpts(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("dt_policy", ct.c_int32), ("out_stride", ct.c_int64),
-                ("max_vel", ct.c_double), ("ring_depth", ct.c_int32), ("reserved", ct.c_int32)]
+                ("max_vel", ct.c_double), ("ring_depth", ct.c_int32), ("stepped_min_n", ct.c_int32)]
 
 
 _lib = None
@@ -213,7 +213,7 @@ def fields(charges: dict, points: torch.Tensor, times, precision: str = "mixed",
 
 
 def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "strict", out_stride: int = 1,
-               max_vel: float = 0.0, ring_depth: int = 0, device=None, check: bool = True,
+               max_vel: float = 0.0, ring_depth: int = 0, stepped_min_n: int = 0, device=None, check: bool = True,
                ctx: Context | None = None):
     """Self-consistent oscillator run (Algorithm 1).  Returns a dict of [n_out][n_dip]
     float64 GPU tensors: d, d_dot, energy, Ed."""
@@ -223,7 +223,7 @@ def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "st
     off = np.ascontiguousarray(inst_off, dtype=np.int32)
     n_out = int(steps) // int(out_stride) + 1
     res = {k: torch.empty((n_out, n), dtype=torch.float64, device=dev) for k in ("d", "d_dot", "energy", "Ed")}
-    opts = RunOpts(FP64, DT_POLICIES[policy], int(out_stride), float(max_vel), int(ring_depth), 0)
+    opts = RunOpts(FP64, DT_POLICIES[policy], int(out_stride), float(max_vel), int(ring_depth), int(stepped_min_n))
     L = load_library()
     _check(L.lw_dipole_run(ctx.handle, arr, n, off.ctypes.data_as(ct.POINTER(ct.c_int32)), len(off) - 1,
                            float(dt), int(steps), ct.byref(opts), ct.c_void_p(res["d"].data_ptr()),
