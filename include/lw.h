@@ -73,6 +73,16 @@ lw_status lw_destroy(lw_ctx *ctx);
  * kernel of this context since the previous call; LW_OK if none. */
 lw_status lw_sync_status(lw_ctx *ctx, void *stream);
 
+/* Launch-shape tuning of lw_fields (on by default; LW_AUTOTUNE=0 in the
+ * environment turns it off at lw_create).  While on, the first lw_fields call
+ * of each shape class (precision, field kind, charge and time counts, point
+ * count rounded up to a power of two) times every candidate workgroup size and
+ * times-per-workgroup on its own inputs and keeps the fastest: that call
+ * synchronises `stream` and writes d_out several times, the last time with the
+ * result.  Choices persist in the context, and across processes in the file
+ * named by LW_TUNE_CACHE when set. */
+lw_status lw_set_autotune(lw_ctx *ctx, int32_t enable);
+
 /* ------------------------------------------------------------------------ */
 /* point charges with prescribed trajectories (Sec. 3.1)                     */
 /* ------------------------------------------------------------------------ */

@@ -10,7 +10,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -61,6 +63,10 @@ struct lw_ctx {
     hipGraph_t graph = nullptr;        // last stepped run's graph, released once the stream passed it
     hipGraphExec_t graph_exec = nullptr;
     hipEvent_t graph_done = nullptr;
+    // launch-shape tuner for the grid kernel: shape class -> best (block, tchunk)
+    bool autotune = true;
+    std::map<std::string, lw::FieldLaunch> tuned;
+    std::string tune_file;
 };
 
 namespace {
@@ -146,6 +152,46 @@ lw_status check_traj(const lw_traj &T, int idx, double t_max)
     return LW_OK;
 }
 
+// Shape class of a grid-field call: precision, field kind, charges, times and
+// the point count rounded up to a power of two.
+std::string field_key(const lw_opts &o, int nch, int nt, int64_t npts)
+{
+    int64_t p2 = 1;
+    while (p2 < npts) p2 <<= 1;
+    return "fields p" + std::to_string(o.precision) + " k" + std::to_string(o.field_kind) + " c" + std::to_string(nch) +
+           " t" + std::to_string(nt) + " n" + std::to_string(p2);
+}
+
+void load_tune_file(lw_ctx *ctx)
+{
+    const char *f = std::getenv("LW_TUNE_CACHE");
+    if (!f || !*f) return;
+    ctx->tune_file = f;
+    FILE *fp = std::fopen(f, "r");
+    if (!fp) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, fp)) {
+        // "<key words...> | <block> <tchunk>"
+        char *bar = std::strchr(line, '|');
+        if (!bar) continue;
+        std::string key(line, bar - line);
+        while (!key.empty() && key.back() == ' ') key.pop_back();
+        int b = 0, t = 0;
+        if (std::sscanf(bar + 1, "%d %d", &b, &t) == 2 && b >= 64 && b <= 256 && b % 64 == 0 && t >= 1)
+            ctx->tuned[key] = lw::FieldLaunch{b, t};
+    }
+    std::fclose(fp);
+}
+
+void save_tune_entry(lw_ctx *ctx, const std::string &key, const lw::FieldLaunch &L)
+{
+    if (ctx->tune_file.empty()) return;
+    FILE *fp = std::fopen(ctx->tune_file.c_str(), "a");
+    if (!fp) return;
+    std::fprintf(fp, "%s | %d %d\n", key.c_str(), L.block, L.tchunk);
+    std::fclose(fp);
+}
+
 }  // namespace
 
 extern "C" {
@@ -177,7 +223,17 @@ lw_status lw_create(lw_ctx **out, int32_t device)
         delete c;
         return fail(LW_E_HIP, "lw_create: HIP initialisation failed");
     }
+    const char *at = std::getenv("LW_AUTOTUNE");
+    if (at && at[0] == '0') c->autotune = false;
+    load_tune_file(c);
     *out = c;
+    return LW_OK;
+}
+
+lw_status lw_set_autotune(lw_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return fail(LW_E_INVALID, "lw_set_autotune: null context");
+    ctx->autotune = enable != 0;
     return LW_OK;
 }
 
@@ -265,8 +321,42 @@ lw_status lw_fields(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, co
     const double mask_r = opts->mask_radius < 0.0 ? 1e-10 : opts->mask_radius;
     const double tol_rel = opts->precision == LW_FP64 ? 4.0 * 2.220446049250313e-16 : 2.3283064365386963e-10;
     LW_HIP(lw::launch_prep(d_ch, n_charges, d_times, n_times, d_recs, d_flags, n_pts, s));
-    LW_HIP(lw::launch_fields(d_recs, n_charges, d_pts, n_pts, n_times, *opts, tol_rel, mask_r, d_out, d_flags,
-                             ctx->field_launch, s));
+    lw::FieldLaunch L = ctx->field_launch;
+    const std::string key = field_key(*opts, n_charges, n_times, n_pts);
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) {
+        L = it->second;
+    } else if (ctx->autotune) {
+        // time every candidate shape once (after one untimed launch) on this call's
+        // own inputs; the final launch below writes the result
+        hipEvent_t e0, e1;
+        LW_HIP(hipEventCreate(&e0));
+        LW_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        for (int b : {64, 128, 256})
+            for (int t : {1, 2, 4, 8, 16}) {
+                if (t > 1 && t >= 2 * n_times) continue;
+                const lw::FieldLaunch C{b, t};
+                LW_HIP(lw::launch_fields(d_recs, n_charges, d_pts, n_pts, n_times, *opts, tol_rel, mask_r, d_out,
+                                         nullptr, C, s));
+                LW_HIP(hipEventRecord(e0, s));
+                LW_HIP(lw::launch_fields(d_recs, n_charges, d_pts, n_pts, n_times, *opts, tol_rel, mask_r, d_out,
+                                         nullptr, C, s));
+                LW_HIP(hipEventRecord(e1, s));
+                LW_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                LW_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    L = C;
+                }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ctx->tuned[key] = L;
+        save_tune_entry(ctx, key, L);
+    }
+    LW_HIP(lw::launch_fields(d_recs, n_charges, d_pts, n_pts, n_times, *opts, tol_rel, mask_r, d_out, d_flags, L, s));
     return LW_OK;
 }
 

@@ -29,8 +29,8 @@ FLAG_MASKED, FLAG_NOCONV = 1, 2
 STATUS_NAMES = {0: "LW_OK", 1: "LW_E_INVALID", 2: "LW_E_SUPERLUMINAL", 3: "LW_E_DT_TOO_LARGE",
                 4: "LW_E_VELOCITY", 5: "LW_E_NOCONV", 6: "LW_E_HIP", 7: "LW_E_NOMEM",
                 8: "LW_E_NONFINITE", 9: "LW_E_HISTORY"}
-EXPORTS = ("lw_last_error", "lw_create", "lw_destroy", "lw_sync_status", "lw_fields", "lw_dipole_run",
-           "lw_pair_modes", "lw_gamma0")
+EXPORTS = ("lw_last_error", "lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields",
+           "lw_dipole_run", "lw_pair_modes", "lw_gamma0")
 OUTPUT_NAMES = ("phi", "Ax", "Ay", "Az", "Ex", "Ey", "Ez", "Bx", "By", "Bz")
 
 
@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH):
     L.lw_create.argtypes = [ct.POINTER(vp), i32]
     L.lw_destroy.argtypes = [vp]
     L.lw_sync_status.argtypes = [vp, vp]
+    L.lw_set_autotune.argtypes = [vp, i32]
     L.lw_fields.argtypes = [vp, ct.POINTER(Traj), i32, vp, i64, ct.POINTER(dbl), i32, ct.POINTER(Opts), vp, vp, vp]
     L.lw_dipole_run.argtypes = [vp, ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, i64,
                                 ct.POINTER(RunOpts), vp, vp, vp, vp, vp]
@@ -86,7 +87,8 @@ def load_library(path: str = LIB_PATH):
                                 ct.POINTER(dbl), ct.POINTER(i64), ct.POINTER(dbl)]
     L.lw_gamma0.restype = dbl
     L.lw_gamma0.argtypes = [dbl, dbl, dbl]
-    for name in ("lw_create", "lw_destroy", "lw_sync_status", "lw_fields", "lw_dipole_run", "lw_pair_modes"):
+    for name in ("lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields", "lw_dipole_run",
+                 "lw_pair_modes"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -108,6 +110,9 @@ class Context:
         h = ct.c_void_p()
         _check(L.lw_create(ct.byref(h), self.device))
         self.handle = h
+
+    def set_autotune(self, enable: bool):
+        _check(load_library().lw_set_autotune(self.handle, int(bool(enable))))
 
     def close(self):
         if self.handle:
