@@ -144,6 +144,24 @@ lw_status lw_fields(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, co
                     int64_t n_pts, const double *h_times, int32_t n_times, const lw_opts *opts,
                     void *d_out, uint32_t *d_flags, void *stream);
 
+/* Vector-Jacobian product of lw_fields with respect to the trajectory
+ * parameters: d_grad[c][k] = sum over points p, times t and outputs j of
+ * d_cot[t][j][p] * d out[t][j][p] / d theta_{c,k}, for the parameters
+ *   k = 0 q, 1..3 c0, 4 amp, 5 omega, 6 phase, 7 accel, 8..10 v
+ * of charge c (those a kind does not use get 0).  The derivative follows the
+ * retarded time through the implicit-function theorem on Eq. (ret_t) and the
+ * trajectory's own derivatives (the jerk enters through d a / d t').
+ *   d_cot   device, [n_times][10][n_pts], FP32 if opts->precision is LW_MIXED,
+ *           FP64 otherwise (the layout of lw_fields' output); (point, time)
+ *           entries with a non-finite cotangent, and pairs closer than the
+ *           mask radius, contribute nothing
+ *   d_grad  device FP64 [n_charges][11], overwritten
+ * The forward quantities are recomputed in FP64 whatever the precision.
+ * Sums run in a fixed order: the result is bitwise reproducible.  Asynchronous. */
+lw_status lw_fields_vjp(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, const double *d_pts,
+                        int64_t n_pts, const double *h_times, int32_t n_times, const lw_opts *opts,
+                        const void *d_cot, double *d_grad, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Lorentz oscillators (Secs. 2.3, 3.2; Algorithm 1)                         */
 /* ------------------------------------------------------------------------ */

@@ -1,0 +1,263 @@
+// lw_adjoint.hip -- vector-Jacobian product of the grid fields with respect to
+// the trajectory parameters of every charge (FP64).
+//
+// For one (point x, time t, charge) the outputs O = (Phi, A, E, B) depend on the
+// retarded separation R = x - r(t'), velocity v(t') and acceleration a(t') and
+// on q, with t' = t - tau and tau the root of c tau = |x - r(t - tau)| (Eq.
+// (ret_t)).  For a parameter theta of the trajectory,
+//   dR = -r_theta dtheta + v dtau,  dv = v_theta dtheta - a dtau,
+//   da = a_theta dtheta - j dtau   (j = da/dt', the jerk),
+// and differentiating the retarded-time equation (implicit function theorem)
+//   dtau = -(n . r_theta) / (c kappa) dtheta,  c kappa = c - n . v.
+// With Rb, vb, ab the cotangents of R, v, a (the reverse of the Lienard-Wiechert
+// evaluator) and s = Rb.v - vb.a - ab.j, the cotangent of the trajectory
+// position is rb = -Rb - s n / (c kappa), and the gradient of a parameter is
+// rb . r_theta + vb . v_theta + ab . a_theta.  Sums over points and times are
+// per-workgroup partials reduced in a fixed order (bitwise reproducible).
+#include <math.h>
+
+#include "lw_device.hpp"
+#include "lw_internal.hpp"
+
+namespace lw {
+
+// Parameter order of the gradient rows.
+enum { P_Q = 0, P_C0 = 1, P_AMP = 4, P_OMEGA = 5, P_PHASE = 6, P_ACCEL = 7, P_V = 8, NP = 11 };
+
+// Reverse of lw_terms<double>: given the cotangent ob of (Phi, A, E, B), the
+// cotangents of R, v, a and of kq = q / (4 pi eps0).
+__device__ __forceinline__ void lw_terms_vjp(const Kin &k, double kq, int field_kind, const double ob[10],
+                                             double Rb[3], double vb[3], double ab[3], double &kqb, double n[3],
+                                             double &kappa_out)
+{
+    const double ic = INV_C;
+    const double D = sqrt(k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2]);
+    const double iD = 1.0 / D;
+    double b[3], d[3], u[3];
+    for (int i = 0; i < 3; ++i) {
+        n[i] = k.R[i] * iD;
+        b[i] = k.v[i] * ic;
+        d[i] = k.a[i] * ic;
+        u[i] = n[i] - b[i];
+    }
+    const double nb = n[0] * b[0] + n[1] * b[1] + n[2] * b[2];
+    const double kappa = 1.0 - nb;
+    const double bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    const double nd = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
+    const double ik = 1.0 / kappa;
+    const double kqD = kq * iD;
+    const double phi = kqD * ik;
+    const double f = phi * ik * ik;
+    const bool coul = field_kind != F_RADIATION, rad = field_kind != F_COULOMB;
+    const double cu = (coul ? (1.0 - bb) * iD : 0.0) + (rad ? nd * ic : 0.0);
+    const double cd = rad ? kappa * ic : 0.0;
+    double W[3], E[3], m[3];
+    for (int i = 0; i < 3; ++i) {
+        W[i] = u[i] * cu - d[i] * cd;
+        E[i] = f * W[i];
+        m[i] = n[i] * ic;
+    }
+    const double pc = phi * ic;
+    // ---- reverse ----
+    const double Phib = ob[0];
+    const double Ab[3] = {ob[1], ob[2], ob[3]};
+    const double Eb[3] = {ob[4], ob[5], ob[6]};
+    const double Bb[3] = {ob[7], ob[8], ob[9]};
+    // B = m x E
+    double mb[3], Et[3];
+    mb[0] = E[1] * Bb[2] - E[2] * Bb[1];
+    mb[1] = E[2] * Bb[0] - E[0] * Bb[2];
+    mb[2] = E[0] * Bb[1] - E[1] * Bb[0];
+    Et[0] = Eb[0] + (Bb[1] * m[2] - Bb[2] * m[1]);
+    Et[1] = Eb[1] + (Bb[2] * m[0] - Bb[0] * m[2]);
+    Et[2] = Eb[2] + (Bb[0] * m[1] - Bb[1] * m[0]);
+    // A = pc b
+    const double pcb = Ab[0] * b[0] + Ab[1] * b[1] + Ab[2] * b[2];
+    double bbar[3] = {pc * Ab[0], pc * Ab[1], pc * Ab[2]};
+    // E = f W, W = u cu - d cd
+    const double fb = Et[0] * W[0] + Et[1] * W[1] + Et[2] * W[2];
+    double ub[3], dbar[3];
+    double cub = 0.0, cdb = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        const double Wb = f * Et[i];
+        ub[i] = Wb * cu;
+        cub += Wb * u[i];
+        dbar[i] = -Wb * cd;
+        cdb -= Wb * d[i];
+    }
+    // phi = kqD ik feeds Phi, pc and f
+    const double phib = Phib + pcb * ic + fb * ik * ik;
+    const double ikb_f = fb * 2.0 * phi * ik;
+    double ikb = ikb_f + phib * kqD;
+    const double kqDb = phib * ik;
+    // cu, cd
+    const double bbb = coul ? -cub * iD : 0.0;
+    double iDb = coul ? cub * (1.0 - bb) : 0.0;
+    const double ndb = rad ? cub * ic : 0.0;
+    double kappab = rad ? cdb * ic : 0.0;
+    // m = n / c
+    double nbar[3] = {mb[0] * ic, mb[1] * ic, mb[2] * ic};
+    // kqD = kq iD
+    iDb += kqDb * kq;
+    kqb = kqDb * iD;
+    // ik = 1 / kappa
+    kappab -= ikb * ik * ik;
+    // nd = n . d
+    for (int i = 0; i < 3; ++i) {
+        nbar[i] += ndb * d[i] + ub[i];
+        dbar[i] += ndb * n[i];
+        bbar[i] += -ub[i] + 2.0 * bbb * b[i];
+    }
+    // kappa = 1 - n . b
+    const double nbb = -kappab;
+    for (int i = 0; i < 3; ++i) {
+        nbar[i] += nbb * b[i];
+        bbar[i] += nbb * n[i];
+        vb[i] = bbar[i] * ic;
+        ab[i] = dbar[i] * ic;
+    }
+    // n = R iD with iD = 1/|R|
+    iDb += nbar[0] * k.R[0] + nbar[1] * k.R[1] + nbar[2] * k.R[2];
+    const double s = -iDb * iD * iD;
+    for (int i = 0; i < 3; ++i) Rb[i] = nbar[i] * iD + s * n[i];
+    kappa_out = kappa;
+}
+
+// Gradient of one (point, time, charge) contribution, added into g[NP].
+__device__ __forceinline__ void pair_param_grad(const SrcRec &S, const Kin &k, int field_kind, const double ob[10],
+                                                double g[NP])
+{
+    double Rb[3], vb[3], ab[3], n[3], kqb, kappa;
+    lw_terms_vjp(k, S.kq, field_kind, ob, Rb, vb, ab, kqb, n, kappa);
+    // jerk at t': -omega^2 v for the harmonic families, 0 otherwise
+    const bool harm = (S.kind == K_CIRCULAR || S.kind == K_LINEAR_OSC);
+    const double w2 = harm ? S.omega * S.omega : 0.0;
+    double sres = 0.0;
+    for (int i = 0; i < 3; ++i) sres += Rb[i] * k.v[i] - vb[i] * k.a[i] + ab[i] * w2 * k.v[i];
+    const double fac = sres / (C_LIGHT - (n[0] * k.v[0] + n[1] * k.v[1] + n[2] * k.v[2]));
+    double rb[3];
+    for (int i = 0; i < 3; ++i) rb[i] = -Rb[i] - fac * n[i];
+    g[P_Q] += kqb * K_COUL;
+    for (int i = 0; i < 3; ++i) g[P_C0 + i] += rb[i];
+    const double A = S.amp, om = S.omega, c = k.cph, sn = k.sph, tp = k.tp;
+    const double r1 = rb[0] * S.e1[0] + rb[1] * S.e1[1] + rb[2] * S.e1[2];
+    const double v1 = vb[0] * S.e1[0] + vb[1] * S.e1[1] + vb[2] * S.e1[2];
+    const double a1 = ab[0] * S.e1[0] + ab[1] * S.e1[1] + ab[2] * S.e1[2];
+    if (S.kind == K_CIRCULAR) {
+        const double r2 = rb[0] * S.e2[0] + rb[1] * S.e2[1] + rb[2] * S.e2[2];
+        const double v2 = vb[0] * S.e2[0] + vb[1] * S.e2[1] + vb[2] * S.e2[2];
+        const double a2 = ab[0] * S.e2[0] + ab[1] * S.e2[1] + ab[2] * S.e2[2];
+        // projections on the radial (c e1 + s e2) and tangential (-s e1 + c e2) directions
+        const double Pr = r1 * c + r2 * sn, Qr = r2 * c - r1 * sn;
+        const double Pv = v1 * c + v2 * sn, Qv = v2 * c - v1 * sn;
+        const double Pa = a1 * c + a2 * sn, Qa = a2 * c - a1 * sn;
+        const double gphi = A * Qr - A * om * Pv - A * om * om * Qa;
+        g[P_AMP] += Pr + om * Qv - om * om * Pa;
+        g[P_PHASE] += gphi;
+        g[P_OMEGA] += tp * gphi + A * Qv - 2.0 * A * om * Pa;
+    } else if (S.kind == K_LINEAR_OSC) {
+        const double gphi = -A * sn * r1 - A * om * c * v1 + A * om * om * sn * a1;
+        g[P_AMP] += r1 * c - om * sn * v1 - om * om * c * a1;
+        g[P_PHASE] += gphi;
+        g[P_OMEGA] += tp * gphi - A * sn * v1 - 2.0 * A * om * c * a1;
+    } else if (S.kind == K_ACCEL) {
+        if (tp >= 0.0) g[P_ACCEL] += 0.5 * tp * tp * r1 + tp * v1 + a1;
+    } else if (S.kind == K_UNIFORM_VELOCITY) {
+        for (int i = 0; i < 3; ++i) g[P_V + i] += rb[i] * tp + vb[i];
+    }
+}
+
+template <typename G>
+__global__ __launch_bounds__(256) void fields_vjp_kernel(const SrcRec *__restrict__ recs, int nch,
+                                                         const double *__restrict__ pts, int64_t npts, int nt,
+                                                         int tchunk, int field_kind, int max_iter, double tol_rel,
+                                                         double mask_r, const G *__restrict__ cot,
+                                                         double *__restrict__ partial)
+{
+    __shared__ double red[4][NP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t p = (int64_t)blockIdx.x * 256 + tid;
+    const bool live = p < npts;
+    double x[3] = {0.0, 0.0, 0.0};
+    if (live) {
+        x[0] = pts[p];
+        x[1] = pts[npts + p];
+        x[2] = pts[2 * npts + p];
+    }
+    const int t0 = blockIdx.y * tchunk;
+    const int t1 = min(t0 + tchunk, nt);
+    const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    for (int c = 0; c < nch; ++c) {
+        double g[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) g[j] = 0.0;
+        if (live) {
+            for (int ti = t0; ti < t1; ++ti) {
+                const SrcRec &S = recs[(int64_t)ti * nch + c];
+                double ob[10];
+                bool fin = true;
+#pragma unroll
+                for (int j = 0; j < 10; ++j) {
+                    ob[j] = (double)cot[((int64_t)ti * 10 + j) * npts + p];
+                    fin = fin && isfinite(ob[j]);
+                }
+                if (!fin) continue;
+                Kin k;
+                retarded(S, x, max_iter, tol_rel, k);
+                const double D2 = k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2];
+                if (!(D2 >= mask_r * mask_r) || D2 == 0.0) continue;
+                pair_param_grad(S, k, field_kind, ob, g);
+            }
+        }
+        // workgroup sum in a fixed order: shuffle tree per wave, then the four waves
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            double v = g[j];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) red[wave][j] = v;
+        }
+        __syncthreads();
+        if (tid < NP)
+            partial[(blk * nch + c) * NP + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+        __syncthreads();
+    }
+}
+
+__global__ void vjp_reduce_kernel(const double *__restrict__ partial, int64_t nblk, int nout, double *__restrict__ grad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nout) return;
+    double s = 0.0;
+    for (int64_t b = 0; b < nblk; ++b) s += partial[b * nout + i];
+    grad[i] = s;
+}
+
+int vjp_params() { return NP; }
+
+size_t vjp_partial_doubles(int64_t npts, int nt, int nch, int tchunk)
+{
+    const int64_t gx = (npts + 255) / 256, gy = (nt + tchunk - 1) / tchunk;
+    return (size_t)(gx * gy) * (size_t)nch * NP;
+}
+
+hipError_t launch_fields_vjp(const SrcRec *d_recs, int nch, const double *d_pts, int64_t npts, int nt,
+                             const lw_opts &o, double tol_rel, double mask_r, const void *d_cot, double *d_partial,
+                             int tchunk, double *d_grad, hipStream_t s)
+{
+    const dim3 grid((unsigned)((npts + 255) / 256), (unsigned)((nt + tchunk - 1) / tchunk));
+    const int max_iter = o.max_iter > 0 ? o.max_iter : 100;
+    if (o.precision == LW_MIXED)
+        hipLaunchKernelGGL(fields_vjp_kernel<float>, grid, dim3(256), 0, s, d_recs, nch, d_pts, npts, nt, tchunk,
+                           o.field_kind, max_iter, tol_rel, mask_r, (const float *)d_cot, d_partial);
+    else
+        hipLaunchKernelGGL(fields_vjp_kernel<double>, grid, dim3(256), 0, s, d_recs, nch, d_pts, npts, nt, tchunk,
+                           o.field_kind, max_iter, tol_rel, mask_r, (const double *)d_cot, d_partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nout = nch * NP;
+    const int64_t nblk = (int64_t)grid.x * grid.y;
+    hipLaunchKernelGGL(vjp_reduce_kernel, dim3((nout + 255) / 256), dim3(256), 0, s, d_partial, nblk, nout, d_grad);
+    return hipGetLastError();
+}
+
+}  // namespace lw

@@ -273,38 +273,55 @@ lw_status lw_sync_status(lw_ctx *ctx, void *stream)
     return LW_OK;
 }
 
-lw_status lw_fields(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, const double *d_pts, int64_t n_pts,
-                    const double *h_times, int32_t n_times, const lw_opts *opts, void *d_out, uint32_t *d_flags,
-                    void *stream)
+}  // extern "C"
+
+namespace {
+
+// Argument checks shared by lw_fields and lw_fields_vjp.  Sets *noop when there
+// is nothing to compute.
+lw_status check_fields_args(const char *who, lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges,
+                            const double *d_pts, int64_t n_pts, const double *h_times, int32_t n_times,
+                            const lw_opts *opts, const void *d_out, bool *noop)
 {
-    if (!ctx || !opts) return fail(LW_E_INVALID, "lw_fields: null context or options");
-    if (n_charges < 1 || !h_charges) return fail(LW_E_INVALID, "lw_fields: need at least one charge");
-    if (n_pts < 0 || n_times < 0) return fail(LW_E_INVALID, "lw_fields: negative size");
-    if (opts->precision != LW_FP64 && opts->precision != LW_MIXED)
-        return fail(LW_E_INVALID, "lw_fields: unknown precision");
+    const std::string w = who;
+    *noop = false;
+    if (!ctx || !opts) return fail(LW_E_INVALID, w + ": null context or options");
+    if (n_charges < 1 || !h_charges) return fail(LW_E_INVALID, w + ": need at least one charge");
+    if (n_pts < 0 || n_times < 0) return fail(LW_E_INVALID, w + ": negative size");
+    if (opts->precision != LW_FP64 && opts->precision != LW_MIXED) return fail(LW_E_INVALID, w + ": unknown precision");
     if (opts->field_kind < LW_FIELD_TOTAL || opts->field_kind > LW_FIELD_RADIATION)
-        return fail(LW_E_INVALID, "lw_fields: unknown field kind");
+        return fail(LW_E_INVALID, w + ": unknown field kind");
     if (opts->max_iter < 0 || opts->max_iter > 100000 || opts->reserved != 0 || std::isnan(opts->mask_radius))
-        return fail(LW_E_INVALID, "lw_fields: bad options");
-    if (n_pts == 0 || n_times == 0) return LW_OK;
-    if (!d_pts || !d_out || !h_times) return fail(LW_E_INVALID, "lw_fields: null buffer");
-    if (n_times > 65535 * 64) return fail(LW_E_INVALID, "lw_fields: too many times");
+        return fail(LW_E_INVALID, w + ": bad options");
+    if (n_pts == 0 || n_times == 0) {
+        *noop = true;
+        return LW_OK;
+    }
+    if (!d_pts || !d_out || !h_times) return fail(LW_E_INVALID, w + ": null buffer");
+    if (n_times > 65535 * 64) return fail(LW_E_INVALID, w + ": too many times");
+    if (n_pts > ((int64_t)1 << 40)) return fail(LW_E_INVALID, w + ": too many points");
     double t_max = -INFINITY;
     for (int i = 0; i < n_times; ++i) {
-        if (!std::isfinite(h_times[i])) return fail(LW_E_INVALID, "lw_fields: non-finite time");
+        if (!std::isfinite(h_times[i])) return fail(LW_E_INVALID, w + ": non-finite time");
         t_max = std::max(t_max, h_times[i]);
     }
     for (int c = 0; c < n_charges; ++c) {
         lw_status st = check_traj(h_charges[c], c, t_max);
         if (st != LW_OK) return st;
     }
-    LW_HIP(hipSetDevice(ctx->device));
-    hipStream_t s = (hipStream_t)stream;
+    return LW_OK;
+}
 
+// Stages charges and times and enqueues the record preparation; returns the
+// device records.  extra_bytes of workspace follow the records (at *d_extra).
+lw_status stage_records(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, const double *h_times,
+                        int32_t n_times, uint32_t *d_flags, int64_t n_pts, size_t extra_bytes, hipStream_t s,
+                        lw::SrcRec **d_recs_out, void **d_extra)
+{
     const size_t ch_bytes = align_up(sizeof(lw_traj) * (size_t)n_charges, 256);
     const size_t tm_bytes = align_up(sizeof(double) * (size_t)n_times, 256);
     const size_t rec_bytes = align_up(lw::src_rec_bytes() * (size_t)n_charges * (size_t)n_times, 256);
-    lw_status st = ensure_work(ctx, ch_bytes + tm_bytes + rec_bytes, s);
+    lw_status st = ensure_work(ctx, ch_bytes + tm_bytes + rec_bytes + extra_bytes, s);
     if (st != LW_OK) return st;
     st = acquire_stage(ctx, ch_bytes + tm_bytes);
     if (st != LW_OK) return st;
@@ -314,13 +331,33 @@ lw_status lw_fields(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, co
     char *work = (char *)ctx->d_work;
     st = upload(ctx, work, ch_bytes + tm_bytes, s);
     if (st != LW_OK) return st;
-    const lw_traj *d_ch = (const lw_traj *)work;
-    const double *d_times = (const double *)(work + ch_bytes);
     lw::SrcRec *d_recs = (lw::SrcRec *)(work + ch_bytes + tm_bytes);
+    LW_HIP(lw::launch_prep((const lw_traj *)work, n_charges, (const double *)(work + ch_bytes), n_times, d_recs,
+                           d_flags, n_pts, s));
+    *d_recs_out = d_recs;
+    if (d_extra) *d_extra = work + ch_bytes + tm_bytes + rec_bytes;
+    return LW_OK;
+}
 
+}  // namespace
+
+extern "C" {
+
+lw_status lw_fields(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, const double *d_pts, int64_t n_pts,
+                    const double *h_times, int32_t n_times, const lw_opts *opts, void *d_out, uint32_t *d_flags,
+                    void *stream)
+{
+    bool noop = false;
+    lw_status st0 = check_fields_args("lw_fields", ctx, h_charges, n_charges, d_pts, n_pts, h_times, n_times, opts,
+                                      d_out, &noop);
+    if (st0 != LW_OK || noop) return st0;
+    LW_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    lw::SrcRec *d_recs = nullptr;
+    lw_status st = stage_records(ctx, h_charges, n_charges, h_times, n_times, d_flags, n_pts, 0, s, &d_recs, nullptr);
+    if (st != LW_OK) return st;
     const double mask_r = opts->mask_radius < 0.0 ? 1e-10 : opts->mask_radius;
     const double tol_rel = opts->precision == LW_FP64 ? 4.0 * 2.220446049250313e-16 : 2.3283064365386963e-10;
-    LW_HIP(lw::launch_prep(d_ch, n_charges, d_times, n_times, d_recs, d_flags, n_pts, s));
     lw::FieldLaunch L = ctx->field_launch;
     const std::string key = field_key(*opts, n_charges, n_times, n_pts);
     auto it = ctx->tuned.find(key);
@@ -357,6 +394,34 @@ lw_status lw_fields(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, co
         save_tune_entry(ctx, key, L);
     }
     LW_HIP(lw::launch_fields(d_recs, n_charges, d_pts, n_pts, n_times, *opts, tol_rel, mask_r, d_out, d_flags, L, s));
+    return LW_OK;
+}
+
+lw_status lw_fields_vjp(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, const double *d_pts,
+                        int64_t n_pts, const double *h_times, int32_t n_times, const lw_opts *opts, const void *d_cot,
+                        double *d_grad, void *stream)
+{
+    bool noop = false;
+    if (!d_grad) return fail(LW_E_INVALID, "lw_fields_vjp: null gradient buffer");
+    lw_status st = check_fields_args("lw_fields_vjp", ctx, h_charges, n_charges, d_pts, n_pts, h_times, n_times, opts,
+                                     d_cot, &noop);
+    if (st != LW_OK) return st;
+    LW_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (noop) {
+        LW_HIP(hipMemsetAsync(d_grad, 0, sizeof(double) * (size_t)n_charges * lw::vjp_params(), s));
+        return LW_OK;
+    }
+    const int tchunk = 4;
+    const size_t part_bytes = align_up(sizeof(double) * lw::vjp_partial_doubles(n_pts, n_times, n_charges, tchunk), 256);
+    lw::SrcRec *d_recs = nullptr;
+    void *d_partial = nullptr;
+    st = stage_records(ctx, h_charges, n_charges, h_times, n_times, nullptr, n_pts, part_bytes, s, &d_recs, &d_partial);
+    if (st != LW_OK) return st;
+    const double mask_r = opts->mask_radius < 0.0 ? 1e-10 : opts->mask_radius;
+    const double tol_rel = 4.0 * 2.220446049250313e-16;     // the adjoint recomputes the forward in FP64
+    LW_HIP(lw::launch_fields_vjp(d_recs, n_charges, d_pts, n_pts, n_times, *opts, tol_rel, mask_r, d_cot,
+                                 (double *)d_partial, tchunk, d_grad, s));
     return LW_OK;
 }
 

@@ -47,6 +47,8 @@ struct Kin {
     double R[3];
     double v[3];
     double a[3];
+    double tp;          // retarded time t'
+    double cph, sph;    // cos, sin of the phase at t' (oscillating families)
     uint32_t flags;
 };
 
@@ -230,6 +232,9 @@ __device__ __forceinline__ void solve_circular(const SrcRec &S, const double w[3
         tau = tn;
     }
     k.flags = ok ? 0u : FLAG_NOCONV;
+    k.tp = S.t - tau;
+    k.cph = ph.c;
+    k.sph = ph.s;
     double ro[3], vo[3];
     for (int i = 0; i < 3; ++i) {
         ro[i] = A * (ph.c * S.e1[i] + ph.s * S.e2[i]);
@@ -269,6 +274,9 @@ __device__ __forceinline__ void solve_linear(const SrcRec &S, const double w[3],
         tau = tn;
     }
     k.flags = ok ? 0u : FLAG_NOCONV;
+    k.tp = S.t - tau;
+    k.cph = ph.c;
+    k.sph = ph.s;
     for (int i = 0; i < 3; ++i) {
         k.R[i] = w[i] - A * ph.c * S.e1[i];
         k.v[i] = -A * om * ph.s * S.e1[i];
@@ -307,6 +315,9 @@ __device__ __forceinline__ void solve_accel(const SrcRec &S, const double w[3], 
     }
     k.flags = ok ? 0u : FLAG_NOCONV;
     const double tp = t - tau;
+    k.tp = tp;
+    k.cph = 1.0;
+    k.sph = 0.0;
     const double s = (tp >= 0.0) ? 0.5 * acc * tp * tp : 0.0;
     const double vel = (tp >= 0.0) ? acc * tp : 0.0;
     const double ac = (tp >= 0.0) ? acc : 0.0;
@@ -329,6 +340,9 @@ __device__ __forceinline__ void solve_uniform(const SrcRec &S, const double x[3]
     const double sq = sqrt(wv * wv + den * ww);
     // the two algebraically equal forms, chosen to avoid cancellation
     const double tau = (wv >= 0.0) ? (wv + sq) / den : ww / (sq - wv);
+    k.tp = S.t - tau;
+    k.cph = 1.0;
+    k.sph = 0.0;
     for (int i = 0; i < 3; ++i) {
         k.R[i] = wt[i] + S.v[i] * tau;
         k.v[i] = S.v[i];
@@ -348,6 +362,9 @@ __device__ __forceinline__ void retarded(const SrcRec &S, const double x[3], int
     case K_UNIFORM_VELOCITY: solve_uniform(S, x, k); break;
     default:
         for (int i = 0; i < 3; ++i) { k.R[i] = w[i]; k.v[i] = 0.0; k.a[i] = 0.0; }
+        k.tp = S.t - sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]) * INV_C;
+        k.cph = 1.0;
+        k.sph = 0.0;
         k.flags = 0u;
         break;
     }

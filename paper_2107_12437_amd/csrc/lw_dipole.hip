@@ -153,6 +153,9 @@ __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, 
     k.a[0] = cf * h[2] * Sj.px;
     k.a[1] = cf * h[2] * Sj.py;
     k.a[2] = cf * h[2] * Sj.pz;
+    k.tp = 0.0;
+    k.cph = 1.0;
+    k.sph = 0.0;
     k.flags = 0u;
     double o[10];
     lw_terms<double>(k, kq, F_TOTAL, o);

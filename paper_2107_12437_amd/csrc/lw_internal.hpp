@@ -26,6 +26,14 @@ hipError_t launch_fields(const SrcRec *d_recs, int nch, const double *d_pts, int
                          const FieldLaunch &L, hipStream_t s);
 size_t src_rec_bytes();
 
+// Vector-Jacobian product of the grid fields with respect to the 11 trajectory
+// parameters of every charge (lw_adjoint.hip).
+int vjp_params();
+size_t vjp_partial_doubles(int64_t npts, int nt, int nch, int tchunk);
+hipError_t launch_fields_vjp(const SrcRec *d_recs, int nch, const double *d_pts, int64_t npts, int nt,
+                             const lw_opts &o, double tol_rel, double mask_r, const void *d_cot, double *d_partial,
+                             int tchunk, double *d_grad, hipStream_t s);
+
 // Lorentz-oscillator runs.
 struct DipDev;     // device-side oscillator constants
 size_t dip_dev_bytes();

@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "LW_OK", 1: "LW_E_INVALID", 2: "LW_E_SUPERLUMINAL", 3: "LW_E_
                 4: "LW_E_VELOCITY", 5: "LW_E_NOCONV", 6: "LW_E_HIP", 7: "LW_E_NOMEM",
                 8: "LW_E_NONFINITE", 9: "LW_E_HISTORY"}
 EXPORTS = ("lw_last_error", "lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields",
-           "lw_dipole_run", "lw_pair_modes", "lw_gamma0")
+           "lw_fields_vjp", "lw_dipole_run", "lw_pair_modes", "lw_gamma0")
+PARAM_NAMES = ("q", "c0x", "c0y", "c0z", "amp", "omega", "phase", "accel", "vx", "vy", "vz")
 OUTPUT_NAMES = ("phi", "Ax", "Ay", "Az", "Ex", "Ey", "Ez", "Bx", "By", "Bz")
 
 
@@ -81,14 +82,15 @@ def load_library(path: str = LIB_PATH):
     L.lw_sync_status.argtypes = [vp, vp]
     L.lw_set_autotune.argtypes = [vp, i32]
     L.lw_fields.argtypes = [vp, ct.POINTER(Traj), i32, vp, i64, ct.POINTER(dbl), i32, ct.POINTER(Opts), vp, vp, vp]
+    L.lw_fields_vjp.argtypes = [vp, ct.POINTER(Traj), i32, vp, i64, ct.POINTER(dbl), i32, ct.POINTER(Opts), vp, vp, vp]
     L.lw_dipole_run.argtypes = [vp, ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, i64,
                                 ct.POINTER(RunOpts), vp, vp, vp, vp, vp]
     L.lw_pair_modes.argtypes = [ct.POINTER(dbl), i64, i32, ct.POINTER(i32), i32, dbl, i64,
                                 ct.POINTER(dbl), ct.POINTER(i64), ct.POINTER(dbl)]
     L.lw_gamma0.restype = dbl
     L.lw_gamma0.argtypes = [dbl, dbl, dbl]
-    for name in ("lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields", "lw_dipole_run",
-                 "lw_pair_modes"):
+    for name in ("lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields", "lw_fields_vjp",
+                 "lw_dipole_run", "lw_pair_modes"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -215,6 +217,69 @@ def fields(charges: dict, points: torch.Tensor, times, precision: str = "mixed",
     """Phi, A, E, B of the charges at points ([3, n] float64 on the GPU) and times.
     Returns (out [n_times][10][n_pts], flags [n_pts] int32)."""
     return FieldsCall(charges, points, times, precision, field_kind, mask_radius, max_iter, True, ctx).launch()
+
+
+def fields_vjp(charges: dict, points: torch.Tensor, times, cotangent: torch.Tensor, field_kind: str = "total",
+               mask_radius: float = 1e-10, max_iter: int = 0, ctx: Context | None = None) -> torch.Tensor:
+    """Gradient [n_charges][11] (PARAM_NAMES order) of sum(cotangent * fields(...)) with respect
+    to each charge's trajectory parameters.  cotangent has the layout of fields' output; its
+    dtype (float32 / float64) selects the matching precision."""
+    if not (isinstance(points, torch.Tensor) and points.is_cuda and points.dtype == torch.float64):
+        raise ValueError("points must be a [3, n] float64 tensor on the GPU")
+    pts = points.contiguous()
+    ctx = ctx or default_context(pts.device.index)
+    arr, n = pack_charges(charges)
+    tms = np.ascontiguousarray(np.atleast_1d(times), dtype=np.float64)
+    cot = cotangent.contiguous()
+    if cot.shape != (len(tms), 10, pts.shape[1]) or cot.device != pts.device:
+        raise ValueError("cotangent must be [n_times][10][n_pts] on the points' device")
+    prec = {torch.float32: MIXED, torch.float64: FP64}[cot.dtype]
+    opts = Opts(prec, FIELD_KINDS[field_kind], int(max_iter), 0, float(mask_radius))
+    grad = torch.empty((n, len(PARAM_NAMES)), dtype=torch.float64, device=pts.device)
+    L = load_library()
+    _check(L.lw_fields_vjp(ctx.handle, arr, n, ct.c_void_p(pts.data_ptr()), pts.shape[1],
+                           tms.ctypes.data_as(ct.POINTER(ct.c_double)), len(tms), ct.byref(opts),
+                           ct.c_void_p(cot.data_ptr()), ct.c_void_p(grad.data_ptr()), _stream_ptr(pts.device)))
+    return grad
+
+
+def charges_to_params(charges: dict) -> torch.Tensor:
+    """[n, 11] float64 tensor of the differentiable trajectory parameters."""
+    c = charges
+    cols = [c["q"][:, None], c["c0"], c["amp"][:, None], c["omega"][:, None], c["phase"][:, None],
+            c["accel"][:, None], c["v"]]
+    return torch.tensor(np.concatenate(cols, axis=1), dtype=torch.float64)
+
+
+def params_to_charges(params: torch.Tensor, template: dict) -> dict:
+    """Charge dict with the parameters of `params` and the kinds and axes of `template`."""
+    p = params.detach().cpu().numpy()
+    c = {k: np.array(v, copy=True) for k, v in template.items()}
+    c["q"], c["c0"], c["amp"], c["omega"] = p[:, 0], p[:, 1:4], p[:, 4], p[:, 5]
+    c["phase"], c["accel"], c["v"] = p[:, 6], p[:, 7], p[:, 8:11]
+    return c
+
+
+class LWFieldsFn(torch.autograd.Function):
+    """Phi, A, E, B on the GPU as a differentiable function of the [n, 11] trajectory
+    parameters (CPU float64 tensor): the backward pass calls lw_fields_vjp."""
+
+    @staticmethod
+    def forward(fctx, params, points, template, times, precision, field_kind, mask_radius):
+        charges = params_to_charges(params, template)
+        out, _ = fields(charges, points, times, precision=precision, field_kind=field_kind,
+                        mask_radius=mask_radius)
+        fctx.save_for_backward(params)
+        fctx.meta = (points, template, times, field_kind, mask_radius)
+        return out
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        (params,) = fctx.saved_tensors
+        points, template, times, field_kind, mask_radius = fctx.meta
+        charges = params_to_charges(params, template)
+        g = fields_vjp(charges, points, times, grad_out, field_kind=field_kind, mask_radius=mask_radius)
+        return g.cpu(), None, None, None, None, None, None
 
 
 def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "strict", out_stride: int = 1,
