@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--cpu-sample-points", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dipole", action="store_true")
+    ap.add_argument("--cluster-steps", type=int, default=500,
+                    help="steps of the uneven-cluster workload to time")
     ap.add_argument("--grid-only", action="store_true",
                     help="time only the mixed grid step (for profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -192,6 +194,39 @@ def main():
                "ms": round(dsec * 1e3, 3), "dtype": "f64"}
         log(f"[bench] dipoles: {dsec * 1e3:.2f} ms, {dip['dipole_steps_per_s']:.3e} dipole-steps/s")
 
+    clusters = None
+    vjp = None
+    if not args.no_dipole:
+        cw = I.workload_clusters(steps=args.cluster_steps)
+        n_c = len(cw["dipoles"]["omega0"])
+        lw.dipole_run(cw["dipoles"], cw["inst_off"], cw["dt"], 10, out_stride=10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lw.dipole_run(cw["dipoles"], cw["inst_off"], cw["dt"], cw["steps"], out_stride=10, check=False)
+        torch.cuda.synchronize()
+        csec = time.perf_counter() - t0
+        lw.sync_status()
+        clusters = {"workload": cw["name"], "dipoles": n_c, "steps": cw["steps"],
+                    "dipole_steps_per_s": n_c * cw["steps"] / csec, "ms": round(csec * 1e3, 3), "dtype": "f64",
+                    "note": "the uneven-cluster workload runs 50,000 steps; this line times a prefix of it"}
+        log(f"[bench] clusters: {csec * 1e3:.1f} ms for {cw['steps']} steps, "
+            f"{clusters['dipole_steps_per_s']:.3e} dipole-steps/s")
+        dw = I.workload_detector()
+        dpts = torch.tensor(dw["points"], dtype=torch.float64, device="cuda")
+        dout, _ = lw.fields(dw["charges"], dpts, dw["times"], precision="fp64")
+        cot = torch.zeros_like(dout)
+        cot[:, 4:7] = 2.0 * dout[:, 4:7] / len(dw["times"])
+        lw.fields_vjp(dw["charges"], dpts, dw["times"], cot)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            lw.fields_vjp(dw["charges"], dpts, dw["times"], cot)
+        torch.cuda.synchronize()
+        vsec = (time.perf_counter() - t0) / 3
+        pairs = dpts.shape[1] * len(dw["charges"]["kind"]) * len(dw["times"])
+        vjp = {"workload": dw["name"], "ms": round(vsec * 1e3, 3), "pair_vjps_per_s": pairs / vsec, "dtype": "f64"}
+        log(f"[bench] grid VJP: {vsec * 1e3:.2f} ms, {vjp['pair_vjps_per_s']:.3e} pair VJPs/s")
+
     line = {
         "metric": METRIC, "value": value, "unit": "LW evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
@@ -200,6 +235,7 @@ def main():
                    "times": n_t, "evals_per_step": evals},
         "fp64_value": fp64_value, "mixed_over_fp64": value / fp64_value,
         "roofline": roofline, "cpu_baseline": cpu, "errors_vs_oracle": err, "dipoles": dip,
+        "clusters": clusters, "grid_vjp": vjp,
     }
     print(json.dumps(line), flush=True)
 
