@@ -215,6 +215,30 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
                         double *d_moment, double *d_ddot, double *d_energy, double *d_drive,
                         void *stream);
 
+/* Gradient of a detector objective with respect to the oscillator positions,
+ * by a backward-in-time discrete adjoint of the run.  The run is that of
+ * lw_dipole_run (same arguments; out_stride is ignored); the objective is
+ *   J = (1/n_snap) sum_k sum_p |E(r_p, t_k)|^2
+ * with E the total field (Eq. (E)) of every oscillator charge of every instance
+ * at detector point r_p and time t_k, read from the stored history at its
+ * retarded time.  The adjoint transposes each RK4 step and the delay coupling:
+ * every drive pair's retarded time is differentiated by the implicit-function
+ * theorem against the interpolated history, and the cotangents owed to earlier
+ * source times accumulate in an adjoint history read back as the sweep reaches
+ * them.  The forward history is kept whole in device memory (24 bytes per dipole
+ * per step).
+ *   d_det_pts    device FP64 SoA [3][n_det]
+ *   h_snap_times host FP64 [n_snap], each in [0, steps dt]
+ *   d_grad_pos   device FP64 [n_dip][3]: dJ/d origin, overwritten
+ *   h_J          host: J
+ * Instances may hold at most 1024 dipoles.  Synchronises `stream` and returns
+ * the run's latched errors (as lw_sync_status).  The position sums use device
+ * atomics: results agree to rounding between runs, not bitwise. */
+lw_status lw_dipole_run_vjp(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
+                            int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts, const double *d_det_pts,
+                            int64_t n_det, const double *h_snap_times, int32_t n_snap, double *d_grad_pos,
+                            double *h_J, void *stream);
+
 /* Collective decay rates and frequency shift of two-dipole instances from a
  * finished run's moments (Sec. 2.4, Eq. (KE)): the sum and difference of the
  * two moments are the in-phase and anti-phase normal modes; each is fitted,

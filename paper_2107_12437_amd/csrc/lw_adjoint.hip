@@ -24,105 +24,6 @@ namespace lw {
 // Parameter order of the gradient rows.
 enum { P_Q = 0, P_C0 = 1, P_AMP = 4, P_OMEGA = 5, P_PHASE = 6, P_ACCEL = 7, P_V = 8, NP = 11 };
 
-// Reverse of lw_terms<double>: given the cotangent ob of (Phi, A, E, B), the
-// cotangents of R, v, a and of kq = q / (4 pi eps0).
-__device__ __forceinline__ void lw_terms_vjp(const Kin &k, double kq, int field_kind, const double ob[10],
-                                             double Rb[3], double vb[3], double ab[3], double &kqb, double n[3],
-                                             double &kappa_out)
-{
-    const double ic = INV_C;
-    const double D = sqrt(k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2]);
-    const double iD = 1.0 / D;
-    double b[3], d[3], u[3];
-    for (int i = 0; i < 3; ++i) {
-        n[i] = k.R[i] * iD;
-        b[i] = k.v[i] * ic;
-        d[i] = k.a[i] * ic;
-        u[i] = n[i] - b[i];
-    }
-    const double nb = n[0] * b[0] + n[1] * b[1] + n[2] * b[2];
-    const double kappa = 1.0 - nb;
-    const double bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-    const double nd = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
-    const double ik = 1.0 / kappa;
-    const double kqD = kq * iD;
-    const double phi = kqD * ik;
-    const double f = phi * ik * ik;
-    const bool coul = field_kind != F_RADIATION, rad = field_kind != F_COULOMB;
-    const double cu = (coul ? (1.0 - bb) * iD : 0.0) + (rad ? nd * ic : 0.0);
-    const double cd = rad ? kappa * ic : 0.0;
-    double W[3], E[3], m[3];
-    for (int i = 0; i < 3; ++i) {
-        W[i] = u[i] * cu - d[i] * cd;
-        E[i] = f * W[i];
-        m[i] = n[i] * ic;
-    }
-    const double pc = phi * ic;
-    // ---- reverse ----
-    const double Phib = ob[0];
-    const double Ab[3] = {ob[1], ob[2], ob[3]};
-    const double Eb[3] = {ob[4], ob[5], ob[6]};
-    const double Bb[3] = {ob[7], ob[8], ob[9]};
-    // B = m x E
-    double mb[3], Et[3];
-    mb[0] = E[1] * Bb[2] - E[2] * Bb[1];
-    mb[1] = E[2] * Bb[0] - E[0] * Bb[2];
-    mb[2] = E[0] * Bb[1] - E[1] * Bb[0];
-    Et[0] = Eb[0] + (Bb[1] * m[2] - Bb[2] * m[1]);
-    Et[1] = Eb[1] + (Bb[2] * m[0] - Bb[0] * m[2]);
-    Et[2] = Eb[2] + (Bb[0] * m[1] - Bb[1] * m[0]);
-    // A = pc b
-    const double pcb = Ab[0] * b[0] + Ab[1] * b[1] + Ab[2] * b[2];
-    double bbar[3] = {pc * Ab[0], pc * Ab[1], pc * Ab[2]};
-    // E = f W, W = u cu - d cd
-    const double fb = Et[0] * W[0] + Et[1] * W[1] + Et[2] * W[2];
-    double ub[3], dbar[3];
-    double cub = 0.0, cdb = 0.0;
-    for (int i = 0; i < 3; ++i) {
-        const double Wb = f * Et[i];
-        ub[i] = Wb * cu;
-        cub += Wb * u[i];
-        dbar[i] = -Wb * cd;
-        cdb -= Wb * d[i];
-    }
-    // phi = kqD ik feeds Phi, pc and f
-    const double phib = Phib + pcb * ic + fb * ik * ik;
-    const double ikb_f = fb * 2.0 * phi * ik;
-    double ikb = ikb_f + phib * kqD;
-    const double kqDb = phib * ik;
-    // cu, cd
-    const double bbb = coul ? -cub * iD : 0.0;
-    double iDb = coul ? cub * (1.0 - bb) : 0.0;
-    const double ndb = rad ? cub * ic : 0.0;
-    double kappab = rad ? cdb * ic : 0.0;
-    // m = n / c
-    double nbar[3] = {mb[0] * ic, mb[1] * ic, mb[2] * ic};
-    // kqD = kq iD
-    iDb += kqDb * kq;
-    kqb = kqDb * iD;
-    // ik = 1 / kappa
-    kappab -= ikb * ik * ik;
-    // nd = n . d
-    for (int i = 0; i < 3; ++i) {
-        nbar[i] += ndb * d[i] + ub[i];
-        dbar[i] += ndb * n[i];
-        bbar[i] += -ub[i] + 2.0 * bbb * b[i];
-    }
-    // kappa = 1 - n . b
-    const double nbb = -kappab;
-    for (int i = 0; i < 3; ++i) {
-        nbar[i] += nbb * b[i];
-        bbar[i] += nbb * n[i];
-        vb[i] = bbar[i] * ic;
-        ab[i] = dbar[i] * ic;
-    }
-    // n = R iD with iD = 1/|R|
-    iDb += nbar[0] * k.R[0] + nbar[1] * k.R[1] + nbar[2] * k.R[2];
-    const double s = -iDb * iD * iD;
-    for (int i = 0; i < 3; ++i) Rb[i] = nbar[i] * iD + s * n[i];
-    kappa_out = kappa;
-}
-
 // Gradient of one (point, time, charge) contribution, added into g[NP].
 __device__ __forceinline__ void pair_param_grad(const SrcRec &S, const Kin &k, int field_kind, const double ob[10],
                                                 double g[NP])

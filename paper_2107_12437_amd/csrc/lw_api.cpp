@@ -64,6 +64,8 @@ struct lw_ctx {
     hipGraphExec_t graph_exec = nullptr;
     hipEvent_t graph_done = nullptr;
     // launch-shape tuner for the grid kernel: shape class -> best (block, tchunk)
+    void *d_work2 = nullptr;           // adjoint runs: full history and its cotangents
+    size_t work2_cap = 0;
     bool autotune = true;
     std::map<std::string, lw::FieldLaunch> tuned;
     std::string tune_file;
@@ -86,6 +88,22 @@ lw_status ensure_work(lw_ctx *ctx, size_t bytes, hipStream_t s)
         return fail(LW_E_NOMEM, "device workspace allocation of " + std::to_string(cap) + " bytes failed");
     }
     ctx->work_cap = cap;
+    return LW_OK;
+}
+
+lw_status ensure_work2(lw_ctx *ctx, size_t bytes, hipStream_t s)
+{
+    if (bytes <= ctx->work2_cap) return LW_OK;
+    LW_HIP(hipStreamSynchronize(s));
+    if (ctx->d_work2) LW_HIP(hipFree(ctx->d_work2));
+    ctx->d_work2 = nullptr;
+    ctx->work2_cap = 0;
+    size_t cap = align_up(std::max(bytes, (size_t)1 << 20), (size_t)1 << 20);
+    if (hipMalloc(&ctx->d_work2, cap) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LW_E_NOMEM, "adjoint workspace allocation of " + std::to_string(cap) + " bytes failed");
+    }
+    ctx->work2_cap = cap;
     return LW_OK;
 }
 
@@ -252,6 +270,7 @@ lw_status lw_destroy(lw_ctx *ctx)
     if (ctx->stage_evt) (void)hipEventDestroy(ctx->stage_evt);
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     if (ctx->d_work) (void)hipFree(ctx->d_work);
+    if (ctx->d_work2) (void)hipFree(ctx->d_work2);
     if (ctx->d_err) (void)hipFree(ctx->d_err);
     delete ctx;
     return LW_OK;
@@ -602,6 +621,75 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
         LW_HIP(hipStreamWaitEvent(s, ctx->join_b, 0));
     }
     return LW_OK;
+}
+
+lw_status lw_dipole_run_vjp(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
+                            int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts, const double *d_det_pts,
+                            int64_t n_det, const double *h_snap_times, int32_t n_snap, double *d_grad_pos, double *h_J,
+                            void *stream)
+{
+    if (!ctx || !opts || !h_dip || !h_inst_off || !d_det_pts || !h_snap_times || !d_grad_pos || !h_J)
+        return fail(LW_E_INVALID, "lw_dipole_run_vjp: null argument");
+    if (n_det < 1 || n_snap < 1 || n_dip < 1 || n_inst < 1 || steps < 1)
+        return fail(LW_E_INVALID, "lw_dipole_run_vjp: empty detector, snapshots, dipoles or run");
+    for (int k = 0; k < n_snap; ++k)
+        if (!(h_snap_times[k] >= 0.0 && h_snap_times[k] <= (double)steps * dt))
+            return fail(LW_E_INVALID, "lw_dipole_run_vjp: snapshot times must lie in [0, steps dt]");
+    int max_n = 0;
+    for (int k = 0; k < n_inst; ++k) max_n = std::max(max_n, h_inst_off[k + 1] - h_inst_off[k]);
+    if (max_n > 1024) return fail(LW_E_INVALID, "lw_dipole_run_vjp: instances of more than 1024 dipoles");
+    if (n_det * (int64_t)n_snap > ((int64_t)1 << 36)) return fail(LW_E_INVALID, "lw_dipole_run_vjp: detector too large");
+    LW_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t rows = steps + 1;
+    int64_t ring = 1;
+    while (ring < rows) ring <<= 1;
+    if (ring > (1 << 26)) return fail(LW_E_INVALID, "lw_dipole_run_vjp: run too long for the stored history");
+    const int64_t nblk = (n_det * n_snap + 255) / 256;
+    const size_t out_b = align_up(sizeof(double) * (size_t)(rows * n_dip), 256);
+    const size_t hist_b = align_up(sizeof(double) * (size_t)(ring * n_dip * 3), 256);
+    const size_t jp_b = align_up(sizeof(double) * (size_t)(nblk + 1), 256);
+    const size_t dip_b = align_up(sizeof(lw_dipole) * (size_t)n_dip, 256);
+    const size_t off_b = align_up(sizeof(int32_t) * (size_t)(n_inst + 1), 256);
+    const size_t tm_b = align_up(sizeof(double) * (size_t)n_snap, 256);
+    const size_t dev_b = align_up(lw::dip_dev_bytes() * (size_t)n_dip, 256);
+    lw_status st = ensure_work2(ctx, 3 * out_b + 2 * hist_b + jp_b + 256 + dip_b + off_b + tm_b + dev_b, s);
+    if (st != LW_OK) return st;
+    char *w2 = (char *)ctx->d_work2;
+    double *d_D = (double *)w2;
+    double *d_V = (double *)(w2 + out_b);
+    double *d_Ed = (double *)(w2 + 2 * out_b);
+    double *d_hist = (double *)(w2 + 3 * out_b);
+    double *d_hbar = (double *)(w2 + 3 * out_b + hist_b);
+    double *d_Jpart = (double *)(w2 + 3 * out_b + 2 * hist_b);
+    double *d_J = (double *)(w2 + 3 * out_b + 2 * hist_b + jp_b);
+    char *tail = w2 + 3 * out_b + 2 * hist_b + jp_b + 256;
+    // forward run with every step stored
+    lw_run_opts fo = *opts;
+    fo.out_stride = 1;
+    st = lw_dipole_run(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, steps, &fo, d_D, d_V, nullptr, d_Ed, stream);
+    if (st != LW_OK) return st;
+    // oscillator records, offsets and snapshot times for the adjoint kernels
+    st = acquire_stage(ctx, dip_b + off_b + tm_b);
+    if (st != LW_OK) return st;
+    char *stage = (char *)ctx->h_stage;
+    std::memcpy(stage, h_dip, sizeof(lw_dipole) * (size_t)n_dip);
+    std::memcpy(stage + dip_b, h_inst_off, sizeof(int32_t) * (size_t)(n_inst + 1));
+    std::memcpy(stage + dip_b + off_b, h_snap_times, sizeof(double) * (size_t)n_snap);
+    st = upload(ctx, tail, dip_b + off_b + tm_b, s);
+    if (st != LW_OK) return st;
+    const lw_dipole *d_in = (const lw_dipole *)tail;
+    const int32_t *d_off = (const int32_t *)(tail + dip_b);
+    const double *d_times = (const double *)(tail + dip_b + off_b);
+    lw::DipDev *d_dev = (lw::DipDev *)(tail + dip_b + off_b + tm_b);
+    LW_HIP(lw::launch_dipole_prep(d_in, n_dip, d_dev, s));
+    LW_HIP(lw::launch_dipole_vjp(d_dev, d_off, n_inst, max_n, n_dip, d_D, d_V, d_Ed, d_hist, d_hbar, (int)ring, steps,
+                                 dt, d_det_pts, n_det, d_times, n_snap, d_grad_pos, d_Jpart, d_J, ctx->d_err, s));
+    double J = 0.0;
+    LW_HIP(hipMemcpyAsync(&J, d_J, sizeof(double), hipMemcpyDeviceToHost, s));
+    st = lw_sync_status(ctx, stream);
+    *h_J = J;
+    return st;
 }
 
 // ---------------------------------------------------------------------------

@@ -16,22 +16,10 @@
 #include <math.h>
 
 #include "lw_device.hpp"
+#include "lw_dipole.hpp"
 #include "lw_internal.hpp"
 
 namespace lw {
-
-struct DipDev {
-    double origin[3];
-    double axis[3];
-    double omega0;
-    double q;
-    double f;        // q^2 / m  (m = m1 m2 / (m1 + m2), Eq. (eff_mass))
-    double gamma0;   // q^2 omega0^2 / (6 pi eps0 c^3 m)  (Sec. 2.3)
-    double cfp;      // offset of the +q charge per unit moment: m2 / (m1 + m2) / q   (Eq. (r_1))
-    double cfm;      // offset of the -q charge per unit moment: -m1 / (m1 + m2) / q  (Eq. (r_2))
-    double vfac;     // charge speed per unit d_dot: max(m1, m2) / (m1 + m2) / q
-    double d0;
-};
 
 size_t dip_dev_bytes() { return sizeof(DipDev); }
 
@@ -63,26 +51,6 @@ hipError_t launch_dipole_prep(const lw_dipole *d_in, int n, DipDev *d_dev, hipSt
     hipLaunchKernelGGL(dipole_prep_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d_in, n, d_dev);
     return hipGetLastError();
 }
-
-// Per-dipole constants of the instance, staged in LDS.
-struct DipLds {
-    double ox, oy, oz;
-    double px, py, pz;
-    double cfp, cfm;
-    double d0;
-};
-
-// Stored kinematics (d, d_dot, d_ddot) of source j at s steps after t = 0 (s
-// real).  Static at d0 before t = 0 (Sec. 3.2); linear interpolation between
-// stored steps (Sec. 3.1); beyond the newest step `nstep` a second-order
-// Taylor step from it (reached only when c dt exceeds a separation).
-struct Hist {
-    const double *ring;   // [ring][n][3]
-    int n;
-    int mask;             // ring - 1
-    double dt;
-    double inv_dt;
-};
 
 __device__ __forceinline__ void hist_at(const Hist &H, int j, double d0, int64_t nstep, double s, double out[3],
                                         double &slope, uint32_t &err)
@@ -162,7 +130,6 @@ __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, 
     return o[4] * Si.px + o[5] * Si.py + o[6] * Si.pz;
 }
 
-enum { ERR_HISTORY = 1u, ERR_NOCONV = 2u, ERR_VELOCITY = 4u, ERR_NONFINITE = 8u };
 
 // Drive fields of all targets of the instance at stage times theta in
 // `thetas[0..nth)` (in steps after nstep), written to Eout[th * n + i].
@@ -328,10 +295,6 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
 // reach, so all blocks of a launch may run in any order.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ DipLds dip_lds(const DipDev &D)
-{
-    return DipLds{D.origin[0], D.origin[1], D.origin[2], D.axis[0], D.axis[1], D.axis[2], D.cfp, D.cfm, D.d0};
-}
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict__ dev, const int32_t *__restrict__ tgt,

@@ -1,0 +1,49 @@
+// lw_dipole.hpp -- oscillator records and history access shared by the
+// forward run (lw_dipole.hip) and its adjoint (lw_dipole_adjoint.hip).
+#pragma once
+
+#include "lw_device.hpp"
+
+namespace lw {
+
+struct DipDev {
+    double origin[3];
+    double axis[3];
+    double omega0;
+    double q;
+    double f;        // q^2 / m  (m = m1 m2 / (m1 + m2), Eq. (eff_mass))
+    double gamma0;   // q^2 omega0^2 / (6 pi eps0 c^3 m)  (Sec. 2.3)
+    double cfp;      // offset of the +q charge per unit moment: m2 / (m1 + m2) / q   (Eq. (r_1))
+    double cfm;      // offset of the -q charge per unit moment: -m1 / (m1 + m2) / q  (Eq. (r_2))
+    double vfac;     // charge speed per unit d_dot: max(m1, m2) / (m1 + m2) / q
+    double d0;
+};
+
+// Per-dipole constants of the instance, staged in LDS.
+struct DipLds {
+    double ox, oy, oz;
+    double px, py, pz;
+    double cfp, cfm;
+    double d0;
+};
+
+// Stored kinematics (d, d_dot, d_ddot) of source j at s steps after t = 0 (s
+// real).  Static at d0 before t = 0 (Sec. 3.2); linear interpolation between
+// stored steps (Sec. 3.1); beyond the newest step `nstep` a second-order
+// Taylor step from it (reached only when c dt exceeds a separation).
+struct Hist {
+    const double *ring;   // [ring][n][3]
+    int n;
+    int mask;             // ring - 1
+    double dt;
+    double inv_dt;
+};
+
+__device__ __forceinline__ DipLds dip_lds(const DipDev &D)
+{
+    return DipLds{D.origin[0], D.origin[1], D.origin[2], D.axis[0], D.axis[1], D.axis[2], D.cfp, D.cfm, D.d0};
+}
+
+enum { ERR_HISTORY = 1u, ERR_NOCONV = 2u, ERR_VELOCITY = 4u, ERR_NONFINITE = 8u };
+
+}  // namespace lw

@@ -57,4 +57,14 @@ hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const 
                                uint32_t *d_err, int graph_chunk, hipStream_t s, hipStream_t cap,
                                hipGraph_t *graph_out, hipGraphExec_t *exec_out);
 
+// Gradient of the detector objective with respect to the oscillator positions
+// from a finished stride-1 run (lw_dipole_adjoint.hip).  d_hist / d_hbar hold
+// ring x n_dip x 3 doubles (ring >= steps + 1, power of two); d_Jpart one
+// double per detector workgroup ((npts * n_snap + 255) / 256).
+hipError_t launch_dipole_vjp(const DipDev *d_dev, const int32_t *d_off, int n_inst, int max_n, int n_dip,
+                             const double *d_D, const double *d_V, const double *d_Ed, double *d_hist, double *d_hbar,
+                             int ring, int64_t steps, double dt, const double *d_pts, int64_t npts,
+                             const double *d_times, int n_snap, double *d_grad, double *d_Jpart, double *d_J,
+                             uint32_t *d_err, hipStream_t s);
+
 }  // namespace lw

@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "LW_OK", 1: "LW_E_INVALID", 2: "LW_E_SUPERLUMINAL", 3: "LW_E_
                 4: "LW_E_VELOCITY", 5: "LW_E_NOCONV", 6: "LW_E_HIP", 7: "LW_E_NOMEM",
                 8: "LW_E_NONFINITE", 9: "LW_E_HISTORY"}
 EXPORTS = ("lw_last_error", "lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields",
-           "lw_fields_vjp", "lw_dipole_run", "lw_pair_modes", "lw_gamma0")
+           "lw_fields_vjp", "lw_dipole_run", "lw_dipole_run_vjp", "lw_pair_modes", "lw_gamma0")
 PARAM_NAMES = ("q", "c0x", "c0y", "c0z", "amp", "omega", "phase", "accel", "vx", "vy", "vz")
 OUTPUT_NAMES = ("phi", "Ax", "Ay", "Az", "Ex", "Ey", "Ez", "Bx", "By", "Bz")
 
@@ -85,12 +85,14 @@ def load_library(path: str = LIB_PATH):
     L.lw_fields_vjp.argtypes = [vp, ct.POINTER(Traj), i32, vp, i64, ct.POINTER(dbl), i32, ct.POINTER(Opts), vp, vp, vp]
     L.lw_dipole_run.argtypes = [vp, ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, i64,
                                 ct.POINTER(RunOpts), vp, vp, vp, vp, vp]
+    L.lw_dipole_run_vjp.argtypes = [vp, ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, i64,
+                                    ct.POINTER(RunOpts), vp, i64, ct.POINTER(dbl), i32, vp, ct.POINTER(dbl), vp]
     L.lw_pair_modes.argtypes = [ct.POINTER(dbl), i64, i32, ct.POINTER(i32), i32, dbl, i64,
                                 ct.POINTER(dbl), ct.POINTER(i64), ct.POINTER(dbl)]
     L.lw_gamma0.restype = dbl
     L.lw_gamma0.argtypes = [dbl, dbl, dbl]
     for name in ("lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields", "lw_fields_vjp",
-                 "lw_dipole_run", "lw_pair_modes"):
+                 "lw_dipole_run", "lw_dipole_run_vjp", "lw_pair_modes"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -302,6 +304,49 @@ def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "st
     if check:
         sync_status(ctx, dev)
     return res
+
+
+def dipole_run_vjp(dipoles: dict, inst_off, dt: float, steps: int, det_points: torch.Tensor, snap_times,
+                   policy: str = "strict", max_vel: float = 0.0, ring_depth: int = 0, stepped_min_n: int = 0,
+                   ctx: Context | None = None):
+    """(J, dJ/d origin [n_dip, 3] GPU tensor) of J = (1/n_snap) sum |E|^2 of all oscillator
+    charges over the detector points ([3, n] float64 on the GPU) at snap_times."""
+    if not (isinstance(det_points, torch.Tensor) and det_points.is_cuda and det_points.dtype == torch.float64):
+        raise ValueError("det_points must be a [3, n] float64 tensor on the GPU")
+    pts = det_points.contiguous()
+    dev = pts.device
+    ctx = ctx or default_context(dev.index)
+    arr, n = pack_dipoles(dipoles)
+    off = np.ascontiguousarray(inst_off, dtype=np.int32)
+    tms = np.ascontiguousarray(np.atleast_1d(snap_times), dtype=np.float64)
+    grad = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    J = ct.c_double()
+    opts = RunOpts(FP64, DT_POLICIES[policy], 1, float(max_vel), int(ring_depth), int(stepped_min_n))
+    _check(load_library().lw_dipole_run_vjp(ctx.handle, arr, n, off.ctypes.data_as(ct.POINTER(ct.c_int32)),
+                                            len(off) - 1, float(dt), int(steps), ct.byref(opts),
+                                            ct.c_void_p(pts.data_ptr()), pts.shape[1],
+                                            tms.ctypes.data_as(ct.POINTER(ct.c_double)), len(tms),
+                                            ct.c_void_p(grad.data_ptr()), ct.byref(J), _stream_ptr(dev)))
+    return J.value, grad
+
+
+class DipoleDetectorFn(torch.autograd.Function):
+    """J = (1/n_snap) sum |E|^2 of the oscillators' charges on a detector as a differentiable
+    function of the origins ([n_dip, 3] CPU float64 tensor); backward uses the stored gradient
+    of lw_dipole_run_vjp."""
+
+    @staticmethod
+    def forward(fctx, origins, template, inst_off, dt, steps, det_points, snap_times, policy):
+        dip = {k: np.array(v, copy=True) for k, v in template.items()}
+        dip["origin"] = origins.detach().cpu().numpy()
+        J, grad = dipole_run_vjp(dip, inst_off, dt, steps, det_points, snap_times, policy=policy)
+        fctx.save_for_backward(grad.cpu())
+        return torch.tensor(J, dtype=torch.float64)
+
+    @staticmethod
+    def backward(fctx, gJ):
+        (grad,) = fctx.saved_tensors
+        return gJ * grad, None, None, None, None, None, None, None
 
 
 def sync_status(ctx: Context | None = None, device=None):
