@@ -390,7 +390,7 @@ lw_status lw_fields(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, co
         LW_HIP(hipEventCreate(&e1));
         float best = 1e30f;
         for (int b : {64, 128, 256})
-            for (int t : {1, 2, 4, 8, 16}) {
+            for (int t : {1, 2, 4}) {
                 if (t > 1 && t >= 2 * n_times) continue;
                 const lw::FieldLaunch C{b, t};
                 LW_HIP(lw::launch_fields(d_recs, n_charges, d_pts, n_pts, n_times, *opts, tol_rel, mask_r, d_out,

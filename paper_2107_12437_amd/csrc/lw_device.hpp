@@ -39,41 +39,65 @@ struct alignas(16) SrcRec {
     double Lmax;      // accel: distance travelled along e1 by time t
     double v[3];
     double rt[3];     // uniform velocity: position at time t
+    // FP32 coefficients of beta and beta_dot (mixed path) in the orbit frame:
+    // circular  beta = -s bw1 + c bw2,  beta_dot = -(c aw1 + s aw2);
+    // linear    beta = -s bw1,          beta_dot = -c aw1;
+    // bw = amp omega / c * e, aw = amp omega^2 / c * e
+    float bw1[3], bw2[3], aw1[3], aw2[3];
 };
 
 // Retarded kinematics seen from the observation point: R = x - r(t'),
 // velocity and acceleration of the charge at t' (Sec. 2.1).
 struct Kin {
     double R[3];
-    double v[3];
+    double v[3];        // FP64 path
     double a[3];
+    float bf[3], df[3]; // mixed path: beta = v / c and beta_dot = a / c in FP32
     double tp;          // retarded time t'
     double cph, sph;    // cos, sin of the phase at t' (oscillating families)
     uint32_t flags;
 };
+
+// The mixed path's beta and beta_dot from FP64 velocity and acceleration.
+__device__ __forceinline__ void kin_beta_from_va(Kin &k)
+{
+    for (int i = 0; i < 3; ++i) {
+        k.bf[i] = (float)(k.v[i] * INV_C);
+        k.df[i] = (float)(k.a[i] * INV_C);
+    }
+}
+
+// a * b + k with the constant k read from a scalar register pair.  Polynomial
+// coefficients used this way stay out of vector registers: held there, every
+// accumulate would first need a copy of its coefficient (the two-address form
+// overwrites the addend), and the coefficients would take ~30 VGPRs.
+__device__ __forceinline__ double fma_k(double a, double b, double k)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
 
 // sin and cos of a small angle |x| <= 0.75 from their Taylor series (terms
 // through x^17 and x^16; the truncation error is below 1e-18).
 __device__ __forceinline__ void sincos_small(double x, double &s, double &c)
 {
     const double x2 = x * x;
-    double ps = -1.0 / 355687428096000.0;          // -1/17!
-    ps = fma(ps, x2, 1.0 / 1307674368000.0);       //  1/15!
-    ps = fma(ps, x2, -1.0 / 6227020800.0);         // -1/13!
-    ps = fma(ps, x2, 1.0 / 39916800.0);            //  1/11!
-    ps = fma(ps, x2, -1.0 / 362880.0);             // -1/9!
-    ps = fma(ps, x2, 1.0 / 5040.0);                //  1/7!
-    ps = fma(ps, x2, -1.0 / 120.0);
-    ps = fma(ps, x2, 1.0 / 6.0);
+    double ps = fma_k(x2, -1.0 / 355687428096000.0, 1.0 / 1307674368000.0);   // -1/17!, 1/15!
+    ps = fma_k(ps, x2, -1.0 / 6227020800.0);       // -1/13!
+    ps = fma_k(ps, x2, 1.0 / 39916800.0);          //  1/11!
+    ps = fma_k(ps, x2, -1.0 / 362880.0);           // -1/9!
+    ps = fma_k(ps, x2, 1.0 / 5040.0);              //  1/7!
+    ps = fma_k(ps, x2, -1.0 / 120.0);
+    ps = fma_k(ps, x2, 1.0 / 6.0);
     // ps now holds 1/3! - x^2/5! + ...; sin x = x - x^3 * ps
     s = fma(-x * x2, ps, x);
-    double pc = 1.0 / 20922789888000.0;            //  1/16!
-    pc = fma(pc, x2, -1.0 / 87178291200.0);        // -1/14!
-    pc = fma(pc, x2, 1.0 / 479001600.0);           //  1/12!
-    pc = fma(pc, x2, -1.0 / 3628800.0);            // -1/10!
-    pc = fma(pc, x2, 1.0 / 40320.0);               //  1/8!
-    pc = fma(pc, x2, -1.0 / 720.0);                // -1/6!
-    pc = fma(pc, x2, 1.0 / 24.0);                  //  1/4!
+    double pc = fma_k(x2, 1.0 / 20922789888000.0, -1.0 / 87178291200.0);       // 1/16!, -1/14!
+    pc = fma_k(pc, x2, 1.0 / 479001600.0);         //  1/12!
+    pc = fma_k(pc, x2, -1.0 / 3628800.0);          // -1/10!
+    pc = fma_k(pc, x2, 1.0 / 40320.0);             //  1/8!
+    pc = fma_k(pc, x2, -1.0 / 720.0);              // -1/6!
+    pc = fma_k(pc, x2, 1.0 / 24.0);                //  1/4!
     pc = fma(pc, x2, -0.5);                        // -1/2!
     c = fma(pc, x2, 1.0);
 }
@@ -107,12 +131,17 @@ __device__ __forceinline__ double sqrt_rough(double x) { return __builtin_amdgcn
 // updates: small changes rotate it, large ones recompute it.
 struct Phase {
     double c, s;
+    // from cw, sw = cos, sin(omega tau)
+    __device__ __forceinline__ void set_from(const SrcRec &S, double cw, double sw)
+    {
+        c = S.cT * cw + S.sT * sw;      // cos(Theta - w tau)
+        s = S.sT * cw - S.cT * sw;      // sin(Theta - w tau)
+    }
     __device__ __forceinline__ void set(const SrcRec &S, double tau)
     {
         double sw, cw;
         sincos_reduced(S.omega * tau, sw, cw);
-        c = S.cT * cw + S.sT * sw;      // cos(Theta - w tau)
-        s = S.sT * cw - S.cT * sw;      // sin(Theta - w tau)
+        set_from(S, cw, sw);
     }
     __device__ __forceinline__ void advance(const SrcRec &S, double tau_new, double dtau)
     {
@@ -120,8 +149,8 @@ struct Phase {
         if (fabs(ang) <= 0x1p-8) {
             // |ang| <= 2^-8: Taylor through x^7 and x^6 (truncation below 5e-25)
             const double a2 = ang * ang;
-            const double sa = fma(-ang * a2, fma(fma(-a2, 1.0 / 5040.0, 1.0 / 120.0), -a2, 1.0 / 6.0), ang);
-            const double ca = fma(a2, fma(a2, fma(-a2, 1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+            const double sa = fma(-ang * a2, fma_k(fma_k(a2, -1.0 / 5040.0, 1.0 / 120.0), -a2, 1.0 / 6.0), ang);
+            const double ca = fma(a2, fma(a2, fma_k(a2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
             const double cn = c * ca - s * sa;
             const double sn = s * ca + c * sa;
             c = cn;
@@ -157,15 +186,39 @@ __device__ __forceinline__ double rcp_steer(double x)
     return fma(r, fma(-x, r, 1.0), r);
 }
 
+// |x| and 1/|x| from s = |x|^2 (s > 0 and normal): v_rsq_f64 refined by one
+// Goldschmidt step (both the root and the half-reciprocal), then Newton
+// corrections of the root on its residual s - r^2.  FULL takes two corrections
+// (the root to about one ulp, for the FP64 tolerance), otherwise one (relative
+// error far below the 2^-32 tolerance of the mixed path).  The reciprocal keeps
+// the Goldschmidt step's accuracy, which is what steering terms need.
+template <bool FULL>
+__device__ __forceinline__ void root_rsqrt(double s, double &r, double &ir)
+{
+    const double y = __builtin_amdgcn_rsq(s);
+    double g = s * y, h = 0.5 * y;
+    const double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    g = fma(fma(-g, g, s), h, g);
+    if (FULL) g = fma(fma(-g, g, s), h, g);
+    r = g;
+    ir = 2.0 * h;
+}
+
 // One safeguarded Halley update of g(tau) = c tau - D(tau) with g' = c - D'
 // and g'' = -D''.  An exact root, or a step below the rounding of tau, returns
 // tau itself (converged).  The Halley step is used while its denominator stays
 // above g'^2 (the step is then at most twice Newton's), else Newton's.  A step
 // leaving the bracket goes to the nearer end if that end has not been
 // evaluated yet (the geometric bounds are often close to the root), otherwise
-// bisects; so does a step onto an end already evaluated.
-__device__ __forceinline__ double halley_step(double tau, double D, double dD, double ddD, Bracket &b)
+// bisects; so does a step onto an end already evaluated.  `free_step` reports
+// whether the returned iterate is the plain Halley/Newton step (not moved onto
+// the bracket).
+__device__ __forceinline__ double halley_step(double tau, double D, double dD, double ddD, Bracket &b,
+                                              bool &free_step)
 {
+    free_step = true;
     const double g = C_LIGHT * tau - D;
     if (g == 0.0) return tau;
     if (g < 0.0) {
@@ -180,9 +233,19 @@ __device__ __forceinline__ double halley_step(double tau, double D, double dD, d
     double tn = (den > gp * gp) ? tau - 2.0 * g * gp * rcp_steer(den) : tau - g * rcp_steer(gp);
     if (tn == tau) return tau;
     // landing on an evaluated end again would cycle: bisect instead
-    if (tn <= b.lo) tn = b.lo_ev ? 0.5 * (b.lo + b.hi) : b.lo;
-    else if (tn >= b.hi) tn = b.hi_ev ? 0.5 * (b.lo + b.hi) : b.hi;
+    if (tn <= b.lo) {
+        tn = b.lo_ev ? 0.5 * (b.lo + b.hi) : b.lo;
+        free_step = false;
+    } else if (tn >= b.hi) {
+        tn = b.hi_ev ? 0.5 * (b.lo + b.hi) : b.hi;
+        free_step = false;
+    }
     return tn;
+}
+__device__ __forceinline__ double halley_step(double tau, double D, double dD, double ddD, Bracket &b)
+{
+    bool free_step;
+    return halley_step(tau, D, dD, ddD, b, free_step);
 }
 
 // Plain Newton update (same safeguards), for sources whose D'' is not tracked.
@@ -190,6 +253,7 @@ __device__ __forceinline__ double newton_step(double tau, double D, double dD, B
 {
     return halley_step(tau, D, dD, 0.0, b);
 }
+
 
 // Converged when the last step is below tol_rel (relative), or when both
 // bracket ends have been evaluated and lie within 4 tol_rel of each other
@@ -199,99 +263,166 @@ __device__ __forceinline__ bool converged(double tn, double tau, double tol_rel,
     return fabs(tn - tau) <= tol_rel * tn || (b.lo_ev && b.hi_ev && b.hi - b.lo <= 4.0 * tol_rel * tn);
 }
 
+// A-posteriori stop for trajectories whose g is smooth in tau (circular and
+// linear oscillation): from tau, Newton's step leaves an error of about
+// |g''| / (2 g') dtau^2 and Halley's a smaller (cubic) one, so once that bound
+// is below tol/4 the new iterate is accepted without evaluating D at it.
+// Only a free (unclamped) step qualifies.
+__device__ __forceinline__ bool converged_smooth(double tn, double tau, double tol_rel, const Bracket &b,
+                                                 bool free_step, double dD, double ddD)
+{
+    const double st = tn - tau;
+    return converged(tn, tau, tol_rel, b) ||
+           (free_step && fabs(ddD) * (st * st) <= 0.5 * tol_rel * tn * (C_LIGHT - dD));
+}
+
+// Part of a source's retarded-time problem that does not depend on the
+// observation time, for one observation point: the point in the source's frame,
+// the geometric bracket on tau and the starting value with cos/sin(omega tau0).
+// Field kernels build it once per (point, charge) and reuse it for every time.
+struct Geo {
+    double w[3];      // x - c0
+    double w1, w2, w3;// circular: coordinates along e1, e2, e3; linear, accel: w1 along e1, w2 = distance^2 from the axis
+    double lo, hi;    // bracket on c tau / c (circular, linear)
+    double tau0;      // starting value (circular, linear)
+    double cw, sw;    // cos, sin of omega tau0
+};
+
+__device__ __forceinline__ void geo_prepare(const SrcRec &S, const double x[3], Geo &g)
+{
+    for (int i = 0; i < 3; ++i) g.w[i] = x[i] - S.c0[i];
+    const double *w = g.w;
+    const double A = S.amp;
+    g.w1 = w[0] * S.e1[0] + w[1] * S.e1[1] + w[2] * S.e1[2];
+    if (S.kind == K_CIRCULAR) {
+        const double w1 = g.w1;
+        const double w2 = w[0] * S.e2[0] + w[1] * S.e2[1] + w[2] * S.e2[2];
+        const double w3 = w[0] * S.e3[0] + w[1] * S.e3[1] + w[2] * S.e3[2];
+        g.w2 = w2;
+        g.w3 = w3;
+        const double rho = sqrt_rough(w1 * w1 + w2 * w2);
+        const double WA = w1 * w1 + w2 * w2 + w3 * w3 + A * A;
+        // the distance to the orbit lies between these, so c tau does too
+        // (widened by 1e-6 to cover the rough square roots)
+        g.lo = sqrt_rough(w3 * w3 + (rho - A) * (rho - A)) * (INV_C * (1.0 - 1e-6));
+        g.hi = sqrt_rough(w3 * w3 + (rho + A) * (rho + A)) * (INV_C * (1.0 + 1e-6));
+        g.tau0 = fmin(fmax(sqrt_rough(WA) * INV_C, g.lo), g.hi);
+        sincos_reduced(S.omega * g.tau0, g.sw, g.cw);
+    } else if (S.kind == K_LINEAR_OSC || S.kind == K_ACCEL) {
+        const double w1 = g.w1;
+        const double p0 = w[0] - w1 * S.e1[0], p1 = w[1] - w1 * S.e1[1], p2 = w[2] - w1 * S.e1[2];
+        const double perp2 = p0 * p0 + p1 * p1 + p2 * p2;     // distance^2 from the axis line
+        g.w2 = perp2;
+        if (S.kind == K_LINEAR_OSC) {
+            const double W2 = perp2 + w1 * w1;
+            const double u = fmin(fmax(w1, -A), A);
+            g.lo = sqrt_rough(perp2 + (w1 - u) * (w1 - u)) * (INV_C * (1.0 - 1e-6));
+            g.hi = sqrt_rough(W2 + A * A + 2.0 * A * fabs(w1)) * (INV_C * (1.0 + 1e-6));
+            g.tau0 = fmin(fmax(sqrt_rough(W2 + 0.5 * A * A) * INV_C, g.lo), g.hi);
+            sincos_reduced(S.omega * g.tau0, g.sw, g.cw);
+        }
+    }
+}
+
 // --- circular orbit: r = c0 + amp (cos th e1 + sin th e2), th = Theta - w tau ---
-__device__ __forceinline__ void solve_circular(const SrcRec &S, const double w[3], int max_iter,
-                                               double tol_rel, Kin &k)
+template <bool FULL>
+__device__ __forceinline__ void solve_circular(const SrcRec &S, const Geo &g, int max_iter, double tol_rel, Kin &k)
 {
     const double A = S.amp, om = S.omega;
-    const double w1 = w[0] * S.e1[0] + w[1] * S.e1[1] + w[2] * S.e1[2];
-    const double w2 = w[0] * S.e2[0] + w[1] * S.e2[1] + w[2] * S.e2[2];
-    const double w3 = w[0] * S.e3[0] + w[1] * S.e3[1] + w[2] * S.e3[2];
-    const double rho = sqrt_rough(w1 * w1 + w2 * w2);
-    const double WA = w1 * w1 + w2 * w2 + w3 * w3 + A * A;
-    // the distance to the orbit lies between these, so c tau does too
-    // (widened by 1e-6 to cover the rough square roots)
-    Bracket b(sqrt_rough(w3 * w3 + (rho - A) * (rho - A)) * (INV_C * (1.0 - 1e-6)),
-              sqrt_rough(w3 * w3 + (rho + A) * (rho + A)) * (INV_C * (1.0 + 1e-6)));
-    double tau = fmin(fmax(sqrt_rough(WA) * INV_C, b.lo), b.hi);
+    const double w1 = g.w1, w2 = g.w2, w3 = g.w3;
+    Bracket b(g.lo, g.hi);
+    double tau = g.tau0;
     Phase ph;
-    ph.set(S, tau);
+    ph.set_from(S, g.cw, g.sw);
     bool ok = (b.hi == b.lo);
     for (int it = 0; it < max_iter && !ok; ++it) {
         // R = x - r(t') in the orbit frame (no cancellation near the orbit)
         const double x1 = w1 - A * ph.c, x2 = w2 - A * ph.s;
-        const double D = sqrt(x1 * x1 + x2 * x2 + w3 * w3);
-        const double iD = (D > 0.0) ? rcp_steer(D) : 0.0;
+        double D, iD;
+        root_rsqrt<FULL>(fmax(x1 * x1 + x2 * x2 + w3 * w3, 1e-300), D, iD);
         const double Q = ph.c * x2 - ph.s * x1;              // D' = n . v = A w Q / D
         const double P = w1 * ph.c + w2 * ph.s;              // D'' = (A w^2 P - D'^2) / D
         const double dD = A * om * Q * iD;
         const double ddD = (A * om * om * P - dD * dD) * iD;
-        const double tn = halley_step(tau, D, dD, ddD, b);
+        bool free_step;
+        const double tn = halley_step(tau, D, dD, ddD, b, free_step);
         ph.advance(S, tn, tn - tau);
-        ok = converged(tn, tau, tol_rel, b);
+        ok = converged_smooth(tn, tau, tol_rel, b, free_step, dD, ddD);
         tau = tn;
     }
     k.flags = ok ? 0u : FLAG_NOCONV;
     k.tp = S.t - tau;
     k.cph = ph.c;
     k.sph = ph.s;
-    double ro[3], vo[3];
-    for (int i = 0; i < 3; ++i) {
-        ro[i] = A * (ph.c * S.e1[i] + ph.s * S.e2[i]);
-        vo[i] = A * (-ph.s * S.e1[i] + ph.c * S.e2[i]);
-        k.R[i] = w[i] - ro[i];
-        k.v[i] = om * vo[i];
-        k.a[i] = -om * om * ro[i];
+    if (FULL) {
+        double ro[3], vo[3];
+        for (int i = 0; i < 3; ++i) {
+            ro[i] = A * (ph.c * S.e1[i] + ph.s * S.e2[i]);
+            vo[i] = A * (-ph.s * S.e1[i] + ph.c * S.e2[i]);
+            k.R[i] = g.w[i] - ro[i];
+            k.v[i] = om * vo[i];
+            k.a[i] = -om * om * ro[i];
+        }
+    } else {
+        const float cf = (float)ph.c, sf = (float)ph.s;
+        for (int i = 0; i < 3; ++i) {
+            k.R[i] = g.w[i] - A * (ph.c * S.e1[i] + ph.s * S.e2[i]);
+            k.bf[i] = cf * S.bw2[i] - sf * S.bw1[i];
+            k.df[i] = -(cf * S.aw1[i] + sf * S.aw2[i]);
+        }
     }
 }
 
 // --- linear oscillation: r = c0 + amp cos th e1 ---
-__device__ __forceinline__ void solve_linear(const SrcRec &S, const double w[3], int max_iter,
-                                             double tol_rel, Kin &k)
+template <bool FULL>
+__device__ __forceinline__ void solve_linear(const SrcRec &S, const Geo &g, int max_iter, double tol_rel, Kin &k)
 {
     const double A = S.amp, om = S.omega;
-    const double w1 = w[0] * S.e1[0] + w[1] * S.e1[1] + w[2] * S.e1[2];
-    const double p0 = w[0] - w1 * S.e1[0], p1 = w[1] - w1 * S.e1[1], p2 = w[2] - w1 * S.e1[2];
-    const double perp2 = p0 * p0 + p1 * p1 + p2 * p2;       // distance^2 from the axis line
-    const double W2 = perp2 + w1 * w1;
-    const double u = fmin(fmax(w1, -A), A);
-    Bracket b(sqrt_rough(perp2 + (w1 - u) * (w1 - u)) * (INV_C * (1.0 - 1e-6)),
-              sqrt_rough(W2 + A * A + 2.0 * A * fabs(w1)) * (INV_C * (1.0 + 1e-6)));
-    double tau = fmin(fmax(sqrt_rough(W2 + 0.5 * A * A) * INV_C, b.lo), b.hi);
+    const double w1 = g.w1, perp2 = g.w2;
+    Bracket b(g.lo, g.hi);
+    double tau = g.tau0;
     Phase ph;
-    ph.set(S, tau);
+    ph.set_from(S, g.cw, g.sw);
     bool ok = (b.hi == b.lo);
     for (int it = 0; it < max_iter && !ok; ++it) {
         const double x1 = w1 - A * ph.c;                     // R . e1
-        const double D = sqrt(perp2 + x1 * x1);
-        const double iD = (D > 0.0) ? rcp_steer(D) : 0.0;
+        double D, iD;
+        root_rsqrt<FULL>(fmax(perp2 + x1 * x1, 1e-300), D, iD);
         const double v1 = A * om * ph.s;                     // d x1 / d tau = -v1
         const double dD = -v1 * x1 * iD;
         const double ddD = (v1 * v1 + x1 * A * om * om * ph.c - dD * dD) * iD;
-        const double tn = halley_step(tau, D, dD, ddD, b);
+        bool free_step;
+        const double tn = halley_step(tau, D, dD, ddD, b, free_step);
         ph.advance(S, tn, tn - tau);
-        ok = converged(tn, tau, tol_rel, b);
+        ok = converged_smooth(tn, tau, tol_rel, b, free_step, dD, ddD);
         tau = tn;
     }
     k.flags = ok ? 0u : FLAG_NOCONV;
     k.tp = S.t - tau;
     k.cph = ph.c;
     k.sph = ph.s;
-    for (int i = 0; i < 3; ++i) {
-        k.R[i] = w[i] - A * ph.c * S.e1[i];
-        k.v[i] = -A * om * ph.s * S.e1[i];
-        k.a[i] = -A * om * om * ph.c * S.e1[i];
+    if (FULL) {
+        for (int i = 0; i < 3; ++i) {
+            k.R[i] = g.w[i] - A * ph.c * S.e1[i];
+            k.v[i] = -A * om * ph.s * S.e1[i];
+            k.a[i] = -A * om * om * ph.c * S.e1[i];
+        }
+    } else {
+        const float cf = (float)ph.c, sf = (float)ph.s;
+        for (int i = 0; i < 3; ++i) {
+            k.R[i] = g.w[i] - A * ph.c * S.e1[i];
+            k.bf[i] = -sf * S.bw1[i];
+            k.df[i] = -cf * S.aw1[i];
+        }
     }
 }
 
 // --- uniform acceleration from rest at t = 0 along e1 ---
-__device__ __forceinline__ void solve_accel(const SrcRec &S, const double w[3], int max_iter,
-                                            double tol_rel, Kin &k)
+template <bool FULL>
+__device__ __forceinline__ void solve_accel(const SrcRec &S, const Geo &g, int max_iter, double tol_rel, Kin &k)
 {
     const double acc = S.accel, L = S.Lmax, t = S.t;
-    const double w1 = w[0] * S.e1[0] + w[1] * S.e1[1] + w[2] * S.e1[2];
-    const double p0 = w[0] - w1 * S.e1[0], p1 = w[1] - w1 * S.e1[1], p2 = w[2] - w1 * S.e1[2];
-    const double perp2 = p0 * p0 + p1 * p1 + p2 * p2;       // distance^2 from the line of motion
+    const double w1 = g.w1, perp2 = g.w2;
     const double W2 = perp2 + w1 * w1;
     // positions up to time t fill the segment [0, L] along e1
     const double u = fmin(fmax(w1, 0.0), L);
@@ -305,8 +436,8 @@ __device__ __forceinline__ void solve_accel(const SrcRec &S, const double w[3], 
         const double s = (tp > 0.0) ? 0.5 * acc * tp * tp : 0.0;   // distance along e1
         const double vel = (tp > 0.0) ? acc * tp : 0.0;
         const double x1 = w1 - s;
-        const double D = sqrt(perp2 + x1 * x1);
-        const double iD = (D > 0.0) ? rcp_steer(D) : 0.0;
+        double D, iD;
+        root_rsqrt<FULL>(fmax(perp2 + x1 * x1, 1e-300), D, iD);
         const double dD = vel * x1 * iD;                      // d x1 / d tau = vel
         const double ddD = (vel * vel - ((tp > 0.0) ? acc * x1 : 0.0) - dD * dD) * iD;
         const double tn = halley_step(tau, D, dD, ddD, b);
@@ -322,7 +453,7 @@ __device__ __forceinline__ void solve_accel(const SrcRec &S, const double w[3], 
     const double vel = (tp >= 0.0) ? acc * tp : 0.0;
     const double ac = (tp >= 0.0) ? acc : 0.0;
     for (int i = 0; i < 3; ++i) {
-        k.R[i] = w[i] - s * S.e1[i];
+        k.R[i] = g.w[i] - s * S.e1[i];
         k.v[i] = vel * S.e1[i];
         k.a[i] = ac * S.e1[i];
     }
@@ -351,18 +482,28 @@ __device__ __forceinline__ void solve_uniform(const SrcRec &S, const double x[3]
     k.flags = 0u;
 }
 
-__device__ __forceinline__ void retarded(const SrcRec &S, const double x[3], int max_iter, double tol_rel,
-                                         Kin &k)
+// Retarded kinematics of source S (its record for the observation time) seen
+// from point x, with g = geo_prepare(record of any time of this source, x).
+// FULL: FP64 tolerance (square roots to about one ulp); otherwise the mixed
+// path's relaxed tolerance.
+template <bool FULL>
+__device__ __forceinline__ void retarded_geo(const SrcRec &S, const Geo &g, const double x[3], int max_iter,
+                                             double tol_rel, Kin &k)
 {
-    double w[3] = {x[0] - S.c0[0], x[1] - S.c0[1], x[2] - S.c0[2]};
     switch (S.kind) {
-    case K_CIRCULAR: solve_circular(S, w, max_iter, tol_rel, k); break;
-    case K_LINEAR_OSC: solve_linear(S, w, max_iter, tol_rel, k); break;
-    case K_ACCEL: solve_accel(S, w, max_iter, tol_rel, k); break;
-    case K_UNIFORM_VELOCITY: solve_uniform(S, x, k); break;
+    case K_CIRCULAR: solve_circular<FULL>(S, g, max_iter, tol_rel, k); break;
+    case K_LINEAR_OSC: solve_linear<FULL>(S, g, max_iter, tol_rel, k); break;
+    case K_ACCEL:
+        solve_accel<FULL>(S, g, max_iter, tol_rel, k);
+        if (!FULL) kin_beta_from_va(k);
+        break;
+    case K_UNIFORM_VELOCITY:
+        solve_uniform(S, x, k);
+        if (!FULL) kin_beta_from_va(k);
+        break;
     default:
-        for (int i = 0; i < 3; ++i) { k.R[i] = w[i]; k.v[i] = 0.0; k.a[i] = 0.0; }
-        k.tp = S.t - sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]) * INV_C;
+        for (int i = 0; i < 3; ++i) { k.R[i] = g.w[i]; k.v[i] = 0.0; k.a[i] = 0.0; k.bf[i] = 0.f; k.df[i] = 0.f; }
+        k.tp = S.t - sqrt(g.w[0] * g.w[0] + g.w[1] * g.w[1] + g.w[2] * g.w[2]) * INV_C;
         k.cph = 1.0;
         k.sph = 0.0;
         k.flags = 0u;
@@ -370,9 +511,23 @@ __device__ __forceinline__ void retarded(const SrcRec &S, const double x[3], int
     }
 }
 
+template <bool FULL>
+__device__ __forceinline__ void retarded(const SrcRec &S, const double x[3], int max_iter, double tol_rel, Kin &k)
+{
+    Geo g;
+    geo_prepare(S, x, g);
+    retarded_geo<FULL>(S, g, x, max_iter, tol_rel, k);
+}
+
 template <typename F> __device__ __forceinline__ F recip(F x);
 template <> __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
+// FP64: v_rcp_f64 and two Newton-Raphson steps (within about one ulp)
+template <> __device__ __forceinline__ double recip<double>(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
 
 // Lienard-Wiechert outputs of one charge from its retarded kinematics, in
 // precision F: out = (Phi, A, E, B).  With u = n - beta and kappa = 1 - n.beta,
@@ -382,7 +537,9 @@ template <> __device__ __forceinline__ double recip<double>(double x) { return 1
 // for the total field (Eq. (E)); the Coulomb and radiation parts keep their
 // own terms.  B = n x E / c (Eq. (B)), Phi = kq / (kappa R) (Eq. (V)),
 // A = Phi beta / c (Eq. (A) in SI form).
-// |R| and 1/|R| in precision F: FP32 through v_rsq_f32, FP64 correctly rounded.
+// |R| and 1/|R| in precision F: FP32 through v_rsq_f32; FP64 from the refined
+// v_rsq_f64 with one more Newton-Raphson step on the reciprocal (both within
+// about one ulp).  |R| = 0 gives NaN, which the caller masks.
 __device__ __forceinline__ void dist_inv(float R0, float R1, float R2, float &D, float &iD)
 {
     const float D2 = R0 * R0 + R1 * R1 + R2 * R2;
@@ -391,8 +548,8 @@ __device__ __forceinline__ void dist_inv(float R0, float R1, float R2, float &D,
 }
 __device__ __forceinline__ void dist_inv(double R0, double R1, double R2, double &D, double &iD)
 {
-    D = sqrt(R0 * R0 + R1 * R1 + R2 * R2);
-    iD = 1.0 / D;
+    root_rsqrt<true>(R0 * R0 + R1 * R1 + R2 * R2, D, iD);
+    iD = fma(iD, fma(-D, iD, 1.0), iD);
 }
 
 // Returns the retarded distance |R| in precision F (for masking).
@@ -403,8 +560,14 @@ __device__ __forceinline__ F lw_terms(const Kin &k, double kq, int field_kind, F
     F D, iD;
     dist_inv(R0, R1, R2, D, iD);
     const F n0 = R0 * iD, n1 = R1 * iD, n2 = R2 * iD;
-    const F b0 = (F)(k.v[0] * INV_C), b1 = (F)(k.v[1] * INV_C), b2 = (F)(k.v[2] * INV_C);
-    const F d0 = (F)(k.a[0] * INV_C), d1 = (F)(k.a[1] * INV_C), d2 = (F)(k.a[2] * INV_C);
+    F b0, b1, b2, d0, d1, d2;
+    if constexpr (sizeof(F) == 4) {
+        b0 = k.bf[0]; b1 = k.bf[1]; b2 = k.bf[2];
+        d0 = k.df[0]; d1 = k.df[1]; d2 = k.df[2];
+    } else {
+        b0 = k.v[0] * INV_C; b1 = k.v[1] * INV_C; b2 = k.v[2] * INV_C;
+        d0 = k.a[0] * INV_C; d1 = k.a[1] * INV_C; d2 = k.a[2] * INV_C;
+    }
     const F ic = (F)INV_C;
     const F nb = n0 * b0 + n1 * b1 + n2 * b2;
     const F kappa = (F)1 - nb;

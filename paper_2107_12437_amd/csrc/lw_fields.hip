@@ -4,7 +4,8 @@
 // points and a chunk of observation times; for each time it loops over all
 // charges, whose per-(time, charge) records are wave-uniform and come in
 // through scalar loads.  Per pair: FP64 retarded-time solve (Eq. (ret_t)),
-// Lienard-Wiechert terms in the working precision, compensated running sum.
+// Lienard-Wiechert terms in the working precision, running sum over charges in
+// FP64 (exact enough that the FP32 path needs no compensation term).
 // The ten outputs of a (point, time) are written as ten coalesced SoA rows
 // with non-temporal stores (written once, never re-read by the kernel).
 #include <math.h>
@@ -48,6 +49,13 @@ __global__ void prep_kernel(const lw_traj *__restrict__ ch, int nch, const doubl
         R.sT = s;
         R.accel = T.accel;
         R.Lmax = (t > 0.0) ? 0.5 * T.accel * t * t : 0.0;
+        const double bw = T.amp * T.omega * INV_C, aw = bw * T.omega;
+        for (int i = 0; i < 3; ++i) {
+            R.bw1[i] = (float)(bw * T.e1[i]);
+            R.bw2[i] = (float)(bw * T.e2[i]);
+            R.aw1[i] = (float)(aw * T.e1[i]);
+            R.aw2[i] = (float)(aw * T.e2[i]);
+        }
         recs[r] = R;
     }
     if (flags)
@@ -58,55 +66,62 @@ template <typename F> __device__ __forceinline__ F qnan();
 template <> __device__ __forceinline__ float qnan<float>() { return __builtin_nanf(""); }
 template <> __device__ __forceinline__ double qnan<double>() { return __builtin_nan(""); }
 
-// F: working precision of the field terms and of the outputs.  In FP32 the
-// running sums over charges carry a Kahan compensation term.
-template <typename F>
-__global__ __launch_bounds__(256) void fields_kernel(const SrcRec *__restrict__ recs, int nch,
+// F: working precision of the field terms and of the outputs.  The sums over
+// charges are FP64 in both (an FP32 term converts exactly, and an FP64 add costs
+// one instruction, half of a compensated FP32 add).  Each lane owns one point
+// and TCH consecutive times: the charge loop is outermost, so the part of each
+// retarded-time problem that does not depend on time (frame coordinates,
+// bracket, starting value and its sincos) is built once per (point, charge) and
+// serves all TCH times, whose sums stay in registers.
+template <typename F, int TCH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void fields_kernel(const SrcRec *__restrict__ recs, int nch,
                                                      const double *__restrict__ pts, int64_t npts, int nt,
-                                                     int tchunk, int field_kind, int max_iter, double tol_rel,
+                                                     int t_base, int field_kind, int max_iter, double tol_rel,
                                                      double mask_r, F *__restrict__ out,
                                                      uint32_t *__restrict__ flags)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npts) return;
     const double x[3] = {pts[p], pts[npts + p], pts[2 * npts + p]};
-    const int t0 = blockIdx.y * tchunk;
-    const int t1 = min(t0 + tchunk, nt);
-    uint32_t fl_all = 0u;
-    for (int ti = t0; ti < t1; ++ti) {
-        F sum[10], cmp[10];
+    const int t0 = t_base + blockIdx.y * TCH;
+    const int nti = min(TCH, nt - t0);
+    double sum[TCH][10];
+    uint32_t fl[TCH];
 #pragma unroll
-        for (int j = 0; j < 10; ++j) { sum[j] = (F)0; cmp[j] = (F)0; }
-        uint32_t fl = 0u;
-        const SrcRec *R = recs + (int64_t)ti * nch;
-        for (int c = 0; c < nch; ++c) {
-            Kin k;
-            retarded(R[c], x, max_iter, tol_rel, k);
-            fl |= k.flags;
-            F o[10];
-            const F D = lw_terms<F>(k, R[c].kq, field_kind, o);
-            if (!(D >= (F)mask_r)) fl |= FLAG_MASKED;
+    for (int j = 0; j < TCH; ++j) {
+        fl[j] = 0u;
 #pragma unroll
-            for (int j = 0; j < 10; ++j) {
-                if constexpr (sizeof(F) == 4) {
-                    const F y = o[j] - cmp[j];
-                    const F t = sum[j] + y;
-                    cmp[j] = (t - sum[j]) - y;
-                    sum[j] = t;
-                } else {
-                    sum[j] += o[j];
-                }
+        for (int q = 0; q < 10; ++q) sum[j][q] = 0.0;
+    }
+    const SrcRec *R0 = recs + (int64_t)t0 * nch;
+    for (int c = 0; c < nch; ++c) {
+        Geo g;
+        geo_prepare(R0[c], x, g);
+#pragma unroll
+        for (int j = 0; j < TCH; ++j) {
+            if (j < nti) {
+                const SrcRec &S = R0[(int64_t)j * nch + c];
+                Kin k;
+                retarded_geo<sizeof(F) == 8>(S, g, x, max_iter, tol_rel, k);
+                F o[10];
+                const F D = lw_terms<F>(k, S.kq, field_kind, o);
+                fl[j] |= k.flags | ((D >= (F)mask_r) ? 0u : FLAG_MASKED);
+#pragma unroll
+                for (int q = 0; q < 10; ++q) sum[j][q] += (double)o[q];
             }
         }
-        F *dst = out + (int64_t)ti * 10 * npts + p;
-        if (fl & FLAG_MASKED) {
+    }
+    uint32_t fl_all = 0u;
 #pragma unroll
-            for (int j = 0; j < 10; ++j) __builtin_nontemporal_store(qnan<F>(), dst + (int64_t)j * npts);
-        } else {
+    for (int j = 0; j < TCH; ++j) {
+        if (j < nti) {
+            F *dst = out + (int64_t)(t0 + j) * 10 * npts + p;
+            const bool masked = (fl[j] & FLAG_MASKED) != 0u;
 #pragma unroll
-            for (int j = 0; j < 10; ++j) __builtin_nontemporal_store(sum[j] - cmp[j], dst + (int64_t)j * npts);
+            for (int q = 0; q < 10; ++q)
+                __builtin_nontemporal_store(masked ? qnan<F>() : (F)sum[j][q], dst + (int64_t)q * npts);
+            fl_all |= fl[j];
         }
-        fl_all |= fl;
     }
     if (flags && fl_all) atomicOr(flags + p, fl_all);
 }
@@ -125,22 +140,45 @@ hipError_t launch_prep(const lw_traj *d_ch, int nch, const double *d_times, int 
     return hipGetLastError();
 }
 
+template <typename F, int TCH>
+static hipError_t launch_fields_t(const SrcRec *d_recs, int nch, const double *d_pts, int64_t npts, int nt,
+                                  const lw_opts &o, double tol_rel, double mask_r, F *d_out, uint32_t *d_flags,
+                                  int block, hipStream_t s)
+{
+    const int max_iter = o.max_iter > 0 ? o.max_iter : 100;
+    const unsigned gx = (unsigned)((npts + block - 1) / block);
+    // grid.y holds at most 65535 time tiles: longer time lists go in slices
+    const int per_launch = 65535 * TCH;
+    for (int tb = 0; tb < nt; tb += per_launch) {
+        const int n_here = min(per_launch, nt - tb);
+        const dim3 grid(gx, (unsigned)((n_here + TCH - 1) / TCH));
+        hipLaunchKernelGGL((fields_kernel<F, TCH>), grid, dim3(block), 0, s, d_recs, nch, d_pts, npts, nt, tb,
+                           o.field_kind, max_iter, tol_rel, mask_r, d_out, d_flags);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename F>
+static hipError_t launch_fields_f(const SrcRec *d_recs, int nch, const double *d_pts, int64_t npts, int nt,
+                                  const lw_opts &o, double tol_rel, double mask_r, F *d_out, uint32_t *d_flags,
+                                  const FieldLaunch &L, hipStream_t s)
+{
+    if (L.tchunk >= 4)
+        return launch_fields_t<F, 4>(d_recs, nch, d_pts, npts, nt, o, tol_rel, mask_r, d_out, d_flags, L.block, s);
+    if (L.tchunk >= 2)
+        return launch_fields_t<F, 2>(d_recs, nch, d_pts, npts, nt, o, tol_rel, mask_r, d_out, d_flags, L.block, s);
+    return launch_fields_t<F, 1>(d_recs, nch, d_pts, npts, nt, o, tol_rel, mask_r, d_out, d_flags, L.block, s);
+}
+
 hipError_t launch_fields(const SrcRec *d_recs, int nch, const double *d_pts, int64_t npts, int nt,
                          const lw_opts &o, double tol_rel, double mask_r, void *d_out, uint32_t *d_flags,
                          const FieldLaunch &L, hipStream_t s)
 {
-    const int block = L.block;
-    int tchunk = L.tchunk < 1 ? 1 : L.tchunk;
-    if ((nt + tchunk - 1) / tchunk > 65535) tchunk = (nt + 65534) / 65535;   // grid.y limit
-    const dim3 grid((unsigned)((npts + block - 1) / block), (unsigned)((nt + tchunk - 1) / tchunk));
-    const int max_iter = o.max_iter > 0 ? o.max_iter : 100;
     if (o.precision == LW_MIXED)
-        hipLaunchKernelGGL(fields_kernel<float>, grid, dim3(block), 0, s, d_recs, nch, d_pts, npts, nt, tchunk,
-                           o.field_kind, max_iter, tol_rel, mask_r, (float *)d_out, d_flags);
-    else
-        hipLaunchKernelGGL(fields_kernel<double>, grid, dim3(block), 0, s, d_recs, nch, d_pts, npts, nt, tchunk,
-                           o.field_kind, max_iter, tol_rel, mask_r, (double *)d_out, d_flags);
-    return hipGetLastError();
+        return launch_fields_f<float>(d_recs, nch, d_pts, npts, nt, o, tol_rel, mask_r, (float *)d_out, d_flags, L, s);
+    return launch_fields_f<double>(d_recs, nch, d_pts, npts, nt, o, tol_rel, mask_r, (double *)d_out, d_flags, L, s);
 }
 
 }  // namespace lw

@@ -14,7 +14,7 @@ struct SrcRec;
 // Launch parameters of the grid-field kernel chosen by the tuner.
 struct FieldLaunch {
     int block;       // threads per workgroup (multiple of 64)
-    int tchunk;      // observation times handled by one workgroup
+    int tchunk;      // observation times per lane, kept in registers: 1, 2 or 4
 };
 
 // Grid fields: preparation of (time, charge) records, then the fused
