@@ -4,7 +4,8 @@
 A step is one lw_fields call on the mixed-precision grid workload: 16 charges
 (linear oscillation, circular orbit, uniform acceleration; seeded), a 512x512
 plane over +-100 nm, 64 snapshots over the first femtosecond -- FP64 retarded
-times, FP32 field expressions with Kahan sums, FP32 outputs (671 MB per step).
+times, FP32 field expressions summed over charges in FP64, FP32 outputs (671 MB
+per step).
 Inputs are resident in HBM before the timed region.
 
 The JSON line also carries the FP64 form of the same step, the oscillator
@@ -29,18 +30,19 @@ METRIC = "charge·point LW evals/s (mixed vs FP64) + dipole-steps/s at stated er
 
 # Algorithmic work per LW eval (one point, one charge, one time), counted from
 # the formulas: 86 FP32 flops for Phi, A, E, B of one charge (FMA = 2 flops)
-# and 150 FP64 flops for the retarded-time solve (3 Newton iterations of 50).
+# and 150 FP64 flops for the retarded-time solve (3 Newton iterations of 50, a
+# fixed count that does not follow the solver's actual iterations).
 FLOP_LW_FP32 = 86
 FLOP_SOLVE_FP64 = 150
 # Vector ALU peak of MI355X for FP64 and for unpacked FP32: 256 CUs x 4 SIMDs
 # x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# HBM bytes per launch of fields_kernel<float> on this workload from the profiler's
+# HBM bytes per launch of fields_kernel<float, 2> on this workload from the profiler's
 # FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0) counters, calibrated on a plain 1 GiB copy
 # (profiles/fields_kernel_mixed_grid512x512x64t.md).  Valid only for the kernel
 # sources they were taken on; reported as null once those change.
-TRAFFIC_BYTES = 680.8e6
-TRAFFIC_SOURCES_SHA = "7b9e275bd8f93068"
+TRAFFIC_BYTES = 681.9e6
+TRAFFIC_SOURCES_SHA = "b056cbf3603d8635"
 
 
 def kernel_sources_sha() -> str:
@@ -196,6 +198,7 @@ def main():
 
     clusters = None
     vjp = None
+    dip_vjp = None
     if not args.no_dipole:
         cw = I.workload_clusters(steps=args.cluster_steps)
         n_c = len(cw["dipoles"]["omega0"])
@@ -226,6 +229,20 @@ def main():
         pairs = dpts.shape[1] * len(dw["charges"]["kind"]) * len(dw["times"])
         vjp = {"workload": dw["name"], "ms": round(vsec * 1e3, 3), "pair_vjps_per_s": pairs / vsec, "dtype": "f64"}
         log(f"[bench] grid VJP: {vsec * 1e3:.2f} ms, {vjp['pair_vjps_per_s']:.3e} pair VJPs/s")
+        # oscillator adjoint: forward run with stored history, detector VJP, backward sweep
+        ow = I.workload_dipole_detector()
+        opts_pts = torch.tensor(ow["points"], dtype=torch.float64, device="cuda")
+        n_o = len(ow["dipoles"]["omega0"])
+        lw.dipole_run_vjp(ow["dipoles"], ow["inst_off"], ow["dt"], ow["steps"], opts_pts, ow["times"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lw.dipole_run_vjp(ow["dipoles"], ow["inst_off"], ow["dt"], ow["steps"], opts_pts, ow["times"])
+        torch.cuda.synchronize()
+        osec = time.perf_counter() - t0
+        dip_vjp = {"workload": ow["name"], "ms": round(osec * 1e3, 3),
+                   "dipole_steps_per_s": n_o * ow["steps"] / osec, "gradients": 3 * n_o, "dtype": "f64",
+                   "note": "forward run, detector objective and its VJP, backward sweep; one call"}
+        log(f"[bench] oscillator adjoint: {osec * 1e3:.2f} ms for {n_o} dipoles x {ow['steps']} steps")
 
     line = {
         "metric": METRIC, "value": value, "unit": "LW evals/s", "n_gpus": 1, "steps": args.steps,
@@ -235,7 +252,7 @@ def main():
                    "times": n_t, "evals_per_step": evals},
         "fp64_value": fp64_value, "mixed_over_fp64": value / fp64_value,
         "roofline": roofline, "cpu_baseline": cpu, "errors_vs_oracle": err, "dipoles": dip,
-        "clusters": clusters, "grid_vjp": vjp,
+        "clusters": clusters, "grid_vjp": vjp, "oscillator_adjoint": dip_vjp,
     }
     print(json.dumps(line), flush=True)
 
