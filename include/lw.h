@@ -192,7 +192,7 @@ typedef struct {
     int32_t stepped_min_n; /* instances of at least this many dipoles (or whose history does
                               not fit in LDS) advance one launch per step with one workgroup
                               per dipole; smaller ones run whole in one workgroup
-                              (0: 48; < 0: only when the history does not fit)             */
+                              (0: 16; < 0: only when the history does not fit)             */
 } lw_run_opts;
 
 /* Runs `steps` RK4 steps of Eq. (LO_equation) for n_inst independent

@@ -504,7 +504,7 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
     // small instances whose ring fits in LDS run whole in one workgroup each;
     // the others advance one launch per step with one workgroup per dipole
     const int lds_limit = 64 * 1024;
-    const int stepped_min = opts->stepped_min_n == 0 ? 48 : (opts->stepped_min_n < 0 ? (1 << 30) : opts->stepped_min_n);
+    const int stepped_min = opts->stepped_min_n == 0 ? 16 : (opts->stepped_min_n < 0 ? (1 << 30) : opts->stepped_min_n);
     std::vector<int32_t> lds_list, tgt, tgt_lo, tgt_n;
     std::vector<int64_t> tgt_base;
     int max_lds_n = 0;
@@ -646,48 +646,85 @@ lw_status lw_dipole_run_vjp(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, 
     while (ring < rows) ring <<= 1;
     if (ring > (1 << 26)) return fail(LW_E_INVALID, "lw_dipole_run_vjp: run too long for the stored history");
     const int64_t nblk = (n_det * n_snap + 255) / 256;
+    // drive pairs per step (2 stages x n targets x (n-1) sources x 2 charges) and of E_d(0)
+    std::vector<int64_t> pair_off(n_inst + 1, 0), pair_off0(n_inst + 1, 0);
+    for (int k = 0; k < n_inst; ++k) {
+        const int64_t n = h_inst_off[k + 1] - h_inst_off[k];
+        pair_off[k + 1] = pair_off[k] + 4 * n * (n - 1);
+        pair_off0[k + 1] = pair_off0[k] + 2 * n * (n - 1);
+    }
+    const int64_t n_pairs = pair_off[n_inst], n_pairs0 = pair_off0[n_inst];
     const size_t out_b = align_up(sizeof(double) * (size_t)(rows * n_dip), 256);
     const size_t hist_b = align_up(sizeof(double) * (size_t)(ring * n_dip * 3), 256);
     const size_t jp_b = align_up(sizeof(double) * (size_t)(nblk + 1), 256);
     const size_t dip_b = align_up(sizeof(lw_dipole) * (size_t)n_dip, 256);
     const size_t off_b = align_up(sizeof(int32_t) * (size_t)(n_inst + 1), 256);
+    const size_t po_b = align_up(sizeof(int64_t) * (size_t)(n_inst + 1), 256);
     const size_t tm_b = align_up(sizeof(double) * (size_t)n_snap, 256);
     const size_t dev_b = align_up(lw::dip_dev_bytes() * (size_t)n_dip, 256);
-    lw_status st = ensure_work2(ctx, 3 * out_b + 2 * hist_b + jp_b + 256 + dip_b + off_b + tm_b + dev_b, s);
+    const size_t state_b = align_up(sizeof(double) * 6 * (size_t)n_dip, 256);
+    const size_t rbp_b = align_up(sizeof(double) * 3 * (size_t)std::max<int64_t>(n_pairs, 1), 256);
+    const size_t rbp0_b = align_up(sizeof(double) * 3 * (size_t)std::max<int64_t>(n_pairs0, 1), 256);
+    const size_t taup_b = align_up(sizeof(double) * (size_t)std::max<int64_t>(n_pairs, 1), 256);
+    const size_t ctr_b = 256;
+    const size_t stage_b = dip_b + off_b + 2 * po_b + tm_b;
+    lw_status st = ensure_work2(ctx, 3 * out_b + 2 * hist_b + jp_b + 256 + stage_b + dev_b + state_b + rbp_b + rbp0_b +
+                                         taup_b + ctr_b, s);
     if (st != LW_OK) return st;
     char *w2 = (char *)ctx->d_work2;
-    double *d_D = (double *)w2;
-    double *d_V = (double *)(w2 + out_b);
-    double *d_Ed = (double *)(w2 + 2 * out_b);
-    double *d_hist = (double *)(w2 + 3 * out_b);
-    double *d_hbar = (double *)(w2 + 3 * out_b + hist_b);
-    double *d_Jpart = (double *)(w2 + 3 * out_b + 2 * hist_b);
-    double *d_J = (double *)(w2 + 3 * out_b + 2 * hist_b + jp_b);
-    char *tail = w2 + 3 * out_b + 2 * hist_b + jp_b + 256;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { char *p = w2 + o; o += bytes; return p; };
+    double *d_D = (double *)take(out_b);
+    double *d_V = (double *)take(out_b);
+    double *d_Ed = (double *)take(out_b);
+    double *d_hist = (double *)take(hist_b);
+    double *d_hbar = (double *)take(hist_b);
+    double *d_Jpart = (double *)take(jp_b);
+    double *d_J = (double *)take(256);
+    char *stage_dev = take(stage_b);
+    lw::DipDev *d_dev = (lw::DipDev *)take(dev_b);
+    double *d_state = (double *)take(state_b);
+    double *d_rbp = (double *)take(rbp_b);
+    double *d_rbp0 = (double *)take(rbp0_b);
+    double *d_taup = (double *)take(taup_b);
+    int64_t *d_step = (int64_t *)take(ctr_b);
     // forward run with every step stored
     lw_run_opts fo = *opts;
     fo.out_stride = 1;
     st = lw_dipole_run(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, steps, &fo, d_D, d_V, nullptr, d_Ed, stream);
     if (st != LW_OK) return st;
-    // oscillator records, offsets and snapshot times for the adjoint kernels
-    st = acquire_stage(ctx, dip_b + off_b + tm_b);
+    // oscillator records, offsets, pair offsets and snapshot times for the adjoint kernels
+    st = acquire_stage(ctx, stage_b);
     if (st != LW_OK) return st;
     char *stage = (char *)ctx->h_stage;
     std::memcpy(stage, h_dip, sizeof(lw_dipole) * (size_t)n_dip);
     std::memcpy(stage + dip_b, h_inst_off, sizeof(int32_t) * (size_t)(n_inst + 1));
-    std::memcpy(stage + dip_b + off_b, h_snap_times, sizeof(double) * (size_t)n_snap);
-    st = upload(ctx, tail, dip_b + off_b + tm_b, s);
+    std::memcpy(stage + dip_b + off_b, pair_off.data(), sizeof(int64_t) * (size_t)(n_inst + 1));
+    std::memcpy(stage + dip_b + off_b + po_b, pair_off0.data(), sizeof(int64_t) * (size_t)(n_inst + 1));
+    std::memcpy(stage + dip_b + off_b + 2 * po_b, h_snap_times, sizeof(double) * (size_t)n_snap);
+    st = upload(ctx, stage_dev, stage_b, s);
     if (st != LW_OK) return st;
-    const lw_dipole *d_in = (const lw_dipole *)tail;
-    const int32_t *d_off = (const int32_t *)(tail + dip_b);
-    const double *d_times = (const double *)(tail + dip_b + off_b);
-    lw::DipDev *d_dev = (lw::DipDev *)(tail + dip_b + off_b + tm_b);
+    const lw_dipole *d_in = (const lw_dipole *)stage_dev;
+    const int32_t *d_off = (const int32_t *)(stage_dev + dip_b);
+    const int64_t *d_pair_off = (const int64_t *)(stage_dev + dip_b + off_b);
+    const int64_t *d_pair_off0 = (const int64_t *)(stage_dev + dip_b + off_b + po_b);
+    const double *d_times = (const double *)(stage_dev + dip_b + off_b + 2 * po_b);
     LW_HIP(lw::launch_dipole_prep(d_in, n_dip, d_dev, s));
-    LW_HIP(lw::launch_dipole_vjp(d_dev, d_off, n_inst, max_n, n_dip, d_D, d_V, d_Ed, d_hist, d_hbar, (int)ring, steps,
-                                 dt, d_det_pts, n_det, d_times, n_snap, d_grad_pos, d_Jpart, d_J, ctx->d_err, s));
+    if (!ctx->capture) LW_HIP(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const hipError_t he = lw::launch_dipole_vjp(d_dev, d_off, d_pair_off, d_pair_off0, n_inst, n_pairs, n_pairs0, n_dip,
+                                                d_D, d_V, d_Ed, d_hist, d_hbar, (int)ring, steps, dt, d_det_pts, n_det,
+                                                d_times, n_snap, d_grad_pos, d_Jpart, d_J, d_state, d_rbp, d_rbp0,
+                                                d_taup, d_step, ctx->d_err, 256, s, ctx->capture, &graph, &exec);
     double J = 0.0;
-    LW_HIP(hipMemcpyAsync(&J, d_J, sizeof(double), hipMemcpyDeviceToHost, s));
-    st = lw_sync_status(ctx, stream);
+    if (he == hipSuccess) (void)hipMemcpyAsync(&J, d_J, sizeof(double), hipMemcpyDeviceToHost, s);
+    // the call ends synchronised with the stream, so the step graph can go now
+    st = he == hipSuccess ? lw_sync_status(ctx, stream) : LW_OK;
+    if (he != hipSuccess) (void)hipStreamSynchronize(s);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    LW_HIP(he);
     *h_J = J;
     return st;
 }

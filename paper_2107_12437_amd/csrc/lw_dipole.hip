@@ -302,7 +302,8 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
                                                         const int32_t *__restrict__ tgt_n,
                                                         const int64_t *__restrict__ ring_base, double *__restrict__ ring,
                                                         double *__restrict__ Ecur, const int64_t *__restrict__ step_ctr,
-                                                        int ring_depth, int64_t stride, double dt, double max_vel,
+                                                        int kstep, int ring_depth, int64_t stride, double dt,
+                                                        double max_vel,
                                                         int max_iter, int init, double *__restrict__ out_d,
                                                         double *__restrict__ out_v, double *__restrict__ out_E,
                                                         double *__restrict__ out_Ed, int n_dip,
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
     const int i0 = tgt_lo[blockIdx.x];
     const int n = tgt_n[blockIdx.x];
     const int i = gi - i0;
-    const int64_t nstep = init ? 0 : *step_ctr;
+    const int64_t nstep = init ? 0 : *step_ctr + kstep;
     double *rp = ring + ring_base[blockIdx.x];
     Hist H{rp, n, ring_depth - 1, dt, 1.0 / dt};
     uint32_t err = 0u;
@@ -392,9 +393,9 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
     if (err) atomicOr(d_err, err);
 }
 
-__global__ void step_advance_kernel(int64_t *step_ctr)
+__global__ void step_advance_kernel(int64_t *step_ctr, int64_t delta)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *step_ctr += 1;
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step_ctr += delta;
 }
 
 __global__ void step_reset_kernel(int64_t *step_ctr)
@@ -414,19 +415,19 @@ hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const 
     const dim3 grid((unsigned)n_tgt), block(B);
     hipLaunchKernelGGL(step_reset_kernel, dim3(1), dim3(1), 0, s, d_step);
     hipLaunchKernelGGL(lo_step_kernel<B>, grid, block, 0, s, d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_ring_base, d_ring,
-                       d_Ecur, d_step, ring, stride, dt, max_vel, max_iter, 1, d_moment, d_ddot, d_energy, d_drive,
-                       n_dip, d_err);
+                       d_Ecur, d_step, 0, ring, stride, dt, max_vel, max_iter, 1, d_moment, d_ddot, d_energy,
+                       d_drive, n_dip, d_err);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || steps == 0) return e;
-    // a chunk of steps is captured once into a graph and replayed; the step
-    // index lives on the device, so every replay continues where the last ended
+    // a chunk of steps is captured once into a graph and replayed: launch k of
+    // a chunk advances step base + k, and the base (on the device) moves by the
+    // chunk at its end, so every replay continues where the last ended
     auto enqueue = [&](hipStream_t q, int64_t count) {
-        for (int64_t k = 0; k < count; ++k) {
+        for (int64_t k = 0; k < count; ++k)
             hipLaunchKernelGGL(lo_step_kernel<B>, grid, block, 0, q, d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_ring_base,
-                               d_ring, d_Ecur, d_step, ring, stride, dt, max_vel, max_iter, 0, d_moment, d_ddot,
-                               d_energy, d_drive, n_dip, d_err);
-            hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(1), 0, q, d_step);
-        }
+                               d_ring, d_Ecur, d_step, (int)k, ring, stride, dt, max_vel, max_iter, 0, d_moment,
+                               d_ddot, d_energy, d_drive, n_dip, d_err);
+        hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(1), 0, q, d_step, count);
     };
     const int64_t chunk = graph_chunk > 0 ? graph_chunk : 0;
     if (chunk == 0 || steps < chunk || !cap) {
@@ -443,7 +444,7 @@ hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const 
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     const int64_t reps = steps / chunk;
     for (int64_t r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(exec, s);
-    if (e == hipSuccess) {
+    if (e == hipSuccess && steps > reps * chunk) {
         enqueue(s, steps - reps * chunk);
         e = hipGetLastError();
     }

@@ -81,26 +81,48 @@ __device__ __forceinline__ void hist_eval(const Hist &H, int j, double d0, int64
 // Retarded field of charge (cf, kq) of source j at point x and time base*dt
 // (samples up to nstep); fills the kinematics and the history evaluation.
 __device__ void pair_solve(const Hist &H, const double x[3], const DipLds &Sj, int j, double cf, int64_t nstep,
-                           double base, int max_iter, Kin &k, HistEval &e, uint32_t &err)
+                           double base, int max_iter, Kin &k, HistEval &e, uint32_t &err, double tau_init = 0.0,
+                           double *tau_out = nullptr)
 {
     const double dx = x[0] - Sj.ox, dy = x[1] - Sj.oy, dz = x[2] - Sj.oz;
     const double L2 = dx * dx + dy * dy + dz * dz;
     const double L = sqrt(L2);
     const double sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;
     Bracket b(0.0, 2.0 * L * INV_C);
-    double tau = L * INV_C;
+    // warm start from the same pair's retarded time one step later, if given
+    double tau = (tau_init > 0.0 && tau_init < b.hi) ? tau_init : L * INV_C;
+    const double tol = 4.0 * 2.220446049250313e-16;
     bool ok = false;
     for (int it = 0; it < max_iter; ++it) {
-        hist_eval(H, j, Sj.d0, nstep, base - tau * H.inv_dt, e);
+        const double s = base - tau * H.inv_dt;
+        hist_eval(H, j, Sj.d0, nstep, s, e);
         const double rho = cf * e.d;
         const double D = sqrt(fmax(L2 - 2.0 * rho * sD + rho * rho, 0.0));
-        const double dD = (D > 0.0) ? cf * e.sd * (sD - rho) * rcp_steer(D) : 0.0;
-        const double tn = newton_step(tau, D, dD, b);
-        ok = converged(tn, tau, 4.0 * 2.220446049250313e-16, b);
+        const double r1 = cf * e.sd;                             // d rho / d t'
+        const double dD = (D > 0.0) ? r1 * (sD - rho) * rcp_steer(D) : 0.0;
+        bool free_step;
+        const double tn = halley_step(tau, D, dD, 0.0, b, free_step);
+        ok = converged(tn, tau, tol, b);
         if (ok) break;
+        // within one interpolation segment (or one side of the history's ends)
+        // g is smooth with |g''| <= rho'^2 / D + |rho''|: once Newton's error
+        // bound from tau is below tol/4 the new iterate is accepted, and the
+        // history is evaluated there once more
+        const double st = tn - tau;
+        const double r2 = (e.region == 2) ? cf * e.sv : 0.0;
+        const double sn = base - tn * H.inv_dt;
+        const bool same_seg = (e.region == 1) ? (floor(sn) == floor(s) && sn < (double)nstep)
+                                              : (e.region == 2 ? sn >= (double)nstep : sn < 0.0);
         tau = tn;
+        if (free_step && same_seg && D > 0.0 &&
+            (r1 * r1 + fabs(r2) * D) * (st * st) <= 0.5 * tol * tn * D * (C_LIGHT - fabs(r1))) {
+            hist_eval(H, j, Sj.d0, nstep, sn, e);
+            ok = true;
+            break;
+        }
     }
     if (!ok) err |= ERR_NOCONV;
+    if (tau_out) *tau_out = tau;
     const double rho = cf * e.d;
     k.R[0] = dx - rho * Sj.px;
     k.R[1] = dy - rho * Sj.py;
@@ -117,11 +139,19 @@ __device__ void pair_solve(const Hist &H, const double x[3], const DipLds &Sj, i
     k.flags = 0u;
 }
 
+// Cotangents of the history samples one pair read: samples k and k+1
+// (interpolation), sample k alone (Taylor step past the newest sample), or none
+// (static pre-history).
+struct HistBar {
+    int region;
+    int64_t k;
+    double c0[3], c1[3];
+};
+
 // Reverse of pair_solve + the field: given the cotangent Eb of the pair's E,
-// returns the cotangent of Delta = x - R_j and adds the cotangents of the
-// source's history samples into hbar ([ring][n][3], device atomics).
-__device__ void pair_vjp(const Hist &H, const Kin &k, const HistEval &e, const DipLds &Sj, int j, double cf, double kq,
-                         const double Eb[3], double *hbar, double Db[3])
+// returns the cotangent of Delta = x - R_j and the cotangents of the samples.
+__device__ void pair_vjp(const Kin &k, const HistEval &e, const DipLds &Sj, double cf, double kq, const double Eb[3],
+                         double Db[3], HistBar &hb)
 {
     const double ob[10] = {0.0, 0.0, 0.0, 0.0, Eb[0], Eb[1], Eb[2], 0.0, 0.0, 0.0};
     double Rb[3], vb[3], ab[3], n[3], kqb, kappa;
@@ -135,26 +165,38 @@ __device__ void pair_vjp(const Hist &H, const Kin &k, const HistEval &e, const D
     const double gp = C_LIGHT - cf * e.sd * np;                          // d g / d tau
     const double q = stau / gp;
     for (int i = 0; i < 3; ++i) Db[i] = Rb[i] + q * n[i];
+    hb.region = e.region;
+    hb.k = e.k;
     if (e.region == 0) return;                                            // static pre-history: no samples
     const double db = -cf * Rp - q * cf * np;                             // cotangent of d(t') at fixed t'
     const double vbb = cf * vp, abb = cf * ap;
     if (e.region == 1) {
-        double *h0 = hbar + ((int64_t)(e.k & H.mask) * H.n + j) * 3;
-        double *h1 = hbar + ((int64_t)((e.k + 1) & H.mask) * H.n + j) * 3;
         const double w0 = 1.0 - e.u, w1 = e.u;
-        atomicAdd(h0 + 0, w0 * db);
-        atomicAdd(h0 + 1, w0 * vbb);
-        atomicAdd(h0 + 2, w0 * abb);
-        atomicAdd(h1 + 0, w1 * db);
-        atomicAdd(h1 + 1, w1 * vbb);
-        atomicAdd(h1 + 2, w1 * abb);
+        hb.c0[0] = w0 * db;
+        hb.c0[1] = w0 * vbb;
+        hb.c0[2] = w0 * abb;
+        hb.c1[0] = w1 * db;
+        hb.c1[1] = w1 * vbb;
+        hb.c1[2] = w1 * abb;
     } else {
         // Taylor step from sample k: d = d_k + v_k tt + a_k tt^2/2, v = v_k + a_k tt, a = a_k
         const double tt = e.u;
-        double *h = hbar + ((int64_t)(e.k & H.mask) * H.n + j) * 3;
-        atomicAdd(h + 0, db);
-        atomicAdd(h + 1, tt * db + vbb);
-        atomicAdd(h + 2, 0.5 * tt * tt * db + tt * vbb + abb);
+        hb.c0[0] = db;
+        hb.c0[1] = tt * db + vbb;
+        hb.c0[2] = 0.5 * tt * tt * db + tt * vbb + abb;
+        hb.c1[0] = hb.c1[1] = hb.c1[2] = 0.0;
+    }
+}
+
+// Adds a pair's sample cotangents into hbar ([ring][n][3]) with device atomics.
+__device__ __forceinline__ void scatter_global(const Hist &H, int j, const HistBar &hb, double *hbar)
+{
+    if (hb.region == 0) return;
+    double *h0 = hbar + ((int64_t)(hb.k & H.mask) * H.n + j) * 3;
+    for (int c = 0; c < 3; ++c) atomicAdd(h0 + c, hb.c0[c]);
+    if (hb.region == 1) {
+        double *h1 = hbar + ((int64_t)((hb.k + 1) & H.mask) * H.n + j) * 3;
+        for (int c = 0; c < 3; ++c) atomicAdd(h1 + c, hb.c1[c]);
     }
 }
 
@@ -175,7 +217,13 @@ __global__ void hist_build_kernel(const DipDev *__restrict__ dev, const double *
 
 // Detector field, objective partials and the detector's cotangents: one lane
 // per (snapshot, point); instances are laid out in the history by the global
-// dipole index (one shared [ring][n_dip][3] array).
+// dipole index (one shared [ring][n_dip][3] array).  The lanes of a workgroup
+// see a source at nearby retarded times, so their sample cotangents are first
+// summed in LDS slots relative to the workgroup's earliest sample, then added to
+// hbar with one device atomic per touched slot (a lane beyond the slots adds
+// its own directly).
+constexpr int DET_SLOTS = 64;
+
 __global__ __launch_bounds__(256) void detector_vjp_kernel(const DipDev *__restrict__ dev, int n_dip,
                                                            const double *__restrict__ hist, double *__restrict__ hbar,
                                                            int ring, int64_t nstep, double dt,
@@ -185,6 +233,8 @@ __global__ __launch_bounds__(256) void detector_vjp_kernel(const DipDev *__restr
                                                            int max_iter, uint32_t *__restrict__ d_err)
 {
     __shared__ double red[4];
+    __shared__ double slot[DET_SLOTS * 3];
+    __shared__ int64_t kmin_w[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t gid = (int64_t)blockIdx.x * 256 + tid;
     const bool live = gid < npts * n_snap;
@@ -194,6 +244,7 @@ __global__ __launch_bounds__(256) void detector_vjp_kernel(const DipDev *__restr
     const double base = times[ks] / dt;
     Hist H{hist, n_dip, ring - 1, dt, 1.0 / dt};
     uint32_t err = 0u;
+    for (int t = tid; t < DET_SLOTS * 3; t += 256) slot[t] = 0.0;
     double E[3] = {0.0, 0.0, 0.0};
     if (live) {
         for (int j = 0; j < n_dip; ++j) {
@@ -225,20 +276,50 @@ __global__ __launch_bounds__(256) void detector_vjp_kernel(const DipDev *__restr
         const DipDev &Dj = dev[j];
         const DipLds Sj = dip_lds(Dj);
         double Rj[3] = {0.0, 0.0, 0.0};
-        if (live) {
-            for (int w = 0; w < 2; ++w) {
+        for (int w = 0; w < 2; ++w) {
+            HistBar hb;
+            hb.region = 0;
+            hb.k = 0;
+            if (live) {
                 const double cf = w ? Sj.cfm : Sj.cfp;
                 const double kq = (w ? -Dj.q : Dj.q) * K_COUL;
                 Kin k;
                 HistEval e;
                 pair_solve(H, x, Sj, j, cf, nstep, base, max_iter, k, e, err);
                 double Db[3];
-                pair_vjp(H, k, e, Sj, j, cf, kq, Eb, hbar, Db);
+                pair_vjp(k, e, Sj, cf, kq, Eb, Db, hb);
                 // Delta = x - R_j: the source position gets -Db
                 Rj[0] -= Db[0];
                 Rj[1] -= Db[1];
                 Rj[2] -= Db[2];
             }
+            // earliest sample this workgroup touches for (j, w)
+            int64_t km = hb.region ? hb.k : INT64_MAX;
+            for (int off = 32; off > 0; off >>= 1) km = min(km, (int64_t)__shfl_xor(km, off, 64));
+            if (lane == 0) kmin_w[wave] = km;
+            __syncthreads();
+            const int64_t kb = min(min(kmin_w[0], kmin_w[1]), min(kmin_w[2], kmin_w[3]));
+            if (kb != INT64_MAX) {
+                if (hb.region) {
+                    const int64_t sl = hb.k - kb;
+                    if (sl + 1 < DET_SLOTS) {
+                        for (int c = 0; c < 3; ++c) atomicAdd(&slot[sl * 3 + c], hb.c0[c]);
+                        if (hb.region == 1)
+                            for (int c = 0; c < 3; ++c) atomicAdd(&slot[(sl + 1) * 3 + c], hb.c1[c]);
+                    } else {
+                        scatter_global(H, j, hb, hbar);
+                    }
+                }
+                __syncthreads();
+                for (int t = tid; t < DET_SLOTS * 3; t += 256) {
+                    const double v = slot[t];
+                    if (v != 0.0) {
+                        atomicAdd(hbar + ((int64_t)((kb + t / 3) & H.mask) * H.n + j) * 3 + t % 3, v);
+                        slot[t] = 0.0;
+                    }
+                }
+            }
+            __syncthreads();
         }
         for (int c = 0; c < 3; ++c) {
             double v = Rj[c];
@@ -262,149 +343,281 @@ __device__ __forceinline__ double load_agent(const double *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Backward sweep, one instance per workgroup.  ybd/ybv: cotangent of
-// y[n+1] = (d, d_dot), then of y[n]; eext: cotangent of Ec[n+1] = Ee[n].  The
-// history and its cotangents are shared arrays [ring][n_dip][3] indexed by the
-// global dipole index; this workgroup only touches its own instance's dipoles.
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void lo_reverse_kernel(const DipDev *__restrict__ dev,
-                                                           const int32_t *__restrict__ off, int n_dip,
-                                                           const double *__restrict__ hist, double *__restrict__ hbar,
-                                                           int ring, int64_t steps, double dt,
-                                                           double *__restrict__ Rbar, int max_iter,
-                                                           uint32_t *__restrict__ d_err)
+// Per-dipole cotangent state of the backward sweep.  yd, yv: cotangent of the
+// state (d, d_dot) after the step being reversed; ee, em, ec: cotangents of the
+// drives at t_n + dt, t_n + dt/2 and t_n of that step; ext: cotangent of the
+// drive at t_{n+1} received from outside the step (the stored d_ddot of
+// sample n+1 and the next step's first stage).
+struct AdjState {
+    double *yd, *yv, *ext, *em, *ee, *ec;
+};
+
+// Transpose of one RK4 step of dipole g (linear in y and in the three stage
+// drives): maps (yd, yv, ext) of y[n+1] to the cotangents of y[n] (partial:
+// sample n's own cotangent is added once complete) and of Ec, Em, Ee.
+__device__ __forceinline__ void rk4_transpose(const DipDev &P, double h, AdjState &A, int g)
 {
-    extern __shared__ double lds[];
-    const int inst = blockIdx.x;
-    const int i0 = off[inst], n = off[inst + 1] - i0;
+    const double w2 = P.omega0 * P.omega0, gm = P.gamma0, f = P.f;
+    const double yd = A.yd[g], yv = A.yv[g];
+    double k1d = h / 6.0 * yd, k1v = h / 6.0 * yv;
+    double k2d = h / 3.0 * yd, k2v = h / 3.0 * yv;
+    double k3d = h / 3.0 * yd, k3v = h / 3.0 * yv;
+    const double k4d = h / 6.0 * yd, k4v = h / 6.0 * yv;
+    double ad = yd, av = yv, Ee = A.ext[g], Em = 0.0, Ec = 0.0;
+    // k4 = A y4 + e Ee;  y4 = y + h k3
+    double td = -w2 * k4v, tv = k4d - gm * k4v;
+    Ee += f * k4v;
+    ad += td; av += tv; k3d += h * td; k3v += h * tv;
+    // k3 = A y3 + e Em;  y3 = y + h/2 k2
+    td = -w2 * k3v; tv = k3d - gm * k3v;
+    Em += f * k3v;
+    ad += td; av += tv; k2d += 0.5 * h * td; k2v += 0.5 * h * tv;
+    // k2 = A y2 + e Em;  y2 = y + h/2 k1
+    td = -w2 * k2v; tv = k2d - gm * k2v;
+    Em += f * k2v;
+    ad += td; av += tv; k1d += 0.5 * h * td; k1v += 0.5 * h * tv;
+    // k1 = A y + e Ec
+    ad += -w2 * k1v; av += k1d - gm * k1v;
+    Ec += f * k1v;
+    A.yd[g] = ad;
+    A.yv[g] = av;
+    A.em[g] = Em;
+    A.ee[g] = Ee;
+    A.ec[g] = Ec;
+}
+
+// Adds the completed cotangent of sample n (d, d_dot, d_ddot = f Ec - gamma0
+// d_dot - omega0^2 d) of dipole g: into y[n] unless n = 0 (y[0] is fixed), and
+// into the drive at t_n (ext for the step before).
+__device__ __forceinline__ void take_sample(const DipDev &P, const double *hbar, int64_t n, int n_dip, int mask,
+                                            AdjState &A, int g)
+{
+    const double *hb = hbar + ((int64_t)(n & mask) * n_dip + g) * 3;
+    const double bd = load_agent(hb), bv = load_agent(hb + 1), ba = load_agent(hb + 2);
+    if (n > 0) {
+        A.yd[g] += bd - P.omega0 * P.omega0 * ba;
+        A.yv[g] += bv - P.gamma0 * ba;
+    }
+    A.ext[g] = A.ec[g] + P.f * ba;
+}
+
+// Start of the sweep: zero cotangent state; the step base starts at the last step.
+__global__ void adj_init_kernel(int n_dip, int64_t steps, AdjState A, int64_t *__restrict__ step_base)
+{
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n_dip; g += gridDim.x * blockDim.x) {
+        A.yd[g] = 0.0;
+        A.yv[g] = 0.0;
+        A.ext[g] = 0.0;
+        A.ec[g] = 0.0;
+        A.em[g] = 0.0;
+        A.ee[g] = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *step_base = steps - 1;
+}
+
+__global__ void adj_base_kernel(int64_t *__restrict__ step_base, int64_t delta)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *step_base += delta;
+}
+
+// Instance of global dipole g (last instance whose first dipole is <= g).
+__device__ __forceinline__ int instance_of(const int32_t *off, int n_inst, int g)
+{
+    int lo = 0, hi = n_inst;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Maps a pair index of the flattened list to (instance, stage, target, source,
+// charge).  Per instance of n dipoles: stages x n targets x (n - 1) sources x
+// 2 charges, stages first; `pair_off` holds the prefix sums over instances
+// (instances without pairs repeat an offset and are never selected).
+struct PairIx {
+    int i0, n, th, i, j, w;
+};
+__device__ __forceinline__ PairIx pair_index(const int64_t *pair_off, const int32_t *off, int n_inst, int64_t idx)
+{
+    int lo = 0, hi = n_inst;                     // last instance with pair_off <= idx
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pair_off[mid] <= idx) lo = mid; else hi = mid;
+    }
+    PairIx P;
+    P.i0 = off[lo];
+    P.n = off[lo + 1] - P.i0;
+    const int M = 2 * (P.n - 1);
+    const int64_t rem = idx - pair_off[lo];
+    const int64_t per_stage = (int64_t)P.n * M;
+    P.th = (int)(rem / per_stage);
+    const int64_t r2 = rem - P.th * per_stage;
+    P.i = (int)(r2 / M);
+    const int mm = (int)(r2 - (int64_t)P.i * M);
+    const int jj = mm >> 1;
+    P.w = mm & 1;
+    P.j = jj < P.i ? jj : jj + 1;
+    return P;
+}
+
+// One step n = *step_base - k of the backward sweep, one workgroup per dipole
+// (the target).  Its prologue completes the dipole's sample n + 1 (every pair
+// that reads it belongs to a later step, already reversed) and transposes step
+// n; then every drive pair of the target at stages t_n + dt/2 and t_n + dt
+// reverses its field evaluation, scattering into the source's samples and
+// accumulating the cotangent of the (target - source) separation in rbp.  The
+// pair's retarded time is kept in taup as the next (earlier) step's start.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void adj_step_kernel(const DipDev *__restrict__ dev,
+                                                         const int32_t *__restrict__ off,
+                                                         const int64_t *__restrict__ pair_off, int n_inst, int n_dip,
+                                                         const double *__restrict__ hist, double *__restrict__ hbar,
+                                                         int mask, double dt, AdjState A, double *__restrict__ rbp,
+                                                         double *__restrict__ taup,
+                                                         const int64_t *__restrict__ step_base, int k, int max_iter,
+                                                         uint32_t *__restrict__ d_err)
+{
+    __shared__ double s_em, s_ee;
     const int tid = threadIdx.x;
-    if (n <= 0) return;
-    double *ybd = lds;
-    double *ybv = ybd + n;
-    double *eext = ybv + n;
-    double *emb = eext + n;
-    double *eeb = emb + n;
-    double *ecb = eeb + n;
-    double *rb = ecb + n;                         // [n][3]
-    const Hist H{hist, n_dip, ring - 1, dt, 1.0 / dt};
-    uint32_t err = 0u;
+    const int g = blockIdx.x;
+    const int64_t nstep = *step_base - k;
+    if (nstep < 0) return;
+    const DipDev &Di = dev[g];
+    const int inst = instance_of(off, n_inst, g);
+    const int i0 = off[inst], n = off[inst + 1] - i0, i = g - i0;
     const int M = 2 * (n - 1);
-    const int64_t mask = ring - 1;
-
-    // sample N (cotangents from the detector only)
-    for (int i = tid; i < n; i += BLOCK) {
-        const DipDev &P = dev[i0 + i];
-        const double *hb = hbar + ((steps & mask) * n_dip + i0 + i) * 3;
-        const double bd = load_agent(hb), bv = load_agent(hb + 1), ba = load_agent(hb + 2);
-        ybd[i] = bd - P.omega0 * P.omega0 * ba;
-        ybv[i] = bv - P.gamma0 * ba;
-        eext[i] = P.f * ba;
-        rb[3 * i] = rb[3 * i + 1] = rb[3 * i + 2] = 0.0;
-    }
-    __syncthreads();
-
-    for (int64_t nstep = steps - 1; nstep >= 0; --nstep) {
-        // RK4 transpose: y' = y + h/6 (k1 + 2k2 + 2k3 + k4), k = A y_stage + e E,
-        // A = [[0, 1], [-w0^2, -gamma0]], e = (0, f)
-        for (int i = tid; i < n; i += BLOCK) {
-            const DipDev &P = dev[i0 + i];
-            const double w2 = P.omega0 * P.omega0, g = P.gamma0, f = P.f, h = dt;
-            const double yd = ybd[i], yv = ybv[i];
-            double k1d = h / 6.0 * yd, k1v = h / 6.0 * yv;
-            double k2d = h / 3.0 * yd, k2v = h / 3.0 * yv;
-            double k3d = h / 3.0 * yd, k3v = h / 3.0 * yv;
-            const double k4d = h / 6.0 * yd, k4v = h / 6.0 * yv;
-            double ad = yd, av = yv, Ee = eext[i], Em = 0.0, Ec = 0.0;
-            // k4 = A y4 + e Ee;  y4 = y + h k3
-            double td = -w2 * k4v, tv = k4d - g * k4v;
-            Ee += f * k4v;
-            ad += td; av += tv; k3d += h * td; k3v += h * tv;
-            // k3 = A y3 + e Em;  y3 = y + h/2 k2
-            td = -w2 * k3v; tv = k3d - g * k3v;
-            Em += f * k3v;
-            ad += td; av += tv; k2d += 0.5 * h * td; k2v += 0.5 * h * tv;
-            // k2 = A y2 + e Em;  y2 = y + h/2 k1
-            td = -w2 * k2v; tv = k2d - g * k2v;
-            Em += f * k2v;
-            ad += td; av += tv; k1d += 0.5 * h * td; k1v += 0.5 * h * tv;
-            // k1 = A y + e Ec
-            ad += -w2 * k1v; av += k1d - g * k1v;
-            Ec += f * k1v;
-            ybd[i] = ad;
-            ybv[i] = av;
-            emb[i] = Em;
-            eeb[i] = Ee;
-            ecb[i] = Ec;
-        }
-        __syncthreads();
-        // drive pairs of this step: (stage, target i, source j != i, charge)
-        for (int m = tid; m < 2 * n * M; m += BLOCK) {
-            const int th = m / (n * M);
-            const int rem = m - th * n * M;
-            const int i = rem / M, mm = rem - (rem / M) * M;
-            const int jj = mm >> 1, w = mm & 1;
-            const int j = jj < i ? jj : jj + 1;
-            const double Es = th ? eeb[i] : emb[i];
-            if (Es == 0.0) continue;
-            const DipDev &Di = dev[i0 + i];
-            const DipDev &Dj = dev[i0 + j];
-            const DipLds Sj = dip_lds(Dj);
-            const double cf = w ? Sj.cfm : Sj.cfp;
-            const double kq = (w ? -Dj.q : Dj.q) * K_COUL;
-            const double x[3] = {Di.origin[0], Di.origin[1], Di.origin[2]};
-            Kin k;
-            HistEval e;
-            pair_solve(H, x, Sj, i0 + j, cf, nstep, (double)nstep + (th ? 1.0 : 0.5), max_iter, k, e, err);
-            const double Eb[3] = {Es * Di.axis[0], Es * Di.axis[1], Es * Di.axis[2]};
-            double Db[3];
-            pair_vjp(H, k, e, Sj, i0 + j, cf, kq, Eb, hbar, Db);
-            for (int c = 0; c < 3; ++c) {        // Delta = R_i - R_j
-                atomicAdd(&rb[3 * i + c], Db[c]);
-                atomicAdd(&rb[3 * j + c], -Db[c]);
-            }
-        }
-        __threadfence();
-        __syncthreads();
-        // sample nstep is complete: (d, d_dot) feed y[nstep]; d_ddot = f Ec[nstep] - ...
-        for (int i = tid; i < n; i += BLOCK) {
-            const DipDev &P = dev[i0 + i];
-            const double *hb = hbar + ((nstep & mask) * n_dip + i0 + i) * 3;
-            const double bd = load_agent(hb), bv = load_agent(hb + 1), ba = load_agent(hb + 2);
-            if (nstep > 0) {
-                ybd[i] += bd - P.omega0 * P.omega0 * ba;
-                ybv[i] += bv - P.gamma0 * ba;
-            }
-            eext[i] = ecb[i] + P.f * ba;         // cotangent of Ec[nstep] (= Ee[nstep-1], or E_d(0))
-        }
-        __syncthreads();
-    }
-    // E_d(0): drive from the static pre-history, depends on the positions only
-    for (int m = tid; m < n * M; m += BLOCK) {
-        const int i = m / M, mm = m - (m / M) * M;
-        const int jj = mm >> 1, w = mm & 1;
-        const int j = jj < i ? jj : jj + 1;
-        const double Es = eext[i];
-        if (Es == 0.0) continue;
-        const DipDev &Di = dev[i0 + i];
-        const DipDev &Dj = dev[i0 + j];
+    uint32_t err = 0u;
+    const Hist H{hist, n_dip, mask, dt, 1.0 / dt};
+    const double x[3] = {Di.origin[0], Di.origin[1], Di.origin[2]};
+    const double Eu[3] = {Di.axis[0], Di.axis[1], Di.axis[2]};   // unit drive cotangent
+    // the pair work does not depend on the cotangents: each lane solves its
+    // first pair and reverses it for a unit drive cotangent while thread 0
+    // finishes the dipole's state; the products are scaled afterwards
+    // (everything is linear in the drive cotangent)
+    int m2 = tid;
+    double Du[3] = {0.0, 0.0, 0.0};
+    HistBar hu;
+    hu.region = 0;
+    hu.k = 0;
+    int gj = 0;
+    int64_t idx = 0;
+    auto solve_unit = [&](int mm2) {
+        const int th = mm2 / M, m = mm2 - th * M;
+        const int jj = m >> 1, w = m & 1;
+        gj = i0 + (jj < i ? jj : jj + 1);
+        const DipDev &Dj = dev[gj];
         const DipLds Sj = dip_lds(Dj);
         const double cf = w ? Sj.cfm : Sj.cfp;
         const double kq = (w ? -Dj.q : Dj.q) * K_COUL;
+        idx = pair_off[inst] + ((int64_t)th * n + i) * M + m;
+        Kin kn;
+        HistEval e;
+        double tau;
+        pair_solve(H, x, Sj, gj, cf, nstep, (double)nstep + (th ? 1.0 : 0.5), max_iter, kn, e, err, taup[idx], &tau);
+        taup[idx] = tau;
+        pair_vjp(kn, e, Sj, cf, kq, Eu, Du, hu);
+    };
+    if (m2 < 2 * M) solve_unit(m2);
+    if (tid == 0) {
+        take_sample(Di, hbar, nstep + 1, n_dip, mask, A, g);
+        rk4_transpose(Di, dt, A, g);
+        s_em = A.em[g];
+        s_ee = A.ee[g];
+    }
+    __syncthreads();
+    for (; m2 < 2 * M; m2 += BLOCK) {
+        if (m2 != tid) solve_unit(m2);
+        const double Es = (m2 / M) ? s_ee : s_em;
+        HistBar hb = hu;
+        for (int c = 0; c < 3; ++c) {
+            hb.c0[c] = Es * hu.c0[c];
+            hb.c1[c] = Es * hu.c1[c];
+        }
+        scatter_global(H, gj, hb, hbar);
+        double *r = rbp + idx * 3;
+        r[0] += Es * Du[0];
+        r[1] += Es * Du[1];
+        r[2] += Es * Du[2];
+    }
+    if (err) atomicOr(d_err, err);
+}
+
+// After the sweep: sample 0 gives the cotangent of E_d(0) (y[0] is fixed).
+__global__ void adj_finish_kernel(const DipDev *__restrict__ dev, int n_dip, const double *__restrict__ hbar, int mask,
+                                  AdjState A)
+{
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n_dip; g += gridDim.x * blockDim.x)
+        take_sample(dev[g], hbar, 0, n_dip, mask, A, g);
+}
+
+// E_d(0): the drive from the static pre-history depends on the positions only;
+// its cotangent is ext after the sweep.  One stage per pair.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void adj_drive0_kernel(const DipDev *__restrict__ dev,
+                                                           const int32_t *__restrict__ off,
+                                                           const int64_t *__restrict__ pair_off0, int n_inst,
+                                                           int64_t n_pairs0, int n_dip, const double *__restrict__ hist,
+                                                           int mask, double dt, AdjState A, double *__restrict__ rbp0,
+                                                           int max_iter, uint32_t *__restrict__ d_err)
+{
+    const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= n_pairs0) return;
+    uint32_t err = 0u;
+    const Hist H{hist, n_dip, mask, dt, 1.0 / dt};
+    const PairIx P = pair_index(pair_off0, off, n_inst, idx);
+    const int gi = P.i0 + P.i, gj = P.i0 + P.j;
+    const double Es = A.ext[gi];
+    double Db[3] = {0.0, 0.0, 0.0};
+    if (Es != 0.0) {
+        const DipDev &Di = dev[gi];
+        const DipDev &Dj = dev[gj];
+        const DipLds Sj = dip_lds(Dj);
+        const double cf = P.w ? Sj.cfm : Sj.cfp;
+        const double kq = (P.w ? -Dj.q : Dj.q) * K_COUL;
         const double x[3] = {Di.origin[0], Di.origin[1], Di.origin[2]};
         Kin k;
         HistEval e;
-        pair_solve(H, x, Sj, i0 + j, cf, 0, 0.0, max_iter, k, e, err);
+        pair_solve(H, x, Sj, gj, cf, 0, 0.0, max_iter, k, e, err);
         const double Eb[3] = {Es * Di.axis[0], Es * Di.axis[1], Es * Di.axis[2]};
-        double Db[3];
-        pair_vjp(H, k, e, Sj, i0 + j, cf, kq, Eb, hbar, Db);
-        for (int c = 0; c < 3; ++c) {
-            atomicAdd(&rb[3 * i + c], Db[c]);
-            atomicAdd(&rb[3 * j + c], -Db[c]);
-        }
+        HistBar hb;
+        pair_vjp(k, e, Sj, cf, kq, Eb, Db, hb);      // pre-history: no sample cotangents
     }
-    __syncthreads();
-    for (int idx = tid; idx < 3 * n; idx += BLOCK) Rbar[3 * i0 + idx] += rb[idx];
+    rbp0[idx * 3 + 0] = Db[0];
+    rbp0[idx * 3 + 1] = Db[1];
+    rbp0[idx * 3 + 2] = Db[2];
     if (err) atomicOr(d_err, err);
+}
+
+// Position gradient of each dipole from the per-pair separation cotangents
+// (fixed order): + for pairs it targets, - for pairs it sources.
+__global__ void adj_positions_kernel(const int32_t *__restrict__ off, const int64_t *__restrict__ pair_off,
+                                     const int64_t *__restrict__ pair_off0, int n_inst, const double *__restrict__ rbp,
+                                     const double *__restrict__ rbp0, double *__restrict__ Rbar)
+{
+    const int inst = blockIdx.x;
+    const int i0 = off[inst], n = off[inst + 1] - i0;
+    const int M = 2 * (n - 1);
+    for (int a = threadIdx.x; a < n; a += blockDim.x) {
+        double s[3] = {0.0, 0.0, 0.0};
+        for (int b = 0; b < n; ++b) {
+            if (b == a) continue;
+            for (int w = 0; w < 2; ++w) {
+                // a as target of source b, and b as target of source a
+                const int ja = (b < a ? b : b - 1) * 2 + w;     // slot of source b in a's list
+                const int jb = (a < b ? a : a - 1) * 2 + w;     // slot of source a in b's list
+                for (int th = 0; th < 2; ++th) {
+                    const double *pa = rbp + (pair_off[inst] + ((int64_t)th * n + a) * M + ja) * 3;
+                    const double *pb = rbp + (pair_off[inst] + ((int64_t)th * n + b) * M + jb) * 3;
+                    for (int c = 0; c < 3; ++c) s[c] += pa[c] - pb[c];
+                }
+                const double *qa = rbp0 + (pair_off0[inst] + (int64_t)a * M + ja) * 3;
+                const double *qb = rbp0 + (pair_off0[inst] + (int64_t)b * M + jb) * 3;
+                for (int c = 0; c < 3; ++c) s[c] += qa[c] - qb[c];
+            }
+        }
+        for (int c = 0; c < 3; ++c) Rbar[(int64_t)(i0 + a) * 3 + c] += s[c];
+    }
 }
 
 __global__ void fill_zero_kernel(double *__restrict__ p, int64_t n)
@@ -413,17 +626,24 @@ __global__ void fill_zero_kernel(double *__restrict__ p, int64_t n)
         p[i] = 0.0;
 }
 
-hipError_t launch_dipole_vjp(const DipDev *d_dev, const int32_t *d_off, int n_inst, int max_n, int n_dip,
+hipError_t launch_dipole_vjp(const DipDev *d_dev, const int32_t *d_off, const int64_t *d_pair_off,
+                             const int64_t *d_pair_off0, int n_inst, int64_t n_pairs, int64_t n_pairs0, int n_dip,
                              const double *d_D, const double *d_V, const double *d_Ed, double *d_hist, double *d_hbar,
                              int ring, int64_t steps, double dt, const double *d_pts, int64_t npts,
                              const double *d_times, int n_snap, double *d_grad, double *d_Jpart, double *d_J,
-                             uint32_t *d_err, hipStream_t s)
+                             double *d_state, double *d_rbp, double *d_rbp0, double *d_taup, int64_t *d_step,
+                             uint32_t *d_err, int graph_chunk, hipStream_t s, hipStream_t cap, hipGraph_t *graph_out,
+                             hipGraphExec_t *exec_out)
 {
+    constexpr int B = 256;
     const int max_iter = 60;
     const int64_t rows = steps + 1;
     const int64_t hn = (int64_t)ring * n_dip * 3;
+    const int mask = ring - 1;
     hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, s, d_hbar, hn);
     hipLaunchKernelGGL(fill_zero_kernel, dim3(1), dim3(256), 0, s, d_grad, (int64_t)n_dip * 3);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, s, d_rbp, n_pairs * 3);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, s, d_taup, n_pairs);
     hipLaunchKernelGGL(hist_build_kernel, dim3((unsigned)((rows * n_dip + 255) / 256)), dim3(256), 0, s, d_dev, d_D,
                        d_V, d_Ed, n_dip, rows, d_hist);
     const int64_t lanes = npts * n_snap;
@@ -431,9 +651,51 @@ hipError_t launch_dipole_vjp(const DipDev *d_dev, const int32_t *d_off, int n_in
     hipLaunchKernelGGL(detector_vjp_kernel, dim3(nblk), dim3(256), 0, s, d_dev, n_dip, d_hist, d_hbar, ring, steps,
                        dt, d_pts, npts, d_times, n_snap, d_grad, d_Jpart, max_iter, d_err);
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, s, d_Jpart, (int64_t)nblk, d_J);
-    const size_t shmem = sizeof(double) * 9 * (size_t)max_n;
-    hipLaunchKernelGGL(lo_reverse_kernel<256>, dim3((unsigned)n_inst), dim3(256), shmem, s, d_dev, d_off, n_dip, d_hist,
-                       d_hbar, ring, steps, dt, d_grad, max_iter, d_err);
+    AdjState A{d_state, d_state + n_dip, d_state + 2 * (int64_t)n_dip, d_state + 3 * (int64_t)n_dip,
+               d_state + 4 * (int64_t)n_dip, d_state + 5 * (int64_t)n_dip};
+    hipLaunchKernelGGL(adj_init_kernel, dim3((unsigned)((n_dip + 255) / 256)), dim3(256), 0, s, n_dip, steps, A,
+                       d_step);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // one launch per step, n = base - k; after `count` launches the base moves
+    // down by count, so a captured chunk replays as the next `count` steps
+    auto enqueue = [&](hipStream_t q, int64_t count) {
+        for (int64_t k = 0; k < count; ++k)
+            hipLaunchKernelGGL(adj_step_kernel<B>, dim3((unsigned)n_dip), dim3(B), 0, q, d_dev, d_off, d_pair_off,
+                               n_inst, n_dip, d_hist, d_hbar, mask, dt, A, d_rbp, d_taup, d_step, (int)k, max_iter,
+                               d_err);
+        hipLaunchKernelGGL(adj_base_kernel, dim3(1), dim3(1), 0, q, d_step, -count);
+    };
+    const int64_t chunk = graph_chunk > 0 ? graph_chunk : 0;
+    if (chunk == 0 || steps < chunk || !cap) {
+        enqueue(s, steps);
+        e = hipGetLastError();
+    } else {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            enqueue(cap, chunk);
+            e = hipStreamEndCapture(cap, &graph);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        const int64_t reps = steps / chunk;
+        for (int64_t r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(exec, s);
+        if (e == hipSuccess && steps > reps * chunk) {
+            enqueue(s, steps - reps * chunk);
+            e = hipGetLastError();
+        }
+        *graph_out = graph;
+        *exec_out = exec;
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(adj_finish_kernel, dim3((unsigned)((n_dip + 255) / 256)), dim3(256), 0, s, d_dev, n_dip, d_hbar,
+                       mask, A);
+    if (n_pairs0 > 0)
+        hipLaunchKernelGGL(adj_drive0_kernel<B>, dim3((unsigned)((n_pairs0 + B - 1) / B)), dim3(B), 0, s, d_dev, d_off,
+                           d_pair_off0, n_inst, n_pairs0, n_dip, d_hist, mask, dt, A, d_rbp0, max_iter, d_err);
+    hipLaunchKernelGGL(adj_positions_kernel, dim3((unsigned)n_inst), dim3(256), 0, s, d_off, d_pair_off, d_pair_off0,
+                       n_inst, d_rbp, d_rbp0, d_grad);
     return hipGetLastError();
 }
 
