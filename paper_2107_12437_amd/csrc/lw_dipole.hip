@@ -52,14 +52,16 @@ hipError_t launch_dipole_prep(const lw_dipole *d_in, int n, DipDev *d_dev, hipSt
     return hipGetLastError();
 }
 
+// region: 0 before t = 0, 1 between stored samples, 2 past the newest sample.
 __device__ __forceinline__ void hist_at(const Hist &H, int j, double d0, int64_t nstep, double s, double out[3],
-                                        double &slope, uint32_t &err)
+                                        double &slope, int &region, uint32_t &err)
 {
     if (s < 0.0) {
         out[0] = d0;
         out[1] = 0.0;
         out[2] = 0.0;
         slope = 0.0;
+        region = 0;
         return;
     }
     const double fk = floor(s);
@@ -71,6 +73,7 @@ __device__ __forceinline__ void hist_at(const Hist &H, int j, double d0, int64_t
         out[1] = h[1] + h[2] * tt;
         out[2] = h[2];
         slope = out[1];
+        region = 2;
         return;
     }
     if (k + H.mask < nstep) err |= 1u;          // the slot was overwritten: history too short
@@ -81,35 +84,62 @@ __device__ __forceinline__ void hist_at(const Hist &H, int j, double d0, int64_t
     out[1] = (1.0 - u) * h0[1] + u * h1[1];
     out[2] = (1.0 - u) * h0[2] + u * h1[2];
     slope = (h1[0] - h0[0]) * H.inv_dt;           // d/dt' of the interpolated moment
+    region = 1;
 }
 
-// p_i . E of charge (cf, q_signed) of source dipole j seen at the origin of
-// target i at time (nstep + theta) dt.  The retarded time uses the exact
-// slope of the interpolated position, so Newton converges quadratically; the
-// field uses the interpolated (d, d_dot, d_ddot) at the converged time.
-__device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double cf, double kq,
-                             int64_t nstep, double theta, int max_iter, uint32_t &err)
+// Retarded time of the charge at offset cf d(t') p_j of source j, seen from a
+// point at separation Delta (|Delta|^2 = L2, Delta . p_j = sD) from the
+// source's origin at time base * dt: the root of c tau = |Delta - cf d(t -
+// tau) p_j| in [0, tau_hi], from tau.  Newton uses the exact slope of the
+// interpolated moment.  Within one interpolation segment (or one side of the
+// history's ends) g is smooth with |g''| <= rho'^2 / D + |rho''| (rho = cf d),
+// so once Newton's error bound from the current iterate is below tol/4 the new
+// iterate is accepted and the history evaluated there once more.  h holds the
+// stored (d, d_dot, d_ddot) at the returned root.
+__device__ __forceinline__ double retarded_hist(const Hist &H, int j, double d0, int64_t nstep, double base, double L2,
+                                                double sD, double cf, double tau, double tau_hi, int max_iter,
+                                                double h[3], uint32_t &err)
 {
-    const double dx = Si.ox - Sj.ox, dy = Si.oy - Sj.oy, dz = Si.oz - Sj.oz;
-    const double L2 = dx * dx + dy * dy + dz * dz;
-    const double L = sqrt(L2);
-    const double sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;     // Delta . p_j
-    const double base = (double)nstep + theta;
-    Bracket b(0.0, 2.0 * L * INV_C);
-    double tau = L * INV_C;
-    double h[3], slope;
+    const double tol = 4.0 * 2.220446049250313e-16;
+    Bracket b(0.0, tau_hi);
     bool ok = false;
     for (int it = 0; it < max_iter; ++it) {
-        hist_at(H, j, Sj.d0, nstep, base - tau * H.inv_dt, h, slope, err);
+        const double s = base - tau * H.inv_dt;
+        double slope;
+        int region;
+        hist_at(H, j, d0, nstep, s, h, slope, region, err);
         const double rho = cf * h[0];                            // charge offset along p_j
-        const double D = sqrt(fmax(L2 - 2.0 * rho * sD + rho * rho, 0.0));
-        const double dD = (D > 0.0) ? cf * slope * (sD - rho) * rcp_steer(D) : 0.0;
-        const double tn = newton_step(tau, D, dD, b);
-        ok = converged(tn, tau, 4.0 * 2.220446049250313e-16, b);
+        double D, iD;
+        root_rsqrt<true>(fmax(L2 - 2.0 * rho * sD + rho * rho, 1e-300), D, iD);
+        const double r1 = cf * slope;
+        const double dD = r1 * (sD - rho) * iD;
+        bool free_step;
+        const double tn = halley_step(tau, D, dD, 0.0, b, free_step);
+        ok = converged(tn, tau, tol, b);
         if (ok) break;                                           // keep h at the last evaluated tau
+        const double st = tn - tau;
+        const double r2 = (region == 2) ? cf * h[2] : 0.0;
+        const double sn = base - tn * H.inv_dt;
+        const bool same_seg = (region == 1) ? (floor(sn) == floor(s) && sn < (double)nstep)
+                                            : (region == 2 ? sn >= (double)nstep : sn < 0.0);
         tau = tn;
+        if (free_step && same_seg && (r1 * r1 + fabs(r2) * D) * (st * st) <= 0.5 * tol * tn * D * (C_LIGHT - fabs(r1))) {
+            double sl;
+            int rg;
+            hist_at(H, j, d0, nstep, sn, h, sl, rg, err);
+            ok = true;
+            break;
+        }
     }
     if (!ok) err |= 2u;
+    return tau;
+}
+
+// p_i . E at the origin of target i of the charge (cf, kq) of source j whose
+// stored state at the retarded time is h.
+__device__ __forceinline__ double drive_field(const DipLds &Si, const DipLds &Sj, double dx, double dy, double dz,
+                                              double cf, double kq, const double h[3])
+{
     Kin k;
     const double rho = cf * h[0];
     k.R[0] = dx - rho * Sj.px;
@@ -130,6 +160,20 @@ __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, 
     return o[4] * Si.px + o[5] * Si.py + o[6] * Si.pz;
 }
 
+// p_i . E of charge (cf, q_signed) of source dipole j seen at the origin of
+// target i at time (nstep + theta) dt.
+__device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double cf, double kq,
+                             int64_t nstep, double theta, int max_iter, uint32_t &err)
+{
+    const double dx = Si.ox - Sj.ox, dy = Si.oy - Sj.oy, dz = Si.oz - Sj.oz;
+    const double L2 = dx * dx + dy * dy + dz * dz;
+    const double L = sqrt(L2);
+    const double sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;     // Delta . p_j
+    double h[3];
+    retarded_hist(H, j, Sj.d0, nstep, (double)nstep + theta, L2, sD, cf, L * INV_C, 2.0 * L * INV_C, max_iter, h,
+                  err);
+    return drive_field(Si, Sj, dx, dy, dz, cf, kq, h);
+}
 
 // Drive fields of all targets of the instance at stage times theta in
 // `thetas[0..nth)` (in steps after nstep), written to Eout[th * n + i].
