@@ -117,8 +117,8 @@ enum { LW_FLAG_MASKED = 1u, LW_FLAG_NOCONV = 2u };
 
 typedef struct {
     int32_t precision;   /* LW_FP64: FP64 throughout.  LW_MIXED: FP64 retarded time and
-                            kinematics, FP32 field expressions with Kahan-compensated FP32
-                            sums over charges, FP32 outputs.                                */
+                            kinematics, FP32 field expressions summed over charges in FP64,
+                            FP32 outputs.                                                   */
     int32_t field_kind;  /* E and B as the total field of Eq. (E) or its Coulomb or
                             radiation part (Eqs. (ECoulomb), (Eradiation)); Phi and A
                             are unaffected                                                  */

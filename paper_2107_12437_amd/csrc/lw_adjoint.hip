@@ -124,13 +124,22 @@ __global__ __launch_bounds__(256) void fields_vjp_kernel(const SrcRec *__restric
     }
 }
 
-__global__ void vjp_reduce_kernel(const double *__restrict__ partial, int64_t nblk, int nout, double *__restrict__ grad)
+// One workgroup per output: strided partial sums per lane, then a tree, all in
+// a fixed order (bitwise reproducible).
+__global__ __launch_bounds__(256) void vjp_reduce_kernel(const double *__restrict__ partial, int64_t nblk, int nout,
+                                                         double *__restrict__ grad)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nout) return;
+    __shared__ double red[256];
+    const int o = blockIdx.x, tid = threadIdx.x;
     double s = 0.0;
-    for (int64_t b = 0; b < nblk; ++b) s += partial[b * nout + i];
-    grad[i] = s;
+    for (int64_t b = tid; b < nblk; b += 256) s += partial[b * nout + o];
+    red[tid] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off) red[tid] += red[tid + off];
+        __syncthreads();
+    }
+    if (tid == 0) grad[o] = red[0];
 }
 
 int vjp_params() { return NP; }
@@ -157,7 +166,7 @@ hipError_t launch_fields_vjp(const SrcRec *d_recs, int nch, const double *d_pts,
     if (e != hipSuccess) return e;
     const int nout = nch * NP;
     const int64_t nblk = (int64_t)grid.x * grid.y;
-    hipLaunchKernelGGL(vjp_reduce_kernel, dim3((nout + 255) / 256), dim3(256), 0, s, d_partial, nblk, nout, d_grad);
+    hipLaunchKernelGGL(vjp_reduce_kernel, dim3(nout), dim3(256), 0, s, d_partial, nblk, nout, d_grad);
     return hipGetLastError();
 }
 

@@ -229,8 +229,10 @@ __device__ __forceinline__ double halley_step(double tau, double D, double dD, d
         b.hi_ev = true;
     }
     const double gp = C_LIGHT - dD;
+    const double gp2 = gp * gp;
     const double den = fma(2.0 * gp, gp, g * ddD);          // 2 g'^2 - g g''
-    double tn = (den > gp * gp) ? tau - 2.0 * g * gp * rcp_steer(den) : tau - g * rcp_steer(gp);
+    // Newton's step is the same formula with the denominator 2 g'^2
+    double tn = tau - 2.0 * g * gp * rcp_steer((den > gp2) ? den : 2.0 * gp2);
     if (tn == tau) return tau;
     // landing on an evaluated end again would cycle: bisect instead
     if (tn <= b.lo) {
@@ -264,16 +266,18 @@ __device__ __forceinline__ bool converged(double tn, double tau, double tol_rel,
 }
 
 // A-posteriori stop for trajectories whose g is smooth in tau (circular and
-// linear oscillation): from tau, Newton's step leaves an error of about
-// |g''| / (2 g') dtau^2 and Halley's a smaller (cubic) one, so once that bound
-// is below tol/4 the new iterate is accepted without evaluating D at it.
-// Only a free (unclamped) step qualifies.
+// linear oscillation, either side of the start of uniform acceleration): from
+// tau, Newton's step leaves an error of about |g''| / (2 g') dtau^2 and
+// Halley's a smaller (cubic) one, so once that bound is below tol/4 the new
+// iterate is accepted without evaluating D at it.  Only a free (unclamped)
+// step qualifies; a clamped or bisection step ends the iteration once it is
+// below tol (rounding noise near the root gives free steps of a few ulp, which
+// the bound accepts).
 __device__ __forceinline__ bool converged_smooth(double tn, double tau, double tol_rel, const Bracket &b,
                                                  bool free_step, double dD, double ddD)
 {
     const double st = tn - tau;
-    return converged(tn, tau, tol_rel, b) ||
-           (free_step && fabs(ddD) * (st * st) <= 0.5 * tol_rel * tn * (C_LIGHT - dD));
+    return fabs(st) <= tol_rel * tn || (free_step && fabs(ddD) * (st * st) <= 0.5 * tol_rel * tn * (C_LIGHT - dD));
 }
 
 // Part of a source's retarded-time problem that does not depend on the
@@ -440,8 +444,11 @@ __device__ __forceinline__ void solve_accel(const SrcRec &S, const Geo &g, int m
         root_rsqrt<FULL>(fmax(perp2 + x1 * x1, 1e-300), D, iD);
         const double dD = vel * x1 * iD;                      // d x1 / d tau = vel
         const double ddD = (vel * vel - ((tp > 0.0) ? acc * x1 : 0.0) - dD * dD) * iD;
-        const double tn = halley_step(tau, D, dD, ddD, b);
-        ok = converged(tn, tau, tol_rel, b);
+        bool free_step;
+        const double tn = halley_step(tau, D, dD, ddD, b, free_step);
+        // g is smooth on either side of t' = 0 (the start of the motion), so the
+        // a-posteriori stop applies to a step that stays on one side
+        ok = converged_smooth(tn, tau, tol_rel, b, free_step && ((t - tn > 0.0) == (tp > 0.0)), dD, ddD);
         tau = tn;
     }
     k.flags = ok ? 0u : FLAG_NOCONV;

@@ -330,12 +330,21 @@ __global__ __launch_bounds__(256) void detector_vjp_kernel(const DipDev *__restr
     if (err) atomicOr(d_err, err);
 }
 
-__global__ void sum_partials_kernel(const double *__restrict__ part, int64_t n, double *__restrict__ out)
+// Sum of the per-workgroup objective partials in a fixed order (one workgroup).
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double *__restrict__ part, int64_t n,
+                                                           double *__restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
     double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s += part[i];
-    *out = s;
+    for (int64_t i = tid; i < n; i += 256) s += part[i];
+    red[tid] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off) red[tid] += red[tid + off];
+        __syncthreads();
+    }
+    if (tid == 0) *out = red[0];
 }
 
 __device__ __forceinline__ double load_agent(const double *p)
@@ -650,7 +659,7 @@ hipError_t launch_dipole_vjp(const DipDev *d_dev, const int32_t *d_off, const in
     const unsigned nblk = (unsigned)((lanes + 255) / 256);
     hipLaunchKernelGGL(detector_vjp_kernel, dim3(nblk), dim3(256), 0, s, d_dev, n_dip, d_hist, d_hbar, ring, steps,
                        dt, d_pts, npts, d_times, n_snap, d_grad, d_Jpart, max_iter, d_err);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, s, d_Jpart, (int64_t)nblk, d_J);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, d_Jpart, (int64_t)nblk, d_J);
     AdjState A{d_state, d_state + n_dip, d_state + 2 * (int64_t)n_dip, d_state + 3 * (int64_t)n_dip,
                d_state + 4 * (int64_t)n_dip, d_state + 5 * (int64_t)n_dip};
     hipLaunchKernelGGL(adj_init_kernel, dim3((unsigned)((n_dip + 255) / 256)), dim3(256), 0, s, n_dip, steps, A,
