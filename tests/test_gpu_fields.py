@@ -1,8 +1,9 @@
 """GPU parity of lw_fields against the FP64 oracle.
 
 Tolerances: the FP64 path against the oracle to 1e-12 (relative L2 and
-relative max per output group); the mixed path (FP32 field expressions with
-Kahan sums, FP64 retarded time) to 1e-5, the bound the fields are specified to.
+relative max per output group); the mixed path (FP32 field expressions summed
+over charges in FP64, FP64 retarded time) to 1e-5, the bound the fields are
+specified to.
 """
 import math
 
