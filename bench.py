@@ -42,7 +42,7 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # (profiles/fields_kernel_mixed_grid512x512x64t.md).  Valid only for the kernel
 # sources they were taken on; reported as null once those change.
 TRAFFIC_BYTES = 681.9e6
-TRAFFIC_SOURCES_SHA = "b056cbf3603d8635"
+TRAFFIC_SOURCES_SHA = "db9cf3116672fa63"
 
 
 def kernel_sources_sha() -> str:
@@ -88,18 +88,64 @@ def errors(got, ref):
     return res
 
 
+def run_part(part: str, cluster_steps: int, I, lw, torch):
+    """One workload alone: a warm-up call, then one timed call (for profiler runs)."""
+    if part == "pairs":
+        pw = I.workload_dipole_pairs()
+
+        def call(steps):
+            lw.dipole_run(pw["dipoles"], pw["inst_off"], pw["dt"], steps, policy="extrapolate", check=False)
+        call(200)
+        steps = pw["steps"]
+    elif part == "clusters":
+        cw = I.workload_clusters(steps=cluster_steps)
+
+        def call(steps):
+            lw.dipole_run(cw["dipoles"], cw["inst_off"], cw["dt"], steps, out_stride=10, check=False)
+        call(10)
+        steps = cw["steps"]
+    elif part == "grid-vjp":
+        dw = I.workload_detector()
+        dpts = torch.tensor(dw["points"], dtype=torch.float64, device="cuda")
+        dout, _ = lw.fields(dw["charges"], dpts, dw["times"], precision="fp64")
+        cot = torch.zeros_like(dout)
+        cot[:, 4:7] = 2.0 * dout[:, 4:7] / len(dw["times"])
+
+        def call(steps):
+            lw.fields_vjp(dw["charges"], dpts, dw["times"], cot)
+        call(0)
+        steps = 0
+    else:
+        ow = I.workload_dipole_detector()
+        opts = torch.tensor(ow["points"], dtype=torch.float64, device="cuda")
+
+        def call(steps):
+            lw.dipole_run_vjp(ow["dipoles"], ow["inst_off"], ow["dt"], ow["steps"], opts, ow["times"])
+        call(0)
+        steps = ow["steps"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    call(steps)
+    torch.cuda.synchronize()
+    lw.sync_status()
+    log(f"[bench] {part}: {(time.perf_counter() - t0) * 1e3:.2f} ms")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample-points", type=int, default=4096)
+    ap.add_argument("--cpu-sample-points", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dipole", action="store_true")
     ap.add_argument("--cluster-steps", type=int, default=500,
                     help="steps of the uneven-cluster workload to time")
     ap.add_argument("--grid-only", action="store_true",
                     help="time only the mixed grid step (for profiler runs)")
+    ap.add_argument("--part", choices=("pairs", "clusters", "grid-vjp", "adjoint"), default=None,
+                    help="run only this workload once after one warm-up, print its time and exit "
+                         "(for profiler runs; --cluster-steps sets the cluster run's length)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="run one plain device-to-device copy of BYTES and exit (calibrates the "
                          "profiler's byte counters)")
@@ -129,6 +175,9 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copied {4 * n} bytes")
         return
+    if args.part:
+        run_part(args.part, args.cluster_steps, I, lw, torch)
+        return
     w = I.workload_grid_mixed()
     pts = torch.tensor(w["points"], dtype=torch.float64, device="cuda")
     n_pts, n_ch, n_t = pts.shape[1], len(w["charges"]["kind"]), len(w["times"])
@@ -153,7 +202,8 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TFLOPS, 1),
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_VALU_TFLOPS, 4),
                 "traffic": TRAFFIC_BYTES if kernel_sources_sha() == TRAFFIC_SOURCES_SHA else None,
-                "kernel": "fields_kernel<float>", "flop_per_eval": FLOP_LW_FP32 + FLOP_SOLVE_FP64,
+                "kernel": "fields_kernel<float, TCH> (TCH: the tuned times per lane)",
+                "flop_per_eval": FLOP_LW_FP32 + FLOP_SOLVE_FP64,
                 "kernel_ms": round(kern_ms, 4)}
 
     # errors of both forms against the oracle on a sample of the same launch
@@ -166,19 +216,49 @@ def main():
     err = None
     if not args.no_cpu_baseline:
         import oracle as O
-        sub_pts = np.ascontiguousarray(w["points"][:, pidx])
-        log(f"[bench] oracle on {len(pidx)} points x {n_ch} charges x {n_t} times (1 core)")
+        from concurrent.futures import ThreadPoolExecutor
+        # the C oracle runs with the GIL released, so threads over disjoint point
+        # slices use that many host cores (capped at the 16 of one GPU's share)
+        workers = max(1, min(16, os.cpu_count() or 1))
+        chunks = [np.ascontiguousarray(w["points"][:, c]) for c in np.array_split(pidx, workers)]
+        log(f"[bench] oracle on {len(pidx)} points x {n_ch} charges x {n_t} times ({workers} threads)")
         t0 = time.perf_counter()
-        ref, _ = O.fields(w["charges"], sub_pts, w["times"])
+        with ThreadPoolExecutor(workers) as ex:
+            parts = list(ex.map(lambda c: O.fields(w["charges"], c, w["times"])[0], chunks))
         cpu_s = time.perf_counter() - t0
+        ref = np.concatenate(parts, axis=2)
         cpu_evals = len(pidx) * n_ch * n_t
-        cpu = {"value": cpu_evals / cpu_s, "unit": "LW evals/s", "cores": 1, "kind": "oracle",
+        # one core on a slice of the same sample
+        n1 = min(1024, len(pidx))
+        t0 = time.perf_counter()
+        O.fields(w["charges"], np.ascontiguousarray(w["points"][:, pidx[:n1]]), w["times"])
+        s1 = time.perf_counter() - t0
+        cpu = {"value": cpu_evals / cpu_s, "unit": "LW evals/s", "cores": workers, "kind": "oracle",
                "sample": f"{len(pidx)} seeded grid points x {n_ch} charges x {n_t} times of the same "
-                         f"workload ({cpu_evals} evals, {cpu_s:.1f} s, serial FP64 C oracle)"}
+                         f"workload ({cpu_evals} evals, {cpu_s:.1f} s wall on {workers} threads, FP64 C "
+                         f"oracle, disjoint point slices)",
+               "serial_value": n1 * n_ch * n_t / s1,
+               "serial_sample": f"{n1} of those points on one core ({s1:.1f} s)"}
         gm = out_m[:, :, torch.tensor(pidx, device="cuda")].double().cpu().numpy()
         gf = out_f[:, :, torch.tensor(pidx, device="cuda")].cpu().numpy()
         err = {"mixed": errors(gm, ref), "fp64": errors(gf, ref)}
-        log(f"[bench] oracle {cpu['value']:.3e} evals/s; mixed E relmax {err['mixed']['E']['relmax']:.2e}")
+        log(f"[bench] oracle {cpu['value']:.3e} evals/s ({workers} threads), {cpu['serial_value']:.3e} on one "
+            f"core; mixed E relmax {err['mixed']['E']['relmax']:.2e}")
+
+    # field stage alone: uniform-velocity charges have a closed-form retarded time
+    uw = I.workload_uniform_velocity()
+    upts = torch.tensor(uw["points"], dtype=torch.float64, device="cuda")
+    u_evals = upts.shape[1] * len(uw["charges"]["kind"]) * len(uw["times"])
+    uwall, ukern = timed_calls(lw.FieldsCall(uw["charges"], upts, uw["times"], precision="mixed"),
+                               max(3, args.steps // 4), 1)
+    u_tf = u_evals * FLOP_LW_FP32 / (ukern * 1e-3) / 1e12
+    field_stage = {"workload": uw["name"], "kernel_ms": round(ukern, 4), "evals_per_s": u_evals / (ukern * 1e-3),
+                   "fp32_tflops_algorithmic": round(u_tf, 3),
+                   "frac_unpacked_fp32_peak": round(u_tf / PEAK_VALU_TFLOPS, 4),
+                   "frac_packed_fp32_peak": round(u_tf / 157.3, 4),
+                   "note": "86 FP32 flops per eval; the closed-form FP64 retarded time is not counted"}
+    log(f"[bench] field stage (uniform velocity): {ukern:.3f} ms, {u_tf:.1f} FP32 TFLOP/s algorithmic")
+    del upts
 
     dip = None
     if not args.no_dipole:
@@ -252,7 +332,7 @@ def main():
                    "times": n_t, "evals_per_step": evals},
         "fp64_value": fp64_value, "mixed_over_fp64": value / fp64_value,
         "roofline": roofline, "cpu_baseline": cpu, "errors_vs_oracle": err, "dipoles": dip,
-        "clusters": clusters, "grid_vjp": vjp, "oscillator_adjoint": dip_vjp,
+        "clusters": clusters, "grid_vjp": vjp, "oscillator_adjoint": dip_vjp, "field_stage": field_stage,
     }
     print(json.dumps(line), flush=True)
 
