@@ -114,6 +114,8 @@ typedef struct {
 enum { LW_FP64 = 0, LW_MIXED = 1 };
 enum { LW_FIELD_TOTAL = 0, LW_FIELD_COULOMB = 1, LW_FIELD_RADIATION = 2 };
 enum { LW_FLAG_MASKED = 1u, LW_FLAG_NOCONV = 2u };
+/* Output components (lw_opts.outputs): rows of the output in this order. */
+enum { LW_OUT_PHI = 1, LW_OUT_A = 2, LW_OUT_E = 4, LW_OUT_B = 8, LW_OUT_S = 16 };
 
 typedef struct {
     int32_t precision;   /* LW_FP64: FP64 throughout.  LW_MIXED: FP64 retarded time and
@@ -123,7 +125,10 @@ typedef struct {
                             radiation part (Eqs. (ECoulomb), (Eradiation)); Phi and A
                             are unaffected                                                  */
     int32_t max_iter;    /* cap on retarded-time iterations per pair (0: 100)               */
-    int32_t reserved;    /* must be 0                                                       */
+    int32_t outputs;     /* LW_OUT_* bits selecting the output rows, in the order Phi (1 row),
+                            A (3), E (3), B (3), S (3); S = E x B / mu0 is the Poynting
+                            vector (W/m^2) of the summed fields (Sec. 2.2).  0: Phi | A |
+                            E | B, the 10 rows of Eqs. (V), (A), (E), (B)                   */
     double mask_radius;  /* (point, time) with a retarded distance below this to any charge
                             gets NaN outputs and LW_FLAG_MASKED (m; < 0: 1e-10)             */
 } lw_opts;
@@ -134,9 +139,11 @@ typedef struct {
  *   h_charges  host array of n_charges trajectories (n_charges >= 1)
  *   d_pts      device FP64, SoA [3][n_pts]: x[], then y[], then z[]
  *   h_times    host FP64 [n_times] observation times (s)
- *   d_out      device, SoA [n_times][10][n_pts] with components
- *              Phi, Ax, Ay, Az, Ex, Ey, Ez, Bx, By, Bz (V, V s/m, V/m, T);
- *              FP64 for LW_FP64, FP32 for LW_MIXED
+ *   d_out      device, SoA [n_times][n_rows][n_pts]: the rows opts->outputs
+ *              selects, in the order Phi; Ax, Ay, Az; Ex, Ey, Ez; Bx, By, Bz;
+ *              Sx, Sy, Sz (V, V s/m, V/m, T, W/m^2); by default the first 10;
+ *              FP64 for LW_FP64, FP32 for LW_MIXED (S is formed from the FP64
+ *              sums of E and B and rounded once)
  *   d_flags    device uint32 [n_pts] or NULL: LW_FLAG_* OR-ed over times
  * Returns LW_E_SUPERLUMINAL if a charge moves at >= c at or before a requested
  * time.  n_pts == 0 or n_times == 0 is a no-op.  Asynchronous. */
@@ -151,10 +158,11 @@ lw_status lw_fields(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, co
  * of charge c (those a kind does not use get 0).  The derivative follows the
  * retarded time through the implicit-function theorem on Eq. (ret_t) and the
  * trajectory's own derivatives (the jerk enters through d a / d t').
- *   d_cot   device, [n_times][10][n_pts], FP32 if opts->precision is LW_MIXED,
- *           FP64 otherwise (the layout of lw_fields' output); (point, time)
- *           entries with a non-finite cotangent, and pairs closer than the
- *           mask radius, contribute nothing
+ *   d_cot   device, [n_times][n_rows][n_pts], FP32 if opts->precision is
+ *           LW_MIXED, FP64 otherwise: the layout of lw_fields' output for the
+ *           same opts->outputs, which may not include LW_OUT_S (LW_E_INVALID);
+ *           (point, time) entries with a non-finite cotangent, and pairs
+ *           closer than the mask radius, contribute nothing
  *   d_grad  device FP64 [n_charges][11], overwritten
  * The forward quantities are recomputed in FP64 whatever the precision.
  * Sums run in a fixed order: the result is bitwise reproducible.  Asynchronous. */

@@ -71,9 +71,9 @@ __device__ __forceinline__ void pair_param_grad(const SrcRec &S, const Kin &k, i
 template <typename G>
 __global__ __launch_bounds__(256) void fields_vjp_kernel(const SrcRec *__restrict__ recs, int nch,
                                                          const double *__restrict__ pts, int64_t npts, int nt,
-                                                         int tchunk, int field_kind, int max_iter, double tol_rel,
-                                                         double mask_r, const G *__restrict__ cot,
-                                                         double *__restrict__ partial)
+                                                         int tchunk, int field_kind, int outputs, int nrows,
+                                                         int max_iter, double tol_rel, double mask_r,
+                                                         const G *__restrict__ cot, double *__restrict__ partial)
 {
     __shared__ double red[4][NP];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -88,6 +88,15 @@ __global__ __launch_bounds__(256) void fields_vjp_kernel(const SrcRec *__restric
     const int t0 = blockIdx.y * tchunk;
     const int t1 = min(t0 + tchunk, nt);
     const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    // cotangent row of each of the 10 outputs (-1: not requested, cotangent 0)
+    int row[10];
+    {
+        int r = 0;
+        row[0] = (outputs & OUT_PHI) ? r++ : -1;
+        for (int q = 1; q < 4; ++q) row[q] = (outputs & OUT_A) ? r++ : -1;
+        for (int q = 4; q < 7; ++q) row[q] = (outputs & OUT_E) ? r++ : -1;
+        for (int q = 7; q < 10; ++q) row[q] = (outputs & OUT_B) ? r++ : -1;
+    }
     for (int c = 0; c < nch; ++c) {
         double g[NP];
 #pragma unroll
@@ -99,7 +108,7 @@ __global__ __launch_bounds__(256) void fields_vjp_kernel(const SrcRec *__restric
                 bool fin = true;
 #pragma unroll
                 for (int j = 0; j < 10; ++j) {
-                    ob[j] = (double)cot[((int64_t)ti * 10 + j) * npts + p];
+                    ob[j] = row[j] >= 0 ? (double)cot[((int64_t)ti * nrows + row[j]) * npts + p] : 0.0;
                     fin = fin && isfinite(ob[j]);
                 }
                 if (!fin) continue;
@@ -156,12 +165,13 @@ hipError_t launch_fields_vjp(const SrcRec *d_recs, int nch, const double *d_pts,
 {
     const dim3 grid((unsigned)((npts + 255) / 256), (unsigned)((nt + tchunk - 1) / tchunk));
     const int max_iter = o.max_iter > 0 ? o.max_iter : 100;
+    const int om = output_mask(o.outputs), nrows = output_rows(o.outputs);
     if (o.precision == LW_MIXED)
         hipLaunchKernelGGL(fields_vjp_kernel<float>, grid, dim3(256), 0, s, d_recs, nch, d_pts, npts, nt, tchunk,
-                           o.field_kind, max_iter, tol_rel, mask_r, (const float *)d_cot, d_partial);
+                           o.field_kind, om, nrows, max_iter, tol_rel, mask_r, (const float *)d_cot, d_partial);
     else
         hipLaunchKernelGGL(fields_vjp_kernel<double>, grid, dim3(256), 0, s, d_recs, nch, d_pts, npts, nt, tchunk,
-                           o.field_kind, max_iter, tol_rel, mask_r, (const double *)d_cot, d_partial);
+                           o.field_kind, om, nrows, max_iter, tol_rel, mask_r, (const double *)d_cot, d_partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nout = nch * NP;

@@ -176,8 +176,9 @@ std::string field_key(const lw_opts &o, int nch, int nt, int64_t npts)
 {
     int64_t p2 = 1;
     while (p2 < npts) p2 <<= 1;
+    const int om = lw::output_mask(o.outputs);
     return "fields p" + std::to_string(o.precision) + " k" + std::to_string(o.field_kind) + " c" + std::to_string(nch) +
-           " t" + std::to_string(nt) + " n" + std::to_string(p2);
+           " t" + std::to_string(nt) + " n" + std::to_string(p2) + (om == 15 ? "" : " o" + std::to_string(om));
 }
 
 void load_tune_file(lw_ctx *ctx)
@@ -310,8 +311,10 @@ lw_status check_fields_args(const char *who, lw_ctx *ctx, const lw_traj *h_charg
     if (opts->precision != LW_FP64 && opts->precision != LW_MIXED) return fail(LW_E_INVALID, w + ": unknown precision");
     if (opts->field_kind < LW_FIELD_TOTAL || opts->field_kind > LW_FIELD_RADIATION)
         return fail(LW_E_INVALID, w + ": unknown field kind");
-    if (opts->max_iter < 0 || opts->max_iter > 100000 || opts->reserved != 0 || std::isnan(opts->mask_radius))
+    if (opts->max_iter < 0 || opts->max_iter > 100000 || std::isnan(opts->mask_radius))
         return fail(LW_E_INVALID, w + ": bad options");
+    if ((opts->outputs & ~(LW_OUT_PHI | LW_OUT_A | LW_OUT_E | LW_OUT_B | LW_OUT_S)) != 0)
+        return fail(LW_E_INVALID, w + ": unknown output bits");
     if (n_pts == 0 || n_times == 0) {
         *noop = true;
         return LW_OK;
@@ -427,8 +430,9 @@ lw_status lw_fields_vjp(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges
     if (st != LW_OK) return st;
     LW_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
+    if (opts->outputs & LW_OUT_S) return fail(LW_E_INVALID, "lw_fields_vjp: the Poynting vector has no adjoint here");
     if (noop) {
-        LW_HIP(hipMemsetAsync(d_grad, 0, sizeof(double) * (size_t)n_charges * lw::vjp_params(), s));
+        LW_HIP(lw::launch_fill_zero(d_grad, (int64_t)n_charges * lw::vjp_params(), s));
         return LW_OK;
     }
     const int tchunk = 4;

@@ -21,6 +21,7 @@ constexpr double K_COUL = 1.0 / (4.0 * PI * EPS0);
 enum { K_STATIONARY = 0, K_UNIFORM_VELOCITY = 1, K_LINEAR_OSC = 2, K_CIRCULAR = 3, K_ACCEL = 4 };
 enum { F_TOTAL = 0, F_COULOMB = 1, F_RADIATION = 2 };
 enum { FLAG_MASKED = 1u, FLAG_NOCONV = 2u };
+enum { OUT_PHI = 1, OUT_A = 2, OUT_E = 4, OUT_B = 8, OUT_S = 16 };
 
 // Per (time, charge) source record, written by the preparation kernel and read
 // wave-uniformly (scalar loads) by the field kernels.

@@ -17,6 +17,29 @@ namespace lw {
 
 size_t src_rec_bytes() { return sizeof(SrcRec); }
 
+int output_mask(int outputs) { return outputs == 0 ? (OUT_PHI | OUT_A | OUT_E | OUT_B) : outputs; }
+
+int output_rows(int outputs)
+{
+    const int m = output_mask(outputs);
+    return ((m & OUT_PHI) ? 1 : 0) + 3 * (((m & OUT_A) ? 1 : 0) + ((m & OUT_E) ? 1 : 0) + ((m & OUT_B) ? 1 : 0) +
+                                          ((m & OUT_S) ? 1 : 0));
+}
+
+__global__ void fill_zero_f64_kernel(double *__restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+hipError_t launch_fill_zero(double *d, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(fill_zero_f64_kernel, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, s, d, n);
+    return hipGetLastError();
+}
+
 __global__ void prep_kernel(const lw_traj *__restrict__ ch, int nch, const double *__restrict__ times, int nt,
                             SrcRec *__restrict__ recs, uint32_t *__restrict__ flags, int64_t npts)
 {
@@ -76,9 +99,9 @@ template <> __device__ __forceinline__ double qnan<double>() { return __builtin_
 template <typename F, int TCH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void fields_kernel(const SrcRec *__restrict__ recs, int nch,
                                                      const double *__restrict__ pts, int64_t npts, int nt,
-                                                     int t_base, int field_kind, int max_iter, double tol_rel,
-                                                     double mask_r, F *__restrict__ out,
-                                                     uint32_t *__restrict__ flags)
+                                                     int t_base, int field_kind, int outputs, int nrows,
+                                                     int max_iter, double tol_rel, double mask_r,
+                                                     F *__restrict__ out, uint32_t *__restrict__ flags)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npts) return;
@@ -106,8 +129,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
                 F o[10];
                 const F D = lw_terms<F>(k, S.kq, field_kind, o);
                 fl[j] |= k.flags | ((D >= (F)mask_r) ? 0u : FLAG_MASKED);
+                // the sums the requested rows need (the mask is uniform)
+                if (outputs & OUT_PHI) sum[j][0] += (double)o[0];
+                if (outputs & OUT_A)
 #pragma unroll
-                for (int q = 0; q < 10; ++q) sum[j][q] += (double)o[q];
+                    for (int q = 1; q < 4; ++q) sum[j][q] += (double)o[q];
+                if (outputs & (OUT_E | OUT_S))
+#pragma unroll
+                    for (int q = 4; q < 7; ++q) sum[j][q] += (double)o[q];
+                if (outputs & (OUT_B | OUT_S))
+#pragma unroll
+                    for (int q = 7; q < 10; ++q) sum[j][q] += (double)o[q];
             }
         }
     }
@@ -115,11 +147,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
 #pragma unroll
     for (int j = 0; j < TCH; ++j) {
         if (j < nti) {
-            F *dst = out + (int64_t)(t0 + j) * 10 * npts + p;
+            F *dst = out + (int64_t)(t0 + j) * nrows * npts + p;
             const bool masked = (fl[j] & FLAG_MASKED) != 0u;
-#pragma unroll
-            for (int q = 0; q < 10; ++q)
-                __builtin_nontemporal_store(masked ? qnan<F>() : (F)sum[j][q], dst + (int64_t)q * npts);
+            int r = 0;
+            auto put = [&](double v) {
+                __builtin_nontemporal_store(masked ? qnan<F>() : (F)v, dst + (int64_t)r * npts);
+                ++r;
+            };
+            const double *S = sum[j];
+            if (outputs & OUT_PHI) put(S[0]);
+            if (outputs & OUT_A) { put(S[1]); put(S[2]); put(S[3]); }
+            if (outputs & OUT_E) { put(S[4]); put(S[5]); put(S[6]); }
+            if (outputs & OUT_B) { put(S[7]); put(S[8]); put(S[9]); }
+            if (outputs & OUT_S) {
+                // Poynting vector E x B / mu0 of the summed fields, 1/mu0 = eps0 c^2
+                constexpr double IMU0 = EPS0 * C_LIGHT * C_LIGHT;
+                put((S[5] * S[9] - S[6] * S[8]) * IMU0);
+                put((S[6] * S[7] - S[4] * S[9]) * IMU0);
+                put((S[4] * S[8] - S[5] * S[7]) * IMU0);
+            }
             fl_all |= fl[j];
         }
     }
@@ -153,7 +199,8 @@ static hipError_t launch_fields_t(const SrcRec *d_recs, int nch, const double *d
         const int n_here = min(per_launch, nt - tb);
         const dim3 grid(gx, (unsigned)((n_here + TCH - 1) / TCH));
         hipLaunchKernelGGL((fields_kernel<F, TCH>), grid, dim3(block), 0, s, d_recs, nch, d_pts, npts, nt, tb,
-                           o.field_kind, max_iter, tol_rel, mask_r, d_out, d_flags);
+                           o.field_kind, output_mask(o.outputs), output_rows(o.outputs), max_iter, tol_rel, mask_r,
+                           d_out, d_flags);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -25,6 +25,11 @@ hipError_t launch_fields(const SrcRec *d_recs, int nch, const double *d_pts, int
                          const lw_opts &o, double tol_rel, double mask_r, void *d_out, uint32_t *d_flags,
                          const FieldLaunch &L, hipStream_t s);
 size_t src_rec_bytes();
+// Output rows of an outputs mask (0: Phi | A | E | B).
+int output_mask(int outputs);
+int output_rows(int outputs);
+// Zero-fills n doubles with a kernel (no memset node if the stream is captured).
+hipError_t launch_fill_zero(double *d, int64_t n, hipStream_t s);
 
 // Vector-Jacobian product of the grid fields with respect to the 11 trajectory
 // parameters of every charge (lw_adjoint.hip).

@@ -24,6 +24,21 @@ LIB_PATH = os.path.join(HERE, "liblw.so")
 FP64, MIXED = 0, 1
 FIELD_KINDS = {"total": 0, "coulomb": 1, "radiation": 2}
 PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+# output components (LW_OUT_*): bit and rows, in the order of the output rows
+OUTPUTS = {"phi": (1, 1), "A": (2, 3), "E": (4, 3), "B": (8, 3), "S": (16, 3)}
+DEFAULT_OUTPUTS = ("phi", "A", "E", "B")
+
+
+def output_mask(outputs) -> tuple[int, int]:
+    """(LW_OUT_* mask, rows) of a sequence of component names (None: phi, A, E, B)."""
+    names = DEFAULT_OUTPUTS if outputs is None else tuple(outputs)
+    bad = [n for n in names if n not in OUTPUTS]
+    if bad or not names:
+        raise ValueError(f"outputs must name some of {tuple(OUTPUTS)}: {names}")
+    mask = 0
+    for n in names:
+        mask |= OUTPUTS[n][0]
+    return mask, sum(r for b, r in OUTPUTS.values() if mask & b)
 DT_POLICIES = {"strict": 0, "extrapolate": 1}
 FLAG_MASKED, FLAG_NOCONV = 1, 2
 STATUS_NAMES = {0: "LW_OK", 1: "LW_E_INVALID", 2: "LW_E_SUPERLUMINAL", 3: "LW_E_DT_TOO_LARGE",
@@ -50,7 +65,7 @@ class Traj(ct.Structure):
 
 class Opts(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("field_kind", ct.c_int32), ("max_iter", ct.c_int32),
-                ("reserved", ct.c_int32), ("mask_radius", ct.c_double)]
+                ("outputs", ct.c_int32), ("mask_radius", ct.c_double)]
 
 
 class Dipole(ct.Structure):
@@ -189,7 +204,7 @@ class FieldsCall:
 
     def __init__(self, charges: dict, points: torch.Tensor, times, precision: str = "mixed",
                  field_kind: str = "total", mask_radius: float = 1e-10, max_iter: int = 0,
-                 with_flags: bool = True, ctx: Context | None = None):
+                 with_flags: bool = True, ctx: Context | None = None, outputs=None):
         if not (isinstance(points, torch.Tensor) and points.is_cuda and points.dtype == torch.float64
                 and points.dim() == 2 and points.shape[0] == 3):
             raise ValueError("points must be a [3, n] float64 tensor on the GPU")
@@ -197,10 +212,11 @@ class FieldsCall:
         self.ctx = ctx or default_context(points.device.index)
         self.charges, self.n_charges = pack_charges(charges)
         self.times = np.ascontiguousarray(np.atleast_1d(times), dtype=np.float64)
-        self.opts = Opts(PRECISIONS[precision], FIELD_KINDS[field_kind], int(max_iter), 0, float(mask_radius))
+        mask, rows = output_mask(outputs)
+        self.opts = Opts(PRECISIONS[precision], FIELD_KINDS[field_kind], int(max_iter), mask, float(mask_radius))
         n_pts = self.points.shape[1]
         dtype = torch.float32 if precision == "mixed" else torch.float64
-        self.out = torch.empty((len(self.times), 10, n_pts), dtype=dtype, device=points.device)
+        self.out = torch.empty((len(self.times), rows, n_pts), dtype=dtype, device=points.device)
         self.flags = torch.empty(n_pts, dtype=torch.int32, device=points.device) if with_flags else None
         self.n_pts = n_pts
 
@@ -215,17 +231,22 @@ class FieldsCall:
 
 
 def fields(charges: dict, points: torch.Tensor, times, precision: str = "mixed", field_kind: str = "total",
-           mask_radius: float = 1e-10, max_iter: int = 0, ctx: Context | None = None):
-    """Phi, A, E, B of the charges at points ([3, n] float64 on the GPU) and times.
-    Returns (out [n_times][10][n_pts], flags [n_pts] int32)."""
-    return FieldsCall(charges, points, times, precision, field_kind, mask_radius, max_iter, True, ctx).launch()
+           mask_radius: float = 1e-10, max_iter: int = 0, ctx: Context | None = None, outputs=None):
+    """Phi, A, E, B (or the components named in `outputs`, from phi, A, E, B and the
+    Poynting vector S) of the charges at points ([3, n] float64 on the GPU) and times.
+    Returns (out [n_times][rows][n_pts], flags [n_pts] int32); rows follow the order
+    phi, A, E, B, S."""
+    return FieldsCall(charges, points, times, precision, field_kind, mask_radius, max_iter, True, ctx,
+                      outputs).launch()
 
 
 def fields_vjp(charges: dict, points: torch.Tensor, times, cotangent: torch.Tensor, field_kind: str = "total",
-               mask_radius: float = 1e-10, max_iter: int = 0, ctx: Context | None = None) -> torch.Tensor:
+               mask_radius: float = 1e-10, max_iter: int = 0, ctx: Context | None = None,
+               outputs=None) -> torch.Tensor:
     """Gradient [n_charges][11] (PARAM_NAMES order) of sum(cotangent * fields(...)) with respect
-    to each charge's trajectory parameters.  cotangent has the layout of fields' output; its
-    dtype (float32 / float64) selects the matching precision."""
+    to each charge's trajectory parameters.  cotangent has the layout of fields' output for the
+    same `outputs` (phi, A, E, B; not S); its dtype (float32 / float64) selects the matching
+    precision."""
     if not (isinstance(points, torch.Tensor) and points.is_cuda and points.dtype == torch.float64):
         raise ValueError("points must be a [3, n] float64 tensor on the GPU")
     pts = points.contiguous()
@@ -233,10 +254,11 @@ def fields_vjp(charges: dict, points: torch.Tensor, times, cotangent: torch.Tens
     arr, n = pack_charges(charges)
     tms = np.ascontiguousarray(np.atleast_1d(times), dtype=np.float64)
     cot = cotangent.contiguous()
-    if cot.shape != (len(tms), 10, pts.shape[1]) or cot.device != pts.device:
-        raise ValueError("cotangent must be [n_times][10][n_pts] on the points' device")
+    mask, rows = output_mask(outputs)
+    if cot.shape != (len(tms), rows, pts.shape[1]) or cot.device != pts.device:
+        raise ValueError(f"cotangent must be [n_times][{rows}][n_pts] on the points' device")
     prec = {torch.float32: MIXED, torch.float64: FP64}[cot.dtype]
-    opts = Opts(prec, FIELD_KINDS[field_kind], int(max_iter), 0, float(mask_radius))
+    opts = Opts(prec, FIELD_KINDS[field_kind], int(max_iter), mask, float(mask_radius))
     grad = torch.empty((n, len(PARAM_NAMES)), dtype=torch.float64, device=pts.device)
     L = load_library()
     _check(L.lw_fields_vjp(ctx.handle, arr, n, ct.c_void_p(pts.data_ptr()), pts.shape[1],
