@@ -259,6 +259,16 @@ def main():
                    "note": "86 FP32 flops per eval; the closed-form FP64 retarded time is not counted"}
     log(f"[bench] field stage (uniform velocity): {ukern:.3f} ms, {u_tf:.1f} FP32 TFLOP/s algorithmic")
     del upts
+    # many-charge source: 1024 charges on four current loops
+    mw = I.workload_many_charges()
+    mpts = torch.tensor(mw["points"], dtype=torch.float64, device="cuda")
+    m_evals = mpts.shape[1] * len(mw["charges"]["kind"]) * len(mw["times"])
+    _, mkern = timed_calls(lw.FieldsCall(mw["charges"], mpts, mw["times"], precision="mixed"),
+                           max(3, args.steps // 4), 1)
+    many = {"workload": mw["name"], "kernel_ms": round(mkern, 4), "evals_per_s": m_evals / (mkern * 1e-3),
+            "precision": "mixed"}
+    log(f"[bench] many charges: {mkern:.3f} ms, {many['evals_per_s']:.4e} evals/s")
+    del mpts
 
     dip = None
     if not args.no_dipole:
@@ -333,6 +343,7 @@ def main():
         "fp64_value": fp64_value, "mixed_over_fp64": value / fp64_value,
         "roofline": roofline, "cpu_baseline": cpu, "errors_vs_oracle": err, "dipoles": dip,
         "clusters": clusters, "grid_vjp": vjp, "oscillator_adjoint": dip_vjp, "field_stage": field_stage,
+        "many_charges": many,
     }
     print(json.dumps(line), flush=True)
 

@@ -225,6 +225,47 @@ def workload_detector(grid_n: int = 256, n_times: int = 32, n_charges: int = 64)
     }
 
 
+def current_loop(n_charges: int, radius: float, speed: float, q: float = E_CHARGE,
+                 normal=(0.0, 0.0, 1.0), center=(0.0, 0.0, 0.0)) -> dict:
+    """n equal charges sharing one circular orbit at phases 2 pi k / n: a ring charge
+    n q with the steady current n q omega / (2 pi) once n is large (a continuous
+    source approximated by point charges, Sec. 2.2)."""
+    e1, e2 = orbit_basis(np.asarray(normal, float))
+    ch = empty_charges(n_charges)
+    ch["kind"][:] = CIRCULAR
+    ch["q"][:] = q
+    ch["c0"][:] = center
+    ch["e1"][:] = e1
+    ch["e2"][:] = e2
+    ch["amp"][:] = radius
+    ch["omega"][:] = speed / radius
+    ch["phase"][:] = 2 * math.pi * np.arange(n_charges) / n_charges
+    return ch
+
+
+def workload_many_charges(n_charges: int = 1024, grid_n: int = 256, n_times: int = 8) -> dict:
+    """Many-charge source: four current loops of n/4 charges each (radii 5-20 nm, speeds
+    0.01-0.1 c, seeded orientations, alternating signs, centres below z = 0, so every
+    charge stays 10 nm below the plane), seen on a 256x256 plane over +-100 nm at
+    z = 30 nm, 8 snapshots over 1 fs."""
+    rng = rng_for(6)
+    loops = []
+    per = n_charges // 4
+    for k in range(4):
+        normal = unit_sphere(rng, 1)[0]
+        loops.append(current_loop(per if k < 3 else n_charges - 3 * per, rng.uniform(5e-9, 20e-9),
+                                  rng.uniform(0.01, 0.1) * C_LIGHT, q=E_CHARGE * (1 if k % 2 == 0 else -1),
+                                  normal=normal,
+                                  center=[rng.uniform(-20e-9, 20e-9), rng.uniform(-20e-9, 20e-9),
+                                          rng.uniform(-20e-9, 0.0)]))
+    return {
+        "name": f"loops-{n_charges}q-{grid_n}x{grid_n}-{n_times}t",
+        "charges": concat_charges(loops),
+        "points": plane_grid(100e-9, grid_n, z=30e-9),
+        "times": (np.arange(n_times) + 1) * 1e-15 / n_times,
+    }
+
+
 # ----------------------------------------------------------------------------
 # Lorentz-oscillator workloads
 # ----------------------------------------------------------------------------

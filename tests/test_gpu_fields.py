@@ -83,6 +83,18 @@ def test_detector_workload_sample():
     assert_fields_close(got, ref, TOL_MIXED, "detector")
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL_FP64), ("mixed", TOL_MIXED)])
+def test_many_charges_current_loops(precision, tol):
+    """A many-charge source: four current loops of 64 charges each (256 in all) on a
+    20x20 plane, 3 snapshots.  The fields of the loops are far weaker than those of
+    single charges (their contributions cancel around each ring), so the tolerance
+    is taken relative to each output group's largest magnitude."""
+    w = I.workload_many_charges(n_charges=256, grid_n=20, n_times=3)
+    ref, _ = run_oracle(w)
+    got, _ = run_gpu(w, precision)
+    assert_fields_close(got, ref, tol, f"loops {precision}")
+
+
 def test_masking_and_flags():
     w = I.workload_tiny_orbit()
     r, *_ = O.kinematics(w["charges"], 0, w["times"][0])

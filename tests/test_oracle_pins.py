@@ -337,6 +337,29 @@ def test_oscillating_dipole_matches_appendix_d():
         assert np.all(err < GOLD["app_d_rel_error"]["value"]), err
 
 
+def test_current_loop_axis_fields_are_static_ring_fields():
+    """64 charges q sharing one circular orbit (R = 10 nm, speed 1e-3 c) at phases
+    2 pi k / 64: on the axis the transverse fields cancel by symmetry, and E_z, B_z are
+    those of a static ring charge 64 q and of the steady current I = 64 q omega / (2 pi)
+    up to O(beta^2) = 1e-6: E_z = k Q z / (R^2 + z^2)^(3/2) and, by Biot-Savart,
+    B_z = mu0 I R^2 / (2 (R^2 + z^2)^(3/2)) (Jackson, Sec. 5.5)."""
+    n, R, v = 64, 10e-9, 1e-3 * C
+    ch = I.current_loop(n, R, v)
+    w = v / R
+    z = np.array([0.3, 1.0, 3.0]) * R
+    pts = np.stack([np.zeros_like(z), np.zeros_like(z), z])
+    out, _ = O.fields(ch, pts, [1e-15, 1.3e-15])
+    D3 = (R * R + z * z) ** 1.5
+    Ez = K * n * E * z / D3
+    mu0 = 1.0 / (EPS0 * C * C)
+    Bz = mu0 * (n * E * w / (2 * math.pi)) * R * R / (2 * D3)
+    for it in range(2):
+        assert np.all(np.abs(out[it, 4:6]) <= 1e-10 * np.abs(out[it, 6]))      # E_x, E_y
+        assert np.all(np.abs(out[it, 7:9]) <= 1e-10 * np.abs(out[it, 9]))      # B_x, B_y
+        assert np.all(np.abs(out[it, 6] / Ez - 1) < 3e-6), out[it, 6] / Ez - 1
+        assert np.all(np.abs(out[it, 9] / Bz - 1) < 3e-6), out[it, 9] / Bz - 1
+
+
 def test_masking_rule():
     w = I.workload_tiny_orbit()
     out, flags = O.fields(w["charges"], w["points"], w["times"])
