@@ -41,8 +41,8 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0) counters, calibrated on a plain 1 GiB copy
 # (profiles/fields_kernel_mixed_grid512x512x64t.md).  Valid only for the kernel
 # sources they were taken on; reported as null once those change.
-TRAFFIC_BYTES = 681.9e6
-TRAFFIC_SOURCES_SHA = "db9cf3116672fa63"
+TRAFFIC_BYTES = 682.0e6
+TRAFFIC_SOURCES_SHA = "9f69e8271795bf4a"
 
 
 def kernel_sources_sha() -> str:
