@@ -50,10 +50,10 @@ def lib():
         L.or_lw_pair.restype = ct.c_uint
         L.or_fields.argtypes = [ct.POINTER(Traj), ct.c_int, dp, ct.c_int64, dp, ct.c_int, ct.c_int,
                                 ct.c_double, dp, ct.POINTER(ct.c_uint32)]
-        L.or_dipole_run.argtypes = [ct.c_int, dp, dp, dp, dp, dp, dp, dp, ct.c_int,
+        L.or_dipole_run.argtypes = [ct.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, ct.c_int,
                                     ct.POINTER(ct.c_int32), ct.c_double, ct.c_int64, ct.c_int,
                                     ct.c_double, ct.c_int64, dp, dp, dp, dp, dp]
-        L.or_dipole_fields.argtypes = [ct.c_int, dp, dp, dp, dp, dp, dp, ct.c_double, ct.c_int64, dp,
+        L.or_dipole_fields.argtypes = [ct.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, ct.c_double, ct.c_int64, dp,
                                        dp, ct.c_int64, dp, ct.c_int, dp]
         _lib = L
     return _lib
@@ -65,6 +65,13 @@ def _dp(a: np.ndarray):
 
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _motion(dip: dict, n: int):
+    """Origin motion arrays (amplitude [n][3], omega, phase) or Nones for fixed origins."""
+    if "motion_amp" not in dip or not np.any(dip["motion_amp"]):
+        return None, None, None
+    return (_f64(np.reshape(dip["motion_amp"], (n, 3))), _f64(dip["motion_omega"]), _f64(dip["motion_phase"]))
 
 
 def pack(charges: dict):
@@ -135,15 +142,20 @@ def fields(charges: dict, points, times, kind: int = TOTAL, mask_radius: float =
 def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: int = DT_STRICT,
                max_vel: float = 299792458.0 / 100, out_stride: int = 1, want_hist: bool = False):
     """Runs Algorithm 1 on independent instances.  Returns dict of [n_out][n_dip] arrays
-    d, d_dot, energy, Ed (and hist [(steps+1)][n_dip][3] when asked)."""
+    d, d_dot, energy, Ed (and hist [(steps+1)][n_dip][3] when asked).  Optional keys
+    motion_amp [n][3], motion_omega, motion_phase move the origins as
+    origin + motion_amp cos(motion_omega t + motion_phase) (Sec. 4.3)."""
     dip = {k: _f64(v) for k, v in dipoles.items()}
     n = len(dip["omega0"])
     off = np.ascontiguousarray(inst_off, dtype=np.int32)
     n_out = steps // out_stride + 1
     res = {k: np.empty((n_out, n)) for k in ("d", "d_dot", "energy", "Ed")}
     hist = np.empty((steps + 1, n, 3)) if want_hist else None
+    mamp, mom, mph = _motion(dip, n)
     st = lib().or_dipole_run(n, _dp(dip["origin"]), _dp(dip["axis"]), _dp(dip["omega0"]), _dp(dip["q"]),
-                             _dp(dip["m1"]), _dp(dip["m2"]), _dp(dip["d0"]), len(off) - 1,
+                             _dp(dip["m1"]), _dp(dip["m2"]), _dp(dip["d0"]),
+                             _dp(mamp) if mamp is not None else None, _dp(mom) if mom is not None else None,
+                             _dp(mph) if mph is not None else None, len(off) - 1,
                              off.ctypes.data_as(ct.POINTER(ct.c_int32)), float(dt), int(steps),
                              int(policy), float(max_vel), int(out_stride), _dp(res["d"]),
                              _dp(res["d_dot"]), _dp(res["energy"]), _dp(res["Ed"]),
@@ -163,8 +175,11 @@ def dipole_fields(dipoles: dict, dt: float, steps: int, hist, points, times):
     pts = _f64(points)
     tms = _f64(np.atleast_1d(times))
     out = np.empty((len(tms), 3, pts.shape[1]))
+    mamp, mom, mph = _motion(dip, n)
     st = lib().or_dipole_fields(n, _dp(dip["origin"]), _dp(dip["axis"]), _dp(dip["q"]), _dp(dip["m1"]),
-                                _dp(dip["m2"]), _dp(dip["d0"]), float(dt), int(steps), _dp(h), _dp(pts),
+                                _dp(dip["m2"]), _dp(dip["d0"]),
+                                _dp(mamp) if mamp is not None else None, _dp(mom) if mom is not None else None,
+                                _dp(mph) if mph is not None else None, float(dt), int(steps), _dp(h), _dp(pts),
                                 pts.shape[1], _dp(tms), len(tms), _dp(out))
     if st:
         raise OracleError(st, "dipole fields")

@@ -304,6 +304,7 @@ enum { OR_DT_STRICT = 0, OR_DT_EXTRAPOLATE = 1 };
 typedef struct {
     int n_dip;
     const double *origin, *axis, *q;
+    const double *mamp, *momega, *mphase;  /* origin motion O + mamp cos(momega t + mphase), or NULL */
     const double *d0;
     double *coef_p, *coef_m;   /* m2/(m1+m2), -m1/(m1+m2): charge offsets per unit r_dip */
     double *hist;              /* [(steps+1)][n_dip][3] = (d, d_dot, d_ddot) */
@@ -342,20 +343,42 @@ static void lo_hist_at(const or_lo *L, int jd, int64_t n, double tp, double out[
     }
 }
 
+/* Origin (centre of mass) of dipole jd at time t and its velocity and
+ * acceleration: fixed, or moving as O + m cos(w t + phi) (Sec. 4.3, moving
+ * dipoles; the motion is prescribed for all t, before t = 0 as well). */
+static void lo_origin(const or_lo *L, int jd, double t, double R[3], double V[3], double A[3])
+{
+    int k;
+    double c = 1.0, s = 0.0, w = 0.0;
+    if (L->mamp) {
+        w = L->momega[jd];
+        c = cos(w * t + L->mphase[jd]);
+        s = sin(w * t + L->mphase[jd]);
+    }
+    for (k = 0; k < 3; ++k) {
+        double m = L->mamp ? L->mamp[jd * 3 + k] : 0.0;
+        R[k] = L->origin[jd * 3 + k] + m * c;
+        V[k] = -w * m * s;
+        A[k] = -w * w * m * c;
+    }
+}
+
 /* Position, velocity, acceleration of charge `which` (0: +q at the positive end,
- * 1: -q) of dipole jd at time tp, by Eqs. (r_1), (r_2) with r_dip = (d/q) p. */
+ * 1: -q) of dipole jd at time tp, by Eqs. (r_1), (r_2) with r_dip = (d/q) p
+ * about the dipole's origin at tp. */
 static void lo_charge_kin(const or_lo *L, int jd, int which, int64_t n, double tp,
                           double r[3], double v[3], double a[3])
 {
-    double h[3], cf;
+    double h[3], cf, R[3], V[3], A[3];
     int k;
     lo_hist_at(L, jd, n, tp, h);
+    lo_origin(L, jd, tp, R, V, A);
     cf = (which == 0 ? L->coef_p[jd] : L->coef_m[jd]) / L->q[jd];
     for (k = 0; k < 3; ++k) {
         double p = L->axis[jd * 3 + k];
-        r[k] = L->origin[jd * 3 + k] + cf * h[0] * p;
-        v[k] = cf * h[1] * p;
-        a[k] = cf * h[2] * p;
+        r[k] = R[k] + cf * h[0] * p;
+        v[k] = V[k] + cf * h[1] * p;
+        a[k] = A[k] + cf * h[2] * p;
     }
 }
 
@@ -374,7 +397,11 @@ static int lo_charge_field(const or_lo *L, int jd, int which, int64_t n, const d
     double lo = 0.0, hi, tau, r[3], v[3], a[3], Rv[3], R, nn[3], beta[3], bdot[3], nmb[3];
     double cr1[3], cr2[3], kappa, beta2, K, qc;
     int k, grow = 0, it = 0;
-    for (k = 0; k < 3; ++k) Rv[k] = x[k] - L->origin[jd * 3 + k];
+    {
+        double O[3], V[3], A[3];
+        lo_origin(L, jd, t, O, V, A);
+        for (k = 0; k < 3; ++k) Rv[k] = x[k] - O[k];
+    }
     hi = 2.0 * norm3(Rv) / OR_C;
     if (hi <= 0.0) return OR_E_INVALID;
     while (lo_g(L, jd, which, n, x, t, hi) < 0.0) { hi *= 2.0; if (++grow > 64) return OR_E_NOCONV; }
@@ -411,9 +438,9 @@ static int lo_charge_field(const or_lo *L, int jd, int which, int64_t n, const d
  * instance [i_lo, i_hi) (Eq. (LO_equation); own dipole excluded, Sec. 3.2). */
 static int lo_drive(const or_lo *L, int i, int i_lo, int i_hi, int64_t n, double t, double *Ed)
 {
-    double sum = 0.0, comp = 0.0, E[3];
-    const double *x = &L->origin[i * 3];
+    double sum = 0.0, comp = 0.0, E[3], x[3], V[3], A[3];
     int jd, w, st;
+    lo_origin(L, i, t, x, V, A);                 /* the field is taken at the origin at time t */
     for (jd = i_lo; jd < i_hi; ++jd) {
         if (jd == i) continue;
         for (w = 0; w < 2; ++w) {
@@ -441,6 +468,7 @@ static int lo_drive(const or_lo *L, int i, int i_lo, int i_hi, int64_t n, double
  * moment d, d_dot, energy of Eq. (dipoleE), drive field E_d.  Any may be NULL. */
 int or_dipole_run(int n_dip, const double *origin, const double *axis, const double *omega0,
                   const double *q, const double *m1, const double *m2, const double *d0,
+                  const double *mamp, const double *momega, const double *mphase,
                   int n_inst, const int32_t *inst_off, double dt, int64_t steps, int policy,
                   double max_vel, int64_t out_stride,
                   double *out_d, double *out_v, double *out_E, double *out_Ed, double *hist_out)
@@ -461,15 +489,19 @@ int or_dipole_run(int n_dip, const double *origin, const double *axis, const dou
             for (a = inst_off[inst]; a < inst_off[inst + 1]; ++a)
                 for (b = a + 1; b < inst_off[inst + 1]; ++b) {
                     double d[3];
+                    double low;
                     d[0] = origin[a * 3] - origin[b * 3];
                     d[1] = origin[a * 3 + 1] - origin[b * 3 + 1];
                     d[2] = origin[a * 3 + 2] - origin[b * 3 + 2];
-                    if (!(OR_C * dt < norm3(d))) return OR_E_DT_TOO_LARGE;
+                    /* moving origins: the separation never falls below this */
+                    low = norm3(d) - (mamp ? norm3(&mamp[a * 3]) + norm3(&mamp[b * 3]) : 0.0);
+                    if (!(OR_C * dt < low)) return OR_E_DT_TOO_LARGE;
                 }
         }
     }
     nstore = steps + 1;
     L.n_dip = n_dip; L.origin = origin; L.axis = axis; L.q = q; L.d0 = d0; L.dt = dt;
+    L.mamp = mamp; L.momega = momega; L.mphase = mphase;
     L.hist = (double *)malloc(sizeof(double) * 3 * (size_t)nstore * (size_t)n_dip);
     L.coef_p = (double *)malloc(sizeof(double) * (size_t)n_dip);
     L.coef_m = (double *)malloc(sizeof(double) * (size_t)n_dip);
@@ -548,8 +580,10 @@ int or_dipole_run(int n_dip, const double *origin, const double *axis, const dou
             h[1] = ynew[2 * i + 1];
             h[2] = q[i] * q[i] / mass[i] * Eend[i] - gam[i] * h[1] - omega0[i] * omega0[i] * h[0];
             Ecur[i] = Eend[i];
-            /* the charge speeds are |coef| * |d_dot| / q; Sec. 3.2 raises above max_vel */
+            /* the charge speeds are at most |origin velocity| + |coef| * |d_dot| / q;
+               Sec. 3.2 raises above max_vel */
             speed = fmax(fabs(L.coef_p[i]), fabs(L.coef_m[i])) * fabs(h[1]) / q[i];
+            if (mamp) speed += fabs(momega[i]) * norm3(&mamp[i * 3]);
             if (!(isfinite(h[0]) && isfinite(h[1]) && isfinite(h[2]))) { st = OR_E_NONFINITE; goto done; }
             if (max_vel > 0.0 && speed > max_vel) { st = OR_E_VELOCITY; goto done; }
         }
@@ -565,7 +599,8 @@ done:
  * <= steps*dt), from a finished run's history hist ([(steps+1)][n_dip][3]).
  * out is [n_times][3][n_pts] (E only, total field). */
 int or_dipole_fields(int n_dip, const double *origin, const double *axis, const double *q,
-                     const double *m1, const double *m2, const double *d0, double dt, int64_t steps,
+                     const double *m1, const double *m2, const double *d0,
+                     const double *mamp, const double *momega, const double *mphase, double dt, int64_t steps,
                      const double *hist, const double *pts, int64_t n_pts, const double *times,
                      int n_times, double *out)
 {
@@ -573,6 +608,7 @@ int or_dipole_fields(int n_dip, const double *origin, const double *axis, const 
     int i, ti, w, k, st = OR_OK;
     int64_t p;
     L.n_dip = n_dip; L.origin = origin; L.axis = axis; L.q = q; L.d0 = d0; L.dt = dt;
+    L.mamp = mamp; L.momega = momega; L.mphase = mphase;
     L.hist = (double *)hist;
     L.coef_p = (double *)malloc(sizeof(double) * (size_t)n_dip);
     L.coef_m = (double *)malloc(sizeof(double) * (size_t)n_dip);

@@ -279,6 +279,10 @@ def empty_dipoles(n: int) -> dict:
         "m1": np.full(n, M_E),
         "m2": np.full(n, M_E),
         "d0": np.zeros(n),
+        # origin motion: origin + motion_amp cos(motion_omega t + motion_phase) (Sec. 4.3)
+        "motion_amp": np.zeros((n, 3)),
+        "motion_omega": np.zeros(n),
+        "motion_phase": np.zeros(n),
     }
 
 

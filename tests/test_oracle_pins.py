@@ -445,6 +445,67 @@ def test_static_prehistory_drive():
     np.testing.assert_allclose(r["Ed"][0, 0], Ef @ dip["axis"][0], rtol=1e-9)
 
 
+def test_moving_dipole_prehistory_drive_is_a_trajectory_field():
+    """Moving dipoles (Sec. 4.3): before t = 0 a dipole's moment is static, so a source
+    whose origin moves as O + m cos(w t + phi) carries its two charges on exactly that
+    trajectory, the linear-oscillation family of the grid path.  The drive of the moving
+    target at t = 0 is then p_i . E of those two trajectory charges at the target's own
+    position R_i(0), from the independent grid-field evaluator (itself pinned to the
+    closed forms above).  The origin speed here is 2e-4 c, so its velocity and
+    acceleration terms are far above the tolerance."""
+    dip = I.empty_dipoles(2)
+    dip["axis"][0] = [0.6, 0.8, 0.0]
+    dip["axis"][1] = [0.0, 0.6, 0.8]
+    dip["origin"][1] = [9e-9, 2e-9, -3e-9]
+    dip["omega0"][:] = 2 * math.pi * 200e12
+    dip["m1"][1] = 3 * ME
+    dip["d0"][:] = [E * 2e-12, -E * 3e-12]
+    wR = 2 * math.pi * 100e12
+    dip["motion_amp"][0] = [0.0, 0.0, 0.1e-9]
+    dip["motion_amp"][1] = [0.06e-9, -0.08e-9, 0.0]
+    dip["motion_omega"][:] = [wR, 0.7 * wR]
+    dip["motion_phase"][:] = [0.3, 2.1]
+    r = O.dipole_run(dip, [0, 2], 1e-18, 1)
+    m1, m2 = dip["m1"][1], dip["m2"][1]
+    rdip = dip["d0"][1] / E * dip["axis"][1]
+    amp = np.linalg.norm(dip["motion_amp"][1])
+    ch = I.empty_charges(2)
+    for k, (sign, off) in enumerate(((1.0, m2 / (m1 + m2)), (-1.0, -m1 / (m1 + m2)))):
+        ch["kind"][k] = I.LINEAR_OSC
+        ch["q"][k] = sign * E
+        ch["c0"][k] = dip["origin"][1] + off * rdip
+        ch["e1"][k] = dip["motion_amp"][1] / amp
+        ch["e2"][k] = I.orbit_basis(ch["e1"][k])[0]
+        ch["amp"][k] = amp
+        ch["omega"][k] = dip["motion_omega"][1]
+        ch["phase"][k] = dip["motion_phase"][1]
+    x = dip["origin"][0] + dip["motion_amp"][0] * math.cos(dip["motion_phase"][0])
+    out, _ = O.fields(ch, x[:, None], [0.0])
+    Ed = out[0, 4:7, 0] @ dip["axis"][0]
+    single = K * E / np.linalg.norm(x - dip["origin"][1]) ** 2
+    assert abs(r["Ed"][0, 0] - Ed) <= 1e-12 * single, (r["Ed"][0, 0], Ed)
+    # and the motion matters at this level: the fixed-origin drive differs
+    fixed = {k: np.array(v, copy=True) for k, v in dip.items()}
+    fixed["motion_amp"][:] = 0.0
+    rf = O.dipole_run(fixed, [0, 2], 1e-18, 1)
+    assert abs(rf["Ed"][0, 0] - Ed) > 1e-6 * single
+
+
+def test_moving_dipoles_dt_rule_uses_the_closest_approach():
+    """The strict time-step rule (Sec. 3.2) holds against the smallest separation the
+    moving origins can reach: |O_i - O_j| - |m_i| - |m_j|."""
+    dip = I.empty_dipoles(2)
+    dip["origin"][1] = [10e-9, 0.0, 0.0]
+    dip["omega0"][:] = 2 * math.pi * 200e12
+    dip["d0"][0] = E * 1e-12
+    dt = 9e-9 / C                                  # c dt = 9 nm < 10 nm
+    O.dipole_run(dip, [0, 2], dt, 2)
+    dip["motion_amp"][1] = [0.0, 1.5e-9, 0.0]      # closest approach 8.5 nm < c dt
+    dip["motion_omega"][1] = 1e12
+    with pytest.raises(O.OracleError):
+        O.dipole_run(dip, [0, 2], dt, 2)
+
+
 def greens_ratios(orientation, R, w0):
     """delta_12/gamma_0 and gamma_12/gamma_0 from the free-space dyadic Green's function
     of App. A (the bracketed form with the k0^2 e^{ikR}/(4 pi R) prefactor; E = G d/eps0),
