@@ -175,9 +175,12 @@ lw_status lw_fields_vjp(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges
 /* ------------------------------------------------------------------------ */
 
 /* One oscillator (the paper's Dipole): two charges +q (mass m1) and -q (mass
- * m2) about the centre of mass `origin`, displaced along the unit axis p by
+ * m2) about the centre of mass R(t), displaced along the unit axis p by
  * r_dip = (d/q) p (Eqs. (r_1), (r_2)); d0 is the signed initial moment along p
- * (C m).  Layout: 88 bytes. */
+ * (C m).  The centre of mass is fixed at `origin`, or moves (Sec. 4.3, moving
+ * dipoles) as R(t) = origin + motion_amp cos(motion_omega t + motion_phase)
+ * for all t, before t = 0 as well; its drive field is taken at R(t) and its
+ * charges ride on R(t).  Layout: 128 bytes. */
 typedef struct {
     double origin[3];
     double axis[3];
@@ -185,6 +188,10 @@ typedef struct {
     double q;          /* C, > 0 */
     double m1, m2;     /* kg    */
     double d0;         /* C m   */
+    double motion_amp[3];   /* m; all 0: fixed origin                    */
+    double motion_omega;    /* rad/s, nonzero when motion_amp is;
+                               motion_omega |motion_amp| < c / 10         */
+    double motion_phase;    /* rad                                        */
 } lw_dipole;
 
 enum { LW_DT_STRICT = 0, LW_DT_EXTRAPOLATE = 1 };

@@ -482,6 +482,9 @@ int or_dipole_run(int n_dip, const double *origin, const double *axis, const dou
         return OR_E_INVALID;
     for (inst = 0; inst < n_inst; ++inst)
         if (inst_off[inst + 1] < inst_off[inst]) return OR_E_INVALID;
+    if (mamp)
+        for (i = 0; i < n_dip; ++i)       /* a moving origin needs a frequency; a fixed offset belongs in origin */
+            if (norm3(&mamp[i * 3]) > 0.0 && momega[i] == 0.0) return OR_E_INVALID;
     if (policy == OR_DT_STRICT) {
         /* Sec. 3.2: radiation must not reach another dipole within one step */
         for (inst = 0; inst < n_inst; ++inst) {

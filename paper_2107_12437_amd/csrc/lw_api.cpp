@@ -91,6 +91,10 @@ lw_status ensure_work(lw_ctx *ctx, size_t bytes, hipStream_t s)
     return LW_OK;
 }
 
+// How far a dipole's origin strays from its mean position (0 when fixed; a
+// nonzero amplitude needs a nonzero frequency).
+double motion_reach(const lw_dipole &D) { return norm3(D.motion_amp); }
+
 lw_status ensure_work2(lw_ctx *ctx, size_t bytes, hipStream_t s)
 {
     if (bytes <= ctx->work2_cap) return LW_OK;
@@ -467,7 +471,10 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
         const lw_dipole &D = h_dip[i];
         if (!finite3(D.origin) || !unit3(D.axis) || !(D.omega0 > 0.0) || !std::isfinite(D.omega0) ||
             !(D.q > 0.0) || !std::isfinite(D.q) || !(D.m1 > 0.0) || !(D.m2 > 0.0) || !std::isfinite(D.m1) ||
-            !std::isfinite(D.m2) || !std::isfinite(D.d0))
+            !std::isfinite(D.m2) || !std::isfinite(D.d0) || !finite3(D.motion_amp) ||
+            !std::isfinite(D.motion_omega) || !std::isfinite(D.motion_phase) ||
+            !(std::fabs(D.motion_omega) * norm3(D.motion_amp) < 0.1 * C_LIGHT) ||
+            (norm3(D.motion_amp) > 0.0 && D.motion_omega == 0.0))
             return fail(LW_E_INVALID, "lw_dipole_run: bad parameters for dipole " + std::to_string(i));
     }
     // separations inside each instance: distinct origins, the dt rule, and the
@@ -483,11 +490,13 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
                 const double d[3] = {h_dip[a].origin[0] - h_dip[b].origin[0], h_dip[a].origin[1] - h_dip[b].origin[1],
                                      h_dip[a].origin[2] - h_dip[b].origin[2]};
                 const double r = norm3(d);
-                if (!(r > 0.0)) return fail(LW_E_INVALID, "lw_dipole_run: two dipoles share an origin");
-                if (opts->dt_policy == LW_DT_STRICT && !(C_LIGHT * dt < r))
+                // moving origins (Sec. 4.3) stay within their amplitudes of the mean position
+                const double swing = motion_reach(h_dip[a]) + motion_reach(h_dip[b]);
+                if (!(r - swing > 0.0)) return fail(LW_E_INVALID, "lw_dipole_run: two dipoles can share an origin");
+                if (opts->dt_policy == LW_DT_STRICT && !(C_LIGHT * dt < r - swing))
                     return fail(LW_E_DT_TOO_LARGE, "lw_dipole_run: c*dt is not below the separation of dipoles " +
                                                        std::to_string(a) + " and " + std::to_string(b));
-                max_sep = std::max(max_sep, r);
+                max_sep = std::max(max_sep, r + swing);
             }
     }
     // depth: the longest retarded time (plus the charges' own excursion) in
@@ -642,6 +651,9 @@ lw_status lw_dipole_run_vjp(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, 
     int max_n = 0;
     for (int k = 0; k < n_inst; ++k) max_n = std::max(max_n, h_inst_off[k + 1] - h_inst_off[k]);
     if (max_n > 1024) return fail(LW_E_INVALID, "lw_dipole_run_vjp: instances of more than 1024 dipoles");
+    for (int i = 0; i < n_dip; ++i)
+        if (motion_reach(h_dip[i]) > 0.0)
+            return fail(LW_E_INVALID, "lw_dipole_run_vjp: moving dipoles have no adjoint here");
     if (n_det * (int64_t)n_snap > ((int64_t)1 << 36)) return fail(LW_E_INVALID, "lw_dipole_run_vjp: detector too large");
     LW_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;

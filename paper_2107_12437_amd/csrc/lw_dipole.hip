@@ -43,6 +43,13 @@ __global__ void dipole_prep_kernel(const lw_dipole *__restrict__ in, int n, DipD
     o.cfm = -D.m1 / M / D.q;
     o.vfac = fmax(D.m1, D.m2) / M / D.q;
     o.d0 = D.d0;
+    const double am = sqrt(D.motion_amp[0] * D.motion_amp[0] + D.motion_amp[1] * D.motion_amp[1] +
+                           D.motion_amp[2] * D.motion_amp[2]);
+    const bool moves = am > 0.0;                  // the host requires motion_omega != 0 then
+    for (int k = 0; k < 3; ++k) o.mamp[k] = moves ? D.motion_amp[k] : 0.0;
+    o.mw = moves ? D.motion_omega : 0.0;
+    o.mph = moves ? D.motion_phase : 0.0;
+    o.mspeed = moves ? fabs(D.motion_omega) * am : 0.0;
     dev[i] = o;
 }
 
@@ -160,19 +167,113 @@ __device__ __forceinline__ double drive_field(const DipLds &Si, const DipLds &Sj
     return o[4] * Si.px + o[5] * Si.py + o[6] * Si.pz;
 }
 
+// Retarded time of the charge at offset cf d(t') p_j of a moving source j seen
+// from X at time base * dt: the root of c tau = |X - R_j(t') - cf d(t') p_j|,
+// t' = t - tau, with R_j(t') = O_j + m_j cos(w t' + phi).  The same iteration
+// and stopping rule as retarded_hist, with the origin's velocity and
+// acceleration in the slope and the bound on g''.  Returns tau; h holds the
+// stored state at the root and Ro, Vo, Ao the origin's position, velocity and
+// acceleration there.
+__device__ double retarded_hist_moving(const Hist &H, int j, const DipLds &Sj, const double X[3], double cf,
+                                       int64_t nstep, double base, double tau, double tau_hi, int max_iter,
+                                       double h[3], double Ro[3], double Vo[3], double Ao[3], uint32_t &err)
+{
+    const double tol = 4.0 * 2.220446049250313e-16;
+    const double O[3] = {Sj.ox, Sj.oy, Sj.oz};
+    const double m[3] = {Sj.mx, Sj.my, Sj.mz};
+    const double p[3] = {Sj.px, Sj.py, Sj.pz};
+    const double am = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+    Bracket b(0.0, tau_hi);
+    bool ok = false;
+    auto origin = [&](double s) {
+        double sn, c;
+        sincos(Sj.mw * (s * H.dt) + Sj.mph, &sn, &c);
+        for (int k = 0; k < 3; ++k) {
+            Ro[k] = O[k] + m[k] * c;
+            Vo[k] = -Sj.mw * m[k] * sn;
+            Ao[k] = -Sj.mw * Sj.mw * m[k] * c;
+        }
+    };
+    for (int it = 0; it < max_iter; ++it) {
+        const double s = base - tau * H.inv_dt;
+        double slope;
+        int region;
+        hist_at(H, j, Sj.d0, nstep, s, h, slope, region, err);
+        origin(s);
+        const double rho = cf * h[0];
+        double Rv[3], vel[3];
+        for (int k = 0; k < 3; ++k) {
+            Rv[k] = X[k] - Ro[k] - rho * p[k];
+            vel[k] = Vo[k] + cf * slope * p[k];                 // d/dt' of the charge position
+        }
+        double D, iD;
+        root_rsqrt<true>(fmax(Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2], 1e-300), D, iD);
+        const double dD = (Rv[0] * vel[0] + Rv[1] * vel[1] + Rv[2] * vel[2]) * iD;
+        bool free_step;
+        const double tn = halley_step(tau, D, dD, 0.0, b, free_step);
+        ok = converged(tn, tau, tol, b);
+        if (ok) break;
+        const double st = tn - tau;
+        const double sn = base - tn * H.inv_dt;
+        const bool same_seg = (region == 1) ? (floor(sn) == floor(s) && sn < (double)nstep)
+                                            : (region == 2 ? sn >= (double)nstep : sn < 0.0);
+        const double v2 = vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2];
+        const double acc = Sj.mw * Sj.mw * am + ((region == 2) ? fabs(cf * h[2]) : 0.0);
+        tau = tn;
+        if (free_step && same_seg && (v2 + acc * D) * (st * st) <= 0.5 * tol * tn * D * (C_LIGHT - sqrt(v2))) {
+            double sl;
+            int rg;
+            hist_at(H, j, Sj.d0, nstep, sn, h, sl, rg, err);
+            origin(sn);
+            ok = true;
+            break;
+        }
+    }
+    if (!ok) err |= 2u;
+    return tau;
+}
+
 // p_i . E of charge (cf, q_signed) of source dipole j seen at the origin of
-// target i at time (nstep + theta) dt.
+// target i at time (nstep + theta) dt.  Moving origins (Sec. 4.3): the field is
+// taken at the target's origin at that time, and the source's charges ride on
+// its origin at the retarded time.
 __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double cf, double kq,
                              int64_t nstep, double theta, int max_iter, uint32_t &err)
 {
-    const double dx = Si.ox - Sj.ox, dy = Si.oy - Sj.oy, dz = Si.oz - Sj.oz;
-    const double L2 = dx * dx + dy * dy + dz * dz;
-    const double L = sqrt(L2);
-    const double sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;     // Delta . p_j
-    double h[3];
-    retarded_hist(H, j, Sj.d0, nstep, (double)nstep + theta, L2, sD, cf, L * INV_C, 2.0 * L * INV_C, max_iter, h,
-                  err);
-    return drive_field(Si, Sj, dx, dy, dz, cf, kq, h);
+    const double base = (double)nstep + theta;
+    double X[3];
+    origin_at(Si, base * H.dt, X);
+    if (Sj.mw == 0.0) {
+        const double dx = X[0] - Sj.ox, dy = X[1] - Sj.oy, dz = X[2] - Sj.oz;
+        const double L2 = dx * dx + dy * dy + dz * dz;
+        const double L = sqrt(L2);
+        const double sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;     // Delta . p_j
+        double h[3];
+        retarded_hist(H, j, Sj.d0, nstep, base, L2, sD, cf, L * INV_C, 2.0 * L * INV_C, max_iter, h, err);
+        return drive_field(Si, Sj, dx, dy, dz, cf, kq, h);
+    }
+    // moving source: start from the present separation of the origins; the
+    // bracket's upper end covers the origin's whole swing
+    const double dx = X[0] - Sj.ox, dy = X[1] - Sj.oy, dz = X[2] - Sj.oz;
+    const double reach = sqrt(dx * dx + dy * dy + dz * dz) + sqrt(Sj.mx * Sj.mx + Sj.my * Sj.my + Sj.mz * Sj.mz);
+    double h[3], Ro[3], Vo[3], Ao[3];
+    retarded_hist_moving(H, j, Sj, X, cf, nstep, base, reach * INV_C, 2.0 * reach * INV_C, max_iter, h, Ro, Vo, Ao,
+                         err);
+    Kin k;
+    const double rho = cf * h[0];
+    const double p[3] = {Sj.px, Sj.py, Sj.pz};
+    for (int c = 0; c < 3; ++c) {
+        k.R[c] = X[c] - Ro[c] - rho * p[c];
+        k.v[c] = Vo[c] + cf * h[1] * p[c];
+        k.a[c] = Ao[c] + cf * h[2] * p[c];
+    }
+    k.tp = 0.0;
+    k.cph = 1.0;
+    k.sph = 0.0;
+    k.flags = 0u;
+    double o[10];
+    lw_terms<double>(k, kq, F_TOTAL, o);
+    return o[4] * Si.px + o[5] * Si.py + o[6] * Si.pz;
 }
 
 // Drive fields of all targets of the instance at stage times theta in
@@ -238,7 +339,7 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
 
     for (int j = tid; j < n; j += BLOCK) {
         const DipDev &D = dev[i0 + j];
-        S[j] = DipLds{D.origin[0], D.origin[1], D.origin[2], D.axis[0], D.axis[1], D.axis[2], D.cfp, D.cfm, D.d0};
+        S[j] = dip_lds(D);
         qv[j] = D.q;
     }
     if (tid == 0) s_err = 0u;
@@ -268,13 +369,14 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
     __syncthreads();
 
     // constants of the dipole this thread advances (the first BLOCK of the instance)
-    double own_w2 = 0.0, own_g = 0.0, own_f = 0.0, own_vfac = 0.0, own_ie = 0.0;
+    double own_w2 = 0.0, own_g = 0.0, own_f = 0.0, own_vfac = 0.0, own_ie = 0.0, own_ms = 0.0;
     if (tid < n) {
         const DipDev &D = dev[i0 + tid];
         own_w2 = D.omega0 * D.omega0;
         own_g = D.gamma0;
         own_f = D.f;
         own_vfac = D.vfac;
+        own_ms = D.mspeed;
         own_ie = 0.5 / D.f;
     }
     const double thetas[2] = {0.5, 1.0};
@@ -282,13 +384,14 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
         drive_all<BLOCK>(H, S, qv, n, nstep, thetas, 2, Enew, max_iter, err);
         __syncthreads();
         for (int i = tid; i < n; i += BLOCK) {
-            double w2 = own_w2, g = own_g, f = own_f, vfac = own_vfac, ie = own_ie;
+            double w2 = own_w2, g = own_g, f = own_f, vfac = own_vfac, ie = own_ie, ms = own_ms;
             if (i != tid) {
                 const DipDev &D = dev[i0 + i];
                 w2 = D.omega0 * D.omega0;
                 g = D.gamma0;
                 f = D.f;
                 vfac = D.vfac;
+                ms = D.mspeed;
                 ie = 0.5 / D.f;
             }
             const double *h = ringp + ((int64_t)(nstep & (ring - 1)) * n + i) * 3;
@@ -311,7 +414,7 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
             hn[2] = an;
             Ecur[i] = Ee;
             if (!(isfinite(dn) && isfinite(vn) && isfinite(an))) err |= ERR_NONFINITE;
-            if (max_vel > 0.0 && vfac * fabs(vn) > max_vel) err |= ERR_VELOCITY;
+            if (max_vel > 0.0 && ms + vfac * fabs(vn) > max_vel) err |= ERR_VELOCITY;
             if ((nstep + 1) % stride == 0) {
                 const int64_t row = (nstep + 1) / stride;
                 const int64_t o = row * n_dip + i0 + i;
@@ -424,7 +527,7 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             hn[2] = an;
             Ecur[gi] = Ee;
             if (!(isfinite(dn) && isfinite(vn) && isfinite(an))) err |= ERR_NONFINITE;
-            if (max_vel > 0.0 && D.vfac * fabs(vn) > max_vel) err |= ERR_VELOCITY;
+            if (max_vel > 0.0 && D.mspeed + D.vfac * fabs(vn) > max_vel) err |= ERR_VELOCITY;
             if ((nstep + 1) % stride == 0) {
                 const int64_t o = (nstep + 1) / stride * n_dip + gi;
                 out_d[o] = dn;

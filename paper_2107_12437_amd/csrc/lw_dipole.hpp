@@ -17,6 +17,9 @@ struct DipDev {
     double cfm;      // offset of the -q charge per unit moment: -m1 / (m1 + m2) / q  (Eq. (r_2))
     double vfac;     // charge speed per unit d_dot: max(m1, m2) / (m1 + m2) / q
     double d0;
+    double mamp[3];  // origin motion: origin + mamp cos(mw t + mph) (Sec. 4.3); mw = 0 when fixed
+    double mw, mph;
+    double mspeed;   // largest origin speed, mw |mamp|
 };
 
 // Per-dipole constants of the instance, staged in LDS.
@@ -25,7 +28,22 @@ struct DipLds {
     double px, py, pz;
     double cfp, cfm;
     double d0;
+    double mx, my, mz, mw, mph;   // origin motion (mw = 0: fixed origin)
 };
+
+// Origin of a dipole at time t (fixed, or moving as O + m cos(w t + phi)).
+__device__ __forceinline__ void origin_at(const DipLds &S, double t, double R[3])
+{
+    R[0] = S.ox;
+    R[1] = S.oy;
+    R[2] = S.oz;
+    if (S.mw != 0.0) {
+        const double c = cos(S.mw * t + S.mph);
+        R[0] += S.mx * c;
+        R[1] += S.my * c;
+        R[2] += S.mz * c;
+    }
+}
 
 // Stored kinematics (d, d_dot, d_ddot) of source j at s steps after t = 0 (s
 // real).  Static at d0 before t = 0 (Sec. 3.2); linear interpolation between
@@ -41,7 +59,8 @@ struct Hist {
 
 __device__ __forceinline__ DipLds dip_lds(const DipDev &D)
 {
-    return DipLds{D.origin[0], D.origin[1], D.origin[2], D.axis[0], D.axis[1], D.axis[2], D.cfp, D.cfm, D.d0};
+    return DipLds{D.origin[0], D.origin[1], D.origin[2], D.axis[0], D.axis[1], D.axis[2], D.cfp, D.cfm, D.d0,
+                  D.mamp[0], D.mamp[1], D.mamp[2], D.mw, D.mph};
 }
 
 enum { ERR_HISTORY = 1u, ERR_NOCONV = 2u, ERR_VELOCITY = 4u, ERR_NONFINITE = 8u };

@@ -70,7 +70,8 @@ class Opts(ct.Structure):
 
 class Dipole(ct.Structure):
     _fields_ = [("origin", ct.c_double * 3), ("axis", ct.c_double * 3), ("omega0", ct.c_double),
-                ("q", ct.c_double), ("m1", ct.c_double), ("m2", ct.c_double), ("d0", ct.c_double)]
+                ("q", ct.c_double), ("m1", ct.c_double), ("m2", ct.c_double), ("d0", ct.c_double),
+                ("motion_amp", ct.c_double * 3), ("motion_omega", ct.c_double), ("motion_phase", ct.c_double)]
 
 
 class RunOpts(ct.Structure):
@@ -195,6 +196,10 @@ def pack_dipoles(dipoles: dict):
         d.m1 = float(dipoles["m1"][i])
         d.m2 = float(dipoles["m2"][i])
         d.d0 = float(dipoles["d0"][i])
+        if "motion_amp" in dipoles:
+            d.motion_amp[:] = [float(v) for v in dipoles["motion_amp"][i]]
+            d.motion_omega = float(dipoles["motion_omega"][i])
+            d.motion_phase = float(dipoles["motion_phase"][i])
     return arr, n
 
 

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     assert ct.sizeof(lw.Traj) == 144
-    assert ct.sizeof(lw.Dipole) == 88
+    assert ct.sizeof(lw.Dipole) == 128
     assert ct.sizeof(lw.Opts) == 24
     assert ct.sizeof(lw.RunOpts) == 32
 

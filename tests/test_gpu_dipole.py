@@ -190,3 +190,76 @@ def test_stepped_matches_persistent_through_graph_replays():
         assert (np.abs(a[k] - b[k]) / scale).max() <= 1e-12, k
     sc = single_charge_scale(w)[None, :]
     assert (np.abs(a["Ed"] - b["Ed"]) / sc).max() <= 1e-14
+
+
+def moving_workload(n, steps, seed, extra_static_pair=True):
+    """A cluster of n dipoles whose origins oscillate (amplitudes 0.1-0.5 nm along seeded
+    directions, 10-100 THz, seeded phases; Sec. 4.3), plus a fixed pair as a second
+    instance; dt = T0/200."""
+    rng = I.rng_for(seed)
+    dip = I.cluster_dipoles(rng, n, 15e-9, 10e-9, 2 * math.pi * 200e12, 0.01, True)
+    dip["motion_amp"][:] = I.unit_sphere(rng, n) * rng.uniform(0.1e-9, 0.5e-9, size=(n, 1))
+    dip["motion_omega"][:] = 2 * math.pi * rng.uniform(10e12, 100e12, size=n)
+    dip["motion_phase"][:] = rng.uniform(0, 2 * math.pi, size=n)
+    parts, off = [dip], [0, n]
+    if extra_static_pair:
+        pair = I.empty_dipoles(2)
+        pair["origin"][:] = [[80e-9, 0, 0], [92e-9, 0, 0]]
+        pair["axis"][:] = [[0, 1.0, 0], [0, 1.0, 0]]
+        pair["omega0"][:] = 2 * math.pi * 200e12
+        pair["d0"][:] = [I.E_CHARGE * 1e-12, 0.0]
+        parts.append(pair)
+        off.append(n + 2)
+    return {"dipoles": I.concat_dipoles(parts), "inst_off": np.array(off, np.int32),
+            "dt": 1 / 200e12 / 200, "steps": steps}
+
+
+@pytest.mark.parametrize("stepped_min_n", [0, 2])
+def test_moving_dipoles_parity(stepped_min_n):
+    """Moving dipoles on the persistent path (default) and forced onto the stepped path,
+    400 steps, strict policy, against the oracle."""
+    w = moving_workload(6, 400, 97)
+    got = gpu_run(w, "strict", stepped_min_n=stepped_min_n)
+    ref = oracle_run(w, "strict")
+    assert_state_close(got, ref, w, what=f"moving (stepped_min_n={stepped_min_n})")
+    # the motion matters: the fixed-origin run differs well above the tolerance
+    fixed = dict(w, dipoles={k: np.array(v, copy=True) for k, v in w["dipoles"].items()})
+    fixed["dipoles"]["motion_amp"][:] = 0.0
+    ref_fixed = oracle_run(fixed, "strict")
+    scale = single_charge_scale(w)[None, :]
+    assert (np.abs(ref_fixed["Ed"] - ref["Ed"]) / scale).max() > 1e3 * TOL_DRIVE
+
+
+def test_moving_close_pair_extrapolates():
+    """Two moving dipoles 3 nm apart (below c dt), 600 steps with the Taylor step past the
+    newest sample."""
+    dip = I.empty_dipoles(2)
+    dip["origin"][:] = [[0, 0, 0], [3e-9, 0, 0]]
+    dip["axis"][:] = [[0, 1.0, 0], [0, 0.6, 0.8]]
+    dip["omega0"][:] = 2 * math.pi * 200e12
+    dip["d0"][:] = [I.E_CHARGE * 1e-12, 0.0]
+    dip["motion_amp"][:] = [[0.2e-9, 0, 0], [0, 0, 0.3e-9]]
+    dip["motion_omega"][:] = [2 * math.pi * 50e12, 2 * math.pi * 70e12]
+    dip["motion_phase"][:] = [0.0, 1.0]
+    w = {"dipoles": dip, "inst_off": np.array([0, 2], np.int32), "dt": 1 / 200e12 / 200, "steps": 600}
+    got = gpu_run(w, "extrapolate")
+    ref = oracle_run(w, "extrapolate")
+    assert_state_close(got, ref, w, what="moving close pair")
+
+
+def test_moving_dipoles_are_checked():
+    import torch
+    from paper_2107_12437_amd import lw
+    w = moving_workload(4, 10, 98, extra_static_pair=False)
+    bad = {k: np.array(v, copy=True) for k, v in w["dipoles"].items()}
+    bad["motion_omega"][1] = 0.0                     # an amplitude without a frequency
+    with pytest.raises(lw.LWError):
+        lw.dipole_run(bad, w["inst_off"], w["dt"], 10)
+    close = {k: np.array(v, copy=True) for k, v in w["dipoles"].items()}
+    close["motion_amp"][1] = [0.0, 0.0, 12e-9]        # the swing brings two origins within c dt
+    with pytest.raises(lw.LWError):
+        lw.dipole_run(close, w["inst_off"], w["dt"], 10)
+    pts = torch.zeros((3, 4), dtype=torch.float64, device="cuda")
+    pts[2] = 1e-7
+    with pytest.raises(lw.LWError):                  # no adjoint for moving origins
+        lw.dipole_run_vjp(w["dipoles"], w["inst_off"], w["dt"], 10, pts, [5 * w["dt"]])
