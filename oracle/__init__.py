@@ -52,7 +52,7 @@ def lib():
                                 ct.c_double, dp, ct.POINTER(ct.c_uint32)]
         L.or_dipole_run.argtypes = [ct.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp, ct.c_int,
                                     ct.POINTER(ct.c_int32), ct.c_double, ct.c_int64, ct.c_int,
-                                    ct.c_double, ct.c_int64, dp, dp, dp, dp, dp]
+                                    ct.c_double, ct.c_int64, dp, dp, dp, dp, dp, dp, dp]
         L.or_dipole_fields.argtypes = [ct.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, ct.c_double, ct.c_int64, dp,
                                        dp, ct.c_int64, dp, ct.c_int, dp]
         _lib = L
@@ -142,14 +142,14 @@ def fields(charges: dict, points, times, kind: int = TOTAL, mask_radius: float =
 def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: int = DT_STRICT,
                max_vel: float = 299792458.0 / 100, out_stride: int = 1, want_hist: bool = False):
     """Runs Algorithm 1 on independent instances.  Returns dict of [n_out][n_dip] arrays
-    d, d_dot, energy, Ed (and hist [(steps+1)][n_dip][3] when asked).  Optional keys
+    d, d_dot, energy, Ed, W_abs, W_rad (and hist [(steps+1)][n_dip][3] when asked).  Optional keys
     motion_amp [n][3], motion_omega, motion_phase move the origins as
     origin + motion_amp cos(motion_omega t + motion_phase) (Sec. 4.3)."""
     dip = {k: _f64(v) for k, v in dipoles.items()}
     n = len(dip["omega0"])
     off = np.ascontiguousarray(inst_off, dtype=np.int32)
     n_out = steps // out_stride + 1
-    res = {k: np.empty((n_out, n)) for k in ("d", "d_dot", "energy", "Ed")}
+    res = {k: np.empty((n_out, n)) for k in ("d", "d_dot", "energy", "Ed", "W_abs", "W_rad")}
     hist = np.empty((steps + 1, n, 3)) if want_hist else None
     mamp, mom, mph = _motion(dip, n)
     st = lib().or_dipole_run(n, _dp(dip["origin"]), _dp(dip["axis"]), _dp(dip["omega0"]), _dp(dip["q"]),
@@ -158,8 +158,8 @@ def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: int = DT_
                              _dp(mph) if mph is not None else None, len(off) - 1,
                              off.ctypes.data_as(ct.POINTER(ct.c_int32)), float(dt), int(steps),
                              int(policy), float(max_vel), int(out_stride), _dp(res["d"]),
-                             _dp(res["d_dot"]), _dp(res["energy"]), _dp(res["Ed"]),
-                             _dp(hist) if hist is not None else None)
+                             _dp(res["d_dot"]), _dp(res["energy"]), _dp(res["Ed"]), _dp(res["W_abs"]),
+                             _dp(res["W_rad"]), _dp(hist) if hist is not None else None)
     if st:
         raise OracleError(st, "dipole run")
     if hist is not None:

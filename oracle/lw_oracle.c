@@ -465,16 +465,23 @@ static int lo_drive(const or_lo *L, int i, int i_lo, int i_hi, int64_t n, double
  * t_{n+1} is reused as the first stage of the next step.  Sample 0 is
  * (d0, 0, d_ddot(0)).
  * Outputs every out_stride steps (n_out = steps/out_stride + 1 rows of n_dip):
- * moment d, d_dot, energy of Eq. (dipoleE), drive field E_d.  Any may be NULL. */
+ * moment d, d_dot, energy of Eq. (dipoleE), drive field E_d, and since t = 0
+ * the work done on the dipole by its drive field (integral of E_d d_dot) and
+ * the energy it radiated (integral of the Larmor power |d_ddot|^2/(6 pi eps0
+ * c^3)), both by the trapezoid rule over steps (Sec. 2.5: the sum over dipoles
+ * of energy - absorbed + radiated is the conserved W_total).  Any may be NULL. */
 int or_dipole_run(int n_dip, const double *origin, const double *axis, const double *omega0,
                   const double *q, const double *m1, const double *m2, const double *d0,
                   const double *mamp, const double *momega, const double *mphase,
                   int n_inst, const int32_t *inst_off, double dt, int64_t steps, int policy,
                   double max_vel, int64_t out_stride,
-                  double *out_d, double *out_v, double *out_E, double *out_Ed, double *hist_out)
+                  double *out_d, double *out_v, double *out_E, double *out_Ed, double *out_Wabs,
+                  double *out_Wrad, double *hist_out)
 {
     or_lo L;
-    double *mass, *gam, *Ecur, *Emid, *Eend, *ynew;
+    double *mass, *gam, *Ecur, *Emid, *Eend, *ynew, *Wabs, *Wrad;
+    /* Larmor power of a dipole, |d_ddot|^2 / (6 pi eps0 c^3) (Sec. 2.5) */
+    const double KLAR = 1.0 / (6.0 * OR_PI * OR_EPS0 * OR_C * OR_C * OR_C);
     int i, inst, st = OR_OK;
     int64_t n, nstore;
     if (n_dip <= 0 || n_inst <= 0 || inst_off[0] != 0 || inst_off[n_inst] != n_dip || !(dt > 0.0) ||
@@ -514,7 +521,9 @@ int or_dipole_run(int n_dip, const double *origin, const double *axis, const dou
     Emid = (double *)malloc(sizeof(double) * (size_t)n_dip);
     Eend = (double *)malloc(sizeof(double) * (size_t)n_dip);
     ynew = (double *)malloc(sizeof(double) * 2 * (size_t)n_dip);
-    if (!L.hist || !L.coef_p || !L.coef_m || !mass || !gam || !Ecur || !Emid || !Eend || !ynew) {
+    Wabs = (double *)calloc((size_t)n_dip, sizeof(double));
+    Wrad = (double *)calloc((size_t)n_dip, sizeof(double));
+    if (!L.hist || !L.coef_p || !L.coef_m || !mass || !gam || !Ecur || !Emid || !Eend || !ynew || !Wabs || !Wrad) {
         st = OR_E_NOMEM;
         goto done;
     }
@@ -548,6 +557,8 @@ int or_dipole_run(int n_dip, const double *origin, const double *axis, const dou
                 if (out_E) out_E[row * n_dip + i] =
                     mass[i] / (2.0 * q[i] * q[i]) * (omega0[i] * omega0[i] * h[0] * h[0] + h[1] * h[1]);
                 if (out_Ed) out_Ed[row * n_dip + i] = Ecur[i];
+                if (out_Wabs) out_Wabs[row * n_dip + i] = Wabs[i];
+                if (out_Wrad) out_Wrad[row * n_dip + i] = Wrad[i];
             }
         }
         if (n == steps) break;
@@ -578,10 +589,15 @@ int or_dipole_run(int n_dip, const double *origin, const double *axis, const dou
         }
         for (i = 0; i < n_dip; ++i) {
             double *h = &L.hist[((n + 1) * n_dip + i) * 3];
+            const double *ho = &L.hist[(n * n_dip + i) * 3];
             double speed;
             h[0] = ynew[2 * i];
             h[1] = ynew[2 * i + 1];
             h[2] = q[i] * q[i] / mass[i] * Eend[i] - gam[i] * h[1] - omega0[i] * omega0[i] * h[0];
+            /* energy bookkeeping of Sec. 2.5, trapezoid rule over the step: work done
+               by the drive field (E_d d_dot) and the Larmor power of the dipole */
+            Wabs[i] += 0.5 * dt * (ho[1] * Ecur[i] + h[1] * Eend[i]);
+            Wrad[i] += 0.5 * dt * KLAR * (ho[2] * ho[2] + h[2] * h[2]);
             Ecur[i] = Eend[i];
             /* the charge speeds are at most |origin velocity| + |coef| * |d_dot| / q;
                Sec. 3.2 raises above max_vel */
@@ -594,7 +610,7 @@ int or_dipole_run(int n_dip, const double *origin, const double *axis, const dou
     if (hist_out) memcpy(hist_out, L.hist, sizeof(double) * 3 * (size_t)nstore * (size_t)n_dip);
 done:
     free(L.hist); free(L.coef_p); free(L.coef_m); free(mass); free(gam);
-    free(Ecur); free(Emid); free(Eend); free(ynew);
+    free(Ecur); free(Emid); free(Eend); free(ynew); free(Wabs); free(Wrad);
     return st;
 }
 

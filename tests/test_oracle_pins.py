@@ -651,6 +651,32 @@ def test_energy_balance_identity():
         assert abs(dE - work) <= 1e-4 * scale, (i, dE, work, scale)
 
 
+def test_total_energy_is_conserved():
+    """Sec. 2.5: W_total = sum_i (energy_i - W_abs,i + integral of the Larmor power
+    |d_ddot_i|^2 / (6 pi eps0 c^3)) is constant.  With the Larmor form it holds up to the
+    cycle-scale difference from the radiation-reaction term of Eq. (LO_equation) and the
+    quadrature: to 1e-7 of the initial energy and 2 % of the radiated energy here (a wrong
+    Larmor prefactor or a flipped sign of the absorbed work breaks both by far)."""
+    w0 = 2 * math.pi * 200e12
+    dt = 1 / 200e12 / 1000
+    dip = I.empty_dipoles(3)
+    dip["origin"][1] = [12e-9, 0, 0]
+    dip["origin"][2] = [0, 15e-9, 4e-9]
+    dip["axis"][2] = [0, 0.6, 0.8]
+    dip["omega0"][:] = w0 * np.array([1.0, 1.001, 0.999])
+    dip["d0"][:] = E * 1e-12 * np.array([1.0, -0.5, 0.3])
+    r = O.dipole_run(dip, [0, 3], dt, 20000)
+    W = (r["energy"] - r["W_abs"] + r["W_rad"]).sum(axis=1)
+    dev = np.abs(W - W[0]).max()
+    assert dev <= 1e-7 * r["energy"][0].sum(), dev / r["energy"][0].sum()
+    assert dev <= 0.02 * r["W_rad"][-1].sum(), dev / r["W_rad"][-1].sum()
+    # the radiated energy is the Larmor integral of the stored d_ddot (trapezoid)
+    h = O.dipole_run(dip, [0, 3], dt, 200, want_hist=True)["hist"]
+    P = h[:, :, 2] ** 2 / (6 * math.pi * EPS0 * C ** 3)
+    Wr = dt * (P.sum(axis=0) - 0.5 * (P[0] + P[-1]))
+    np.testing.assert_allclose(O.dipole_run(dip, [0, 3], dt, 200)["W_rad"][-1], Wr, rtol=1e-12)
+
+
 def test_prony_recovers_damped_cosine():
     dt = 1e-17
     t = np.arange(20000) * dt
