@@ -218,17 +218,23 @@ typedef struct {
  * steps; static at d0 before t = 0).  All dipoles advance together.
  * Outputs (device FP64, [steps/out_stride + 1][n_dip], row k = step k*stride):
  *   d_moment  moment d along the axis (required)
- *   d_ddot    d d/dt                    (nullable)
+ *   d_dot     d d/dt                    (nullable)
  *   d_energy  energy of Eq. (dipoleE)   (nullable)
  *   d_drive   drive field E_d           (nullable)
+ *   d_wabs    work done on the dipole by its drive field since t = 0, the
+ *             integral of E_d d_dot (nullable)
+ *   d_wrad    energy radiated since t = 0, the integral of the Larmor power
+ *             |d_ddot|^2 / (6 pi eps0 c^3) (nullable)
+ *   (both by the trapezoid rule over steps; the sum over the dipoles of an
+ *   instance of energy - wabs + wrad is the conserved W_total of Sec. 2.5)
  * Small instances run concurrently with the stepped ones on a second stream of
  * the context that is joined back into `stream` before the call's work ends.
  * Asynchronous: speed-limit, non-finite and history errors are reported by
  * lw_sync_status(). */
 lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
                         int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts,
-                        double *d_moment, double *d_ddot, double *d_energy, double *d_drive,
-                        void *stream);
+                        double *d_moment, double *d_dot, double *d_energy, double *d_drive,
+                        double *d_wabs, double *d_wrad, void *stream);
 
 /* Gradient of a detector objective with respect to the oscillator positions,
  * by a backward-in-time discrete adjoint of the run.  The run is that of

@@ -454,7 +454,8 @@ lw_status lw_fields_vjp(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges
 
 lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
                         int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts, double *d_moment,
-                        double *d_ddot, double *d_energy, double *d_drive, void *stream)
+                        double *d_dot, double *d_energy, double *d_drive, double *d_wabs, double *d_wrad,
+                        void *stream)
 {
     if (!ctx || !opts || !h_dip || !h_inst_off || !d_moment) return fail(LW_E_INVALID, "lw_dipole_run: null argument");
     if (n_dip < 1 || n_inst < 1) return fail(LW_E_INVALID, "lw_dipole_run: need at least one dipole and instance");
@@ -547,7 +548,7 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
     const size_t t64_bytes = align_up(sizeof(int64_t) * (n_tgt + 1), 256);
     const size_t stage_bytes = in_bytes + off_bytes + list_bytes + 3 * t32_bytes + t64_bytes;
     const size_t dev_bytes = align_up(lw::dip_dev_bytes() * (size_t)n_dip, 256);
-    const size_t ecur_bytes = align_up(sizeof(double) * (size_t)n_dip, 256);
+    const size_t ecur_bytes = align_up(sizeof(double) * 3 * (size_t)n_dip, 256);   // E_d(t_n), then 2 energy sums
     const size_t step_bytes = 256;
     const size_t ring_bytes = align_up(sizeof(double) * (size_t)std::max<int64_t>(ring_doubles, 1), 256);
     lw_status st = ensure_work(ctx, stage_bytes + dev_bytes + ecur_bytes + step_bytes + ring_bytes, s);
@@ -598,6 +599,7 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
     lw::DipDev *d_dev = (lw::DipDev *)(work + o);
     o += dev_bytes;
     double *d_Ecur = (double *)(work + o);
+    double *d_W = d_Ecur + n_dip;
     o += ecur_bytes;
     int64_t *d_step = (int64_t *)(work + o);
     o += step_bytes;
@@ -616,17 +618,16 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
         LW_HIP(hipStreamWaitEvent(ctx->side, ctx->join_a, 0));
         small_s = ctx->side;
     }
+    const lw::RunOut out{d_moment, d_dot, d_energy, d_drive, d_wabs, d_wrad, opts->out_stride, n_dip};
     LW_HIP(lw::launch_dipole_instances(d_dev, d_off, d_list, (int)lds_list.size(), max_lds_n, true, nullptr, nullptr,
-                                       ring, steps, opts->out_stride, dt, max_vel, max_iter, d_moment, d_ddot,
-                                       d_energy, d_drive, n_dip, ctx->d_err, small_s));
+                                       ring, steps, dt, max_vel, max_iter, out, ctx->d_err, small_s));
     if (n_tgt > 0) {
         if (!ctx->capture) LW_HIP(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
         if (!ctx->graph_done) LW_HIP(hipEventCreateWithFlags(&ctx->graph_done, hipEventDisableTiming));
         const int chunk = 256;
-        LW_HIP(lw::launch_dipole_steps(d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_tgt_base, (int)n_tgt, d_ring, d_Ecur, d_step,
-                                       ring, steps, opts->out_stride, dt, max_vel, max_iter, d_moment, d_ddot,
-                                       d_energy, d_drive, n_dip, ctx->d_err, chunk, s, ctx->capture, &ctx->graph,
-                                       &ctx->graph_exec));
+        LW_HIP(lw::launch_dipole_steps(d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_tgt_base, (int)n_tgt, d_ring, d_Ecur, d_W,
+                                       d_step, ring, steps, dt, max_vel, max_iter, out, ctx->d_err, chunk, s,
+                                       ctx->capture, &ctx->graph, &ctx->graph_exec));
         LW_HIP(hipEventRecord(ctx->graph_done, s));
     }
     if (both) {
@@ -707,7 +708,8 @@ lw_status lw_dipole_run_vjp(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, 
     // forward run with every step stored
     lw_run_opts fo = *opts;
     fo.out_stride = 1;
-    st = lw_dipole_run(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, steps, &fo, d_D, d_V, nullptr, d_Ed, stream);
+    st = lw_dipole_run(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, steps, &fo, d_D, d_V, nullptr, d_Ed, nullptr, nullptr,
+                       stream);
     if (st != LW_OK) return st;
     // oscillator records, offsets, pair offsets and snapshot times for the adjoint kernels
     st = acquire_stage(ctx, stage_b);

@@ -313,13 +313,11 @@ template <int BLOCK, bool RING_LDS>
 __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__restrict__ dev,
                                                              const int32_t *__restrict__ off,
                                                              const int32_t *__restrict__ inst_list, int ring,
-                                                             int64_t steps, int64_t stride, double dt,
+                                                             int64_t steps, double dt,
                                                              double max_vel, int max_iter,
                                                              double *__restrict__ ring_global,
-                                                             const int64_t *__restrict__ ring_off,
-                                                             double *__restrict__ out_d, double *__restrict__ out_v,
-                                                             double *__restrict__ out_E, double *__restrict__ out_Ed,
-                                                             int n_dip, uint32_t *__restrict__ d_err)
+                                                             const int64_t *__restrict__ ring_off, RunOut out,
+                                                             uint32_t *__restrict__ d_err)
 {
     extern __shared__ double lds[];
     const int inst = inst_list[blockIdx.x];
@@ -328,12 +326,14 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
     const int tid = threadIdx.x;
     if (n <= 0) return;
 
-    // LDS layout: constants, q, Ecur, Emid/Eend, (ring), error word
+    // LDS layout: constants, q, Ecur, Emid/Eend, absorbed and radiated energy, (ring)
     DipLds *S = (DipLds *)lds;
     double *qv = (double *)(S + n);
     double *Ecur = qv + n;
     double *Enew = Ecur + n;                    // [2][n]: mid, end
-    double *ring_lds = Enew + 2 * n;
+    double *Wab = Enew + 2 * n;
+    double *Wra = Wab + n;
+    double *ring_lds = Wra + n;
     double *ringp = RING_LDS ? ring_lds : ring_global + ring_off[blockIdx.x];
     __shared__ uint32_t s_err;
 
@@ -361,10 +361,9 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
         h[1] = 0.0;
         h[2] = D.f * Ecur[i] - D.omega0 * D.omega0 * D.d0;
         const int gi = i0 + i;
-        out_d[gi] = D.d0;
-        if (out_v) out_v[gi] = 0.0;
-        if (out_E) out_E[gi] = D.omega0 * D.omega0 * D.d0 * D.d0 / (2.0 * D.f);
-        if (out_Ed) out_Ed[gi] = Ecur[i];
+        Wab[i] = 0.0;
+        Wra[i] = 0.0;
+        put_row(out, 0, gi, D.d0, 0.0, D.omega0 * D.omega0 * D.d0 * D.d0 / (2.0 * D.f), Ecur[i], 0.0, 0.0);
     }
     __syncthreads();
 
@@ -415,14 +414,13 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
             Ecur[i] = Ee;
             if (!(isfinite(dn) && isfinite(vn) && isfinite(an))) err |= ERR_NONFINITE;
             if (max_vel > 0.0 && ms + vfac * fabs(vn) > max_vel) err |= ERR_VELOCITY;
-            if ((nstep + 1) % stride == 0) {
-                const int64_t row = (nstep + 1) / stride;
-                const int64_t o = row * n_dip + i0 + i;
-                out_d[o] = dn;
-                if (out_v) out_v[o] = vn;
-                if (out_E) out_E[o] = (w2 * dn * dn + vn * vn) * ie;
-                if (out_Ed) out_Ed[o] = Ee;
-            }
+            // energy bookkeeping (Sec. 2.5), trapezoid rule over the step
+            const double wa = Wab[i] + 0.5 * dt * (y1 * Ec + vn * Ee);
+            const double wr = Wra[i] + 0.5 * dt * K_LARMOR * (h[2] * h[2] + an * an);
+            Wab[i] = wa;
+            Wra[i] = wr;
+            if ((nstep + 1) % out.stride == 0)
+                put_row(out, (nstep + 1) / out.stride, i0 + i, dn, vn, (w2 * dn * dn + vn * vn) * ie, Ee, wa, wr);
         }
         if (err) atomicOr(&s_err, err);
         __syncthreads();
@@ -448,13 +446,10 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
                                                         const int32_t *__restrict__ tgt_lo,
                                                         const int32_t *__restrict__ tgt_n,
                                                         const int64_t *__restrict__ ring_base, double *__restrict__ ring,
-                                                        double *__restrict__ Ecur, const int64_t *__restrict__ step_ctr,
-                                                        int kstep, int ring_depth, int64_t stride, double dt,
-                                                        double max_vel,
-                                                        int max_iter, int init, double *__restrict__ out_d,
-                                                        double *__restrict__ out_v, double *__restrict__ out_E,
-                                                        double *__restrict__ out_Ed, int n_dip,
-                                                        uint32_t *__restrict__ d_err)
+                                                        double *__restrict__ Ecur, double *__restrict__ W,
+                                                        const int64_t *__restrict__ step_ctr, int kstep,
+                                                        int ring_depth, double dt, double max_vel, int max_iter,
+                                                        int init, RunOut out, uint32_t *__restrict__ d_err)
 {
     __shared__ double red[2][BLOCK];
     const int tid = threadIdx.x;
@@ -503,10 +498,9 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             h[1] = 0.0;
             h[2] = f * E0 - w2 * D.d0;
             Ecur[gi] = E0;
-            out_d[gi] = D.d0;
-            if (out_v) out_v[gi] = 0.0;
-            if (out_E) out_E[gi] = w2 * D.d0 * D.d0 * (0.5 / f);
-            if (out_Ed) out_Ed[gi] = E0;
+            W[2 * gi] = 0.0;
+            W[2 * gi + 1] = 0.0;
+            put_row(out, 0, gi, D.d0, 0.0, w2 * D.d0 * D.d0 * (0.5 / f), E0, 0.0, 0.0);
         } else {
             const double Em = red[0][0], Ee = red[1][0], Ec = Ecur[gi];
             const double *h = rp + ((int64_t)(nstep & (ring_depth - 1)) * n + i) * 3;
@@ -528,13 +522,13 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             Ecur[gi] = Ee;
             if (!(isfinite(dn) && isfinite(vn) && isfinite(an))) err |= ERR_NONFINITE;
             if (max_vel > 0.0 && D.mspeed + D.vfac * fabs(vn) > max_vel) err |= ERR_VELOCITY;
-            if ((nstep + 1) % stride == 0) {
-                const int64_t o = (nstep + 1) / stride * n_dip + gi;
-                out_d[o] = dn;
-                if (out_v) out_v[o] = vn;
-                if (out_E) out_E[o] = (w2 * dn * dn + vn * vn) * (0.5 / f);
-                if (out_Ed) out_Ed[o] = Ee;
-            }
+            // energy bookkeeping (Sec. 2.5), trapezoid rule over the step
+            const double wa = W[2 * gi] + 0.5 * dt * (y1 * Ec + vn * Ee);
+            const double wr = W[2 * gi + 1] + 0.5 * dt * K_LARMOR * (h[2] * h[2] + an * an);
+            W[2 * gi] = wa;
+            W[2 * gi + 1] = wr;
+            if ((nstep + 1) % out.stride == 0)
+                put_row(out, (nstep + 1) / out.stride, gi, dn, vn, (w2 * dn * dn + vn * vn) * (0.5 / f), Ee, wa, wr);
         }
     }
     if (err) atomicOr(d_err, err);
@@ -551,10 +545,9 @@ __global__ void step_reset_kernel(int64_t *step_ctr)
 }
 
 hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const int32_t *d_tgt_lo, const int32_t *d_tgt_n,
-                               const int64_t *d_ring_base, int n_tgt, double *d_ring, double *d_Ecur, int64_t *d_step,
-                               int ring, int64_t steps, int64_t stride, double dt, double max_vel, int max_iter,
-                               double *d_moment, double *d_ddot, double *d_energy, double *d_drive, int n_dip,
-                               uint32_t *d_err, int graph_chunk, hipStream_t s, hipStream_t cap,
+                               const int64_t *d_ring_base, int n_tgt, double *d_ring, double *d_Ecur, double *d_W,
+                               int64_t *d_step, int ring, int64_t steps, double dt, double max_vel, int max_iter,
+                               const RunOut &out, uint32_t *d_err, int graph_chunk, hipStream_t s, hipStream_t cap,
                                hipGraph_t *graph_out, hipGraphExec_t *exec_out)
 {
     constexpr int B = 256;
@@ -562,8 +555,7 @@ hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const 
     const dim3 grid((unsigned)n_tgt), block(B);
     hipLaunchKernelGGL(step_reset_kernel, dim3(1), dim3(1), 0, s, d_step);
     hipLaunchKernelGGL(lo_step_kernel<B>, grid, block, 0, s, d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_ring_base, d_ring,
-                       d_Ecur, d_step, 0, ring, stride, dt, max_vel, max_iter, 1, d_moment, d_ddot, d_energy,
-                       d_drive, n_dip, d_err);
+                       d_Ecur, d_W, d_step, 0, ring, dt, max_vel, max_iter, 1, out, d_err);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || steps == 0) return e;
     // a chunk of steps is captured once into a graph and replayed: launch k of
@@ -572,8 +564,7 @@ hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const 
     auto enqueue = [&](hipStream_t q, int64_t count) {
         for (int64_t k = 0; k < count; ++k)
             hipLaunchKernelGGL(lo_step_kernel<B>, grid, block, 0, q, d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_ring_base,
-                               d_ring, d_Ecur, d_step, (int)k, ring, stride, dt, max_vel, max_iter, 0, d_moment,
-                               d_ddot, d_energy, d_drive, n_dip, d_err);
+                               d_ring, d_Ecur, d_W, d_step, (int)k, ring, dt, max_vel, max_iter, 0, out, d_err);
         hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(1), 0, q, d_step, count);
     };
     const int64_t chunk = graph_chunk > 0 ? graph_chunk : 0;
@@ -603,42 +594,37 @@ hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const 
 
 int ring_lds_bytes(int n, int ring)
 {
-    return (int)(sizeof(DipLds) * n + sizeof(double) * 4 * n + sizeof(double) * 3 * (size_t)ring * n);
+    return (int)(sizeof(DipLds) * n + sizeof(double) * 6 * n + sizeof(double) * 3 * (size_t)ring * n);
 }
 
 template <int BLOCK>
 static hipError_t launch_lo(bool ring_lds, dim3 grid, size_t shmem, hipStream_t s, const DipDev *d_dev,
-                            const int32_t *d_off, const int32_t *d_list, int ring, int64_t steps, int64_t stride,
-                            double dt, double max_vel, int max_iter, double *d_ring_global,
-                            const int64_t *d_ring_off, double *d_moment, double *d_ddot, double *d_energy,
-                            double *d_drive, int n_dip, uint32_t *d_err)
+                            const int32_t *d_off, const int32_t *d_list, int ring, int64_t steps, double dt,
+                            double max_vel, int max_iter, double *d_ring_global, const int64_t *d_ring_off,
+                            const RunOut &out, uint32_t *d_err)
 {
     if (ring_lds)
         hipLaunchKernelGGL((lo_instances_kernel<BLOCK, true>), grid, dim3(BLOCK), shmem, s, d_dev, d_off, d_list,
-                           ring, steps, stride, dt, max_vel, max_iter, d_ring_global, d_ring_off, d_moment,
-                           d_ddot, d_energy, d_drive, n_dip, d_err);
+                           ring, steps, dt, max_vel, max_iter, d_ring_global, d_ring_off, out, d_err);
     else
         hipLaunchKernelGGL((lo_instances_kernel<BLOCK, false>), grid, dim3(BLOCK), shmem, s, d_dev, d_off,
-                           d_list, ring, steps, stride, dt, max_vel, max_iter, d_ring_global, d_ring_off,
-                           d_moment, d_ddot, d_energy, d_drive, n_dip, d_err);
+                           d_list, ring, steps, dt, max_vel, max_iter, d_ring_global, d_ring_off, out, d_err);
     return hipGetLastError();
 }
 
 hipError_t launch_dipole_instances(const DipDev *d_dev, const int32_t *d_off, const int32_t *d_list, int n_list,
                                    int max_n, bool ring_lds, const int64_t *d_ring_off, double *d_ring_global,
-                                   int ring, int64_t steps, int64_t stride, double dt, double max_vel,
-                                   int max_iter, double *d_moment, double *d_ddot, double *d_energy,
-                                   double *d_drive, int n_dip, uint32_t *d_err, hipStream_t s)
+                                   int ring, int64_t steps, double dt, double max_vel, int max_iter,
+                                   const RunOut &out, uint32_t *d_err, hipStream_t s)
 {
     if (n_list <= 0) return hipSuccess;
     const size_t shmem = (size_t)ring_lds_bytes(max_n, ring_lds ? ring : 0);
     const dim3 grid((unsigned)n_list);
     if (max_n <= 8)
-        return launch_lo<64>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, stride, dt, max_vel,
-                             max_iter, d_ring_global, d_ring_off, d_moment, d_ddot, d_energy, d_drive, n_dip,
-                             d_err);
-    return launch_lo<256>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, stride, dt, max_vel,
-                          max_iter, d_ring_global, d_ring_off, d_moment, d_ddot, d_energy, d_drive, n_dip, d_err);
+        return launch_lo<64>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel, max_iter,
+                             d_ring_global, d_ring_off, out, d_err);
+    return launch_lo<256>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel, max_iter,
+                          d_ring_global, d_ring_off, out, d_err);
 }
 
 }  // namespace lw

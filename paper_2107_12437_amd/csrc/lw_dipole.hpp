@@ -3,6 +3,7 @@
 #pragma once
 
 #include "lw_device.hpp"
+#include "lw_internal.hpp"
 
 namespace lw {
 
@@ -64,5 +65,21 @@ __device__ __forceinline__ DipLds dip_lds(const DipDev &D)
 }
 
 enum { ERR_HISTORY = 1u, ERR_NOCONV = 2u, ERR_VELOCITY = 4u, ERR_NONFINITE = 8u };
+
+// Larmor power per |d_ddot|^2 (Sec. 2.5): 1 / (6 pi eps0 c^3).
+constexpr double K_LARMOR = 1.0 / (6.0 * PI * EPS0 * C_LIGHT * C_LIGHT * C_LIGHT);
+
+// Writes row `row` of the outputs for dipole gi.
+__device__ __forceinline__ void put_row(const RunOut &o, int64_t row, int gi, double d, double v, double E, double Ed,
+                                        double wa, double wr)
+{
+    const int64_t k = row * o.n_dip + gi;
+    o.d[k] = d;
+    if (o.v) o.v[k] = v;
+    if (o.E) o.E[k] = E;
+    if (o.Ed) o.Ed[k] = Ed;
+    if (o.wabs) o.wabs[k] = wa;
+    if (o.wrad) o.wrad[k] = wr;
+}
 
 }  // namespace lw

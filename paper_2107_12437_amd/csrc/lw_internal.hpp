@@ -11,6 +11,17 @@ namespace lw {
 
 struct SrcRec;
 
+// Outputs of an oscillator run, [steps/stride + 1][n_dip] each; all but d may
+// be null.  wabs: work done on the dipole by its drive field since t = 0 (the
+// integral of E_d d_dot); wrad: energy radiated since t = 0 (the integral of
+// the Larmor power |d_ddot|^2 / (6 pi eps0 c^3)); both by the trapezoid rule
+// over steps (Sec. 2.5).
+struct RunOut {
+    double *d, *v, *E, *Ed, *wabs, *wrad;
+    int64_t stride;
+    int n_dip;
+};
+
 // Launch parameters of the grid-field kernel chosen by the tuner.
 struct FieldLaunch {
     int block;       // threads per workgroup (multiple of 64)
@@ -49,17 +60,16 @@ hipError_t launch_dipole_prep(const lw_dipole *d_in, int n, DipDev *d_dev, hipSt
 // ring lives in LDS, otherwise at d_ring_global + d_ring_off[block].
 hipError_t launch_dipole_instances(const DipDev *d_dev, const int32_t *d_off, const int32_t *d_list, int n_list,
                                    int max_n, bool ring_lds, const int64_t *d_ring_off, double *d_ring_global,
-                                   int ring, int64_t steps, int64_t stride, double dt, double max_vel,
-                                   int max_iter, double *d_moment, double *d_ddot, double *d_energy,
-                                   double *d_drive, int n_dip, uint32_t *d_err, hipStream_t s);
+                                   int ring, int64_t steps, double dt, double max_vel, int max_iter,
+                                   const RunOut &out, uint32_t *d_err, hipStream_t s);
 
 // Large instances: one launch per step (captured into a replayed graph when
 // graph_chunk > 0 and a capture stream is given), one workgroup per target.
+// d_W: 2 doubles per dipole of running energy sums (absorbed, radiated).
 hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const int32_t *d_tgt_lo, const int32_t *d_tgt_n,
-                               const int64_t *d_ring_base, int n_tgt, double *d_ring, double *d_Ecur, int64_t *d_step,
-                               int ring, int64_t steps, int64_t stride, double dt, double max_vel, int max_iter,
-                               double *d_moment, double *d_ddot, double *d_energy, double *d_drive, int n_dip,
-                               uint32_t *d_err, int graph_chunk, hipStream_t s, hipStream_t cap,
+                               const int64_t *d_ring_base, int n_tgt, double *d_ring, double *d_Ecur, double *d_W,
+                               int64_t *d_step, int ring, int64_t steps, double dt, double max_vel, int max_iter,
+                               const RunOut &out, uint32_t *d_err, int graph_chunk, hipStream_t s, hipStream_t cap,
                                hipGraph_t *graph_out, hipGraphExec_t *exec_out);
 
 // Gradient of the detector objective with respect to the oscillator positions

@@ -100,7 +100,7 @@ def load_library(path: str = LIB_PATH):
     L.lw_fields.argtypes = [vp, ct.POINTER(Traj), i32, vp, i64, ct.POINTER(dbl), i32, ct.POINTER(Opts), vp, vp, vp]
     L.lw_fields_vjp.argtypes = [vp, ct.POINTER(Traj), i32, vp, i64, ct.POINTER(dbl), i32, ct.POINTER(Opts), vp, vp, vp]
     L.lw_dipole_run.argtypes = [vp, ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, i64,
-                                ct.POINTER(RunOpts), vp, vp, vp, vp, vp]
+                                ct.POINTER(RunOpts), vp, vp, vp, vp, vp, vp, vp]
     L.lw_dipole_run_vjp.argtypes = [vp, ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, i64,
                                     ct.POINTER(RunOpts), vp, i64, ct.POINTER(dbl), i32, vp, ct.POINTER(dbl), vp]
     L.lw_pair_modes.argtypes = [ct.POINTER(dbl), i64, i32, ct.POINTER(i32), i32, dbl, i64,
@@ -313,21 +313,26 @@ class LWFieldsFn(torch.autograd.Function):
 
 def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "strict", out_stride: int = 1,
                max_vel: float = 0.0, ring_depth: int = 0, stepped_min_n: int = 0, device=None, check: bool = True,
-               ctx: Context | None = None):
+               ctx: Context | None = None, energy_balance: bool = False):
     """Self-consistent oscillator run (Algorithm 1).  Returns a dict of [n_out][n_dip]
-    float64 GPU tensors: d, d_dot, energy, Ed."""
+    float64 GPU tensors: d, d_dot, energy, Ed, and with energy_balance the work absorbed
+    from the drive field W_abs and the Larmor energy radiated W_rad since t = 0 (Sec. 2.5:
+    the sum over an instance of energy - W_abs + W_rad is conserved)."""
     dev = _as_device(device)
     ctx = ctx or default_context(dev.index)
     arr, n = pack_dipoles(dipoles)
     off = np.ascontiguousarray(inst_off, dtype=np.int32)
     n_out = int(steps) // int(out_stride) + 1
-    res = {k: torch.empty((n_out, n), dtype=torch.float64, device=dev) for k in ("d", "d_dot", "energy", "Ed")}
+    keys = ("d", "d_dot", "energy", "Ed") + (("W_abs", "W_rad") if energy_balance else ())
+    res = {k: torch.empty((n_out, n), dtype=torch.float64, device=dev) for k in keys}
     opts = RunOpts(FP64, DT_POLICIES[policy], int(out_stride), float(max_vel), int(ring_depth), int(stepped_min_n))
     L = load_library()
     _check(L.lw_dipole_run(ctx.handle, arr, n, off.ctypes.data_as(ct.POINTER(ct.c_int32)), len(off) - 1,
                            float(dt), int(steps), ct.byref(opts), ct.c_void_p(res["d"].data_ptr()),
                            ct.c_void_p(res["d_dot"].data_ptr()), ct.c_void_p(res["energy"].data_ptr()),
-                           ct.c_void_p(res["Ed"].data_ptr()), _stream_ptr(dev)))
+                           ct.c_void_p(res["Ed"].data_ptr()),
+                           ct.c_void_p(res["W_abs"].data_ptr()) if energy_balance else None,
+                           ct.c_void_p(res["W_rad"].data_ptr()) if energy_balance else None, _stream_ptr(dev)))
     if check:
         sync_status(ctx, dev)
     return res

@@ -263,3 +263,28 @@ def test_moving_dipoles_are_checked():
     pts[2] = 1e-7
     with pytest.raises(lw.LWError):                  # no adjoint for moving origins
         lw.dipole_run_vjp(w["dipoles"], w["inst_off"], w["dt"], 10, pts, [5 * w["dt"]])
+
+
+@pytest.mark.parametrize("stepped_min_n", [0, 2])
+def test_energy_balance_outputs(stepped_min_n):
+    """W_abs (work of the drive field) and W_rad (Larmor energy) against the oracle on both
+    run paths with strided rows, and the conserved W_total of Sec. 2.5 on the GPU's own
+    outputs (1e-7 of the initial energy at dt = T0/1000)."""
+    from paper_2107_12437_amd import lw
+    w0 = 2 * math.pi * 200e12
+    dip = I.empty_dipoles(3)
+    dip["origin"][1] = [12e-9, 0, 0]
+    dip["origin"][2] = [0, 15e-9, 4e-9]
+    dip["axis"][2] = [0, 0.6, 0.8]
+    dip["omega0"][:] = w0 * np.array([1.0, 1.001, 0.999])
+    dip["d0"][:] = I.E_CHARGE * 1e-12 * np.array([1.0, -0.5, 0.3])
+    dt, steps, stride = 1 / 200e12 / 1000, 6000, 5
+    r = lw.dipole_run(dip, [0, 3], dt, steps, out_stride=stride, stepped_min_n=stepped_min_n, energy_balance=True)
+    got = {k: v.cpu().numpy() for k, v in r.items()}
+    ref = O.dipole_run(dip, [0, 3], dt, steps, out_stride=stride)
+    for k in ("W_abs", "W_rad"):
+        scale = np.abs(ref[k]).max(axis=0, keepdims=True)
+        err = np.abs(got[k] - ref[k]) / scale
+        assert err.max() <= 1e-10, (k, err.max())
+    W = (got["energy"] - got["W_abs"] + got["W_rad"]).sum(axis=1)
+    assert np.abs(W - W[0]).max() <= 1e-7 * got["energy"][0].sum()
