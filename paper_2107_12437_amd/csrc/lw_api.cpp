@@ -547,7 +547,7 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
     const size_t t32_bytes = align_up(sizeof(int32_t) * (n_tgt + 1), 256);
     const size_t t64_bytes = align_up(sizeof(int64_t) * (n_tgt + 1), 256);
     const size_t stage_bytes = in_bytes + off_bytes + list_bytes + 3 * t32_bytes + t64_bytes;
-    const size_t dev_bytes = align_up(lw::dip_dev_bytes() * (size_t)n_dip, 256);
+    const size_t dev_bytes = align_up(lw::dip_dev_bytes(n_dip), 256);
     const size_t ecur_bytes = align_up(sizeof(double) * 3 * (size_t)n_dip, 256);   // E_d(t_n), then 2 energy sums
     const size_t step_bytes = 256;
     const size_t ring_bytes = align_up(sizeof(double) * (size_t)std::max<int64_t>(ring_doubles, 1), 256);
@@ -619,14 +619,16 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
         small_s = ctx->side;
     }
     const lw::RunOut out{d_moment, d_dot, d_energy, d_drive, d_wabs, d_wrad, opts->out_stride, n_dip};
+    bool moving = false;
+    for (int i = 0; i < n_dip; ++i) moving = moving || motion_reach(h_dip[i]) > 0.0;
     LW_HIP(lw::launch_dipole_instances(d_dev, d_off, d_list, (int)lds_list.size(), max_lds_n, true, nullptr, nullptr,
-                                       ring, steps, dt, max_vel, max_iter, out, ctx->d_err, small_s));
+                                       ring, steps, dt, max_vel, max_iter, out, moving, ctx->d_err, small_s));
     if (n_tgt > 0) {
         if (!ctx->capture) LW_HIP(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
         if (!ctx->graph_done) LW_HIP(hipEventCreateWithFlags(&ctx->graph_done, hipEventDisableTiming));
         const int chunk = 256;
         LW_HIP(lw::launch_dipole_steps(d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_tgt_base, (int)n_tgt, d_ring, d_Ecur, d_W,
-                                       d_step, ring, steps, dt, max_vel, max_iter, out, ctx->d_err, chunk, s,
+                                       d_step, ring, steps, dt, max_vel, max_iter, out, moving, ctx->d_err, chunk, s,
                                        ctx->capture, &ctx->graph, &ctx->graph_exec));
         LW_HIP(hipEventRecord(ctx->graph_done, s));
     }
@@ -678,7 +680,7 @@ lw_status lw_dipole_run_vjp(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, 
     const size_t off_b = align_up(sizeof(int32_t) * (size_t)(n_inst + 1), 256);
     const size_t po_b = align_up(sizeof(int64_t) * (size_t)(n_inst + 1), 256);
     const size_t tm_b = align_up(sizeof(double) * (size_t)n_snap, 256);
-    const size_t dev_b = align_up(lw::dip_dev_bytes() * (size_t)n_dip, 256);
+    const size_t dev_b = align_up(lw::dip_dev_bytes(n_dip), 256);
     const size_t state_b = align_up(sizeof(double) * 6 * (size_t)n_dip, 256);
     const size_t rbp_b = align_up(sizeof(double) * 3 * (size_t)std::max<int64_t>(n_pairs, 1), 256);
     const size_t rbp0_b = align_up(sizeof(double) * 3 * (size_t)std::max<int64_t>(n_pairs0, 1), 256);

@@ -21,9 +21,10 @@
 
 namespace lw {
 
-size_t dip_dev_bytes() { return sizeof(DipDev); }
+size_t dip_dev_bytes(int n) { return dip_dev_array_bytes(n) + sizeof(double) * SF_COUNT * (size_t)n; }
 
-__global__ void dipole_prep_kernel(const lw_dipole *__restrict__ in, int n, DipDev *__restrict__ dev)
+__global__ void dipole_prep_kernel(const lw_dipole *__restrict__ in, int n, DipDev *__restrict__ dev,
+                                   double *__restrict__ soa)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -51,11 +52,15 @@ __global__ void dipole_prep_kernel(const lw_dipole *__restrict__ in, int n, DipD
     o.mph = moves ? D.motion_phase : 0.0;
     o.mspeed = moves ? fabs(D.motion_omega) * am : 0.0;
     dev[i] = o;
+    const double f[SF_COUNT] = {o.origin[0], o.origin[1], o.origin[2], o.axis[0], o.axis[1], o.axis[2], o.cfp,
+                                o.cfm,       o.d0,        o.q,         o.mamp[0], o.mamp[1], o.mamp[2], o.mw, o.mph};
+    for (int k = 0; k < SF_COUNT; ++k) soa[(int64_t)k * n + i] = f[k];
 }
 
 hipError_t launch_dipole_prep(const lw_dipole *d_in, int n, DipDev *d_dev, hipStream_t s)
 {
-    hipLaunchKernelGGL(dipole_prep_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d_in, n, d_dev);
+    hipLaunchKernelGGL(dipole_prep_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d_in, n, d_dev,
+                       dip_soa(d_dev, n));
     return hipGetLastError();
 }
 
@@ -187,7 +192,7 @@ __device__ double retarded_hist_moving(const Hist &H, int j, const DipLds &Sj, c
     bool ok = false;
     auto origin = [&](double s) {
         double sn, c;
-        sincos(Sj.mw * (s * H.dt) + Sj.mph, &sn, &c);
+        sincos_reduced(Sj.mw * (s * H.dt) + Sj.mph, sn, c);
         for (int k = 0; k < 3; ++k) {
             Ro[k] = O[k] + m[k] * c;
             Vo[k] = -Sj.mw * m[k] * sn;
@@ -237,28 +242,20 @@ __device__ double retarded_hist_moving(const Hist &H, int j, const DipLds &Sj, c
 // target i at time (nstep + theta) dt.  Moving origins (Sec. 4.3): the field is
 // taken at the target's origin at that time, and the source's charges ride on
 // its origin at the retarded time.
-__device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double cf, double kq,
-                             int64_t nstep, double theta, int max_iter, uint32_t &err)
+// The moving-source branch of pair_drive (compiled only into the kernels that
+// run moving dipoles).
+__device__ __forceinline__ double pair_drive_moving(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double cf,
+                                                 double kq, int64_t nstep, double base, const double X[3],
+                                                 int max_iter, uint32_t &err)
 {
-    const double base = (double)nstep + theta;
-    double X[3];
-    origin_at(Si, base * H.dt, X);
-    if (Sj.mw == 0.0) {
-        const double dx = X[0] - Sj.ox, dy = X[1] - Sj.oy, dz = X[2] - Sj.oz;
-        const double L2 = dx * dx + dy * dy + dz * dz;
-        const double L = sqrt(L2);
-        const double sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;     // Delta . p_j
-        double h[3];
-        retarded_hist(H, j, Sj.d0, nstep, base, L2, sD, cf, L * INV_C, 2.0 * L * INV_C, max_iter, h, err);
-        return drive_field(Si, Sj, dx, dy, dz, cf, kq, h);
-    }
-    // moving source: start from the present separation of the origins; the
-    // bracket's upper end covers the origin's whole swing
+    // start from the present separation of the origins; the bracket's upper
+    // end covers the origin's whole swing
     const double dx = X[0] - Sj.ox, dy = X[1] - Sj.oy, dz = X[2] - Sj.oz;
     const double reach = sqrt(dx * dx + dy * dy + dz * dz) + sqrt(Sj.mx * Sj.mx + Sj.my * Sj.my + Sj.mz * Sj.mz);
     double h[3], Ro[3], Vo[3], Ao[3];
-    retarded_hist_moving(H, j, Sj, X, cf, nstep, base, reach * INV_C, 2.0 * reach * INV_C, max_iter, h, Ro, Vo, Ao,
-                         err);
+    const double hi = 2.0 * reach * INV_C;
+    const double t0 = reach * INV_C;
+    const double tau = retarded_hist_moving(H, j, Sj, X, cf, nstep, base, t0, hi, max_iter, h, Ro, Vo, Ao, err);
     Kin k;
     const double rho = cf * h[0];
     const double p[3] = {Sj.px, Sj.py, Sj.pz};
@@ -276,9 +273,32 @@ __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, 
     return o[4] * Si.px + o[5] * Si.py + o[6] * Si.pz;
 }
 
+// MOVING: origins may move; without it every origin is taken as fixed (the
+// kernels for fixed origins carry none of the moving-origin code).
+template <bool MOVING>
+__device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double cf, double kq,
+                             int64_t nstep, double theta, int max_iter, uint32_t &err)
+{
+    const double base = (double)nstep + theta;
+    double X[3] = {Si.ox, Si.oy, Si.oz};
+    if (MOVING) origin_at(Si, base * H.dt, X);
+    if (!MOVING || Sj.mw == 0.0) {
+        const double dx = X[0] - Sj.ox, dy = X[1] - Sj.oy, dz = X[2] - Sj.oz;
+        const double L2 = dx * dx + dy * dy + dz * dz;
+        const double L = sqrt(L2);
+        const double sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;     // Delta . p_j
+        double h[3];
+        const double hi = 2.0 * L * INV_C;
+        retarded_hist(H, j, Sj.d0, nstep, base, L2, sD, cf, L * INV_C, hi, max_iter, h, err);
+        return drive_field(Si, Sj, dx, dy, dz, cf, kq, h);
+    }
+    if constexpr (MOVING) return pair_drive_moving(H, Si, Sj, j, cf, kq, nstep, base, X, max_iter, err);
+    return 0.0;
+}
+
 // Drive fields of all targets of the instance at stage times theta in
 // `thetas[0..nth)` (in steps after nstep), written to Eout[th * n + i].
-template <int BLOCK>
+template <int BLOCK, bool MOVING>
 __device__ void drive_all(const Hist &H, const DipLds *S, const double *qv, int n, int64_t nstep,
                           const double *thetas, int nth, double *Eout, int max_iter, uint32_t &err)
 {
@@ -301,7 +321,7 @@ __device__ void drive_all(const Hist &H, const DipLds *S, const double *qv, int 
                 const int j = jj < i ? jj : jj + 1;
                 const double cf = w ? S[j].cfm : S[j].cfp;
                 const double kq = (w ? -qv[j] : qv[j]) * K_COUL;
-                acc += pair_drive(H, S[i], S[j], j, cf, kq, nstep, thetas[th], max_iter, err);
+                acc += pair_drive<MOVING>(H, S[i], S[j], j, cf, kq, nstep, thetas[th], max_iter, err);
             }
         }
         for (int off = 1; off < Lg; off <<= 1) acc += __shfl_xor(acc, off, 64);
@@ -309,7 +329,7 @@ __device__ void drive_all(const Hist &H, const DipLds *S, const double *qv, int 
     }
 }
 
-template <int BLOCK, bool RING_LDS>
+template <int BLOCK, bool RING_LDS, bool MOVING>
 __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__restrict__ dev,
                                                              const int32_t *__restrict__ off,
                                                              const int32_t *__restrict__ inst_list, int ring,
@@ -326,14 +346,16 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
     const int tid = threadIdx.x;
     if (n <= 0) return;
 
-    // LDS layout: constants, q, Ecur, Emid/Eend, absorbed and radiated energy, (ring)
+    // LDS layout: constants, q, Ecur, Emid/Eend, absorbed and radiated energy,
+    // oscillator constants (w0^2, gamma0, f, vfac, origin speed), (ring)
     DipLds *S = (DipLds *)lds;
     double *qv = (double *)(S + n);
     double *Ecur = qv + n;
     double *Enew = Ecur + n;                    // [2][n]: mid, end
     double *Wab = Enew + 2 * n;
     double *Wra = Wab + n;
-    double *ring_lds = Wra + n;
+    double *Kc = Wra + n;                       // [5][n]
+    double *ring_lds = Kc + 5 * n;
     double *ringp = RING_LDS ? ring_lds : ring_global + ring_off[blockIdx.x];
     __shared__ uint32_t s_err;
 
@@ -341,6 +363,11 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
         const DipDev &D = dev[i0 + j];
         S[j] = dip_lds(D);
         qv[j] = D.q;
+        Kc[j] = D.omega0 * D.omega0;
+        Kc[n + j] = D.gamma0;
+        Kc[2 * n + j] = D.f;
+        Kc[3 * n + j] = D.vfac;
+        Kc[4 * n + j] = D.mspeed;
     }
     if (tid == 0) s_err = 0u;
     __syncthreads();
@@ -351,7 +378,7 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
     // t = 0: drive from the static pre-history, then sample 0 = (d0, 0, d_ddot(0))
     {
         const double th0[1] = {0.0};
-        drive_all<BLOCK>(H, S, qv, n, 0, th0, 1, Ecur, max_iter, err);
+        drive_all<BLOCK, MOVING>(H, S, qv, n, 0, th0, 1, Ecur, max_iter, err);
     }
     __syncthreads();
     for (int i = tid; i < n; i += BLOCK) {
@@ -367,32 +394,12 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
     }
     __syncthreads();
 
-    // constants of the dipole this thread advances (the first BLOCK of the instance)
-    double own_w2 = 0.0, own_g = 0.0, own_f = 0.0, own_vfac = 0.0, own_ie = 0.0, own_ms = 0.0;
-    if (tid < n) {
-        const DipDev &D = dev[i0 + tid];
-        own_w2 = D.omega0 * D.omega0;
-        own_g = D.gamma0;
-        own_f = D.f;
-        own_vfac = D.vfac;
-        own_ms = D.mspeed;
-        own_ie = 0.5 / D.f;
-    }
     const double thetas[2] = {0.5, 1.0};
     for (int64_t nstep = 0; nstep < steps; ++nstep) {
-        drive_all<BLOCK>(H, S, qv, n, nstep, thetas, 2, Enew, max_iter, err);
+        drive_all<BLOCK, MOVING>(H, S, qv, n, nstep, thetas, 2, Enew, max_iter, err);
         __syncthreads();
         for (int i = tid; i < n; i += BLOCK) {
-            double w2 = own_w2, g = own_g, f = own_f, vfac = own_vfac, ie = own_ie, ms = own_ms;
-            if (i != tid) {
-                const DipDev &D = dev[i0 + i];
-                w2 = D.omega0 * D.omega0;
-                g = D.gamma0;
-                f = D.f;
-                vfac = D.vfac;
-                ms = D.mspeed;
-                ie = 0.5 / D.f;
-            }
+            const double w2 = Kc[i], g = Kc[n + i], f = Kc[2 * n + i], vfac = Kc[3 * n + i], ms = Kc[4 * n + i];
             const double *h = ringp + ((int64_t)(nstep & (ring - 1)) * n + i) * 3;
             const double Em = Enew[i], Ee = Enew[n + i], Ec = Ecur[i];
             const double y0 = h[0], y1 = h[1];
@@ -420,7 +427,7 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
             Wab[i] = wa;
             Wra[i] = wr;
             if ((nstep + 1) % out.stride == 0)
-                put_row(out, (nstep + 1) / out.stride, i0 + i, dn, vn, (w2 * dn * dn + vn * vn) * ie, Ee, wa, wr);
+                put_row(out, (nstep + 1) / out.stride, i0 + i, dn, vn, (w2 * dn * dn + vn * vn) * (0.5 / f), Ee, wa, wr);
         }
         if (err) atomicOr(&s_err, err);
         __syncthreads();
@@ -441,7 +448,7 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
 // ---------------------------------------------------------------------------
 
 
-template <int BLOCK>
+template <int BLOCK, bool MOVING>
 __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict__ dev, const int32_t *__restrict__ tgt,
                                                         const int32_t *__restrict__ tgt_lo,
                                                         const int32_t *__restrict__ tgt_n,
@@ -449,7 +456,8 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
                                                         double *__restrict__ Ecur, double *__restrict__ W,
                                                         const int64_t *__restrict__ step_ctr, int kstep,
                                                         int ring_depth, double dt, double max_vel, int max_iter,
-                                                        int init, RunOut out, uint32_t *__restrict__ d_err)
+                                                        int init, RunOut out, const double *__restrict__ soa,
+                                                        uint32_t *__restrict__ d_err)
 {
     __shared__ double red[2][BLOCK];
     const int tid = threadIdx.x;
@@ -469,12 +477,12 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
         const int th = m / M, mm = m - th * M;
         const int jj = mm >> 1, w = mm & 1;
         const int j = jj < i ? jj : jj + 1;
-        const DipDev &Dj = dev[i0 + j];
-        const DipLds Sj = dip_lds(Dj);
+        const DipLds Sj = soa_lds(soa, out.n_dip, (uint32_t)(i0 + j));
+        const double qj = soa_get(soa, out.n_dip, SF_Q, (uint32_t)(i0 + j));
         const double cf = w ? Sj.cfm : Sj.cfp;
-        const double kq = (w ? -Dj.q : Dj.q) * K_COUL;
+        const double kq = (w ? -qj : qj) * K_COUL;
         const double theta = init ? 0.0 : (th ? 1.0 : 0.5);
-        const double e = pair_drive(H, Si, Sj, j, cf, kq, nstep, theta, max_iter, err);
+        const double e = pair_drive<MOVING>(H, Si, Sj, j, cf, kq, nstep, theta, max_iter, err);
         if (th) acc1 += e; else acc0 += e;
     }
     red[0][tid] = acc0;
@@ -547,24 +555,32 @@ __global__ void step_reset_kernel(int64_t *step_ctr)
 hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const int32_t *d_tgt_lo, const int32_t *d_tgt_n,
                                const int64_t *d_ring_base, int n_tgt, double *d_ring, double *d_Ecur, double *d_W,
                                int64_t *d_step, int ring, int64_t steps, double dt, double max_vel, int max_iter,
-                               const RunOut &out, uint32_t *d_err, int graph_chunk, hipStream_t s, hipStream_t cap,
-                               hipGraph_t *graph_out, hipGraphExec_t *exec_out)
+                               const RunOut &out, bool moving, uint32_t *d_err, int graph_chunk, hipStream_t s,
+                               hipStream_t cap, hipGraph_t *graph_out, hipGraphExec_t *exec_out)
 {
     constexpr int B = 256;
     if (n_tgt <= 0) return hipSuccess;
     const dim3 grid((unsigned)n_tgt), block(B);
+    const double *soa = dip_soa(const_cast<DipDev *>(d_dev), out.n_dip);
+    auto step = [&](hipStream_t q, int k, int init) {
+        if (moving)
+            hipLaunchKernelGGL((lo_step_kernel<B, true>), grid, block, 0, q, d_dev, d_tgt, d_tgt_lo, d_tgt_n,
+                               d_ring_base, d_ring, d_Ecur, d_W, d_step, k, ring, dt, max_vel, max_iter, init, out,
+                               soa, d_err);
+        else
+            hipLaunchKernelGGL((lo_step_kernel<B, false>), grid, block, 0, q, d_dev, d_tgt, d_tgt_lo, d_tgt_n,
+                               d_ring_base, d_ring, d_Ecur, d_W, d_step, k, ring, dt, max_vel, max_iter, init, out,
+                               soa, d_err);
+    };
     hipLaunchKernelGGL(step_reset_kernel, dim3(1), dim3(1), 0, s, d_step);
-    hipLaunchKernelGGL(lo_step_kernel<B>, grid, block, 0, s, d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_ring_base, d_ring,
-                       d_Ecur, d_W, d_step, 0, ring, dt, max_vel, max_iter, 1, out, d_err);
+    step(s, 0, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || steps == 0) return e;
     // a chunk of steps is captured once into a graph and replayed: launch k of
     // a chunk advances step base + k, and the base (on the device) moves by the
     // chunk at its end, so every replay continues where the last ended
     auto enqueue = [&](hipStream_t q, int64_t count) {
-        for (int64_t k = 0; k < count; ++k)
-            hipLaunchKernelGGL(lo_step_kernel<B>, grid, block, 0, q, d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_ring_base,
-                               d_ring, d_Ecur, d_W, d_step, (int)k, ring, dt, max_vel, max_iter, 0, out, d_err);
+        for (int64_t k = 0; k < count; ++k) step(q, (int)k, 0);
         hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(1), 0, q, d_step, count);
     };
     const int64_t chunk = graph_chunk > 0 ? graph_chunk : 0;
@@ -594,20 +610,20 @@ hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const 
 
 int ring_lds_bytes(int n, int ring)
 {
-    return (int)(sizeof(DipLds) * n + sizeof(double) * 6 * n + sizeof(double) * 3 * (size_t)ring * n);
+    return (int)(sizeof(DipLds) * n + sizeof(double) * 11 * n + sizeof(double) * 3 * (size_t)ring * n);
 }
 
-template <int BLOCK>
+template <int BLOCK, bool MOVING>
 static hipError_t launch_lo(bool ring_lds, dim3 grid, size_t shmem, hipStream_t s, const DipDev *d_dev,
                             const int32_t *d_off, const int32_t *d_list, int ring, int64_t steps, double dt,
                             double max_vel, int max_iter, double *d_ring_global, const int64_t *d_ring_off,
                             const RunOut &out, uint32_t *d_err)
 {
     if (ring_lds)
-        hipLaunchKernelGGL((lo_instances_kernel<BLOCK, true>), grid, dim3(BLOCK), shmem, s, d_dev, d_off, d_list,
-                           ring, steps, dt, max_vel, max_iter, d_ring_global, d_ring_off, out, d_err);
+        hipLaunchKernelGGL((lo_instances_kernel<BLOCK, true, MOVING>), grid, dim3(BLOCK), shmem, s, d_dev, d_off,
+                           d_list, ring, steps, dt, max_vel, max_iter, d_ring_global, d_ring_off, out, d_err);
     else
-        hipLaunchKernelGGL((lo_instances_kernel<BLOCK, false>), grid, dim3(BLOCK), shmem, s, d_dev, d_off,
+        hipLaunchKernelGGL((lo_instances_kernel<BLOCK, false, MOVING>), grid, dim3(BLOCK), shmem, s, d_dev, d_off,
                            d_list, ring, steps, dt, max_vel, max_iter, d_ring_global, d_ring_off, out, d_err);
     return hipGetLastError();
 }
@@ -615,16 +631,20 @@ static hipError_t launch_lo(bool ring_lds, dim3 grid, size_t shmem, hipStream_t 
 hipError_t launch_dipole_instances(const DipDev *d_dev, const int32_t *d_off, const int32_t *d_list, int n_list,
                                    int max_n, bool ring_lds, const int64_t *d_ring_off, double *d_ring_global,
                                    int ring, int64_t steps, double dt, double max_vel, int max_iter,
-                                   const RunOut &out, uint32_t *d_err, hipStream_t s)
+                                   const RunOut &out, bool moving, uint32_t *d_err, hipStream_t s)
 {
     if (n_list <= 0) return hipSuccess;
     const size_t shmem = (size_t)ring_lds_bytes(max_n, ring_lds ? ring : 0);
     const dim3 grid((unsigned)n_list);
     if (max_n <= 8)
-        return launch_lo<64>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel, max_iter,
-                             d_ring_global, d_ring_off, out, d_err);
-    return launch_lo<256>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel, max_iter,
-                          d_ring_global, d_ring_off, out, d_err);
+        return moving ? launch_lo<64, true>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel,
+                                            max_iter, d_ring_global, d_ring_off, out, d_err)
+                      : launch_lo<64, false>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel,
+                                             max_iter, d_ring_global, d_ring_off, out, d_err);
+    return moving ? launch_lo<256, true>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel,
+                                         max_iter, d_ring_global, d_ring_off, out, d_err)
+                  : launch_lo<256, false>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel,
+                                          max_iter, d_ring_global, d_ring_off, out, d_err);
 }
 
 }  // namespace lw

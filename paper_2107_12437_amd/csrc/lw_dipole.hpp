@@ -32,14 +32,42 @@ struct DipLds {
     double mx, my, mz, mw, mph;   // origin motion (mw = 0: fixed origin)
 };
 
-// Origin of a dipole at time t (fixed, or moving as O + m cos(w t + phi)).
+// Structure-of-arrays copy of the source fields the pair loops read: field f of
+// dipole j at soa[f * n + j] (n dipoles in the run), so that a wave's load of
+// one field over consecutive sources is coalesced.  It follows the DipDev
+// array in the same block (dip_soa).
+enum { SF_OX, SF_OY, SF_OZ, SF_PX, SF_PY, SF_PZ, SF_CFP, SF_CFM, SF_D0, SF_Q, SF_MX, SF_MY, SF_MZ, SF_MW, SF_MPH,
+       SF_COUNT };
+
+__host__ __device__ inline size_t dip_dev_array_bytes(int n) { return (sizeof(DipDev) * (size_t)n + 255) & ~(size_t)255; }
+__host__ __device__ inline double *dip_soa(DipDev *dev, int n) { return (double *)((char *)dev + dip_dev_array_bytes(n)); }
+
+// Field f of dipole j (the 32-bit byte offset of j lets each load take the
+// field's base as a scalar operand).
+__device__ __forceinline__ double soa_get(const double *__restrict__ s, int64_t n, int f, uint32_t j)
+{
+    return *(const double *)((const char *)(s + f * n) + j * 8u);
+}
+
+__device__ __forceinline__ DipLds soa_lds(const double *__restrict__ s, int64_t n, uint32_t j)
+{
+    return DipLds{soa_get(s, n, SF_OX, j),  soa_get(s, n, SF_OY, j),  soa_get(s, n, SF_OZ, j),
+                  soa_get(s, n, SF_PX, j),  soa_get(s, n, SF_PY, j),  soa_get(s, n, SF_PZ, j),
+                  soa_get(s, n, SF_CFP, j), soa_get(s, n, SF_CFM, j), soa_get(s, n, SF_D0, j),
+                  soa_get(s, n, SF_MX, j),  soa_get(s, n, SF_MY, j),  soa_get(s, n, SF_MZ, j),
+                  soa_get(s, n, SF_MW, j),  soa_get(s, n, SF_MPH, j)};
+}
+
+// Origin of a dipole at time t (fixed, or moving as O + m cos(w t + phi); the
+// phase stays far below the 2^30 limit of sincos_reduced over any run).
 __device__ __forceinline__ void origin_at(const DipLds &S, double t, double R[3])
 {
     R[0] = S.ox;
     R[1] = S.oy;
     R[2] = S.oz;
     if (S.mw != 0.0) {
-        const double c = cos(S.mw * t + S.mph);
+        double sn, c;
+        sincos_reduced(S.mw * t + S.mph, sn, c);
         R[0] += S.mx * c;
         R[1] += S.my * c;
         R[2] += S.mz * c;

@@ -485,7 +485,7 @@ __global__ __launch_bounds__(BLOCK) void adj_step_kernel(const DipDev *__restric
                                                          int mask, double dt, AdjState A, double *__restrict__ rbp,
                                                          double *__restrict__ taup,
                                                          const int64_t *__restrict__ step_base, int k, int max_iter,
-                                                         uint32_t *__restrict__ d_err)
+                                                         const double *__restrict__ soa, uint32_t *__restrict__ d_err)
 {
     __shared__ double s_em, s_ee;
     const int tid = threadIdx.x;
@@ -515,10 +515,10 @@ __global__ __launch_bounds__(BLOCK) void adj_step_kernel(const DipDev *__restric
         const int th = mm2 / M, m = mm2 - th * M;
         const int jj = m >> 1, w = m & 1;
         gj = i0 + (jj < i ? jj : jj + 1);
-        const DipDev &Dj = dev[gj];
-        const DipLds Sj = dip_lds(Dj);
+        const DipLds Sj = soa_lds(soa, n_dip, (uint32_t)gj);
+        const double qj = soa_get(soa, n_dip, SF_Q, (uint32_t)gj);
         const double cf = w ? Sj.cfm : Sj.cfp;
-        const double kq = (w ? -Dj.q : Dj.q) * K_COUL;
+        const double kq = (w ? -qj : qj) * K_COUL;
         idx = pair_off[inst] + ((int64_t)th * n + i) * M + m;
         Kin kn;
         HistEval e;
@@ -668,11 +668,12 @@ hipError_t launch_dipole_vjp(const DipDev *d_dev, const int32_t *d_off, const in
     if (e != hipSuccess) return e;
     // one launch per step, n = base - k; after `count` launches the base moves
     // down by count, so a captured chunk replays as the next `count` steps
+    const double *soa = dip_soa(const_cast<DipDev *>(d_dev), n_dip);
     auto enqueue = [&](hipStream_t q, int64_t count) {
         for (int64_t k = 0; k < count; ++k)
             hipLaunchKernelGGL(adj_step_kernel<B>, dim3((unsigned)n_dip), dim3(B), 0, q, d_dev, d_off, d_pair_off,
                                n_inst, n_dip, d_hist, d_hbar, mask, dt, A, d_rbp, d_taup, d_step, (int)k, max_iter,
-                               d_err);
+                               soa, d_err);
         hipLaunchKernelGGL(adj_base_kernel, dim3(1), dim3(1), 0, q, d_step, -count);
     };
     const int64_t chunk = graph_chunk > 0 ? graph_chunk : 0;
