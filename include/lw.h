@@ -197,7 +197,11 @@ typedef struct {
 enum { LW_DT_STRICT = 0, LW_DT_EXTRAPOLATE = 1 };
 
 typedef struct {
-    int32_t precision;   /* LW_FP64 (the only value accepted for oscillator runs)           */
+    int32_t precision;   /* LW_FP64: FP64 throughout.  LW_MIXED: each source dipole's field
+                            at a target in FP32, its two charges' nearly cancelling
+                            monopole terms differenced without cancellation; retarded
+                            times, state and sums stay FP64 (lw_dipole_run_vjp: FP64
+                            only)                                                         */
     int32_t dt_policy;   /* LW_DT_STRICT: require c*dt < smallest separation (Sec. 3.2).
                             LW_DT_EXTRAPOLATE: allow it; a source read beyond its newest
                             stored step is a second-order Taylor step from that sample     */

@@ -462,7 +462,8 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
     if (h_inst_off[0] != 0 || h_inst_off[n_inst] != n_dip)
         return fail(LW_E_INVALID, "lw_dipole_run: instance offsets must run from 0 to n_dip");
     if (!(dt > 0.0) || !std::isfinite(dt) || steps < 0) return fail(LW_E_INVALID, "lw_dipole_run: bad dt or steps");
-    if (opts->precision != LW_FP64) return fail(LW_E_INVALID, "lw_dipole_run: oscillator runs are FP64 only");
+    if (opts->precision != LW_FP64 && opts->precision != LW_MIXED)
+        return fail(LW_E_INVALID, "lw_dipole_run: unknown precision");
     if (opts->dt_policy != LW_DT_STRICT && opts->dt_policy != LW_DT_EXTRAPOLATE)
         return fail(LW_E_INVALID, "lw_dipole_run: unknown dt policy");
     if (opts->out_stride < 1 || opts->ring_depth < 0 ||
@@ -621,14 +622,15 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
     const lw::RunOut out{d_moment, d_dot, d_energy, d_drive, d_wabs, d_wrad, opts->out_stride, n_dip};
     bool moving = false;
     for (int i = 0; i < n_dip; ++i) moving = moving || motion_reach(h_dip[i]) > 0.0;
+    const bool mixed = opts->precision == LW_MIXED;
     LW_HIP(lw::launch_dipole_instances(d_dev, d_off, d_list, (int)lds_list.size(), max_lds_n, true, nullptr, nullptr,
-                                       ring, steps, dt, max_vel, max_iter, out, moving, ctx->d_err, small_s));
+                                       ring, steps, dt, max_vel, max_iter, out, moving, mixed, ctx->d_err, small_s));
     if (n_tgt > 0) {
         if (!ctx->capture) LW_HIP(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
         if (!ctx->graph_done) LW_HIP(hipEventCreateWithFlags(&ctx->graph_done, hipEventDisableTiming));
         const int chunk = 256;
         LW_HIP(lw::launch_dipole_steps(d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_tgt_base, (int)n_tgt, d_ring, d_Ecur, d_W,
-                                       d_step, ring, steps, dt, max_vel, max_iter, out, moving, ctx->d_err, chunk, s,
+                                       d_step, ring, steps, dt, max_vel, max_iter, out, moving, mixed, ctx->d_err, chunk, s,
                                        ctx->capture, &ctx->graph, &ctx->graph_exec));
         LW_HIP(hipEventRecord(ctx->graph_done, s));
     }
@@ -654,6 +656,7 @@ lw_status lw_dipole_run_vjp(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, 
     int max_n = 0;
     for (int k = 0; k < n_inst; ++k) max_n = std::max(max_n, h_inst_off[k + 1] - h_inst_off[k]);
     if (max_n > 1024) return fail(LW_E_INVALID, "lw_dipole_run_vjp: instances of more than 1024 dipoles");
+    if (opts->precision != LW_FP64) return fail(LW_E_INVALID, "lw_dipole_run_vjp: the oscillator adjoint is FP64 only");
     for (int i = 0; i < n_dip; ++i)
         if (motion_reach(h_dip[i]) > 0.0)
             return fail(LW_E_INVALID, "lw_dipole_run_vjp: moving dipoles have no adjoint here");

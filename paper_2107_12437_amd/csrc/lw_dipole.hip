@@ -19,6 +19,8 @@
 #include "lw_dipole.hpp"
 #include "lw_internal.hpp"
 
+#include <type_traits>
+
 namespace lw {
 
 size_t dip_dev_bytes(int n) { return dip_dev_array_bytes(n) + sizeof(double) * SF_COUNT * (size_t)n; }
@@ -238,31 +240,128 @@ __device__ double retarded_hist_moving(const Hist &H, int j, const DipLds &Sj, c
     return tau;
 }
 
-// p_i . E of charge (cf, q_signed) of source dipole j seen at the origin of
-// target i at time (nstep + theta) dt.  Moving origins (Sec. 4.3): the field is
-// taken at the target's origin at that time, and the source's charges ride on
-// its origin at the retarded time.
-// The moving-source branch of pair_drive (compiled only into the kernels that
-// run moving dipoles).
-__device__ __forceinline__ double pair_drive_moving(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double cf,
-                                                 double kq, int64_t nstep, double base, const double X[3],
-                                                 int max_iter, uint32_t &err)
+// Stored samples k and k + 1 of one source; k = -1 stands for the static
+// pre-history (t' < 0), where the state is (d0, 0, 0).
+struct Seg {
+    int64_t k;
+    double d0, v0, a0;    // sample k: d, d_dot, d_ddot
+    double d1, v1, a1;    // sample k + 1
+};
+
+__device__ __forceinline__ void seg_load(const Hist &H, int j, double d0, int64_t nstep, int64_t k, Seg &g,
+                                         uint32_t &err)
+{
+    // k = -1 reads ring slot `mask` (in bounds) and discards it
+    const bool pre = k < 0;
+    g.k = pre ? -1 : k;
+    if (!pre && k + H.mask < nstep) err |= ERR_HISTORY;   // the slot was overwritten: history too short
+    const double *p0 = H.ring + ((int64_t)(g.k & H.mask) * H.n + j) * 3;
+    const double *p1 = H.ring + ((int64_t)((g.k + 1) & H.mask) * H.n + j) * 3;
+    g.d0 = pre ? d0 : p0[0];
+    g.v0 = pre ? 0.0 : p0[1];
+    g.a0 = pre ? 0.0 : p0[2];
+    g.d1 = pre ? d0 : p1[0];
+    g.v1 = pre ? 0.0 : p1[1];
+    g.a1 = pre ? 0.0 : p1[2];
+}
+
+// Retarded time of the charge at offset cf d(t') p_j of a fixed source j, in
+// closed form on the interpolated history.  Within the segment [k, k + 1] of
+// stored steps the moment is linear in tau (t' = t - tau), so the charge's
+// offset is rho = a + b tau and c tau = |Delta - rho p_j| becomes
+//   (c^2 - b^2) tau^2 + 2 b P tau - Q = 0,
+// P = sD - a, Q = |Delta - a p_j|^2 = L2 - 2 a sD + a^2, whose positive root
+// tau = Q / (b P + sqrt(b^2 P^2 + (c^2 - b^2) Q)) has no cancellation
+// (|b| << c).  The root is unique (the charge is slower than light), so if it
+// falls outside the loaded segment it lies in the segment its own s points to,
+// which is loaded next.  Returns false when the root lies past the newest
+// stored step (the caller then uses the Newton solve with the extrapolation)
+// or the hops do not settle.  On success h is the interpolated state at the
+// root and g holds the segment it lies in.
+__device__ __forceinline__ bool retarded_seg(const Hist &H, int j, double d0, int64_t nstep, double base, double L2,
+                                             double sD, double cf, Seg &g, double h[3], uint32_t &err)
+{
+    constexpr double C2 = C_LIGHT * C_LIGHT;
+    for (int hop = 0; hop < 4; ++hop) {
+        double a = cf * d0, b = 0.0;
+        if (g.k >= 0) {
+            const double dd = g.d1 - g.d0;
+            a = cf * fma(base - (double)g.k, dd, g.d0);
+            b = -cf * dd * H.inv_dt;
+        }
+        const double P = sD - a;
+        const double Q = fma(a, a - 2.0 * sD, L2);
+        const double bP = b * P;
+        double S, iS;
+        root_rsqrt<true>(fma(bP, bP, (C2 - b * b) * Q), S, iS);
+        const double tau = Q * recip<double>(bP + S);
+        const double s = base - tau * H.inv_dt;
+        // a root within rounding of a segment end belongs to either side
+        const double eps = 1e-9;
+        if (g.k < 0 ? s <= eps : (s >= (double)g.k - eps && s <= (double)g.k + 1.0 + eps)) {
+            const double u = g.k < 0 ? 0.0 : s - (double)g.k;
+            h[0] = fma(u, g.d1 - g.d0, g.d0);
+            h[1] = fma(u, g.v1 - g.v0, g.v0);
+            h[2] = fma(u, g.a1 - g.a0, g.a0);
+            return true;
+        }
+        const int64_t kn = s < 0.0 ? -1 : (int64_t)floor(s);
+        if (kn >= nstep) return false;
+        seg_load(H, j, d0, nstep, kn, g, err);
+    }
+    return false;
+}
+
+// Interpolated state h at the retarded time of the charge (cf) of fixed source
+// j seen at separation Delta (|Delta|^2 = L2, |Delta| = L, Delta . p_j = sD):
+// the closed form on the segment cached in g, else Newton (past the newest
+// stored step).  g.k = INT64_MIN marks an empty cache.
+__device__ __forceinline__ void charge_fixed(const Hist &H, int j, double d0, int64_t nstep, double base, double L2,
+                                             double L, double sD, double cf, int max_iter, Seg &g, double h[3],
+                                             uint32_t &err)
+{
+    if (g.k == INT64_MIN) {
+        const double s0 = base - L * INV_C * H.inv_dt;
+        const int64_t k0 = s0 < 0.0 ? -1 : (int64_t)floor(s0);
+        if (k0 < nstep) seg_load(H, j, d0, nstep, k0, g, err);
+    }
+    if (g.k != INT64_MIN && retarded_seg(H, j, d0, nstep, base, L2, sD, cf, g, h, err)) return;
+    retarded_hist(H, j, d0, nstep, base, L2, sD, cf, L * INV_C, 2.0 * L * INV_C, max_iter, h, err);
+}
+
+// Retarded separation R = X - r(t'), velocity and acceleration of the charge
+// (cf) of a moving source j seen from X at time base * dt (Sec. 4.3: the
+// charges ride on the source's origin at the retarded time).
+__device__ __forceinline__ void charge_moving(const Hist &H, const DipLds &Sj, int j, double cf, int64_t nstep,
+                                              double base, const double X[3], int max_iter, double R[3],
+                                              double v[3], double a[3], uint32_t &err)
 {
     // start from the present separation of the origins; the bracket's upper
     // end covers the origin's whole swing
     const double dx = X[0] - Sj.ox, dy = X[1] - Sj.oy, dz = X[2] - Sj.oz;
     const double reach = sqrt(dx * dx + dy * dy + dz * dz) + sqrt(Sj.mx * Sj.mx + Sj.my * Sj.my + Sj.mz * Sj.mz);
     double h[3], Ro[3], Vo[3], Ao[3];
-    const double hi = 2.0 * reach * INV_C;
-    const double t0 = reach * INV_C;
-    const double tau = retarded_hist_moving(H, j, Sj, X, cf, nstep, base, t0, hi, max_iter, h, Ro, Vo, Ao, err);
-    Kin k;
+    retarded_hist_moving(H, j, Sj, X, cf, nstep, base, reach * INV_C, 2.0 * reach * INV_C, max_iter, h, Ro, Vo, Ao,
+                         err);
     const double rho = cf * h[0];
     const double p[3] = {Sj.px, Sj.py, Sj.pz};
     for (int c = 0; c < 3; ++c) {
-        k.R[c] = X[c] - Ro[c] - rho * p[c];
-        k.v[c] = Vo[c] + cf * h[1] * p[c];
-        k.a[c] = Ao[c] + cf * h[2] * p[c];
+        R[c] = X[c] - Ro[c] - rho * p[c];
+        v[c] = Vo[c] + cf * h[1] * p[c];
+        a[c] = Ao[c] + cf * h[2] * p[c];
+    }
+}
+
+// p_i . E of one charge from its retarded separation, velocity and
+// acceleration (FP64 field, Eq. (E)).
+__device__ __forceinline__ double charge_field(const DipLds &Si, const double R[3], const double v[3],
+                                               const double a[3], double kq)
+{
+    Kin k;
+    for (int c = 0; c < 3; ++c) {
+        k.R[c] = R[c];
+        k.v[c] = v[c];
+        k.a[c] = a[c];
     }
     k.tp = 0.0;
     k.cph = 1.0;
@@ -273,8 +372,11 @@ __device__ __forceinline__ double pair_drive_moving(const Hist &H, const DipLds 
     return o[4] * Si.px + o[5] * Si.py + o[6] * Si.pz;
 }
 
-// MOVING: origins may move; without it every origin is taken as fixed (the
-// kernels for fixed origins carry none of the moving-origin code).
+// p_i . E at the origin of target i of the charge (cf, kq) of source j, at
+// time (nstep + theta) dt, all in FP64.  Moving origins (Sec. 4.3): the field is
+// taken at the target's origin at that time.  MOVING: origins may move; without
+// it every origin is taken as fixed (the kernels for fixed origins carry none
+// of the moving-origin code).
 template <bool MOVING>
 __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double cf, double kq,
                              int64_t nstep, double theta, int max_iter, uint32_t &err)
@@ -285,24 +387,157 @@ __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, 
     if (!MOVING || Sj.mw == 0.0) {
         const double dx = X[0] - Sj.ox, dy = X[1] - Sj.oy, dz = X[2] - Sj.oz;
         const double L2 = dx * dx + dy * dy + dz * dz;
-        const double L = sqrt(L2);
         const double sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;     // Delta . p_j
+        Seg g;
+        g.k = INT64_MIN;
         double h[3];
-        const double hi = 2.0 * L * INV_C;
-        retarded_hist(H, j, Sj.d0, nstep, base, L2, sD, cf, L * INV_C, hi, max_iter, h, err);
+        charge_fixed(H, j, Sj.d0, nstep, base, L2, sqrt(L2), sD, cf, max_iter, g, h, err);
         return drive_field(Si, Sj, dx, dy, dz, cf, kq, h);
     }
-    if constexpr (MOVING) return pair_drive_moving(H, Si, Sj, j, cf, kq, nstep, base, X, max_iter, err);
+    if constexpr (MOVING) {
+        double R[3], v[3], a[3];
+        charge_moving(H, Sj, j, cf, nstep, base, X, max_iter, R, v, a, err);
+        return charge_field(Si, R, v, a, kq);
+    }
     return 0.0;
 }
 
+// FP32 part of one charge's field in the mixed form: with n = R/|R|,
+// beta = v/c and kappa = 1 - n.beta, the field of Eq. (E) less its static
+// monopole term kq R / |R|^3,
+//   f(R) c1 - beta (1 - beta^2) / (kappa^3 |R|^2) + radiation term,
+//   c1 = (1 - beta^2) / kappa^3 - 1 = (n.beta (1 + kappa + kappa^2) - beta^2) / kappa^3,
+// projected on p_i, per unit kq, in lengths scaled by 1/Ls (x = R / Ls,
+// ga = acceleration Ls / c^2).
+__device__ __forceinline__ float dynamic_terms_f32(const float x[3], const float be[3], const float ga[3],
+                                                  const float pi[3])
+{
+    const float ix = __builtin_amdgcn_rsqf(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    float n[3];
+    for (int c = 0; c < 3; ++c) n[c] = x[c] * ix;
+    const float nb = n[0] * be[0] + n[1] * be[1] + n[2] * be[2];
+    const float kap = 1.0f - nb;
+    const float bb = be[0] * be[0] + be[1] * be[1] + be[2] * be[2];
+    const float ik = __builtin_amdgcn_rcpf(kap);
+    const float ik3 = ik * ik * ik;
+    const float c1 = (nb * (1.0f + kap + kap * kap) - bb) * ik3 * ix * ix * ix;
+    const float cb = (1.0f - bb) * ik3 * ix * ix;
+    const float nd = n[0] * ga[0] + n[1] * ga[1] + n[2] * ga[2];
+    const float cr = ik3 * ix;
+    float r = 0.0f;
+    for (int c = 0; c < 3; ++c) r += pi[c] * (x[c] * c1 - be[c] * cb + ((n[c] - be[c]) * nd - ga[c] * kap) * cr);
+    return r;
+}
+
+// Mixed form of the drive of one source dipole at a target (both charges: +q
+// at cfp d p_j, -q at cfm d p_j), at time (nstep + theta) dt.  The retarded
+// times are FP64 (the closed form, the two charges sharing one history
+// segment).  The field is the sum of
+//  - the static monopole difference kq [f(R+) - f(R-)], f(R) = R / |R|^3, the
+//    dominant term in the near field, in FP64.  R+ and R- differ by
+//    D = (rho- - rho+) p_j, taken exactly from the charges' offsets although
+//    far below |R| (1e-4 |R| at 10 nm for a 1e-12 m displacement, down to
+//    1e-13 |R| for the small induced moments of distant dipoles), by the
+//    identities
+//      f(a) - f(b) = D / |a|^3 + b (|b|^3 - |a|^3) / (|a|^3 |b|^3),
+//      |b|^3 - |a|^3 = (|b| - |a|) (|a|^2 + |a| |b| + |b|^2),
+//      |b| - |a| = -D . (a + b) / (|a| + |b|),
+//    in which nothing cancels;
+//  - each charge's velocity and radiation terms (dynamic_terms_f32) in FP32.
+//    Against the static term they are of relative size omega |R| / c and its
+//    square in the near field, and they have the same sign for both charges
+//    (their q beta and q beta_dot agree), so their rounding stays at that size
+//    times 2^-24.
+// Lengths are scaled by 1/|Delta| so that FP32 stays in range at nanometre
+// separations.  A moving source's origin velocity is common to both charges,
+// so its velocity terms would cancel: moving sources take the FP64 field of
+// each charge.  kq is that of the +q charge.
+template <bool MOVING>
+__device__ double dipole_drive_mixed(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double kq,
+                                     int64_t nstep, double theta, int max_iter, uint32_t &err)
+{
+    const double base = (double)nstep + theta;
+    double X[3] = {Si.ox, Si.oy, Si.oz};
+    if (MOVING) origin_at(Si, base * H.dt, X);
+    if constexpr (MOVING) {
+        if (Sj.mw != 0.0) {
+            double R[3], v[3], a[3];
+            charge_moving(H, Sj, j, Sj.cfp, nstep, base, X, max_iter, R, v, a, err);
+            double e = charge_field(Si, R, v, a, kq);
+            charge_moving(H, Sj, j, Sj.cfm, nstep, base, X, max_iter, R, v, a, err);
+            return e + charge_field(Si, R, v, a, -kq);
+        }
+    }
+    const double p[3] = {Sj.px, Sj.py, Sj.pz};
+    const double dl[3] = {X[0] - Sj.ox, X[1] - Sj.oy, X[2] - Sj.oz};
+    const double L2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
+    const double sD = dl[0] * p[0] + dl[1] * p[1] + dl[2] * p[2];
+    double L, iL;
+    root_rsqrt<true>(L2, L, iL);
+    Seg g;
+    g.k = INT64_MIN;
+    double hp[3], hm[3];
+    charge_fixed(H, j, Sj.d0, nstep, base, L2, L, sD, Sj.cfp, max_iter, g, hp, err);
+    charge_fixed(H, j, Sj.d0, nstep, base, L2, L, sD, Sj.cfm, max_iter, g, hm, err);
+    const double rp = Sj.cfp * hp[0] * iL, rm = Sj.cfm * hm[0] * iL;   // scaled offsets
+    // static monopole difference (FP64)
+    double a[3], b[3], sab[3];
+    for (int c = 0; c < 3; ++c) {
+        const double u = dl[c] * iL;
+        a[c] = u - rp * p[c];
+        b[c] = u - rm * p[c];
+        sab[c] = a[c] + b[c];
+    }
+    const double dsc = rm - rp;                     // D = dsc p_j (scaled)
+    double ra, ia, rb, ib;
+    root_rsqrt<true>(a[0] * a[0] + a[1] * a[1] + a[2] * a[2], ra, ia);
+    root_rsqrt<true>(b[0] * b[0] + b[1] * b[1] + b[2] * b[2], rb, ib);
+    const double ia3 = ia * ia * ia, ib3 = ib * ib * ib;
+    const double dab = -dsc * (p[0] * sab[0] + p[1] * sab[1] + p[2] * sab[2]) * recip<double>(ra + rb);
+    const double c3 = dab * (ra * ra + ra * rb + rb * rb) * ia3 * ib3;
+    const double pip = Si.px * p[0] + Si.py * p[1] + Si.pz * p[2];
+    const double st = dsc * ia3 * pip + c3 * (Si.px * b[0] + Si.py * b[1] + Si.pz * b[2]);
+    // velocity and radiation terms of both charges (FP32)
+    const float pi[3] = {(float)Si.px, (float)Si.py, (float)Si.pz};
+    const double gsc = INV_C * INV_C * L;           // acceleration -> beta_dot L / c
+    float xa[3], xb[3], bp[3], bm[3], gp[3], gm[3];
+    for (int c = 0; c < 3; ++c) {
+        xa[c] = (float)a[c];
+        xb[c] = (float)b[c];
+        bp[c] = (float)(Sj.cfp * hp[1] * INV_C * p[c]);
+        bm[c] = (float)(Sj.cfm * hm[1] * INV_C * p[c]);
+        gp[c] = (float)(Sj.cfp * hp[2] * gsc * p[c]);
+        gm[c] = (float)(Sj.cfm * hm[2] * gsc * p[c]);
+    }
+    const float rest = dynamic_terms_f32(xa, bp, gp, pi) - dynamic_terms_f32(xb, bm, gm, pi);
+    return kq * iL * iL * (st + (double)rest);
+}
+
+// Drive contribution of work unit w of source j: in FP64 one unit per charge
+// (w = 0: +q, 1: -q), in the mixed form one unit per source dipole.
+template <bool MOVING, bool MIXED>
+__device__ __forceinline__ double unit_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double qj,
+                                             int w, int64_t nstep, double theta, int max_iter, uint32_t &err)
+{
+    if constexpr (MIXED) {
+        return dipole_drive_mixed<MOVING>(H, Si, Sj, j, qj * K_COUL, nstep, theta, max_iter, err);
+    } else {
+        const double cf = w ? Sj.cfm : Sj.cfp;
+        const double kq = (w ? -qj : qj) * K_COUL;
+        return pair_drive<MOVING>(H, Si, Sj, j, cf, kq, nstep, theta, max_iter, err);
+    }
+}
+
+template <bool MIXED> constexpr int units_per_source() { return MIXED ? 1 : 2; }
+
 // Drive fields of all targets of the instance at stage times theta in
 // `thetas[0..nth)` (in steps after nstep), written to Eout[th * n + i].
-template <int BLOCK, bool MOVING>
+template <int BLOCK, bool MOVING, bool MIXED>
 __device__ void drive_all(const Hist &H, const DipLds *S, const double *qv, int n, int64_t nstep,
                           const double *thetas, int nth, double *Eout, int max_iter, uint32_t &err)
 {
-    const int M = 2 * (n - 1);                    // pairs per (target, stage)
+    constexpr int U = units_per_source<MIXED>();
+    const int M = U * (n - 1);                    // work units per (target, stage)
     const int G = nth * n;                        // (target, stage) groups
     int Lg = 1;
     while (Lg < M && Lg < 64) Lg <<= 1;
@@ -317,11 +552,9 @@ __device__ void drive_all(const Hist &H, const DipLds *S, const double *qv, int 
         if (g < G && M > 0) {
             const int th = g / n, i = g % n;
             for (int m = sub; m < M; m += Lg) {
-                const int jj = m >> 1, w = m & 1;
+                const int jj = m / U, w = m % U;
                 const int j = jj < i ? jj : jj + 1;
-                const double cf = w ? S[j].cfm : S[j].cfp;
-                const double kq = (w ? -qv[j] : qv[j]) * K_COUL;
-                acc += pair_drive<MOVING>(H, S[i], S[j], j, cf, kq, nstep, thetas[th], max_iter, err);
+                acc += unit_drive<MOVING, MIXED>(H, S[i], S[j], j, qv[j], w, nstep, thetas[th], max_iter, err);
             }
         }
         for (int off = 1; off < Lg; off <<= 1) acc += __shfl_xor(acc, off, 64);
@@ -329,7 +562,7 @@ __device__ void drive_all(const Hist &H, const DipLds *S, const double *qv, int 
     }
 }
 
-template <int BLOCK, bool RING_LDS, bool MOVING>
+template <int BLOCK, bool RING_LDS, bool MOVING, bool MIXED>
 __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__restrict__ dev,
                                                              const int32_t *__restrict__ off,
                                                              const int32_t *__restrict__ inst_list, int ring,
@@ -378,7 +611,7 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
     // t = 0: drive from the static pre-history, then sample 0 = (d0, 0, d_ddot(0))
     {
         const double th0[1] = {0.0};
-        drive_all<BLOCK, MOVING>(H, S, qv, n, 0, th0, 1, Ecur, max_iter, err);
+        drive_all<BLOCK, MOVING, MIXED>(H, S, qv, n, 0, th0, 1, Ecur, max_iter, err);
     }
     __syncthreads();
     for (int i = tid; i < n; i += BLOCK) {
@@ -396,7 +629,7 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
 
     const double thetas[2] = {0.5, 1.0};
     for (int64_t nstep = 0; nstep < steps; ++nstep) {
-        drive_all<BLOCK, MOVING>(H, S, qv, n, nstep, thetas, 2, Enew, max_iter, err);
+        drive_all<BLOCK, MOVING, MIXED>(H, S, qv, n, nstep, thetas, 2, Enew, max_iter, err);
         __syncthreads();
         for (int i = tid; i < n; i += BLOCK) {
             const double w2 = Kc[i], g = Kc[n + i], f = Kc[2 * n + i], vfac = Kc[3 * n + i], ms = Kc[4 * n + i];
@@ -448,7 +681,7 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
 // ---------------------------------------------------------------------------
 
 
-template <int BLOCK, bool MOVING>
+template <int BLOCK, bool MOVING, bool MIXED>
 __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict__ dev, const int32_t *__restrict__ tgt,
                                                         const int32_t *__restrict__ tgt_lo,
                                                         const int32_t *__restrict__ tgt_n,
@@ -470,19 +703,18 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
     Hist H{rp, n, ring_depth - 1, dt, 1.0 / dt};
     uint32_t err = 0u;
     const DipLds Si = dip_lds(dev[gi]);
-    const int M = 2 * (n - 1);                       // source charges
+    constexpr int U = units_per_source<MIXED>();
+    const int M = U * (n - 1);                       // work units per stage
     const int nth = init ? 1 : 2;
     double acc0 = 0.0, acc1 = 0.0;                   // stage t_n + dt/2 (or t = 0), stage t_n + dt
     for (int m = tid; m < nth * M; m += BLOCK) {
         const int th = m / M, mm = m - th * M;
-        const int jj = mm >> 1, w = mm & 1;
+        const int jj = mm / U, w = mm % U;
         const int j = jj < i ? jj : jj + 1;
         const DipLds Sj = soa_lds(soa, out.n_dip, (uint32_t)(i0 + j));
         const double qj = soa_get(soa, out.n_dip, SF_Q, (uint32_t)(i0 + j));
-        const double cf = w ? Sj.cfm : Sj.cfp;
-        const double kq = (w ? -qj : qj) * K_COUL;
         const double theta = init ? 0.0 : (th ? 1.0 : 0.5);
-        const double e = pair_drive<MOVING>(H, Si, Sj, j, cf, kq, nstep, theta, max_iter, err);
+        const double e = unit_drive<MOVING, MIXED>(H, Si, Sj, j, qj, w, nstep, theta, max_iter, err);
         if (th) acc1 += e; else acc0 += e;
     }
     red[0][tid] = acc0;
@@ -552,25 +784,34 @@ __global__ void step_reset_kernel(int64_t *step_ctr)
     if (threadIdx.x == 0 && blockIdx.x == 0) *step_ctr = 0;
 }
 
+// Calls fn(std::integral_constant<bool, a>, std::integral_constant<bool, b>).
+template <typename Fn> static void with_flags(bool a, bool b, Fn &&fn)
+{
+    if (a) {
+        if (b) fn(std::true_type{}, std::true_type{});
+        else fn(std::true_type{}, std::false_type{});
+    } else {
+        if (b) fn(std::false_type{}, std::true_type{});
+        else fn(std::false_type{}, std::false_type{});
+    }
+}
+
 hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const int32_t *d_tgt_lo, const int32_t *d_tgt_n,
                                const int64_t *d_ring_base, int n_tgt, double *d_ring, double *d_Ecur, double *d_W,
                                int64_t *d_step, int ring, int64_t steps, double dt, double max_vel, int max_iter,
-                               const RunOut &out, bool moving, uint32_t *d_err, int graph_chunk, hipStream_t s,
-                               hipStream_t cap, hipGraph_t *graph_out, hipGraphExec_t *exec_out)
+                               const RunOut &out, bool moving, bool mixed, uint32_t *d_err, int graph_chunk,
+                               hipStream_t s, hipStream_t cap, hipGraph_t *graph_out, hipGraphExec_t *exec_out)
 {
     constexpr int B = 256;
     if (n_tgt <= 0) return hipSuccess;
     const dim3 grid((unsigned)n_tgt), block(B);
     const double *soa = dip_soa(const_cast<DipDev *>(d_dev), out.n_dip);
     auto step = [&](hipStream_t q, int k, int init) {
-        if (moving)
-            hipLaunchKernelGGL((lo_step_kernel<B, true>), grid, block, 0, q, d_dev, d_tgt, d_tgt_lo, d_tgt_n,
-                               d_ring_base, d_ring, d_Ecur, d_W, d_step, k, ring, dt, max_vel, max_iter, init, out,
-                               soa, d_err);
-        else
-            hipLaunchKernelGGL((lo_step_kernel<B, false>), grid, block, 0, q, d_dev, d_tgt, d_tgt_lo, d_tgt_n,
-                               d_ring_base, d_ring, d_Ecur, d_W, d_step, k, ring, dt, max_vel, max_iter, init, out,
-                               soa, d_err);
+        with_flags(moving, mixed, [&](auto mv, auto mx) {
+            hipLaunchKernelGGL((lo_step_kernel<B, decltype(mv)::value, decltype(mx)::value>), grid, block, 0, q,
+                               d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_ring_base, d_ring, d_Ecur, d_W, d_step, k, ring, dt,
+                               max_vel, max_iter, init, out, soa, d_err);
+        });
     };
     hipLaunchKernelGGL(step_reset_kernel, dim3(1), dim3(1), 0, s, d_step);
     step(s, 0, 1);
@@ -613,38 +854,38 @@ int ring_lds_bytes(int n, int ring)
     return (int)(sizeof(DipLds) * n + sizeof(double) * 11 * n + sizeof(double) * 3 * (size_t)ring * n);
 }
 
-template <int BLOCK, bool MOVING>
-static hipError_t launch_lo(bool ring_lds, dim3 grid, size_t shmem, hipStream_t s, const DipDev *d_dev,
-                            const int32_t *d_off, const int32_t *d_list, int ring, int64_t steps, double dt,
-                            double max_vel, int max_iter, double *d_ring_global, const int64_t *d_ring_off,
-                            const RunOut &out, uint32_t *d_err)
+template <int BLOCK>
+static hipError_t launch_lo(bool ring_lds, bool moving, bool mixed, dim3 grid, size_t shmem, hipStream_t s,
+                            const DipDev *d_dev, const int32_t *d_off, const int32_t *d_list, int ring, int64_t steps,
+                            double dt, double max_vel, int max_iter, double *d_ring_global,
+                            const int64_t *d_ring_off, const RunOut &out, uint32_t *d_err)
 {
-    if (ring_lds)
-        hipLaunchKernelGGL((lo_instances_kernel<BLOCK, true, MOVING>), grid, dim3(BLOCK), shmem, s, d_dev, d_off,
-                           d_list, ring, steps, dt, max_vel, max_iter, d_ring_global, d_ring_off, out, d_err);
-    else
-        hipLaunchKernelGGL((lo_instances_kernel<BLOCK, false, MOVING>), grid, dim3(BLOCK), shmem, s, d_dev, d_off,
-                           d_list, ring, steps, dt, max_vel, max_iter, d_ring_global, d_ring_off, out, d_err);
+    with_flags(moving, mixed, [&](auto mv, auto mx) {
+        constexpr bool MV = decltype(mv)::value, MX = decltype(mx)::value;
+        if (ring_lds)
+            hipLaunchKernelGGL((lo_instances_kernel<BLOCK, true, MV, MX>), grid, dim3(BLOCK), shmem, s, d_dev, d_off,
+                               d_list, ring, steps, dt, max_vel, max_iter, d_ring_global, d_ring_off, out, d_err);
+        else
+            hipLaunchKernelGGL((lo_instances_kernel<BLOCK, false, MV, MX>), grid, dim3(BLOCK), shmem, s, d_dev,
+                               d_off, d_list, ring, steps, dt, max_vel, max_iter, d_ring_global, d_ring_off, out,
+                               d_err);
+    });
     return hipGetLastError();
 }
 
 hipError_t launch_dipole_instances(const DipDev *d_dev, const int32_t *d_off, const int32_t *d_list, int n_list,
                                    int max_n, bool ring_lds, const int64_t *d_ring_off, double *d_ring_global,
                                    int ring, int64_t steps, double dt, double max_vel, int max_iter,
-                                   const RunOut &out, bool moving, uint32_t *d_err, hipStream_t s)
+                                   const RunOut &out, bool moving, bool mixed, uint32_t *d_err, hipStream_t s)
 {
     if (n_list <= 0) return hipSuccess;
     const size_t shmem = (size_t)ring_lds_bytes(max_n, ring_lds ? ring : 0);
     const dim3 grid((unsigned)n_list);
     if (max_n <= 8)
-        return moving ? launch_lo<64, true>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel,
-                                            max_iter, d_ring_global, d_ring_off, out, d_err)
-                      : launch_lo<64, false>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel,
-                                             max_iter, d_ring_global, d_ring_off, out, d_err);
-    return moving ? launch_lo<256, true>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel,
-                                         max_iter, d_ring_global, d_ring_off, out, d_err)
-                  : launch_lo<256, false>(ring_lds, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel,
-                                          max_iter, d_ring_global, d_ring_off, out, d_err);
+        return launch_lo<64>(ring_lds, moving, mixed, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel,
+                             max_iter, d_ring_global, d_ring_off, out, d_err);
+    return launch_lo<256>(ring_lds, moving, mixed, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel,
+                          max_iter, d_ring_global, d_ring_off, out, d_err);
 }
 
 }  // namespace lw

@@ -61,17 +61,18 @@ hipError_t launch_dipole_prep(const lw_dipole *d_in, int n, DipDev *d_dev, hipSt
 hipError_t launch_dipole_instances(const DipDev *d_dev, const int32_t *d_off, const int32_t *d_list, int n_list,
                                    int max_n, bool ring_lds, const int64_t *d_ring_off, double *d_ring_global,
                                    int ring, int64_t steps, double dt, double max_vel, int max_iter,
-                                   const RunOut &out, bool moving, uint32_t *d_err, hipStream_t s);
+                                   const RunOut &out, bool moving, bool mixed, uint32_t *d_err, hipStream_t s);
 
 // moving: some dipole's origin moves (kernels with the moving-origin code).
+// mixed: FP32 pair fields (FP64 retarded times, state and sums).
 // Large instances: one launch per step (captured into a replayed graph when
 // graph_chunk > 0 and a capture stream is given), one workgroup per target.
 // d_W: 2 doubles per dipole of running energy sums (absorbed, radiated).
 hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const int32_t *d_tgt_lo, const int32_t *d_tgt_n,
                                const int64_t *d_ring_base, int n_tgt, double *d_ring, double *d_Ecur, double *d_W,
                                int64_t *d_step, int ring, int64_t steps, double dt, double max_vel, int max_iter,
-                               const RunOut &out, bool moving, uint32_t *d_err, int graph_chunk, hipStream_t s,
-                               hipStream_t cap, hipGraph_t *graph_out, hipGraphExec_t *exec_out);
+                               const RunOut &out, bool moving, bool mixed, uint32_t *d_err, int graph_chunk,
+                               hipStream_t s, hipStream_t cap, hipGraph_t *graph_out, hipGraphExec_t *exec_out);
 
 // Gradient of the detector objective with respect to the oscillator positions
 // from a finished stride-1 run (lw_dipole_adjoint.hip).  d_hist / d_hbar hold

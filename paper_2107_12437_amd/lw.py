@@ -313,11 +313,13 @@ class LWFieldsFn(torch.autograd.Function):
 
 def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "strict", out_stride: int = 1,
                max_vel: float = 0.0, ring_depth: int = 0, stepped_min_n: int = 0, device=None, check: bool = True,
-               ctx: Context | None = None, energy_balance: bool = False):
+               ctx: Context | None = None, energy_balance: bool = False, precision: str = "fp64"):
     """Self-consistent oscillator run (Algorithm 1).  Returns a dict of [n_out][n_dip]
     float64 GPU tensors: d, d_dot, energy, Ed, and with energy_balance the work absorbed
     from the drive field W_abs and the Larmor energy radiated W_rad since t = 0 (Sec. 2.5:
-    the sum over an instance of energy - W_abs + W_rad is conserved)."""
+    the sum over an instance of energy - W_abs + W_rad is conserved).  precision "mixed"
+    evaluates each source dipole's pair field in FP32 (retarded times, state and sums stay
+    FP64)."""
     dev = _as_device(device)
     ctx = ctx or default_context(dev.index)
     arr, n = pack_dipoles(dipoles)
@@ -325,7 +327,8 @@ def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "st
     n_out = int(steps) // int(out_stride) + 1
     keys = ("d", "d_dot", "energy", "Ed") + (("W_abs", "W_rad") if energy_balance else ())
     res = {k: torch.empty((n_out, n), dtype=torch.float64, device=dev) for k in keys}
-    opts = RunOpts(FP64, DT_POLICIES[policy], int(out_stride), float(max_vel), int(ring_depth), int(stepped_min_n))
+    opts = RunOpts(PRECISIONS[precision], DT_POLICIES[policy], int(out_stride), float(max_vel), int(ring_depth),
+                   int(stepped_min_n))
     L = load_library()
     _check(L.lw_dipole_run(ctx.handle, arr, n, off.ctypes.data_as(ct.POINTER(ct.c_int32)), len(off) - 1,
                            float(dt), int(steps), ct.byref(opts), ct.c_void_p(res["d"].data_ptr()),
