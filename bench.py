@@ -88,7 +88,7 @@ def errors(got, ref):
     return res
 
 
-def run_part(part: str, cluster_steps: int, I, lw, torch):
+def run_part(part: str, cluster_steps: int, precision: str, I, lw, torch):
     """One workload alone: a warm-up call, then one timed call (for profiler runs)."""
     if part == "pairs":
         pw = I.workload_dipole_pairs()
@@ -101,7 +101,8 @@ def run_part(part: str, cluster_steps: int, I, lw, torch):
         cw = I.workload_clusters(steps=cluster_steps)
 
         def call(steps):
-            lw.dipole_run(cw["dipoles"], cw["inst_off"], cw["dt"], steps, out_stride=10, check=False)
+            lw.dipole_run(cw["dipoles"], cw["inst_off"], cw["dt"], steps, out_stride=10, check=False,
+                          precision=precision)
         call(10)
         steps = cw["steps"]
     elif part == "grid-vjp":
@@ -143,6 +144,8 @@ def main():
                     help="steps of the uneven-cluster workload to time")
     ap.add_argument("--grid-only", action="store_true",
                     help="time only the mixed grid step (for profiler runs)")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+                    help="precision of the cluster run in --part clusters")
     ap.add_argument("--part", choices=("pairs", "clusters", "grid-vjp", "adjoint"), default=None,
                     help="run only this workload once after one warm-up, print its time and exit "
                          "(for profiler runs; --cluster-steps sets the cluster run's length)")
@@ -176,7 +179,7 @@ def main():
         log(f"[bench] copied {4 * n} bytes")
         return
     if args.part:
-        run_part(args.part, args.cluster_steps, I, lw, torch)
+        run_part(args.part, args.cluster_steps, args.precision, I, lw, torch)
         return
     w = I.workload_grid_mixed()
     pts = torch.tensor(w["points"], dtype=torch.float64, device="cuda")
@@ -292,18 +295,23 @@ def main():
     if not args.no_dipole:
         cw = I.workload_clusters(steps=args.cluster_steps)
         n_c = len(cw["dipoles"]["omega0"])
-        lw.dipole_run(cw["dipoles"], cw["inst_off"], cw["dt"], 10, out_stride=10)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        lw.dipole_run(cw["dipoles"], cw["inst_off"], cw["dt"], cw["steps"], out_stride=10, check=False)
-        torch.cuda.synchronize()
-        csec = time.perf_counter() - t0
-        lw.sync_status()
         clusters = {"workload": cw["name"], "dipoles": n_c, "steps": cw["steps"],
-                    "dipole_steps_per_s": n_c * cw["steps"] / csec, "ms": round(csec * 1e3, 3), "dtype": "f64",
-                    "note": "the uneven-cluster workload runs 50,000 steps; this line times a prefix of it"}
-        log(f"[bench] clusters: {csec * 1e3:.1f} ms for {cw['steps']} steps, "
-            f"{clusters['dipole_steps_per_s']:.3e} dipole-steps/s")
+                    "note": "the uneven-cluster workload runs 50,000 steps; this line times a prefix of it. "
+                            "mixed: FP32 velocity and radiation terms of each source dipole, FP64 static "
+                            "near-field term, retarded times, state and sums"}
+        for prec in ("fp64", "mixed"):
+            lw.dipole_run(cw["dipoles"], cw["inst_off"], cw["dt"], 10, out_stride=10, precision=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lw.dipole_run(cw["dipoles"], cw["inst_off"], cw["dt"], cw["steps"], out_stride=10, check=False,
+                          precision=prec)
+            torch.cuda.synchronize()
+            csec = time.perf_counter() - t0
+            lw.sync_status()
+            clusters[prec] = {"dipole_steps_per_s": n_c * cw["steps"] / csec, "ms": round(csec * 1e3, 3)}
+            log(f"[bench] clusters ({prec}): {csec * 1e3:.1f} ms for {cw['steps']} steps, "
+                f"{clusters[prec]['dipole_steps_per_s']:.3e} dipole-steps/s")
+        clusters["mixed_over_fp64"] = round(clusters["fp64"]["ms"] / clusters["mixed"]["ms"], 3)
         dw = I.workload_detector()
         dpts = torch.tensor(dw["points"], dtype=torch.float64, device="cuda")
         dout, _ = lw.fields(dw["charges"], dpts, dw["times"], precision="fp64")

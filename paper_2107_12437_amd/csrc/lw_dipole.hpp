@@ -94,6 +94,80 @@ __device__ __forceinline__ DipLds dip_lds(const DipDev &D)
 
 enum { ERR_HISTORY = 1u, ERR_NOCONV = 2u, ERR_VELOCITY = 4u, ERR_NONFINITE = 8u };
 
+// Stored samples k and k + 1 of one source; k = -1 stands for the static
+// pre-history (t' < 0), where the state is (d0, 0, 0).
+struct Seg {
+    int64_t k;
+    double d0, v0, a0;    // sample k: d, d_dot, d_ddot
+    double d1, v1, a1;    // sample k + 1
+};
+
+__device__ __forceinline__ void seg_load(const Hist &H, int j, double d0, int64_t nstep, int64_t k, Seg &g,
+                                         uint32_t &err)
+{
+    // k = -1 reads ring slot `mask` (in bounds) and discards it
+    const bool pre = k < 0;
+    g.k = pre ? -1 : k;
+    if (!pre && k + H.mask < nstep) err |= ERR_HISTORY;   // the slot was overwritten: history too short
+    const double *p0 = H.ring + ((int64_t)(g.k & H.mask) * H.n + j) * 3;
+    const double *p1 = H.ring + ((int64_t)((g.k + 1) & H.mask) * H.n + j) * 3;
+    g.d0 = pre ? d0 : p0[0];
+    g.v0 = pre ? 0.0 : p0[1];
+    g.a0 = pre ? 0.0 : p0[2];
+    g.d1 = pre ? d0 : p1[0];
+    g.v1 = pre ? 0.0 : p1[1];
+    g.a1 = pre ? 0.0 : p1[2];
+}
+
+// Retarded time of the charge at offset cf d(t') p_j of a fixed source j, in
+// closed form on the interpolated history.  Within the segment [k, k + 1] of
+// stored steps the moment is linear in tau (t' = t - tau), so the charge's
+// offset is rho = a + b tau and c tau = |Delta - rho p_j| becomes
+//   (c^2 - b^2) tau^2 + 2 b P tau - Q = 0,
+// P = sD - a, Q = |Delta - a p_j|^2 = L2 - 2 a sD + a^2, whose positive root
+// tau = Q / (b P + sqrt(b^2 P^2 + (c^2 - b^2) Q)) has no cancellation
+// (|b| << c).  The root is unique (the charge is slower than light), so if it
+// falls outside the loaded segment it lies in the segment its own s points to,
+// which is loaded next.  Returns false when the root lies past the newest
+// stored step (the caller then uses the Newton solve with the extrapolation)
+// or the hops do not settle.  On success tau_out is the root, h the
+// interpolated state there and g the segment it lies in.
+__device__ __forceinline__ bool retarded_seg(const Hist &H, int j, double d0, int64_t nstep, double base, double L2,
+                                             double sD, double cf, Seg &g, double h[3], double &tau_out,
+                                             uint32_t &err)
+{
+    constexpr double C2 = C_LIGHT * C_LIGHT;
+    for (int hop = 0; hop < 4; ++hop) {
+        double a = cf * d0, b = 0.0;
+        if (g.k >= 0) {
+            const double dd = g.d1 - g.d0;
+            a = cf * fma(base - (double)g.k, dd, g.d0);
+            b = -cf * dd * H.inv_dt;
+        }
+        const double P = sD - a;
+        const double Q = fma(a, a - 2.0 * sD, L2);
+        const double bP = b * P;
+        double S, iS;
+        root_rsqrt<true>(fma(bP, bP, (C2 - b * b) * Q), S, iS);
+        const double tau = Q * recip<double>(bP + S);
+        const double s = base - tau * H.inv_dt;
+        // a root within rounding of a segment end belongs to either side
+        const double eps = 1e-9;
+        if (g.k < 0 ? s <= eps : (s >= (double)g.k - eps && s <= (double)g.k + 1.0 + eps)) {
+            const double u = g.k < 0 ? 0.0 : s - (double)g.k;
+            h[0] = fma(u, g.d1 - g.d0, g.d0);
+            h[1] = fma(u, g.v1 - g.v0, g.v0);
+            h[2] = fma(u, g.a1 - g.a0, g.a0);
+            tau_out = tau;
+            return true;
+        }
+        const int64_t kn = s < 0.0 ? -1 : (int64_t)floor(s);
+        if (kn >= nstep) return false;
+        seg_load(H, j, d0, nstep, kn, g, err);
+    }
+    return false;
+}
+
 // Larmor power per |d_ddot|^2 (Sec. 2.5): 1 / (6 pi eps0 c^3).
 constexpr double K_LARMOR = 1.0 / (6.0 * PI * EPS0 * C_LIGHT * C_LIGHT * C_LIGHT);
 

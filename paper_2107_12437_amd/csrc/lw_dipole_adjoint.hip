@@ -93,7 +93,23 @@ __device__ void pair_solve(const Hist &H, const double x[3], const DipLds &Sj, i
     double tau = (tau_init > 0.0 && tau_init < b.hi) ? tau_init : L * INV_C;
     const double tol = 4.0 * 2.220446049250313e-16;
     bool ok = false;
-    for (int it = 0; it < max_iter; ++it) {
+    // the closed form on the interpolated history (retarded_seg) from the
+    // start's segment; Newton past the newest stored step
+    {
+        const double s0 = base - tau * H.inv_dt;
+        const int64_t k0 = s0 < 0.0 ? -1 : (int64_t)floor(s0);
+        if (k0 < nstep) {
+            Seg g;
+            seg_load(H, j, Sj.d0, nstep, k0, g, err);
+            double hh[3], tc;
+            if (retarded_seg(H, j, Sj.d0, nstep, base, L2, sD, cf, g, hh, tc, err)) {
+                tau = tc;
+                hist_eval(H, j, Sj.d0, nstep, base - tau * H.inv_dt, e);
+                ok = true;
+            }
+        }
+    }
+    for (int it = 0; it < max_iter && !ok; ++it) {
         const double s = base - tau * H.inv_dt;
         hist_eval(H, j, Sj.d0, nstep, s, e);
         const double rho = cf * e.d;
