@@ -481,26 +481,50 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
     }
     // separations inside each instance: distinct origins, the dt rule, and the
     // longest light travel time (history depth)
-    double max_sep = 0.0;
+    // (squared distances for fixed pairs; moving origins (Sec. 4.3) stay within
+    // their amplitudes of the mean position)
+    std::vector<double> reach((size_t)n_dip);
+    for (int i = 0; i < n_dip; ++i) reach[i] = motion_reach(h_dip[i]);
+    const bool strict = opts->dt_policy == LW_DT_STRICT;
+    const double cdt = C_LIGHT * dt, cdt2 = cdt * cdt;
+    double max_sep = 0.0, max_r2 = 0.0;
     int max_n = 0;
-    for (int k = 0; k < n_inst; ++k) {
+    int bad_a = -1, bad_b = -1;
+    lw_status bad = LW_OK;
+    for (int k = 0; k < n_inst && bad == LW_OK; ++k) {
         const int a0 = h_inst_off[k], a1 = h_inst_off[k + 1];
         if (a1 < a0) return fail(LW_E_INVALID, "lw_dipole_run: decreasing instance offsets");
         max_n = std::max(max_n, a1 - a0);
-        for (int a = a0; a < a1; ++a)
+        for (int a = a0; a < a1 && bad == LW_OK; ++a) {
+            const double *oa = h_dip[a].origin;
             for (int b = a + 1; b < a1; ++b) {
-                const double d[3] = {h_dip[a].origin[0] - h_dip[b].origin[0], h_dip[a].origin[1] - h_dip[b].origin[1],
-                                     h_dip[a].origin[2] - h_dip[b].origin[2]};
-                const double r = norm3(d);
-                // moving origins (Sec. 4.3) stay within their amplitudes of the mean position
-                const double swing = motion_reach(h_dip[a]) + motion_reach(h_dip[b]);
-                if (!(r - swing > 0.0)) return fail(LW_E_INVALID, "lw_dipole_run: two dipoles can share an origin");
-                if (opts->dt_policy == LW_DT_STRICT && !(C_LIGHT * dt < r - swing))
-                    return fail(LW_E_DT_TOO_LARGE, "lw_dipole_run: c*dt is not below the separation of dipoles " +
-                                                       std::to_string(a) + " and " + std::to_string(b));
-                max_sep = std::max(max_sep, r + swing);
+                const double *ob = h_dip[b].origin;
+                const double dx = oa[0] - ob[0], dy = oa[1] - ob[1], dz = oa[2] - ob[2];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double swing = reach[a] + reach[b];
+                if (swing == 0.0) {
+                    max_r2 = std::max(max_r2, r2);
+                    if (!(r2 > 0.0)) bad = LW_E_INVALID;
+                    else if (strict && !(cdt2 < r2)) bad = LW_E_DT_TOO_LARGE;
+                } else {
+                    const double r = std::sqrt(r2);
+                    max_sep = std::max(max_sep, r + swing);
+                    if (!(r - swing > 0.0)) bad = LW_E_INVALID;
+                    else if (strict && !(cdt < r - swing)) bad = LW_E_DT_TOO_LARGE;
+                }
+                if (bad != LW_OK) {
+                    bad_a = a;
+                    bad_b = b;
+                    break;
+                }
             }
+        }
     }
+    if (bad == LW_E_INVALID) return fail(LW_E_INVALID, "lw_dipole_run: two dipoles can share an origin");
+    if (bad == LW_E_DT_TOO_LARGE)
+        return fail(LW_E_DT_TOO_LARGE, "lw_dipole_run: c*dt is not below the separation of dipoles " +
+                                           std::to_string(bad_a) + " and " + std::to_string(bad_b));
+    max_sep = std::max(max_sep, std::sqrt(max_r2));
     // depth: the longest retarded time (plus the charges' own excursion) in
     // steps, two interpolation neighbours and one step of slack
     const double need = std::ceil(2.0 * max_sep / C_LIGHT / dt) + 3.0;

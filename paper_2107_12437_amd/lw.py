@@ -185,22 +185,19 @@ def pack_charges(charges: dict):
 
 
 def pack_dipoles(dipoles: dict):
+    """lw_dipole records (16 doubles each, in the field order of the C struct) for the
+    dipoles, as a ctypes array over one numpy buffer."""
     n = len(dipoles["omega0"])
-    arr = (Dipole * max(n, 1))()
-    for i in range(n):
-        d = arr[i]
-        d.origin[:] = [float(v) for v in dipoles["origin"][i]]
-        d.axis[:] = [float(v) for v in dipoles["axis"][i]]
-        d.omega0 = float(dipoles["omega0"][i])
-        d.q = float(dipoles["q"][i])
-        d.m1 = float(dipoles["m1"][i])
-        d.m2 = float(dipoles["m2"][i])
-        d.d0 = float(dipoles["d0"][i])
-        if "motion_amp" in dipoles:
-            d.motion_amp[:] = [float(v) for v in dipoles["motion_amp"][i]]
-            d.motion_omega = float(dipoles["motion_omega"][i])
-            d.motion_phase = float(dipoles["motion_phase"][i])
-    return arr, n
+    a = np.zeros((max(n, 1), 16), dtype=np.float64)
+    a[:n, 0:3] = np.asarray(dipoles["origin"], dtype=np.float64).reshape(n, 3)
+    a[:n, 3:6] = np.asarray(dipoles["axis"], dtype=np.float64).reshape(n, 3)
+    for col, key in ((6, "omega0"), (7, "q"), (8, "m1"), (9, "m2"), (10, "d0")):
+        a[:n, col] = np.asarray(dipoles[key], dtype=np.float64).reshape(n)
+    if "motion_amp" in dipoles:
+        a[:n, 11:14] = np.asarray(dipoles["motion_amp"], dtype=np.float64).reshape(n, 3)
+        a[:n, 14] = np.asarray(dipoles["motion_omega"], dtype=np.float64).reshape(n)
+        a[:n, 15] = np.asarray(dipoles["motion_phase"], dtype=np.float64).reshape(n)
+    return (Dipole * max(n, 1)).from_buffer(a), n
 
 
 class FieldsCall:

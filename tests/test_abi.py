@@ -68,3 +68,24 @@ def test_pair_modes_rejects_bad_arguments():
     with pytest.raises(lw.LWError) as ei:
         lw.pair_modes(np.zeros((10, 2)), [0, 2], -1.0, 1, 1e15, 0)
     assert ei.value.code == 1
+
+
+def test_dipole_packing_matches_the_struct_fields():
+    """pack_dipoles writes each field where the C struct (lw_dipole) has it."""
+    from paper_2107_12437_amd import lw
+    rng = np.random.default_rng(5)
+    n = 7
+    dip = I.empty_dipoles(n)
+    dip["origin"][:] = rng.normal(size=(n, 3))
+    dip["axis"][:] = I.unit_sphere(rng, n)
+    for k in ("omega0", "q", "m1", "m2", "d0", "motion_omega", "motion_phase"):
+        dip[k][:] = rng.uniform(1, 2, size=n)
+    dip["motion_amp"][:] = rng.normal(size=(n, 3))
+    arr, m = lw.pack_dipoles(dip)
+    assert m == n
+    for i in range(n):
+        d = arr[i]
+        assert list(d.origin) == list(dip["origin"][i]) and list(d.axis) == list(dip["axis"][i])
+        for k in ("omega0", "q", "m1", "m2", "d0", "motion_omega", "motion_phase"):
+            assert getattr(d, k) == dip[k][i], k
+        assert list(d.motion_amp) == list(dip["motion_amp"][i])
