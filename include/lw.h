@@ -284,6 +284,28 @@ lw_status lw_pair_modes(const double *h_moment, int64_t n_rows, int32_t n_dip, c
  * (Sec. 2.3) of an oscillator with reduced mass m. */
 double lw_gamma0(double q, double m, double omega0);
 
+/* Coupling of two identical dipoles (axes p1, p2, resonance omega0) at
+ * separation R from the free-space dyadic Green's function of App. A,
+ * G = k^2 e^{ikR}/(4 pi R) [(1 + (ikR - 1)/(kR)^2) I + (3 - 3ikR - (kR)^2)/(kR)^2 R^R^]
+ * at k = omega0/c, with gamma_0 from Im G(r, r) = k^3/(6 pi):
+ *   out[0] = delta_12 / gamma_0 = -Re(p1.G.p2) / (2 Im G(r, r))   (Eq. (qed_delta))
+ *   out[1] = gamma_12 / gamma_0 =  Im(p1.G.p2) / Im G(r, r)        (Eq. (qed_gamma_ab))
+ * so that gamma_+- = gamma_0 (1 +- out[1]) (Eq. (gamma_super_sub)).
+ * R, p1, p2: host, 3 doubles (p1, p2 unit).  Host only; LW_E_INVALID on bad
+ * arguments. */
+lw_status lw_gf_pair(const double *R, const double *p1, const double *p2, double omega0, double *out);
+
+/* Exact classical normal modes of two identical oscillators (charge q, reduced
+ * mass m, resonance omega0, common unit axis p) at separation R, without the
+ * Markov approximation of the Green's-function rates: the roots omega near
+ * omega0 of Eq. (LO_equation) with the other dipole's field as drive,
+ *   omega0^2 - omega^2 - i gamma_0 omega = +-(q^2 / (m eps0)) p.G(omega).p,
+ * for the in-phase (+) and antiphase (-) modes, by complex Newton from
+ * omega0 - i gamma_0/2.  out[0] = gamma_+ = -2 Im omega_+, out[1] = gamma_-,
+ * out[2] = Re omega_+, out[3] = Re omega_-, out[4] = (Re omega_+ - Re omega_-)/2.
+ * Host only; LW_E_INVALID on bad arguments, LW_E_NOCONV if Newton fails. */
+lw_status lw_exact_modes(const double *R, const double *p, double q, double m, double omega0, double *out);
+
 #ifdef __cplusplus
 }
 #endif

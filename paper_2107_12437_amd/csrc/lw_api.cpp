@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -224,6 +225,86 @@ const char *lw_last_error(void) { return g_last_error.c_str(); }
 double lw_gamma0(double q, double m, double omega0)
 {
     return q * q * omega0 * omega0 / (6.0 * PI * EPS0 * C_LIGHT * C_LIGHT * C_LIGHT * m);
+}
+
+namespace {
+
+using cplx = std::complex<double>;
+
+// p1 . G(R, omega) . p2 for the free-space dyadic Green's function of App. A in
+// the form k^2 e^{ikR} / (4 pi R) [(1 + (ikR - 1)/(kR)^2) I + (3 - 3ikR - (kR)^2)/(kR)^2 R^R^]
+// (the field of a dipole d is G d / eps0), and its derivative in k.
+void green_pp(const double R[3], const double p1[3], const double p2[3], cplx k, cplx &G, cplx &dG)
+{
+    const double r = norm3(R);
+    const double c1 = (p1[0] * R[0] + p1[1] * R[1] + p1[2] * R[2]) / r;
+    const double c2 = (p2[0] * R[0] + p2[1] * R[1] + p2[2] * R[2]) / r;
+    const double pp = p1[0] * p2[0] + p1[1] * p2[1] + p1[2] * p2[2];
+    const cplx I(0.0, 1.0);
+    // G = e^{ikr} / (4 pi r^3) [pp (k^2 r^2 + ikr - 1) + c1 c2 (3 - 3ikr - k^2 r^2)]
+    const cplx e = std::exp(I * k * r) / (4.0 * PI * r * r * r);
+    const cplx a = pp * (k * k * r * r + I * k * r - 1.0) + c1 * c2 * (3.0 - 3.0 * I * k * r - k * k * r * r);
+    const cplx da = pp * (2.0 * k * r * r + I * r) + c1 * c2 * (-3.0 * I * r - 2.0 * k * r * r);
+    G = e * a;
+    dG = e * (I * r * a + da);
+}
+
+}  // namespace
+
+lw_status lw_gf_pair(const double *R, const double *p1, const double *p2, double omega0, double *out)
+{
+    if (!R || !p1 || !p2 || !out) return fail(LW_E_INVALID, "lw_gf_pair: null argument");
+    if (!finite3(R) || !(norm3(R) > 0.0) || !unit3(p1) || !unit3(p2) || !(omega0 > 0.0) || !std::isfinite(omega0))
+        return fail(LW_E_INVALID, "lw_gf_pair: bad separation, axes or frequency");
+    const double k = omega0 / C_LIGHT;
+    cplx G, dG;
+    green_pp(R, p1, p2, cplx(k, 0.0), G, dG);
+    const double im_self = k * k * k / (6.0 * PI);      // Im G(r, r) for a unit axis
+    out[0] = -G.real() / (2.0 * im_self);               // delta_12 / gamma_0   (Eq. (qed_delta))
+    out[1] = G.imag() / im_self;                        // gamma_12 / gamma_0   (Eq. (qed_gamma_ab))
+    return LW_OK;
+}
+
+lw_status lw_exact_modes(const double *R, const double *p, double q, double m, double omega0, double *out)
+{
+    if (!R || !p || !out) return fail(LW_E_INVALID, "lw_exact_modes: null argument");
+    if (!finite3(R) || !(norm3(R) > 0.0) || !unit3(p) || !(q > 0.0) || !(m > 0.0) || !(omega0 > 0.0) ||
+        !std::isfinite(q) || !std::isfinite(m) || !std::isfinite(omega0))
+        return fail(LW_E_INVALID, "lw_exact_modes: bad arguments");
+    // d1, d2 ~ e^{-i omega t}: the oscillator equation with the drive of the other
+    // dipole's field at its origin, p . E = (1/eps0) p . G . p d (G as above at
+    // k = omega / c), gives for d2 = +-d1
+    //   F(omega) = omega0^2 - omega^2 - i gamma0 omega -+ (q^2 / (m eps0)) p.G(omega).p = 0
+    const double g0 = lw_gamma0(q, m, omega0);
+    const double f = q * q / (m * EPS0);
+    const cplx I(0.0, 1.0);
+    cplx roots[2];
+    for (int s = 0; s < 2; ++s) {
+        const double sign = s == 0 ? 1.0 : -1.0;
+        cplx w(omega0, -0.5 * g0);
+        bool ok = false;
+        for (int it = 0; it < 100; ++it) {
+            cplx G, dG;
+            green_pp(R, p, p, w / C_LIGHT, G, dG);
+            const cplx F = omega0 * omega0 - w * w - I * g0 * w - sign * f * G;
+            const cplx dF = -2.0 * w - I * g0 - sign * f * dG / C_LIGHT;
+            const cplx dw = F / dF;
+            w -= dw;
+            if (std::abs(dw) <= 1e-15 * std::abs(w)) {
+                ok = true;
+                break;
+            }
+        }
+        if (!ok || !std::isfinite(w.real()) || !std::isfinite(w.imag()))
+            return fail(LW_E_NOCONV, "lw_exact_modes: the mode root did not converge");
+        roots[s] = w;
+    }
+    out[0] = -2.0 * roots[0].imag();                    // gamma_+ (in-phase mode)
+    out[1] = -2.0 * roots[1].imag();                    // gamma_- (antiphase mode)
+    out[2] = roots[0].real();
+    out[3] = roots[1].real();
+    out[4] = 0.5 * (roots[0].real() - roots[1].real());
+    return LW_OK;
 }
 
 lw_status lw_create(lw_ctx **out, int32_t device)

@@ -45,7 +45,8 @@ STATUS_NAMES = {0: "LW_OK", 1: "LW_E_INVALID", 2: "LW_E_SUPERLUMINAL", 3: "LW_E_
                 4: "LW_E_VELOCITY", 5: "LW_E_NOCONV", 6: "LW_E_HIP", 7: "LW_E_NOMEM",
                 8: "LW_E_NONFINITE", 9: "LW_E_HISTORY"}
 EXPORTS = ("lw_last_error", "lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields",
-           "lw_fields_vjp", "lw_dipole_run", "lw_dipole_run_vjp", "lw_pair_modes", "lw_gamma0")
+           "lw_fields_vjp", "lw_dipole_run", "lw_dipole_run_vjp", "lw_pair_modes", "lw_gamma0", "lw_gf_pair",
+           "lw_exact_modes")
 PARAM_NAMES = ("q", "c0x", "c0y", "c0z", "amp", "omega", "phase", "accel", "vx", "vy", "vz")
 OUTPUT_NAMES = ("phi", "Ax", "Ay", "Az", "Ex", "Ey", "Ez", "Bx", "By", "Bz")
 
@@ -107,8 +108,10 @@ def load_library(path: str = LIB_PATH):
                                 ct.POINTER(dbl), ct.POINTER(i64), ct.POINTER(dbl)]
     L.lw_gamma0.restype = dbl
     L.lw_gamma0.argtypes = [dbl, dbl, dbl]
+    L.lw_gf_pair.argtypes = [ct.POINTER(dbl), ct.POINTER(dbl), ct.POINTER(dbl), dbl, ct.POINTER(dbl)]
+    L.lw_exact_modes.argtypes = [ct.POINTER(dbl), ct.POINTER(dbl), dbl, dbl, dbl, ct.POINTER(dbl)]
     for name in ("lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields", "lw_fields_vjp",
-                 "lw_dipole_run", "lw_dipole_run_vjp", "lw_pair_modes"):
+                 "lw_dipole_run", "lw_dipole_run_vjp", "lw_pair_modes", "lw_gf_pair", "lw_exact_modes"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -407,3 +410,24 @@ def pair_modes(moment, inst_off, dt: float, out_stride: int, omega_ref, skip_ste
 
 def gamma0(q: float, m: float, omega0: float) -> float:
     return float(load_library().lw_gamma0(q, m, omega0))
+
+
+def _vec3(v):
+    a = (ct.c_double * 3)(*[float(x) for x in np.asarray(v, dtype=np.float64).reshape(3)])
+    return a
+
+
+def gf_pair(R, p1, p2, omega0: float) -> tuple[float, float]:
+    """(delta_12 / gamma_0, gamma_12 / gamma_0) of two identical dipoles with axes p1, p2
+    at separation vector R from the free-space dyadic Green's function (App. A)."""
+    out = (ct.c_double * 2)()
+    _check(load_library().lw_gf_pair(_vec3(R), _vec3(p1), _vec3(p2), float(omega0), out))
+    return out[0], out[1]
+
+
+def exact_modes(R, p, q: float, m: float, omega0: float) -> dict:
+    """Exact classical normal modes of two identical oscillators with common axis p at
+    separation vector R: gamma_plus, gamma_minus, omega_plus, omega_minus, delta_omega."""
+    out = (ct.c_double * 5)()
+    _check(load_library().lw_exact_modes(_vec3(R), _vec3(p), float(q), float(m), float(omega0), out))
+    return dict(zip(("gamma_plus", "gamma_minus", "omega_plus", "omega_minus", "delta_omega"), list(out)))
