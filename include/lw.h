@@ -52,7 +52,8 @@ enum {
     LW_E_HIP = 6,           /* a HIP runtime call failed                                        */
     LW_E_NOMEM = 7,         /* device or host allocation failed                                 */
     LW_E_NONFINITE = 8,     /* an oscillator state became NaN or Inf                            */
-    LW_E_HISTORY = 9        /* a retarded time fell outside the stored history window           */
+    LW_E_HISTORY = 9,       /* a retarded time fell outside the stored history window           */
+    LW_E_STATE = 10         /* a resumed run's state was written for other dipoles or depth     */
 };
 
 /* Message for the last failed call on this thread ("" if none). */
@@ -239,6 +240,33 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
                         int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts,
                         double *d_moment, double *d_dot, double *d_energy, double *d_drive,
                         double *d_wabs, double *d_wrad, void *stream);
+
+/* Run state of an oscillator run, for checkpoints and resumed runs: the step
+ * count, every dipole's history ring (the stored (d, d_dot, d_ddot) of the
+ * last `ring` steps), E_d at the last step and the two energy sums, FP64 on
+ * the device.  *n_doubles receives its size in doubles for these arguments
+ * (the history depth follows from the geometry, dt and opts->ring_depth, as in
+ * lw_dipole_run).  Host only; the same argument checks as lw_dipole_run. */
+lw_status lw_dipole_state_size(const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off, int32_t n_inst,
+                               double dt, const lw_run_opts *opts, int64_t *n_doubles);
+
+/* lw_dipole_run with a run state (Algorithm 1 continued across calls):
+ *   d_state  device FP64, n_state doubles, at least lw_dipole_state_size's
+ *            (LW_E_INVALID otherwise); owned by the caller.
+ *   resume   0: the run starts at t = 0, as lw_dipole_run.  Nonzero: it
+ *            continues the run whose state d_state holds, at that state's step
+ *            n0: output row 0 is the state at n0 and row k the state at
+ *            n0 + k out_stride, and `steps` more steps are taken.
+ * Either way d_state holds the run's state after its last step when the call's
+ * work ends, so a run split into calls gives the outputs of one call.  The
+ * dipoles, instances, dt and options must be those the state was written
+ * with; a state of another size or depth is reported as LW_E_STATE by
+ * lw_sync_status().  Asynchronous, like lw_dipole_run. */
+lw_status lw_dipole_run_state(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
+                              int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts,
+                              double *d_moment, double *d_dot, double *d_energy, double *d_drive,
+                              double *d_wabs, double *d_wrad, double *d_state, int64_t n_state, int32_t resume,
+                              void *stream);
 
 /* Gradient of a detector objective with respect to the oscillator positions,
  * by a backward-in-time discrete adjoint of the run.  The run is that of

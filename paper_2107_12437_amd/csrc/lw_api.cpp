@@ -375,6 +375,7 @@ lw_status lw_sync_status(lw_ctx *ctx, void *stream)
     if (e & 4u) return fail(LW_E_VELOCITY, "a dipole charge exceeded the speed limit");
     if (e & 1u) return fail(LW_E_HISTORY, "a retarded time fell outside the stored history");
     if (e & 2u) return fail(LW_E_NOCONV, "a retarded-time solve did not converge");
+    if (e & 16u) return fail(LW_E_STATE, "a resumed run's state does not match its dipoles or history depth");
     return LW_OK;
 }
 
@@ -533,23 +534,24 @@ lw_status lw_fields_vjp(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges
     return LW_OK;
 }
 
-lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
-                        int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts, double *d_moment,
-                        double *d_dot, double *d_energy, double *d_drive, double *d_wabs, double *d_wrad,
-                        void *stream)
+// Validation of an oscillator run's arguments and its history depth: the ring
+// of stored steps covers the longest retarded time.
+static lw_status run_geometry(const char *who, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
+                              int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts, int *ring_out)
 {
-    if (!ctx || !opts || !h_dip || !h_inst_off || !d_moment) return fail(LW_E_INVALID, "lw_dipole_run: null argument");
-    if (n_dip < 1 || n_inst < 1) return fail(LW_E_INVALID, "lw_dipole_run: need at least one dipole and instance");
+    const std::string w = who;
+    if (!opts || !h_dip || !h_inst_off) return fail(LW_E_INVALID, w + ": null argument");
+    if (n_dip < 1 || n_inst < 1) return fail(LW_E_INVALID, w + ": need at least one dipole and instance");
     if (h_inst_off[0] != 0 || h_inst_off[n_inst] != n_dip)
-        return fail(LW_E_INVALID, "lw_dipole_run: instance offsets must run from 0 to n_dip");
-    if (!(dt > 0.0) || !std::isfinite(dt) || steps < 0) return fail(LW_E_INVALID, "lw_dipole_run: bad dt or steps");
+        return fail(LW_E_INVALID, w + ": instance offsets must run from 0 to n_dip");
+    if (!(dt > 0.0) || !std::isfinite(dt) || steps < 0) return fail(LW_E_INVALID, w + ": bad dt or steps");
     if (opts->precision != LW_FP64 && opts->precision != LW_MIXED)
-        return fail(LW_E_INVALID, "lw_dipole_run: unknown precision");
+        return fail(LW_E_INVALID, w + ": unknown precision");
     if (opts->dt_policy != LW_DT_STRICT && opts->dt_policy != LW_DT_EXTRAPOLATE)
-        return fail(LW_E_INVALID, "lw_dipole_run: unknown dt policy");
+        return fail(LW_E_INVALID, w + ": unknown dt policy");
     if (opts->out_stride < 1 || opts->ring_depth < 0 ||
         (opts->ring_depth & (opts->ring_depth - 1)) != 0 || !std::isfinite(opts->max_vel))
-        return fail(LW_E_INVALID, "lw_dipole_run: bad options");
+        return fail(LW_E_INVALID, w + ": bad options");
     for (int i = 0; i < n_dip; ++i) {
         const lw_dipole &D = h_dip[i];
         if (!finite3(D.origin) || !unit3(D.axis) || !(D.omega0 > 0.0) || !std::isfinite(D.omega0) ||
@@ -558,7 +560,7 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
             !std::isfinite(D.motion_omega) || !std::isfinite(D.motion_phase) ||
             !(std::fabs(D.motion_omega) * norm3(D.motion_amp) < 0.1 * C_LIGHT) ||
             (norm3(D.motion_amp) > 0.0 && D.motion_omega == 0.0))
-            return fail(LW_E_INVALID, "lw_dipole_run: bad parameters for dipole " + std::to_string(i));
+            return fail(LW_E_INVALID, w + ": bad parameters for dipole " + std::to_string(i));
     }
     // separations inside each instance: distinct origins, the dt rule, and the
     // longest light travel time (history depth)
@@ -569,13 +571,11 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
     const bool strict = opts->dt_policy == LW_DT_STRICT;
     const double cdt = C_LIGHT * dt, cdt2 = cdt * cdt;
     double max_sep = 0.0, max_r2 = 0.0;
-    int max_n = 0;
     int bad_a = -1, bad_b = -1;
     lw_status bad = LW_OK;
     for (int k = 0; k < n_inst && bad == LW_OK; ++k) {
         const int a0 = h_inst_off[k], a1 = h_inst_off[k + 1];
-        if (a1 < a0) return fail(LW_E_INVALID, "lw_dipole_run: decreasing instance offsets");
-        max_n = std::max(max_n, a1 - a0);
+        if (a1 < a0) return fail(LW_E_INVALID, w + ": decreasing instance offsets");
         for (int a = a0; a < a1 && bad == LW_OK; ++a) {
             const double *oa = h_dip[a].origin;
             for (int b = a + 1; b < a1; ++b) {
@@ -601,22 +601,39 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
             }
         }
     }
-    if (bad == LW_E_INVALID) return fail(LW_E_INVALID, "lw_dipole_run: two dipoles can share an origin");
+    if (bad == LW_E_INVALID) return fail(LW_E_INVALID, w + ": two dipoles can share an origin");
     if (bad == LW_E_DT_TOO_LARGE)
-        return fail(LW_E_DT_TOO_LARGE, "lw_dipole_run: c*dt is not below the separation of dipoles " +
+        return fail(LW_E_DT_TOO_LARGE, w + ": c*dt is not below the separation of dipoles " +
                                            std::to_string(bad_a) + " and " + std::to_string(bad_b));
     max_sep = std::max(max_sep, std::sqrt(max_r2));
     // depth: the longest retarded time (plus the charges' own excursion) in
     // steps, two interpolation neighbours and one step of slack
     const double need = std::ceil(2.0 * max_sep / C_LIGHT / dt) + 3.0;
-    if (need > (double)(1 << 24)) return fail(LW_E_INVALID, "lw_dipole_run: dt too small for the separations");
+    if (need > (double)(1 << 24)) return fail(LW_E_INVALID, w + ": dt too small for the separations");
     int ring = 4;
     while (ring < (int)need) ring <<= 1;
     if (opts->ring_depth) {
         if (opts->ring_depth < (int)need)
-            return fail(LW_E_INVALID, "lw_dipole_run: ring_depth below the longest retarded time");
+            return fail(LW_E_INVALID, w + ": ring_depth below the longest retarded time");
         ring = opts->ring_depth;
     }
+    *ring_out = ring;
+    return LW_OK;
+}
+
+static lw_status dipole_run_impl(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
+                                 int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts,
+                                 double *d_moment, double *d_dot, double *d_energy, double *d_drive, double *d_wabs,
+                                 double *d_wrad, double *d_state, int64_t n_state, bool resume, void *stream)
+{
+    if (!ctx || !opts || !h_dip || !h_inst_off || !d_moment) return fail(LW_E_INVALID, "lw_dipole_run: null argument");
+    int ring = 0;
+    lw_status gst = run_geometry("lw_dipole_run", h_dip, n_dip, h_inst_off, n_inst, dt, steps, opts, &ring);
+    if (gst != LW_OK) return gst;
+    if (resume && !d_state) return fail(LW_E_INVALID, "lw_dipole_run: resume needs a run state");
+    if (d_state && n_state < lw::state_doubles(n_dip, ring))
+        return fail(LW_E_INVALID, "lw_dipole_run: the run state holds " + std::to_string(n_state) + " doubles, " +
+                                      std::to_string(lw::state_doubles(n_dip, ring)) + " are needed");
     if (steps == 0 && !d_moment) return LW_OK;
     LW_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
@@ -636,11 +653,13 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
             lds_list.push_back(k);
             max_lds_n = std::max(max_lds_n, n);
         } else {
+            // a run state keeps every instance's ring at its place in the state
+            const int64_t base = d_state ? lw::state_ring_off(a0, ring) - lw::STATE_HEAD : ring_doubles;
             for (int i = 0; i < n; ++i) {
                 tgt.push_back(a0 + i);
                 tgt_lo.push_back(a0);
                 tgt_n.push_back(n);
-                tgt_base.push_back(ring_doubles);
+                tgt_base.push_back(base);
             }
             ring_doubles += (int64_t)n * ring * 3;
         }
@@ -656,7 +675,7 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
     const size_t dev_bytes = align_up(lw::dip_dev_bytes(n_dip), 256);
     const size_t ecur_bytes = align_up(sizeof(double) * 3 * (size_t)n_dip, 256);   // E_d(t_n), then 2 energy sums
     const size_t step_bytes = 256;
-    const size_t ring_bytes = align_up(sizeof(double) * (size_t)std::max<int64_t>(ring_doubles, 1), 256);
+    const size_t ring_bytes = d_state ? 256 : align_up(sizeof(double) * (size_t)std::max<int64_t>(ring_doubles, 1), 256);
     lw_status st = ensure_work(ctx, stage_bytes + dev_bytes + ecur_bytes + step_bytes + ring_bytes, s);
     if (st != LW_OK) return st;
     // the previous stepped run's graph is released once the stream has passed it
@@ -710,10 +729,19 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
     int64_t *d_step = (int64_t *)(work + o);
     o += step_bytes;
     double *d_ring = (double *)(work + o);
+    if (d_state) {
+        // the stepped path works in the run state itself
+        d_ring = d_state + lw::STATE_HEAD;
+        d_Ecur = d_state + lw::state_ecur_off(n_dip, ring);
+        d_W = d_state + lw::state_w_off(n_dip, ring);
+    }
 
     const double max_vel = opts->max_vel > 0.0 ? opts->max_vel : C_LIGHT / 100.0;
     const int max_iter = 60;
     LW_HIP(lw::launch_dipole_prep(d_in, n_dip, d_dev, s));
+    const lw::RunOut out{d_moment, d_dot, d_energy, d_drive, d_wabs, d_wrad, opts->out_stride, n_dip};
+    // a resumed run's row 0 comes from its state, before either path updates it
+    if (resume) LW_HIP(lw::launch_state_rows(d_dev, d_off, n_inst, d_state, ring, out, ctx->d_err, s));
     const bool both = !lds_list.empty() && n_tgt > 0;
     hipStream_t small_s = s;
     if (both) {
@@ -724,25 +752,57 @@ lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, cons
         LW_HIP(hipStreamWaitEvent(ctx->side, ctx->join_a, 0));
         small_s = ctx->side;
     }
-    const lw::RunOut out{d_moment, d_dot, d_energy, d_drive, d_wabs, d_wrad, opts->out_stride, n_dip};
     bool moving = false;
     for (int i = 0; i < n_dip; ++i) moving = moving || motion_reach(h_dip[i]) > 0.0;
     const bool mixed = opts->precision == LW_MIXED;
     LW_HIP(lw::launch_dipole_instances(d_dev, d_off, d_list, (int)lds_list.size(), max_lds_n, true, nullptr, nullptr,
-                                       ring, steps, dt, max_vel, max_iter, out, moving, mixed, ctx->d_err, small_s));
+                                       ring, steps, dt, max_vel, max_iter, out, moving, mixed, d_state, resume,
+                                       ctx->d_err, small_s));
     if (n_tgt > 0) {
         if (!ctx->capture) LW_HIP(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
         if (!ctx->graph_done) LW_HIP(hipEventCreateWithFlags(&ctx->graph_done, hipEventDisableTiming));
         const int chunk = 256;
         LW_HIP(lw::launch_dipole_steps(d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_tgt_base, (int)n_tgt, d_ring, d_Ecur, d_W,
-                                       d_step, ring, steps, dt, max_vel, max_iter, out, moving, mixed, ctx->d_err, chunk, s,
-                                       ctx->capture, &ctx->graph, &ctx->graph_exec));
+                                       d_step, ring, steps, dt, max_vel, max_iter, out, moving, mixed,
+                                       resume ? d_state : nullptr, ctx->d_err, chunk, s, ctx->capture, &ctx->graph,
+                                       &ctx->graph_exec));
         LW_HIP(hipEventRecord(ctx->graph_done, s));
     }
     if (both) {
         LW_HIP(hipEventRecord(ctx->join_b, ctx->side));
         LW_HIP(hipStreamWaitEvent(s, ctx->join_b, 0));
     }
+    if (d_state) LW_HIP(lw::launch_state_header(d_state, ring, n_dip, steps, resume, s));
+    return LW_OK;
+}
+
+lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
+                        int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts, double *d_moment,
+                        double *d_dot, double *d_energy, double *d_drive, double *d_wabs, double *d_wrad,
+                        void *stream)
+{
+    return dipole_run_impl(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, steps, opts, d_moment, d_dot, d_energy, d_drive,
+                           d_wabs, d_wrad, nullptr, 0, false, stream);
+}
+
+lw_status lw_dipole_run_state(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
+                              int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts, double *d_moment,
+                              double *d_dot, double *d_energy, double *d_drive, double *d_wabs, double *d_wrad,
+                              double *d_state, int64_t n_state, int32_t resume, void *stream)
+{
+    if (!d_state) return fail(LW_E_INVALID, "lw_dipole_run_state: null run state");
+    return dipole_run_impl(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, steps, opts, d_moment, d_dot, d_energy, d_drive,
+                           d_wabs, d_wrad, d_state, n_state, resume != 0, stream);
+}
+
+lw_status lw_dipole_state_size(const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off, int32_t n_inst,
+                               double dt, const lw_run_opts *opts, int64_t *n_doubles)
+{
+    if (!n_doubles) return fail(LW_E_INVALID, "lw_dipole_state_size: null output");
+    int ring = 0;
+    const lw_status st = run_geometry("lw_dipole_state_size", h_dip, n_dip, h_inst_off, n_inst, dt, 0, opts, &ring);
+    if (st != LW_OK) return st;
+    *n_doubles = lw::state_doubles(n_dip, ring);
     return LW_OK;
 }
 

@@ -499,6 +499,7 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
                                                              double max_vel, int max_iter,
                                                              double *__restrict__ ring_global,
                                                              const int64_t *__restrict__ ring_off, RunOut out,
+                                                             double *__restrict__ state, int resume,
                                                              uint32_t *__restrict__ d_err)
 {
     extern __shared__ double lds[];
@@ -536,28 +537,44 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
 
     Hist H{ringp, n, ring - 1, dt, 1.0 / dt};
     uint32_t err = 0u;
+    const int64_t ring3 = (int64_t)ring * n * 3;
+    int64_t n0 = 0;                             // the run's first step
 
-    // t = 0: drive from the static pre-history, then sample 0 = (d0, 0, d_ddot(0))
-    {
-        const double th0[1] = {0.0};
-        drive_all<BLOCK, MOVING, MIXED>(H, S, qv, n, 0, th0, 1, Ecur, max_iter, err);
-    }
-    __syncthreads();
-    for (int i = tid; i < n; i += BLOCK) {
-        const DipDev &D = dev[i0 + i];
-        double *h = ringp + (int64_t)i * 3;
-        h[0] = D.d0;
-        h[1] = 0.0;
-        h[2] = D.f * Ecur[i] - D.omega0 * D.omega0 * D.d0;
-        const int gi = i0 + i;
-        Wab[i] = 0.0;
-        Wra[i] = 0.0;
-        put_row(out, 0, gi, D.d0, 0.0, D.omega0 * D.omega0 * D.d0 * D.d0 / (2.0 * D.f), Ecur[i], 0.0, 0.0);
+    if (resume) {
+        // continue from the run state: history, E_d(t_n0) and the energy sums
+        // (output row 0 is written from the state before this kernel runs)
+        n0 = (int64_t)state[0];
+        const double *sr = state + state_ring_off(i0, ring);
+        for (int64_t k = tid; k < ring3; k += BLOCK) ringp[k] = sr[k];
+        const int64_t oe = state_ecur_off(out.n_dip, ring), ow = state_w_off(out.n_dip, ring);
+        for (int i = tid; i < n; i += BLOCK) {
+            Ecur[i] = state[oe + i0 + i];
+            Wab[i] = state[ow + 2 * (i0 + i)];
+            Wra[i] = state[ow + 2 * (i0 + i) + 1];
+        }
+    } else {
+        // t = 0: drive from the static pre-history, then sample 0 = (d0, 0, d_ddot(0))
+        {
+            const double th0[1] = {0.0};
+            drive_all<BLOCK, MOVING, MIXED>(H, S, qv, n, 0, th0, 1, Ecur, max_iter, err);
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += BLOCK) {
+            const DipDev &D = dev[i0 + i];
+            double *h = ringp + (int64_t)i * 3;
+            h[0] = D.d0;
+            h[1] = 0.0;
+            h[2] = D.f * Ecur[i] - D.omega0 * D.omega0 * D.d0;
+            const int gi = i0 + i;
+            Wab[i] = 0.0;
+            Wra[i] = 0.0;
+            put_row(out, 0, gi, D.d0, 0.0, run_energy(D.omega0 * D.omega0, D.f, D.d0, 0.0), Ecur[i], 0.0, 0.0);
+        }
     }
     __syncthreads();
 
     const double thetas[2] = {0.5, 1.0};
-    for (int64_t nstep = 0; nstep < steps; ++nstep) {
+    for (int64_t nstep = n0; nstep < n0 + steps; ++nstep) {
         drive_all<BLOCK, MOVING, MIXED>(H, S, qv, n, nstep, thetas, 2, Enew, max_iter, err);
         __syncthreads();
         for (int i = tid; i < n; i += BLOCK) {
@@ -588,14 +605,26 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
             const double wr = Wra[i] + 0.5 * dt * K_LARMOR * (h[2] * h[2] + an * an);
             Wab[i] = wa;
             Wra[i] = wr;
-            if ((nstep + 1) % out.stride == 0)
-                put_row(out, (nstep + 1) / out.stride, i0 + i, dn, vn, (w2 * dn * dn + vn * vn) * (0.5 / f), Ee, wa, wr);
+            const int64_t rel = nstep + 1 - n0;
+            if (rel % out.stride == 0)
+                put_row(out, rel / out.stride, i0 + i, dn, vn, run_energy(w2, f, dn, vn), Ee, wa, wr);
         }
         if (err) atomicOr(&s_err, err);
         __syncthreads();
         if (s_err & (ERR_NONFINITE | ERR_VELOCITY | ERR_HISTORY)) break;
     }
     __syncthreads();
+    if (state) {
+        // save the run state: history, E_d and the energy sums
+        double *sr = state + state_ring_off(i0, ring);
+        for (int64_t k = tid; k < ring3; k += BLOCK) sr[k] = ringp[k];
+        const int64_t oe = state_ecur_off(out.n_dip, ring), ow = state_w_off(out.n_dip, ring);
+        for (int i = tid; i < n; i += BLOCK) {
+            state[oe + i0 + i] = Ecur[i];
+            state[ow + 2 * (i0 + i)] = Wab[i];
+            state[ow + 2 * (i0 + i) + 1] = Wra[i];
+        }
+    }
     if (tid == 0 && s_err) atomicOr(d_err, s_err);
 }
 
@@ -669,7 +698,7 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             Ecur[gi] = E0;
             W[2 * gi] = 0.0;
             W[2 * gi + 1] = 0.0;
-            put_row(out, 0, gi, D.d0, 0.0, w2 * D.d0 * D.d0 * (0.5 / f), E0, 0.0, 0.0);
+            put_row(out, 0, gi, D.d0, 0.0, run_energy(w2, f, D.d0, 0.0), E0, 0.0, 0.0);
         } else {
             const double Em = red[0][0], Ee = red[1][0], Ec = Ecur[gi];
             const double *h = rp + ((int64_t)(nstep & (ring_depth - 1)) * n + i) * 3;
@@ -696,8 +725,8 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             const double wr = W[2 * gi + 1] + 0.5 * dt * K_LARMOR * (h[2] * h[2] + an * an);
             W[2 * gi] = wa;
             W[2 * gi + 1] = wr;
-            if ((nstep + 1) % out.stride == 0)
-                put_row(out, (nstep + 1) / out.stride, gi, dn, vn, (w2 * dn * dn + vn * vn) * (0.5 / f), Ee, wa, wr);
+            const int64_t rel = nstep + 1 - step_ctr[1];       // steps since the run's first
+            if (rel % out.stride == 0) put_row(out, rel / out.stride, gi, dn, vn, run_energy(w2, f, dn, vn), Ee, wa, wr);
         }
     }
     if (err) atomicOr(d_err, err);
@@ -708,9 +737,58 @@ __global__ void step_advance_kernel(int64_t *step_ctr, int64_t delta)
     if (threadIdx.x == 0 && blockIdx.x == 0) *step_ctr += delta;
 }
 
-__global__ void step_reset_kernel(int64_t *step_ctr)
+// The run's first step: 0, or the step count of the run state it resumes.
+__global__ void step_start_kernel(int64_t *step_ctr, const double *resume)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *step_ctr = 0;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int64_t n0 = resume ? (int64_t)resume[0] : 0;
+        step_ctr[0] = n0;
+        step_ctr[1] = n0;
+    }
+}
+
+// A resumed run: the header check and output row 0 of every dipole from the
+// state (d, d_dot at the state's step, E_d and the energy sums).
+__global__ void state_rows_kernel(const DipDev *__restrict__ dev, const int32_t *__restrict__ off, int n_inst,
+                                  const double *__restrict__ state, int ring, RunOut out,
+                                  uint32_t *__restrict__ d_err)
+{
+    const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi == 0 && !(state[1] == (double)ring && state[2] == (double)out.n_dip)) atomicOr(d_err, ERR_STATE);
+    if (gi >= out.n_dip) return;
+    const int inst = instance_of(off, n_inst, gi);
+    const int a0 = off[inst], n = off[inst + 1] - a0;
+    const int64_t n0 = (int64_t)state[0];
+    const double *h = state + state_ring_off(a0, ring) + ((int64_t)(n0 & (ring - 1)) * n + (gi - a0)) * 3;
+    const DipDev &D = dev[gi];
+    const int64_t ow = state_w_off(out.n_dip, ring);
+    put_row(out, 0, gi, h[0], h[1], run_energy(D.omega0 * D.omega0, D.f, h[0], h[1]),
+            state[state_ecur_off(out.n_dip, ring) + gi], state[ow + 2 * gi], state[ow + 2 * gi + 1]);
+}
+
+__global__ void state_header_kernel(double *state, int ring, int n_dip, int64_t steps, int resume)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int64_t n0 = resume ? (int64_t)state[0] : 0;
+        state[0] = (double)(n0 + steps);
+        state[1] = (double)ring;
+        state[2] = (double)n_dip;
+        state[3] = 0.0;
+    }
+}
+
+hipError_t launch_state_rows(const DipDev *d_dev, const int32_t *d_off, int n_inst, const double *d_state, int ring,
+                             const RunOut &out, uint32_t *d_err, hipStream_t s)
+{
+    hipLaunchKernelGGL(state_rows_kernel, dim3((out.n_dip + 255) / 256), dim3(256), 0, s, d_dev, d_off, n_inst,
+                       d_state, ring, out, d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_header(double *d_state, int ring, int n_dip, int64_t steps, bool resume, hipStream_t s)
+{
+    hipLaunchKernelGGL(state_header_kernel, dim3(1), dim3(1), 0, s, d_state, ring, n_dip, steps, resume ? 1 : 0);
+    return hipGetLastError();
 }
 
 // Calls fn(std::integral_constant<bool, a>, std::integral_constant<bool, b>).
@@ -728,8 +806,9 @@ template <typename Fn> static void with_flags(bool a, bool b, Fn &&fn)
 hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const int32_t *d_tgt_lo, const int32_t *d_tgt_n,
                                const int64_t *d_ring_base, int n_tgt, double *d_ring, double *d_Ecur, double *d_W,
                                int64_t *d_step, int ring, int64_t steps, double dt, double max_vel, int max_iter,
-                               const RunOut &out, bool moving, bool mixed, uint32_t *d_err, int graph_chunk,
-                               hipStream_t s, hipStream_t cap, hipGraph_t *graph_out, hipGraphExec_t *exec_out)
+                               const RunOut &out, bool moving, bool mixed, const double *d_resume, uint32_t *d_err,
+                               int graph_chunk, hipStream_t s, hipStream_t cap, hipGraph_t *graph_out,
+                               hipGraphExec_t *exec_out)
 {
     constexpr int B = 256;
     if (n_tgt <= 0) return hipSuccess;
@@ -742,8 +821,8 @@ hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const 
                                max_vel, max_iter, init, out, soa, d_err);
         });
     };
-    hipLaunchKernelGGL(step_reset_kernel, dim3(1), dim3(1), 0, s, d_step);
-    step(s, 0, 1);
+    hipLaunchKernelGGL(step_start_kernel, dim3(1), dim3(1), 0, s, d_step, d_resume);
+    if (!d_resume) step(s, 0, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || steps == 0) return e;
     // a chunk of steps is captured once into a graph and replayed: launch k of
@@ -787,17 +866,20 @@ template <int BLOCK>
 static hipError_t launch_lo(bool ring_lds, bool moving, bool mixed, dim3 grid, size_t shmem, hipStream_t s,
                             const DipDev *d_dev, const int32_t *d_off, const int32_t *d_list, int ring, int64_t steps,
                             double dt, double max_vel, int max_iter, double *d_ring_global,
-                            const int64_t *d_ring_off, const RunOut &out, uint32_t *d_err)
+                            const int64_t *d_ring_off, const RunOut &out, double *d_state, bool resume,
+                            uint32_t *d_err)
 {
+    const int rs = resume ? 1 : 0;
     with_flags(moving, mixed, [&](auto mv, auto mx) {
         constexpr bool MV = decltype(mv)::value, MX = decltype(mx)::value;
         if (ring_lds)
             hipLaunchKernelGGL((lo_instances_kernel<BLOCK, true, MV, MX>), grid, dim3(BLOCK), shmem, s, d_dev, d_off,
-                               d_list, ring, steps, dt, max_vel, max_iter, d_ring_global, d_ring_off, out, d_err);
+                               d_list, ring, steps, dt, max_vel, max_iter, d_ring_global, d_ring_off, out, d_state,
+                               rs, d_err);
         else
             hipLaunchKernelGGL((lo_instances_kernel<BLOCK, false, MV, MX>), grid, dim3(BLOCK), shmem, s, d_dev,
                                d_off, d_list, ring, steps, dt, max_vel, max_iter, d_ring_global, d_ring_off, out,
-                               d_err);
+                               d_state, rs, d_err);
     });
     return hipGetLastError();
 }
@@ -805,16 +887,17 @@ static hipError_t launch_lo(bool ring_lds, bool moving, bool mixed, dim3 grid, s
 hipError_t launch_dipole_instances(const DipDev *d_dev, const int32_t *d_off, const int32_t *d_list, int n_list,
                                    int max_n, bool ring_lds, const int64_t *d_ring_off, double *d_ring_global,
                                    int ring, int64_t steps, double dt, double max_vel, int max_iter,
-                                   const RunOut &out, bool moving, bool mixed, uint32_t *d_err, hipStream_t s)
+                                   const RunOut &out, bool moving, bool mixed, double *d_state, bool resume,
+                                   uint32_t *d_err, hipStream_t s)
 {
     if (n_list <= 0) return hipSuccess;
     const size_t shmem = (size_t)ring_lds_bytes(max_n, ring_lds ? ring : 0);
     const dim3 grid((unsigned)n_list);
     if (max_n <= 8)
         return launch_lo<64>(ring_lds, moving, mixed, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel,
-                             max_iter, d_ring_global, d_ring_off, out, d_err);
+                             max_iter, d_ring_global, d_ring_off, out, d_state, resume, d_err);
     return launch_lo<256>(ring_lds, moving, mixed, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel,
-                          max_iter, d_ring_global, d_ring_off, out, d_err);
+                          max_iter, d_ring_global, d_ring_off, out, d_state, resume, d_err);
 }
 
 }  // namespace lw

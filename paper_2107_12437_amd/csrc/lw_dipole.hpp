@@ -92,7 +92,19 @@ __device__ __forceinline__ DipLds dip_lds(const DipDev &D)
                   D.mamp[0], D.mamp[1], D.mamp[2], D.mw, D.mph};
 }
 
-enum { ERR_HISTORY = 1u, ERR_NOCONV = 2u, ERR_VELOCITY = 4u, ERR_NONFINITE = 8u };
+enum { ERR_HISTORY = 1u, ERR_NOCONV = 2u, ERR_VELOCITY = 4u, ERR_NONFINITE = 8u, ERR_STATE = 16u };
+
+// Instance of global dipole g (last instance whose first dipole is <= g).
+__device__ __forceinline__ int instance_of(const int32_t *off, int n_inst, int g)
+{
+    int lo = 0, hi = n_inst;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 
 // Stored samples k and k + 1 of one source; k = -1 stands for the static
 // pre-history (t' < 0), where the state is (d0, 0, 0).
@@ -170,6 +182,13 @@ __device__ __forceinline__ bool retarded_seg(const Hist &H, int j, double d0, in
 
 // Larmor power per |d_ddot|^2 (Sec. 2.5): 1 / (6 pi eps0 c^3).
 constexpr double K_LARMOR = 1.0 / (6.0 * PI * EPS0 * C_LIGHT * C_LIGHT * C_LIGHT);
+
+// Energy of Eq. (dipoleE) from (d, d_dot): (omega0^2 d^2 + d_dot^2) / (2 f),
+// f = q^2 / m, in one fixed order of operations wherever it is evaluated.
+__device__ __forceinline__ double run_energy(double w2, double f, double d, double v)
+{
+    return fma(w2 * d, d, v * v) * (0.5 / f);
+}
 
 // Writes row `row` of the outputs for dipole gi.
 __device__ __forceinline__ void put_row(const RunOut &o, int64_t row, int gi, double d, double v, double E, double Ed,

@@ -445,16 +445,6 @@ __global__ void adj_base_kernel(int64_t *__restrict__ step_base, int64_t delta)
     if (blockIdx.x == 0 && threadIdx.x == 0) *step_base += delta;
 }
 
-// Instance of global dipole g (last instance whose first dipole is <= g).
-__device__ __forceinline__ int instance_of(const int32_t *off, int n_inst, int g)
-{
-    int lo = 0, hi = n_inst;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (off[mid] <= g) lo = mid; else hi = mid;
-    }
-    return lo;
-}
 
 // Maps a pair index of the flattened list to (instance, stage, target, source,
 // charge).  Per instance of n dipoles: stages x n targets x (n - 1) sources x

@@ -22,6 +22,18 @@ struct RunOut {
     int n_dip;
 };
 
+// Run state of an oscillator run (device FP64), enough to continue it exactly:
+//   [0] steps taken n, [1] ring depth, [2] number of dipoles, [3] unused;
+//   the history rings: instance (dipoles a0..a1) at state_ring_off(a0, ring) as
+//     [slot][a1 - a0][3] (d, d_dot, d_ddot), slot = step & (ring - 1);
+//   E_d(t_n) of every dipole (state_ecur_off);
+//   the energy sums (absorbed, radiated) of every dipole (state_w_off).
+constexpr int64_t STATE_HEAD = 4;
+__host__ __device__ inline int64_t state_ring_off(int a0, int ring) { return STATE_HEAD + (int64_t)a0 * ring * 3; }
+__host__ __device__ inline int64_t state_ecur_off(int n_dip, int ring) { return state_ring_off(n_dip, ring); }
+__host__ __device__ inline int64_t state_w_off(int n_dip, int ring) { return state_ecur_off(n_dip, ring) + n_dip; }
+__host__ __device__ inline int64_t state_doubles(int n_dip, int ring) { return state_w_off(n_dip, ring) + 2 * (int64_t)n_dip; }
+
 // Launch parameters of the grid-field kernel chosen by the tuner.
 struct FieldLaunch {
     int block;       // threads per workgroup (multiple of 64)
@@ -58,21 +70,34 @@ hipError_t launch_dipole_prep(const lw_dipole *d_in, int n, DipDev *d_dev, hipSt
 // One launch of the per-instance persistent kernel over the instances listed in
 // d_list[0..n_list); max_n is the largest of them.  With ring_lds the history
 // ring lives in LDS, otherwise at d_ring_global + d_ring_off[block].
+// d_state (nullable): the run state, read at the start when resume is set and
+// written at the end.
 hipError_t launch_dipole_instances(const DipDev *d_dev, const int32_t *d_off, const int32_t *d_list, int n_list,
                                    int max_n, bool ring_lds, const int64_t *d_ring_off, double *d_ring_global,
                                    int ring, int64_t steps, double dt, double max_vel, int max_iter,
-                                   const RunOut &out, bool moving, bool mixed, uint32_t *d_err, hipStream_t s);
+                                   const RunOut &out, bool moving, bool mixed, double *d_state, bool resume,
+                                   uint32_t *d_err, hipStream_t s);
+// A resumed run: checks the state's header against (ring, n_dip) and writes
+// output row 0 of every dipole from it.
+hipError_t launch_state_rows(const DipDev *d_dev, const int32_t *d_off, int n_inst, const double *d_state, int ring,
+                             const RunOut &out, uint32_t *d_err, hipStream_t s);
+// After a run: the state's header (steps taken, ring, n_dip).
+hipError_t launch_state_header(double *d_state, int ring, int n_dip, int64_t steps, bool resume, hipStream_t s);
 
 // moving: some dipole's origin moves (kernels with the moving-origin code).
 // mixed: FP32 pair fields (FP64 retarded times, state and sums).
 // Large instances: one launch per step (captured into a replayed graph when
 // graph_chunk > 0 and a capture stream is given), one workgroup per target.
 // d_W: 2 doubles per dipole of running energy sums (absorbed, radiated).
+// d_step: 2 int64 (the device step base, the run's first step).  resume: the
+// ring, E_d and the sums already hold step (int64)d_resume[0] (a run state)
+// and the first stage is not taken; otherwise the run starts at t = 0.
 hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const int32_t *d_tgt_lo, const int32_t *d_tgt_n,
                                const int64_t *d_ring_base, int n_tgt, double *d_ring, double *d_Ecur, double *d_W,
                                int64_t *d_step, int ring, int64_t steps, double dt, double max_vel, int max_iter,
-                               const RunOut &out, bool moving, bool mixed, uint32_t *d_err, int graph_chunk,
-                               hipStream_t s, hipStream_t cap, hipGraph_t *graph_out, hipGraphExec_t *exec_out);
+                               const RunOut &out, bool moving, bool mixed, const double *d_resume, uint32_t *d_err,
+                               int graph_chunk, hipStream_t s, hipStream_t cap, hipGraph_t *graph_out,
+                               hipGraphExec_t *exec_out);
 
 // Gradient of the detector objective with respect to the oscillator positions
 // from a finished stride-1 run (lw_dipole_adjoint.hip).  d_hist / d_hbar hold

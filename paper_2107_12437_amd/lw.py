@@ -43,10 +43,10 @@ DT_POLICIES = {"strict": 0, "extrapolate": 1}
 FLAG_MASKED, FLAG_NOCONV = 1, 2
 STATUS_NAMES = {0: "LW_OK", 1: "LW_E_INVALID", 2: "LW_E_SUPERLUMINAL", 3: "LW_E_DT_TOO_LARGE",
                 4: "LW_E_VELOCITY", 5: "LW_E_NOCONV", 6: "LW_E_HIP", 7: "LW_E_NOMEM",
-                8: "LW_E_NONFINITE", 9: "LW_E_HISTORY"}
+                8: "LW_E_NONFINITE", 9: "LW_E_HISTORY", 10: "LW_E_STATE"}
 EXPORTS = ("lw_last_error", "lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields",
            "lw_fields_vjp", "lw_dipole_run", "lw_dipole_run_vjp", "lw_pair_modes", "lw_gamma0", "lw_gf_pair",
-           "lw_exact_modes")
+           "lw_exact_modes", "lw_dipole_state_size", "lw_dipole_run_state")
 PARAM_NAMES = ("q", "c0x", "c0y", "c0z", "amp", "omega", "phase", "accel", "vx", "vy", "vz")
 OUTPUT_NAMES = ("phi", "Ax", "Ay", "Az", "Ex", "Ey", "Ez", "Bx", "By", "Bz")
 
@@ -102,6 +102,10 @@ def load_library(path: str = LIB_PATH):
     L.lw_fields_vjp.argtypes = [vp, ct.POINTER(Traj), i32, vp, i64, ct.POINTER(dbl), i32, ct.POINTER(Opts), vp, vp, vp]
     L.lw_dipole_run.argtypes = [vp, ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, i64,
                                 ct.POINTER(RunOpts), vp, vp, vp, vp, vp, vp, vp]
+    L.lw_dipole_run_state.argtypes = [vp, ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, i64,
+                                      ct.POINTER(RunOpts), vp, vp, vp, vp, vp, vp, vp, i64, i32, vp]
+    L.lw_dipole_state_size.argtypes = [ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, ct.POINTER(RunOpts),
+                                       ct.POINTER(i64)]
     L.lw_dipole_run_vjp.argtypes = [vp, ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, i64,
                                     ct.POINTER(RunOpts), vp, i64, ct.POINTER(dbl), i32, vp, ct.POINTER(dbl), vp]
     L.lw_pair_modes.argtypes = [ct.POINTER(dbl), i64, i32, ct.POINTER(i32), i32, dbl, i64,
@@ -111,7 +115,8 @@ def load_library(path: str = LIB_PATH):
     L.lw_gf_pair.argtypes = [ct.POINTER(dbl), ct.POINTER(dbl), ct.POINTER(dbl), dbl, ct.POINTER(dbl)]
     L.lw_exact_modes.argtypes = [ct.POINTER(dbl), ct.POINTER(dbl), dbl, dbl, dbl, ct.POINTER(dbl)]
     for name in ("lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields", "lw_fields_vjp",
-                 "lw_dipole_run", "lw_dipole_run_vjp", "lw_pair_modes", "lw_gf_pair", "lw_exact_modes"):
+                 "lw_dipole_run", "lw_dipole_run_vjp", "lw_pair_modes", "lw_gf_pair", "lw_exact_modes",
+                 "lw_dipole_state_size", "lw_dipole_run_state"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -311,15 +316,35 @@ class LWFieldsFn(torch.autograd.Function):
         return g.cpu(), None, None, None, None, None, None
 
 
+def _run_opts(policy, out_stride, max_vel, ring_depth, stepped_min_n, precision) -> RunOpts:
+    return RunOpts(PRECISIONS[precision], DT_POLICIES[policy], int(out_stride), float(max_vel), int(ring_depth),
+                   int(stepped_min_n))
+
+
+def dipole_state(dipoles: dict, inst_off, dt: float, policy: str = "strict", ring_depth: int = 0,
+                 device=None) -> torch.Tensor:
+    """A zeroed run-state buffer (float64 on the GPU) for dipole_run(..., state=...)."""
+    arr, n = pack_dipoles(dipoles)
+    off = np.ascontiguousarray(inst_off, dtype=np.int32)
+    opts = _run_opts(policy, 1, 0.0, ring_depth, 0, "fp64")
+    size = ct.c_int64(0)
+    _check(load_library().lw_dipole_state_size(arr, n, off.ctypes.data_as(ct.POINTER(ct.c_int32)), len(off) - 1,
+                                               float(dt), ct.byref(opts), ct.byref(size)))
+    return torch.zeros(size.value, dtype=torch.float64, device=_as_device(device))
+
+
 def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "strict", out_stride: int = 1,
                max_vel: float = 0.0, ring_depth: int = 0, stepped_min_n: int = 0, device=None, check: bool = True,
-               ctx: Context | None = None, energy_balance: bool = False, precision: str = "fp64"):
+               ctx: Context | None = None, energy_balance: bool = False, precision: str = "fp64",
+               state: torch.Tensor | None = None, resume: bool = False):
     """Self-consistent oscillator run (Algorithm 1).  Returns a dict of [n_out][n_dip]
     float64 GPU tensors: d, d_dot, energy, Ed, and with energy_balance the work absorbed
     from the drive field W_abs and the Larmor energy radiated W_rad since t = 0 (Sec. 2.5:
     the sum over an instance of energy - W_abs + W_rad is conserved).  precision "mixed"
     evaluates each source dipole's pair field in FP32 (retarded times, state and sums stay
-    FP64)."""
+    FP64).  With a run state (dipole_state) the run's state after its last step is kept
+    there, and resume=True continues the run that state holds: row 0 is then the state's
+    step and `steps` more are taken."""
     dev = _as_device(device)
     ctx = ctx or default_context(dev.index)
     arr, n = pack_dipoles(dipoles)
@@ -327,15 +352,22 @@ def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "st
     n_out = int(steps) // int(out_stride) + 1
     keys = ("d", "d_dot", "energy", "Ed") + (("W_abs", "W_rad") if energy_balance else ())
     res = {k: torch.empty((n_out, n), dtype=torch.float64, device=dev) for k in keys}
-    opts = RunOpts(PRECISIONS[precision], DT_POLICIES[policy], int(out_stride), float(max_vel), int(ring_depth),
-                   int(stepped_min_n))
+    opts = _run_opts(policy, out_stride, max_vel, ring_depth, stepped_min_n, precision)
     L = load_library()
-    _check(L.lw_dipole_run(ctx.handle, arr, n, off.ctypes.data_as(ct.POINTER(ct.c_int32)), len(off) - 1,
-                           float(dt), int(steps), ct.byref(opts), ct.c_void_p(res["d"].data_ptr()),
-                           ct.c_void_p(res["d_dot"].data_ptr()), ct.c_void_p(res["energy"].data_ptr()),
-                           ct.c_void_p(res["Ed"].data_ptr()),
-                           ct.c_void_p(res["W_abs"].data_ptr()) if energy_balance else None,
-                           ct.c_void_p(res["W_rad"].data_ptr()) if energy_balance else None, _stream_ptr(dev)))
+    args = (ctx.handle, arr, n, off.ctypes.data_as(ct.POINTER(ct.c_int32)), len(off) - 1, float(dt), int(steps),
+            ct.byref(opts), ct.c_void_p(res["d"].data_ptr()), ct.c_void_p(res["d_dot"].data_ptr()),
+            ct.c_void_p(res["energy"].data_ptr()), ct.c_void_p(res["Ed"].data_ptr()),
+            ct.c_void_p(res["W_abs"].data_ptr()) if energy_balance else None,
+            ct.c_void_p(res["W_rad"].data_ptr()) if energy_balance else None)
+    if state is None:
+        if resume:
+            raise ValueError("resume needs a run state")
+        _check(L.lw_dipole_run(*args, _stream_ptr(dev)))
+    else:
+        if not (state.is_cuda and state.dtype == torch.float64 and state.is_contiguous()):
+            raise ValueError("state must be a contiguous float64 GPU tensor (dipole_state)")
+        _check(L.lw_dipole_run_state(*args, ct.c_void_p(state.data_ptr()), state.numel(), int(bool(resume)),
+                                     _stream_ptr(dev)))
     if check:
         sync_status(ctx, dev)
     return res

@@ -89,3 +89,30 @@ def test_dipole_packing_matches_the_struct_fields():
         for k in ("omega0", "q", "m1", "m2", "d0", "motion_omega", "motion_phase"):
             assert getattr(d, k) == dip[k][i], k
         assert list(d.motion_amp) == list(dip["motion_amp"][i])
+
+
+def test_dipole_state_size():
+    """The run state holds a header of 4, a ring of `ring` steps x 3 per dipole, E_d and two
+    energy sums per dipole; the ring is the power of two (at least 4) covering
+    2 max-separation / (c dt) + 3 steps."""
+    n = 5
+    dip = I.empty_dipoles(n)
+    dip["origin"][:, 0] = np.arange(n) * 20e-9
+    dip["omega0"][:] = 2 * math.pi * 200e12
+    dt = 1 / 200e12 / 200
+    arr, m = lw.pack_dipoles(dip)
+    off = np.array([0, 2, 5], np.int32)
+    opts = lw.RunOpts(lw.FP64, 0, 1, 0.0, 0, 0)
+    size = ct.c_int64(0)
+    code = lw.load_library().lw_dipole_state_size(arr, m, off.ctypes.data_as(ct.POINTER(ct.c_int32)), 2, dt,
+                                                  ct.byref(opts), ct.byref(size))
+    assert code == 0
+    need = math.ceil(2 * 40e-9 / 299792458.0 / dt) + 3
+    ring = 4
+    while ring < need:
+        ring *= 2
+    assert size.value == 4 + n * ring * 3 + 3 * n
+    opts.ring_depth = 256
+    lw.load_library().lw_dipole_state_size(arr, m, off.ctypes.data_as(ct.POINTER(ct.c_int32)), 2, dt,
+                                           ct.byref(opts), ct.byref(size))
+    assert size.value == 4 + n * 256 * 3 + 3 * n
