@@ -132,6 +132,20 @@ def run_part(part: str, cluster_steps: int, precision: str, I, lw, torch):
     log(f"[bench] {part}: {(time.perf_counter() - t0) * 1e3:.2f} ms")
 
 
+def tuned_threshold(precision: str):
+    """The stepped-path threshold the library tuned for the last oscillator shape class of
+    this precision, from the tuning file (LW_TUNE_CACHE); None if there is none."""
+    path = os.environ.get("LW_TUNE_CACHE", "")
+    if not path or not os.path.exists(path):
+        return None
+    code = {"fp64": 0, "mixed": 1}[precision]
+    found = None
+    for line in open(path):
+        if line.startswith(f"dipoles p{code} ") and "|" in line:
+            found = int(line.split("|")[1])
+    return found
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +172,14 @@ def main():
               "grid tile is independent, so N GPUs would shard the workload without exchange)",
               file=sys.stderr)
         sys.exit(2)
+
+    # a fresh tuning file, unless one is given: the library writes its tuned launch
+    # choices there, and the bench reports the oscillator threshold it picked
+    if not os.environ.get("LW_TUNE_CACHE"):
+        import tempfile
+        fd, tune_path = tempfile.mkstemp(prefix="lw_tune_", suffix=".txt")
+        os.close(fd)
+        os.environ["LW_TUNE_CACHE"] = tune_path
 
     import numpy as np
     import torch
@@ -300,16 +322,20 @@ def main():
                             "mixed: FP32 velocity and radiation terms of each source dipole, FP64 static "
                             "near-field term, retarded times, state and sums"}
         for prec in ("fp64", "mixed"):
-            lw.dipole_run(cw["dipoles"], cw["inst_off"], cw["dt"], 10, out_stride=10, precision=prec)
+            # the warm-up call tunes the stepped-path threshold for this shape class
+            lw.dipole_run(cw["dipoles"], cw["inst_off"], cw["dt"], 10, out_stride=10, precision=prec,
+                          stepped_min_n="tune")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             lw.dipole_run(cw["dipoles"], cw["inst_off"], cw["dt"], cw["steps"], out_stride=10, check=False,
-                          precision=prec)
+                          precision=prec, stepped_min_n="tune")
             torch.cuda.synchronize()
             csec = time.perf_counter() - t0
             lw.sync_status()
-            clusters[prec] = {"dipole_steps_per_s": n_c * cw["steps"] / csec, "ms": round(csec * 1e3, 3)}
-            log(f"[bench] clusters ({prec}): {csec * 1e3:.1f} ms for {cw['steps']} steps, "
+            clusters[prec] = {"dipole_steps_per_s": n_c * cw["steps"] / csec, "ms": round(csec * 1e3, 3),
+                              "stepped_min_n": tuned_threshold(prec)}
+            log(f"[bench] clusters ({prec}, stepped path from {clusters[prec]['stepped_min_n']} dipoles): "
+                f"{csec * 1e3:.1f} ms for {cw['steps']} steps, "
                 f"{clusters[prec]['dipole_steps_per_s']:.3e} dipole-steps/s")
         clusters["mixed_over_fp64"] = round(clusters["fp64"]["ms"] / clusters["mixed"]["ms"], 3)
         dw = I.workload_detector()

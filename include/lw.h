@@ -212,8 +212,14 @@ typedef struct {
     int32_t stepped_min_n; /* instances of at least this many dipoles (or whose history does
                               not fit in LDS) advance one launch per step with one workgroup
                               per dipole; smaller ones run whole in one workgroup
-                              (0: 16; < 0: only when the history does not fit)             */
+                              (0: 16; LW_STEPPED_TUNE: the fastest threshold for the run's
+                              shape class, timed on trial runs of its dipoles at the first
+                              call (which then synchronises the stream) and cached like the
+                              grid shapes; other negative values: only when the history
+                              does not fit)                                              */
 } lw_run_opts;
+
+enum { LW_STEPPED_TUNE = -2 };
 
 /* Runs `steps` RK4 steps of Eq. (LO_equation) for n_inst independent
  * instances; instance k holds dipoles [h_inst_off[k], h_inst_off[k+1]) of

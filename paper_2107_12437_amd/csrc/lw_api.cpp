@@ -69,7 +69,10 @@ struct lw_ctx {
     size_t work2_cap = 0;
     bool autotune = true;
     std::map<std::string, lw::FieldLaunch> tuned;
+    std::map<std::string, int> tuned_dip;   // oscillator runs: shape class -> stepped-path threshold
     std::string tune_file;
+    double *d_trial = nullptr;         // tuner trial outputs
+    size_t trial_cap = 0;
 };
 
 namespace {
@@ -201,8 +204,11 @@ void load_tune_file(lw_ctx *ctx)
         std::string key(line, bar - line);
         while (!key.empty() && key.back() == ' ') key.pop_back();
         int b = 0, t = 0;
-        if (std::sscanf(bar + 1, "%d %d", &b, &t) == 2 && b >= 64 && b <= 256 && b % 64 == 0 && t >= 1)
+        if (key.rfind("dipoles", 0) == 0) {
+            if (std::sscanf(bar + 1, "%d", &b) == 1 && b >= 2) ctx->tuned_dip[key] = b;
+        } else if (std::sscanf(bar + 1, "%d %d", &b, &t) == 2 && b >= 64 && b <= 256 && b % 64 == 0 && t >= 1) {
             ctx->tuned[key] = lw::FieldLaunch{b, t};
+        }
     }
     std::fclose(fp);
 }
@@ -213,6 +219,15 @@ void save_tune_entry(lw_ctx *ctx, const std::string &key, const lw::FieldLaunch 
     FILE *fp = std::fopen(ctx->tune_file.c_str(), "a");
     if (!fp) return;
     std::fprintf(fp, "%s | %d %d\n", key.c_str(), L.block, L.tchunk);
+    std::fclose(fp);
+}
+
+void save_tune_dip(lw_ctx *ctx, const std::string &key, int threshold)
+{
+    if (ctx->tune_file.empty()) return;
+    FILE *fp = std::fopen(ctx->tune_file.c_str(), "a");
+    if (!fp) return;
+    std::fprintf(fp, "%s | %d\n", key.c_str(), threshold);
     std::fclose(fp);
 }
 
@@ -357,6 +372,7 @@ lw_status lw_destroy(lw_ctx *ctx)
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     if (ctx->d_work) (void)hipFree(ctx->d_work);
     if (ctx->d_work2) (void)hipFree(ctx->d_work2);
+    if (ctx->d_trial) (void)hipFree(ctx->d_trial);
     if (ctx->d_err) (void)hipFree(ctx->d_err);
     delete ctx;
     return LW_OK;
@@ -624,6 +640,99 @@ static lw_status run_geometry(const char *who, const lw_dipole *h_dip, int32_t n
 static lw_status dipole_run_impl(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
                                  int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts,
                                  double *d_moment, double *d_dot, double *d_energy, double *d_drive, double *d_wabs,
+                                 double *d_wrad, double *d_state, int64_t n_state, bool resume, void *stream);
+
+// Stepped-path threshold (stepped_min_n) for a run's shape class: precision,
+// moving origins, dt policy, history depth and the instance sizes by power of
+// two.  Cached in the context (and the LW_TUNE_CACHE file); otherwise each
+// threshold that splits the instances differently is timed on trial runs of
+// the call's own dipoles, and the fastest is kept.  A trial's per-step cost is
+// the difference of a 512-step and a 256-step run, so the per-call cost of
+// staging and graph capture drops out.  Trials write two rows of moments into
+// a context buffer and no run state; tuning synchronises the stream once.
+static lw_status tune_stepped(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
+                              int32_t n_inst, double dt, const lw_run_opts *opts, int ring, hipStream_t s, int *out)
+{
+    bool moving = false;
+    for (int i = 0; i < n_dip; ++i) moving = moving || motion_reach(h_dip[i]) > 0.0;
+    std::map<int, int> sizes;                        // ceil(log2 n) -> instances
+    int max_n = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const int n = h_inst_off[k + 1] - h_inst_off[k];
+        if (n <= 0) continue;
+        int b = 0;
+        while ((1 << b) < n) ++b;
+        ++sizes[b];
+        max_n = std::max(max_n, n);
+    }
+    std::string key = "dipoles p" + std::to_string(opts->precision) + " m" + std::to_string(moving ? 1 : 0) + " d" +
+                      std::to_string(opts->dt_policy) + " r" + std::to_string(ring) + " n";
+    for (const auto &kv : sizes) key += " " + std::to_string(1 << kv.first) + ":" + std::to_string(kv.second);
+    auto it = ctx->tuned_dip.find(key);
+    if (it != ctx->tuned_dip.end()) {
+        *out = it->second;
+        return LW_OK;
+    }
+    *out = 16;
+    if (!ctx->autotune) return LW_OK;
+    // candidate thresholds: powers of two up to past the largest instance, one
+    // per distinct split of the instances
+    std::vector<int> cand;
+    int last_split = -1;
+    for (int T = 2; T <= 2 * std::max(max_n, 2); T <<= 1) {
+        int stepped = 0;
+        for (int k = 0; k < n_inst; ++k) {
+            const int n = h_inst_off[k + 1] - h_inst_off[k];
+            if (n > 0 && (n >= T || lw::ring_lds_bytes(n, ring) > 64 * 1024)) ++stepped;
+        }
+        if (stepped != last_split) cand.push_back(T);
+        last_split = stepped;
+    }
+    const size_t need = sizeof(double) * 2 * (size_t)n_dip;
+    if (ctx->trial_cap < need) {
+        LW_HIP(hipStreamSynchronize(s));
+        if (ctx->d_trial) LW_HIP(hipFree(ctx->d_trial));
+        ctx->d_trial = nullptr;
+        ctx->trial_cap = 0;
+        if (hipMalloc((void **)&ctx->d_trial, need) != hipSuccess) return fail(LW_E_NOMEM, "tuner trial buffer");
+        ctx->trial_cap = need;
+    }
+    hipEvent_t ev[3];
+    for (auto &e : ev) LW_HIP(hipEventCreate(&e));
+    float best = 1e30f;
+    lw_status st = LW_OK;
+    for (int T : cand) {
+        lw_run_opts o = *opts;
+        o.stepped_min_n = T;
+        float ms[2] = {0.f, 0.f};
+        for (int r = 0; r < 2 && st == LW_OK; ++r) {
+            const int64_t n_steps = 256 << r;
+            o.out_stride = n_steps;
+            if (hipEventRecord(ev[0], s) != hipSuccess) st = fail(LW_E_HIP, "tuner timing");
+            if (st == LW_OK)
+                st = dipole_run_impl(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, n_steps, &o, ctx->d_trial, nullptr,
+                                     nullptr, nullptr, nullptr, nullptr, nullptr, 0, false, (void *)s);
+            if (st == LW_OK && (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                                hipEventElapsedTime(&ms[r], ev[0], ev[1]) != hipSuccess))
+                st = fail(LW_E_HIP, "tuner timing");
+        }
+        if (st != LW_OK) break;
+        const float per_step = (ms[1] - ms[0]) / 256.0f;
+        if (per_step < best) {
+            best = per_step;
+            *out = T;
+        }
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (st != LW_OK) return st;
+    ctx->tuned_dip[key] = *out;
+    save_tune_dip(ctx, key, *out);
+    return LW_OK;
+}
+
+static lw_status dipole_run_impl(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
+                                 int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts,
+                                 double *d_moment, double *d_dot, double *d_energy, double *d_drive, double *d_wabs,
                                  double *d_wrad, double *d_state, int64_t n_state, bool resume, void *stream)
 {
     if (!ctx || !opts || !h_dip || !h_inst_off || !d_moment) return fail(LW_E_INVALID, "lw_dipole_run: null argument");
@@ -641,7 +750,11 @@ static lw_status dipole_run_impl(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_
     // small instances whose ring fits in LDS run whole in one workgroup each;
     // the others advance one launch per step with one workgroup per dipole
     const int lds_limit = 64 * 1024;
-    const int stepped_min = opts->stepped_min_n == 0 ? 16 : (opts->stepped_min_n < 0 ? (1 << 30) : opts->stepped_min_n);
+    int stepped_min = opts->stepped_min_n == 0 ? 16 : (opts->stepped_min_n < 0 ? (1 << 30) : opts->stepped_min_n);
+    if (opts->stepped_min_n == LW_STEPPED_TUNE) {
+        const lw_status tst = tune_stepped(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, opts, ring, s, &stepped_min);
+        if (tst != LW_OK) return tst;
+    }
     std::vector<int32_t> lds_list, tgt, tgt_lo, tgt_n;
     std::vector<int64_t> tgt_base;
     int max_lds_n = 0;

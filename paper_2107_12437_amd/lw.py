@@ -316,9 +316,12 @@ class LWFieldsFn(torch.autograd.Function):
         return g.cpu(), None, None, None, None, None, None
 
 
+STEPPED_TUNE = -2     # stepped_min_n: threshold timed per shape class (also "tune")
+
+
 def _run_opts(policy, out_stride, max_vel, ring_depth, stepped_min_n, precision) -> RunOpts:
-    return RunOpts(PRECISIONS[precision], DT_POLICIES[policy], int(out_stride), float(max_vel), int(ring_depth),
-                   int(stepped_min_n))
+    smn = STEPPED_TUNE if stepped_min_n == "tune" else int(stepped_min_n)
+    return RunOpts(PRECISIONS[precision], DT_POLICIES[policy], int(out_stride), float(max_vel), int(ring_depth), smn)
 
 
 def dipole_state(dipoles: dict, inst_off, dt: float, policy: str = "strict", ring_depth: int = 0,
@@ -334,9 +337,9 @@ def dipole_state(dipoles: dict, inst_off, dt: float, policy: str = "strict", rin
 
 
 def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "strict", out_stride: int = 1,
-               max_vel: float = 0.0, ring_depth: int = 0, stepped_min_n: int = 0, device=None, check: bool = True,
-               ctx: Context | None = None, energy_balance: bool = False, precision: str = "fp64",
-               state: torch.Tensor | None = None, resume: bool = False):
+               max_vel: float = 0.0, ring_depth: int = 0, stepped_min_n: int | str = 0, device=None,
+               check: bool = True, ctx: Context | None = None, energy_balance: bool = False,
+               precision: str = "fp64", state: torch.Tensor | None = None, resume: bool = False):
     """Self-consistent oscillator run (Algorithm 1).  Returns a dict of [n_out][n_dip]
     float64 GPU tensors: d, d_dot, energy, Ed, and with energy_balance the work absorbed
     from the drive field W_abs and the Larmor energy radiated W_rad since t = 0 (Sec. 2.5:
@@ -344,7 +347,8 @@ def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "st
     evaluates each source dipole's pair field in FP32 (retarded times, state and sums stay
     FP64).  With a run state (dipole_state) the run's state after its last step is kept
     there, and resume=True continues the run that state holds: row 0 is then the state's
-    step and `steps` more are taken."""
+    step and `steps` more are taken.  stepped_min_n="tune" lets the library time the
+    instance-size threshold of the stepped path for this shape class (cached)."""
     dev = _as_device(device)
     ctx = ctx or default_context(dev.index)
     arr, n = pack_dipoles(dipoles)
