@@ -1,10 +1,15 @@
 // lw_dipole.hip -- self-consistent Lorentz-oscillator runs on gfx950.
 //
-// Algorithm 1 of the paper, one workgroup per independent instance, persistent
-// over all time steps.  Each step:
+// Algorithm 1 of the paper.  Small instances run persistently over all time
+// steps in one workgroup each (lo_instances_kernel); large ones take one
+// launch per step with one workgroup per target dipole (lo_step_kernel).
+// Each step:
 //   1. every (target i, stage time, source dipole j != i, charge +/-) pair
-//      solves its retarded time against j's stored history and evaluates the
-//      Lienard-Wiechert field of Eq. (E) at R_i projected on p_i (FP64);
+//      solves its retarded time against j's stored history (in closed form on
+//      the linear interpolation segment, Newton past the newest stored step or
+//      for a moving source) and evaluates the Lienard-Wiechert field of Eq. (E)
+//      at R_i projected on p_i: per charge in FP64, or in the mixed form per
+//      source dipole (FP64 static monopole difference, FP32 remainder);
 //   2. the pairs of one (target, stage) are summed in a fixed order by a lane
 //      group and a shuffle tree (bitwise reproducible);
 //   3. one lane per dipole takes the RK4 step of Eq. (LO_equation), writes
@@ -103,8 +108,9 @@ __device__ __forceinline__ void hist_at(const Hist &H, int j, double d0, int64_t
 
 // Retarded time of the charge at offset cf d(t') p_j of source j, seen from a
 // point at separation Delta (|Delta|^2 = L2, Delta . p_j = sD) from the
-// source's origin at time base * dt: the root of c tau = |Delta - cf d(t -
-// tau) p_j| in [0, tau_hi], from tau.  Newton uses the exact slope of the
+// source's origin at time base * dt, by Newton (where the closed form of
+// retarded_seg does not apply: past the newest stored step): the root of
+// c tau = |Delta - cf d(t - tau) p_j| in [0, tau_hi], from tau.  Newton uses the exact slope of the
 // interpolated moment.  Within one interpolation segment (or one side of the
 // history's ends) g is smooth with |g''| <= rho'^2 / D + |rho''| (rho = cf d),
 // so once Newton's error bound from the current iterate is below tol/4 the new
