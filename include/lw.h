@@ -284,8 +284,15 @@ lw_status lw_dipole_run_state(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip
  * every drive pair's retarded time is differentiated by the implicit-function
  * theorem against the interpolated history, and the cotangents owed to earlier
  * source times accumulate in an adjoint history read back as the sweep reaches
- * them.  The forward history is kept whole in device memory (24 bytes per dipole
- * per step).
+ * them.
+ *   ckpt_every   0 (or >= steps): the forward history is kept whole in device
+ *                memory (24 bytes per dipole per step).  K > 0: checkpointed:
+ *                the forward run keeps its run state (as lw_dipole_run_state)
+ *                every K steps, and the backward sweep recomputes each segment
+ *                of K steps from its state, last segment first, so the device
+ *                holds the states and a window of K steps plus the retarded
+ *                look-back instead of the whole run.  Costs one more forward
+ *                run; the result equals the whole-history one to rounding.
  *   d_det_pts    device FP64 SoA [3][n_det]
  *   h_snap_times host FP64 [n_snap], each in [0, steps dt]
  *   d_grad_pos   device FP64 [n_dip][3]: dJ/d origin, overwritten
@@ -295,8 +302,8 @@ lw_status lw_dipole_run_state(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip
  * atomics: results agree to rounding between runs, not bitwise. */
 lw_status lw_dipole_run_vjp(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
                             int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts, const double *d_det_pts,
-                            int64_t n_det, const double *h_snap_times, int32_t n_snap, double *d_grad_pos,
-                            double *h_J, void *stream);
+                            int64_t n_det, const double *h_snap_times, int32_t n_snap, int32_t ckpt_every,
+                            double *d_grad_pos, double *h_J, void *stream);
 
 /* Collective decay rates and frequency shift of two-dipole instances from a
  * finished run's moments (Sec. 2.4, Eq. (KE)): the sum and difference of the

@@ -919,10 +919,183 @@ lw_status lw_dipole_state_size(const lw_dipole *h_dip, int32_t n_dip, const int3
     return LW_OK;
 }
 
+// The adjoint over segments of K steps recomputed from run states.  The
+// forward pass keeps a run state every K steps; then, from the last segment
+// to the first, the segment is run again from its state with every step
+// stored, the history window (the segment and the state's depth before it) is
+// rebuilt in a ring, and the backward steps are taken, each detector snapshot
+// being reversed just before the sweep consumes its newest sample.  The ring
+// depth of the run states covers both the drive pairs' retarded times and the
+// detector's (the longest detector-to-dipole light time).  Memory: one run
+// state per segment and a window of K + depth steps, instead of the whole run.
+static lw_status vjp_checkpointed(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
+                                  int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts,
+                                  const double *d_det_pts, int64_t n_det, const double *h_snap_times, int32_t n_snap,
+                                  int64_t K, double *d_grad_pos, double *h_J, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    int ring_geo = 0;
+    lw_status st = run_geometry("lw_dipole_run_vjp", h_dip, n_dip, h_inst_off, n_inst, dt, steps, opts, &ring_geo);
+    if (st != LW_OK) return st;
+    // the detector's look-back: an upper bound on the light time from a detector
+    // point to an origin (the farthest corner of the points' bounding box),
+    // doubled and padded as for the drive pairs
+    std::vector<double> P((size_t)(3 * n_det));
+    LW_HIP(hipMemcpyAsync(P.data(), d_det_pts, sizeof(double) * P.size(), hipMemcpyDeviceToHost, s));
+    LW_HIP(hipStreamSynchronize(s));
+    double lo[3], hi[3];
+    for (int c = 0; c < 3; ++c) {
+        const double *x = P.data() + c * n_det;
+        lo[c] = *std::min_element(x, x + n_det);
+        hi[c] = *std::max_element(x, x + n_det);
+        if (!std::isfinite(lo[c]) || !std::isfinite(hi[c]))
+            return fail(LW_E_INVALID, "lw_dipole_run_vjp: detector points must be finite");
+    }
+    double reach2 = 0.0;
+    for (int i = 0; i < n_dip; ++i) {
+        double r2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double e = std::max(std::fabs(lo[c] - h_dip[i].origin[c]), std::fabs(hi[c] - h_dip[i].origin[c]));
+            r2 += e * e;
+        }
+        reach2 = std::max(reach2, r2);
+    }
+    const double w_det = std::ceil(2.0 * std::sqrt(reach2) / C_LIGHT / dt) + 3.0;
+    if (!(w_det < (double)(1 << 24))) return fail(LW_E_INVALID, "lw_dipole_run_vjp: detector too far for dt");
+    int ring_fwd = 4;
+    while (ring_fwd < std::max<int64_t>(ring_geo, (int64_t)w_det + 6)) ring_fwd <<= 1;
+    int64_t ring_h = 4;
+    while (ring_h < K + ring_fwd + 4) ring_h <<= 1;
+    if (ring_h > (1 << 26)) return fail(LW_E_INVALID, "lw_dipole_run_vjp: checkpoint interval too long");
+    const int64_t n_seg = (steps + K - 1) / K;
+    const int64_t sd = lw::state_doubles(n_dip, ring_fwd);
+    std::vector<int64_t> pair_off(n_inst + 1, 0), pair_off0(n_inst + 1, 0);
+    for (int k = 0; k < n_inst; ++k) {
+        const int64_t n = h_inst_off[k + 1] - h_inst_off[k];
+        pair_off[k + 1] = pair_off[k] + 4 * n * (n - 1);
+        pair_off0[k + 1] = pair_off0[k] + 2 * n * (n - 1);
+    }
+    const int64_t n_pairs = pair_off[n_inst], n_pairs0 = pair_off0[n_inst];
+    const int64_t nblk1 = (n_det + 255) / 256;                 // J partials per snapshot
+    const size_t ck_b = align_up(sizeof(double) * (size_t)(sd * n_seg), 256);
+    const size_t ws_b = align_up(sizeof(double) * (size_t)sd, 256);
+    const size_t out_b = align_up(sizeof(double) * (size_t)((K + 1) * n_dip), 256);
+    const size_t hist_b = align_up(sizeof(double) * (size_t)(ring_h * n_dip * 3), 256);
+    const size_t jp_b = align_up(sizeof(double) * (size_t)(nblk1 * n_snap + 1), 256);
+    const size_t dip_b = align_up(sizeof(lw_dipole) * (size_t)n_dip, 256);
+    const size_t off_b = align_up(sizeof(int32_t) * (size_t)(n_inst + 1), 256);
+    const size_t po_b = align_up(sizeof(int64_t) * (size_t)(n_inst + 1), 256);
+    const size_t tm_b = align_up(sizeof(double) * (size_t)n_snap, 256);
+    const size_t dev_b = align_up(lw::dip_dev_bytes(n_dip), 256);
+    const size_t adj_b = align_up(sizeof(double) * 6 * (size_t)n_dip, 256);
+    const size_t rbp_b = align_up(sizeof(double) * 3 * (size_t)std::max<int64_t>(n_pairs, 1), 256);
+    const size_t rbp0_b = align_up(sizeof(double) * 3 * (size_t)std::max<int64_t>(n_pairs0, 1), 256);
+    const size_t taup_b = align_up(sizeof(double) * (size_t)std::max<int64_t>(n_pairs, 1), 256);
+    const size_t stage_b = dip_b + off_b + 2 * po_b + tm_b;
+    st = ensure_work2(ctx, ck_b + ws_b + 3 * out_b + 2 * hist_b + jp_b + 256 + stage_b + dev_b + adj_b + rbp_b +
+                               rbp0_b + taup_b + 256, s);
+    if (st != LW_OK) return st;
+    char *w2 = (char *)ctx->d_work2;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { char *p = w2 + o; o += bytes; return p; };
+    double *d_ckpt = (double *)take(ck_b);
+    double *d_ws = (double *)take(ws_b);
+    double *d_D = (double *)take(out_b);
+    double *d_V = (double *)take(out_b);
+    double *d_Ed = (double *)take(out_b);
+    double *d_hist = (double *)take(hist_b);
+    double *d_hbar = (double *)take(hist_b);
+    double *d_Jpart = (double *)take(jp_b);
+    double *d_J = (double *)take(256);
+    char *stage_dev = take(stage_b);
+    lw::DipDev *d_dev = (lw::DipDev *)take(dev_b);
+    double *d_adj = (double *)take(adj_b);
+    double *d_rbp = (double *)take(rbp_b);
+    double *d_rbp0 = (double *)take(rbp0_b);
+    double *d_taup = (double *)take(taup_b);
+    int64_t *d_step = (int64_t *)take(256);
+    // records, offsets, pair offsets and snapshot times for the adjoint kernels
+    st = acquire_stage(ctx, stage_b);
+    if (st != LW_OK) return st;
+    char *stage = (char *)ctx->h_stage;
+    std::memcpy(stage, h_dip, sizeof(lw_dipole) * (size_t)n_dip);
+    std::memcpy(stage + dip_b, h_inst_off, sizeof(int32_t) * (size_t)(n_inst + 1));
+    std::memcpy(stage + dip_b + off_b, pair_off.data(), sizeof(int64_t) * (size_t)(n_inst + 1));
+    std::memcpy(stage + dip_b + off_b + po_b, pair_off0.data(), sizeof(int64_t) * (size_t)(n_inst + 1));
+    std::memcpy(stage + dip_b + off_b + 2 * po_b, h_snap_times, sizeof(double) * (size_t)n_snap);
+    st = upload(ctx, stage_dev, stage_b, s);
+    if (st != LW_OK) return st;
+    const lw_dipole *d_in = (const lw_dipole *)stage_dev;
+    const int32_t *d_off = (const int32_t *)(stage_dev + dip_b);
+    const int64_t *d_pair_off = (const int64_t *)(stage_dev + dip_b + off_b);
+    const int64_t *d_pair_off0 = (const int64_t *)(stage_dev + dip_b + off_b + po_b);
+    const double *d_times = (const double *)(stage_dev + dip_b + off_b + 2 * po_b);
+    LW_HIP(lw::launch_dipole_prep(d_in, n_dip, d_dev, s));
+    // forward pass: a run state every K steps (outputs: two rows per segment, discarded)
+    lw_run_opts fo = *opts;
+    fo.ring_depth = ring_fwd;
+    for (int64_t g = 0; g < n_seg; ++g) {
+        const int64_t a = g * K, ks = std::min(K, steps - a);
+        if (g > 0) LW_HIP(hipMemcpyAsync(d_ckpt + g * sd, d_ws, sizeof(double) * sd, hipMemcpyDeviceToDevice, s));
+        fo.out_stride = ks;
+        st = lw_dipole_run_state(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, ks, &fo, d_D, nullptr, nullptr, nullptr,
+                                 nullptr, nullptr, d_ws, sd, g > 0 ? 1 : 0, stream);
+        if (st != LW_OK) return st;
+    }
+    // snapshots in the order the sweep meets them: snapshot k is reversed before
+    // the step that consumes its newest sample, min(floor(t_k / dt), steps - 1)
+    std::vector<int64_t> due(n_snap);
+    std::vector<int> order(n_snap);
+    for (int k = 0; k < n_snap; ++k) {
+        due[k] = std::min<int64_t>((int64_t)std::floor(h_snap_times[k] / dt), steps - 1);
+        order[k] = k;
+    }
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return due[x] > due[y]; });
+    LW_HIP(lw::launch_vjp_begin(n_dip, n_pairs, steps, d_hbar, ring_h * n_dip * 3, d_grad_pos, d_rbp, d_taup, d_adj,
+                                d_step, s));
+    fo.out_stride = 1;
+    size_t next = 0;
+    for (int64_t g = n_seg - 1; g >= 0; --g) {
+        const int64_t a = g * K, ks = std::min(K, steps - a);
+        // the segment again, every step stored
+        if (g > 0) LW_HIP(hipMemcpyAsync(d_ws, d_ckpt + g * sd, sizeof(double) * sd, hipMemcpyDeviceToDevice, s));
+        st = lw_dipole_run_state(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, ks, &fo, d_D, d_V, nullptr, d_Ed, nullptr,
+                                 nullptr, d_ws, sd, g > 0 ? 1 : 0, stream);
+        if (st != LW_OK) return st;
+        if (g > 0)
+            LW_HIP(lw::launch_hist_from_state(d_ckpt + g * sd, d_off, n_inst, n_dip, ring_fwd,
+                                              std::max<int64_t>(a - ring_fwd + 1, 0), a - 1, (int)ring_h, d_hist, s));
+        LW_HIP(lw::launch_hist_rows(d_dev, d_D, d_V, d_Ed, n_dip, ks + 1, a, (int)ring_h, d_hist, s));
+        // backward steps a + ks - 1 .. a
+        int64_t n = a + ks - 1;
+        while (n >= a) {
+            while (next < order.size() && due[order[next]] >= n) {
+                const int k = order[next++];
+                // newest sample of the window: the snapshot reads none later
+                LW_HIP(lw::launch_vjp_detector(d_dev, n_dip, d_hist, d_hbar, (int)ring_h, a + ks, dt, d_det_pts, n_det,
+                                               d_times + k, 1, n_snap, d_grad_pos, d_Jpart + (int64_t)k * nblk1,
+                                               ctx->d_err, s));
+            }
+            const int64_t stop = (next < order.size() && due[order[next]] >= a) ? due[order[next]] : a - 1;
+            LW_HIP(lw::launch_vjp_steps(d_dev, d_off, d_pair_off, n_inst, n_dip, d_hist, d_hbar, (int)ring_h, dt, d_adj,
+                                        d_rbp, d_taup, d_step, n - stop, ctx->d_err, s));
+            n = stop;
+        }
+    }
+    LW_HIP(lw::launch_vjp_end(d_dev, d_off, d_pair_off, d_pair_off0, n_inst, n_pairs0, n_dip, d_hist, d_hbar,
+                              (int)ring_h, dt, d_adj, d_rbp, d_rbp0, d_grad_pos, d_Jpart, nblk1 * n_snap, d_J,
+                              ctx->d_err, s));
+    double J = 0.0;
+    LW_HIP(hipMemcpyAsync(&J, d_J, sizeof(double), hipMemcpyDeviceToHost, s));
+    st = lw_sync_status(ctx, stream);
+    *h_J = J;
+    return st;
+}
+
 lw_status lw_dipole_run_vjp(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
                             int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts, const double *d_det_pts,
-                            int64_t n_det, const double *h_snap_times, int32_t n_snap, double *d_grad_pos, double *h_J,
-                            void *stream)
+                            int64_t n_det, const double *h_snap_times, int32_t n_snap, int32_t ckpt_every,
+                            double *d_grad_pos, double *h_J, void *stream)
 {
     if (!ctx || !opts || !h_dip || !h_inst_off || !d_det_pts || !h_snap_times || !d_grad_pos || !h_J)
         return fail(LW_E_INVALID, "lw_dipole_run_vjp: null argument");
@@ -939,6 +1112,12 @@ lw_status lw_dipole_run_vjp(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, 
         if (motion_reach(h_dip[i]) > 0.0)
             return fail(LW_E_INVALID, "lw_dipole_run_vjp: moving dipoles have no adjoint here");
     if (n_det * (int64_t)n_snap > ((int64_t)1 << 36)) return fail(LW_E_INVALID, "lw_dipole_run_vjp: detector too large");
+    if (ckpt_every < 0) return fail(LW_E_INVALID, "lw_dipole_run_vjp: negative checkpoint interval");
+    if (ckpt_every > 0 && ckpt_every < steps) {
+        LW_HIP(hipSetDevice(ctx->device));
+        return vjp_checkpointed(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, steps, opts, d_det_pts, n_det, h_snap_times,
+                                n_snap, ckpt_every, d_grad_pos, h_J, stream);
+    }
     LW_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     const int64_t rows = steps + 1;

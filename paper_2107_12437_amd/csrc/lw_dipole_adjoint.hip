@@ -18,8 +18,11 @@
 // differentiated by the implicit-function theorem on
 //   g = c tau - |Delta - cf d(t - tau) p_j| = 0,  Delta = R_i - R_j,
 // with d(t') the interpolated (or extrapolated, or pre-history) stored moment.
-// The full history of the forward run is kept in device memory (it is small:
-// 24 bytes per dipole per step), so no segment is recomputed.
+// Either the whole history of the forward run is kept in device memory (24
+// bytes per dipole per step), or the sweep runs over segments recomputed from
+// run states (checkpointing): then the history and its cotangents live in a
+// ring of one segment plus the retarded look-back (hist_rows_kernel,
+// hist_from_state_kernel), and each cotangent slot is cleared once read.
 #include <math.h>
 
 #include "lw_device.hpp"
@@ -231,6 +234,44 @@ __global__ void hist_build_kernel(const DipDev *__restrict__ dev, const double *
     hist[idx * 3 + 2] = P.f * Ed[idx] - P.gamma0 * v - P.omega0 * P.omega0 * d;
 }
 
+// History samples row0 .. row0 + nrows - 1 from a stride-1 run's outputs into
+// a ring of `ring` steps ([ring][n_dip][3]).
+__global__ void hist_rows_kernel(const DipDev *__restrict__ dev, const double *__restrict__ D,
+                                 const double *__restrict__ V, const double *__restrict__ Ed, int n_dip, int64_t nrows,
+                                 int64_t row0, int ring, double *__restrict__ hist)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nrows * n_dip) return;
+    const int64_t row = idx / n_dip;
+    const int i = (int)(idx - row * n_dip);
+    const DipDev &P = dev[i];
+    const double d = D[idx], v = V[idx];
+    double *h = hist + (((row0 + row) & (int64_t)(ring - 1)) * n_dip + i) * 3;
+    h[0] = d;
+    h[1] = v;
+    h[2] = P.f * Ed[idx] - P.gamma0 * v - P.omega0 * P.omega0 * d;
+}
+
+// History samples lo .. hi (at most the run state's depth) from a run state's
+// per-instance rings into the adjoint's ring ([ring][n_dip][3]).
+__global__ void hist_from_state_kernel(const double *__restrict__ state, const int32_t *__restrict__ off, int n_inst,
+                                       int n_dip, int ring_state, int64_t lo, int64_t hi, int ring,
+                                       double *__restrict__ hist)
+{
+    const int64_t nk = hi - lo + 1;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (nk <= 0 || idx >= nk * n_dip) return;
+    const int64_t k = lo + idx / n_dip;
+    const int g = (int)(idx % n_dip);
+    const int inst = instance_of(off, n_inst, g);
+    const int a0 = off[inst], n = off[inst + 1] - a0;
+    const double *src = state + state_ring_off(a0, ring_state) + ((k & (int64_t)(ring_state - 1)) * n + (g - a0)) * 3;
+    double *dst = hist + ((k & (int64_t)(ring - 1)) * n_dip + g) * 3;
+    dst[0] = src[0];
+    dst[1] = src[1];
+    dst[2] = src[2];
+}
+
 // Detector field, objective partials and the detector's cotangents: one lane
 // per (snapshot, point); instances are laid out in the history by the global
 // dipole index (one shared [ring][n_dip][3] array).  The lanes of a workgroup
@@ -244,7 +285,7 @@ __global__ __launch_bounds__(256) void detector_vjp_kernel(const DipDev *__restr
                                                            const double *__restrict__ hist, double *__restrict__ hbar,
                                                            int ring, int64_t nstep, double dt,
                                                            const double *__restrict__ pts, int64_t npts,
-                                                           const double *__restrict__ times, int n_snap,
+                                                           const double *__restrict__ times, int n_snap, int n_norm,
                                                            double *__restrict__ Rbar, double *__restrict__ Jpart,
                                                            int max_iter, uint32_t *__restrict__ d_err)
 {
@@ -281,13 +322,13 @@ __global__ __launch_bounds__(256) void detector_vjp_kernel(const DipDev *__restr
         }
     }
     // objective partial per workgroup (fixed order)
-    double jv = live ? (E[0] * E[0] + E[1] * E[1] + E[2] * E[2]) / n_snap : 0.0;
+    double jv = live ? (E[0] * E[0] + E[1] * E[1] + E[2] * E[2]) / n_norm : 0.0;
     for (int off = 32; off > 0; off >>= 1) jv += __shfl_xor(jv, off, 64);
     if (lane == 0) red[wave] = jv;
     __syncthreads();
     if (tid == 0) Jpart[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
     // cotangent of E and its scatter
-    const double Eb[3] = {2.0 * E[0] / n_snap, 2.0 * E[1] / n_snap, 2.0 * E[2] / n_snap};
+    const double Eb[3] = {2.0 * E[0] / n_norm, 2.0 * E[1] / n_norm, 2.0 * E[2] / n_norm};
     for (int j = 0; j < n_dip; ++j) {
         const DipDev &Dj = dev[j];
         const DipLds Sj = dip_lds(Dj);
@@ -414,11 +455,16 @@ __device__ __forceinline__ void rk4_transpose(const DipDev &P, double h, AdjStat
 // Adds the completed cotangent of sample n (d, d_dot, d_ddot = f Ec - gamma0
 // d_dot - omega0^2 d) of dipole g: into y[n] unless n = 0 (y[0] is fixed), and
 // into the drive at t_n (ext for the step before).
-__device__ __forceinline__ void take_sample(const DipDev &P, const double *hbar, int64_t n, int n_dip, int mask,
+// The slot is cleared once read, so a ring shorter than the run can hold the
+// adjoint history (no pair adds to sample n once the sweep has passed step n).
+__device__ __forceinline__ void take_sample(const DipDev &P, double *hbar, int64_t n, int n_dip, int mask,
                                             AdjState &A, int g)
 {
-    const double *hb = hbar + ((int64_t)(n & mask) * n_dip + g) * 3;
+    double *hb = hbar + ((int64_t)(n & mask) * n_dip + g) * 3;
     const double bd = load_agent(hb), bv = load_agent(hb + 1), ba = load_agent(hb + 2);
+    hb[0] = 0.0;
+    hb[1] = 0.0;
+    hb[2] = 0.0;
     if (n > 0) {
         A.yd[g] += bd - P.omega0 * P.omega0 * ba;
         A.yv[g] += bv - P.gamma0 * ba;
@@ -559,7 +605,7 @@ __global__ __launch_bounds__(BLOCK) void adj_step_kernel(const DipDev *__restric
 }
 
 // After the sweep: sample 0 gives the cotangent of E_d(0) (y[0] is fixed).
-__global__ void adj_finish_kernel(const DipDev *__restrict__ dev, int n_dip, const double *__restrict__ hbar, int mask,
+__global__ void adj_finish_kernel(const DipDev *__restrict__ dev, int n_dip, double *__restrict__ hbar, int mask,
                                   AdjState A)
 {
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n_dip; g += gridDim.x * blockDim.x)
@@ -664,7 +710,7 @@ hipError_t launch_dipole_vjp(const DipDev *d_dev, const int32_t *d_off, const in
     const int64_t lanes = npts * n_snap;
     const unsigned nblk = (unsigned)((lanes + 255) / 256);
     hipLaunchKernelGGL(detector_vjp_kernel, dim3(nblk), dim3(256), 0, s, d_dev, n_dip, d_hist, d_hbar, ring, steps,
-                       dt, d_pts, npts, d_times, n_snap, d_grad, d_Jpart, max_iter, d_err);
+                       dt, d_pts, npts, d_times, n_snap, n_snap, d_grad, d_Jpart, max_iter, d_err);
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, d_Jpart, (int64_t)nblk, d_J);
     AdjState A{d_state, d_state + n_dip, d_state + 2 * (int64_t)n_dip, d_state + 3 * (int64_t)n_dip,
                d_state + 4 * (int64_t)n_dip, d_state + 5 * (int64_t)n_dip};
@@ -712,6 +758,95 @@ hipError_t launch_dipole_vjp(const DipDev *d_dev, const int32_t *d_off, const in
                            d_pair_off0, n_inst, n_pairs0, n_dip, d_hist, mask, dt, A, d_rbp0, max_iter, d_err);
     hipLaunchKernelGGL(adj_positions_kernel, dim3((unsigned)n_inst), dim3(256), 0, s, d_off, d_pair_off, d_pair_off0,
                        n_inst, d_rbp, d_rbp0, d_grad);
+    return hipGetLastError();
+}
+
+// --- pieces of the checkpointed sweep (segments recomputed from run states) ---
+
+hipError_t launch_hist_rows(const DipDev *d_dev, const double *d_D, const double *d_V, const double *d_Ed, int n_dip,
+                            int64_t nrows, int64_t row0, int ring, double *d_hist, hipStream_t s)
+{
+    const int64_t n = nrows * n_dip;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(hist_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d_dev, d_D, d_V, d_Ed,
+                       n_dip, nrows, row0, ring, d_hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist_from_state(const double *d_state, const int32_t *d_off, int n_inst, int n_dip, int ring_state,
+                                  int64_t lo, int64_t hi, int ring, double *d_hist, hipStream_t s)
+{
+    const int64_t n = (hi - lo + 1) * n_dip;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(hist_from_state_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d_state, d_off,
+                       n_inst, n_dip, ring_state, lo, hi, ring, d_hist);
+    return hipGetLastError();
+}
+
+static AdjState adj_state(double *d_state, int n_dip)
+{
+    return AdjState{d_state, d_state + n_dip, d_state + 2 * (int64_t)n_dip, d_state + 3 * (int64_t)n_dip,
+                    d_state + 4 * (int64_t)n_dip, d_state + 5 * (int64_t)n_dip};
+}
+
+hipError_t launch_vjp_begin(int n_dip, int64_t n_pairs, int64_t steps, double *d_hbar, int64_t hbar_doubles,
+                            double *d_grad, double *d_rbp, double *d_taup, double *d_state, int64_t *d_step,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, s, d_hbar, hbar_doubles);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(1), dim3(256), 0, s, d_grad, (int64_t)n_dip * 3);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, s, d_rbp, n_pairs * 3);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, s, d_taup, n_pairs);
+    hipLaunchKernelGGL(adj_init_kernel, dim3((unsigned)((n_dip + 255) / 256)), dim3(256), 0, s, n_dip, steps,
+                       adj_state(d_state, n_dip), d_step);
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_detector(const DipDev *d_dev, int n_dip, const double *d_hist, double *d_hbar, int ring,
+                               int64_t steps, double dt, const double *d_pts, int64_t npts, const double *d_times,
+                               int n_snap, int n_norm, double *d_grad, double *d_Jpart, uint32_t *d_err,
+                               hipStream_t s)
+{
+    const int64_t lanes = npts * n_snap;
+    if (lanes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(detector_vjp_kernel, dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, s, d_dev, n_dip,
+                       d_hist, d_hbar, ring, steps, dt, d_pts, npts, d_times, n_snap, n_norm, d_grad, d_Jpart, 60,
+                       d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_steps(const DipDev *d_dev, const int32_t *d_off, const int64_t *d_pair_off, int n_inst,
+                            int n_dip, const double *d_hist, double *d_hbar, int ring, double dt, double *d_state,
+                            double *d_rbp, double *d_taup, int64_t *d_step, int64_t count, uint32_t *d_err,
+                            hipStream_t s)
+{
+    constexpr int B = 256;
+    if (count <= 0) return hipSuccess;
+    const AdjState A = adj_state(d_state, n_dip);
+    const double *soa = dip_soa(const_cast<DipDev *>(d_dev), n_dip);
+    for (int64_t k = 0; k < count; ++k)
+        hipLaunchKernelGGL(adj_step_kernel<B>, dim3((unsigned)n_dip), dim3(B), 0, s, d_dev, d_off, d_pair_off, n_inst,
+                           n_dip, d_hist, d_hbar, ring - 1, dt, A, d_rbp, d_taup, d_step, (int)k, 60, soa, d_err);
+    hipLaunchKernelGGL(adj_base_kernel, dim3(1), dim3(1), 0, s, d_step, -count);
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_end(const DipDev *d_dev, const int32_t *d_off, const int64_t *d_pair_off,
+                          const int64_t *d_pair_off0, int n_inst, int64_t n_pairs0, int n_dip, const double *d_hist,
+                          double *d_hbar, int ring, double dt, double *d_state, double *d_rbp, double *d_rbp0,
+                          double *d_grad, const double *d_Jpart, int64_t n_jpart, double *d_J, uint32_t *d_err,
+                          hipStream_t s)
+{
+    constexpr int B = 256;
+    const AdjState A = adj_state(d_state, n_dip);
+    hipLaunchKernelGGL(adj_finish_kernel, dim3((unsigned)((n_dip + 255) / 256)), dim3(256), 0, s, d_dev, n_dip, d_hbar,
+                       ring - 1, A);
+    if (n_pairs0 > 0)
+        hipLaunchKernelGGL(adj_drive0_kernel<B>, dim3((unsigned)((n_pairs0 + B - 1) / B)), dim3(B), 0, s, d_dev, d_off,
+                           d_pair_off0, n_inst, n_pairs0, n_dip, d_hist, ring - 1, dt, A, d_rbp0, 60, d_err);
+    hipLaunchKernelGGL(adj_positions_kernel, dim3((unsigned)n_inst), dim3(256), 0, s, d_off, d_pair_off, d_pair_off0,
+                       n_inst, d_rbp, d_rbp0, d_grad);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, d_Jpart, n_jpart, d_J);
     return hipGetLastError();
 }
 

@@ -99,6 +99,39 @@ hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const 
                                int graph_chunk, hipStream_t s, hipStream_t cap, hipGraph_t *graph_out,
                                hipGraphExec_t *exec_out);
 
+// Pieces of the oscillator adjoint for a sweep over recomputed segments
+// (lw_dipole_adjoint.hip); `ring` is the depth of the windowed history and of
+// its cotangents ([ring][n_dip][3], power of two), whose slots are cleared as
+// the sweep consumes them.  launch_hist_rows: samples row0 .. row0+nrows-1 from
+// a stride-1 run's outputs; launch_hist_from_state: samples lo .. hi from a run
+// state of depth ring_state; launch_vjp_begin: zeroes the cotangents, the
+// gradient and the pair buffers and starts the step base at steps - 1;
+// launch_vjp_detector: J partials (one double per 256 lanes of npts x n_snap)
+// and the detector's cotangents for the given snapshots, J's sum over
+// snapshots being divided by n_norm (the run's snapshot count); launch_vjp_steps:
+// `count` backward steps from the current base; launch_vjp_end: E_d(0), the
+// positions and the sum of n_jpart J partials into d_J.
+hipError_t launch_hist_rows(const DipDev *d_dev, const double *d_D, const double *d_V, const double *d_Ed, int n_dip,
+                            int64_t nrows, int64_t row0, int ring, double *d_hist, hipStream_t s);
+hipError_t launch_hist_from_state(const double *d_state, const int32_t *d_off, int n_inst, int n_dip, int ring_state,
+                                  int64_t lo, int64_t hi, int ring, double *d_hist, hipStream_t s);
+hipError_t launch_vjp_begin(int n_dip, int64_t n_pairs, int64_t steps, double *d_hbar, int64_t hbar_doubles,
+                            double *d_grad, double *d_rbp, double *d_taup, double *d_state, int64_t *d_step,
+                            hipStream_t s);
+hipError_t launch_vjp_detector(const DipDev *d_dev, int n_dip, const double *d_hist, double *d_hbar, int ring,
+                               int64_t steps, double dt, const double *d_pts, int64_t npts, const double *d_times,
+                               int n_snap, int n_norm, double *d_grad, double *d_Jpart, uint32_t *d_err,
+                               hipStream_t s);
+hipError_t launch_vjp_steps(const DipDev *d_dev, const int32_t *d_off, const int64_t *d_pair_off, int n_inst,
+                            int n_dip, const double *d_hist, double *d_hbar, int ring, double dt, double *d_state,
+                            double *d_rbp, double *d_taup, int64_t *d_step, int64_t count, uint32_t *d_err,
+                            hipStream_t s);
+hipError_t launch_vjp_end(const DipDev *d_dev, const int32_t *d_off, const int64_t *d_pair_off,
+                          const int64_t *d_pair_off0, int n_inst, int64_t n_pairs0, int n_dip, const double *d_hist,
+                          double *d_hbar, int ring, double dt, double *d_state, double *d_rbp, double *d_rbp0,
+                          double *d_grad, const double *d_Jpart, int64_t n_jpart, double *d_J, uint32_t *d_err,
+                          hipStream_t s);
+
 // Gradient of the detector objective with respect to the oscillator positions
 // from a finished stride-1 run (lw_dipole_adjoint.hip).  d_hist / d_hbar hold
 // ring x n_dip x 3 doubles (ring >= steps + 1, power of two); d_Jpart one

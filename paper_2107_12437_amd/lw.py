@@ -107,7 +107,7 @@ def load_library(path: str = LIB_PATH):
     L.lw_dipole_state_size.argtypes = [ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, ct.POINTER(RunOpts),
                                        ct.POINTER(i64)]
     L.lw_dipole_run_vjp.argtypes = [vp, ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, i64,
-                                    ct.POINTER(RunOpts), vp, i64, ct.POINTER(dbl), i32, vp, ct.POINTER(dbl), vp]
+                                    ct.POINTER(RunOpts), vp, i64, ct.POINTER(dbl), i32, i32, vp, ct.POINTER(dbl), vp]
     L.lw_pair_modes.argtypes = [ct.POINTER(dbl), i64, i32, ct.POINTER(i32), i32, dbl, i64,
                                 ct.POINTER(dbl), ct.POINTER(i64), ct.POINTER(dbl)]
     L.lw_gamma0.restype = dbl
@@ -379,9 +379,11 @@ def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "st
 
 def dipole_run_vjp(dipoles: dict, inst_off, dt: float, steps: int, det_points: torch.Tensor, snap_times,
                    policy: str = "strict", max_vel: float = 0.0, ring_depth: int = 0, stepped_min_n: int = 0,
-                   ctx: Context | None = None):
+                   ckpt_every: int = 0, ctx: Context | None = None):
     """(J, dJ/d origin [n_dip, 3] GPU tensor) of J = (1/n_snap) sum |E|^2 of all oscillator
-    charges over the detector points ([3, n] float64 on the GPU) at snap_times."""
+    charges over the detector points ([3, n] float64 on the GPU) at snap_times.
+    ckpt_every = K > 0 recomputes the backward sweep's history in segments of K steps from
+    run states kept every K steps; 0 keeps the whole forward history."""
     if not (isinstance(det_points, torch.Tensor) and det_points.is_cuda and det_points.dtype == torch.float64):
         raise ValueError("det_points must be a [3, n] float64 tensor on the GPU")
     pts = det_points.contiguous()
@@ -396,7 +398,7 @@ def dipole_run_vjp(dipoles: dict, inst_off, dt: float, steps: int, det_points: t
     _check(load_library().lw_dipole_run_vjp(ctx.handle, arr, n, off.ctypes.data_as(ct.POINTER(ct.c_int32)),
                                             len(off) - 1, float(dt), int(steps), ct.byref(opts),
                                             ct.c_void_p(pts.data_ptr()), pts.shape[1],
-                                            tms.ctypes.data_as(ct.POINTER(ct.c_double)), len(tms),
+                                            tms.ctypes.data_as(ct.POINTER(ct.c_double)), len(tms), int(ckpt_every),
                                             ct.c_void_p(grad.data_ptr()), ct.byref(J), _stream_ptr(dev)))
     return J.value, grad
 
@@ -407,17 +409,18 @@ class DipoleDetectorFn(torch.autograd.Function):
     of lw_dipole_run_vjp."""
 
     @staticmethod
-    def forward(fctx, origins, template, inst_off, dt, steps, det_points, snap_times, policy):
+    def forward(fctx, origins, template, inst_off, dt, steps, det_points, snap_times, policy, ckpt_every=0):
         dip = {k: np.array(v, copy=True) for k, v in template.items()}
         dip["origin"] = origins.detach().cpu().numpy()
-        J, grad = dipole_run_vjp(dip, inst_off, dt, steps, det_points, snap_times, policy=policy)
+        J, grad = dipole_run_vjp(dip, inst_off, dt, steps, det_points, snap_times, policy=policy,
+                                 ckpt_every=ckpt_every)
         fctx.save_for_backward(grad.cpu())
         return torch.tensor(J, dtype=torch.float64)
 
     @staticmethod
     def backward(fctx, gJ):
         (grad,) = fctx.saved_tensors
-        return gJ * grad, None, None, None, None, None, None, None
+        return gJ * grad, None, None, None, None, None, None, None, None
 
 
 def sync_status(ctx: Context | None = None, device=None):

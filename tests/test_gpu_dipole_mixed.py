@@ -137,6 +137,6 @@ def test_mixed_adjoint_is_rejected():
     ctx = lw.default_context(0)
     code = lw.load_library().lw_dipole_run_vjp(
         ctx.handle, arr, n, off.ctypes.data_as(lw.ct.POINTER(lw.ct.c_int32)), len(off) - 1, float(w["dt"]), 10,
-        lw.ct.byref(opts), lw.ct.c_void_p(pts.data_ptr()), 4, times, 1, lw.ct.c_void_p(grad.data_ptr()),
+        lw.ct.byref(opts), lw.ct.c_void_p(pts.data_ptr()), 4, times, 1, 0, lw.ct.c_void_p(grad.data_ptr()),
         lw.ct.byref(J), None)
     assert code == 1
