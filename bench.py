@@ -88,7 +88,7 @@ def errors(got, ref):
     return res
 
 
-def run_part(part: str, cluster_steps: int, precision: str, I, lw, torch):
+def run_part(part: str, cluster_steps: int, precision: str, ckpt_every: int, I, lw, torch):
     """One workload alone: a warm-up call, then one timed call (for profiler runs)."""
     if part == "pairs":
         pw = I.workload_dipole_pairs()
@@ -121,7 +121,8 @@ def run_part(part: str, cluster_steps: int, precision: str, I, lw, torch):
         opts = torch.tensor(ow["points"], dtype=torch.float64, device="cuda")
 
         def call(steps):
-            lw.dipole_run_vjp(ow["dipoles"], ow["inst_off"], ow["dt"], ow["steps"], opts, ow["times"])
+            lw.dipole_run_vjp(ow["dipoles"], ow["inst_off"], ow["dt"], ow["steps"], opts, ow["times"],
+                              ckpt_every=ckpt_every)
         call(0)
         steps = ow["steps"]
     torch.cuda.synchronize()
@@ -163,6 +164,8 @@ def main():
     ap.add_argument("--part", choices=("pairs", "clusters", "grid-vjp", "adjoint"), default=None,
                     help="run only this workload once after one warm-up, print its time and exit "
                          "(for profiler runs; --cluster-steps sets the cluster run's length)")
+    ap.add_argument("--ckpt-every", type=int, default=250,
+                    help="checkpoint interval of the oscillator adjoint in --part adjoint (0: whole history)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="run one plain device-to-device copy of BYTES and exit (calibrates the "
                          "profiler's byte counters)")
@@ -201,7 +204,7 @@ def main():
         log(f"[bench] copied {4 * n} bytes")
         return
     if args.part:
-        run_part(args.part, args.cluster_steps, args.precision, I, lw, torch)
+        run_part(args.part, args.cluster_steps, args.precision, args.ckpt_every, I, lw, torch)
         return
     w = I.workload_grid_mixed()
     pts = torch.tensor(w["points"], dtype=torch.float64, device="cuda")
@@ -353,20 +356,28 @@ def main():
         pairs = dpts.shape[1] * len(dw["charges"]["kind"]) * len(dw["times"])
         vjp = {"workload": dw["name"], "ms": round(vsec * 1e3, 3), "pair_vjps_per_s": pairs / vsec, "dtype": "f64"}
         log(f"[bench] grid VJP: {vsec * 1e3:.2f} ms, {vjp['pair_vjps_per_s']:.3e} pair VJPs/s")
-        # oscillator adjoint: forward run with stored history, detector VJP, backward sweep
+        # oscillator adjoint: forward run, detector VJP, backward sweep; checkpointed every
+        # 250 steps (segments recomputed) and with the whole history kept
         ow = I.workload_dipole_detector()
         opts_pts = torch.tensor(ow["points"], dtype=torch.float64, device="cuda")
         n_o = len(ow["dipoles"]["omega0"])
-        lw.dipole_run_vjp(ow["dipoles"], ow["inst_off"], ow["dt"], ow["steps"], opts_pts, ow["times"])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        lw.dipole_run_vjp(ow["dipoles"], ow["inst_off"], ow["dt"], ow["steps"], opts_pts, ow["times"])
-        torch.cuda.synchronize()
-        osec = time.perf_counter() - t0
-        dip_vjp = {"workload": ow["name"], "ms": round(osec * 1e3, 3),
-                   "dipole_steps_per_s": n_o * ow["steps"] / osec, "gradients": 3 * n_o, "dtype": "f64",
+        osec = {}
+        for K in (ow["ckpt_every"], 0):
+            lw.dipole_run_vjp(ow["dipoles"], ow["inst_off"], ow["dt"], ow["steps"], opts_pts, ow["times"],
+                              ckpt_every=K)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lw.dipole_run_vjp(ow["dipoles"], ow["inst_off"], ow["dt"], ow["steps"], opts_pts, ow["times"],
+                              ckpt_every=K)
+            torch.cuda.synchronize()
+            osec[K] = time.perf_counter() - t0
+        ck = osec[ow["ckpt_every"]]
+        dip_vjp = {"workload": ow["name"], "ckpt_every": ow["ckpt_every"], "ms": round(ck * 1e3, 3),
+                   "dipole_steps_per_s": n_o * ow["steps"] / ck, "ms_whole_history": round(osec[0] * 1e3, 3),
+                   "gradients": 3 * n_o, "dtype": "f64",
                    "note": "forward run, detector objective and its VJP, backward sweep; one call"}
-        log(f"[bench] oscillator adjoint: {osec * 1e3:.2f} ms for {n_o} dipoles x {ow['steps']} steps")
+        log(f"[bench] oscillator adjoint: {ck * 1e3:.2f} ms checkpointed every {ow['ckpt_every']} steps, "
+            f"{osec[0] * 1e3:.2f} ms with the whole history, for {n_o} dipoles x {ow['steps']} steps")
 
     line = {
         "metric": METRIC, "value": value, "unit": "LW evals/s", "n_gpus": 1, "steps": args.steps,

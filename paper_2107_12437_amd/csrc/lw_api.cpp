@@ -73,6 +73,8 @@ struct lw_ctx {
     std::string tune_file;
     double *d_trial = nullptr;         // tuner trial outputs
     size_t trial_cap = 0;
+    hipStream_t adj_side = nullptr;    // checkpointed adjoint: window builder
+    hipEvent_t adj_built = nullptr, adj_swept = nullptr;
 };
 
 namespace {
@@ -367,6 +369,9 @@ lw_status lw_destroy(lw_ctx *ctx)
     if (ctx->join_a) (void)hipEventDestroy(ctx->join_a);
     if (ctx->join_b) (void)hipEventDestroy(ctx->join_b);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->adj_side) (void)hipStreamDestroy(ctx->adj_side);
+    if (ctx->adj_built) (void)hipEventDestroy(ctx->adj_built);
+    if (ctx->adj_swept) (void)hipEventDestroy(ctx->adj_swept);
     if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     if (ctx->stage_evt) (void)hipEventDestroy(ctx->stage_evt);
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
@@ -920,14 +925,22 @@ lw_status lw_dipole_state_size(const lw_dipole *h_dip, int32_t n_dip, const int3
 }
 
 // The adjoint over segments of K steps recomputed from run states.  The
-// forward pass keeps a run state every K steps; then, from the last segment
-// to the first, the segment is run again from its state with every step
-// stored, the history window (the segment and the state's depth before it) is
-// rebuilt in a ring, and the backward steps are taken, each detector snapshot
-// being reversed just before the sweep consumes its newest sample.  The ring
-// depth of the run states covers both the drive pairs' retarded times and the
-// detector's (the longest detector-to-dipole light time).  Memory: one run
-// state per segment and a window of K + depth steps, instead of the whole run.
+// forward pass keeps a run state every K steps.  The backward sweep then takes
+// the segments from the last to the first; each needs its history window (the
+// segment and the look-back before it, in a ring) and the reverse of the
+// detector snapshots whose newest sample lies in it.  A side stream builds the
+// next (earlier) window while the caller's stream sweeps the current one: it
+// runs the segment again from its state with every step stored, copies the
+// state's ring and the new rows into the history ring, and reverses the
+// segment's snapshots.  The two latency-bound chains (forward steps and
+// backward steps, each on a few workgroups) thus overlap.
+//
+// The history ring holds two windows: the one being swept and the one being
+// built (2K + depth steps).  Each sample is written once, by the latest
+// window that holds it, so the builder never rewrites a sample the sweep
+// reads; the builder of window g - 1 starts only once the sweep of window g + 1
+// has ended, whose ring slots it reuses.  Detector cotangents of window g - 1
+// go to samples the sweep of window g does not read or clear.
 static lw_status vjp_checkpointed(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
                                   int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts,
                                   const double *d_det_pts, int64_t n_det, const double *h_snap_times, int32_t n_snap,
@@ -965,7 +978,7 @@ static lw_status vjp_checkpointed(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n
     int ring_fwd = 4;
     while (ring_fwd < std::max<int64_t>(ring_geo, (int64_t)w_det + 6)) ring_fwd <<= 1;
     int64_t ring_h = 4;
-    while (ring_h < K + ring_fwd + 4) ring_h <<= 1;
+    while (ring_h < 2 * K + ring_fwd + 4) ring_h <<= 1;
     if (ring_h > (1 << 26)) return fail(LW_E_INVALID, "lw_dipole_run_vjp: checkpoint interval too long");
     const int64_t n_seg = (steps + K - 1) / K;
     const int64_t sd = lw::state_doubles(n_dip, ring_fwd);
@@ -976,12 +989,26 @@ static lw_status vjp_checkpointed(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n
         pair_off0[k + 1] = pair_off0[k] + 2 * n * (n - 1);
     }
     const int64_t n_pairs = pair_off[n_inst], n_pairs0 = pair_off0[n_inst];
-    const int64_t nblk1 = (n_det + 255) / 256;                 // J partials per snapshot
+    // snapshots by segment: snapshot k is reversed before the step that consumes
+    // its newest sample, min(floor(t_k / dt), steps - 1); sorted latest first,
+    // the snapshots of one segment are contiguous
+    std::vector<int64_t> due(n_snap);
+    std::vector<int> order(n_snap);
+    for (int k = 0; k < n_snap; ++k) {
+        due[k] = std::min<int64_t>((int64_t)std::floor(h_snap_times[k] / dt), steps - 1);
+        order[k] = k;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return due[x] > due[y]; });
+    std::vector<int> snap_end(n_seg + 1, 0);      // sorted snapshots of segment g: [snap_end[g+1], snap_end[g])
+    for (int r = 0; r < n_snap; ++r) snap_end[due[order[r]] / K] = r + 1;
+    for (int64_t g = n_seg - 1; g >= 0; --g) snap_end[g] = std::max(snap_end[g], snap_end[g + 1]);
+    int64_t n_jpart = 0;                           // J partials: one per 256 lanes of each segment's launch
+    for (int64_t g = 0; g < n_seg; ++g) n_jpart += (n_det * (snap_end[g] - snap_end[g + 1]) + 255) / 256;
     const size_t ck_b = align_up(sizeof(double) * (size_t)(sd * n_seg), 256);
     const size_t ws_b = align_up(sizeof(double) * (size_t)sd, 256);
     const size_t out_b = align_up(sizeof(double) * (size_t)((K + 1) * n_dip), 256);
     const size_t hist_b = align_up(sizeof(double) * (size_t)(ring_h * n_dip * 3), 256);
-    const size_t jp_b = align_up(sizeof(double) * (size_t)(nblk1 * n_snap + 1), 256);
+    const size_t jp_b = align_up(sizeof(double) * (size_t)(n_jpart + 1), 256);
     const size_t dip_b = align_up(sizeof(lw_dipole) * (size_t)n_dip, 256);
     const size_t off_b = align_up(sizeof(int32_t) * (size_t)(n_inst + 1), 256);
     const size_t po_b = align_up(sizeof(int64_t) * (size_t)(n_inst + 1), 256);
@@ -1014,7 +1041,7 @@ static lw_status vjp_checkpointed(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n
     double *d_rbp0 = (double *)take(rbp0_b);
     double *d_taup = (double *)take(taup_b);
     int64_t *d_step = (int64_t *)take(256);
-    // records, offsets, pair offsets and snapshot times for the adjoint kernels
+    // records, offsets, pair offsets and the sorted snapshot times
     st = acquire_stage(ctx, stage_b);
     if (st != LW_OK) return st;
     char *stage = (char *)ctx->h_stage;
@@ -1022,7 +1049,8 @@ static lw_status vjp_checkpointed(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n
     std::memcpy(stage + dip_b, h_inst_off, sizeof(int32_t) * (size_t)(n_inst + 1));
     std::memcpy(stage + dip_b + off_b, pair_off.data(), sizeof(int64_t) * (size_t)(n_inst + 1));
     std::memcpy(stage + dip_b + off_b + po_b, pair_off0.data(), sizeof(int64_t) * (size_t)(n_inst + 1));
-    std::memcpy(stage + dip_b + off_b + 2 * po_b, h_snap_times, sizeof(double) * (size_t)n_snap);
+    double *st_times = (double *)(stage + dip_b + off_b + 2 * po_b);
+    for (int r = 0; r < n_snap; ++r) st_times[r] = h_snap_times[order[r]];
     st = upload(ctx, stage_dev, stage_b, s);
     if (st != LW_OK) return st;
     const lw_dipole *d_in = (const lw_dipole *)stage_dev;
@@ -1042,49 +1070,68 @@ static lw_status vjp_checkpointed(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n
                                  nullptr, nullptr, d_ws, sd, g > 0 ? 1 : 0, stream);
         if (st != LW_OK) return st;
     }
-    // snapshots in the order the sweep meets them: snapshot k is reversed before
-    // the step that consumes its newest sample, min(floor(t_k / dt), steps - 1)
-    std::vector<int64_t> due(n_snap);
-    std::vector<int> order(n_snap);
-    for (int k = 0; k < n_snap; ++k) {
-        due[k] = std::min<int64_t>((int64_t)std::floor(h_snap_times[k] / dt), steps - 1);
-        order[k] = k;
-    }
-    std::sort(order.begin(), order.end(), [&](int x, int y) { return due[x] > due[y]; });
     LW_HIP(lw::launch_vjp_begin(n_dip, n_pairs, steps, d_hbar, ring_h * n_dip * 3, d_grad_pos, d_rbp, d_taup, d_adj,
                                 d_step, s));
+    if (!ctx->adj_side) LW_HIP(hipStreamCreateWithFlags(&ctx->adj_side, hipStreamNonBlocking));
+    if (!ctx->adj_built) LW_HIP(hipEventCreateWithFlags(&ctx->adj_built, hipEventDisableTiming));
+    if (!ctx->adj_swept) LW_HIP(hipEventCreateWithFlags(&ctx->adj_swept, hipEventDisableTiming));
+    hipStream_t t = ctx->adj_side;
     fo.out_stride = 1;
-    size_t next = 0;
-    for (int64_t g = n_seg - 1; g >= 0; --g) {
+    // window g on the side stream: the segment run again with every step stored,
+    // the samples only this window holds, and the reverse of its snapshots
+    int64_t jp_next = 0;
+    auto build = [&](int64_t g) -> lw_status {
         const int64_t a = g * K, ks = std::min(K, steps - a);
-        // the segment again, every step stored
-        if (g > 0) LW_HIP(hipMemcpyAsync(d_ws, d_ckpt + g * sd, sizeof(double) * sd, hipMemcpyDeviceToDevice, s));
-        st = lw_dipole_run_state(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, ks, &fo, d_D, d_V, nullptr, d_Ed, nullptr,
-                                 nullptr, d_ws, sd, g > 0 ? 1 : 0, stream);
-        if (st != LW_OK) return st;
+        const int64_t top = g + 1 < n_seg ? a + K - ring_fwd : a + ks;   // newest sample written here
+        if (top >= a) {      // (with K below the look-back, later windows hold every row)
+            if (g > 0)
+                LW_HIP(hipMemcpyAsync(d_ws, d_ckpt + g * sd, sizeof(double) * sd, hipMemcpyDeviceToDevice, t));
+            const lw_status r = lw_dipole_run_state(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, ks, &fo, d_D, d_V,
+                                                    nullptr, d_Ed, nullptr, nullptr, d_ws, sd, g > 0 ? 1 : 0, t);
+            if (r != LW_OK) return r;
+            LW_HIP(lw::launch_hist_rows(d_dev, d_D, d_V, d_Ed, n_dip, std::min(ks, top - a) + 1, a, (int)ring_h,
+                                        d_hist, t));
+        }
         if (g > 0)
             LW_HIP(lw::launch_hist_from_state(d_ckpt + g * sd, d_off, n_inst, n_dip, ring_fwd,
-                                              std::max<int64_t>(a - ring_fwd + 1, 0), a - 1, (int)ring_h, d_hist, s));
-        LW_HIP(lw::launch_hist_rows(d_dev, d_D, d_V, d_Ed, n_dip, ks + 1, a, (int)ring_h, d_hist, s));
-        // backward steps a + ks - 1 .. a
-        int64_t n = a + ks - 1;
-        while (n >= a) {
-            while (next < order.size() && due[order[next]] >= n) {
-                const int k = order[next++];
-                // newest sample of the window: the snapshot reads none later
-                LW_HIP(lw::launch_vjp_detector(d_dev, n_dip, d_hist, d_hbar, (int)ring_h, a + ks, dt, d_det_pts, n_det,
-                                               d_times + k, 1, n_snap, d_grad_pos, d_Jpart + (int64_t)k * nblk1,
-                                               ctx->d_err, s));
-            }
-            const int64_t stop = (next < order.size() && due[order[next]] >= a) ? due[order[next]] : a - 1;
-            LW_HIP(lw::launch_vjp_steps(d_dev, d_off, d_pair_off, n_inst, n_dip, d_hist, d_hbar, (int)ring_h, dt, d_adj,
-                                        d_rbp, d_taup, d_step, n - stop, ctx->d_err, s));
-            n = stop;
+                                              std::max<int64_t>(a - ring_fwd + 1, 0), std::min(a - 1, top),
+                                              (int)ring_h, d_hist, t));
+        const int r0 = snap_end[g + 1], cnt = snap_end[g] - r0;
+        if (cnt > 0) {
+            // the window's newest sample bounds what the snapshots read
+            LW_HIP(lw::launch_vjp_detector(d_dev, n_dip, d_hist, d_hbar, (int)ring_h, a + ks, dt, d_det_pts, n_det,
+                                           d_times + r0, cnt, n_snap, d_grad_pos, d_Jpart + jp_next, ctx->d_err, t));
+            jp_next += (n_det * cnt + 255) / 256;
         }
+        LW_HIP(hipEventRecord(ctx->adj_built, t));
+        return LW_OK;
+    };
+    // on failure the side stream is drained before returning
+    auto bail = [&](lw_status r) {
+        (void)hipStreamSynchronize(t);
+        return r;
+    };
+    LW_HIP(hipEventRecord(ctx->adj_swept, s));
+    LW_HIP(hipStreamWaitEvent(t, ctx->adj_swept, 0));
+    st = build(n_seg - 1);
+    if (st != LW_OK) return bail(st);
+    for (int64_t g = n_seg - 1; g >= 0; --g) {
+        const int64_t a = g * K, ks = std::min(K, steps - a);
+        if (hipStreamWaitEvent(s, ctx->adj_built, 0) != hipSuccess) return bail(fail(LW_E_HIP, "hipStreamWaitEvent"));
+        if (g > 0) {
+            st = build(g - 1);
+            if (st != LW_OK) return bail(st);
+        }
+        // backward steps a + ks - 1 .. a
+        if (lw::launch_vjp_steps(d_dev, d_off, d_pair_off, n_inst, n_dip, d_hist, d_hbar, (int)ring_h, dt, d_adj,
+                                 d_rbp, d_taup, d_step, ks, ctx->d_err, s) != hipSuccess)
+            return bail(fail(LW_E_HIP, "backward steps"));
+        if (hipEventRecord(ctx->adj_swept, s) != hipSuccess || hipStreamWaitEvent(t, ctx->adj_swept, 0) != hipSuccess)
+            return bail(fail(LW_E_HIP, "hipEventRecord"));
     }
     LW_HIP(lw::launch_vjp_end(d_dev, d_off, d_pair_off, d_pair_off0, n_inst, n_pairs0, n_dip, d_hist, d_hbar,
-                              (int)ring_h, dt, d_adj, d_rbp, d_rbp0, d_grad_pos, d_Jpart, nblk1 * n_snap, d_J,
-                              ctx->d_err, s));
+                              (int)ring_h, dt, d_adj, d_rbp, d_rbp0, d_grad_pos, d_Jpart, jp_next, d_J, ctx->d_err,
+                              s));
     double J = 0.0;
     LW_HIP(hipMemcpyAsync(&J, d_J, sizeof(double), hipMemcpyDeviceToHost, s));
     st = lw_sync_status(ctx, stream);

@@ -377,7 +377,8 @@ def workload_clusters(n_clusters: int = 64, steps: int = 50000, n_min: int = 2, 
 
 def workload_dipole_detector(n_dip: int = 32, steps: int = 5000, grid_n: int = 256, n_snap: int = 32) -> dict:
     """32 dipoles in a 100 nm cube (>= 10 nm spacing) run for 5,000 steps at T0/200 and
-    observed on a detector plane at z = 200 nm at 32 snapshots (LO adjoint workload)."""
+    observed on a detector plane at z = 200 nm at 32 snapshots (LO adjoint workload), with
+    the adjoint checkpointed every 250 steps."""
     rng = rng_for(44)
     dip = cluster_dipoles(rng, n_dip, 50e-9, 10e-9, 2 * math.pi * 200e12, 0.0, False)
     t0 = 1.0 / 200e12
@@ -390,4 +391,5 @@ def workload_dipole_detector(n_dip: int = 32, steps: int = 5000, grid_n: int = 2
         "steps": steps,
         "points": plane_grid(100e-9, grid_n, z=200e-9),
         "times": (np.arange(n_snap) + 1) * steps * dt / n_snap,
+        "ckpt_every": 250,
     }
