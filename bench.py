@@ -88,7 +88,7 @@ def errors(got, ref):
     return res
 
 
-def run_part(part: str, cluster_steps: int, precision: str, ckpt_every: int, I, lw, torch):
+def run_part(part: str, cluster_steps: int, precision: str, ckpt_every: int, adjoint_steps: int, I, lw, torch):
     """One workload alone: a warm-up call, then one timed call (for profiler runs)."""
     if part == "pairs":
         pw = I.workload_dipole_pairs()
@@ -117,7 +117,7 @@ def run_part(part: str, cluster_steps: int, precision: str, ckpt_every: int, I, 
         call(0)
         steps = 0
     else:
-        ow = I.workload_dipole_detector()
+        ow = I.workload_dipole_detector(steps=adjoint_steps) if adjoint_steps > 0 else I.workload_dipole_detector()
         opts = torch.tensor(ow["points"], dtype=torch.float64, device="cuda")
 
         def call(steps):
@@ -164,6 +164,9 @@ def main():
     ap.add_argument("--part", choices=("pairs", "clusters", "grid-vjp", "adjoint"), default=None,
                     help="run only this workload once after one warm-up, print its time and exit "
                          "(for profiler runs; --cluster-steps sets the cluster run's length)")
+    ap.add_argument("--adjoint-steps", type=int, default=0,
+                    help="length of the oscillator run in --part adjoint (0: the workload's 5,000 steps; "
+                         "shorter runs are for counter passes)")
     ap.add_argument("--ckpt-every", type=int, default=250,
                     help="checkpoint interval of the oscillator adjoint in --part adjoint (0: whole history)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -204,7 +207,7 @@ def main():
         log(f"[bench] copied {4 * n} bytes")
         return
     if args.part:
-        run_part(args.part, args.cluster_steps, args.precision, args.ckpt_every, I, lw, torch)
+        run_part(args.part, args.cluster_steps, args.precision, args.ckpt_every, args.adjoint_steps, I, lw, torch)
         return
     w = I.workload_grid_mixed()
     pts = torch.tensor(w["points"], dtype=torch.float64, device="cuda")

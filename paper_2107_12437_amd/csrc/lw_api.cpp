@@ -924,64 +924,76 @@ lw_status lw_dipole_state_size(const lw_dipole *h_dip, int32_t n_dip, const int3
     return LW_OK;
 }
 
-// The adjoint over segments of K steps recomputed from run states.  The
-// forward pass keeps a run state every K steps.  The backward sweep then takes
-// the segments from the last to the first; each needs its history window (the
-// segment and the look-back before it, in a ring) and the reverse of the
-// detector snapshots whose newest sample lies in it.  A side stream builds the
-// next (earlier) window while the caller's stream sweeps the current one: it
-// runs the segment again from its state with every step stored, copies the
-// state's ring and the new rows into the history ring, and reverses the
-// segment's snapshots.  The two latency-bound chains (forward steps and
-// backward steps, each on a few workgroups) thus overlap.
+// The backward sweep of the oscillator adjoint, over segments of K steps from
+// the last to the first.  Sweeping a segment needs its history window (the
+// segment and the look-back before it) and the reverse of the detector
+// snapshots whose newest sample lies in it.  A side stream prepares the next
+// (earlier) segment while the caller's stream sweeps the current one, so the
+// latency-bound backward steps (a few workgroups per launch) overlap with the
+// detector reverse and, when checkpointed, with the segment's recomputation.
 //
-// The history ring holds two windows: the one being swept and the one being
-// built (2K + depth steps).  Each sample is written once, by the latest
-// window that holds it, so the builder never rewrites a sample the sweep
-// reads; the builder of window g - 1 starts only once the sweep of window g + 1
-// has ended, whose ring slots it reuses.  Detector cotangents of window g - 1
-// go to samples the sweep of window g does not read or clear.
-static lw_status vjp_checkpointed(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
-                                  int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts,
-                                  const double *d_det_pts, int64_t n_det, const double *h_snap_times, int32_t n_snap,
-                                  int64_t K, double *d_grad_pos, double *h_J, void *stream)
+// whole = true: the forward run stores every step, the history ring holds the
+// whole run, and every snapshot is reversed in one launch before the sweep.
+//
+// whole = false (checkpointing): the forward pass keeps a run state every K
+// steps; preparing a segment runs it again from its state with every step
+// stored and copies the state's ring and the new rows into the history ring,
+// which holds two windows (the one being swept and the one being prepared,
+// 2K + depth steps).  Each sample is written once, by the latest window that
+// holds it, so the preparation never rewrites a sample the sweep reads; the
+// preparation of window g - 1 starts only once the sweep of window g + 1 has
+// ended, whose ring slots it reuses.  Detector cotangents of window g - 1 go
+// to samples the sweep of window g neither reads nor clears.
+static lw_status vjp_pipelined(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
+                               int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts,
+                               const double *d_det_pts, int64_t n_det, const double *h_snap_times, int32_t n_snap,
+                               bool whole, int64_t K, double *d_grad_pos, double *h_J, void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
     int ring_geo = 0;
     lw_status st = run_geometry("lw_dipole_run_vjp", h_dip, n_dip, h_inst_off, n_inst, dt, steps, opts, &ring_geo);
     if (st != LW_OK) return st;
-    // the detector's look-back: an upper bound on the light time from a detector
-    // point to an origin (the farthest corner of the points' bounding box),
-    // doubled and padded as for the drive pairs
-    std::vector<double> P((size_t)(3 * n_det));
-    LW_HIP(hipMemcpyAsync(P.data(), d_det_pts, sizeof(double) * P.size(), hipMemcpyDeviceToHost, s));
-    LW_HIP(hipStreamSynchronize(s));
-    double lo[3], hi[3];
-    for (int c = 0; c < 3; ++c) {
-        const double *x = P.data() + c * n_det;
-        lo[c] = *std::min_element(x, x + n_det);
-        hi[c] = *std::max_element(x, x + n_det);
-        if (!std::isfinite(lo[c]) || !std::isfinite(hi[c]))
-            return fail(LW_E_INVALID, "lw_dipole_run_vjp: detector points must be finite");
-    }
-    double reach2 = 0.0;
-    for (int i = 0; i < n_dip; ++i) {
-        double r2 = 0.0;
+    int ring_fwd = ring_geo;
+    int64_t ring_h = 1;
+    if (whole) {
+        while (ring_h < steps + 1) ring_h <<= 1;
+        if (ring_h > (1 << 26)) return fail(LW_E_INVALID, "lw_dipole_run_vjp: run too long for the stored history");
+    } else {
+        // the detector's look-back: an upper bound on the light time from a
+        // detector point to an origin (the farthest corner of the points'
+        // bounding box), doubled and padded as for the drive pairs
+        std::vector<double> P((size_t)(3 * n_det));
+        LW_HIP(hipMemcpyAsync(P.data(), d_det_pts, sizeof(double) * P.size(), hipMemcpyDeviceToHost, s));
+        LW_HIP(hipStreamSynchronize(s));
+        double lo[3], hi[3];
         for (int c = 0; c < 3; ++c) {
-            const double e = std::max(std::fabs(lo[c] - h_dip[i].origin[c]), std::fabs(hi[c] - h_dip[i].origin[c]));
-            r2 += e * e;
+            const double *x = P.data() + c * n_det;
+            lo[c] = *std::min_element(x, x + n_det);
+            hi[c] = *std::max_element(x, x + n_det);
+            if (!std::isfinite(lo[c]) || !std::isfinite(hi[c]))
+                return fail(LW_E_INVALID, "lw_dipole_run_vjp: detector points must be finite");
         }
-        reach2 = std::max(reach2, r2);
+        double reach2 = 0.0;
+        for (int i = 0; i < n_dip; ++i) {
+            double r2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double e = std::max(std::fabs(lo[c] - h_dip[i].origin[c]), std::fabs(hi[c] - h_dip[i].origin[c]));
+                r2 += e * e;
+            }
+            reach2 = std::max(reach2, r2);
+        }
+        const double w_det = std::ceil(2.0 * std::sqrt(reach2) / C_LIGHT / dt) + 3.0;
+        if (!(w_det < (double)(1 << 24))) return fail(LW_E_INVALID, "lw_dipole_run_vjp: detector too far for dt");
+        ring_fwd = 4;
+        while (ring_fwd < std::max<int64_t>(ring_geo, (int64_t)w_det + 6)) ring_fwd <<= 1;
+        ring_h = 4;
+        while (ring_h < 2 * K + ring_fwd + 4) ring_h <<= 1;
+        if (ring_h > (1 << 26)) return fail(LW_E_INVALID, "lw_dipole_run_vjp: checkpoint interval too long");
     }
-    const double w_det = std::ceil(2.0 * std::sqrt(reach2) / C_LIGHT / dt) + 3.0;
-    if (!(w_det < (double)(1 << 24))) return fail(LW_E_INVALID, "lw_dipole_run_vjp: detector too far for dt");
-    int ring_fwd = 4;
-    while (ring_fwd < std::max<int64_t>(ring_geo, (int64_t)w_det + 6)) ring_fwd <<= 1;
-    int64_t ring_h = 4;
-    while (ring_h < 2 * K + ring_fwd + 4) ring_h <<= 1;
-    if (ring_h > (1 << 26)) return fail(LW_E_INVALID, "lw_dipole_run_vjp: checkpoint interval too long");
     const int64_t n_seg = (steps + K - 1) / K;
-    const int64_t sd = lw::state_doubles(n_dip, ring_fwd);
+    const int64_t sd = whole ? 0 : lw::state_doubles(n_dip, ring_fwd);
+    const int64_t out_rows = whole ? steps + 1 : K + 1;
+    // drive pairs per step (2 stages x n targets x (n-1) sources x 2 charges) and of E_d(0)
     std::vector<int64_t> pair_off(n_inst + 1, 0), pair_off0(n_inst + 1, 0);
     for (int k = 0; k < n_inst; ++k) {
         const int64_t n = h_inst_off[k + 1] - h_inst_off[k];
@@ -1002,11 +1014,15 @@ static lw_status vjp_checkpointed(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n
     std::vector<int> snap_end(n_seg + 1, 0);      // sorted snapshots of segment g: [snap_end[g+1], snap_end[g])
     for (int r = 0; r < n_snap; ++r) snap_end[due[order[r]] / K] = r + 1;
     for (int64_t g = n_seg - 1; g >= 0; --g) snap_end[g] = std::max(snap_end[g], snap_end[g + 1]);
+    // with the whole history every snapshot can be reversed at once, before the
+    // sweep: one launch wide enough to fill the chip
+    if (whole)
+        for (int64_t g = 0; g < n_seg; ++g) snap_end[g] = n_snap;
     int64_t n_jpart = 0;                           // J partials: one per 256 lanes of each segment's launch
     for (int64_t g = 0; g < n_seg; ++g) n_jpart += (n_det * (snap_end[g] - snap_end[g + 1]) + 255) / 256;
-    const size_t ck_b = align_up(sizeof(double) * (size_t)(sd * n_seg), 256);
-    const size_t ws_b = align_up(sizeof(double) * (size_t)sd, 256);
-    const size_t out_b = align_up(sizeof(double) * (size_t)((K + 1) * n_dip), 256);
+    const size_t ck_b = align_up(sizeof(double) * (size_t)(sd * n_seg + 1), 256);
+    const size_t ws_b = align_up(sizeof(double) * (size_t)(sd + 1), 256);
+    const size_t out_b = align_up(sizeof(double) * (size_t)(out_rows * n_dip), 256);
     const size_t hist_b = align_up(sizeof(double) * (size_t)(ring_h * n_dip * 3), 256);
     const size_t jp_b = align_up(sizeof(double) * (size_t)(n_jpart + 1), 256);
     const size_t dip_b = align_up(sizeof(lw_dipole) * (size_t)n_dip, 256);
@@ -1059,16 +1075,27 @@ static lw_status vjp_checkpointed(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n
     const int64_t *d_pair_off0 = (const int64_t *)(stage_dev + dip_b + off_b + po_b);
     const double *d_times = (const double *)(stage_dev + dip_b + off_b + 2 * po_b);
     LW_HIP(lw::launch_dipole_prep(d_in, n_dip, d_dev, s));
-    // forward pass: a run state every K steps (outputs: two rows per segment, discarded)
     lw_run_opts fo = *opts;
-    fo.ring_depth = ring_fwd;
-    for (int64_t g = 0; g < n_seg; ++g) {
-        const int64_t a = g * K, ks = std::min(K, steps - a);
-        if (g > 0) LW_HIP(hipMemcpyAsync(d_ckpt + g * sd, d_ws, sizeof(double) * sd, hipMemcpyDeviceToDevice, s));
-        fo.out_stride = ks;
-        st = lw_dipole_run_state(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, ks, &fo, d_D, nullptr, nullptr, nullptr,
-                                 nullptr, nullptr, d_ws, sd, g > 0 ? 1 : 0, stream);
+    if (whole) {
+        // forward run with every step stored, then the whole history
+        fo.out_stride = 1;
+        st = lw_dipole_run(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, steps, &fo, d_D, d_V, nullptr, d_Ed, nullptr,
+                           nullptr, stream);
         if (st != LW_OK) return st;
+        LW_HIP(lw::launch_hist_rows(d_dev, d_D, d_V, d_Ed, n_dip, steps + 1, 0, (int)ring_h, d_hist, s));
+    } else {
+        // forward pass: a run state every K steps (outputs: two rows per segment, discarded)
+        fo.ring_depth = ring_fwd;
+        for (int64_t g = 0; g < n_seg; ++g) {
+            const int64_t a = g * K, ks = std::min(K, steps - a);
+            if (g > 0)
+                LW_HIP(hipMemcpyAsync(d_ckpt + g * sd, d_ws, sizeof(double) * sd, hipMemcpyDeviceToDevice, s));
+            fo.out_stride = ks;
+            st = lw_dipole_run_state(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, ks, &fo, d_D, nullptr, nullptr,
+                                     nullptr, nullptr, nullptr, d_ws, sd, g > 0 ? 1 : 0, stream);
+            if (st != LW_OK) return st;
+        }
+        fo.out_stride = 1;
     }
     LW_HIP(lw::launch_vjp_begin(n_dip, n_pairs, steps, d_hbar, ring_h * n_dip * 3, d_grad_pos, d_rbp, d_taup, d_adj,
                                 d_step, s));
@@ -1076,26 +1103,28 @@ static lw_status vjp_checkpointed(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n
     if (!ctx->adj_built) LW_HIP(hipEventCreateWithFlags(&ctx->adj_built, hipEventDisableTiming));
     if (!ctx->adj_swept) LW_HIP(hipEventCreateWithFlags(&ctx->adj_swept, hipEventDisableTiming));
     hipStream_t t = ctx->adj_side;
-    fo.out_stride = 1;
-    // window g on the side stream: the segment run again with every step stored,
-    // the samples only this window holds, and the reverse of its snapshots
+    // segment g on the side stream: (checkpointed) the segment run again with
+    // every step stored and the samples only this window holds; then the
+    // reverse of its snapshots
     int64_t jp_next = 0;
-    auto build = [&](int64_t g) -> lw_status {
+    auto prepare = [&](int64_t g) -> lw_status {
         const int64_t a = g * K, ks = std::min(K, steps - a);
-        const int64_t top = g + 1 < n_seg ? a + K - ring_fwd : a + ks;   // newest sample written here
-        if (top >= a) {      // (with K below the look-back, later windows hold every row)
+        if (!whole) {
+            const int64_t top = g + 1 < n_seg ? a + K - ring_fwd : a + ks;   // newest sample written here
+            if (top >= a) {      // (with K below the look-back, later windows hold every row)
+                if (g > 0)
+                    LW_HIP(hipMemcpyAsync(d_ws, d_ckpt + g * sd, sizeof(double) * sd, hipMemcpyDeviceToDevice, t));
+                const lw_status r = lw_dipole_run_state(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, ks, &fo, d_D, d_V,
+                                                        nullptr, d_Ed, nullptr, nullptr, d_ws, sd, g > 0 ? 1 : 0, t);
+                if (r != LW_OK) return r;
+                LW_HIP(lw::launch_hist_rows(d_dev, d_D, d_V, d_Ed, n_dip, std::min(ks, top - a) + 1, a, (int)ring_h,
+                                            d_hist, t));
+            }
             if (g > 0)
-                LW_HIP(hipMemcpyAsync(d_ws, d_ckpt + g * sd, sizeof(double) * sd, hipMemcpyDeviceToDevice, t));
-            const lw_status r = lw_dipole_run_state(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, ks, &fo, d_D, d_V,
-                                                    nullptr, d_Ed, nullptr, nullptr, d_ws, sd, g > 0 ? 1 : 0, t);
-            if (r != LW_OK) return r;
-            LW_HIP(lw::launch_hist_rows(d_dev, d_D, d_V, d_Ed, n_dip, std::min(ks, top - a) + 1, a, (int)ring_h,
-                                        d_hist, t));
+                LW_HIP(lw::launch_hist_from_state(d_ckpt + g * sd, d_off, n_inst, n_dip, ring_fwd,
+                                                  std::max<int64_t>(a - ring_fwd + 1, 0), std::min(a - 1, top),
+                                                  (int)ring_h, d_hist, t));
         }
-        if (g > 0)
-            LW_HIP(lw::launch_hist_from_state(d_ckpt + g * sd, d_off, n_inst, n_dip, ring_fwd,
-                                              std::max<int64_t>(a - ring_fwd + 1, 0), std::min(a - 1, top),
-                                              (int)ring_h, d_hist, t));
         const int r0 = snap_end[g + 1], cnt = snap_end[g] - r0;
         if (cnt > 0) {
             // the window's newest sample bounds what the snapshots read
@@ -1106,25 +1135,62 @@ static lw_status vjp_checkpointed(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n
         LW_HIP(hipEventRecord(ctx->adj_built, t));
         return LW_OK;
     };
-    // on failure the side stream is drained before returning
+    // backward steps replay a captured chunk of C launches (each chunk moves the
+    // device step base by C): C divides K where a divisor in [16, 64] exists
+    int64_t C = 32;
+    for (int64_t c = 64; c >= 16; --c)
+        if (K % c == 0) {
+            C = c;
+            break;
+        }
+    struct StepGraph {           // released once the stream has passed it, on every way out
+        hipStream_t s;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        ~StepGraph()
+        {
+            if (exec) {
+                (void)hipStreamSynchronize(s);
+                (void)hipGraphExecDestroy(exec);
+            }
+            if (graph) (void)hipGraphDestroy(graph);
+        }
+    } sg{s};
+    if (!ctx->capture) LW_HIP(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+    if (K >= C) {
+        LW_HIP(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+        const hipError_t ce = lw::launch_vjp_steps(d_dev, d_off, d_pair_off, n_inst, n_dip, d_hist, d_hbar,
+                                                   (int)ring_h, dt, d_adj, d_rbp, d_taup, d_step, C, ctx->d_err,
+                                                   ctx->capture);
+        const hipError_t ee = hipStreamEndCapture(ctx->capture, &sg.graph);
+        LW_HIP(ce);
+        LW_HIP(ee);
+        LW_HIP(hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0));
+    }
+    // on failure both streams are drained before returning (the graph is
+    // released on the way out)
     auto bail = [&](lw_status r) {
         (void)hipStreamSynchronize(t);
+        (void)hipStreamSynchronize(s);
         return r;
     };
     LW_HIP(hipEventRecord(ctx->adj_swept, s));
     LW_HIP(hipStreamWaitEvent(t, ctx->adj_swept, 0));
-    st = build(n_seg - 1);
+    st = prepare(n_seg - 1);
     if (st != LW_OK) return bail(st);
     for (int64_t g = n_seg - 1; g >= 0; --g) {
         const int64_t a = g * K, ks = std::min(K, steps - a);
         if (hipStreamWaitEvent(s, ctx->adj_built, 0) != hipSuccess) return bail(fail(LW_E_HIP, "hipStreamWaitEvent"));
         if (g > 0) {
-            st = build(g - 1);
+            st = prepare(g - 1);
             if (st != LW_OK) return bail(st);
         }
         // backward steps a + ks - 1 .. a
+        const int64_t reps = sg.exec ? ks / C : 0;
+        for (int64_t r = 0; r < reps; ++r)
+            if (hipGraphLaunch(sg.exec, s) != hipSuccess) return bail(fail(LW_E_HIP, "backward steps"));
         if (lw::launch_vjp_steps(d_dev, d_off, d_pair_off, n_inst, n_dip, d_hist, d_hbar, (int)ring_h, dt, d_adj,
-                                 d_rbp, d_taup, d_step, ks, ctx->d_err, s) != hipSuccess)
+                                 d_rbp, d_taup, d_step, ks - reps * C, ctx->d_err, s) != hipSuccess)
             return bail(fail(LW_E_HIP, "backward steps"));
         if (hipEventRecord(ctx->adj_swept, s) != hipSuccess || hipStreamWaitEvent(t, ctx->adj_swept, 0) != hipSuccess)
             return bail(fail(LW_E_HIP, "hipEventRecord"));
@@ -1160,100 +1226,13 @@ lw_status lw_dipole_run_vjp(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, 
             return fail(LW_E_INVALID, "lw_dipole_run_vjp: moving dipoles have no adjoint here");
     if (n_det * (int64_t)n_snap > ((int64_t)1 << 36)) return fail(LW_E_INVALID, "lw_dipole_run_vjp: detector too large");
     if (ckpt_every < 0) return fail(LW_E_INVALID, "lw_dipole_run_vjp: negative checkpoint interval");
-    if (ckpt_every > 0 && ckpt_every < steps) {
-        LW_HIP(hipSetDevice(ctx->device));
-        return vjp_checkpointed(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, steps, opts, d_det_pts, n_det, h_snap_times,
-                                n_snap, ckpt_every, d_grad_pos, h_J, stream);
-    }
     LW_HIP(hipSetDevice(ctx->device));
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t rows = steps + 1;
-    int64_t ring = 1;
-    while (ring < rows) ring <<= 1;
-    if (ring > (1 << 26)) return fail(LW_E_INVALID, "lw_dipole_run_vjp: run too long for the stored history");
-    const int64_t nblk = (n_det * n_snap + 255) / 256;
-    // drive pairs per step (2 stages x n targets x (n-1) sources x 2 charges) and of E_d(0)
-    std::vector<int64_t> pair_off(n_inst + 1, 0), pair_off0(n_inst + 1, 0);
-    for (int k = 0; k < n_inst; ++k) {
-        const int64_t n = h_inst_off[k + 1] - h_inst_off[k];
-        pair_off[k + 1] = pair_off[k] + 4 * n * (n - 1);
-        pair_off0[k + 1] = pair_off0[k] + 2 * n * (n - 1);
-    }
-    const int64_t n_pairs = pair_off[n_inst], n_pairs0 = pair_off0[n_inst];
-    const size_t out_b = align_up(sizeof(double) * (size_t)(rows * n_dip), 256);
-    const size_t hist_b = align_up(sizeof(double) * (size_t)(ring * n_dip * 3), 256);
-    const size_t jp_b = align_up(sizeof(double) * (size_t)(nblk + 1), 256);
-    const size_t dip_b = align_up(sizeof(lw_dipole) * (size_t)n_dip, 256);
-    const size_t off_b = align_up(sizeof(int32_t) * (size_t)(n_inst + 1), 256);
-    const size_t po_b = align_up(sizeof(int64_t) * (size_t)(n_inst + 1), 256);
-    const size_t tm_b = align_up(sizeof(double) * (size_t)n_snap, 256);
-    const size_t dev_b = align_up(lw::dip_dev_bytes(n_dip), 256);
-    const size_t state_b = align_up(sizeof(double) * 6 * (size_t)n_dip, 256);
-    const size_t rbp_b = align_up(sizeof(double) * 3 * (size_t)std::max<int64_t>(n_pairs, 1), 256);
-    const size_t rbp0_b = align_up(sizeof(double) * 3 * (size_t)std::max<int64_t>(n_pairs0, 1), 256);
-    const size_t taup_b = align_up(sizeof(double) * (size_t)std::max<int64_t>(n_pairs, 1), 256);
-    const size_t ctr_b = 256;
-    const size_t stage_b = dip_b + off_b + 2 * po_b + tm_b;
-    lw_status st = ensure_work2(ctx, 3 * out_b + 2 * hist_b + jp_b + 256 + stage_b + dev_b + state_b + rbp_b + rbp0_b +
-                                         taup_b + ctr_b, s);
-    if (st != LW_OK) return st;
-    char *w2 = (char *)ctx->d_work2;
-    size_t o = 0;
-    auto take = [&](size_t bytes) { char *p = w2 + o; o += bytes; return p; };
-    double *d_D = (double *)take(out_b);
-    double *d_V = (double *)take(out_b);
-    double *d_Ed = (double *)take(out_b);
-    double *d_hist = (double *)take(hist_b);
-    double *d_hbar = (double *)take(hist_b);
-    double *d_Jpart = (double *)take(jp_b);
-    double *d_J = (double *)take(256);
-    char *stage_dev = take(stage_b);
-    lw::DipDev *d_dev = (lw::DipDev *)take(dev_b);
-    double *d_state = (double *)take(state_b);
-    double *d_rbp = (double *)take(rbp_b);
-    double *d_rbp0 = (double *)take(rbp0_b);
-    double *d_taup = (double *)take(taup_b);
-    int64_t *d_step = (int64_t *)take(ctr_b);
-    // forward run with every step stored
-    lw_run_opts fo = *opts;
-    fo.out_stride = 1;
-    st = lw_dipole_run(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, steps, &fo, d_D, d_V, nullptr, d_Ed, nullptr, nullptr,
-                       stream);
-    if (st != LW_OK) return st;
-    // oscillator records, offsets, pair offsets and snapshot times for the adjoint kernels
-    st = acquire_stage(ctx, stage_b);
-    if (st != LW_OK) return st;
-    char *stage = (char *)ctx->h_stage;
-    std::memcpy(stage, h_dip, sizeof(lw_dipole) * (size_t)n_dip);
-    std::memcpy(stage + dip_b, h_inst_off, sizeof(int32_t) * (size_t)(n_inst + 1));
-    std::memcpy(stage + dip_b + off_b, pair_off.data(), sizeof(int64_t) * (size_t)(n_inst + 1));
-    std::memcpy(stage + dip_b + off_b + po_b, pair_off0.data(), sizeof(int64_t) * (size_t)(n_inst + 1));
-    std::memcpy(stage + dip_b + off_b + 2 * po_b, h_snap_times, sizeof(double) * (size_t)n_snap);
-    st = upload(ctx, stage_dev, stage_b, s);
-    if (st != LW_OK) return st;
-    const lw_dipole *d_in = (const lw_dipole *)stage_dev;
-    const int32_t *d_off = (const int32_t *)(stage_dev + dip_b);
-    const int64_t *d_pair_off = (const int64_t *)(stage_dev + dip_b + off_b);
-    const int64_t *d_pair_off0 = (const int64_t *)(stage_dev + dip_b + off_b + po_b);
-    const double *d_times = (const double *)(stage_dev + dip_b + off_b + 2 * po_b);
-    LW_HIP(lw::launch_dipole_prep(d_in, n_dip, d_dev, s));
-    if (!ctx->capture) LW_HIP(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    const hipError_t he = lw::launch_dipole_vjp(d_dev, d_off, d_pair_off, d_pair_off0, n_inst, n_pairs, n_pairs0, n_dip,
-                                                d_D, d_V, d_Ed, d_hist, d_hbar, (int)ring, steps, dt, d_det_pts, n_det,
-                                                d_times, n_snap, d_grad_pos, d_Jpart, d_J, d_state, d_rbp, d_rbp0,
-                                                d_taup, d_step, ctx->d_err, 256, s, ctx->capture, &graph, &exec);
-    double J = 0.0;
-    if (he == hipSuccess) (void)hipMemcpyAsync(&J, d_J, sizeof(double), hipMemcpyDeviceToHost, s);
-    // the call ends synchronised with the stream, so the step graph can go now
-    st = he == hipSuccess ? lw_sync_status(ctx, stream) : LW_OK;
-    if (he != hipSuccess) (void)hipStreamSynchronize(s);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    LW_HIP(he);
-    *h_J = J;
-    return st;
+    // without checkpoints the sweep is still taken in segments, so that the
+    // detector reverse of earlier snapshots overlaps with the later steps
+    const bool whole = ckpt_every == 0 || ckpt_every >= steps;
+    const int64_t K = whole ? std::max<int64_t>(256, ((steps + 15) / 16 + 63) / 64 * 64) : ckpt_every;
+    return vjp_pipelined(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, steps, opts, d_det_pts, n_det, h_snap_times,
+                         n_snap, whole, K, d_grad_pos, h_J, stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -219,21 +219,6 @@ __device__ __forceinline__ void scatter_global(const Hist &H, int j, const HistB
     }
 }
 
-// Full history (d, d_dot, d_ddot) of every dipole from a stride-1 run's outputs.
-__global__ void hist_build_kernel(const DipDev *__restrict__ dev, const double *__restrict__ D,
-                                  const double *__restrict__ V, const double *__restrict__ Ed, int n_dip, int64_t nrows,
-                                  double *__restrict__ hist)
-{
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nrows * n_dip) return;
-    const int i = (int)(idx % n_dip);
-    const DipDev &P = dev[i];
-    const double d = D[idx], v = V[idx];
-    hist[idx * 3 + 0] = d;
-    hist[idx * 3 + 1] = v;
-    hist[idx * 3 + 2] = P.f * Ed[idx] - P.gamma0 * v - P.omega0 * P.omega0 * d;
-}
-
 // History samples row0 .. row0 + nrows - 1 from a stride-1 run's outputs into
 // a ring of `ring` steps ([ring][n_dip][3]).
 __global__ void hist_rows_kernel(const DipDev *__restrict__ dev, const double *__restrict__ D,
@@ -523,7 +508,7 @@ __device__ __forceinline__ PairIx pair_index(const int64_t *pair_off, const int3
 }
 
 // One step n = *step_base - k of the backward sweep, one workgroup per dipole
-// (the target).  Its prologue completes the dipole's sample n + 1 (every pair
+// (the target).  One lane completes the dipole's sample n + 1 (every pair
 // that reads it belongs to a later step, already reversed) and transposes step
 // n; then every drive pair of the target at stages t_n + dt/2 and t_n + dt
 // reverses its field evaluation, scattering into the source's samples and
@@ -563,6 +548,7 @@ __global__ __launch_bounds__(BLOCK) void adj_step_kernel(const DipDev *__restric
     hu.k = 0;
     int gj = 0;
     int64_t idx = 0;
+    double rb[3] = {0.0, 0.0, 0.0};     // the pair's separation cotangent so far, read early
     auto solve_unit = [&](int mm2) {
         const int th = mm2 / M, m = mm2 - th * M;
         const int jj = m >> 1, w = m & 1;
@@ -572,6 +558,9 @@ __global__ __launch_bounds__(BLOCK) void adj_step_kernel(const DipDev *__restric
         const double cf = w ? Sj.cfm : Sj.cfp;
         const double kq = (w ? -qj : qj) * K_COUL;
         idx = pair_off[inst] + ((int64_t)th * n + i) * M + m;
+        rb[0] = rbp[idx * 3];
+        rb[1] = rbp[idx * 3 + 1];
+        rb[2] = rbp[idx * 3 + 2];
         Kin kn;
         HistEval e;
         double tau;
@@ -579,8 +568,11 @@ __global__ __launch_bounds__(BLOCK) void adj_step_kernel(const DipDev *__restric
         taup[idx] = tau;
         pair_vjp(kn, e, Sj, cf, kq, Eu, Du, hu);
     };
+    // the dipole's own sample and RK4 transpose go to a lane without pair work
+    // when there is one, so they run beside the pair solves
+    const int own = (2 * M < BLOCK) ? BLOCK - 1 : 0;
     if (m2 < 2 * M) solve_unit(m2);
-    if (tid == 0) {
+    if (tid == own) {
         take_sample(Di, hbar, nstep + 1, n_dip, mask, A, g);
         rk4_transpose(Di, dt, A, g);
         s_em = A.em[g];
@@ -597,9 +589,9 @@ __global__ __launch_bounds__(BLOCK) void adj_step_kernel(const DipDev *__restric
         }
         scatter_global(H, gj, hb, hbar);
         double *r = rbp + idx * 3;
-        r[0] += Es * Du[0];
-        r[1] += Es * Du[1];
-        r[2] += Es * Du[2];
+        r[0] = rb[0] + Es * Du[0];
+        r[1] = rb[1] + Es * Du[1];
+        r[2] = rb[2] + Es * Du[2];
     }
     if (err) atomicOr(d_err, err);
 }
@@ -685,80 +677,6 @@ __global__ void fill_zero_kernel(double *__restrict__ p, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.0;
-}
-
-hipError_t launch_dipole_vjp(const DipDev *d_dev, const int32_t *d_off, const int64_t *d_pair_off,
-                             const int64_t *d_pair_off0, int n_inst, int64_t n_pairs, int64_t n_pairs0, int n_dip,
-                             const double *d_D, const double *d_V, const double *d_Ed, double *d_hist, double *d_hbar,
-                             int ring, int64_t steps, double dt, const double *d_pts, int64_t npts,
-                             const double *d_times, int n_snap, double *d_grad, double *d_Jpart, double *d_J,
-                             double *d_state, double *d_rbp, double *d_rbp0, double *d_taup, int64_t *d_step,
-                             uint32_t *d_err, int graph_chunk, hipStream_t s, hipStream_t cap, hipGraph_t *graph_out,
-                             hipGraphExec_t *exec_out)
-{
-    constexpr int B = 256;
-    const int max_iter = 60;
-    const int64_t rows = steps + 1;
-    const int64_t hn = (int64_t)ring * n_dip * 3;
-    const int mask = ring - 1;
-    hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, s, d_hbar, hn);
-    hipLaunchKernelGGL(fill_zero_kernel, dim3(1), dim3(256), 0, s, d_grad, (int64_t)n_dip * 3);
-    hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, s, d_rbp, n_pairs * 3);
-    hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, s, d_taup, n_pairs);
-    hipLaunchKernelGGL(hist_build_kernel, dim3((unsigned)((rows * n_dip + 255) / 256)), dim3(256), 0, s, d_dev, d_D,
-                       d_V, d_Ed, n_dip, rows, d_hist);
-    const int64_t lanes = npts * n_snap;
-    const unsigned nblk = (unsigned)((lanes + 255) / 256);
-    hipLaunchKernelGGL(detector_vjp_kernel, dim3(nblk), dim3(256), 0, s, d_dev, n_dip, d_hist, d_hbar, ring, steps,
-                       dt, d_pts, npts, d_times, n_snap, n_snap, d_grad, d_Jpart, max_iter, d_err);
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, d_Jpart, (int64_t)nblk, d_J);
-    AdjState A{d_state, d_state + n_dip, d_state + 2 * (int64_t)n_dip, d_state + 3 * (int64_t)n_dip,
-               d_state + 4 * (int64_t)n_dip, d_state + 5 * (int64_t)n_dip};
-    hipLaunchKernelGGL(adj_init_kernel, dim3((unsigned)((n_dip + 255) / 256)), dim3(256), 0, s, n_dip, steps, A,
-                       d_step);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // one launch per step, n = base - k; after `count` launches the base moves
-    // down by count, so a captured chunk replays as the next `count` steps
-    const double *soa = dip_soa(const_cast<DipDev *>(d_dev), n_dip);
-    auto enqueue = [&](hipStream_t q, int64_t count) {
-        for (int64_t k = 0; k < count; ++k)
-            hipLaunchKernelGGL(adj_step_kernel<B>, dim3((unsigned)n_dip), dim3(B), 0, q, d_dev, d_off, d_pair_off,
-                               n_inst, n_dip, d_hist, d_hbar, mask, dt, A, d_rbp, d_taup, d_step, (int)k, max_iter,
-                               soa, d_err);
-        hipLaunchKernelGGL(adj_base_kernel, dim3(1), dim3(1), 0, q, d_step, -count);
-    };
-    const int64_t chunk = graph_chunk > 0 ? graph_chunk : 0;
-    if (chunk == 0 || steps < chunk || !cap) {
-        enqueue(s, steps);
-        e = hipGetLastError();
-    } else {
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            enqueue(cap, chunk);
-            e = hipStreamEndCapture(cap, &graph);
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        const int64_t reps = steps / chunk;
-        for (int64_t r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(exec, s);
-        if (e == hipSuccess && steps > reps * chunk) {
-            enqueue(s, steps - reps * chunk);
-            e = hipGetLastError();
-        }
-        *graph_out = graph;
-        *exec_out = exec;
-    }
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(adj_finish_kernel, dim3((unsigned)((n_dip + 255) / 256)), dim3(256), 0, s, d_dev, n_dip, d_hbar,
-                       mask, A);
-    if (n_pairs0 > 0)
-        hipLaunchKernelGGL(adj_drive0_kernel<B>, dim3((unsigned)((n_pairs0 + B - 1) / B)), dim3(B), 0, s, d_dev, d_off,
-                           d_pair_off0, n_inst, n_pairs0, n_dip, d_hist, mask, dt, A, d_rbp0, max_iter, d_err);
-    hipLaunchKernelGGL(adj_positions_kernel, dim3((unsigned)n_inst), dim3(256), 0, s, d_off, d_pair_off, d_pair_off0,
-                       n_inst, d_rbp, d_rbp0, d_grad);
-    return hipGetLastError();
 }
 
 // --- pieces of the checkpointed sweep (segments recomputed from run states) ---

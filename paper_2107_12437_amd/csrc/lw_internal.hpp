@@ -99,10 +99,14 @@ hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const 
                                int graph_chunk, hipStream_t s, hipStream_t cap, hipGraph_t *graph_out,
                                hipGraphExec_t *exec_out);
 
-// Pieces of the oscillator adjoint for a sweep over recomputed segments
-// (lw_dipole_adjoint.hip); `ring` is the depth of the windowed history and of
-// its cotangents ([ring][n_dip][3], power of two), whose slots are cleared as
-// the sweep consumes them.  launch_hist_rows: samples row0 .. row0+nrows-1 from
+// Pieces of the oscillator adjoint (lw_dipole_adjoint.hip), whose sweep runs
+// over segments of steps; `ring` is the depth of the history and of its
+// cotangents ([ring][n_dip][3], power of two: the whole run, or windows of
+// recomputed segments), whose slots are cleared as the sweep consumes them.
+// d_pair_off / d_pair_off0: per-instance prefix sums of the drive pairs of a
+// step (4 n (n-1)) and of E_d(0) (2 n (n-1)); d_state 6 n_dip doubles; d_rbp /
+// d_rbp0 three doubles per pair, d_taup one per pair; d_step a device step
+// index.  launch_hist_rows: samples row0 .. row0+nrows-1 from
 // a stride-1 run's outputs; launch_hist_from_state: samples lo .. hi from a run
 // state of depth ring_state; launch_vjp_begin: zeroes the cotangents, the
 // gradient and the pair buffers and starts the step base at steps - 1;
@@ -132,22 +136,5 @@ hipError_t launch_vjp_end(const DipDev *d_dev, const int32_t *d_off, const int64
                           double *d_grad, const double *d_Jpart, int64_t n_jpart, double *d_J, uint32_t *d_err,
                           hipStream_t s);
 
-// Gradient of the detector objective with respect to the oscillator positions
-// from a finished stride-1 run (lw_dipole_adjoint.hip).  d_hist / d_hbar hold
-// ring x n_dip x 3 doubles (ring >= steps + 1, power of two); d_Jpart one
-// double per detector workgroup ((npts * n_snap + 255) / 256).  d_pair_off /
-// d_pair_off0: per-instance prefix sums of the drive pairs of a step (4 n (n-1))
-// and of E_d(0) (2 n (n-1)); d_state 6 n_dip doubles; d_rbp / d_rbp0 three
-// doubles per pair, d_taup one per pair; d_step a device step index.  Steps
-// are reversed one launch each, `graph_chunk` of them captured on `cap` into a
-// graph handed back for the caller to release after the stream has passed it.
-hipError_t launch_dipole_vjp(const DipDev *d_dev, const int32_t *d_off, const int64_t *d_pair_off,
-                             const int64_t *d_pair_off0, int n_inst, int64_t n_pairs, int64_t n_pairs0, int n_dip,
-                             const double *d_D, const double *d_V, const double *d_Ed, double *d_hist, double *d_hbar,
-                             int ring, int64_t steps, double dt, const double *d_pts, int64_t npts,
-                             const double *d_times, int n_snap, double *d_grad, double *d_Jpart, double *d_J,
-                             double *d_state, double *d_rbp, double *d_rbp0, double *d_taup, int64_t *d_step,
-                             uint32_t *d_err, int graph_chunk, hipStream_t s, hipStream_t cap, hipGraph_t *graph_out,
-                             hipGraphExec_t *exec_out);
 
 }  // namespace lw
