@@ -1030,7 +1030,7 @@ static lw_status vjp_pipelined(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_di
     const size_t po_b = align_up(sizeof(int64_t) * (size_t)(n_inst + 1), 256);
     const size_t tm_b = align_up(sizeof(double) * (size_t)n_snap, 256);
     const size_t dev_b = align_up(lw::dip_dev_bytes(n_dip), 256);
-    const size_t adj_b = align_up(sizeof(double) * 6 * (size_t)n_dip, 256);
+    const size_t adj_b = align_up(sizeof(double) * 12 * (size_t)n_dip, 256);
     const size_t rbp_b = align_up(sizeof(double) * 3 * (size_t)std::max<int64_t>(n_pairs, 1), 256);
     const size_t rbp0_b = align_up(sizeof(double) * 3 * (size_t)std::max<int64_t>(n_pairs0, 1), 256);
     const size_t taup_b = align_up(sizeof(double) * (size_t)std::max<int64_t>(n_pairs, 1), 256);
@@ -1160,8 +1160,8 @@ static lw_status vjp_pipelined(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_di
     if (K >= C) {
         LW_HIP(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
         const hipError_t ce = lw::launch_vjp_steps(d_dev, d_off, d_pair_off, n_inst, n_dip, d_hist, d_hbar,
-                                                   (int)ring_h, dt, d_adj, d_rbp, d_taup, d_step, C, ctx->d_err,
-                                                   ctx->capture);
+                                                   (int)ring_h, dt, d_adj, d_rbp, d_taup, d_step, C, steps,
+                                                   ctx->d_err, ctx->capture);
         const hipError_t ee = hipStreamEndCapture(ctx->capture, &sg.graph);
         LW_HIP(ce);
         LW_HIP(ee);
@@ -1190,7 +1190,7 @@ static lw_status vjp_pipelined(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_di
         for (int64_t r = 0; r < reps; ++r)
             if (hipGraphLaunch(sg.exec, s) != hipSuccess) return bail(fail(LW_E_HIP, "backward steps"));
         if (lw::launch_vjp_steps(d_dev, d_off, d_pair_off, n_inst, n_dip, d_hist, d_hbar, (int)ring_h, dt, d_adj,
-                                 d_rbp, d_taup, d_step, ks - reps * C, ctx->d_err, s) != hipSuccess)
+                                 d_rbp, d_taup, d_step, ks - reps * C, steps, ctx->d_err, s) != hipSuccess)
             return bail(fail(LW_E_HIP, "backward steps"));
         if (hipEventRecord(ctx->adj_swept, s) != hipSuccess || hipStreamWaitEvent(t, ctx->adj_swept, 0) != hipSuccess)
             return bail(fail(LW_E_HIP, "hipEventRecord"));

@@ -81,6 +81,29 @@ __device__ __forceinline__ void hist_eval(const Hist &H, int j, double d0, int64
     e.u = u;
 }
 
+// hist_eval at s from the segment the closed form already loaded, when s lies
+// in it (the same values and operations, without reading the samples again).
+__device__ __forceinline__ void seg_eval(const Hist &H, int j, const Seg &g, double d0, int64_t nstep, double s,
+                                         HistEval &e)
+{
+    const double fk = floor(s);
+    const int64_t k = (int64_t)fk;
+    if (s < 0.0 || k >= nstep || k != g.k) {
+        hist_eval(H, j, d0, nstep, s, e);
+        return;
+    }
+    const double u = s - fk;
+    e.d = (1.0 - u) * g.d0 + u * g.d1;
+    e.v = (1.0 - u) * g.v0 + u * g.v1;
+    e.a = (1.0 - u) * g.a0 + u * g.a1;
+    e.sd = (g.d1 - g.d0) * H.inv_dt;
+    e.sv = (g.v1 - g.v0) * H.inv_dt;
+    e.sa = (g.a1 - g.a0) * H.inv_dt;
+    e.region = 1;
+    e.k = k;
+    e.u = u;
+}
+
 // Retarded field of charge (cf, kq) of source j at point x and time base*dt
 // (samples up to nstep); fills the kinematics and the history evaluation.
 __device__ void pair_solve(const Hist &H, const double x[3], const DipLds &Sj, int j, double cf, int64_t nstep,
@@ -92,12 +115,14 @@ __device__ void pair_solve(const Hist &H, const double x[3], const DipLds &Sj, i
     const double L = sqrt(L2);
     const double sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;
     Bracket b(0.0, 2.0 * L * INV_C);
-    // warm start from the same pair's retarded time one step later, if given
-    double tau = (tau_init > 0.0 && tau_init < b.hi) ? tau_init : L * INV_C;
+    double tau = L * INV_C;
     const double tol = 4.0 * 2.220446049250313e-16;
     bool ok = false;
     // the closed form on the interpolated history (retarded_seg) from the
-    // start's segment; Newton past the newest stored step
+    // segment of tau = L/c (the charge sits within |rho| << L of its origin, so
+    // that is the root's segment or a neighbour); Newton past the newest
+    // stored step, warm-started from the same pair's retarded time one step
+    // later if given (read only there)
     {
         const double s0 = base - tau * H.inv_dt;
         const int64_t k0 = s0 < 0.0 ? -1 : (int64_t)floor(s0);
@@ -107,11 +132,12 @@ __device__ void pair_solve(const Hist &H, const double x[3], const DipLds &Sj, i
             double hh[3], tc;
             if (retarded_seg(H, j, Sj.d0, nstep, base, L2, sD, cf, g, hh, tc, err)) {
                 tau = tc;
-                hist_eval(H, j, Sj.d0, nstep, base - tau * H.inv_dt, e);
+                seg_eval(H, j, g, Sj.d0, nstep, base - tau * H.inv_dt, e);
                 ok = true;
             }
         }
     }
+    if (!ok && tau_init > 0.0 && tau_init < b.hi) tau = tau_init;
     for (int it = 0; it < max_iter && !ok; ++it) {
         const double s = base - tau * H.inv_dt;
         hist_eval(H, j, Sj.d0, nstep, s, e);
@@ -403,18 +429,22 @@ struct AdjState {
     double *yd, *yv, *ext, *em, *ee, *ec;
 };
 
-// Transpose of one RK4 step of dipole g (linear in y and in the three stage
-// drives): maps (yd, yv, ext) of y[n+1] to the cotangents of y[n] (partial:
-// sample n's own cotangent is added once complete) and of Ec, Em, Ee.
-__device__ __forceinline__ void rk4_transpose(const DipDev &P, double h, AdjState &A, int g)
+// Transpose of one RK4 step of a dipole (linear in y and in the three stage
+// drives): maps the cotangents (yd, yv, ext) of y[n+1] to those of y[n]
+// (partial: sample n's own cotangent is added once complete), returned in
+// yd, yv, and to the cotangents of the drives Ec, Em, Ee.
+__device__ __forceinline__ void rk4_transpose(const DipDev &P, double h, double &yd, double &yv, double ext,
+                                              double &Em, double &Ee, double &Ec)
 {
     const double w2 = P.omega0 * P.omega0, gm = P.gamma0, f = P.f;
-    const double yd = A.yd[g], yv = A.yv[g];
     double k1d = h / 6.0 * yd, k1v = h / 6.0 * yv;
     double k2d = h / 3.0 * yd, k2v = h / 3.0 * yv;
     double k3d = h / 3.0 * yd, k3v = h / 3.0 * yv;
     const double k4d = h / 6.0 * yd, k4v = h / 6.0 * yv;
-    double ad = yd, av = yv, Ee = A.ext[g], Em = 0.0, Ec = 0.0;
+    double ad = yd, av = yv;
+    Ee = ext;
+    Em = 0.0;
+    Ec = 0.0;
     // k4 = A y4 + e Ee;  y4 = y + h k3
     double td = -w2 * k4v, tv = k4d - gm * k4v;
     Ee += f * k4v;
@@ -430,18 +460,13 @@ __device__ __forceinline__ void rk4_transpose(const DipDev &P, double h, AdjStat
     // k1 = A y + e Ec
     ad += -w2 * k1v; av += k1d - gm * k1v;
     Ec += f * k1v;
-    A.yd[g] = ad;
-    A.yv[g] = av;
-    A.em[g] = Em;
-    A.ee[g] = Ee;
-    A.ec[g] = Ec;
+    yd = ad;
+    yv = av;
 }
 
 // Adds the completed cotangent of sample n (d, d_dot, d_ddot = f Ec - gamma0
 // d_dot - omega0^2 d) of dipole g: into y[n] unless n = 0 (y[0] is fixed), and
-// into the drive at t_n (ext for the step before).
-// The slot is cleared once read, so a ring shorter than the run can hold the
-// adjoint history (no pair adds to sample n once the sweep has passed step n).
+// into the drive at t_n (ext for the step before); clears the slot.
 __device__ __forceinline__ void take_sample(const DipDev &P, double *hbar, int64_t n, int n_dip, int mask,
                                             AdjState &A, int g)
 {
@@ -507,92 +532,152 @@ __device__ __forceinline__ PairIx pair_index(const int64_t *pair_off, const int3
     return P;
 }
 
-// One step n = *step_base - k of the backward sweep, one workgroup per dipole
-// (the target).  One lane completes the dipole's sample n + 1 (every pair
-// that reads it belongs to a later step, already reversed) and transposes step
-// n; then every drive pair of the target at stages t_n + dt/2 and t_n + dt
-// reverses its field evaluation, scattering into the source's samples and
-// accumulating the cotangent of the (target - source) separation in rbp.  The
-// pair's retarded time is kept in taup as the next (earlier) step's start.
+// One step n = *step_base - k of the backward sweep, one workgroup per source
+// dipole j.
+//  1. Every workgroup of an instance finishes the step's drive cotangents of
+//     all the instance's dipoles (read-only): the cotangent state S_{n+1}
+//     (buffer (n+1) & 1) plus the completed sample n + 1 (every pair that
+//     reads it belongs to a later step, already reversed), transposed through
+//     RK4 step n.  Workgroup j alone writes dipole j's S_n (buffer n & 1) and
+//     clears its sample n + 2, which the step before was the last to read.
+//  2. Every drive pair with source j (targets i != j, charges w, stages
+//     t_n + dt/2 and t_n + dt) reverses its field evaluation for a unit drive
+//     cotangent; this does not depend on step 1 and runs beside it.  The
+//     pair's retarded time is kept in taup as the next (earlier) step's start.
+//  3. Each pair scales its products by its target's stage cotangent, adds the
+//     (target - source) separation cotangent into its slot of rbp, and its
+//     sample cotangents into LDS slots relative to the workgroup's earliest
+//     sample.  The slots then go to source j's adjoint history with one
+//     device atomic each: only this workgroup writes source j's samples in the
+//     step, so the atomics are uncontended (a detector reverse running on
+//     another stream may add to the same samples).
+constexpr int ADJ_SLOTS = 128;
+
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void adj_step_kernel(const DipDev *__restrict__ dev,
                                                          const int32_t *__restrict__ off,
                                                          const int64_t *__restrict__ pair_off, int n_inst, int n_dip,
                                                          const double *__restrict__ hist, double *__restrict__ hbar,
-                                                         int mask, double dt, AdjState A, double *__restrict__ rbp,
-                                                         double *__restrict__ taup,
-                                                         const int64_t *__restrict__ step_base, int k, int max_iter,
-                                                         const double *__restrict__ soa, uint32_t *__restrict__ d_err)
+                                                         int mask, double dt, AdjState A0, AdjState A1,
+                                                         double *__restrict__ rbp, double *__restrict__ taup,
+                                                         const int64_t *__restrict__ step_base, int k, int64_t last,
+                                                         int max_iter, const double *__restrict__ soa,
+                                                         uint32_t *__restrict__ d_err)
 {
-    __shared__ double s_em, s_ee;
-    const int tid = threadIdx.x;
-    const int g = blockIdx.x;
+    __shared__ double s_es[2][1024];            // stage drive cotangents of the instance's dipoles
+    __shared__ double slot[ADJ_SLOTS * 3];
+    __shared__ int64_t kmin_w[BLOCK / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j = blockIdx.x;
     const int64_t nstep = *step_base - k;
     if (nstep < 0) return;
-    const DipDev &Di = dev[g];
-    const int inst = instance_of(off, n_inst, g);
-    const int i0 = off[inst], n = off[inst + 1] - i0, i = g - i0;
+    const int inst = instance_of(off, n_inst, j);
+    const int i0 = off[inst], n = off[inst + 1] - i0, jl = j - i0;
     const int M = 2 * (n - 1);
+    const bool odd = (nstep & 1) != 0;
+    const AdjState &Ain = odd ? A0 : A1;        // S_{n+1}
+    const AdjState &Aout = odd ? A1 : A0;       // S_n
     uint32_t err = 0u;
     const Hist H{hist, n_dip, mask, dt, 1.0 / dt};
-    const double x[3] = {Di.origin[0], Di.origin[1], Di.origin[2]};
-    const double Eu[3] = {Di.axis[0], Di.axis[1], Di.axis[2]};   // unit drive cotangent
-    // the pair work does not depend on the cotangents: each lane solves its
-    // first pair and reverses it for a unit drive cotangent while thread 0
-    // finishes the dipole's state; the products are scaled afterwards
-    // (everything is linear in the drive cotangent)
+    const DipLds Sj = soa_lds(soa, n_dip, (uint32_t)j);
+    const double qj = soa_get(soa, n_dip, SF_Q, (uint32_t)j);
+    for (int t = tid; t < ADJ_SLOTS * 3; t += BLOCK) slot[t] = 0.0;
+    // 2. the pair work (first pair of each lane)
     int m2 = tid;
     double Du[3] = {0.0, 0.0, 0.0};
     HistBar hu;
     hu.region = 0;
     hu.k = 0;
-    int gj = 0;
+    int th = 0, il = 0;
     int64_t idx = 0;
     double rb[3] = {0.0, 0.0, 0.0};     // the pair's separation cotangent so far, read early
     auto solve_unit = [&](int mm2) {
-        const int th = mm2 / M, m = mm2 - th * M;
-        const int jj = m >> 1, w = m & 1;
-        gj = i0 + (jj < i ? jj : jj + 1);
-        const DipLds Sj = soa_lds(soa, n_dip, (uint32_t)gj);
-        const double qj = soa_get(soa, n_dip, SF_Q, (uint32_t)gj);
+        th = mm2 / M;
+        const int m = mm2 - th * M;
+        const int ii = m >> 1, w = m & 1;
+        il = ii < jl ? ii : ii + 1;                   // target (local index)
+        const uint32_t gi = (uint32_t)(i0 + il);
+        const double x[3] = {soa_get(soa, n_dip, SF_OX, gi), soa_get(soa, n_dip, SF_OY, gi),
+                             soa_get(soa, n_dip, SF_OZ, gi)};
+        const double Eu[3] = {soa_get(soa, n_dip, SF_PX, gi), soa_get(soa, n_dip, SF_PY, gi),
+                              soa_get(soa, n_dip, SF_PZ, gi)};       // unit drive cotangent
         const double cf = w ? Sj.cfm : Sj.cfp;
         const double kq = (w ? -qj : qj) * K_COUL;
-        idx = pair_off[inst] + ((int64_t)th * n + i) * M + m;
+        const int jj = jl < il ? jl : jl - 1;         // the source's place in the target's list
+        idx = pair_off[inst] + ((int64_t)th * n + il) * M + 2 * jj + w;
         rb[0] = rbp[idx * 3];
         rb[1] = rbp[idx * 3 + 1];
         rb[2] = rbp[idx * 3 + 2];
+        const double tw = taup[idx];
         Kin kn;
         HistEval e;
         double tau;
-        pair_solve(H, x, Sj, gj, cf, nstep, (double)nstep + (th ? 1.0 : 0.5), max_iter, kn, e, err, taup[idx], &tau);
+        pair_solve(H, x, Sj, j, cf, nstep, (double)nstep + (th ? 1.0 : 0.5), max_iter, kn, e, err, tw, &tau);
         taup[idx] = tau;
         pair_vjp(kn, e, Sj, cf, kq, Eu, Du, hu);
     };
-    // the dipole's own sample and RK4 transpose go to a lane without pair work
-    // when there is one, so they run beside the pair solves
-    const int own = (2 * M < BLOCK) ? BLOCK - 1 : 0;
     if (m2 < 2 * M) solve_unit(m2);
-    if (tid == own) {
-        take_sample(Di, hbar, nstep + 1, n_dip, mask, A, g);
-        rk4_transpose(Di, dt, A, g);
-        s_em = A.em[g];
-        s_ee = A.ee[g];
+    // 1. the instance's drive cotangents; dipole j's S_n
+    for (int ql = tid; ql < n; ql += BLOCK) {
+        const int gq = i0 + ql;
+        const DipDev &P = dev[gq];
+        const double *hb = hbar + ((int64_t)((nstep + 1) & mask) * n_dip + gq) * 3;
+        const double bd = load_agent(hb), bv = load_agent(hb + 1), ba = load_agent(hb + 2);
+        double yd = Ain.yd[gq] + (bd - P.omega0 * P.omega0 * ba);
+        double yv = Ain.yv[gq] + (bv - P.gamma0 * ba);
+        const double ext = Ain.ec[gq] + P.f * ba;
+        double em, ee, ec;
+        rk4_transpose(P, dt, yd, yv, ext, em, ee, ec);
+        s_es[0][ql] = em;
+        s_es[1][ql] = ee;
+        if (gq == j) {
+            Aout.yd[gq] = yd;
+            Aout.yv[gq] = yv;
+            Aout.ec[gq] = ec;
+            if (nstep + 2 <= last) {
+                double *hc = hbar + ((int64_t)((nstep + 2) & mask) * n_dip + gq) * 3;
+                hc[0] = 0.0;
+                hc[1] = 0.0;
+                hc[2] = 0.0;
+            }
+        }
     }
+    // earliest sample the workgroup's first pairs touch
+    int64_t km = (m2 < 2 * M && hu.region) ? hu.k : INT64_MAX;
+    for (int o = 32; o > 0; o >>= 1) km = min(km, (int64_t)__shfl_xor(km, o, 64));
+    if (lane == 0) kmin_w[wave] = km;
     __syncthreads();
+    int64_t kb = kmin_w[0];
+    for (int v = 1; v < BLOCK / 64; ++v) kb = min(kb, kmin_w[v]);
+    // 3. scale, separation cotangents, sample cotangents into the slots
     for (; m2 < 2 * M; m2 += BLOCK) {
         if (m2 != tid) solve_unit(m2);
-        const double Es = (m2 / M) ? s_ee : s_em;
+        const double Es = s_es[th][il];
+        double *r = rbp + idx * 3;
+        r[0] = rb[0] + Es * Du[0];
+        r[1] = rb[1] + Es * Du[1];
+        r[2] = rb[2] + Es * Du[2];
+        if (hu.region == 0) continue;
         HistBar hb = hu;
         for (int c = 0; c < 3; ++c) {
             hb.c0[c] = Es * hu.c0[c];
             hb.c1[c] = Es * hu.c1[c];
         }
-        scatter_global(H, gj, hb, hbar);
-        double *r = rbp + idx * 3;
-        r[0] = rb[0] + Es * Du[0];
-        r[1] = rb[1] + Es * Du[1];
-        r[2] = rb[2] + Es * Du[2];
+        const int64_t sl = hb.k - kb;
+        if (sl >= 0 && sl + 1 < ADJ_SLOTS) {
+            for (int c = 0; c < 3; ++c) atomicAdd(&slot[sl * 3 + c], hb.c0[c]);
+            if (hb.region == 1)
+                for (int c = 0; c < 3; ++c) atomicAdd(&slot[(sl + 1) * 3 + c], hb.c1[c]);
+        } else {
+            scatter_global(H, j, hb, hbar);
+        }
     }
+    __syncthreads();
+    if (kb != INT64_MAX)
+        for (int t = tid; t < ADJ_SLOTS * 3; t += BLOCK) {
+            const double v = slot[t];
+            if (v != 0.0) atomicAdd(hbar + ((int64_t)((kb + t / 3) & mask) * n_dip + j) * 3 + t % 3, v);
+        }
     if (err) atomicOr(d_err, err);
 }
 
@@ -717,6 +802,8 @@ hipError_t launch_vjp_begin(int n_dip, int64_t n_pairs, int64_t steps, double *d
     hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, s, d_taup, n_pairs);
     hipLaunchKernelGGL(adj_init_kernel, dim3((unsigned)((n_dip + 255) / 256)), dim3(256), 0, s, n_dip, steps,
                        adj_state(d_state, n_dip), d_step);
+    hipLaunchKernelGGL(adj_init_kernel, dim3((unsigned)((n_dip + 255) / 256)), dim3(256), 0, s, n_dip, steps,
+                       adj_state(d_state + 6 * (int64_t)n_dip, n_dip), d_step);
     return hipGetLastError();
 }
 
@@ -735,16 +822,17 @@ hipError_t launch_vjp_detector(const DipDev *d_dev, int n_dip, const double *d_h
 
 hipError_t launch_vjp_steps(const DipDev *d_dev, const int32_t *d_off, const int64_t *d_pair_off, int n_inst,
                             int n_dip, const double *d_hist, double *d_hbar, int ring, double dt, double *d_state,
-                            double *d_rbp, double *d_taup, int64_t *d_step, int64_t count, uint32_t *d_err,
-                            hipStream_t s)
+                            double *d_rbp, double *d_taup, int64_t *d_step, int64_t count, int64_t steps,
+                            uint32_t *d_err, hipStream_t s)
 {
     constexpr int B = 256;
     if (count <= 0) return hipSuccess;
-    const AdjState A = adj_state(d_state, n_dip);
+    const AdjState A0 = adj_state(d_state, n_dip), A1 = adj_state(d_state + 6 * (int64_t)n_dip, n_dip);
     const double *soa = dip_soa(const_cast<DipDev *>(d_dev), n_dip);
     for (int64_t k = 0; k < count; ++k)
         hipLaunchKernelGGL(adj_step_kernel<B>, dim3((unsigned)n_dip), dim3(B), 0, s, d_dev, d_off, d_pair_off, n_inst,
-                           n_dip, d_hist, d_hbar, ring - 1, dt, A, d_rbp, d_taup, d_step, (int)k, 60, soa, d_err);
+                           n_dip, d_hist, d_hbar, ring - 1, dt, A0, A1, d_rbp, d_taup, d_step, (int)k, steps, 60,
+                           soa, d_err);
     hipLaunchKernelGGL(adj_base_kernel, dim3(1), dim3(1), 0, s, d_step, -count);
     return hipGetLastError();
 }

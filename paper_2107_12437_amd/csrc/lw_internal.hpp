@@ -104,7 +104,8 @@ hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const 
 // cotangents ([ring][n_dip][3], power of two: the whole run, or windows of
 // recomputed segments), whose slots are cleared as the sweep consumes them.
 // d_pair_off / d_pair_off0: per-instance prefix sums of the drive pairs of a
-// step (4 n (n-1)) and of E_d(0) (2 n (n-1)); d_state 6 n_dip doubles; d_rbp /
+// step (4 n (n-1)) and of E_d(0) (2 n (n-1)); d_state 12 n_dip doubles (the
+// cotangent state, double-buffered by step parity); d_rbp /
 // d_rbp0 three doubles per pair, d_taup one per pair; d_step a device step
 // index.  launch_hist_rows: samples row0 .. row0+nrows-1 from
 // a stride-1 run's outputs; launch_hist_from_state: samples lo .. hi from a run
@@ -128,8 +129,8 @@ hipError_t launch_vjp_detector(const DipDev *d_dev, int n_dip, const double *d_h
                                hipStream_t s);
 hipError_t launch_vjp_steps(const DipDev *d_dev, const int32_t *d_off, const int64_t *d_pair_off, int n_inst,
                             int n_dip, const double *d_hist, double *d_hbar, int ring, double dt, double *d_state,
-                            double *d_rbp, double *d_taup, int64_t *d_step, int64_t count, uint32_t *d_err,
-                            hipStream_t s);
+                            double *d_rbp, double *d_taup, int64_t *d_step, int64_t count, int64_t steps,
+                            uint32_t *d_err, hipStream_t s);
 hipError_t launch_vjp_end(const DipDev *d_dev, const int32_t *d_off, const int64_t *d_pair_off,
                           const int64_t *d_pair_off0, int n_inst, int64_t n_pairs0, int n_dip, const double *d_hist,
                           double *d_hbar, int ring, double dt, double *d_state, double *d_rbp, double *d_rbp0,
