@@ -656,8 +656,8 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
                                                         int init, RunOut out, const double *__restrict__ soa,
                                                         uint32_t *__restrict__ d_err)
 {
-    __shared__ double red[2][BLOCK];
-    const int tid = threadIdx.x;
+    __shared__ double red[2][BLOCK / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int gi = tgt[blockIdx.x];
     const int i0 = tgt_lo[blockIdx.x];
     const int n = tgt_n[blockIdx.x];
@@ -670,6 +670,21 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
     constexpr int U = units_per_source<MIXED>();
     const int M = U * (n - 1);                       // work units per stage
     const int nth = init ? 1 : 2;
+    // the target's own state (only this workgroup writes it, and only at its
+    // end): when the last lane has no pair work it reads the state into LDS
+    // while the others solve, so the tail does not wait on those loads; held
+    // in LDS, the values add no register pressure to the pair loop
+    __shared__ double own[6];
+    const bool early = !init && nth * M < BLOCK;
+    if (early && tid == BLOCK - 1) {
+        const double *h = rp + ((int64_t)(nstep & (ring_depth - 1)) * n + i) * 3;
+        own[0] = h[0];
+        own[1] = h[1];
+        own[2] = h[2];
+        own[3] = Ecur[gi];
+        own[4] = W[2 * gi];
+        own[5] = W[2 * gi + 1];
+    }
     double acc0 = 0.0, acc1 = 0.0;                   // stage t_n + dt/2 (or t = 0), stage t_n + dt
     for (int m = tid; m < nth * M; m += BLOCK) {
         const int th = m / M, mm = m - th * M;
@@ -681,22 +696,27 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
         const double e = unit_drive<MOVING, MIXED>(H, Si, Sj, j, qj, w, nstep, theta, max_iter, err);
         if (th) acc1 += e; else acc0 += e;
     }
-    red[0][tid] = acc0;
-    red[1][tid] = acc1;
-    __syncthreads();
-    for (int off = BLOCK / 2; off > 0; off >>= 1) {
-        if (tid < off) {
-            red[0][tid] += red[0][tid + off];
-            red[1][tid] += red[1][tid + off];
-        }
-        __syncthreads();
+    // block sums in a fixed order: within each wave, then over the waves
+    for (int o = 32; o > 0; o >>= 1) {
+        acc0 += __shfl_xor(acc0, o, 64);
+        acc1 += __shfl_xor(acc1, o, 64);
     }
+    if (lane == 0) {
+        red[0][wave] = acc0;
+        red[1][wave] = acc1;
+    }
+    __syncthreads();
     if (tid == 0) {
+        double s0 = red[0][0], s1 = red[1][0];
+        for (int v = 1; v < BLOCK / 64; ++v) {
+            s0 += red[0][v];
+            s1 += red[1][v];
+        }
         const DipDev &D = dev[gi];
         const double w2 = D.omega0 * D.omega0, g = D.gamma0, f = D.f;
         if (init) {
             // t = 0: drive from the static pre-history, sample 0 = (d0, 0, d_ddot(0))
-            const double E0 = red[0][0];
+            const double E0 = s0;
             double *h = rp + (int64_t)i * 3;
             h[0] = D.d0;
             h[1] = 0.0;
@@ -706,9 +726,24 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             W[2 * gi + 1] = 0.0;
             put_row(out, 0, gi, D.d0, 0.0, run_energy(w2, f, D.d0, 0.0), E0, 0.0, 0.0);
         } else {
-            const double Em = red[0][0], Ee = red[1][0], Ec = Ecur[gi];
-            const double *h = rp + ((int64_t)(nstep & (ring_depth - 1)) * n + i) * 3;
-            const double y0 = h[0], y1 = h[1];
+            const double Em = s0, Ee = s1;
+            double y0, y1, a0, Ec, W0, W1;
+            if (early) {
+                y0 = own[0];
+                y1 = own[1];
+                a0 = own[2];
+                Ec = own[3];
+                W0 = own[4];
+                W1 = own[5];
+            } else {
+                const double *h = rp + ((int64_t)(nstep & (ring_depth - 1)) * n + i) * 3;
+                y0 = h[0];
+                y1 = h[1];
+                a0 = h[2];
+                Ec = Ecur[gi];
+                W0 = W[2 * gi];
+                W1 = W[2 * gi + 1];
+            }
             const double k1d = y1, k1v = f * Ec - g * y1 - w2 * y0;
             const double y0b = y0 + 0.5 * dt * k1d, y1b = y1 + 0.5 * dt * k1v;
             const double k2d = y1b, k2v = f * Em - g * y1b - w2 * y0b;
@@ -727,8 +762,8 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             if (!(isfinite(dn) && isfinite(vn) && isfinite(an))) err |= ERR_NONFINITE;
             if (max_vel > 0.0 && D.mspeed + D.vfac * fabs(vn) > max_vel) err |= ERR_VELOCITY;
             // energy bookkeeping (Sec. 2.5), trapezoid rule over the step
-            const double wa = W[2 * gi] + 0.5 * dt * (y1 * Ec + vn * Ee);
-            const double wr = W[2 * gi + 1] + 0.5 * dt * K_LARMOR * (h[2] * h[2] + an * an);
+            const double wa = W0 + 0.5 * dt * (y1 * Ec + vn * Ee);
+            const double wr = W1 + 0.5 * dt * K_LARMOR * (a0 * a0 + an * an);
             W[2 * gi] = wa;
             W[2 * gi + 1] = wr;
             const int64_t rel = nstep + 1 - step_ctr[1];       // steps since the run's first
