@@ -1030,7 +1030,7 @@ static lw_status vjp_pipelined(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_di
     const size_t po_b = align_up(sizeof(int64_t) * (size_t)(n_inst + 1), 256);
     const size_t tm_b = align_up(sizeof(double) * (size_t)n_snap, 256);
     const size_t dev_b = align_up(lw::dip_dev_bytes(n_dip), 256);
-    const size_t adj_b = align_up(sizeof(double) * 12 * (size_t)n_dip, 256);
+    const size_t adj_b = align_up(sizeof(double) * 8 * (size_t)n_dip, 256);   // two cotangent states
     const size_t rbp_b = align_up(sizeof(double) * 3 * (size_t)std::max<int64_t>(n_pairs, 1), 256);
     const size_t rbp0_b = align_up(sizeof(double) * 3 * (size_t)std::max<int64_t>(n_pairs0, 1), 256);
     const size_t taup_b = align_up(sizeof(double) * (size_t)std::max<int64_t>(n_pairs, 1), 256);

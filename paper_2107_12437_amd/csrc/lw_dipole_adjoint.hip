@@ -420,14 +420,15 @@ __device__ __forceinline__ double load_agent(const double *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Per-dipole cotangent state of the backward sweep.  yd, yv: cotangent of the
-// state (d, d_dot) after the step being reversed; ee, em, ec: cotangents of the
-// drives at t_n + dt, t_n + dt/2 and t_n of that step; ext: cotangent of the
-// drive at t_{n+1} received from outside the step (the stored d_ddot of
-// sample n+1 and the next step's first stage).
+// Per-dipole cotangent state of the backward sweep once steps >= n are
+// reversed.  yd, yv: cotangent of the state (d, d_dot) at t_n (partial until
+// sample n's own cotangent is added); ec: cotangent of the drive at t_n from
+// the first stage of step n; ext: after the sweep, the whole cotangent of the
+// drive at t = 0 (sample 0's d_ddot and ec).
 struct AdjState {
-    double *yd, *yv, *ext, *em, *ee, *ec;
+    double *yd, *yv, *ext, *ec;
 };
+constexpr int ADJ_FIELDS = 4;
 
 // Transpose of one RK4 step of a dipole (linear in y and in the three stage
 // drives): maps the cotangents (yd, yv, ext) of y[n+1] to those of y[n]
@@ -490,8 +491,6 @@ __global__ void adj_init_kernel(int n_dip, int64_t steps, AdjState A, int64_t *_
         A.yv[g] = 0.0;
         A.ext[g] = 0.0;
         A.ec[g] = 0.0;
-        A.em[g] = 0.0;
-        A.ee[g] = 0.0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *step_base = steps - 1;
 }
@@ -788,8 +787,7 @@ hipError_t launch_hist_from_state(const double *d_state, const int32_t *d_off, i
 
 static AdjState adj_state(double *d_state, int n_dip)
 {
-    return AdjState{d_state, d_state + n_dip, d_state + 2 * (int64_t)n_dip, d_state + 3 * (int64_t)n_dip,
-                    d_state + 4 * (int64_t)n_dip, d_state + 5 * (int64_t)n_dip};
+    return AdjState{d_state, d_state + n_dip, d_state + 2 * (int64_t)n_dip, d_state + 3 * (int64_t)n_dip};
 }
 
 hipError_t launch_vjp_begin(int n_dip, int64_t n_pairs, int64_t steps, double *d_hbar, int64_t hbar_doubles,
@@ -803,7 +801,7 @@ hipError_t launch_vjp_begin(int n_dip, int64_t n_pairs, int64_t steps, double *d
     hipLaunchKernelGGL(adj_init_kernel, dim3((unsigned)((n_dip + 255) / 256)), dim3(256), 0, s, n_dip, steps,
                        adj_state(d_state, n_dip), d_step);
     hipLaunchKernelGGL(adj_init_kernel, dim3((unsigned)((n_dip + 255) / 256)), dim3(256), 0, s, n_dip, steps,
-                       adj_state(d_state + 6 * (int64_t)n_dip, n_dip), d_step);
+                       adj_state(d_state + ADJ_FIELDS * (int64_t)n_dip, n_dip), d_step);
     return hipGetLastError();
 }
 
@@ -827,7 +825,7 @@ hipError_t launch_vjp_steps(const DipDev *d_dev, const int32_t *d_off, const int
 {
     constexpr int B = 256;
     if (count <= 0) return hipSuccess;
-    const AdjState A0 = adj_state(d_state, n_dip), A1 = adj_state(d_state + 6 * (int64_t)n_dip, n_dip);
+    const AdjState A0 = adj_state(d_state, n_dip), A1 = adj_state(d_state + ADJ_FIELDS * (int64_t)n_dip, n_dip);
     const double *soa = dip_soa(const_cast<DipDev *>(d_dev), n_dip);
     for (int64_t k = 0; k < count; ++k)
         hipLaunchKernelGGL(adj_step_kernel<B>, dim3((unsigned)n_dip), dim3(B), 0, s, d_dev, d_off, d_pair_off, n_inst,

@@ -104,7 +104,7 @@ hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const 
 // cotangents ([ring][n_dip][3], power of two: the whole run, or windows of
 // recomputed segments), whose slots are cleared as the sweep consumes them.
 // d_pair_off / d_pair_off0: per-instance prefix sums of the drive pairs of a
-// step (4 n (n-1)) and of E_d(0) (2 n (n-1)); d_state 12 n_dip doubles (the
+// step (4 n (n-1)) and of E_d(0) (2 n (n-1)); d_state 8 n_dip doubles (the
 // cotangent state, double-buffered by step parity); d_rbp /
 // d_rbp0 three doubles per pair, d_taup one per pair; d_step a device step
 // index.  launch_hist_rows: samples row0 .. row0+nrows-1 from
