@@ -114,3 +114,36 @@ def test_autograd_and_full_detector_workload():
             vals.append((Jp - Jm) / (2 * h))
         fd = (4 * vals[0] - vals[1]) / 3
         assert abs(g[i, c] - fd) <= 1e-5 * np.abs(g).max(), (i, c, g[i, c], fd)
+
+
+def test_large_instance_directional_derivative():
+    """A 72-dipole cluster (288 drive pairs per source and step: each lane of the backward
+    step takes more than one pair) next to a pair, 200 steps. The gradient's projection on
+    a seeded direction of all 222 origin coordinates matches the Richardson-extrapolated
+    central difference of the GPU's own J (whose values match the oracle's in the tests
+    above), to 1e-5 of |g| |v|."""
+    import torch
+    from paper_2107_12437_amd import lw
+    rng = I.rng_for(95)
+    a = I.cluster_dipoles(rng, 72, 60e-9, 10e-9, 2 * math.pi * 200e12, 0.01, True)
+    b = I.cluster_dipoles(rng, 2, 20e-9, 10e-9, 2 * math.pi * 200e12, 0.01, True)
+    b["origin"] += np.array([200e-9, 0.0, 0.0])
+    dip = I.concat_dipoles([a, b])
+    off = np.array([0, 72, 74], np.int32)
+    dt = 1 / 200e12 / 200
+    steps = 200
+    times = np.array([100 * dt, 150 * dt, 200 * dt])
+    dpts = torch.tensor(I.plane_grid(150e-9, 8, z=120e-9), dtype=torch.float64, device="cuda")
+    J, grad = lw.dipole_run_vjp(dip, off, dt, steps, dpts, times)
+    g = grad.cpu().numpy()
+    v = rng.normal(size=g.shape)
+    v /= np.linalg.norm(v)
+
+    def J_at(h):
+        d = {k: np.array(x, copy=True) for k, x in dip.items()}
+        d["origin"] = d["origin"] + h * v
+        return lw.dipole_run_vjp(d, off, dt, steps, dpts, times)[0]
+
+    vals = [(J_at(h) - J_at(-h)) / (2 * h) for h in (1e-12, 2e-12)]
+    fd = (4 * vals[0] - vals[1]) / 3
+    assert abs((g * v).sum() - fd) <= 1e-5 * np.linalg.norm(g), ((g * v).sum(), fd, np.linalg.norm(g))
