@@ -782,6 +782,23 @@ static lw_status dipole_run_impl(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_
             ring_doubles += (int64_t)n * ring * 3;
         }
     }
+    // largest instances first: their workgroups (n - 1 sources each) start in the
+    // first waves of the dispatch and the small ones fill in behind them, which
+    // shortens the step's tail; each instance's targets stay contiguous
+    {
+        std::vector<size_t> ord(tgt.size());
+        for (size_t q = 0; q < ord.size(); ++q) ord[q] = q;
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return tgt_n[x] > tgt_n[y]; });
+        auto permute = [&](auto &v) {
+            auto w = v;
+            for (size_t q = 0; q < ord.size(); ++q) w[q] = v[ord[q]];
+            v.swap(w);
+        };
+        permute(tgt);
+        permute(tgt_lo);
+        permute(tgt_n);
+        permute(tgt_base);
+    }
     const size_t n_tgt = tgt.size();
 
     const size_t in_bytes = align_up(sizeof(lw_dipole) * (size_t)n_dip, 256);
