@@ -155,6 +155,50 @@ __device__ __forceinline__ double retarded_hist(const Hist &H, int j, double d0,
     return tau;
 }
 
+// Retarded time past the newest stored step (the Taylor extrapolation of the
+// history from sample nstep, Sec. 2.3 with the dt reading of the extrapolating
+// policy): there the charge's offset is quadratic in tau,
+//   rho(tau) = cf (d + v u + a u^2 / 2),  u = (base - nstep) dt - tau,
+// and c tau = |Delta - rho p_j| is solved by the closed form of retarded_seg
+// on the tangent line of rho, taken twice (at tau = L/c, then at the first
+// root).  The linearisation error is rho'' (tau1 - tau0)^2 / 2, with
+// |tau1 - tau0| ~ |rho| / c.  The result is accepted under retarded_hist's
+// a-posteriori bound on the last step; returns false (the caller then uses
+// Newton) when the root lies inside the stored history or the bound fails.
+__device__ __forceinline__ bool retarded_ext(const Hist &H, int j, int64_t nstep, double base, double L2, double L,
+                                             double sD, double cf, double h[3], double &tau_out)
+{
+    constexpr double C2 = C_LIGHT * C_LIGHT;
+    const double *hn = H.ring + ((int64_t)(nstep & H.mask) * H.n + j) * 3;
+    const double U = (base - (double)nstep) * H.dt;
+    const double al = cf * hn[0], be = cf * hn[1], ga = 0.5 * cf * hn[2];
+    double tau = L * INV_C, step = 0.0, r1 = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+        const double u = U - tau;
+        const double rho = al + u * (be + u * ga);
+        r1 = -(be + 2.0 * ga * u);                      // d rho / d tau
+        const double a = rho - r1 * tau;                // tangent line a + r1 tau
+        const double P = sD - a;
+        const double Q = fma(a, a - 2.0 * sD, L2);
+        const double bP = r1 * P;
+        double S, iS;
+        root_rsqrt<true>(fma(bP, bP, (C2 - r1 * r1) * Q), S, iS);
+        const double tn = Q * recip<double>(bP + S);
+        step = tn - tau;
+        tau = tn;
+    }
+    const double u = U - tau;
+    if (!(u >= 0.0)) return false;                      // inside the stored history
+    const double D = C_LIGHT * tau, r2 = 2.0 * ga;
+    const double tol = 4.0 * 2.220446049250313e-16;
+    if (!((r1 * r1 + fabs(r2) * D) * (step * step) <= 0.5 * tol * tau * D * (C_LIGHT - fabs(r1)))) return false;
+    h[0] = hn[0] + hn[1] * u + 0.5 * hn[2] * u * u;
+    h[1] = hn[1] + hn[2] * u;
+    h[2] = hn[2];
+    tau_out = tau;
+    return true;
+}
+
 // p_i . E at the origin of target i of the charge (cf, kq) of source j whose
 // stored state at the retarded time is h.
 __device__ __forceinline__ double drive_field(const DipLds &Si, const DipLds &Sj, double dx, double dy, double dz,
@@ -248,8 +292,9 @@ __device__ double retarded_hist_moving(const Hist &H, int j, const DipLds &Sj, c
 
 // Interpolated state h at the retarded time of the charge (cf) of fixed source
 // j seen at separation Delta (|Delta|^2 = L2, |Delta| = L, Delta . p_j = sD):
-// the closed form on the segment cached in g, else Newton (past the newest
-// stored step).  g.k = INT64_MIN marks an empty cache.
+// the closed form on the segment cached in g; past the newest stored step the
+// closed form on the extrapolation; else Newton.  g.k = INT64_MIN marks an
+// empty cache.
 __device__ __forceinline__ void charge_fixed(const Hist &H, int j, double d0, int64_t nstep, double base, double L2,
                                              double L, double sD, double cf, int max_iter, Seg &g, double h[3],
                                              uint32_t &err)
@@ -261,6 +306,7 @@ __device__ __forceinline__ void charge_fixed(const Hist &H, int j, double d0, in
     }
     double tau;
     if (g.k != INT64_MIN && retarded_seg(H, j, d0, nstep, base, L2, sD, cf, g, h, tau, err)) return;
+    if (retarded_ext(H, j, nstep, base, L2, L, sD, cf, h, tau)) return;
     retarded_hist(H, j, d0, nstep, base, L2, sD, cf, L * INV_C, 2.0 * L * INV_C, max_iter, h, err);
 }
 
