@@ -199,31 +199,6 @@ __device__ __forceinline__ bool retarded_ext(const Hist &H, int j, int64_t nstep
     return true;
 }
 
-// p_i . E at the origin of target i of the charge (cf, kq) of source j whose
-// stored state at the retarded time is h.
-__device__ __forceinline__ double drive_field(const DipLds &Si, const DipLds &Sj, double dx, double dy, double dz,
-                                              double cf, double kq, const double h[3])
-{
-    Kin k;
-    const double rho = cf * h[0];
-    k.R[0] = dx - rho * Sj.px;
-    k.R[1] = dy - rho * Sj.py;
-    k.R[2] = dz - rho * Sj.pz;
-    k.v[0] = cf * h[1] * Sj.px;
-    k.v[1] = cf * h[1] * Sj.py;
-    k.v[2] = cf * h[1] * Sj.pz;
-    k.a[0] = cf * h[2] * Sj.px;
-    k.a[1] = cf * h[2] * Sj.py;
-    k.a[2] = cf * h[2] * Sj.pz;
-    k.tp = 0.0;
-    k.cph = 1.0;
-    k.sph = 0.0;
-    k.flags = 0u;
-    double o[10];
-    lw_terms<double>(k, kq, F_TOTAL, o);
-    return o[4] * Si.px + o[5] * Si.py + o[6] * Si.pz;
-}
-
 // Retarded time of the charge at offset cf d(t') p_j of a moving source j seen
 // from X at time base * dt: the root of c tau = |X - R_j(t') - cf d(t') p_j|,
 // t' = t - tau, with R_j(t') = O_j + m_j cos(w t' + phi).  The same iteration
@@ -358,6 +333,34 @@ __device__ __forceinline__ double charge_field(const DipLds &Si, const double R[
 // taken at the target's origin at that time.  MOVING: origins may move; without
 // it every origin is taken as fixed (the kernels for fixed origins carry none
 // of the moving-origin code).
+// p_i . E (Eq. (E), total field, FP64) at the origin of target i of the charge
+// (cf, kq) of a fixed source j, from its stored state h at the retarded time.
+// The charge moves along p_j, so beta and beta_dot are multiples of p_j and
+// every vector product of Eq. (E) reduces to the scalars
+//   w = R . p_j = sD - rho,  p_i . R = sI - rho pij,  pij = p_i . p_j,
+// with R = Delta - rho p_j, rho = cf d:
+//   p_i . E = f [(p_i . n - b pij) cu - e pij cd],  n = R / |R|,
+//   b = cf d_dot / c, e = cf d_ddot / c, kappa = 1 - b (n . p_j),
+//   f = kq / (kappa^3 |R|), cu = (1 - b^2) / |R| + e (n . p_j) / c,
+//   cd = kappa / c.
+__device__ __forceinline__ double drive_scalar(double L2, double sD, double sI, double pij, double cf, double kq,
+                                               const double h[3])
+{
+    const double rho = cf * h[0];
+    double D, iD;
+    root_rsqrt<true>(fma(rho, rho - 2.0 * sD, L2), D, iD);
+    iD = fma(iD, fma(-D, iD, 1.0), iD);
+    const double b = cf * h[1] * INV_C, e = cf * h[2] * INV_C;
+    const double wn = (sD - rho) * iD;                  // n . p_j
+    const double pin = (sI - rho * pij) * iD;           // p_i . n
+    const double kappa = 1.0 - b * wn;
+    const double ik = recip<double>(kappa);
+    const double f = kq * iD * ik * ik * ik;
+    const double cu = (1.0 - b * b) * iD + e * wn * INV_C;
+    const double cd = kappa * INV_C;
+    return f * ((pin - b * pij) * cu - e * pij * cd);
+}
+
 template <bool MOVING>
 __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double cf, double kq,
                              int64_t nstep, double theta, int max_iter, uint32_t &err)
@@ -373,7 +376,9 @@ __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, 
         g.k = INT64_MIN;
         double h[3];
         charge_fixed(H, j, Sj.d0, nstep, base, L2, sqrt(L2), sD, cf, max_iter, g, h, err);
-        return drive_field(Si, Sj, dx, dy, dz, cf, kq, h);
+        const double sI = dx * Si.px + dy * Si.py + dz * Si.pz;                  // Delta . p_i
+        const double pij = Si.px * Sj.px + Si.py * Sj.py + Si.pz * Sj.pz;
+        return drive_scalar(L2, sD, sI, pij, cf, kq, h);
     }
     if constexpr (MOVING) {
         double R[3], v[3], a[3];

@@ -5,7 +5,12 @@ largest magnitude of each output per dipole (1e-11: both sides are FP64 and
 differ by the retarded-time solver and the order of the pair sums).  The drive
 field is the near-cancelling sum of opposite charges' fields, so it is compared
 relative to the sum of the single-charge field magnitudes (1e-13, a few hundred
-ulp).  Collective rates and shifts extracted from the moments agree to 1e-3.
+ulp).  A dipole driven only through such a field inherits its rounding relative
+to the net drive: r = (single-charge scale) / max |E_d| per dipole (about 1e6 for a
+pair 745 nm apart, whose net field is 1e-6 of a single charge's), so its state
+tolerance is max(1e-11, 2 eps r) (both sides round each charge's field; the
+per-step errors average out in the response, measured at 0.1 eps r).  Collective
+rates and shifts extracted from the moments agree to 1e-3.
 """
 import math
 
@@ -21,6 +26,7 @@ pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ready(), reason="needs
 
 TOL_STATE = 1e-11
 TOL_DRIVE = 1e-13
+EPS = 2.220446049250313e-16
 
 
 def gpu_run(w, policy, stride=1, **kw):
@@ -51,18 +57,22 @@ def single_charge_scale(w):
 
 
 def assert_state_close(got, ref, w, keys=("d", "d_dot", "energy", "Ed"), tol=TOL_STATE, what=""):
-    """d, d_dot, energy relative to their largest magnitude per dipole (tol); Ed relative
-    to the single-charge field scale (TOL_DRIVE)."""
+    """d, d_dot, energy relative to their largest magnitude per dipole (tol, or 2 eps times
+    the dipole's drive cancellation ratio where that is larger); Ed relative to the
+    single-charge field scale (TOL_DRIVE)."""
+    sc = single_charge_scale(w)
+    net = np.abs(ref["Ed"]).max(axis=0)
+    ratio = np.where(net > 0, sc / np.where(net > 0, net, 1.0), 0.0)
     for k in keys:
         if k == "Ed":
-            scale = single_charge_scale(w)[None, :]
+            scale = sc[None, :]
             t = TOL_DRIVE
         else:
             scale = np.abs(ref[k]).max(axis=0, keepdims=True)
-            t = tol
+            t = np.maximum(tol, 2 * EPS * ratio)[None, :]
         scale = np.where(scale > 0, scale, 1.0)
         err = np.abs(got[k] - ref[k]) / scale
-        assert err.max() <= t, f"{what} {k}: max relative error {err.max():.3e} at {np.unravel_index(err.argmax(), err.shape)}"
+        assert (err <= t).all(), f"{what} {k}: max relative error {err.max():.3e} at {np.unravel_index(err.argmax(), err.shape)}"
 
 
 def test_pairs_extrapolate_parity():
