@@ -339,10 +339,11 @@ __device__ __forceinline__ double charge_field(const DipLds &Si, const double R[
 // every vector product of Eq. (E) reduces to the scalars
 //   w = R . p_j = sD - rho,  p_i . R = sI - rho pij,  pij = p_i . p_j,
 // with R = Delta - rho p_j, rho = cf d:
-//   p_i . E = f [(p_i . n - b pij) cu - e pij cd],  n = R / |R|,
+//   p_i . E = f [(p_i . n - b pij) (1 - b^2) / |R| - e q / c],  n = R / |R|,
 //   b = cf d_dot / c, e = cf d_ddot / c, kappa = 1 - b (n . p_j),
-//   f = kq / (kappa^3 |R|), cu = (1 - b^2) / |R| + e (n . p_j) / c,
-//   cd = kappa / c.
+//   f = kq / (kappa^3 |R|), q = pij - (p_i . n)(n . p_j),
+// where the radiation term's beta parts cancel exactly (q is p_i . the part
+// of p_j across n).
 __device__ __forceinline__ double drive_scalar(double L2, double sD, double sI, double pij, double cf, double kq,
                                                const double h[3])
 {
@@ -356,9 +357,8 @@ __device__ __forceinline__ double drive_scalar(double L2, double sD, double sI, 
     const double kappa = 1.0 - b * wn;
     const double ik = recip<double>(kappa);
     const double f = kq * iD * ik * ik * ik;
-    const double cu = (1.0 - b * b) * iD + e * wn * INV_C;
-    const double cd = kappa * INV_C;
-    return f * ((pin - b * pij) * cu - e * pij * cd);
+    const double q = pij - pin * wn;
+    return f * ((pin - b * pij) * (1.0 - b * b) * iD - e * q * INV_C);
 }
 
 template <bool MOVING>
@@ -388,31 +388,37 @@ __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, 
     return 0.0;
 }
 
-// FP32 part of one charge's field in the mixed form: with n = R/|R|,
-// beta = v/c and kappa = 1 - n.beta, the field of Eq. (E) less its static
-// monopole term kq R / |R|^3,
-//   f(R) c1 - beta (1 - beta^2) / (kappa^3 |R|^2) + radiation term,
-//   c1 = (1 - beta^2) / kappa^3 - 1 = (n.beta (1 + kappa + kappa^2) - beta^2) / kappa^3,
-// projected on p_i, per unit kq, in lengths scaled by 1/Ls (x = R / Ls,
-// ga = acceleration Ls / c^2).
-__device__ __forceinline__ float dynamic_terms_f32(const float x[3], const float be[3], const float ga[3],
-                                                  const float pi[3])
+// Velocity and radiation part of one charge's field in the mixed form: with
+// n = R/|R|, beta = v/c and kappa = 1 - n.beta, the field of Eq. (E) less its
+// static monopole term kq R / |R|^3, projected on p_i, per unit kq, in lengths
+// scaled by 1/Ls (ix = Ls / |R|, ga = acceleration Ls / c^2).  The charge
+// moves along p_j (beta = be p_j, acceleration ga p_j), so with P = p_i . n,
+// X = n . p_j, pij = p_i . p_j and q = pij - P X (p_i . the part of p_j across
+// n) it is
+//   ix^2 be kappa^-3 [P (X (1 + kappa + kappa^2) - be) - pij (1 - be^2)]
+//     - ga q ix kappa^-3,
+// where the radiation term's beta parts have cancelled exactly.  Its first
+// order in beta, lead = ix^2 be (3 P X - pij) - ga q ix, carries the
+// near-field coupling in the phase of the velocity: for close pairs the
+// reactive coupling is 1e4 times the dissipative one, so FP32 rounding there
+// moves the collective rates by 1e-3 gamma_0.  lead is FP64 (dynamic_lead);
+// the rest, which is smaller by a factor of order beta (dynamic_corr_f32:
+// (kappa^-3 - 1) = be X (1 + kappa + kappa^2) kappa^-3 taken out exactly), is
+// FP32.
+__device__ __forceinline__ double dynamic_lead(double P, double X, double ix, double be, double ga, double pij,
+                                               double q)
 {
-    const float ix = __builtin_amdgcn_rsqf(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-    float n[3];
-    for (int c = 0; c < 3; ++c) n[c] = x[c] * ix;
-    const float nb = n[0] * be[0] + n[1] * be[1] + n[2] * be[2];
-    const float kap = 1.0f - nb;
-    const float bb = be[0] * be[0] + be[1] * be[1] + be[2] * be[2];
+    return be * ix * ix * (3.0 * P * X - pij) - ga * q * ix;
+}
+__device__ __forceinline__ float dynamic_corr_f32(float P, float X, float ix, float be, float ga, float pij, float q)
+{
+    const float kap = 1.0f - be * X;
+    const float s3 = 1.0f + kap + kap * kap;
     const float ik = __builtin_amdgcn_rcpf(kap);
     const float ik3 = ik * ik * ik;
-    const float c1 = (nb * (1.0f + kap + kap * kap) - bb) * ik3 * ix * ix * ix;
-    const float cb = (1.0f - bb) * ik3 * ix * ix;
-    const float nd = n[0] * ga[0] + n[1] * ga[1] + n[2] * ga[2];
-    const float cr = ik3 * ix;
-    float r = 0.0f;
-    for (int c = 0; c < 3; ++c) r += pi[c] * (x[c] * c1 - be[c] * cb + ((n[c] - be[c]) * nd - ga[c] * kap) * cr);
-    return r;
+    const float A = P * X * s3 - P * be - pij + pij * be * be;
+    return be * be * ix * ix * (X * s3 * ik3 * A - P * X * X * (kap + 2.0f) - P + pij * be) -
+           ga * q * ix * be * X * s3 * ik3;
 }
 
 // Mixed form of the drive of one source dipole at a target (both charges: +q
@@ -429,11 +435,12 @@ __device__ __forceinline__ float dynamic_terms_f32(const float x[3], const float
 //      |b|^3 - |a|^3 = (|b| - |a|) (|a|^2 + |a| |b| + |b|^2),
 //      |b| - |a| = -D . (a + b) / (|a| + |b|),
 //    in which nothing cancels;
-//  - each charge's velocity and radiation terms (dynamic_terms_f32) in FP32.
-//    Against the static term they are of relative size omega |R| / c and its
-//    square in the near field, and they have the same sign for both charges
-//    (their q beta and q beta_dot agree), so their rounding stays at that size
-//    times 2^-24.
+//  - each charge's velocity and radiation terms, first order in beta in FP64
+//    (dynamic_lead) and the remainder in FP32 (dynamic_corr_f32).  Against
+//    the static term they are of relative size omega |R| / c and its square
+//    in the near field, and they have the same sign for both charges (their
+//    q beta and q beta_dot agree), so the FP32 remainder's rounding stays at
+//    its own size times 2^-24.
 // Lengths are scaled by 1/|Delta| so that FP32 stays in range at nanometre
 // separations.  A moving source's origin velocity is common to both charges,
 // so its velocity terms would cancel: moving sources take the FP64 field of
@@ -466,37 +473,33 @@ __device__ double dipole_drive_mixed(const Hist &H, const DipLds &Si, const DipL
     charge_fixed(H, j, Sj.d0, nstep, base, L2, L, sD, Sj.cfp, max_iter, g, hp, err);
     charge_fixed(H, j, Sj.d0, nstep, base, L2, L, sD, Sj.cfm, max_iter, g, hm, err);
     const double rp = Sj.cfp * hp[0] * iL, rm = Sj.cfm * hm[0] * iL;   // scaled offsets
+    // a = u - rp p_j and b = u - rm p_j (u = Delta / |Delta|) enter only through
+    // u . p_j, p_i . u, p_i . p_j and their own lengths
+    const double cup = sD * iL;
+    const double ciu = (dl[0] * Si.px + dl[1] * Si.py + dl[2] * Si.pz) * iL;
+    const double pij = Si.px * p[0] + Si.py * p[1] + Si.pz * p[2];
     // static monopole difference (FP64)
-    double a[3], b[3], sab[3];
-    for (int c = 0; c < 3; ++c) {
-        const double u = dl[c] * iL;
-        a[c] = u - rp * p[c];
-        b[c] = u - rm * p[c];
-        sab[c] = a[c] + b[c];
-    }
     const double dsc = rm - rp;                     // D = dsc p_j (scaled)
     double ra, ia, rb, ib;
-    root_rsqrt<true>(a[0] * a[0] + a[1] * a[1] + a[2] * a[2], ra, ia);
-    root_rsqrt<true>(b[0] * b[0] + b[1] * b[1] + b[2] * b[2], rb, ib);
+    root_rsqrt<true>(fma(rp, rp - 2.0 * cup, 1.0), ra, ia);
+    root_rsqrt<true>(fma(rm, rm - 2.0 * cup, 1.0), rb, ib);
     const double ia3 = ia * ia * ia, ib3 = ib * ib * ib;
-    const double dab = -dsc * (p[0] * sab[0] + p[1] * sab[1] + p[2] * sab[2]) * recip<double>(ra + rb);
+    const double dab = -dsc * (2.0 * cup - (rp + rm)) * recip<double>(ra + rb);   // |b| - |a|
     const double c3 = dab * (ra * ra + ra * rb + rb * rb) * ia3 * ib3;
-    const double pip = Si.px * p[0] + Si.py * p[1] + Si.pz * p[2];
-    const double st = dsc * ia3 * pip + c3 * (Si.px * b[0] + Si.py * b[1] + Si.pz * b[2]);
-    // velocity and radiation terms of both charges (FP32)
-    const float pi[3] = {(float)Si.px, (float)Si.py, (float)Si.pz};
+    const double st = dsc * ia3 * pij + c3 * (ciu - rm * pij);
+    // velocity and radiation terms of both charges: first order in beta in
+    // FP64, the rest in FP32
     const double gsc = INV_C * INV_C * L;           // acceleration -> beta_dot L / c
-    float xa[3], xb[3], bp[3], bm[3], gp[3], gm[3];
-    for (int c = 0; c < 3; ++c) {
-        xa[c] = (float)a[c];
-        xb[c] = (float)b[c];
-        bp[c] = (float)(Sj.cfp * hp[1] * INV_C * p[c]);
-        bm[c] = (float)(Sj.cfm * hm[1] * INV_C * p[c]);
-        gp[c] = (float)(Sj.cfp * hp[2] * gsc * p[c]);
-        gm[c] = (float)(Sj.cfm * hm[2] * gsc * p[c]);
-    }
-    const float rest = dynamic_terms_f32(xa, bp, gp, pi) - dynamic_terms_f32(xb, bm, gm, pi);
-    return kq * iL * iL * (st + (double)rest);
+    const double Pa = (ciu - rp * pij) * ia, Xa = (cup - rp) * ia, Pb = (ciu - rm * pij) * ib, Xb = (cup - rm) * ib;
+    const double qa = pij - Pa * Xa, qb = pij - Pb * Xb;
+    const double bea = Sj.cfp * hp[1] * INV_C, gaa = Sj.cfp * hp[2] * gsc;
+    const double beb = Sj.cfm * hm[1] * INV_C, gab = Sj.cfm * hm[2] * gsc;
+    const float fpij = (float)pij;
+    const float corr = dynamic_corr_f32((float)Pa, (float)Xa, (float)ia, (float)bea, (float)gaa, fpij, (float)qa) -
+                       dynamic_corr_f32((float)Pb, (float)Xb, (float)ib, (float)beb, (float)gab, fpij, (float)qb);
+    const double rest = dynamic_lead(Pa, Xa, ia, bea, gaa, pij, qa) - dynamic_lead(Pb, Xb, ib, beb, gab, pij, qb) +
+                        (double)corr;
+    return kq * iL * iL * (st + rest);
 }
 
 // Drive contribution of work unit w of source j: in FP64 one unit per charge
