@@ -287,10 +287,14 @@ __global__ void hist_from_state_kernel(const double *__restrict__ state, const i
 // per (snapshot, point); instances are laid out in the history by the global
 // dipole index (one shared [ring][n_dip][3] array).  The lanes of a workgroup
 // see a source at nearby retarded times, so their sample cotangents are first
-// summed in LDS slots relative to the workgroup's earliest sample, then added to
-// hbar with one device atomic per touched slot (a lane beyond the slots adds
-// its own directly).
-constexpr int DET_SLOTS = 64;
+// summed in LDS, then added to hbar with one device atomic per touched slot.
+// Sources are taken DET_JG at a time, each with its own window of DET_SJ
+// samples, whose start is the workgroup's earliest possible sample of that
+// source from geometry (floor(t / dt - L / (c dt)) - 2, minimised over the
+// lanes; the charges sit far less than 2 c dt from their origins).  So the
+// sources' reverses need no barrier between them: three per group of sources
+// (a lane whose sample falls outside its window adds it to hbar directly).
+constexpr int DET_JG = 32, DET_SJ = 48;
 
 __global__ __launch_bounds__(256) void detector_vjp_kernel(const DipDev *__restrict__ dev, int n_dip,
                                                            const double *__restrict__ hist, double *__restrict__ hbar,
@@ -301,8 +305,8 @@ __global__ __launch_bounds__(256) void detector_vjp_kernel(const DipDev *__restr
                                                            int max_iter, uint32_t *__restrict__ d_err)
 {
     __shared__ double red[4];
-    __shared__ double slot[DET_SLOTS * 3];
-    __shared__ int64_t kmin_w[4];
+    __shared__ double slot[DET_JG * DET_SJ * 3];
+    __shared__ int kb_s[2][DET_JG];                 // window starts, by group parity
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t gid = (int64_t)blockIdx.x * 256 + tid;
     const bool live = gid < npts * n_snap;
@@ -312,7 +316,8 @@ __global__ __launch_bounds__(256) void detector_vjp_kernel(const DipDev *__restr
     const double base = times[ks] / dt;
     Hist H{hist, n_dip, ring - 1, dt, 1.0 / dt};
     uint32_t err = 0u;
-    for (int t = tid; t < DET_SLOTS * 3; t += 256) slot[t] = 0.0;
+    for (int t = tid; t < DET_JG * DET_SJ * 3; t += 256) slot[t] = 0.0;
+    for (int t = tid; t < 2 * DET_JG; t += 256) kb_s[t / DET_JG][t % DET_JG] = INT_MAX;
     double E[3] = {0.0, 0.0, 0.0};
     if (live) {
         for (int j = 0; j < n_dip; ++j) {
@@ -338,62 +343,68 @@ __global__ __launch_bounds__(256) void detector_vjp_kernel(const DipDev *__restr
     if (lane == 0) red[wave] = jv;
     __syncthreads();
     if (tid == 0) Jpart[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
-    // cotangent of E and its scatter
+    // cotangent of E and its scatter, DET_JG sources at a time
     const double Eb[3] = {2.0 * E[0] / n_norm, 2.0 * E[1] / n_norm, 2.0 * E[2] / n_norm};
-    for (int j = 0; j < n_dip; ++j) {
-        const DipDev &Dj = dev[j];
-        const DipLds Sj = dip_lds(Dj);
-        double Rj[3] = {0.0, 0.0, 0.0};
-        for (int w = 0; w < 2; ++w) {
-            HistBar hb;
-            hb.region = 0;
-            hb.k = 0;
-            if (live) {
-                const double cf = w ? Sj.cfm : Sj.cfp;
-                const double kq = (w ? -Dj.q : Dj.q) * K_COUL;
-                Kin k;
-                HistEval e;
-                pair_solve(H, x, Sj, j, cf, nstep, base, max_iter, k, e, err);
-                double Db[3];
-                pair_vjp(k, e, Sj, cf, kq, Eb, Db, hb);
-                // Delta = x - R_j: the source position gets -Db
-                Rj[0] -= Db[0];
-                Rj[1] -= Db[1];
-                Rj[2] -= Db[2];
+    for (int j0 = 0, par = 0; j0 < n_dip; j0 += DET_JG, par ^= 1) {
+        const int jn = min(DET_JG, n_dip - j0);
+        int *kb = kb_s[par];
+        if (live)
+            for (int jl = 0; jl < jn; ++jl) {
+                const DipDev &Dj = dev[j0 + jl];
+                const double dx = x[0] - Dj.origin[0], dy = x[1] - Dj.origin[1], dz = x[2] - Dj.origin[2];
+                const double L = sqrt(dx * dx + dy * dy + dz * dz);
+                atomicMin(&kb[jl], (int)floor(base - L * INV_C * H.inv_dt) - 2);
             }
-            // earliest sample this workgroup touches for (j, w)
-            int64_t km = hb.region ? hb.k : INT64_MAX;
-            for (int off = 32; off > 0; off >>= 1) km = min(km, (int64_t)__shfl_xor(km, off, 64));
-            if (lane == 0) kmin_w[wave] = km;
-            __syncthreads();
-            const int64_t kb = min(min(kmin_w[0], kmin_w[1]), min(kmin_w[2], kmin_w[3]));
-            if (kb != INT64_MAX) {
-                if (hb.region) {
-                    const int64_t sl = hb.k - kb;
-                    if (sl + 1 < DET_SLOTS) {
-                        for (int c = 0; c < 3; ++c) atomicAdd(&slot[sl * 3 + c], hb.c0[c]);
+        // the other parity's starts are free again: the previous group's flush is done
+        for (int t = tid; t < DET_JG; t += 256) kb_s[par ^ 1][t] = INT_MAX;
+        __syncthreads();
+        for (int jl = 0; jl < jn; ++jl) {
+            const int j = j0 + jl;
+            const DipDev &Dj = dev[j];
+            const DipLds Sj = dip_lds(Dj);
+            const int64_t kbj = kb[jl];
+            double Rj[3] = {0.0, 0.0, 0.0};
+            if (live)
+                for (int w = 0; w < 2; ++w) {
+                    const double cf = w ? Sj.cfm : Sj.cfp;
+                    const double kq = (w ? -Dj.q : Dj.q) * K_COUL;
+                    Kin k;
+                    HistEval e;
+                    pair_solve(H, x, Sj, j, cf, nstep, base, max_iter, k, e, err);
+                    double Db[3];
+                    HistBar hb;
+                    pair_vjp(k, e, Sj, cf, kq, Eb, Db, hb);
+                    // Delta = x - R_j: the source position gets -Db
+                    Rj[0] -= Db[0];
+                    Rj[1] -= Db[1];
+                    Rj[2] -= Db[2];
+                    if (hb.region == 0) continue;
+                    const int64_t sl = hb.k - kbj;
+                    if (sl >= 0 && sl + 1 < DET_SJ) {
+                        double *r = slot + ((int64_t)jl * DET_SJ + sl) * 3;
+                        for (int c = 0; c < 3; ++c) atomicAdd(r + c, hb.c0[c]);
                         if (hb.region == 1)
-                            for (int c = 0; c < 3; ++c) atomicAdd(&slot[(sl + 1) * 3 + c], hb.c1[c]);
+                            for (int c = 0; c < 3; ++c) atomicAdd(r + 3 + c, hb.c1[c]);
                     } else {
                         scatter_global(H, j, hb, hbar);
                     }
                 }
-                __syncthreads();
-                for (int t = tid; t < DET_SLOTS * 3; t += 256) {
-                    const double v = slot[t];
-                    if (v != 0.0) {
-                        atomicAdd(hbar + ((int64_t)((kb + t / 3) & H.mask) * H.n + j) * 3 + t % 3, v);
-                        slot[t] = 0.0;
-                    }
-                }
+            for (int c = 0; c < 3; ++c) {
+                double v = Rj[c];
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                if (lane == 0 && v != 0.0) atomicAdd(&Rbar[j * 3 + c], v);
             }
-            __syncthreads();
         }
-        for (int c = 0; c < 3; ++c) {
-            double v = Rj[c];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (lane == 0 && v != 0.0) atomicAdd(&Rbar[j * 3 + c], v);
+        __syncthreads();
+        for (int t = tid; t < jn * DET_SJ * 3; t += 256) {
+            const double v = slot[t];
+            if (v != 0.0) {
+                const int jl = t / (DET_SJ * 3), r = t - jl * DET_SJ * 3;
+                atomicAdd(hbar + ((int64_t)(((int64_t)kb[jl] + r / 3) & H.mask) * H.n + j0 + jl) * 3 + r % 3, v);
+                slot[t] = 0.0;
+            }
         }
+        __syncthreads();
     }
     if (err) atomicOr(d_err, err);
 }
