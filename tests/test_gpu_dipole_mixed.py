@@ -96,7 +96,8 @@ def test_mixed_moving_parity():
 
 def test_mixed_gamma_domega_parity():
     """Collective rates and shift of 8 pairs (8,000 steps) from the mixed run's moments
-    against those of the oracle's moments: within 1e-3."""
+    against those of the oracle's moments: within 1e-4 (the first-order velocity terms are
+    FP64, so the mixed rates follow the FP64 ones)."""
     from paper_2107_12437_amd import lw
     w = I.workload_dipole_pairs(n_inst=8, steps=8000)
     got = gpu_run(w, "extrapolate", stride=2, precision="mixed")
@@ -109,7 +110,7 @@ def test_mixed_gamma_domega_parity():
         r = X.pair_modes(ref["d"][:, 2 * k], ref["d"][:, 2 * k + 1], w["dt"], 2, w0, skips[k])
         for jj, key in ((0, "gamma_plus"), (1, "gamma_minus"), (4, "delta_omega")):
             scale = max(abs(r[key]), g0)
-            assert abs(modes[k, jj] - r[key]) <= 1e-3 * scale, (k, key, modes[k, jj], r[key])
+            assert abs(modes[k, jj] - r[key]) <= 1e-4 * scale, (k, key, modes[k, jj], r[key])
 
 
 def test_mixed_matches_fp64_on_the_cluster_benchmark():
