@@ -290,9 +290,13 @@ lw_status lw_dipole_run_state(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip
  *                the forward run keeps its run state (as lw_dipole_run_state)
  *                every K steps, and the backward sweep recomputes each segment
  *                of K steps from its state, last segment first, so the device
- *                holds the states and a window of K steps plus the retarded
- *                look-back instead of the whole run.  Costs one more forward
- *                run; the result equals the whole-history one to rounding.
+ *                holds the states and two windows of K steps plus the
+ *                retarded look-back instead of the whole run.  A second stream
+ *                of the context recomputes the next segment while the current
+ *                one is swept, so the extra forward run mostly overlaps.  The
+ *                result equals the whole-history one to rounding.  Negative:
+ *                LW_E_INVALID; so is a K whose window would exceed 2^26 steps.
+ * Moving origins and LW_MIXED are rejected (LW_E_INVALID).
  *   d_det_pts    device FP64 SoA [3][n_det]
  *   h_snap_times host FP64 [n_snap], each in [0, steps dt]
  *   d_grad_pos   device FP64 [n_dip][3]: dJ/d origin, overwritten
