@@ -106,6 +106,8 @@ __device__ __forceinline__ void seg_eval(const Hist &H, int j, const Seg &g, dou
 
 // Retarded field of charge (cf, kq) of source j at point x and time base*dt
 // (samples up to nstep); fills the kinematics and the history evaluation.
+// tau_init (> 0) starts Newton; tau_out receives Newton's root and is left
+// alone when the closed form settles the pair.
 __device__ void pair_solve(const Hist &H, const double x[3], const DipLds &Sj, int j, double cf, int64_t nstep,
                            double base, int max_iter, Kin &k, HistEval &e, uint32_t &err, double tau_init = 0.0,
                            double *tau_out = nullptr)
@@ -117,7 +119,7 @@ __device__ void pair_solve(const Hist &H, const double x[3], const DipLds &Sj, i
     Bracket b(0.0, 2.0 * L * INV_C);
     double tau = L * INV_C;
     const double tol = 4.0 * 2.220446049250313e-16;
-    bool ok = false;
+    bool ok = false, closed = false;
     // the closed form on the interpolated history (retarded_seg) from the
     // segment of tau = L/c (the charge sits within |rho| << L of its origin, so
     // that is the root's segment or a neighbour); Newton past the newest
@@ -134,6 +136,7 @@ __device__ void pair_solve(const Hist &H, const double x[3], const DipLds &Sj, i
                 tau = tc;
                 seg_eval(H, j, g, Sj.d0, nstep, base - tau * H.inv_dt, e);
                 ok = true;
+                closed = true;
             }
         }
     }
@@ -167,7 +170,7 @@ __device__ void pair_solve(const Hist &H, const double x[3], const DipLds &Sj, i
         }
     }
     if (!ok) err |= ERR_NOCONV;
-    if (tau_out) *tau_out = tau;
+    if (tau_out && !closed) *tau_out = tau;        // Newton's root, the next step's start
     const double rho = cf * e.d;
     k.R[0] = dx - rho * Sj.px;
     k.R[1] = dy - rho * Sj.py;
@@ -621,21 +624,42 @@ __global__ __launch_bounds__(BLOCK) void adj_step_kernel(const DipDev *__restric
         const double tw = taup[idx];
         Kin kn;
         HistEval e;
-        double tau;
+        double tau = tw;
         pair_solve(H, x, Sj, j, cf, nstep, (double)nstep + (th ? 1.0 : 0.5), max_iter, kn, e, err, tw, &tau);
-        taup[idx] = tau;
+        if (tau != tw) taup[idx] = tau;     // (only Newton reads it; the closed form leaves it)
         pair_vjp(kn, e, Sj, cf, kq, Eu, Du, hu);
     };
+    // step 1's first dipole: its loads go out before the pair work, which does
+    // not depend on them
+    double pb[3] = {0.0, 0.0, 0.0}, py[3] = {0.0, 0.0, 0.0};
+    if (tid < n) {
+        const int gq = i0 + tid;
+        const double *hb = hbar + ((int64_t)((nstep + 1) & mask) * n_dip + gq) * 3;
+        pb[0] = load_agent(hb);
+        pb[1] = load_agent(hb + 1);
+        pb[2] = load_agent(hb + 2);
+        py[0] = Ain.yd[gq];
+        py[1] = Ain.yv[gq];
+        py[2] = Ain.ec[gq];
+    }
     if (m2 < 2 * M) solve_unit(m2);
     // 1. the instance's drive cotangents; dipole j's S_n
     for (int ql = tid; ql < n; ql += BLOCK) {
         const int gq = i0 + ql;
         const DipDev &P = dev[gq];
-        const double *hb = hbar + ((int64_t)((nstep + 1) & mask) * n_dip + gq) * 3;
-        const double bd = load_agent(hb), bv = load_agent(hb + 1), ba = load_agent(hb + 2);
-        double yd = Ain.yd[gq] + (bd - P.omega0 * P.omega0 * ba);
-        double yv = Ain.yv[gq] + (bv - P.gamma0 * ba);
-        const double ext = Ain.ec[gq] + P.f * ba;
+        if (ql != tid) {
+            const double *hb = hbar + ((int64_t)((nstep + 1) & mask) * n_dip + gq) * 3;
+            pb[0] = load_agent(hb);
+            pb[1] = load_agent(hb + 1);
+            pb[2] = load_agent(hb + 2);
+            py[0] = Ain.yd[gq];
+            py[1] = Ain.yv[gq];
+            py[2] = Ain.ec[gq];
+        }
+        const double bd = pb[0], bv = pb[1], ba = pb[2];
+        double yd = py[0] + (bd - P.omega0 * P.omega0 * ba);
+        double yv = py[1] + (bv - P.gamma0 * ba);
+        const double ext = py[2] + P.f * ba;
         double em, ee, ec;
         rk4_transpose(P, dt, yd, yv, ext, em, ee, ec);
         s_es[0][ql] = em;
