@@ -666,8 +666,8 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
             Wab[i] = wa;
             Wra[i] = wr;
             const int64_t rel = nstep + 1 - n0;
-            if (rel % out.stride == 0)
-                put_row(out, rel / out.stride, i0 + i, dn, vn, run_energy(w2, f, dn, vn), Ee, wa, wr);
+            const int64_t row = out_row(rel, out.stride);
+            if (row >= 0) put_row(out, row, i0 + i, dn, vn, run_energy(w2, f, dn, vn), Ee, wa, wr);
         }
         if (err) atomicOr(&s_err, err);
         __syncthreads();
@@ -821,7 +821,8 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             W[2 * gi] = wa;
             W[2 * gi + 1] = wr;
             const int64_t rel = nstep + 1 - step_ctr[1];       // steps since the run's first
-            if (rel % out.stride == 0) put_row(out, rel / out.stride, gi, dn, vn, run_energy(w2, f, dn, vn), Ee, wa, wr);
+            const int64_t row = out_row(rel, out.stride);
+            if (row >= 0) put_row(out, row, gi, dn, vn, run_energy(w2, f, dn, vn), Ee, wa, wr);
         }
     }
     if (err) atomicOr(d_err, err);

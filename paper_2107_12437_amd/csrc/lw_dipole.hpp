@@ -190,6 +190,15 @@ __device__ __forceinline__ double run_energy(double w2, double f, double d, doub
     return fma(w2 * d, d, v * v) * (0.5 / f);
 }
 
+// Output row of the state after `rel` steps of the call, or -1 when the
+// stride skips it (stride 1, the usual case, needs no 64-bit division, which
+// has no hardware instruction and would sit on each step's critical path).
+__device__ __forceinline__ int64_t out_row(int64_t rel, int64_t stride)
+{
+    if (stride == 1) return rel;
+    return rel % stride == 0 ? rel / stride : -1;
+}
+
 // Writes row `row` of the outputs for dipole gi.
 __device__ __forceinline__ void put_row(const RunOut &o, int64_t row, int gi, double d, double v, double E, double Ed,
                                         double wa, double wr)
