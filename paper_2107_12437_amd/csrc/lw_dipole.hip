@@ -528,18 +528,20 @@ __device__ void drive_all(const Hist &H, const DipLds *S, const double *qv, int 
     constexpr int U = units_per_source<MIXED>();
     const int M = U * (n - 1);                    // work units per (target, stage)
     const int G = nth * n;                        // (target, stage) groups
-    int Lg = 1;
-    while (Lg < M && Lg < 64) Lg <<= 1;
-    while (Lg > 1 && Lg * G > BLOCK) Lg >>= 1;
-    const int per_pass = BLOCK / Lg;
-    const int npass = (G + per_pass - 1) / per_pass;
+    // lanes per group Lg = 2^lg; the index arithmetic uses shifts (integer
+    // division has no hardware instruction), and a group's stage is 0 or 1
+    int lg = 0;
+    while ((1 << lg) < M && lg < 6) ++lg;
+    while (lg > 0 && (G << lg) > BLOCK) --lg;
+    const int Lg = 1 << lg;
+    const int per_pass = BLOCK >> lg;
     const int tid = threadIdx.x;
-    const int sub = tid % Lg;
-    for (int pass = 0; pass < npass; ++pass) {
-        const int g = pass * per_pass + tid / Lg;
+    const int sub = tid & (Lg - 1);
+    for (int g0 = 0; g0 < G; g0 += per_pass) {
+        const int g = g0 + (tid >> lg);
         double acc = 0.0;
         if (g < G && M > 0) {
-            const int th = g / n, i = g % n;
+            const int th = g >= n ? 1 : 0, i = g - th * n;
             for (int m = sub; m < M; m += Lg) {
                 const int jj = m / U, w = m % U;
                 const int j = jj < i ? jj : jj + 1;
@@ -741,7 +743,7 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
     }
     double acc0 = 0.0, acc1 = 0.0;                   // stage t_n + dt/2 (or t = 0), stage t_n + dt
     for (int m = tid; m < nth * M; m += BLOCK) {
-        const int th = m / M, mm = m - th * M;
+        const int th = m >= M ? 1 : 0, mm = m - th * M;    // (nth <= 2 stages)
         const int jj = mm / U, w = mm % U;
         const int j = jj < i ? jj : jj + 1;
         const DipLds Sj = soa_lds(soa, out.n_dip, (uint32_t)(i0 + j));

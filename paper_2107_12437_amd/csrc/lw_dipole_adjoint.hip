@@ -605,7 +605,7 @@ __global__ __launch_bounds__(BLOCK) void adj_step_kernel(const DipDev *__restric
     int64_t idx = 0;
     double rb[3] = {0.0, 0.0, 0.0};     // the pair's separation cotangent so far, read early
     auto solve_unit = [&](int mm2) {
-        th = mm2 / M;
+        th = mm2 >= M ? 1 : 0;                      // (2 M units: two stages)
         const int m = mm2 - th * M;
         const int ii = m >> 1, w = m & 1;
         il = ii < jl ? ii : ii + 1;                   // target (local index)
