@@ -58,6 +58,7 @@ __global__ void dipole_prep_kernel(const lw_dipole *__restrict__ in, int n, DipD
     o.mw = moves ? D.motion_omega : 0.0;
     o.mph = moves ? D.motion_phase : 0.0;
     o.mspeed = moves ? fabs(D.motion_omega) * am : 0.0;
+    o.ehalf = 0.5 / o.f;
     dev[i] = o;
     const double f[SF_COUNT] = {o.origin[0], o.origin[1], o.origin[2], o.axis[0], o.axis[1], o.axis[2], o.cfp,
                                 o.cfm,       o.d0,        o.q,         o.mamp[0], o.mamp[1], o.mamp[2], o.mw, o.mph};
@@ -572,15 +573,15 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
     if (n <= 0) return;
 
     // LDS layout: constants, q, Ecur, Emid/Eend, absorbed and radiated energy,
-    // oscillator constants (w0^2, gamma0, f, vfac, origin speed), (ring)
+    // oscillator constants (w0^2, gamma0, f, vfac, origin speed, 0.5 / f), (ring)
     DipLds *S = (DipLds *)lds;
     double *qv = (double *)(S + n);
     double *Ecur = qv + n;
     double *Enew = Ecur + n;                    // [2][n]: mid, end
     double *Wab = Enew + 2 * n;
     double *Wra = Wab + n;
-    double *Kc = Wra + n;                       // [5][n]
-    double *ring_lds = Kc + 5 * n;
+    double *Kc = Wra + n;                       // [6][n]
+    double *ring_lds = Kc + 6 * n;
     double *ringp = RING_LDS ? ring_lds : ring_global + ring_off[blockIdx.x];
     __shared__ uint32_t s_err;
 
@@ -593,6 +594,7 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
         Kc[2 * n + j] = D.f;
         Kc[3 * n + j] = D.vfac;
         Kc[4 * n + j] = D.mspeed;
+        Kc[5 * n + j] = D.ehalf;
     }
     if (tid == 0) s_err = 0u;
     __syncthreads();
@@ -630,7 +632,7 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
             const int gi = i0 + i;
             Wab[i] = 0.0;
             Wra[i] = 0.0;
-            put_row(out, 0, gi, D.d0, 0.0, run_energy(D.omega0 * D.omega0, D.f, D.d0, 0.0), Ecur[i], 0.0, 0.0);
+            put_row(out, 0, gi, D.d0, 0.0, run_energy(D.omega0 * D.omega0, D.ehalf, D.d0, 0.0), Ecur[i], 0.0, 0.0);
         }
     }
     __syncthreads();
@@ -669,7 +671,7 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
             Wra[i] = wr;
             const int64_t rel = nstep + 1 - n0;
             const int64_t row = out_row(rel, out.stride);
-            if (row >= 0) put_row(out, row, i0 + i, dn, vn, run_energy(w2, f, dn, vn), Ee, wa, wr);
+            if (row >= 0) put_row(out, row, i0 + i, dn, vn, run_energy(w2, Kc[5 * n + i], dn, vn), Ee, wa, wr);
         }
         if (err) atomicOr(&s_err, err);
         __syncthreads();
@@ -780,7 +782,7 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             Ecur[gi] = E0;
             W[2 * gi] = 0.0;
             W[2 * gi + 1] = 0.0;
-            put_row(out, 0, gi, D.d0, 0.0, run_energy(w2, f, D.d0, 0.0), E0, 0.0, 0.0);
+            put_row(out, 0, gi, D.d0, 0.0, run_energy(w2, D.ehalf, D.d0, 0.0), E0, 0.0, 0.0);
         } else {
             const double Em = s0, Ee = s1;
             double y0, y1, a0, Ec, W0, W1;
@@ -824,7 +826,7 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             W[2 * gi + 1] = wr;
             const int64_t rel = nstep + 1 - step_ctr[1];       // steps since the run's first
             const int64_t row = out_row(rel, out.stride);
-            if (row >= 0) put_row(out, row, gi, dn, vn, run_energy(w2, f, dn, vn), Ee, wa, wr);
+            if (row >= 0) put_row(out, row, gi, dn, vn, run_energy(w2, D.ehalf, dn, vn), Ee, wa, wr);
         }
     }
     if (err) atomicOr(d_err, err);
@@ -860,7 +862,7 @@ __global__ void state_rows_kernel(const DipDev *__restrict__ dev, const int32_t 
     const double *h = state + state_ring_off(a0, ring) + ((int64_t)(n0 & (ring - 1)) * n + (gi - a0)) * 3;
     const DipDev &D = dev[gi];
     const int64_t ow = state_w_off(out.n_dip, ring);
-    put_row(out, 0, gi, h[0], h[1], run_energy(D.omega0 * D.omega0, D.f, h[0], h[1]),
+    put_row(out, 0, gi, h[0], h[1], run_energy(D.omega0 * D.omega0, D.ehalf, h[0], h[1]),
             state[state_ecur_off(out.n_dip, ring) + gi], state[ow + 2 * gi], state[ow + 2 * gi + 1]);
 }
 
@@ -957,7 +959,7 @@ hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const 
 
 int ring_lds_bytes(int n, int ring)
 {
-    return (int)(sizeof(DipLds) * n + sizeof(double) * 11 * n + sizeof(double) * 3 * (size_t)ring * n);
+    return (int)(sizeof(DipLds) * n + sizeof(double) * 12 * n + sizeof(double) * 3 * (size_t)ring * n);
 }
 
 template <int BLOCK>

@@ -21,6 +21,7 @@ struct DipDev {
     double mamp[3];  // origin motion: origin + mamp cos(mw t + mph) (Sec. 4.3); mw = 0 when fixed
     double mw, mph;
     double mspeed;   // largest origin speed, mw |mamp|
+    double ehalf;    // 0.5 / f, the factor of the energy (run_energy)
 };
 
 // Per-dipole constants of the instance, staged in LDS.
@@ -185,9 +186,11 @@ constexpr double K_LARMOR = 1.0 / (6.0 * PI * EPS0 * C_LIGHT * C_LIGHT * C_LIGHT
 
 // Energy of Eq. (dipoleE) from (d, d_dot): (omega0^2 d^2 + d_dot^2) / (2 f),
 // f = q^2 / m, in one fixed order of operations wherever it is evaluated.
-__device__ __forceinline__ double run_energy(double w2, double f, double d, double v)
+// ehalf = 0.5 / f is the dipole's constant (DipDev::ehalf), so that no
+// division sits on a step's critical path.
+__device__ __forceinline__ double run_energy(double w2, double ehalf, double d, double v)
 {
-    return fma(w2 * d, d, v * v) * (0.5 / f);
+    return fma(w2 * d, d, v * v) * ehalf;
 }
 
 // Output row of the state after `rel` steps of the call, or -1 when the
