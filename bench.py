@@ -155,8 +155,8 @@ def main():
     ap.add_argument("--cpu-sample-points", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dipole", action="store_true")
-    ap.add_argument("--cluster-steps", type=int, default=500,
-                    help="steps of the uneven-cluster workload to time")
+    ap.add_argument("--cluster-steps", type=int, default=50000,
+                    help="steps of the uneven-cluster workload to time (its full run: 50,000)")
     ap.add_argument("--grid-only", action="store_true",
                     help="time only the mixed grid step (for profiler runs)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
@@ -324,9 +324,10 @@ def main():
         cw = I.workload_clusters(steps=args.cluster_steps)
         n_c = len(cw["dipoles"]["omega0"])
         clusters = {"workload": cw["name"], "dipoles": n_c, "steps": cw["steps"],
-                    "note": "the uneven-cluster workload runs 50,000 steps; this line times a prefix of it. "
-                            "mixed: FP32 velocity and radiation terms of each source dipole, FP64 static "
-                            "near-field term, retarded times, state and sums"}
+                    "note": ("the whole 50,000-step run, " if cw["steps"] >= 50000 else
+                             "the uneven-cluster workload runs 50,000 steps; this line times a prefix of it, ") +
+                            "moments every 10th step. mixed: FP32 velocity and radiation terms of each source "
+                            "dipole, FP64 static near-field term, retarded times, state and sums"}
         for prec in ("fp64", "mixed"):
             # the warm-up call tunes the stepped-path threshold for this shape class
             lw.dipole_run(cw["dipoles"], cw["inst_off"], cw["dt"], 10, out_stride=10, precision=prec,
