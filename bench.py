@@ -316,6 +316,29 @@ def main():
         dip = {"workload": pw["name"], "dipole_steps_per_s": n_dip * pw["steps"] / dsec,
                "ms": round(dsec * 1e3, 3), "dtype": "f64"}
         log(f"[bench] dipoles: {dsec * 1e3:.2f} ms, {dip['dipole_steps_per_s']:.3e} dipole-steps/s")
+        # the timed run's collective rates (host extraction) against the Green's-function
+        # rates of App. A, for the pairs at least 7.5 nm apart (c dt at T0/200)
+        w0 = float(pw["dipoles"]["omega0"][0])
+        seps = np.asarray(pw["separations"])
+        skips = [max(2000, int(math.ceil(3.0 * R / (I.C_LIGHT * pw["dt"])))) for R in seps]
+        modes = lw.pair_modes(r["d"], pw["inst_off"], pw["dt"], 1, w0, skips)
+        g0 = lw.gamma0(I.E_CHARGE, I.M_E / 2, w0)
+        eg, ed = [], []
+        for k, R in enumerate(seps):
+            if R < 7.5e-9:
+                continue
+            d12, g12 = lw.gf_pair(np.array([R, 0.0, 0.0]), np.array([1.0, 0.0, 0.0]), np.array([1.0, 0.0, 0.0]), w0)
+            eg.append(abs(modes[k, 0] / g0 - (1 + g12)) / (1 + abs(g12)))
+            ed.append(abs(modes[k, 4] / g0 - d12) / max(abs(d12), 1.0))
+        dip["vs_green_function"] = {
+            "pairs": len(eg), "gamma_plus_relmax": float(max(eg)), "gamma_plus_relmedian": float(np.median(eg)),
+            "delta_omega_max": float(max(ed)), "delta_omega_median": float(np.median(ed)),
+            "note": "gamma+ relative to gamma0 (1 + gamma12); delta_omega in units of gamma0 relative to "
+                    "max(|delta12|, 1); pairs at least 7.5 nm apart. At dt = T0/200 RK4's own damping, "
+                    "(omega0 dt)^6 / (72 dt) = 0.027 gamma0 on the energy, sets the gamma error; at T0/2000 "
+                    "the rates are within 0.2 % of the theory (GPU tests)"}
+        log(f"[bench] dipoles vs Green's function ({len(eg)} pairs): gamma+ rel max {max(eg):.2e} "
+            f"(median {np.median(eg):.2e}), delta_omega max {max(ed):.2e} (median {np.median(ed):.2e})")
 
     clusters = None
     vjp = None
