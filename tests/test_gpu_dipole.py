@@ -104,6 +104,27 @@ def test_cluster_strict_parity():
     assert_state_close(got, ref, w, what="cluster")
 
 
+def test_cluster_workload_full_batch_sampled_instances():
+    """The 64-cluster workload at its full size (12,530 dipoles, clusters of 2 to 955) in
+    the launch configuration bench.py times (tuned path choice, moments every 10th step),
+    200 steps. Instances are independent, so the oracle runs a sample of them alone: the
+    four smallest clusters and the largest one of at most 40 dipoles. Each must match its
+    slice of the batched run."""
+    w = I.workload_clusters(steps=200)
+    got = gpu_run(w, "strict", stride=10, stepped_min_n="tune")
+    off = w["inst_off"]
+    sizes = np.diff(off)
+    pick = list(np.argsort(sizes, kind="stable")[:4])
+    pick.append(max((k for k in range(len(sizes)) if sizes[k] <= 40), key=lambda k: sizes[k]))
+    for k in pick:
+        a0, a1 = int(off[k]), int(off[k + 1])
+        one = {"dipoles": {kk: np.asarray(v)[a0:a1] for kk, v in w["dipoles"].items()},
+               "inst_off": np.array([0, a1 - a0], np.int32), "dt": w["dt"], "steps": w["steps"]}
+        ref = oracle_run(one, "strict", stride=10)
+        sub = {kk: v[:, a0:a1] for kk, v in got.items()}
+        assert_state_close(sub, ref, one, what=f"cluster {k} ({a1 - a0} dipoles)")
+
+
 def test_large_cluster_global_ring():
     """A 40-dipole cluster whose history ring does not fit in LDS (ring in device memory)."""
     rng = I.rng_for(72)
