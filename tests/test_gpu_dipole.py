@@ -84,6 +84,22 @@ def test_pairs_extrapolate_parity():
     assert_state_close(got, ref, w, what="pairs")
 
 
+def test_pair_workload_full_size_sampled_instances():
+    """The pair workload at its full size (256 instances, 20,000 steps, extrapolating) in
+    the launch configuration bench.py times. The oracle runs 8 instances alone, spread
+    over the separations (closest and farthest included), and each must match its slice
+    of the batched run."""
+    w = I.workload_dipole_pairs()
+    got = gpu_run(w, "extrapolate")
+    order = np.argsort(np.asarray(w["separations"]), kind="stable")
+    for k in order[np.linspace(0, len(order) - 1, 8).round().astype(int)]:
+        one = {"dipoles": {kk: np.asarray(v)[2 * k:2 * k + 2] for kk, v in w["dipoles"].items()},
+               "inst_off": np.array([0, 2], np.int32), "dt": w["dt"], "steps": w["steps"]}
+        ref = oracle_run(one, "extrapolate")
+        sub = {kk: v[:, 2 * k:2 * k + 2] for kk, v in got.items()}
+        assert_state_close(sub, ref, one, what=f"pair {k} ({w['separations'][k]:.3e} m)")
+
+
 def test_pairs_strided_outputs():
     w = I.workload_dipole_pairs(n_inst=6, steps=1000)
     got = gpu_run(w, "extrapolate", stride=7)
