@@ -55,6 +55,7 @@ def lib():
                                     ct.c_double, ct.c_int64, dp, dp, dp, dp, dp, dp, dp]
         L.or_dipole_fields.argtypes = [ct.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, ct.c_double, ct.c_int64, dp,
                                        dp, ct.c_int64, dp, ct.c_int, dp]
+        L.or_hist_at.argtypes = [dp, ct.c_int, ct.c_int, ct.c_int64, ct.c_double, dp, ct.c_double, dp]
         _lib = L
     return _lib
 
@@ -165,6 +166,18 @@ def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: int = DT_
     if hist is not None:
         res["hist"] = hist
     return res
+
+
+def hist_at(hist, jd: int, n: int, dt: float, d0, tp: float):
+    """(d, d_dot, d_ddot) of dipole jd at time tp read from samples 0..n of a history
+    [(n+1)][n_dip][3], as the oscillator run and the detector field read it."""
+    h = _f64(hist)
+    d0a = _f64(d0)
+    out = np.zeros(3)
+    st = lib().or_hist_at(_dp(h), h.shape[1], int(jd), int(n), float(dt), _dp(d0a), float(tp), _dp(out))
+    if st:
+        raise OracleError(st, "history reading")
+    return out
 
 
 def dipole_fields(dipoles: dict, dt: float, steps: int, hist, points, times):

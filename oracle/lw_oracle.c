@@ -343,6 +343,19 @@ static void lo_hist_at(const or_lo *L, int jd, int64_t n, double tp, double out[
     }
 }
 
+/* The history reading above on its own, for tests: hist holds samples 0..n of
+ * n_dip dipoles as [(n+1)][n_dip][3]; d0 the moments before t = 0. */
+int or_hist_at(const double *hist, int n_dip, int jd, int64_t n, double dt, const double *d0, double tp,
+               double out[3])
+{
+    or_lo L;
+    if (n_dip <= 0 || jd < 0 || jd >= n_dip || n < 0 || !(dt > 0.0)) return OR_E_INVALID;
+    memset(&L, 0, sizeof(L));
+    L.n_dip = n_dip; L.hist = (double *)hist; L.dt = dt; L.d0 = d0;
+    lo_hist_at(&L, jd, n, tp, out);
+    return OR_OK;
+}
+
 /* Origin (centre of mass) of dipole jd at time t and its velocity and
  * acceleration: fixed, or moving as O + m cos(w t + phi) (Sec. 4.3, moving
  * dipoles; the motion is prescribed for all t, before t = 0 as well). */

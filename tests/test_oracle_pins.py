@@ -709,3 +709,286 @@ def test_error_paths():
     with pytest.raises(O.OracleError) as ei:
         O.fields(fast, np.zeros((3, 1)) + 5e-9, [0.0])
     assert ei.value.code == 2
+
+
+# ----------------------------------------------------------------------------
+# history reading (Sec. 3.1, Sec. 3.2) and the detector field of a run
+# ----------------------------------------------------------------------------
+
+def _analytic_history(f, n, dt, n_dip=2, jd=1):
+    """Samples (f, f', f'') at t_k = k dt, k = 0..n, of dipole jd in an n_dip history; the
+    other dipoles hold unrelated values so that a wrong dipole index shows."""
+    h = np.full((n + 1, n_dip, 3), 7.0)
+    t = np.arange(n + 1) * dt
+    h[:, jd] = np.stack([f(t, 0), f(t, 1), f(t, 2)], axis=1)
+    return h
+
+
+def _cosine(A=1.3, w=1.0, ph=0.4):
+    """f(t) = A cos(w t + ph) and its derivatives of order k."""
+    return lambda t, k: A * w ** k * np.cos(w * np.asarray(t) + ph + k * math.pi / 2)
+
+
+def test_history_reading_between_samples_is_linear_interpolation():
+    """Between stored steps each of d, d_dot, d_ddot is interpolated linearly (Sec. 3.1):
+    exact at the samples, exact for data linear in time, and within the interpolation
+    bound of a smooth function, whose leading term is interpolant - f = u (1 - u) dt^2 f''/2
+    (swapped weights would miss by (1 - 2u) dt f', far outside the bound)."""
+    dt, n = 0.05, 40
+    f = _cosine()
+    h = _analytic_history(f, n, dt)
+    d0 = np.array([0.0, 0.5])
+    for k in (0, 7, 39):
+        np.testing.assert_array_equal(O.hist_at(h, 1, n, dt, d0, k * dt), h[k, 1])
+    for k in (0, 3, 38):
+        for u in (0.1, 0.25, 0.8):
+            t = (k + u) * dt
+            got = O.hist_at(h, 1, n, dt, d0, t)
+            for order in range(3):
+                exact = f(t, order)
+                lead = 0.5 * u * (1 - u) * dt * dt * f(t, order + 2)    # interpolant - f
+                bound = u * (1 - u) * dt ** 3 * abs(f(t, order + 3)) + 1e-15 + 0.2 * dt ** 4 * 1.3
+                assert abs(got[order] - exact - lead) <= bound, (k, u, order, got[order] - exact, lead)
+    # linear data are reproduced to rounding
+    lin = np.zeros((n + 1, 2, 3))
+    tt = np.arange(n + 1) * dt
+    lin[:, 1] = np.stack([0.3 + 2.0 * tt, 2.0 + 0 * tt, 0 * tt], axis=1)
+    for t in (0.013, 0.77, 1.99):
+        np.testing.assert_allclose(O.hist_at(lin, 1, n, dt, d0, t), [0.3 + 2.0 * t, 2.0, 0.0], rtol=1e-14)
+
+
+def test_history_reading_past_newest_sample_is_second_order_taylor():
+    """Past the newest stored step n (dt larger than the light time between dipoles, the
+    extrapolating reading of Sec. 3.2's time-step rule) the reading is the second-order
+    Taylor polynomial of sample n.  Taylor's theorem then fixes the error against the
+    function the samples came from: f(t_n + u) - d = f'''(t_n) u^3/6 + O(u^4), and
+    f'(t_n + u) - d_dot = f'''(t_n) u^2/2 + O(u^3), f''(t_n + u) - d_ddot = f'''(t_n) u +
+    O(u^2).  A dropped 1/2 leaves f'' u^2/2, a flipped sign of u leaves 2 f' u: both are
+    orders of magnitude outside these bounds."""
+    dt, n = 0.05, 12
+    for ph in (0.4, 1.9, -2.5):
+        f = _cosine(ph=ph)
+        h = _analytic_history(f, n, dt)
+        tn = n * dt
+        for u in (0.2 * dt, 0.5 * dt, dt, 1.7 * dt):
+            got = O.hist_at(h, 1, n, dt, [0.0, 0.0], tn + u)
+            f3 = f(tn, 3)
+            M4 = 1.3                                   # max |f''''| of A cos
+            terms = ((u ** 3 / 6, u ** 4 / 24), (u ** 2 / 2, u ** 3 / 6), (u, u ** 2 / 2))
+            for order, (lead, rem) in enumerate(terms):
+                err = f(tn + u, order) - got[order]
+                assert abs(err - f3 * lead) <= M4 * rem + 1e-15, (ph, u, order, err, f3 * lead)
+
+
+def test_history_reading_before_start_is_static():
+    """Dipoles are static at their initial moment before t = 0 (Sec. 3.2)."""
+    h = _analytic_history(_cosine(), 5, 0.1)
+    for t in (-1e-30, -0.05, -3.0):
+        np.testing.assert_array_equal(O.hist_at(h, 1, 5, 0.1, [0.0, -0.25], t), [-0.25, 0.0, 0.0])
+        np.testing.assert_array_equal(O.hist_at(h, 0, 5, 0.1, [0.9, -0.25], t), [0.9, 0.0, 0.0])
+
+
+def _pair_2nm():
+    dip = I.empty_dipoles(2)
+    dip["axis"][0] = [0.6, 0.8, 0.0]
+    dip["axis"][1] = [0.0, 0.6, 0.8]
+    dip["origin"][1] = [1.6e-9, 0.9e-9, -0.7e-9]          # 1.94 nm: read past the newest step
+    dip["omega0"][:] = 2 * math.pi * 200e12 * np.array([1.0, 1.003])
+    dip["m1"][1] = 3 * ME
+    dip["d0"][:] = [E * 2e-12, -E * 1.5e-12]
+    return dip
+
+
+def test_extrapolated_drive_is_the_field_of_uniformly_accelerated_charges():
+    """Run-level pin of the extrapolating reading.  In the first step only sample 0 =
+    (d0, 0, d_ddot_0) is stored, so a source read at 0 < t' reads d0 + d_ddot_0 t'^2/2,
+    d_ddot_0 t' and d_ddot_0, and before t = 0 it is static at d0.  Its charges, placed by
+    Eqs. (r_1), (r_2), therefore move exactly as the grid path's uniform-acceleration
+    family: at rest at c0 = R + c_f d0/q p until t = 0, then c0 + (c_f d_ddot_0/q) t^2 p/2.
+    The drive E_d(dt) (output row 1) of a 1.94 nm pair at dt = T0/200 (c dt = 7.5 nm) must
+    be p_i . E of those four trajectory charges from the independent grid evaluator, and
+    sample 0's d_ddot_0 must satisfy Eq. (LO_equation) at t = 0.  A dropped 1/2 moves the
+    charges by 3e-4 of their offset (1e-7 of the single-charge field); a wrong sign of the
+    velocity changes its 5e-8 share: both far above the 1e-12 tolerance."""
+    dip = _pair_2nm()
+    w0 = dip["omega0"]
+    dt = 1 / 200e12 / 200
+    r = O.dipole_run(dip, [0, 2], dt, 1, policy=O.DT_EXTRAPOLATE, want_hist=True)
+    h0 = r["hist"][0]
+    m = dip["m1"] * dip["m2"] / (dip["m1"] + dip["m2"])
+    np.testing.assert_allclose(h0[:, 0], dip["d0"], rtol=0)
+    np.testing.assert_array_equal(h0[:, 1], 0.0)
+    ddot_eom = E * E / m * r["Ed"][0] - w0 ** 2 * dip["d0"]
+    np.testing.assert_allclose(h0[:, 2], ddot_eom, rtol=1e-12)
+    for i, j in ((0, 1), (1, 0)):
+        M = dip["m1"][j] + dip["m2"][j]
+        ch = I.empty_charges(2)
+        for k, (sign, cf) in enumerate(((1.0, dip["m2"][j] / M), (-1.0, -dip["m1"][j] / M))):
+            ch["kind"][k] = I.ACCEL
+            ch["q"][k] = sign * E
+            ch["c0"][k] = dip["origin"][j] + cf * dip["d0"][j] / E * dip["axis"][j]
+            ch["e1"][k] = dip["axis"][j]
+            ch["accel"][k] = cf * h0[j, 2] / E
+        x = dip["origin"][i]
+        out, _ = O.fields(ch, x[:, None], [dt])
+        Ed = out[0, 4:7, 0] @ dip["axis"][i]
+        single = K * E / np.linalg.norm(x - dip["origin"][j]) ** 2
+        assert abs(r["Ed"][1, i] - Ed) <= 1e-12 * single, (i, r["Ed"][1, i], Ed)
+        # the charges' motion is visible far above the tolerance: static charges differ
+        ch["accel"][:] = 0.0
+        out_s, _ = O.fields(ch, x[:, None], [dt])
+        assert abs(out_s[0, 4:7, 0] @ dip["axis"][i] - Ed) > 1e-9 * single
+
+
+def test_extrapolating_policy_is_strict_when_nothing_is_read_past_the_newest_step():
+    """With c dt below the separation no retarded time passes the newest stored step, so
+    the extrapolating policy must give the strict run bitwise (the Taylor step is only a
+    reading of what lies beyond the stored history, never a change inside it)."""
+    dip = I.empty_dipoles(2)
+    dip["origin"][1] = [3e-9, 0.0, 0.0]
+    dip["omega0"][:] = 2 * math.pi * 200e12
+    dip["d0"][:] = [E * 1e-12, 0.0]
+    T0 = 1 / 200e12
+    a = O.dipole_run(dip, [0, 2], T0 / 2000, 4000, policy=O.DT_EXTRAPOLATE)
+    b = O.dipole_run(dip, [0, 2], T0 / 2000, 4000, policy=O.DT_STRICT)
+    for k in ("d", "d_dot", "Ed", "energy"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def _dip_fields_case(moving=False):
+    dip = I.empty_dipoles(3)
+    dip["axis"][1] = [0.0, 0.6, 0.8]
+    dip["axis"][2] = [0.48, 0.6, 0.64]
+    dip["origin"][1] = [12e-9, -4e-9, 3e-9]
+    dip["origin"][2] = [-6e-9, 9e-9, -5e-9]
+    dip["omega0"][:] = 2 * math.pi * 200e12
+    dip["m1"][2] = 4 * ME
+    dip["m2"][1] = 0.5 * ME
+    dip["d0"][:] = E * 1e-12 * np.array([1.5, -2.0, 0.7])
+    if moving:
+        wR = 2 * math.pi * 90e12
+        dip["motion_amp"][1] = [0.05e-9, 0.0, -0.12e-9]
+        dip["motion_amp"][2] = [0.0, 0.2e-9, 0.0]
+        dip["motion_omega"][1:] = [wR, 1.3 * wR]
+        dip["motion_phase"][1:] = [0.7, -1.1]
+    return dip
+
+
+def _charges_of(dip, j, kind, moment, rate=0.0):
+    """The two charges of dipole j as grid-path trajectories whose offsets from the origin
+    are those of a moment `moment` changing at `rate` (Eqs. (r_1), (r_2))."""
+    M = dip["m1"][j] + dip["m2"][j]
+    ch = I.empty_charges(2)
+    for k, (sign, cf) in enumerate(((1.0, dip["m2"][j] / M), (-1.0, -dip["m1"][j] / M))):
+        ch["kind"][k] = kind
+        ch["q"][k] = sign * dip["q"][j]
+        ch["c0"][k] = dip["origin"][j] + cf * moment / dip["q"][j] * dip["axis"][j]
+        ch["v"][k] = cf * rate / dip["q"][j] * dip["axis"][j]
+        amp = np.linalg.norm(dip["motion_amp"][j])
+        if kind == I.LINEAR_OSC:
+            ch["e1"][k] = dip["motion_amp"][j] / amp
+            ch["e2"][k] = I.orbit_basis(ch["e1"][k])[0]
+            ch["amp"][k] = amp
+            ch["omega"][k] = dip["motion_omega"][j]
+            ch["phase"][k] = dip["motion_phase"][j]
+    return ch
+
+
+def test_detector_field_before_any_retarded_time_reaches_the_run_is_coulomb():
+    """Before a source's retarded time passes t = 0 its moment is static at d0 (Sec. 3.2),
+    so the detector field is the Coulomb field of the charges placed by Eqs. (r_1), (r_2)
+    (unequal masses here).  With moving origins the static moment rides on the prescribed
+    origin motion, so each charge follows the grid path's linear-oscillation family,
+    itself pinned above."""
+    dip = _dip_fields_case()
+    steps, dt = 4, 2.5e-17
+    hist = np.full((steps + 1, 3, 3), 1e-25)          # never read: every t' < 0
+    pts = np.array([[60e-9, 0, 0], [0, -70e-9, 20e-9], [40e-9, 50e-9, -45e-9]]).T
+    times = [0.0, 3e-17, 1e-16]                          # < 60 nm / c - 13 nm / c
+    got = O.dipole_fields(dip, dt, steps, hist, pts, times)
+    for it in range(len(times)):
+        for p in range(pts.shape[1]):
+            x = pts[:, p]
+            ref = np.zeros(3)
+            for j in range(3):
+                for ch_k in range(2):
+                    ch = _charges_of(dip, j, I.STATIONARY, dip["d0"][j])
+                    rv = x - ch["c0"][ch_k]
+                    ref += K * ch["q"][ch_k] * rv / np.linalg.norm(rv) ** 3
+            scale = K * E / np.linalg.norm(x) ** 2
+            assert np.abs(got[it, :, p] - ref).max() <= 1e-12 * scale
+    mov = _dip_fields_case(moving=True)
+    got = O.dipole_fields(mov, dt, steps, hist, pts, times)
+    ref = np.zeros_like(got)
+    for j in range(3):
+        kind = I.LINEAR_OSC if np.any(mov["motion_amp"][j]) else I.STATIONARY
+        o, _ = O.fields(_charges_of(mov, j, kind, mov["d0"][j]), pts, times)
+        ref += o[:, 4:7]
+    scale = K * E / np.linalg.norm(pts, axis=0) ** 2
+    assert np.all(np.abs(got - ref) <= 1e-12 * scale)
+    assert np.all(np.abs(ref - O.dipole_fields(dip, dt, steps, hist, pts, times)) > 1e-9 * scale)
+
+
+def test_detector_field_of_a_linear_history_is_that_of_uniformly_moving_charges():
+    """A history whose moment is linear in time, d = a + b t, d_dot = b, d_ddot = 0, is
+    reproduced exactly by the linear interpolation, so once every retarded time is past
+    t = 0 each charge moves uniformly: c0 = R + c_f a/q p, v = c_f b/q p.  The detector
+    field then equals the grid path's uniform-velocity field (itself pinned to the
+    textbook closed form of a uniformly moving charge) to rounding."""
+    dip = _dip_fields_case()
+    steps, dt = 200, 1e-17
+    a = E * 1e-10 * np.array([0.8, -1.1, 0.6])
+    b = E * 0.02 * C * np.array([1.0, 0.7, -1.3])
+    t = np.arange(steps + 1) * dt
+    hist = np.zeros((steps + 1, 3, 3))
+    hist[:, :, 0] = a[None, :] + b[None, :] * t[:, None]
+    hist[:, :, 1] = b[None, :]
+    pts = np.array([[60e-9, 0, 0], [0, -70e-9, 20e-9], [40e-9, 50e-9, -45e-9], [-20e-9, 30e-9, 80e-9]]).T
+    times = [6e-16, 1.23e-15, 2e-15]                    # every retarded time > 0
+    got = O.dipole_fields(dip, dt, steps, hist, pts, times)
+    ref = np.zeros_like(got)
+    for j in range(3):
+        o, _ = O.fields(_charges_of(dip, j, I.UNIFORM_VELOCITY, a[j], b[j]), pts, times)
+        ref += o[:, 4:7]
+    scale = K * E / np.linalg.norm(pts, axis=0) ** 2
+    assert np.all(np.abs(got - ref) <= 1e-12 * scale), np.abs(got - ref).max(axis=(0, 1)) / scale
+    # the motion is far above the tolerance
+    st = np.zeros_like(got)
+    for j in range(3):
+        o, _ = O.fields(_charges_of(dip, j, I.STATIONARY, a[j] + b[j] * 1e-15), pts, times)
+        st += o[:, 4:7]
+    assert np.all(np.abs(st - ref).max(axis=(0, 1)) > 1e-6 * scale)
+
+
+def test_detector_field_of_an_isolated_oscillator_is_the_dipole_field():
+    """An isolated oscillator (its run pinned above to the exact RK4 propagator) seen from
+    0.2 to 5 wavelengths: the field is that of an ideal dipole p(t) at its origin (the
+    time-domain form of App. D's Eq. (analytical_E_dipole)),
+        E = k_e {[3n(n.p) - p]/r^3 + [3n(n.p') - p']/(c r^2) + n x (n x p'')/(c^2 r)},
+    with p, p', p'' at t - r/c.  Times are chosen so that t - r/c is a stored step, where
+    the history holds the run's exact (d, d_dot, d_ddot).  The two charges' finite
+    separation (1e-12 m) leaves relative corrections of order 1e-6."""
+    w0 = 2 * math.pi * 200e12
+    dip = _single(w0, d0=E * 1e-12)
+    dip["axis"][0] = [0.0, 0.6, 0.8]
+    dip["origin"][0] = [3e-9, -2e-9, 1e-9]
+    dt = 1 / 200e12 / 200
+    steps = 1200
+    r = O.dipole_run(dip, [0, 1], dt, steps, want_hist=True)
+    lam = 2 * math.pi * C / w0
+    dirs = I.unit_sphere(np.random.default_rng(7), 4)
+    p_hat = dip["axis"][0]
+    for rr in (0.2 * lam, 1.0 * lam, 5.0 * lam):
+        for nvec in dirs:
+            x = dip["origin"][0] + rr * nvec
+            for nstep in (700, 913, 1001):
+                t = nstep * dt + rr / C
+                if t > steps * dt:
+                    continue
+                got = O.dipole_fields(dip, dt, steps, r["hist"], x[:, None], [t])[0, :, 0]
+                d, dd, ddd = r["hist"][nstep, 0]
+                p, pd, pdd = d * p_hat, dd * p_hat, ddd * p_hat
+                ref = K * ((3 * nvec * (nvec @ p) - p) / rr ** 3 + (3 * nvec * (nvec @ pd) - pd) / (C * rr ** 2)
+                           + np.cross(nvec, np.cross(nvec, pdd)) / (C * C * rr))
+                scale = K * np.linalg.norm(p_hat) * E * 1e-12 * (1 / rr ** 3 + w0 / (C * rr ** 2) + w0 ** 2 / (C * C * rr))
+                assert np.abs(got - ref).max() <= 2e-5 * scale, (rr / lam, nstep, np.abs(got - ref).max() / scale)
