@@ -43,6 +43,13 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # sources they were taken on; reported as null once those change.
 TRAFFIC_BYTES = 682.0e6
 TRAFFIC_SOURCES_SHA = "9f69e8271795bf4a"
+# Algorithmic FP64 work per charge-pair drive of the oscillator step (one source
+# charge seen by one target dipole at one stage time), counted from the method's
+# definition: the retarded time on the interpolated history (30 flops, one
+# iteration), the charge's position, beta and beta_dot from the moment (15), the
+# total field of Eq. (E) (58) and its projection on the target's axis with the sum
+# over sources (6).  One square root and two divisions are not counted.
+FLOP_DRIVE_FP64 = 109
 
 
 def kernel_sources_sha() -> str:
@@ -76,6 +83,9 @@ def timed_calls(call, steps: int, warmup: int):
 
 
 def errors(got, ref):
+    """relL2 and relmax of each output group (relative to the group's largest magnitude),
+    and the 99.9th percentile of the pointwise relative error |got - ref| / |ref| of the
+    group's vector at each unmasked (point, time)."""
     import numpy as np
     res = {}
     ok = np.isfinite(ref).all(axis=1)
@@ -83,9 +93,31 @@ def errors(got, ref):
         g = got[:, comps, :].transpose(0, 2, 1)[ok]
         r = ref[:, comps, :].transpose(0, 2, 1)[ok]
         d = g - r
+        den = np.linalg.norm(r, axis=1)
+        nz = den > 0
         res[name] = {"relL2": float(np.sqrt((d * d).sum() / (r * r).sum())),
-                     "relmax": float(np.abs(d).max() / np.abs(r).max())}
+                     "relmax": float(np.abs(d).max() / np.abs(r).max()),
+                     "p999_pointwise": float(np.percentile(np.linalg.norm(d, axis=1)[nz] / den[nz], 99.9))}
     return res
+
+
+def host_cpu() -> dict:
+    """The host's CPU model, its physical cores and the threads this process may use."""
+    import subprocess
+    info = {"model": None, "physical_cores": None, "usable_threads": len(os.sched_getaffinity(0))}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = {}
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        info["model"] = kv.get("Model name")
+        if kv.get("Core(s) per socket") and kv.get("Socket(s)"):
+            info["physical_cores"] = int(kv["Core(s) per socket"]) * int(kv["Socket(s)"])
+    except (OSError, subprocess.SubprocessError, ValueError):
+        pass
+    return info
 
 
 def run_part(part: str, cluster_steps: int, precision: str, ckpt_every: int, adjoint_steps: int, I, lw, torch):
@@ -131,6 +163,40 @@ def run_part(part: str, cluster_steps: int, precision: str, ckpt_every: int, adj
     torch.cuda.synchronize()
     lw.sync_status()
     log(f"[bench] {part}: {(time.perf_counter() - t0) * 1e3:.2f} ms")
+
+
+def dipole_cpu_baseline(pw: dict, I) -> dict:
+    """The FP64 oracle on a slice of the pair workload: every 4th instance for all its
+    steps, instances spread over threads (the C oracle runs with the GIL released), and
+    two instances on one core."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle as O
+    hcpu = host_cpu()
+    workers = max(1, min(16, hcpu["usable_threads"]))
+    inst = list(range(0, len(pw["inst_off"]) - 1, 4))
+    dip = pw["dipoles"]
+
+    def one(k, steps):
+        sel = slice(int(pw["inst_off"][k]), int(pw["inst_off"][k + 1]))
+        sub = {key: np.ascontiguousarray(v[sel]) for key, v in dip.items()}
+        O.dipole_run(sub, [0, sel.stop - sel.start], pw["dt"], steps, policy=O.DT_EXTRAPOLATE, out_stride=100)
+        return sel.stop - sel.start
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(workers) as ex:
+        n_dips = list(ex.map(lambda k: one(k, pw["steps"]), inst))
+    sec = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    n1 = one(inst[0], pw["steps"]) + one(inst[1], pw["steps"])
+    s1 = time.perf_counter() - t0
+    return {"value": sum(n_dips) * pw["steps"] / sec, "unit": "dipole-steps/s", "cores": workers, "kind": "oracle",
+            "sample": f"{len(inst)} of the {len(pw['inst_off']) - 1} pair instances (every 4th) x {pw['steps']} "
+                      f"steps, {sec:.1f} s wall on {workers} threads, FP64 C oracle",
+            "serial_value": n1 * pw["steps"] / s1,
+            "serial_sample": f"2 instances x {pw['steps']} steps on one core ({s1:.2f} s)",
+            "cpu_model": hcpu["model"], "physical_cores": hcpu["physical_cores"]}
 
 
 def tuned_threshold(precision: str):
@@ -250,7 +316,8 @@ def main():
         from concurrent.futures import ThreadPoolExecutor
         # the C oracle runs with the GIL released, so threads over disjoint point
         # slices use that many host cores (capped at the 16 of one GPU's share)
-        workers = max(1, min(16, os.cpu_count() or 1))
+        hcpu = host_cpu()
+        workers = max(1, min(16, hcpu["usable_threads"]))
         chunks = [np.ascontiguousarray(w["points"][:, c]) for c in np.array_split(pidx, workers)]
         log(f"[bench] oracle on {len(pidx)} points x {n_ch} charges x {n_t} times ({workers} threads)")
         t0 = time.perf_counter()
@@ -269,7 +336,8 @@ def main():
                          f"workload ({cpu_evals} evals, {cpu_s:.1f} s wall on {workers} threads, FP64 C "
                          f"oracle, disjoint point slices)",
                "serial_value": n1 * n_ch * n_t / s1,
-               "serial_sample": f"{n1} of those points on one core ({s1:.1f} s)"}
+               "serial_sample": f"{n1} of those points on one core ({s1:.1f} s)",
+               "cpu_model": hcpu["model"], "physical_cores": hcpu["physical_cores"]}
         gm = out_m[:, :, torch.tensor(pidx, device="cuda")].double().cpu().numpy()
         gf = out_f[:, :, torch.tensor(pidx, device="cuda")].cpu().numpy()
         err = {"mixed": errors(gm, ref), "fp64": errors(gf, ref)}
@@ -339,6 +407,10 @@ def main():
                     "the rates are within 0.2 % of the theory (GPU tests)"}
         log(f"[bench] dipoles vs Green's function ({len(eg)} pairs): gamma+ rel max {max(eg):.2e} "
             f"(median {np.median(eg):.2e}), delta_omega max {max(ed):.2e} (median {np.median(ed):.2e})")
+        if not args.no_cpu_baseline:
+            dip["cpu_baseline"] = dipole_cpu_baseline(pw, I)
+            log(f"[bench] oracle pairs: {dip['cpu_baseline']['value']:.3e} dipole-steps/s on "
+                f"{dip['cpu_baseline']['cores']} threads")
 
     clusters = None
     vjp = None
@@ -346,6 +418,8 @@ def main():
     if not args.no_dipole:
         cw = I.workload_clusters(steps=args.cluster_steps)
         n_c = len(cw["dipoles"]["omega0"])
+        sizes = np.diff(cw["inst_off"]).astype(np.int64)
+        drives = int((sizes * (sizes - 1) * 4).sum())       # source charges x targets x 2 new stage times
         clusters = {"workload": cw["name"], "dipoles": n_c, "steps": cw["steps"],
                     "note": ("the whole 50,000-step run, " if cw["steps"] >= 50000 else
                              "the uneven-cluster workload runs 50,000 steps; this line times a prefix of it, ") +
@@ -356,14 +430,26 @@ def main():
             lw.dipole_run(cw["dipoles"], cw["inst_off"], cw["dt"], 10, out_stride=10, precision=prec,
                           stepped_min_n="tune")
             torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             t0 = time.perf_counter()
+            ev0.record()
             lw.dipole_run(cw["dipoles"], cw["inst_off"], cw["dt"], cw["steps"], out_stride=10, check=False,
                           precision=prec, stepped_min_n="tune")
+            ev1.record()
             torch.cuda.synchronize()
             csec = time.perf_counter() - t0
             lw.sync_status()
+            step_ms = ev0.elapsed_time(ev1) / cw["steps"]
+            ach = drives * FLOP_DRIVE_FP64 / (step_ms * 1e-3) / 1e12
             clusters[prec] = {"dipole_steps_per_s": n_c * cw["steps"] / csec, "ms": round(csec * 1e3, 3),
-                              "stepped_min_n": tuned_threshold(prec)}
+                              "stepped_min_n": tuned_threshold(prec), "step_us": round(step_ms * 1e3, 2),
+                              "roofline": {"bound": "alu", "achieved": round(ach, 3),
+                                           "peak": round(PEAK_VALU_TFLOPS, 1), "unit": "TFLOP/s",
+                                           "frac": round(ach / PEAK_VALU_TFLOPS, 4), "traffic": None,
+                                           "kernel": "lo_step_kernel (one launch per step, graph-replayed)",
+                                           "flop_per_drive": FLOP_DRIVE_FP64, "drives_per_step": drives,
+                                           "note": "per-step time from events on the launch stream over the "
+                                                   "whole run; algorithmic FP64 flops per charge-pair drive"}}
             log(f"[bench] clusters ({prec}, stepped path from {clusters[prec]['stepped_min_n']} dipoles): "
                 f"{csec * 1e3:.1f} ms for {cw['steps']} steps, "
                 f"{clusters[prec]['dipole_steps_per_s']:.3e} dipole-steps/s")

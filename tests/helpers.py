@@ -30,6 +30,24 @@ def field_errors(got: np.ndarray, ref: np.ndarray) -> dict:
     return res
 
 
+def pointwise_rel_p999(got: np.ndarray, ref: np.ndarray) -> dict:
+    """99.9th percentile over unmasked (point, time) entries of the pointwise relative error
+    |got - ref| / |ref| of each output group's vector (Phi as a scalar), so that the weak
+    field far from the charges is judged on its own scale, not the group's maximum."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    ok = np.isfinite(ref).all(axis=1)
+    res = {}
+    for name, comps in GROUPS.items():
+        g = got[:, comps, :].transpose(0, 2, 1)[ok]
+        r = ref[:, comps, :].transpose(0, 2, 1)[ok]
+        num = np.linalg.norm(g - r, axis=1)
+        den = np.linalg.norm(r, axis=1)
+        nz = den > 0
+        res[name] = float(np.percentile(num[nz] / den[nz], 99.9)) if nz.any() else 0.0
+    return res
+
+
 def assert_fields_close(got, ref, tol: float, what: str = ""):
     errs = field_errors(got, ref)
     bad = {k: v for k, v in errs.items() if not (v[0] <= tol and v[1] <= tol)}

@@ -18,9 +18,10 @@ distant dipoles (offsets near 1e-19 m at 700 nm) that leaves about 3 significant
 in the oracle's pair field. The mixed form takes the offset difference exactly and is
 the more accurate of the two there.
 
-The collective rates and the shift are compared at 1e-3. Over an 8,000-step window the
-energy decays by only about 4e-6, so this needs the moments to about 1e-9. That
-requirement is why the static near-field term stays in FP64.
+The collective rates and the shift are compared at 1e-4 of max(|value|, gamma_0), ten
+times inside the stated 1e-3. Over an 8,000-step window the energy decays by only about
+4e-6, so this needs the moments to about 1e-9. That requirement is why the static
+near-field term stays in FP64.
 """
 import math
 
