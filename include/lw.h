@@ -152,6 +152,30 @@ lw_status lw_fields(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, co
                     int64_t n_pts, const double *h_times, int32_t n_times, const lw_opts *opts,
                     void *d_out, uint32_t *d_flags, void *stream);
 
+/* Largest scratch of lw_fields_noalloc, in bytes: the charges (144 bytes each), the
+ * times (8 bytes each) and one 224-byte record per (time, charge), each part
+ * rounded up to 256 bytes.  For example 64 times x 280 charges fit. */
+#define LW_NOALLOC_SCRATCH_BYTES (4u << 20)
+
+/* lw_fields without any allocation, for callers that cannot allocate device or
+ * pinned host memory during the call (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, outputs
+ * and errors as lw_fields, with these differences:
+ *   - The charges, times and per-(time, charge) records go to a fixed scratch
+ *     array of LW_NOALLOC_SCRATCH_BYTES on each GPU (static device memory of
+ *     the library, held until the process ends), not to the context's
+ *     workspace.  A call that needs more returns LW_E_INVALID before any work.
+ *   - h_charges and h_times are copied from pageable host memory on `stream`;
+ *     the call returns once the copies have read them.
+ *   - The launch shape is the context's default (no tuning, no timing).
+ * Every call on one GPU shares that GPU's scratch: calls that may overlap on
+ * one GPU (different streams, or threads without ordering) race and give wrong
+ * results; calls on one stream are ordered and safe.  The context is used only
+ * for its device and launch shape.  Asynchronous. */
+lw_status lw_fields_noalloc(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, const double *d_pts,
+                            int64_t n_pts, const double *h_times, int32_t n_times, const lw_opts *opts,
+                            void *d_out, uint32_t *d_flags, void *stream);
+
 /* Vector-Jacobian product of lw_fields with respect to the trajectory
  * parameters: d_grad[c][k] = sum over points p, times t and outputs j of
  * d_cot[t][j][p] * d out[t][j][p] / d theta_{c,k}, for the parameters

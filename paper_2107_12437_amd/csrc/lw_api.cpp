@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -45,6 +46,31 @@ double norm3(const double *v) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2
 bool unit3(const double *v) { return std::fabs(norm3(v) - 1.0) <= 1e-9; }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Scratch of lw_fields_noalloc: the charges, the times and the (time, charge)
+// records of one call.  It is static device memory, one copy per GPU, held until
+// the process ends.  In host code the array's name is not a device address:
+// scratch_setup takes each device's address with hipGetSymbolAddress (with that
+// device current) and every host use goes through g_scratch[device].
+static __device__ __align__(256) unsigned char scratch[LW_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[MAX_DEVICES] = {};
+
+// Once per device, with `device` current: the device address of its scratch.
+lw_status scratch_setup(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES) return fail(LW_E_INVALID, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[device]) return LW_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(LW_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[device] = ptr;
+    return LW_OK;
+}
 
 }  // namespace
 
@@ -347,6 +373,12 @@ lw_status lw_create(lw_ctx **out, int32_t device)
     const char *at = std::getenv("LW_AUTOTUNE");
     if (at && at[0] == '0') c->autotune = false;
     load_tune_file(c);
+    const lw_status sst = scratch_setup(device);
+    if (sst != LW_OK) {
+        const std::string msg = g_last_error;
+        lw_destroy(c);
+        return fail(sst, "lw_create: " + msg);
+    }
     *out = c;
     return LW_OK;
 }
@@ -523,6 +555,47 @@ lw_status lw_fields(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, co
         save_tune_entry(ctx, key, L);
     }
     LW_HIP(lw::launch_fields(d_recs, n_charges, d_pts, n_pts, n_times, *opts, tol_rel, mask_r, d_out, d_flags, L, s));
+    return LW_OK;
+}
+
+lw_status lw_fields_noalloc(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, const double *d_pts,
+                            int64_t n_pts, const double *h_times, int32_t n_times, const lw_opts *opts, void *d_out,
+                            uint32_t *d_flags, void *stream)
+{
+    bool noop = false;
+    lw_status st = check_fields_args("lw_fields_noalloc", ctx, h_charges, n_charges, d_pts, n_pts, h_times, n_times,
+                                     opts, d_out, &noop);
+    if (st != LW_OK || noop) return st;
+    // the three parts of the scratch, each sized in a way that cannot overflow
+    // (check_fields_args bounds n_times; n_charges is a positive int32)
+    const size_t cap = LW_NOALLOC_SCRATCH_BYTES;
+    const size_t ch_bytes = align_up(sizeof(lw_traj) * (size_t)n_charges, 256);
+    const size_t tm_bytes = align_up(sizeof(double) * (size_t)n_times, 256);
+    const size_t n_rec = (size_t)n_charges * (size_t)n_times;
+    if (ch_bytes > cap || tm_bytes > cap || n_rec > cap / lw::src_rec_bytes() ||
+        ch_bytes + tm_bytes + align_up(lw::src_rec_bytes() * n_rec, 256) > cap)
+        return fail(LW_E_INVALID, "lw_fields_noalloc: " + std::to_string(n_charges) + " charges x " +
+                                      std::to_string(n_times) + " times need more than the " +
+                                      std::to_string(cap) + "-byte scratch (LW_NOALLOC_SCRATCH_BYTES)");
+    LW_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    void *base = g_scratch[ctx->device];
+    if (!base) {
+        st = scratch_setup(ctx->device);
+        if (st != LW_OK) return st;
+        base = g_scratch[ctx->device];
+    }
+    char *sc = (char *)base;
+    LW_HIP(hipMemcpyAsync(sc, h_charges, sizeof(lw_traj) * (size_t)n_charges, hipMemcpyHostToDevice, s));
+    LW_HIP(hipMemcpyAsync(sc + ch_bytes, h_times, sizeof(double) * (size_t)n_times, hipMemcpyHostToDevice, s));
+    lw::SrcRec *d_recs = (lw::SrcRec *)(sc + ch_bytes + tm_bytes);
+    // the prep kernel rewrites every record of this call and clears the flags
+    LW_HIP(lw::launch_prep((const lw_traj *)sc, n_charges, (const double *)(sc + ch_bytes), n_times, d_recs, d_flags,
+                           n_pts, s));
+    const double mask_r = opts->mask_radius < 0.0 ? 1e-10 : opts->mask_radius;
+    const double tol_rel = opts->precision == LW_FP64 ? 4.0 * 2.220446049250313e-16 : 2.3283064365386963e-10;
+    LW_HIP(lw::launch_fields(d_recs, n_charges, d_pts, n_pts, n_times, *opts, tol_rel, mask_r, d_out, d_flags,
+                             ctx->field_launch, s));
     return LW_OK;
 }
 

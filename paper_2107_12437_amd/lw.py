@@ -45,7 +45,7 @@ STATUS_NAMES = {0: "LW_OK", 1: "LW_E_INVALID", 2: "LW_E_SUPERLUMINAL", 3: "LW_E_
                 4: "LW_E_VELOCITY", 5: "LW_E_NOCONV", 6: "LW_E_HIP", 7: "LW_E_NOMEM",
                 8: "LW_E_NONFINITE", 9: "LW_E_HISTORY", 10: "LW_E_STATE"}
 EXPORTS = ("lw_last_error", "lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields",
-           "lw_fields_vjp", "lw_dipole_run", "lw_dipole_run_vjp", "lw_pair_modes", "lw_gamma0", "lw_gf_pair",
+           "lw_fields_noalloc", "lw_fields_vjp", "lw_dipole_run", "lw_dipole_run_vjp", "lw_pair_modes", "lw_gamma0", "lw_gf_pair",
            "lw_exact_modes", "lw_dipole_state_size", "lw_dipole_run_state")
 PARAM_NAMES = ("q", "c0x", "c0y", "c0z", "amp", "omega", "phase", "accel", "vx", "vy", "vz")
 OUTPUT_NAMES = ("phi", "Ax", "Ay", "Az", "Ex", "Ey", "Ez", "Bx", "By", "Bz")
@@ -99,6 +99,8 @@ def load_library(path: str = LIB_PATH):
     L.lw_sync_status.argtypes = [vp, vp]
     L.lw_set_autotune.argtypes = [vp, i32]
     L.lw_fields.argtypes = [vp, ct.POINTER(Traj), i32, vp, i64, ct.POINTER(dbl), i32, ct.POINTER(Opts), vp, vp, vp]
+    L.lw_fields_noalloc.argtypes = [vp, ct.POINTER(Traj), i32, vp, i64, ct.POINTER(dbl), i32, ct.POINTER(Opts), vp,
+                                    vp, vp]
     L.lw_fields_vjp.argtypes = [vp, ct.POINTER(Traj), i32, vp, i64, ct.POINTER(dbl), i32, ct.POINTER(Opts), vp, vp, vp]
     L.lw_dipole_run.argtypes = [vp, ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, i64,
                                 ct.POINTER(RunOpts), vp, vp, vp, vp, vp, vp, vp]
@@ -114,7 +116,8 @@ def load_library(path: str = LIB_PATH):
     L.lw_gamma0.argtypes = [dbl, dbl, dbl]
     L.lw_gf_pair.argtypes = [ct.POINTER(dbl), ct.POINTER(dbl), ct.POINTER(dbl), dbl, ct.POINTER(dbl)]
     L.lw_exact_modes.argtypes = [ct.POINTER(dbl), ct.POINTER(dbl), dbl, dbl, dbl, ct.POINTER(dbl)]
-    for name in ("lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields", "lw_fields_vjp",
+    for name in ("lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields", "lw_fields_noalloc",
+                 "lw_fields_vjp",
                  "lw_dipole_run", "lw_dipole_run_vjp", "lw_pair_modes", "lw_gf_pair", "lw_exact_modes",
                  "lw_dipole_state_size", "lw_dipole_run_state"):
         getattr(L, name).restype = i32
@@ -230,9 +233,11 @@ class FieldsCall:
         self.flags = torch.empty(n_pts, dtype=torch.int32, device=points.device) if with_flags else None
         self.n_pts = n_pts
 
-    def launch(self):
+    def launch(self, noalloc: bool = False):
+        """Enqueues the call; noalloc takes lw_fields_noalloc (no allocation, fixed scratch)."""
         L = load_library()
-        _check(L.lw_fields(self.ctx.handle, self.charges, self.n_charges, ct.c_void_p(self.points.data_ptr()),
+        fn = L.lw_fields_noalloc if noalloc else L.lw_fields
+        _check(fn(self.ctx.handle, self.charges, self.n_charges, ct.c_void_p(self.points.data_ptr()),
                            self.n_pts, self.times.ctypes.data_as(ct.POINTER(ct.c_double)), len(self.times),
                            ct.byref(self.opts), ct.c_void_p(self.out.data_ptr()),
                            ct.c_void_p(self.flags.data_ptr()) if self.flags is not None else None,
@@ -248,6 +253,15 @@ def fields(charges: dict, points: torch.Tensor, times, precision: str = "mixed",
     phi, A, E, B, S."""
     return FieldsCall(charges, points, times, precision, field_kind, mask_radius, max_iter, True, ctx,
                       outputs).launch()
+
+
+def fields_noalloc(charges: dict, points: torch.Tensor, times, precision: str = "mixed", field_kind: str = "total",
+                   mask_radius: float = 1e-10, max_iter: int = 0, ctx: Context | None = None, outputs=None):
+    """fields() through lw_fields_noalloc: the library allocates nothing during the call (its
+    inputs go to a fixed per-GPU scratch of LW_NOALLOC_SCRATCH_BYTES).  The output tensors are
+    allocated here, by torch, before the call."""
+    return FieldsCall(charges, points, times, precision, field_kind, mask_radius, max_iter, True, ctx,
+                      outputs).launch(noalloc=True)
 
 
 def fields_vjp(charges: dict, points: torch.Tensor, times, cotangent: torch.Tensor, field_kind: str = "total",
