@@ -35,13 +35,14 @@ class Traj(ct.Structure):
                 ("accel", ct.c_double), ("v", ct.c_double * 3)]
 
 
-_lib = None
+_libs: dict = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        path = _build.build(force=False)
+def lib(extended: bool = False):
+    """The FP64 oracle library, or the same source built in x87 extended precision (a
+    64-bit significand, about 3 more decimal digits) when `extended`."""
+    if extended not in _libs:
+        path = _build.build(force=False, extended=extended)
         L = ct.CDLL(path)
         dp = ct.POINTER(ct.c_double)
         L.or_traj_kin.argtypes = [ct.POINTER(Traj), ct.c_double, dp, dp, dp, dp]
@@ -56,8 +57,14 @@ def lib():
         L.or_dipole_fields.argtypes = [ct.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp, ct.c_double, ct.c_int64, dp,
                                        dp, ct.c_int64, dp, ct.c_int, dp]
         L.or_hist_at.argtypes = [dp, ct.c_int, ct.c_int, ct.c_int64, ct.c_double, dp, ct.c_double, dp]
-        _lib = L
-    return _lib
+        L.or_real_digits.argtypes = []
+        _libs[extended] = L
+    return _libs[extended]
+
+
+def real_digits(extended: bool = False) -> int:
+    """Significand bits of the oracle's working precision (53, or 64 when extended)."""
+    return lib(extended).or_real_digits()
 
 
 def _dp(a: np.ndarray):
@@ -124,8 +131,9 @@ def lw_pair(charges: dict, i: int, x, t: float, kind: int = TOTAL, mask_r: float
     return None if f else out
 
 
-def fields(charges: dict, points, times, kind: int = TOTAL, mask_radius: float = 1e-10):
-    """[n_times][10][n_pts] FP64 outputs and per-point flags."""
+def fields(charges: dict, points, times, kind: int = TOTAL, mask_radius: float = 1e-10, extended: bool = False):
+    """[n_times][10][n_pts] outputs (FP64, or computed in extended precision and rounded
+    to FP64 when `extended`) and per-point flags."""
     arr, n = pack(charges)
     pts = _f64(points)
     assert pts.ndim == 2 and pts.shape[0] == 3
@@ -133,7 +141,7 @@ def fields(charges: dict, points, times, kind: int = TOTAL, mask_radius: float =
     npts = pts.shape[1]
     out = np.empty((len(tms), 10, npts))
     flags = np.zeros(npts, dtype=np.uint32)
-    st = lib().or_fields(arr, n, _dp(pts), npts, _dp(tms), len(tms), int(kind), float(mask_radius),
+    st = lib(extended).or_fields(arr, n, _dp(pts), npts, _dp(tms), len(tms), int(kind), float(mask_radius),
                          _dp(out), flags.ctypes.data_as(ct.POINTER(ct.c_uint32)))
     if st:
         raise OracleError(st, "fields")
@@ -141,11 +149,13 @@ def fields(charges: dict, points, times, kind: int = TOTAL, mask_radius: float =
 
 
 def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: int = DT_STRICT,
-               max_vel: float = 299792458.0 / 100, out_stride: int = 1, want_hist: bool = False):
+               max_vel: float = 299792458.0 / 100, out_stride: int = 1, want_hist: bool = False,
+               extended: bool = False):
     """Runs Algorithm 1 on independent instances.  Returns dict of [n_out][n_dip] arrays
     d, d_dot, energy, Ed, W_abs, W_rad (and hist [(steps+1)][n_dip][3] when asked).  Optional keys
     motion_amp [n][3], motion_omega, motion_phase move the origins as
-    origin + motion_amp cos(motion_omega t + motion_phase) (Sec. 4.3)."""
+    origin + motion_amp cos(motion_omega t + motion_phase) (Sec. 4.3).  `extended` runs the
+    extended-precision build (state and arithmetic in long double, outputs rounded to FP64)."""
     dip = {k: _f64(v) for k, v in dipoles.items()}
     n = len(dip["omega0"])
     off = np.ascontiguousarray(inst_off, dtype=np.int32)
@@ -153,7 +163,7 @@ def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: int = DT_
     res = {k: np.empty((n_out, n)) for k in ("d", "d_dot", "energy", "Ed", "W_abs", "W_rad")}
     hist = np.empty((steps + 1, n, 3)) if want_hist else None
     mamp, mom, mph = _motion(dip, n)
-    st = lib().or_dipole_run(n, _dp(dip["origin"]), _dp(dip["axis"]), _dp(dip["omega0"]), _dp(dip["q"]),
+    st = lib(extended).or_dipole_run(n, _dp(dip["origin"]), _dp(dip["axis"]), _dp(dip["omega0"]), _dp(dip["q"]),
                              _dp(dip["m1"]), _dp(dip["m2"]), _dp(dip["d0"]),
                              _dp(mamp) if mamp is not None else None, _dp(mom) if mom is not None else None,
                              _dp(mph) if mph is not None else None, len(off) - 1,
@@ -168,19 +178,19 @@ def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: int = DT_
     return res
 
 
-def hist_at(hist, jd: int, n: int, dt: float, d0, tp: float):
+def hist_at(hist, jd: int, n: int, dt: float, d0, tp: float, extended: bool = False):
     """(d, d_dot, d_ddot) of dipole jd at time tp read from samples 0..n of a history
     [(n+1)][n_dip][3], as the oscillator run and the detector field read it."""
     h = _f64(hist)
     d0a = _f64(d0)
     out = np.zeros(3)
-    st = lib().or_hist_at(_dp(h), h.shape[1], int(jd), int(n), float(dt), _dp(d0a), float(tp), _dp(out))
+    st = lib(extended).or_hist_at(_dp(h), h.shape[1], int(jd), int(n), float(dt), _dp(d0a), float(tp), _dp(out))
     if st:
         raise OracleError(st, "history reading")
     return out
 
 
-def dipole_fields(dipoles: dict, dt: float, steps: int, hist, points, times):
+def dipole_fields(dipoles: dict, dt: float, steps: int, hist, points, times, extended: bool = False):
     """E ([n_times][3][n_pts]) of all dipole charges from a finished run's history."""
     dip = {k: _f64(v) for k, v in dipoles.items()}
     n = len(dip["omega0"])
@@ -189,7 +199,7 @@ def dipole_fields(dipoles: dict, dt: float, steps: int, hist, points, times):
     tms = _f64(np.atleast_1d(times))
     out = np.empty((len(tms), 3, pts.shape[1]))
     mamp, mom, mph = _motion(dip, n)
-    st = lib().or_dipole_fields(n, _dp(dip["origin"]), _dp(dip["axis"]), _dp(dip["q"]), _dp(dip["m1"]),
+    st = lib(extended).or_dipole_fields(n, _dp(dip["origin"]), _dp(dip["axis"]), _dp(dip["q"]), _dp(dip["m1"]),
                                 _dp(dip["m2"]), _dp(dip["d0"]),
                                 _dp(mamp) if mamp is not None else None, _dp(mom) if mom is not None else None,
                                 _dp(mph) if mph is not None else None, float(dt), int(steps), _dp(h), _dp(pts),

@@ -1,7 +1,8 @@
-"""Builds the oracle's shared library (plain C, gcc, no fast-math, no FMA contraction).
+"""Builds the oracle's shared libraries (plain C, gcc, no fast-math, no FMA contraction):
+the FP64 oracle and the same source in x87 extended precision (long double).
 
-The oracle is test infrastructure: only tests/, the smoke check and the benchmark's
-CPU baseline load it.
+The oracle is test infrastructure: only tests/, the smoke check and the benchmark's CPU
+baseline load it.
 """
 from __future__ import annotations
 
@@ -12,17 +13,25 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lw_oracle.c")
 LIB = os.path.join(HERE, "_liblworacle.so")
+LIB_EXT = os.path.join(HERE, "_liblworacle_ld.so")
+FLAGS = ["-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-Wall", "-Wextra"]
 
 
-def build(force: bool = True) -> str:
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
-        return LIB
-    tmp = LIB + ".tmp"
-    cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+def _build_one(path: str, defs: list[str], force: bool) -> str:
+    if not force and os.path.exists(path) and os.path.getmtime(path) >= os.path.getmtime(SRC):
+        return path
+    tmp = path + ".tmp"
+    subprocess.run(["gcc", *FLAGS, *defs, "-o", tmp, SRC, "-lm"], check=True)
+    os.replace(tmp, path)
+    return path
+
+
+def build(force: bool = True, extended: bool = False) -> str:
+    """Builds both libraries when stale (or always with force); returns the path of the
+    FP64 one, or of the extended-precision one when `extended`."""
+    _build_one(LIB, [], force)
+    _build_one(LIB_EXT, ["-DOR_REAL=long double", "-DOR_LONG"], force)
+    return LIB_EXT if extended else LIB
 
 
 if __name__ == "__main__":

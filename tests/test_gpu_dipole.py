@@ -1,16 +1,21 @@
-"""GPU parity of lw_dipole_run (Algorithm 1) against the FP64 oracle.
+"""GPU parity of lw_dipole_run (Algorithm 1) against the oracle.
 
 Moments, velocities and energies are compared element by element relative to the
 largest magnitude of each output per dipole (1e-11: both sides are FP64 and
 differ by the retarded-time solver and the order of the pair sums).  The drive
 field is the near-cancelling sum of opposite charges' fields, so it is compared
 relative to the sum of the single-charge field magnitudes (1e-13, a few hundred
-ulp).  A dipole driven only through such a field inherits its rounding relative
-to the net drive: r = (single-charge scale) / max |E_d| per dipole (about 1e6 for a
-pair 745 nm apart, whose net field is 1e-6 of a single charge's), so its state
-tolerance is max(1e-11, 2 eps r) (both sides round each charge's field; the
-per-step errors average out in the response, measured at 0.1 eps r).  Collective
-rates and shifts extracted from the moments agree to 1e-3.
+ulp).
+
+A dipole driven only through such a field inherits its rounding relative to the
+net drive: r = (single-charge scale) / max |E_d| per dipole, about 2e5 for the
+driven dipole of a collinear pair 1 um apart.  The pair tests therefore take the
+oracle's extended-precision build as the reference, whose own cancellation error
+is 2^11 smaller.  Against it the GPU's FP64 form was measured at 0.13-0.22 eps r
+on pairs from 100 nm to 1 um (the FP64 oracle at 0.02-0.06 eps r, the mixed form
+at 0.01 eps r), so the state tolerance is max(1e-11, 0.5 eps r).  The cluster
+tests keep the FP64 oracle under the same bound (0.22 + 0.06 eps r < 0.5 eps r).
+Collective rates and shifts extracted from the moments agree to 1e-4 of gamma_0.
 """
 import math
 
@@ -26,6 +31,8 @@ pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ready(), reason="needs
 
 TOL_STATE = 1e-11
 TOL_DRIVE = 1e-13
+TOL_CANCEL = 0.5          # state tolerance per eps r of the drive's cancellation (measured <= 0.22)
+TOL_MIXED_STATE = 1e-5
 EPS = 2.220446049250313e-16
 
 
@@ -35,9 +42,10 @@ def gpu_run(w, policy, stride=1, **kw):
     return {k: v.cpu().numpy() for k, v in r.items()}
 
 
-def oracle_run(w, policy, stride=1):
+def oracle_run(w, policy, stride=1, extended=False):
     return O.dipole_run(w["dipoles"], w["inst_off"], w["dt"], w["steps"],
-                        policy=O.DT_EXTRAPOLATE if policy == "extrapolate" else O.DT_STRICT, out_stride=stride)
+                        policy=O.DT_EXTRAPOLATE if policy == "extrapolate" else O.DT_STRICT, out_stride=stride,
+                        extended=extended)
 
 
 def single_charge_scale(w):
@@ -57,9 +65,9 @@ def single_charge_scale(w):
 
 
 def assert_state_close(got, ref, w, keys=("d", "d_dot", "energy", "Ed"), tol=TOL_STATE, what=""):
-    """d, d_dot, energy relative to their largest magnitude per dipole (tol, or 2 eps times
-    the dipole's drive cancellation ratio where that is larger); Ed relative to the
-    single-charge field scale (TOL_DRIVE)."""
+    """d, d_dot, energy relative to their largest magnitude per dipole (tol, or TOL_CANCEL
+    eps times the dipole's drive cancellation ratio where that is larger); Ed relative to
+    the single-charge field scale (TOL_DRIVE)."""
     sc = single_charge_scale(w)
     net = np.abs(ref["Ed"]).max(axis=0)
     ratio = np.where(net > 0, sc / np.where(net > 0, net, 1.0), 0.0)
@@ -69,7 +77,7 @@ def assert_state_close(got, ref, w, keys=("d", "d_dot", "energy", "Ed"), tol=TOL
             t = TOL_DRIVE
         else:
             scale = np.abs(ref[k]).max(axis=0, keepdims=True)
-            t = np.maximum(tol, 2 * EPS * ratio)[None, :]
+            t = np.maximum(tol, TOL_CANCEL * EPS * ratio)[None, :]
         scale = np.where(scale > 0, scale, 1.0)
         err = np.abs(got[k] - ref[k]) / scale
         assert (err <= t).all(), f"{what} {k}: max relative error {err.max():.3e} at {np.unravel_index(err.argmax(), err.shape)}"
@@ -80,22 +88,25 @@ def test_pairs_extrapolate_parity():
     a third of them closer than c dt) for 1,500 steps."""
     w = I.workload_dipole_pairs(n_inst=24, steps=1500)
     got = gpu_run(w, "extrapolate")
-    ref = oracle_run(w, "extrapolate")
+    ref = oracle_run(w, "extrapolate", extended=True)
     assert_state_close(got, ref, w, what="pairs")
 
 
 def test_pair_workload_full_size_sampled_instances():
     """The pair workload at its full size (256 instances, 20,000 steps, extrapolating) in
     the launch configuration bench.py times. The oracle runs 8 instances alone, spread
-    over the separations (closest and farthest included), and each must match its slice
-    of the batched run."""
+    over the separations (closest and farthest included), in its extended-precision
+    build, and each must match its slice of the batched run."""
+    from concurrent.futures import ThreadPoolExecutor
     w = I.workload_dipole_pairs()
     got = gpu_run(w, "extrapolate")
     order = np.argsort(np.asarray(w["separations"]), kind="stable")
-    for k in order[np.linspace(0, len(order) - 1, 8).round().astype(int)]:
-        one = {"dipoles": {kk: np.asarray(v)[2 * k:2 * k + 2] for kk, v in w["dipoles"].items()},
-               "inst_off": np.array([0, 2], np.int32), "dt": w["dt"], "steps": w["steps"]}
-        ref = oracle_run(one, "extrapolate")
+    picks = order[np.linspace(0, len(order) - 1, 8).round().astype(int)]
+    ones = [{"dipoles": {kk: np.ascontiguousarray(np.asarray(v)[2 * k:2 * k + 2]) for kk, v in w["dipoles"].items()},
+             "inst_off": np.array([0, 2], np.int32), "dt": w["dt"], "steps": w["steps"]} for k in picks]
+    with ThreadPoolExecutor(8) as ex:          # the C oracle runs with the GIL released
+        refs = list(ex.map(lambda one: oracle_run(one, "extrapolate", extended=True), ones))
+    for k, one, ref in zip(picks, ones, refs):
         sub = {kk: v[:, 2 * k:2 * k + 2] for kk, v in got.items()}
         assert_state_close(sub, ref, one, what=f"pair {k} ({w['separations'][k]:.3e} m)")
 
@@ -103,7 +114,7 @@ def test_pair_workload_full_size_sampled_instances():
 def test_pairs_strided_outputs():
     w = I.workload_dipole_pairs(n_inst=6, steps=1000)
     got = gpu_run(w, "extrapolate", stride=7)
-    ref = oracle_run(w, "extrapolate", stride=7)
+    ref = oracle_run(w, "extrapolate", stride=7, extended=True)
     assert got["d"].shape == (1000 // 7 + 1, 12)
     assert_state_close(got, ref, w, what="strided")
 
@@ -335,3 +346,36 @@ def test_energy_balance_outputs(stepped_min_n):
         assert err.max() <= 1e-10, (k, err.max())
     W = (got["energy"] - got["W_abs"] + got["W_rad"]).sum(axis=1)
     assert np.abs(W - W[0]).max() <= 1e-7 * got["energy"][0].sum()
+
+
+def test_far_pairs_against_the_extended_oracle():
+    """Pairs 100 nm to 1 um apart, whose driven dipole sees the near-cancelling field of
+    two charges (cancellation ratio r up to 2e5), against the oracle's extended-precision
+    build (64-bit significand, 2^11 less cancellation error), 1,500 steps.  Printed: the
+    errors of the GPU's FP64 and mixed forms and of the FP64 oracle, in units of eps r of
+    the driven dipole.  For collinear (p) pairs the charges' fields cancel along the
+    separation and the mixed form is the more accurate; for side-by-side (s) pairs the
+    projected fields add and every form is at FP64 rounding."""
+    seps = [1e-7, 1.6e-7, 2.5e-7, 4e-7, 6.3e-7, 1e-6]
+    for orient in ("p", "s"):
+        w = I.workload_dipole_pairs(seps=seps, steps=1500, orientation=orient)
+        ref = oracle_run(w, "extrapolate", extended=True)
+        o64 = oracle_run(w, "extrapolate")
+        g64 = gpu_run(w, "extrapolate")
+        gmx = gpu_run(w, "extrapolate", precision="mixed")
+        sc = single_charge_scale(w)
+        for k, sep in enumerate(seps):
+            j = 2 * k + 1                      # the driven dipole
+            r = sc[j] / np.abs(ref["Ed"][:, j]).max()
+            den = np.abs(ref["d"][:, j]).max()
+            e = {name: np.abs(x["d"][:, j] - ref["d"][:, j]).max() / den for name, x in
+                 (("gpu_fp64", g64), ("gpu_mixed", gmx), ("oracle_fp64", o64))}
+            print(f"{orient} {sep:.2e} m r={r:.2e}: " +
+                  ", ".join(f"{n} {v:.2e} ({v / (EPS * r):.3f} eps r)" for n, v in e.items()), flush=True)
+            assert e["gpu_fp64"] <= max(TOL_STATE, TOL_CANCEL * EPS * r)
+            assert e["oracle_fp64"] <= max(TOL_STATE, 0.25 * EPS * r)
+            # the mixed form differences the two charges' static terms exactly, so it keeps
+            # the digits the per-charge FP64 form loses (measured 0.01 eps r)
+            assert e["gpu_mixed"] <= max(1e-13, 0.05 * EPS * r)
+            if orient == "p":
+                assert e["gpu_mixed"] < e["gpu_fp64"] / 4

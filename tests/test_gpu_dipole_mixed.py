@@ -66,10 +66,11 @@ def assert_mixed_close(got, ref, w, what, keys=("d", "d_dot", "energy", "Ed"), t
 
 def test_mixed_pairs_parity():
     """24 two-dipole instances of the pair recipe (1 nm - 1 um, a third closer than c dt),
-    1,500 steps with the extrapolation past the newest sample."""
+    1,500 steps with the extrapolation past the newest sample, against the oracle's
+    extended-precision build."""
     w = I.workload_dipole_pairs(n_inst=24, steps=1500)
     got = gpu_run(w, "extrapolate", precision="mixed")
-    ref = oracle_run(w, "extrapolate")
+    ref = oracle_run(w, "extrapolate", extended=True)
     assert_mixed_close(got, ref, w, "mixed pairs")
 
 
