@@ -250,7 +250,9 @@ enum { LW_STEPPED_TUNE = -2 };
  * h_dip.  Each dipole is driven by the component along its axis of the total
  * field at its origin of the other dipoles' charges in its instance, read at
  * their retarded times from the stored history (linear interpolation between
- * steps; static at d0 before t = 0).  All dipoles advance together.
+ * steps; static at d0 before t = 0).  All dipoles advance together.  The
+ * paper's run() followed by its extraction of the collective decay rates and
+ * frequency shift (Secs. 2.4, 3.2).
  * Outputs (device FP64, [steps/out_stride + 1][n_dip], row k = step k*stride):
  *   d_moment  moment d along the axis (required)
  *   d_dot     d d/dt                    (nullable)
@@ -262,14 +264,24 @@ enum { LW_STEPPED_TUNE = -2 };
  *             |d_ddot|^2 / (6 pi eps0 c^3) (nullable)
  *   (both by the trapezoid rule over steps; the sum over the dipoles of an
  *   instance of energy - wabs + wrad is the conserved W_total of Sec. 2.5)
+ * and, for two-dipole instances (host, nullable; when either is given the call
+ * synchronises `stream`, returns the run's latched errors as lw_sync_status
+ * does, and fits the moments copied back as lw_pair_modes does, with the first
+ * dipole's omega0 as reference and a transient of max(2000 steps, three light
+ * times of the separation) skipped):
+ *   h_gamma   [n_inst][2]: gamma+ and gamma-, the energy decay rates of the
+ *             in-phase and anti-phase modes (s^-1)
+ *   h_domega  [n_inst]: delta_omega = (omega+ - omega-)/2 (rad/s)
+ *   NaN for other instances, for a mode the run does not excite (delta_omega
+ *   then falls back as in lw_pair_modes) and for runs too short to fit.
  * Small instances run concurrently with the stepped ones on a second stream of
  * the context that is joined back into `stream` before the call's work ends.
- * Asynchronous: speed-limit, non-finite and history errors are reported by
- * lw_sync_status(). */
+ * Asynchronous unless h_gamma or h_domega is given: speed-limit, non-finite
+ * and history errors are reported by lw_sync_status(). */
 lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
                         int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts,
                         double *d_moment, double *d_dot, double *d_energy, double *d_drive,
-                        double *d_wabs, double *d_wrad, void *stream);
+                        double *d_wabs, double *d_wrad, double *h_gamma, double *h_domega, void *stream);
 
 /* Run state of an oscillator run, for checkpoints and resumed runs: the step
  * count, every dipole's history ring (the stored (d, d_dot, d_ddot) of the

@@ -775,6 +775,15 @@ static lw_status tune_stepped(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip
         if (hipMalloc((void **)&ctx->d_trial, need) != hipSuccess) return fail(LW_E_NOMEM, "tuner trial buffer");
         ctx->trial_cap = need;
     }
+    // The trials run the call's own dipoles for up to 512 steps, which may latch an
+    // error (speed limit, history) that the call itself, if shorter, never meets:
+    // the error word a caller has not read yet is saved, each candidate runs on a
+    // cleared word, a candidate whose trials latched anything is dropped, and the
+    // saved word is put back.
+    uint32_t saved_err = 0;
+    const uint32_t zero_err = 0;
+    LW_HIP(hipStreamSynchronize(s));
+    LW_HIP(hipMemcpy(&saved_err, ctx->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost));
     hipEvent_t ev[3];
     for (auto &e : ev) LW_HIP(hipEventCreate(&e));
     float best = 1e30f;
@@ -783,6 +792,8 @@ static lw_status tune_stepped(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip
         lw_run_opts o = *opts;
         o.stepped_min_n = T;
         float ms[2] = {0.f, 0.f};
+        if (hipMemcpy(ctx->d_err, &zero_err, sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess)
+            st = fail(LW_E_HIP, "tuner error word");
         for (int r = 0; r < 2 && st == LW_OK; ++r) {
             const int64_t n_steps = 256 << r;
             o.out_stride = n_steps;
@@ -795,6 +806,12 @@ static lw_status tune_stepped(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip
                 st = fail(LW_E_HIP, "tuner timing");
         }
         if (st != LW_OK) break;
+        uint32_t trial_err = 0;
+        if (hipMemcpy(&trial_err, ctx->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess) {
+            st = fail(LW_E_HIP, "tuner error word");
+            break;
+        }
+        if (trial_err) continue;                 // this threshold's trials did not run clean
         const float per_step = (ms[1] - ms[0]) / 256.0f;
         if (per_step < best) {
             best = per_step;
@@ -802,7 +819,14 @@ static lw_status tune_stepped(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip
         }
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
+    if (hipMemcpy(ctx->d_err, &saved_err, sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess && st == LW_OK)
+        st = fail(LW_E_HIP, "tuner error word");
     if (st != LW_OK) return st;
+    // no candidate ran clean: keep the default and do not cache a choice
+    if (best == 1e30f) {
+        *out = 16;
+        return LW_OK;
+    }
     ctx->tuned_dip[key] = *out;
     save_tune_dip(ctx, key, *out);
     return LW_OK;
@@ -987,10 +1011,41 @@ static lw_status dipole_run_impl(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_
 lw_status lw_dipole_run(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
                         int32_t n_inst, double dt, int64_t steps, const lw_run_opts *opts, double *d_moment,
                         double *d_dot, double *d_energy, double *d_drive, double *d_wabs, double *d_wrad,
-                        void *stream)
+                        double *h_gamma, double *h_domega, void *stream)
 {
-    return dipole_run_impl(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, steps, opts, d_moment, d_dot, d_energy, d_drive,
-                           d_wabs, d_wrad, nullptr, 0, false, stream);
+    lw_status st = dipole_run_impl(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, steps, opts, d_moment, d_dot, d_energy,
+                                   d_drive, d_wabs, d_wrad, nullptr, 0, false, stream);
+    if (st != LW_OK || (!h_gamma && !h_domega)) return st;
+    // collective rates and shift of the two-dipole instances (Sec. 2.4): wait for
+    // the run (its latched errors are returned first), copy the moments back and
+    // fit the normal modes after the transient of each pair
+    st = lw_sync_status(ctx, stream);
+    if (st != LW_OK) return st;
+    const int64_t stride = opts->out_stride;
+    const int64_t rows = steps / stride + 1;
+    std::vector<double> mom((size_t)rows * (size_t)n_dip);
+    LW_HIP(hipMemcpy(mom.data(), d_moment, sizeof(double) * mom.size(), hipMemcpyDeviceToHost));
+    std::vector<double> w_ref((size_t)n_inst), modes(5 * (size_t)n_inst);
+    std::vector<int64_t> skip((size_t)n_inst, 0);
+    for (int k = 0; k < n_inst; ++k) {
+        const int a = h_inst_off[k];
+        w_ref[k] = h_inst_off[k + 1] > a ? h_dip[a].omega0 : 1.0;
+        if (h_inst_off[k + 1] - a != 2) continue;
+        double d[3];
+        for (int i = 0; i < 3; ++i) d[i] = h_dip[a + 1].origin[i] - h_dip[a].origin[i];
+        skip[k] = std::max<int64_t>(2000, (int64_t)std::ceil(3.0 * norm3(d) / (C_LIGHT * dt)));
+    }
+    st = lw_pair_modes(mom.data(), rows, n_dip, h_inst_off, n_inst, dt, stride, w_ref.data(), skip.data(),
+                       modes.data());
+    if (st != LW_OK) return st;
+    for (int k = 0; k < n_inst; ++k) {
+        if (h_gamma) {
+            h_gamma[2 * k] = modes[5 * k];
+            h_gamma[2 * k + 1] = modes[5 * k + 1];
+        }
+        if (h_domega) h_domega[k] = modes[5 * k + 4];
+    }
+    return LW_OK;
 }
 
 lw_status lw_dipole_run_state(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_dip, const int32_t *h_inst_off,
@@ -1170,7 +1225,7 @@ static lw_status vjp_pipelined(lw_ctx *ctx, const lw_dipole *h_dip, int32_t n_di
         // forward run with every step stored, then the whole history
         fo.out_stride = 1;
         st = lw_dipole_run(ctx, h_dip, n_dip, h_inst_off, n_inst, dt, steps, &fo, d_D, d_V, nullptr, d_Ed, nullptr,
-                           nullptr, stream);
+                           nullptr, nullptr, nullptr, stream);
         if (st != LW_OK) return st;
         LW_HIP(lw::launch_hist_rows(d_dev, d_D, d_V, d_Ed, n_dip, steps + 1, 0, (int)ring_h, d_hist, s));
     } else {

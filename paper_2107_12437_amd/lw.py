@@ -103,7 +103,7 @@ def load_library(path: str = LIB_PATH):
                                     vp, vp]
     L.lw_fields_vjp.argtypes = [vp, ct.POINTER(Traj), i32, vp, i64, ct.POINTER(dbl), i32, ct.POINTER(Opts), vp, vp, vp]
     L.lw_dipole_run.argtypes = [vp, ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, i64,
-                                ct.POINTER(RunOpts), vp, vp, vp, vp, vp, vp, vp]
+                                ct.POINTER(RunOpts), vp, vp, vp, vp, vp, vp, ct.POINTER(dbl), ct.POINTER(dbl), vp]
     L.lw_dipole_run_state.argtypes = [vp, ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, i64,
                                       ct.POINTER(RunOpts), vp, vp, vp, vp, vp, vp, vp, i64, i32, vp]
     L.lw_dipole_state_size.argtypes = [ct.POINTER(Dipole), i32, ct.POINTER(i32), i32, dbl, ct.POINTER(RunOpts),
@@ -353,7 +353,8 @@ def dipole_state(dipoles: dict, inst_off, dt: float, policy: str = "strict", rin
 def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "strict", out_stride: int = 1,
                max_vel: float = 0.0, ring_depth: int = 0, stepped_min_n: int | str = 0, device=None,
                check: bool = True, ctx: Context | None = None, energy_balance: bool = False,
-               precision: str = "fp64", state: torch.Tensor | None = None, resume: bool = False):
+               precision: str = "fp64", state: torch.Tensor | None = None, resume: bool = False,
+               modes: bool = False):
     """Self-consistent oscillator run (Algorithm 1).  Returns a dict of [n_out][n_dip]
     float64 GPU tensors: d, d_dot, energy, Ed, and with energy_balance the work absorbed
     from the drive field W_abs and the Larmor energy radiated W_rad since t = 0 (Sec. 2.5:
@@ -362,7 +363,9 @@ def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "st
     FP64).  With a run state (dipole_state) the run's state after its last step is kept
     there, and resume=True continues the run that state holds: row 0 is then the state's
     step and `steps` more are taken.  stepped_min_n="tune" lets the library time the
-    instance-size threshold of the stepped path for this shape class (cached)."""
+    instance-size threshold of the stepped path for this shape class (cached).  modes=True
+    also returns, from the library, numpy arrays gamma [n_inst][2] (gamma+, gamma-) and
+    delta_omega [n_inst] of the two-dipole instances (the call then synchronises)."""
     dev = _as_device(device)
     ctx = ctx or default_context(dev.index)
     arr, n = pack_dipoles(dipoles)
@@ -380,8 +383,17 @@ def dipole_run(dipoles: dict, inst_off, dt: float, steps: int, policy: str = "st
     if state is None:
         if resume:
             raise ValueError("resume needs a run state")
-        _check(L.lw_dipole_run(*args, _stream_ptr(dev)))
+        n_inst = len(off) - 1
+        gam = np.full((n_inst, 2), np.nan) if modes else None
+        dom = np.full(n_inst, np.nan) if modes else None
+        dp = ct.POINTER(ct.c_double)
+        _check(L.lw_dipole_run(*args, gam.ctypes.data_as(dp) if modes else None,
+                               dom.ctypes.data_as(dp) if modes else None, _stream_ptr(dev)))
+        if modes:
+            res["gamma"], res["delta_omega"] = gam, dom
     else:
+        if modes:
+            raise ValueError("modes are fitted by dipole_run without a run state")
         if not (state.is_cuda and state.dtype == torch.float64 and state.is_contiguous()):
             raise ValueError("state must be a contiguous float64 GPU tensor (dipole_state)")
         _check(L.lw_dipole_run_state(*args, ct.c_void_p(state.data_ptr()), state.numel(), int(bool(resume)),

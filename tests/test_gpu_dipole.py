@@ -18,6 +18,7 @@ tests keep the FP64 oracle under the same bound (0.22 + 0.06 eps r < 0.5 eps r).
 Collective rates and shifts extracted from the moments agree to 1e-4 of gamma_0.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -33,6 +34,7 @@ TOL_STATE = 1e-11
 TOL_DRIVE = 1e-13
 TOL_CANCEL = 0.5          # state tolerance per eps r of the drive's cancellation (measured <= 0.22)
 TOL_MIXED_STATE = 1e-5
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
 EPS = 2.220446049250313e-16
 
 
@@ -56,11 +58,10 @@ def single_charge_scale(w):
     k = 1 / (4 * math.pi * 8.8541878128e-12)
     sc = np.zeros(len(dip["omega0"]))
     for a0, a1 in zip(off[:-1], off[1:]):
-        for i in range(a0, a1):
-            for j in range(a0, a1):
-                if i != j:
-                    L2 = np.sum((dip["origin"][i] - dip["origin"][j]) ** 2)
-                    sc[i] += 2 * k * dip["q"][j] / L2
+        o = np.asarray(dip["origin"])[a0:a1]
+        L2 = ((o[:, None, :] - o[None, :, :]) ** 2).sum(axis=2)
+        np.fill_diagonal(L2, np.inf)
+        sc[a0:a1] = (2 * k * np.asarray(dip["q"])[a0:a1][None, :] / L2).sum(axis=1)
     return sc
 
 
@@ -164,14 +165,18 @@ def test_large_cluster_global_ring():
 
 def test_gamma_domega_parity():
     """Collective rates and shift of 8 pairs extracted on the host from the GPU moments and
-    from the oracle's moments: within 1e-4."""
+    from the oracle's moments: within 1e-4.  lw_dipole_run's own gamma / delta_omega
+    outputs are the same fit of the same moments, bitwise."""
     from paper_2107_12437_amd import lw
     w = I.workload_dipole_pairs(n_inst=8, steps=8000)
-    got = gpu_run(w, "extrapolate", stride=2)
+    r = lw.dipole_run(w["dipoles"], w["inst_off"], w["dt"], w["steps"], policy="extrapolate", out_stride=2,
+                      modes=True)
+    got = {k: v.cpu().numpy() for k, v in r.items() if k not in ("gamma", "delta_omega")}
     ref = oracle_run(w, "extrapolate", stride=2)
     w0 = w["dipoles"]["omega0"][0]
     skips = [X.default_skip(w["dt"], s) for s in w["separations"]]
     modes = lw.pair_modes(got["d"], w["inst_off"], w["dt"], 2, w0, skips)
+    assert np.array_equal(r["gamma"], modes[:, :2]) and np.array_equal(r["delta_omega"], modes[:, 4])
     g0 = lw.gamma0(I.E_CHARGE, I.M_E / 2, w0)
     for k in range(8):
         r = X.pair_modes(ref["d"][:, 2 * k], ref["d"][:, 2 * k + 1], w["dt"], 2, w0, skips[k])
@@ -379,3 +384,37 @@ def test_far_pairs_against_the_extended_oracle():
             assert e["gpu_mixed"] <= max(1e-13, 0.05 * EPS * r)
             if orient == "p":
                 assert e["gpu_mixed"] < e["gpu_fp64"] / 4
+
+
+def test_all_clusters_against_oracle_runs():
+    """All 64 clusters of the uneven-cluster workload (12,530 dipoles, 2 to 955 per cluster)
+    for 20 steps in the launch configuration bench.py times (tuned path choice, moments
+    every 10th step), against the oracle run of every cluster alone
+    (tests/golden/c5a_clusters_20steps.npz, written by make_goldens.py from the oracle)."""
+    w = I.workload_clusters(steps=20)
+    ref = dict(np.load(os.path.join(GOLD, "c5a_clusters_20steps.npz")))
+    got = gpu_run(w, "strict", stride=10, stepped_min_n="tune")
+    assert ref["d"].shape == got["d"].shape
+    assert_state_close(got, ref, w, keys=("d", "d_dot", "Ed"), what="64 clusters x 20 steps")
+
+
+def test_smallest_clusters_full_length_against_oracle_runs():
+    """The whole 50,000-step run of the uneven-cluster batch in the launch configuration
+    bench.py times (moments every 5,000th step); its 16 smallest clusters (2 to 12 dipoles)
+    against their oracle runs (tests/golden/c5b_smallest16_50000steps.npz), at the same
+    state tolerance as the short runs (measured: 2.6e-14 of each dipole's largest moment;
+    the runs are linear and damped, so rounding does not grow over the run)."""
+    w = I.workload_clusters(steps=50000)
+    ref = dict(np.load(os.path.join(GOLD, "c5b_smallest16_50000steps.npz")))
+    got = gpu_run(w, "strict", stride=5000, stepped_min_n="tune")
+    off = np.asarray(w["inst_off"])
+    cols = np.concatenate([np.arange(off[c], off[c + 1]) for c in ref["clusters"]])
+    sub_w = {"dipoles": {k: np.asarray(v)[cols] for k, v in w["dipoles"].items()},
+             "inst_off": np.concatenate([[0], np.cumsum([off[c + 1] - off[c] for c in ref["clusters"]])]),
+             "dt": w["dt"], "steps": w["steps"]}
+    sub = {k: got[k][:, cols] for k in ("d", "d_dot", "Ed")}
+    scale = np.abs(ref["d"]).max(axis=0)
+    err = (np.abs(sub["d"] - ref["d"]) / scale).max()
+    print(f"16 smallest clusters x 50,000 steps: max moment error {err:.3e} of each dipole's largest")
+    assert_state_close(sub, {k: ref[k] for k in ("d", "d_dot", "Ed")}, sub_w, keys=("d", "d_dot", "Ed"),
+                       what="16 smallest clusters x 50,000 steps")

@@ -57,3 +57,28 @@ def test_tuned_threshold_is_cached_and_used(tmp_path, monkeypatch, precision):
     assert len(dip_lines(f)) == 1
     for k in a:
         assert np.array_equal(a[k], c[k]), k
+
+
+def test_tuner_trials_do_not_leak_errors(tmp_path, monkeypatch):
+    """The tuner's trial runs (256 and 512 steps) may cross the speed limit where the call
+    itself does not: a 20-step tuned call whose charges reach 0.59 of their peak speed
+    (peak at step 50) under a limit of 0.8 of it must report no error, and an error
+    latched by an earlier call and not yet read must survive the tuning."""
+    from paper_2107_12437_amd import lw
+    monkeypatch.setenv("LW_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    w0 = 2 * math.pi * 200e12
+    dip = I.cluster_dipoles(I.rng_for(86), 3, 20e-9, 10e-9, w0, 0.0, False)
+    dip["d0"][:] = I.E_CHARGE * 1e-12
+    dt = 1 / 200e12 / 200
+    peak = 0.5 * w0 * 1e-12                   # charge speed: half the moment's rate over q
+    ctx = lw.Context(0)
+    r = lw.dipole_run(dip, [0, 3], dt, 20, max_vel=0.8 * peak, stepped_min_n="tune", ctx=ctx)
+    assert np.isfinite(r["d"].cpu().numpy()).all()
+    # a pending error survives a tuned call of a new shape class
+    lw.dipole_run(dip, [0, 3], dt, 120, max_vel=0.8 * peak, ctx=ctx, check=False)
+    dip5 = I.cluster_dipoles(I.rng_for(87), 5, 25e-9, 10e-9, w0, 0.0, False)
+    lw.dipole_run(dip5, [0, 5], dt, 20, stepped_min_n="tune", ctx=ctx, check=False)
+    with pytest.raises(lw.LWError) as ei:
+        lw.sync_status(ctx)
+    assert ei.value.code == 4
+    ctx.close()
