@@ -199,6 +199,37 @@ def dipole_cpu_baseline(pw: dict, I) -> dict:
             "cpu_model": hcpu["model"], "physical_cores": hcpu["physical_cores"]}
 
 
+def paper_regime(I, lw, np) -> dict:
+    """Sec. 4.2 in the paper's own regime: in-phase s and p pairs at 16 separations from
+    7.5 nm to 1 um, dt = T0/1e4, 40,000 steps, all 32 pairs in one lw_dipole_run call with
+    its gamma / delta_omega outputs; mean and max relative errors of delta_12 (relative to
+    max(|delta_12|, gamma_0)) and gamma+ against the Green's-function rates, beside the
+    means the paper reports (Fig. 9 caption)."""
+    w0 = 2 * math.pi * 200e12
+    seps = np.geomspace(7.5e-9, 1e-6, 16)
+    ws = [I.workload_dipole_pairs(seps=seps, orientation=o, steps=40000, steps_per_period=10000, d0_both=True)
+          for o in ("p", "s")]
+    dip = I.concat_dipoles([w["dipoles"] for w in ws])
+    off = np.arange(0, 4 * len(seps) + 1, 2, dtype=np.int32)
+    t0 = time.perf_counter()
+    r = lw.dipole_run(dip, off, ws[0]["dt"], 40000, out_stride=5, modes=True)
+    sec = time.perf_counter() - t0
+    g0 = lw.gamma0(I.E_CHARGE, I.M_E / 2, w0)
+    out = {"workload": "32 in-phase pairs (16 separations 7.5 nm - 1 um, s and p), T0/1e4, 40,000 steps",
+           "ms": round(sec * 1e3, 2), "paper_mean_rel": {"p": [0.0015, 0.0004], "s": [0.0019, 0.0013]}}
+    for oi, o in enumerate(("p", "s")):
+        axis = np.array([1.0, 0.0, 0.0]) if o == "p" else np.array([0.0, 1.0, 0.0])
+        ed, eg = [], []
+        for k, R in enumerate(seps):
+            d12, g12 = lw.gf_pair(np.array([R, 0.0, 0.0]), axis, axis, w0)
+            inst = oi * len(seps) + k
+            ed.append(abs(r["delta_omega"][inst] / g0 - d12) / max(abs(d12), 1.0))
+            eg.append(abs(r["gamma"][inst, 0] / g0 - (1 + g12)) / (1 + g12))
+        out[o] = {"delta12_mean_rel": float(np.mean(ed)), "gamma_plus_mean_rel": float(np.mean(eg)),
+                  "delta12_max_rel": float(np.max(ed)), "gamma_plus_max_rel": float(np.max(eg))}
+    return out
+
+
 def tuned_threshold(precision: str):
     """The stepped-path threshold the library tuned for the last oscillator shape class of
     this precision, from the tuning file (LW_TUNE_CACHE); None if there is none."""
@@ -407,6 +438,12 @@ def main():
                     "the rates are within 0.2 % of the theory (GPU tests)"}
         log(f"[bench] dipoles vs Green's function ({len(eg)} pairs): gamma+ rel max {max(eg):.2e} "
             f"(median {np.median(eg):.2e}), delta_omega max {max(ed):.2e} (median {np.median(ed):.2e})")
+        dip["paper_regime"] = paper_regime(I, lw, np)
+        log(f"[bench] paper regime (T0/1e4, 16 separations): p delta12 "
+            f"{100 * dip['paper_regime']['p']['delta12_mean_rel']:.3f} % gamma+ "
+            f"{100 * dip['paper_regime']['p']['gamma_plus_mean_rel']:.3f} %, s delta12 "
+            f"{100 * dip['paper_regime']['s']['delta12_mean_rel']:.3f} % gamma+ "
+            f"{100 * dip['paper_regime']['s']['gamma_plus_mean_rel']:.3f} %")
         if not args.no_cpu_baseline:
             dip["cpu_baseline"] = dipole_cpu_baseline(pw, I)
             log(f"[bench] oracle pairs: {dip['cpu_baseline']['value']:.3e} dipole-steps/s on "

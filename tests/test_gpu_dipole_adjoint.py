@@ -7,7 +7,9 @@ noise is about 2e-7 relative and the truncation 1e-8.  Richardson extrapolation 
 h and 2h central differences removes the h^2 term; the adjoint must agree to 1e-6
 (relative L2 over the gradient).
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -147,3 +149,46 @@ def test_large_instance_directional_derivative():
     vals = [(J_at(h) - J_at(-h)) / (2 * h) for h in (1e-12, 2e-12)]
     fd = (4 * vals[0] - vals[1]) / 3
     assert abs((g * v).sum() - fd) <= 1e-5 * np.linalg.norm(g), ((g * v).sum(), fd, np.linalg.norm(g))
+
+
+def test_full_length_checkpointed_gradient_against_oracle_differences():
+    """The 32-dipole adjoint workload for its full 5,000 steps, checkpointed every 250
+    steps (the workload's setting), observed on a 64x64 detector over the same plane at
+    its 32 snapshots: dJ/dR of 8 seeded origin coordinates against the central
+    differences of the oracle's extended-precision build at h = 1e-6 max(|R|, 1 nm)
+    (tests/golden/c4b_dipole_detector_fd.json, written by make_goldens.py from the oracle
+    alone), to 1e-6 of each entry plus 1e-8 of the largest."""
+    import torch
+    from paper_2107_12437_amd import lw
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c4b_dipole_detector_fd.json")))
+    w = I.workload_dipole_detector()
+    assert g["workload"] == w["name"]
+    dpts = torch.tensor(I.plane_grid(100e-9, 64, z=200e-9), dtype=torch.float64, device="cuda")
+    J, grad = lw.dipole_run_vjp(w["dipoles"], w["inst_off"], w["dt"], w["steps"], dpts, w["times"],
+                                ckpt_every=w["ckpt_every"])
+    grad = grad.cpu().numpy()
+    big = max(abs(e["dJ"]) for e in g["entries"])
+    rel = []
+    for e in g["entries"]:
+        got = grad[e["dipole"], e["axis"]]
+        rel.append(abs(got - e["dJ"]) / abs(e["dJ"]))
+        assert abs(got - e["dJ"]) <= 1e-6 * abs(e["dJ"]) + 1e-8 * big, (e, got)
+    print(f"checkpointed oscillator gradient vs oracle differences: max relative error {max(rel):.2e}")
+
+
+def test_repeatability_of_the_atomic_sums():
+    """The adjoint accumulates history and position cotangents with FP64 device atomics, so
+    two calls agree to rounding, not bitwise: the 32-dipole workload (500 steps, 32x32
+    detector) twice, gradients within 1e-12 of the largest entry and J bitwise (J's sums
+    run in a fixed order)."""
+    import torch
+    from paper_2107_12437_amd import lw
+    w = I.workload_dipole_detector(steps=500, grid_n=32)
+    dpts = torch.tensor(w["points"], dtype=torch.float64, device="cuda")
+    J1, g1 = lw.dipole_run_vjp(w["dipoles"], w["inst_off"], w["dt"], w["steps"], dpts, w["times"])
+    J2, g2 = lw.dipole_run_vjp(w["dipoles"], w["inst_off"], w["dt"], w["steps"], dpts, w["times"])
+    g1, g2 = g1.cpu().numpy(), g2.cpu().numpy()
+    spread = np.abs(g1 - g2).max() / np.abs(g1).max()
+    print(f"oscillator adjoint run-to-run spread: {spread:.2e} of the largest entry")
+    assert J1 == J2
+    assert spread <= 1e-12
