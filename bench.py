@@ -41,8 +41,8 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0) counters, calibrated on a plain 1 GiB copy
 # (profiles/fields_kernel_mixed_grid512x512x64t.md).  Valid only for the kernel
 # sources they were taken on; reported as null once those change.
-TRAFFIC_BYTES = 682.0e6
-TRAFFIC_SOURCES_SHA = "9f69e8271795bf4a"
+TRAFFIC_BYTES = 682.1e6
+TRAFFIC_SOURCES_SHA = "d5a1bcfe3df66ada"
 # Algorithmic FP64 work per charge-pair drive of the oscillator step (one source
 # charge seen by one target dipole at one stage time), counted from the method's
 # definition: the retarded time on the interpolated history (30 flops, one
@@ -256,6 +256,9 @@ def main():
                     help="steps of the uneven-cluster workload to time (its full run: 50,000)")
     ap.add_argument("--grid-only", action="store_true",
                     help="time only the mixed grid step (for profiler runs)")
+    ap.add_argument("--grid-family", choices=("mix", "circular", "linear", "accel", "uniform"), default="mix",
+                    help="with --grid-only: the benchmark's charges (mix), or 16 charges of one trajectory family "
+                         "on the same grid and times, in both precisions (per-family cost)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="precision of the cluster run in --part clusters")
     ap.add_argument("--part", choices=("pairs", "clusters", "grid-vjp", "adjoint"), default=None,
@@ -310,6 +313,15 @@ def main():
     pts = torch.tensor(w["points"], dtype=torch.float64, device="cuda")
     n_pts, n_ch, n_t = pts.shape[1], len(w["charges"]["kind"]), len(w["times"])
     evals = n_pts * n_ch * n_t
+    if args.grid_only and args.grid_family != "mix":
+        fam = {"circular": I.CIRCULAR, "linear": I.LINEAR_OSC, "accel": I.ACCEL}
+        ch = (I.workload_uniform_velocity()["charges"] if args.grid_family == "uniform" else
+              I.random_grid_charges(I.rng_for(2), n_ch, families=(fam[args.grid_family],)))
+        for prec in ("mixed", "fp64"):
+            _, kms = timed_calls(lw.FieldsCall(ch, pts, w["times"], precision=prec), args.steps, args.warmup)
+            log(f"[bench] {args.grid_family} {prec}: kernel {kms:.3f} ms, "
+                f"{kms * 1e-3 * PEAK_VALU_TFLOPS * 1e12 / 2 / evals:.0f} time-equivalent lane-instructions per eval")
+        return
 
     log(f"[bench] mixed grid: {n_pts} points x {n_ch} charges x {n_t} times")
     mixed = lw.FieldsCall(w["charges"], pts, w["times"], precision="mixed")

@@ -291,6 +291,10 @@ struct Geo {
     double lo, hi;    // bracket on c tau / c (circular, linear)
     double tau0;      // starting value (circular, linear)
     double cw, sw;    // cos, sin of omega tau0
+    // the correction form (circular, linear; see solve_u_mixed), lengths in units of
+    // D0 = c tau0: w1h = w1 / D0, w2h = w2 / D0 (circular), Ah = A / D0, kh = omega tau0,
+    // K0h = (W + A^2 - D0^2) / D0^2 (circular) or (W - D0^2) / D0^2 (linear), W = |x - c0|^2
+    double w1h, w2h, Ah, kh, K0h;
 };
 
 __device__ __forceinline__ void geo_prepare(const SrcRec &S, const double x[3], Geo &g)
@@ -313,6 +317,12 @@ __device__ __forceinline__ void geo_prepare(const SrcRec &S, const double x[3], 
         g.hi = sqrt_rough(w3 * w3 + (rho + A) * (rho + A)) * (INV_C * (1.0 + 1e-6));
         g.tau0 = fmin(fmax(sqrt_rough(WA) * INV_C, g.lo), g.hi);
         sincos_reduced(S.omega * g.tau0, g.sw, g.cw);
+        const double D0 = C_LIGHT * g.tau0, iD0 = rcp_steer(D0);
+        g.w1h = w1 * iD0;
+        g.w2h = w2 * iD0;
+        g.Ah = A * iD0;
+        g.kh = S.omega * g.tau0;
+        g.K0h = fma(-D0, D0, WA) * (iD0 * iD0);
     } else if (S.kind == K_LINEAR_OSC || S.kind == K_ACCEL) {
         const double w1 = g.w1;
         const double p0 = w[0] - w1 * S.e1[0], p1 = w[1] - w1 * S.e1[1], p2 = w[2] - w1 * S.e1[2];
@@ -325,6 +335,12 @@ __device__ __forceinline__ void geo_prepare(const SrcRec &S, const double x[3], 
             g.hi = sqrt_rough(W2 + A * A + 2.0 * A * fabs(w1)) * (INV_C * (1.0 + 1e-6));
             g.tau0 = fmin(fmax(sqrt_rough(W2 + 0.5 * A * A) * INV_C, g.lo), g.hi);
             sincos_reduced(S.omega * g.tau0, g.sw, g.cw);
+            const double D0 = C_LIGHT * g.tau0, iD0 = rcp_steer(D0);
+            g.w1h = w1 * iD0;
+            g.w2h = 0.0;
+            g.Ah = A * iD0;
+            g.kh = S.omega * g.tau0;
+            g.K0h = fma(-D0, D0, W2) * (iD0 * iD0);
         }
     }
 }
@@ -490,6 +506,209 @@ __device__ __forceinline__ void solve_uniform(const SrcRec &S, const double x[3]
     k.flags = 0u;
 }
 
+// Mixed path, circular and linear orbits: the retarded time as a correction to
+// the start, tau = tau0 (1 + u), in units of D0 = c tau0.  With the phase
+// theta = theta0 - kh u (theta0 = Theta - omega tau0, kh = omega tau0), the
+// condition (c tau)^2 = D^2 reads, for the circular orbit,
+//   f(u) = u (2 + u) + 2 Ah P(theta) - K0h = 0,  P = w1h cos theta + w2h sin theta,
+// and for the linear oscillation
+//   f(u) = u (2 + u) - K0h + 2 Ah w1h cos theta - Ah^2 cos^2 theta = 0.
+// f = (c tau - D)(c tau + D) / D0^2 has the root of Eq. (ret_t) as its only root
+// with u > -1, needs no square root, and its terms are all of the size of
+// Ah, so it is solved in FP32: Halley steps until a step is below 2^-10, the
+// phase rotated from theta0 by -kh u with short Taylor polynomials (|kh u| is at
+// most the charge's speed over c).  FP32 rounding of f, amplified by kh, leaves
+// the root's phase good to about 1e-7 rad; one Newton step in FP64 from the FP64
+// phase theta0 then squares the remaining error (phase error below 1e-9 rad).
+// Returns false (the caller takes the safeguarded solver instead) when the FP32
+// steps do not settle or leave the physical range.
+__device__ __forceinline__ void rot_small_f32(float c0, float s0, float a, float &c, float &s)
+{
+    // sin a and cos a through a^9 and a^10 (truncation below 1e-9 for |a| <= 0.75)
+    const float a2 = a * a;
+    const float sa = a * fmaf(a2, fmaf(a2, fmaf(a2, fmaf(a2, 1.f / 362880.f, -1.f / 5040.f), 1.f / 120.f), -1.f / 6.f), 1.f);
+    const float ca = fmaf(a2, fmaf(a2, fmaf(a2, fmaf(a2, fmaf(a2, -1.f / 3628800.f, 1.f / 40320.f), -1.f / 720.f),
+                                           1.f / 24.f), -0.5f), 1.f);
+    c = c0 * ca - s0 * sa;
+    s = s0 * ca + c0 * sa;
+}
+
+template <int KIND>
+__device__ __forceinline__ bool solve_u_mixed(const SrcRec &S, const Geo &g, Kin &k)
+{
+    // phase at tau0 for this observation time (FP64)
+    const double c0 = S.cT * g.cw + S.sT * g.sw;
+    const double s0 = S.sT * g.cw - S.cT * g.sw;
+    const float c0f = (float)c0, s0f = (float)s0;
+    const float w1f = (float)g.w1h, w2f = (float)g.w2h, Af = (float)g.Ah, kf = (float)g.kh, K0f = (float)g.K0h;
+    float u = 0.f, c = c0f, s = s0f;
+    bool ok = false;
+    for (int it = 0; it < 4; ++it) {
+        float fv, fp, fpp;
+        if (KIND == K_CIRCULAR) {
+            const float P = fmaf(w1f, c, w2f * s), Q = fmaf(w2f, c, -w1f * s);
+            fv = fmaf(u, 2.f + u, fmaf(2.f * Af, P, -K0f));
+            fp = fmaf(-2.f * Af * kf, Q, 2.f + 2.f * u);
+            fpp = fmaf(-2.f * Af * kf * kf, P, 2.f);
+        } else {
+            const float gx = fmaf(-Af, c, w1f);                  // w1h - Ah cos theta
+            fv = fmaf(u, 2.f + u, fmaf(2.f * Af * w1f, c, fmaf(-Af * Af * c, c, -K0f)));
+            fp = fmaf(2.f * Af * kf * s, gx, 2.f + 2.f * u);
+            fpp = fmaf(-2.f * Af * kf * kf, fmaf(c, gx, -Af * s * s), 2.f);
+        }
+        const float fp2 = fp * fp;
+        float den = fmaf(2.f, fp2, -fv * fpp);
+        den = den > fp2 ? den : 2.f * fp2;
+        const float d = -2.f * fv * fp * __builtin_amdgcn_rcpf(den);
+        u += d;
+        if (fabsf(d) <= 0x1p-10f) {
+            ok = true;
+            break;
+        }
+        rot_small_f32(c0f, s0f, -kf * u, c, s);
+    }
+    const double a = -g.kh * (double)u;
+    if (!ok || !(fabs(a) <= 0.75) || !(u > -0.5f)) return false;
+    // one Newton step in FP64 from the exact phase
+    const double a2 = a * a;
+    const double sa = a * fma_k(a2, fma_k(a2, fma_k(a2, fma_k(a2, fma_k(a2, -1.0 / 39916800.0, 1.0 / 362880.0),
+                                                          -1.0 / 5040.0), 1.0 / 120.0), -1.0 / 6.0), 1.0);
+    const double ca = fma_k(a2, fma_k(a2, fma_k(a2, fma_k(a2, fma_k(a2, fma_k(a2, 1.0 / 479001600.0, -1.0 / 3628800.0),
+                                                                   1.0 / 40320.0), -1.0 / 720.0), 1.0 / 24.0), -0.5), 1.0);
+    double cd = c0 * ca - s0 * sa, sd = s0 * ca + c0 * sa;
+    double ud = (double)u, fv, fp;
+    if (KIND == K_CIRCULAR) {
+        const double P = fma(g.w1h, cd, g.w2h * sd), Q = fma(g.w2h, cd, -g.w1h * sd);
+        fv = fma(ud, 2.0 + ud, fma(2.0 * g.Ah, P, -g.K0h));
+        fp = fma(-2.0 * g.Ah * g.kh, Q, 2.0 + 2.0 * ud);
+    } else {
+        const double gx = fma(-g.Ah, cd, g.w1h);
+        fv = fma(ud, 2.0 + ud, fma(2.0 * g.Ah * g.w1h, cd, fma(-g.Ah * g.Ah * cd, cd, -g.K0h)));
+        fp = fma(2.0 * g.Ah * g.kh * sd, gx, 2.0 + 2.0 * ud);
+    }
+    const double du = -fv * rcp_steer(fp);
+    ud += du;
+    // rotate the phase by the correction's angle e (|e| below 1e-6: second order suffices)
+    const double e = -g.kh * du, ce = fma(-0.5 * e, e, 1.0);
+    const double cn = cd * ce - sd * e, sn = sd * ce + cd * e;
+    const double tau = fma(g.tau0, ud, g.tau0);
+    k.flags = 0u;
+    k.tp = S.t - tau;
+    k.cph = cn;
+    k.sph = sn;
+    const double A = S.amp;
+    const float cf = (float)cn, sf = (float)sn;
+    if (KIND == K_CIRCULAR) {
+        for (int i = 0; i < 3; ++i) {
+            k.R[i] = g.w[i] - A * (cn * S.e1[i] + sn * S.e2[i]);
+            k.bf[i] = cf * S.bw2[i] - sf * S.bw1[i];
+            k.df[i] = -(cf * S.aw1[i] + sf * S.aw2[i]);
+        }
+    } else {
+        for (int i = 0; i < 3; ++i) {
+            k.R[i] = g.w[i] - A * cn * S.e1[i];
+            k.bf[i] = -sf * S.bw1[i];
+            k.df[i] = -cf * S.aw1[i];
+        }
+    }
+    return true;
+}
+
+// Mixed path, uniform acceleration from rest: the same correction form,
+// tau = tau0 (1 + u) with tau0 = D0 / c the light time from the charge's
+// position at t (distance D0).  With L = a t^2 / 2 travelled by t and
+//   m = a tau (2t - tau) / 2   (tau <= t),   m = L   (tau > t, before the start),
+// the charge sits at L - m along e1 at t - tau, so with X = w1 - L
+//   f(u) = u (2 + u) - mh (2 Xh + mh) - K0h,  mh = m / D0 = (a / 2c)(1 + u)(2t - tau),
+// K0h = (perp^2 + X^2 - D0^2) / D0^2, where m and its first derivative are
+// continuous at the start of the motion.  FP32 Halley steps, then one FP64
+// Newton step, as for the oscillating families.  f has one root with u > -1
+// and f' > 0 around it (f' = 2 (c^2 tau - x1 v) / (c tau0)^2 with |x1 v| < c D),
+// so a lane whose FP32 steps did not settle continues with FP64 Newton steps
+// (up to 30) instead of a separate bracketed solver, whose registers would
+// spill the kernel; only if those fail too is the point flagged.
+__device__ __forceinline__ bool solve_u_accel(const SrcRec &S, const Geo &g, Kin &k)
+{
+    const double t = S.t, acc = S.accel, L = S.Lmax;
+    const double X = g.w1 - L;
+    const double Dn2 = fma(X, X, g.w2);
+    const double D0 = sqrt_rough(Dn2);
+    if (!(D0 > 0.0)) return false;
+    const double iD0 = rcp_steer(D0), tau0 = D0 * INV_C;
+    const double Xh = X * iD0, K0h = fma(-D0, D0, Dn2) * (iD0 * iD0), gh = acc * (0.5 * INV_C), Lh = L * iD0;
+    const float Xf = (float)Xh, K0f = (float)K0h, gf = (float)gh, Lf = (float)Lh, tf = (float)t, t0f = (float)tau0;
+    float u = 0.f;
+    bool ok = false;
+    for (int it = 0; it < 6; ++it) {
+        const float tau = fmaf(t0f, u, t0f);
+        const bool moving = tau < tf;
+        const float m = moving ? gf * (1.f + u) * (2.f * tf - tau) : Lf;
+        const float mp = moving ? 2.f * gf * (tf - tau) : 0.f;
+        const float mpp = moving ? -2.f * gf * t0f : 0.f;
+        const float xm = Xf + m;
+        const float fv = fmaf(u, 2.f + u, fmaf(-m, Xf + xm, -K0f));
+        const float fp = fmaf(-2.f * mp, xm, 2.f + 2.f * u);
+        const float fpp = fmaf(-2.f, fmaf(mpp, xm, mp * mp), 2.f);
+        const float fp2 = fp * fp;
+        float den = fmaf(2.f, fp2, -fv * fpp);
+        den = den > fp2 ? den : 2.f * fp2;
+        const float d = -2.f * fv * fp * __builtin_amdgcn_rcpf(den);
+        u += d;
+        if (fabsf(d) <= 0x1p-10f) {
+            ok = true;
+            break;
+        }
+    }
+    // FP64 Newton: one step after settled FP32 steps, else until it settles
+    double ud = (ok && u > -0.5f) ? (double)u : 0.0;
+    const int n_newton = (ok && u > -0.5f) ? 1 : 30;
+    bool conv = n_newton == 1;
+    for (int it = 0; it < n_newton; ++it) {
+        const double tau = fma(tau0, ud, tau0);
+        const bool moving = tau < t;
+        const double m = moving ? gh * (1.0 + ud) * (2.0 * t - tau) : Lh;
+        const double mp = moving ? 2.0 * gh * (t - tau) : 0.0;
+        const double xm = Xh + m;
+        const double fv = fma(ud, 2.0 + ud, fma(-m, Xh + xm, -K0h));
+        const double fp = fma(-2.0 * mp, xm, 2.0 + 2.0 * ud);
+        const double du = -fv * rcp_steer(fp);
+        ud += du;
+        if (!conv && fabs(du) <= 0x1p-50 * (1.0 + fabs(ud))) {
+            conv = true;
+            break;
+        }
+    }
+    if (!(ud > -0.5)) conv = false;
+    const double tau = fma(tau0, ud, tau0);
+    const double tp = t - tau;
+    const double sd = (tp > 0.0) ? 0.5 * acc * tp * tp : 0.0;
+    const double vel = (tp > 0.0) ? acc * tp : 0.0;
+    const double ac = (tp > 0.0) ? acc : 0.0;
+    k.flags = conv ? 0u : FLAG_NOCONV;
+    k.tp = tp;
+    k.cph = 1.0;
+    k.sph = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        k.R[i] = g.w[i] - sd * S.e1[i];
+        k.v[i] = vel * S.e1[i];
+        k.a[i] = ac * S.e1[i];
+    }
+    return conv;
+}
+
+// The mixed path's rare fallback for the oscillating families (a correction
+// solve that did not settle): the safeguarded solver on a geometry rebuilt
+// here, so that its frame coordinates and bracket need not stay live across
+// the times.
+__device__ __forceinline__ void retarded_fallback_mixed(const SrcRec &S, const double x[3], int max_iter,
+                                                        double tol_rel, Kin &k)
+{
+    Geo gf;
+    geo_prepare(S, x, gf);
+    if (S.kind == K_CIRCULAR) solve_circular<false>(S, gf, max_iter, tol_rel, k);
+    else solve_linear<false>(S, gf, max_iter, tol_rel, k);
+}
+
 // Retarded kinematics of source S (its record for the observation time) seen
 // from point x, with g = geo_prepare(record of any time of this source, x).
 // FULL: FP64 tolerance (square roots to about one ulp); otherwise the mixed
@@ -499,11 +718,21 @@ __device__ __forceinline__ void retarded_geo(const SrcRec &S, const Geo &g, cons
                                              double tol_rel, Kin &k)
 {
     switch (S.kind) {
-    case K_CIRCULAR: solve_circular<FULL>(S, g, max_iter, tol_rel, k); break;
-    case K_LINEAR_OSC: solve_linear<FULL>(S, g, max_iter, tol_rel, k); break;
+    case K_CIRCULAR:
+        if (FULL) solve_circular<FULL>(S, g, max_iter, tol_rel, k);
+        else if (!solve_u_mixed<K_CIRCULAR>(S, g, k)) retarded_fallback_mixed(S, x, max_iter, tol_rel, k);
+        break;
+    case K_LINEAR_OSC:
+        if (FULL) solve_linear<FULL>(S, g, max_iter, tol_rel, k);
+        else if (!solve_u_mixed<K_LINEAR_OSC>(S, g, k)) retarded_fallback_mixed(S, x, max_iter, tol_rel, k);
+        break;
     case K_ACCEL:
-        solve_accel<FULL>(S, g, max_iter, tol_rel, k);
-        if (!FULL) kin_beta_from_va(k);
+        if (FULL) {
+            solve_accel<FULL>(S, g, max_iter, tol_rel, k);
+        } else {
+            solve_u_accel(S, g, k);
+            kin_beta_from_va(k);
+        }
         break;
     case K_UNIFORM_VELOCITY:
         solve_uniform(S, x, k);

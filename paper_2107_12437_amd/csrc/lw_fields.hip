@@ -95,9 +95,15 @@ template <> __device__ __forceinline__ double qnan<double>() { return __builtin_
 // and TCH consecutive times: the charge loop is outermost, so the part of each
 // retarded-time problem that does not depend on time (frame coordinates,
 // bracket, starting value and its sincos) is built once per (point, charge) and
-// serves all TCH times, whose sums stay in registers.
+// serves all TCH times, whose sums stay in registers.  More times per lane hold
+// more sums, so the register budget grows with TCH: the mixed form runs 4 waves
+// per SIMD (128 VGPRs) at one time, 3 (168) at two and 2 (256) at four; the FP64
+// form fits two times in 4 waves (measured faster than 3 waves at 131 VGPRs).
+// The launch tuner picks among them.
+constexpr int waves_for(bool fp64, int tch) { return tch == 1 ? 4 : (tch == 2 ? (fp64 ? 4 : 3) : 2); }
+
 template <typename F, int TCH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void fields_kernel(const SrcRec *__restrict__ recs, int nch,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for(sizeof(F) == 8, TCH)))) void fields_kernel(const SrcRec *__restrict__ recs, int nch,
                                                      const double *__restrict__ pts, int64_t npts, int nt,
                                                      int t_base, int field_kind, int outputs, int nrows,
                                                      int max_iter, double tol_rel, double mask_r,
