@@ -503,6 +503,41 @@ __device__ double dipole_drive_mixed(const Hist &H, const DipLds &Si, const DipL
     return kq * iL * iL * (st + rest);
 }
 
+// p_i . E of both charges of source j in FP64 (Eq. (E), total field), one after
+// the other in one lane: they share the separation of the origins, its
+// projections and the cached history segment (the two charges' retarded times
+// lie about 1e-4 of a step apart), so the lane loads the segment once.  The
+// per-charge terms are those of pair_drive.
+template <bool MOVING>
+__device__ double dipole_drive_fp64(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double kq,
+                                    int64_t nstep, double theta, int max_iter, uint32_t &err)
+{
+    const double base = (double)nstep + theta;
+    double X[3] = {Si.ox, Si.oy, Si.oz};
+    if (MOVING) origin_at(Si, base * H.dt, X);
+    if constexpr (MOVING) {
+        if (Sj.mw != 0.0) {
+            double R[3], v[3], a[3];
+            charge_moving(H, Sj, j, Sj.cfp, nstep, base, X, max_iter, R, v, a, err);
+            const double e = charge_field(Si, R, v, a, kq);
+            charge_moving(H, Sj, j, Sj.cfm, nstep, base, X, max_iter, R, v, a, err);
+            return e + charge_field(Si, R, v, a, -kq);
+        }
+    }
+    const double dx = X[0] - Sj.ox, dy = X[1] - Sj.oy, dz = X[2] - Sj.oz;
+    const double L2 = dx * dx + dy * dy + dz * dz;
+    const double sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;     // Delta . p_j
+    const double sI = dx * Si.px + dy * Si.py + dz * Si.pz;     // Delta . p_i
+    const double pij = Si.px * Sj.px + Si.py * Sj.py + Si.pz * Sj.pz;
+    const double L = sqrt(L2);
+    Seg g;
+    g.k = INT64_MIN;
+    double hp[3], hm[3];
+    charge_fixed(H, j, Sj.d0, nstep, base, L2, L, sD, Sj.cfp, max_iter, g, hp, err);
+    charge_fixed(H, j, Sj.d0, nstep, base, L2, L, sD, Sj.cfm, max_iter, g, hm, err);
+    return drive_scalar(L2, sD, sI, pij, Sj.cfp, kq, hp) + drive_scalar(L2, sD, sI, pij, Sj.cfm, -kq, hm);
+}
+
 // Drive contribution of work unit w of source j: in FP64 one unit per charge
 // (w = 0: +q, 1: -q), in the mixed form one unit per source dipole.
 template <bool MOVING, bool MIXED>
@@ -519,6 +554,17 @@ __device__ __forceinline__ double unit_drive(const Hist &H, const DipLds &Si, co
 }
 
 template <bool MIXED> constexpr int units_per_source() { return MIXED ? 1 : 2; }
+
+// The stepped kernel's work unit: one source dipole per lane in both forms (its
+// targets have many sources, so fewer, fuller units pay; the persistent kernel
+// keeps a lane per charge, which shortens the serial chain of small instances).
+template <bool MOVING, bool MIXED>
+__device__ __forceinline__ double source_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double qj,
+                                               int64_t nstep, double theta, int max_iter, uint32_t &err)
+{
+    if constexpr (MIXED) return dipole_drive_mixed<MOVING>(H, Si, Sj, j, qj * K_COUL, nstep, theta, max_iter, err);
+    else return dipole_drive_fp64<MOVING>(H, Si, Sj, j, qj * K_COUL, nstep, theta, max_iter, err);
+}
 
 // Drive fields of all targets of the instance at stage times theta in
 // `thetas[0..nth)` (in steps after nstep), written to Eout[th * n + i].
@@ -725,15 +771,14 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
     Hist H{rp, n, ring_depth - 1, dt, 1.0 / dt};
     uint32_t err = 0u;
     const DipLds Si = dip_lds(dev[gi]);
-    constexpr int U = units_per_source<MIXED>();
-    const int M = U * (n - 1);                       // work units per stage
+    const int M = n - 1;                             // work units (source dipoles) per stage
     const int nth = init ? 1 : 2;
     // the target's own state (only this workgroup writes it, and only at its
     // end): when the last lane has no pair work it reads the state into LDS
     // while the others solve, so the tail does not wait on those loads; held
     // in LDS, the values add no register pressure to the pair loop
     __shared__ double own[6];
-    const bool early = !init && nth * M < BLOCK;
+    const bool early = !init && (MIXED ? nth * M : M) < BLOCK;
     if (early && tid == BLOCK - 1) {
         const double *h = rp + ((int64_t)(nstep & (ring_depth - 1)) * n + i) * 3;
         own[0] = h[0];
@@ -744,15 +789,29 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
         own[5] = W[2 * gi + 1];
     }
     double acc0 = 0.0, acc1 = 0.0;                   // stage t_n + dt/2 (or t = 0), stage t_n + dt
-    for (int m = tid; m < nth * M; m += BLOCK) {
-        const int th = m >= M ? 1 : 0, mm = m - th * M;    // (nth <= 2 stages)
-        const int jj = mm / U, w = mm % U;
-        const int j = jj < i ? jj : jj + 1;
-        const DipLds Sj = soa_lds(soa, out.n_dip, (uint32_t)(i0 + j));
-        const double qj = soa_get(soa, out.n_dip, SF_Q, (uint32_t)(i0 + j));
-        const double theta = init ? 0.0 : (th ? 1.0 : 0.5);
-        const double e = unit_drive<MOVING, MIXED>(H, Si, Sj, j, qj, w, nstep, theta, max_iter, err);
-        if (th) acc1 += e; else acc0 += e;
+    if constexpr (!MIXED) {
+        // FP64: a lane takes one source for both stage times, which share its
+        // constants and separation (and often the history segment)
+        for (int jj = tid; jj < M; jj += BLOCK) {
+            const int j = jj < i ? jj : jj + 1;
+            const DipLds Sj = soa_lds(soa, out.n_dip, (uint32_t)(i0 + j));
+            const double qj = soa_get(soa, out.n_dip, SF_Q, (uint32_t)(i0 + j));
+            acc0 += source_drive<MOVING, MIXED>(H, Si, Sj, j, qj, nstep, init ? 0.0 : 0.5, max_iter, err);
+            if (!init) acc1 += source_drive<MOVING, MIXED>(H, Si, Sj, j, qj, nstep, 1.0, max_iter, err);
+        }
+    } else {
+        // mixed: a lane per (stage, source); the mixed drive's larger state makes
+        // the merged form slower here (214 against 208 us per step on the
+        // 64-cluster workload)
+        for (int m = tid; m < nth * M; m += BLOCK) {
+            const int th = m >= M ? 1 : 0, jj = m - th * M;    // (nth <= 2 stages)
+            const int j = jj < i ? jj : jj + 1;
+            const DipLds Sj = soa_lds(soa, out.n_dip, (uint32_t)(i0 + j));
+            const double qj = soa_get(soa, out.n_dip, SF_Q, (uint32_t)(i0 + j));
+            const double theta = init ? 0.0 : (th ? 1.0 : 0.5);
+            const double e = source_drive<MOVING, MIXED>(H, Si, Sj, j, qj, nstep, theta, max_iter, err);
+            if (th) acc1 += e; else acc0 += e;
+        }
     }
     // block sums in a fixed order: within each wave, then over the waves
     for (int o = 32; o > 0; o >>= 1) {
