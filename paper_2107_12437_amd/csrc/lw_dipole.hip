@@ -362,6 +362,37 @@ __device__ __forceinline__ double drive_scalar(double L2, double sD, double sI, 
     return f * ((pin - b * pij) * (1.0 - b * b) * iD - e * q * INV_C);
 }
 
+// Separation of a target at X from a fixed source j: |Delta|^2, |Delta|, and
+// the projections Delta . p_j, Delta . p_i and p_i . p_j that the scalar drive
+// needs (constant over a run when both origins are fixed).
+struct PairGeo {
+    double L2, L, sD, sI, pij;
+};
+
+__device__ __forceinline__ PairGeo pair_geo(const double X[3], const DipLds &Si, const DipLds &Sj)
+{
+    PairGeo P;
+    const double dx = X[0] - Sj.ox, dy = X[1] - Sj.oy, dz = X[2] - Sj.oz;
+    P.L2 = dx * dx + dy * dy + dz * dz;
+    P.sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;     // Delta . p_j
+    P.L = sqrt(P.L2);
+    P.sI = dx * Si.px + dy * Si.py + dz * Si.pz;     // Delta . p_i
+    P.pij = Si.px * Sj.px + Si.py * Sj.py + Si.pz * Sj.pz;
+    return P;
+}
+
+// p_i . E of the charge (cf, kq) of the fixed source j at separation P, at
+// time base * dt, from the stored history.
+__device__ __forceinline__ double fixed_drive(const Hist &H, const PairGeo &P, int j, double d0, double cf,
+                                              double kq, int64_t nstep, double base, int max_iter, uint32_t &err)
+{
+    Seg g;
+    g.k = INT64_MIN;
+    double h[3];
+    charge_fixed(H, j, d0, nstep, base, P.L2, P.L, P.sD, cf, max_iter, g, h, err);
+    return drive_scalar(P.L2, P.sD, P.sI, P.pij, cf, kq, h);
+}
+
 template <bool MOVING>
 __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double cf, double kq,
                              int64_t nstep, double theta, int max_iter, uint32_t &err)
@@ -369,18 +400,8 @@ __device__ double pair_drive(const Hist &H, const DipLds &Si, const DipLds &Sj, 
     const double base = (double)nstep + theta;
     double X[3] = {Si.ox, Si.oy, Si.oz};
     if (MOVING) origin_at(Si, base * H.dt, X);
-    if (!MOVING || Sj.mw == 0.0) {
-        const double dx = X[0] - Sj.ox, dy = X[1] - Sj.oy, dz = X[2] - Sj.oz;
-        const double L2 = dx * dx + dy * dy + dz * dz;
-        const double sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;     // Delta . p_j
-        Seg g;
-        g.k = INT64_MIN;
-        double h[3];
-        charge_fixed(H, j, Sj.d0, nstep, base, L2, sqrt(L2), sD, cf, max_iter, g, h, err);
-        const double sI = dx * Si.px + dy * Si.py + dz * Si.pz;                  // Delta . p_i
-        const double pij = Si.px * Sj.px + Si.py * Sj.py + Si.pz * Sj.pz;
-        return drive_scalar(L2, sD, sI, pij, cf, kq, h);
-    }
+    if (!MOVING || Sj.mw == 0.0)
+        return fixed_drive(H, pair_geo(X, Si, Sj), j, Sj.d0, cf, kq, nstep, base, max_iter, err);
     if constexpr (MOVING) {
         double R[3], v[3], a[3];
         charge_moving(H, Sj, j, cf, nstep, base, X, max_iter, R, v, a, err);
@@ -739,6 +760,194 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
 }
 
 // ---------------------------------------------------------------------------
+// Instances of at most SMALL_MAX_N fixed dipoles in FP64, one wave each.  A
+// step of such an instance is a serial chain (drive, then RK4, then the next
+// drive reads the new sample), so its time is the instructions its one wave
+// issues.  Here every lane holds one work unit of drive_all's layout for the
+// whole run (target i, stage theta, source j, charge w: 2 n (n - 1) units in
+// groups of Lg lanes), with the unit's separation and projections computed
+// once, and lanes 0..n-1 keep their dipole's state, constants and energy sums
+// in registers.  The stage sums reach the RK4 lanes by cross-lane reads.  The
+// arithmetic of every drive, sum and RK4 step is that of lo_instances_kernel,
+// in the same order, so both give the same bits.
+// ---------------------------------------------------------------------------
+constexpr int SMALL_MAX_N = 4;     // 2 n * Lg <= 64 lanes for n <= 4
+
+__global__ __launch_bounds__(64) void lo_small_kernel(const DipDev *__restrict__ dev, const int32_t *__restrict__ off,
+                                                      const int32_t *__restrict__ inst_list, int ring, int64_t steps,
+                                                      double dt, double max_vel, int max_iter, RunOut out,
+                                                      double *__restrict__ state, int resume,
+                                                      uint32_t *__restrict__ d_err)
+{
+    constexpr int BLOCK = 64;
+    extern __shared__ double lds[];
+    const int inst = inst_list[blockIdx.x];
+    const int i0 = off[inst];
+    const int n = off[inst + 1] - i0;
+    const int tid = threadIdx.x;
+    if (n <= 0) return;
+    if (n > SMALL_MAX_N) {                      // the host launches none; never silently skip one
+        if (tid == 0) atomicOr(d_err, (uint32_t)ERR_STATE);
+        return;
+    }
+
+    // LDS layout as lo_instances_kernel's (the t = 0 drive and the run state
+    // use it); the step loop reads only the ring
+    DipLds *S = (DipLds *)lds;
+    double *qv = (double *)(S + n);
+    double *Ecur = qv + n;
+    double *Wab = Ecur + 3 * n;
+    double *Wra = Wab + n;
+    double *ringp = Wra + 7 * n;
+    __shared__ uint32_t s_err;
+
+    for (int j = tid; j < n; j += BLOCK) {
+        const DipDev &D = dev[i0 + j];
+        S[j] = dip_lds(D);
+        qv[j] = D.q;
+    }
+    if (tid == 0) s_err = 0u;
+    __syncthreads();
+
+    Hist H{ringp, n, ring - 1, dt, 1.0 / dt};
+    uint32_t err = 0u;
+    int64_t n0 = 0;
+    if (resume) {
+        n0 = (int64_t)state[0];
+        const double *sr = state + state_ring_off(i0, ring);
+        const int64_t ring3 = (int64_t)ring * n * 3;
+        for (int64_t k = tid; k < ring3; k += BLOCK) ringp[k] = sr[k];
+        const int64_t oe = state_ecur_off(out.n_dip, ring), ow = state_w_off(out.n_dip, ring);
+        for (int i = tid; i < n; i += BLOCK) {
+            Ecur[i] = state[oe + i0 + i];
+            Wab[i] = state[ow + 2 * (i0 + i)];
+            Wra[i] = state[ow + 2 * (i0 + i) + 1];
+        }
+    } else {
+        {
+            const double th0[1] = {0.0};
+            drive_all<BLOCK, false, false>(H, S, qv, n, 0, th0, 1, Ecur, max_iter, err);
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += BLOCK) {
+            const DipDev &D = dev[i0 + i];
+            double *h = ringp + (int64_t)i * 3;
+            h[0] = D.d0;
+            h[1] = 0.0;
+            h[2] = D.f * Ecur[i] - D.omega0 * D.omega0 * D.d0;
+            Wab[i] = 0.0;
+            Wra[i] = 0.0;
+            put_row(out, 0, i0 + i, D.d0, 0.0, run_energy(D.omega0 * D.omega0, D.ehalf, D.d0, 0.0), Ecur[i], 0.0,
+                    0.0);
+        }
+    }
+    __syncthreads();
+
+    // this lane's work unit, as drive_all lays them out for two stage times
+    const int M = 2 * (n - 1), G = 2 * n;
+    int lg = 0;
+    while ((1 << lg) < M) ++lg;
+    const int Lg = 1 << lg;
+    const int grp = tid >> lg, sub = tid & (Lg - 1);
+    const bool active = grp < G && sub < M;
+    int uj = 0;
+    double ucf = 0.0, ukq = 0.0, ud0 = 0.0, utheta = 0.0;
+    PairGeo P{0.0, 0.0, 0.0, 0.0, 0.0};
+    if (active) {
+        const int th = grp >= n ? 1 : 0, i = grp - th * n;
+        const int jj = sub >> 1, w = sub & 1;
+        uj = jj < i ? jj : jj + 1;
+        const DipLds Si = S[i], Sj = S[uj];
+        ucf = w ? Sj.cfm : Sj.cfp;
+        ukq = (w ? -qv[uj] : qv[uj]) * K_COUL;
+        ud0 = Sj.d0;
+        utheta = th ? 1.0 : 0.5;
+        const double X[3] = {Si.ox, Si.oy, Si.oz};
+        P = pair_geo(X, Si, Sj);
+    }
+    // lanes 0..n-1: dipole tid's state at the run's first step, constants and sums
+    const bool owner = tid < n;
+    const int me = owner ? tid : 0;
+    double y0 = 0.0, y1 = 0.0, y2 = 0.0, Ec = 0.0, wab = 0.0, wra = 0.0;
+    double w2 = 0.0, gm = 0.0, fq = 0.0, vfac = 0.0, ms = 0.0, eh = 0.0;
+    if (owner) {
+        const DipDev &D = dev[i0 + me];
+        w2 = D.omega0 * D.omega0;
+        gm = D.gamma0;
+        fq = D.f;
+        vfac = D.vfac;
+        ms = D.mspeed;
+        eh = D.ehalf;
+        const double *h = ringp + ((int64_t)(n0 & (ring - 1)) * n + me) * 3;
+        y0 = h[0];
+        y1 = h[1];
+        y2 = h[2];
+        Ec = Ecur[me];
+        wab = Wab[me];
+        wra = Wra[me];
+    }
+    const int src_mid = me << lg, src_end = (n + me) << lg;
+    const double hdt = 0.5 * dt, dt6 = dt / 6.0, hdtl = 0.5 * dt * K_LARMOR;
+    const uint32_t stop_bits = ERR_NONFINITE | ERR_VELOCITY | ERR_HISTORY;
+
+    for (int64_t nstep = n0; nstep < n0 + steps; ++nstep) {
+        double acc = 0.0;
+        if (active) acc += fixed_drive(H, P, uj, ud0, ucf, ukq, nstep, (double)nstep + utheta, max_iter, err);
+        for (int o = 1; o < Lg; o <<= 1) acc += __shfl_xor(acc, o, 64);
+        const double Em = __shfl(acc, src_mid, 64), Ee = __shfl(acc, src_end, 64);
+        if (owner) {
+            // classic RK4 on y = (d, d_dot), as lo_instances_kernel
+            const double k1d = y1, k1v = fq * Ec - gm * y1 - w2 * y0;
+            const double y0b = y0 + hdt * k1d, y1b = y1 + hdt * k1v;
+            const double k2d = y1b, k2v = fq * Em - gm * y1b - w2 * y0b;
+            const double y0c = y0 + hdt * k2d, y1c = y1 + hdt * k2v;
+            const double k3d = y1c, k3v = fq * Em - gm * y1c - w2 * y0c;
+            const double y0d = y0 + dt * k3d, y1d = y1 + dt * k3v;
+            const double k4d = y1d, k4v = fq * Ee - gm * y1d - w2 * y0d;
+            const double dn = y0 + dt6 * (k1d + 2.0 * k2d + 2.0 * k3d + k4d);
+            const double vn = y1 + dt6 * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
+            const double an = fq * Ee - gm * vn - w2 * dn;
+            double *hn = ringp + ((int64_t)((nstep + 1) & (ring - 1)) * n + me) * 3;
+            hn[0] = dn;
+            hn[1] = vn;
+            hn[2] = an;
+            if (!(isfinite(dn) && isfinite(vn) && isfinite(an))) err |= ERR_NONFINITE;
+            if (max_vel > 0.0 && ms + vfac * fabs(vn) > max_vel) err |= ERR_VELOCITY;
+            wab = wab + hdt * (y1 * Ec + vn * Ee);
+            wra = wra + hdtl * (y2 * y2 + an * an);
+            const int64_t row = out_row(nstep + 1 - n0, out.stride);
+            if (row >= 0) put_row(out, row, i0 + me, dn, vn, run_energy(w2, eh, dn, vn), Ee, wab, wra);
+            y0 = dn;
+            y1 = vn;
+            y2 = an;
+            Ec = Ee;
+        }
+        // the new samples are read by other lanes of this wave in the next step
+        __syncthreads();
+        if (__any((err & stop_bits) != 0u)) break;
+    }
+    if (owner) {
+        Ecur[me] = Ec;
+        Wab[me] = wab;
+        Wra[me] = wra;
+    }
+    if (err) atomicOr(&s_err, err);
+    __syncthreads();
+    if (state) {
+        double *sr = state + state_ring_off(i0, ring);
+        const int64_t ring3 = (int64_t)ring * n * 3;
+        for (int64_t k = tid; k < ring3; k += BLOCK) sr[k] = ringp[k];
+        const int64_t oe = state_ecur_off(out.n_dip, ring), ow = state_w_off(out.n_dip, ring);
+        for (int i = tid; i < n; i += BLOCK) {
+            state[oe + i0 + i] = Ecur[i];
+            state[ow + 2 * (i0 + i)] = Wab[i];
+            state[ow + 2 * (i0 + i) + 1] = Wra[i];
+        }
+    }
+    if (tid == 0 && s_err) atomicOr(d_err, s_err);
+}
+
+// ---------------------------------------------------------------------------
 // Large instances: one workgroup per target dipole, one launch per step.
 // The step index comes from a device counter (advanced by step_advance_kernel)
 // so that a captured sequence of steps can be replayed.  Block b advances dipole
@@ -1052,6 +1261,11 @@ hipError_t launch_dipole_instances(const DipDev *d_dev, const int32_t *d_off, co
     if (n_list <= 0) return hipSuccess;
     const size_t shmem = (size_t)ring_lds_bytes(max_n, ring_lds ? ring : 0);
     const dim3 grid((unsigned)n_list);
+    if (ring_lds && !moving && !mixed && max_n <= SMALL_MAX_N) {
+        hipLaunchKernelGGL(lo_small_kernel, grid, dim3(64), shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel,
+                           max_iter, out, d_state, resume ? 1 : 0, d_err);
+        return hipGetLastError();
+    }
     if (max_n <= 8)
         return launch_lo<64>(ring_lds, moving, mixed, grid, shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel,
                              max_iter, d_ring_global, d_ring_off, out, d_state, resume, d_err);
