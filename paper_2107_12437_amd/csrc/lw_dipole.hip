@@ -73,7 +73,8 @@ hipError_t launch_dipole_prep(const lw_dipole *d_in, int n, DipDev *d_dev, hipSt
 }
 
 // region: 0 before t = 0, 1 between stored samples, 2 past the newest sample.
-__device__ __forceinline__ void hist_at(const Hist &H, int j, double d0, int64_t nstep, double s, double out[3],
+template <typename I>
+__device__ __forceinline__ void hist_at(const Hist &H, int j, double d0, I nstep, double s, double out[3],
                                         double &slope, int &region, uint32_t &err)
 {
     if (s < 0.0) {
@@ -85,9 +86,9 @@ __device__ __forceinline__ void hist_at(const Hist &H, int j, double d0, int64_t
         return;
     }
     const double fk = floor(s);
-    const int64_t k = (int64_t)fk;
+    const I k = (I)fk;
     if (k >= nstep) {
-        const double *h = H.ring + ((int64_t)(nstep & H.mask) * H.n + j) * 3;
+        const double *h = H.ring + ((I)(nstep & H.mask) * H.n + j) * 3;
         const double tt = (s - (double)nstep) * H.dt;
         out[0] = h[0] + h[1] * tt + 0.5 * h[2] * tt * tt;
         out[1] = h[1] + h[2] * tt;
@@ -98,8 +99,8 @@ __device__ __forceinline__ void hist_at(const Hist &H, int j, double d0, int64_t
     }
     if (k + H.mask < nstep) err |= 1u;          // the slot was overwritten: history too short
     const double u = s - fk;
-    const double *h0 = H.ring + ((int64_t)(k & H.mask) * H.n + j) * 3;
-    const double *h1 = H.ring + ((int64_t)((k + 1) & H.mask) * H.n + j) * 3;
+    const double *h0 = H.ring + ((I)(k & H.mask) * H.n + j) * 3;
+    const double *h1 = H.ring + ((I)((k + 1) & H.mask) * H.n + j) * 3;
     out[0] = (1.0 - u) * h0[0] + u * h1[0];
     out[1] = (1.0 - u) * h0[1] + u * h1[1];
     out[2] = (1.0 - u) * h0[2] + u * h1[2];
@@ -117,7 +118,8 @@ __device__ __forceinline__ void hist_at(const Hist &H, int j, double d0, int64_t
 // so once Newton's error bound from the current iterate is below tol/4 the new
 // iterate is accepted and the history evaluated there once more.  h holds the
 // stored (d, d_dot, d_ddot) at the returned root.
-__device__ __forceinline__ double retarded_hist(const Hist &H, int j, double d0, int64_t nstep, double base, double L2,
+template <typename I>
+__device__ __forceinline__ double retarded_hist(const Hist &H, int j, double d0, I nstep, double base, double L2,
                                                 double sD, double cf, double tau, double tau_hi, int max_iter,
                                                 double h[3], uint32_t &err)
 {
@@ -166,11 +168,12 @@ __device__ __forceinline__ double retarded_hist(const Hist &H, int j, double d0,
 // |tau1 - tau0| ~ |rho| / c.  The result is accepted under retarded_hist's
 // a-posteriori bound on the last step; returns false (the caller then uses
 // Newton) when the root lies inside the stored history or the bound fails.
-__device__ __forceinline__ bool retarded_ext(const Hist &H, int j, int64_t nstep, double base, double L2, double L,
+template <typename I>
+__device__ __forceinline__ bool retarded_ext(const Hist &H, int j, I nstep, double base, double L2, double L,
                                              double sD, double cf, double h[3], double &tau_out)
 {
     constexpr double C2 = C_LIGHT * C_LIGHT;
-    const double *hn = H.ring + ((int64_t)(nstep & H.mask) * H.n + j) * 3;
+    const double *hn = H.ring + ((I)(nstep & H.mask) * H.n + j) * 3;
     const double U = (base - (double)nstep) * H.dt;
     const double al = cf * hn[0], be = cf * hn[1], ga = 0.5 * cf * hn[2];
     double tau = L * INV_C, step = 0.0, r1 = 0.0;
@@ -269,19 +272,20 @@ __device__ double retarded_hist_moving(const Hist &H, int j, const DipLds &Sj, c
 // Interpolated state h at the retarded time of the charge (cf) of fixed source
 // j seen at separation Delta (|Delta|^2 = L2, |Delta| = L, Delta . p_j = sD):
 // the closed form on the segment cached in g; past the newest stored step the
-// closed form on the extrapolation; else Newton.  g.k = INT64_MIN marks an
+// closed form on the extrapolation; else Newton.  g.k = seg_none<I>() marks an
 // empty cache.
-__device__ __forceinline__ void charge_fixed(const Hist &H, int j, double d0, int64_t nstep, double base, double L2,
-                                             double L, double sD, double cf, int max_iter, Seg &g, double h[3],
+template <typename I>
+__device__ __forceinline__ void charge_fixed(const Hist &H, int j, double d0, I nstep, double base, double L2,
+                                             double L, double sD, double cf, int max_iter, SegT<I> &g, double h[3],
                                              uint32_t &err)
 {
-    if (g.k == INT64_MIN) {
+    if (g.k == seg_none<I>()) {
         const double s0 = base - L * INV_C * H.inv_dt;
-        const int64_t k0 = s0 < 0.0 ? -1 : (int64_t)floor(s0);
+        const I k0 = s0 < 0.0 ? -1 : (I)floor(s0);
         if (k0 < nstep) seg_load(H, j, d0, nstep, k0, g, err);
     }
     double tau;
-    if (g.k != INT64_MIN && retarded_seg(H, j, d0, nstep, base, L2, sD, cf, g, h, tau, err)) return;
+    if (g.k != seg_none<I>() && retarded_seg(H, j, d0, nstep, base, L2, sD, cf, g, h, tau, err)) return;
     if (retarded_ext(H, j, nstep, base, L2, L, sD, cf, h, tau)) return;
     retarded_hist(H, j, d0, nstep, base, L2, sD, cf, L * INV_C, 2.0 * L * INV_C, max_iter, h, err);
 }
@@ -383,11 +387,12 @@ __device__ __forceinline__ PairGeo pair_geo(const double X[3], const DipLds &Si,
 
 // p_i . E of the charge (cf, kq) of the fixed source j at separation P, at
 // time base * dt, from the stored history.
+template <typename I>
 __device__ __forceinline__ double fixed_drive(const Hist &H, const PairGeo &P, int j, double d0, double cf,
-                                              double kq, int64_t nstep, double base, int max_iter, uint32_t &err)
+                                              double kq, I nstep, double base, int max_iter, uint32_t &err)
 {
-    Seg g;
-    g.k = INT64_MIN;
+    SegT<I> g;
+    g.k = seg_none<I>();
     double h[3];
     charge_fixed(H, j, d0, nstep, base, P.L2, P.L, P.sD, cf, max_iter, g, h, err);
     return drive_scalar(P.L2, P.sD, P.sI, P.pij, cf, kq, h);
@@ -490,7 +495,7 @@ __device__ double dipole_drive_mixed(const Hist &H, const DipLds &Si, const DipL
     double L, iL;
     root_rsqrt<true>(L2, L, iL);
     Seg g;
-    g.k = INT64_MIN;
+    g.k = seg_none<int64_t>();
     double hp[3], hm[3];
     charge_fixed(H, j, Sj.d0, nstep, base, L2, L, sD, Sj.cfp, max_iter, g, hp, err);
     charge_fixed(H, j, Sj.d0, nstep, base, L2, L, sD, Sj.cfm, max_iter, g, hm, err);
@@ -552,7 +557,7 @@ __device__ double dipole_drive_fp64(const Hist &H, const DipLds &Si, const DipLd
     const double pij = Si.px * Sj.px + Si.py * Sj.py + Si.pz * Sj.pz;
     const double L = sqrt(L2);
     Seg g;
-    g.k = INT64_MIN;
+    g.k = seg_none<int64_t>();
     double hp[3], hm[3];
     charge_fixed(H, j, Sj.d0, nstep, base, L2, L, sD, Sj.cfp, max_iter, g, hp, err);
     charge_fixed(H, j, Sj.d0, nstep, base, L2, L, sD, Sj.cfm, max_iter, g, hm, err);
@@ -890,7 +895,10 @@ __global__ __launch_bounds__(64) void lo_small_kernel(const DipDev *__restrict__
     const double hdt = 0.5 * dt, dt6 = dt / 6.0, hdtl = 0.5 * dt * K_LARMOR;
     const uint32_t stop_bits = ERR_NONFINITE | ERR_VELOCITY | ERR_HISTORY;
 
-    for (int64_t nstep = n0; nstep < n0 + steps; ++nstep) {
+    // the steps, with 32-bit step indices when the run's last step fits
+    auto run_steps = [&](auto index_type) {
+      using I = decltype(index_type);
+      for (I nstep = (I)n0; nstep < (I)(n0 + steps); ++nstep) {
         double acc = 0.0;
         if (active) acc += fixed_drive(H, P, uj, ud0, ucf, ukq, nstep, (double)nstep + utheta, max_iter, err);
         for (int o = 1; o < Lg; o <<= 1) acc += __shfl_xor(acc, o, 64);
@@ -907,7 +915,7 @@ __global__ __launch_bounds__(64) void lo_small_kernel(const DipDev *__restrict__
             const double dn = y0 + dt6 * (k1d + 2.0 * k2d + 2.0 * k3d + k4d);
             const double vn = y1 + dt6 * (k1v + 2.0 * k2v + 2.0 * k3v + k4v);
             const double an = fq * Ee - gm * vn - w2 * dn;
-            double *hn = ringp + ((int64_t)((nstep + 1) & (ring - 1)) * n + me) * 3;
+            double *hn = ringp + ((I)((nstep + 1) & (ring - 1)) * n + me) * 3;
             hn[0] = dn;
             hn[1] = vn;
             hn[2] = an;
@@ -915,7 +923,7 @@ __global__ __launch_bounds__(64) void lo_small_kernel(const DipDev *__restrict__
             if (max_vel > 0.0 && ms + vfac * fabs(vn) > max_vel) err |= ERR_VELOCITY;
             wab = wab + hdt * (y1 * Ec + vn * Ee);
             wra = wra + hdtl * (y2 * y2 + an * an);
-            const int64_t row = out_row(nstep + 1 - n0, out.stride);
+            const int64_t row = out_row((int64_t)nstep + 1 - n0, out.stride);
             if (row >= 0) put_row(out, row, i0 + me, dn, vn, run_energy(w2, eh, dn, vn), Ee, wab, wra);
             y0 = dn;
             y1 = vn;
@@ -925,7 +933,10 @@ __global__ __launch_bounds__(64) void lo_small_kernel(const DipDev *__restrict__
         // the new samples are read by other lanes of this wave in the next step
         __syncthreads();
         if (__any((err & stop_bits) != 0u)) break;
-    }
+      }
+    };
+    if (n0 + steps < (int64_t)INT32_MAX) run_steps(int{});
+    else run_steps(int64_t{});
     if (owner) {
         Ecur[me] = Ec;
         Wab[me] = wab;

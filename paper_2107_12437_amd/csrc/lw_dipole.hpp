@@ -2,6 +2,8 @@
 // forward run (lw_dipole.hip) and its adjoint (lw_dipole_adjoint.hip).
 #pragma once
 
+#include <limits>
+
 #include "lw_device.hpp"
 #include "lw_internal.hpp"
 
@@ -108,22 +110,30 @@ __device__ __forceinline__ int instance_of(const int32_t *off, int n_inst, int g
 
 
 // Stored samples k and k + 1 of one source; k = -1 stands for the static
-// pre-history (t' < 0), where the state is (d0, 0, 0).
-struct Seg {
-    int64_t k;
+// pre-history (t' < 0), where the state is (d0, 0, 0).  Step indices are of
+// type I: int64_t, or int in a kernel that has checked its run fits (32-bit
+// integer arithmetic is single instructions; 64-bit is not).  Every floating
+// value is the same for both.
+template <typename I>
+struct SegT {
+    I k;
     double d0, v0, a0;    // sample k: d, d_dot, d_ddot
     double d1, v1, a1;    // sample k + 1
 };
+using Seg = SegT<int64_t>;
 
-__device__ __forceinline__ void seg_load(const Hist &H, int j, double d0, int64_t nstep, int64_t k, Seg &g,
-                                         uint32_t &err)
+// Segment index meaning "none loaded".
+template <typename I> __host__ __device__ constexpr I seg_none() { return std::numeric_limits<I>::min(); }
+
+template <typename I>
+__device__ __forceinline__ void seg_load(const Hist &H, int j, double d0, I nstep, I k, SegT<I> &g, uint32_t &err)
 {
     // k = -1 reads ring slot `mask` (in bounds) and discards it
     const bool pre = k < 0;
     g.k = pre ? -1 : k;
     if (!pre && k + H.mask < nstep) err |= ERR_HISTORY;   // the slot was overwritten: history too short
-    const double *p0 = H.ring + ((int64_t)(g.k & H.mask) * H.n + j) * 3;
-    const double *p1 = H.ring + ((int64_t)((g.k + 1) & H.mask) * H.n + j) * 3;
+    const double *p0 = H.ring + ((I)(g.k & H.mask) * H.n + j) * 3;
+    const double *p1 = H.ring + ((I)((g.k + 1) & H.mask) * H.n + j) * 3;
     g.d0 = pre ? d0 : p0[0];
     g.v0 = pre ? 0.0 : p0[1];
     g.a0 = pre ? 0.0 : p0[2];
@@ -145,8 +155,9 @@ __device__ __forceinline__ void seg_load(const Hist &H, int j, double d0, int64_
 // stored step (the caller then uses the Newton solve with the extrapolation)
 // or the hops do not settle.  On success tau_out is the root, h the
 // interpolated state there and g the segment it lies in.
-__device__ __forceinline__ bool retarded_seg(const Hist &H, int j, double d0, int64_t nstep, double base, double L2,
-                                             double sD, double cf, Seg &g, double h[3], double &tau_out,
+template <typename I>
+__device__ __forceinline__ bool retarded_seg(const Hist &H, int j, double d0, I nstep, double base, double L2,
+                                             double sD, double cf, SegT<I> &g, double h[3], double &tau_out,
                                              uint32_t &err)
 {
     constexpr double C2 = C_LIGHT * C_LIGHT;
@@ -174,7 +185,7 @@ __device__ __forceinline__ bool retarded_seg(const Hist &H, int j, double d0, in
             tau_out = tau;
             return true;
         }
-        const int64_t kn = s < 0.0 ? -1 : (int64_t)floor(s);
+        const I kn = s < 0.0 ? -1 : (I)floor(s);
         if (kn >= nstep) return false;
         seg_load(H, j, d0, nstep, kn, g, err);
     }
