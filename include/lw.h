@@ -195,6 +195,29 @@ lw_status lw_fields_vjp(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges
                         int64_t n_pts, const double *h_times, int32_t n_times, const lw_opts *opts,
                         const void *d_cot, double *d_grad, void *stream);
 
+/* Debugging: a histogram of the retarded-time solves (Eq. (ret_t)) of lw_fields
+ * calls, by the iterations each (point, time, charge) pair's solve took.
+ * Bins (uint64 counts):
+ *   0..30                 that many iterations (0: the closed forms of the
+ *                         stationary and uniformly moving charges; the mixed
+ *                         path counts its FP32 steps and its FP64 step)
+ *   31                    31 or more
+ *   LW_ITER_BIN_FALLBACK  mixed-path solves that fell back to the safeguarded
+ *                         FP64 solver (counted here instead of 0..31)
+ *   LW_ITER_BIN_NOCONV    solves flagged as not converged (also counted in
+ *                         their iteration bin)
+ * lw_set_iteration_histogram(ctx, 1) allocates and clears the context's
+ * histogram; while it is on, lw_fields launches a counting instance of the
+ * grid kernel (one time per lane, 256 lanes, no launch tuning; same outputs,
+ * slower) that adds every pair of the call.  0 turns counting off and keeps
+ * the counts.  lw_fields_noalloc and lw_fields_vjp never count.
+ * lw_iteration_histogram synchronises `stream`, copies the n_bins counts to
+ * h_bins (n_bins <= LW_ITER_BINS) and, if reset is nonzero, clears them.
+ * LW_E_INVALID if counting was never turned on for the context. */
+enum { LW_ITER_BINS = 34, LW_ITER_BIN_FALLBACK = 32, LW_ITER_BIN_NOCONV = 33 };
+lw_status lw_set_iteration_histogram(lw_ctx *ctx, int32_t enable);
+lw_status lw_iteration_histogram(lw_ctx *ctx, uint64_t *h_bins, int32_t n_bins, int32_t reset, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Lorentz oscillators (Secs. 2.3, 3.2; Algorithm 1)                         */
 /* ------------------------------------------------------------------------ */

@@ -101,6 +101,8 @@ struct lw_ctx {
     size_t trial_cap = 0;
     hipStream_t adj_side = nullptr;    // checkpointed adjoint: window builder
     hipEvent_t adj_built = nullptr, adj_swept = nullptr;
+    unsigned long long *d_hist = nullptr;   // retarded-time iteration histogram (debugging)
+    bool iter_hist = false;
 };
 
 namespace {
@@ -411,7 +413,41 @@ lw_status lw_destroy(lw_ctx *ctx)
     if (ctx->d_work2) (void)hipFree(ctx->d_work2);
     if (ctx->d_trial) (void)hipFree(ctx->d_trial);
     if (ctx->d_err) (void)hipFree(ctx->d_err);
+    if (ctx->d_hist) (void)hipFree(ctx->d_hist);
     delete ctx;
+    return LW_OK;
+}
+
+lw_status lw_set_iteration_histogram(lw_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return fail(LW_E_INVALID, "lw_set_iteration_histogram: null context");
+    LW_HIP(hipSetDevice(ctx->device));
+    if (enable && !ctx->d_hist) {
+        if (hipMalloc(&ctx->d_hist, sizeof(unsigned long long) * LW_ITER_BINS) != hipSuccess) {
+            ctx->d_hist = nullptr;
+            return fail(LW_E_NOMEM, "lw_set_iteration_histogram: allocation failed");
+        }
+        LW_HIP(lw::launch_fill_zero((double *)ctx->d_hist, LW_ITER_BINS, nullptr));
+        LW_HIP(hipDeviceSynchronize());
+    }
+    ctx->iter_hist = enable != 0;
+    return LW_OK;
+}
+
+lw_status lw_iteration_histogram(lw_ctx *ctx, uint64_t *h_bins, int32_t n_bins, int32_t reset, void *stream)
+{
+    if (!ctx) return fail(LW_E_INVALID, "lw_iteration_histogram: null context");
+    if (!ctx->d_hist) return fail(LW_E_INVALID, "lw_iteration_histogram: counting was never turned on");
+    if (n_bins < 0 || n_bins > LW_ITER_BINS || (n_bins > 0 && !h_bins))
+        return fail(LW_E_INVALID, "lw_iteration_histogram: bad output");
+    LW_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    LW_HIP(hipStreamSynchronize(s));
+    if (n_bins > 0) LW_HIP(hipMemcpy(h_bins, ctx->d_hist, sizeof(uint64_t) * (size_t)n_bins, hipMemcpyDeviceToHost));
+    if (reset) {
+        LW_HIP(lw::launch_fill_zero((double *)ctx->d_hist, LW_ITER_BINS, s));
+        LW_HIP(hipStreamSynchronize(s));
+    }
     return LW_OK;
 }
 
@@ -519,6 +555,11 @@ lw_status lw_fields(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, co
     if (st != LW_OK) return st;
     const double mask_r = opts->mask_radius < 0.0 ? 1e-10 : opts->mask_radius;
     const double tol_rel = opts->precision == LW_FP64 ? 4.0 * 2.220446049250313e-16 : 2.3283064365386963e-10;
+    if (ctx->iter_hist) {
+        LW_HIP(lw::launch_fields(d_recs, n_charges, d_pts, n_pts, n_times, *opts, tol_rel, mask_r, d_out, d_flags,
+                                 ctx->field_launch, s, ctx->d_hist));
+        return LW_OK;
+    }
     lw::FieldLaunch L = ctx->field_launch;
     const std::string key = field_key(*opts, n_charges, n_times, n_pts);
     auto it = ctx->tuned.find(key);

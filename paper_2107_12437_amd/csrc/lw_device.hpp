@@ -57,7 +57,12 @@ struct Kin {
     double tp;          // retarded time t'
     double cph, sph;    // cos, sin of the phase at t' (oscillating families)
     uint32_t flags;
+    int iters;          // solver iterations taken (ITER_FALLBACK set when the mixed path
+                        // fell back to the safeguarded solver); read only by the
+                        // iteration-histogram kernels, dead code elsewhere
 };
+
+constexpr int ITER_FALLBACK = 1 << 16;
 
 // The mixed path's beta and beta_dot from FP64 velocity and acceleration.
 __device__ __forceinline__ void kin_beta_from_va(Kin &k)
@@ -356,7 +361,9 @@ __device__ __forceinline__ void solve_circular(const SrcRec &S, const Geo &g, in
     Phase ph;
     ph.set_from(S, g.cw, g.sw);
     bool ok = (b.hi == b.lo);
+    int n_it = 0;
     for (int it = 0; it < max_iter && !ok; ++it) {
+        ++n_it;
         // R = x - r(t') in the orbit frame (no cancellation near the orbit)
         const double x1 = w1 - A * ph.c, x2 = w2 - A * ph.s;
         double D, iD;
@@ -372,6 +379,7 @@ __device__ __forceinline__ void solve_circular(const SrcRec &S, const Geo &g, in
         tau = tn;
     }
     k.flags = ok ? 0u : FLAG_NOCONV;
+    k.iters = n_it;
     k.tp = S.t - tau;
     k.cph = ph.c;
     k.sph = ph.s;
@@ -405,7 +413,9 @@ __device__ __forceinline__ void solve_linear(const SrcRec &S, const Geo &g, int 
     Phase ph;
     ph.set_from(S, g.cw, g.sw);
     bool ok = (b.hi == b.lo);
+    int n_it = 0;
     for (int it = 0; it < max_iter && !ok; ++it) {
+        ++n_it;
         const double x1 = w1 - A * ph.c;                     // R . e1
         double D, iD;
         root_rsqrt<FULL>(fmax(perp2 + x1 * x1, 1e-300), D, iD);
@@ -419,6 +429,7 @@ __device__ __forceinline__ void solve_linear(const SrcRec &S, const Geo &g, int 
         tau = tn;
     }
     k.flags = ok ? 0u : FLAG_NOCONV;
+    k.iters = n_it;
     k.tp = S.t - tau;
     k.cph = ph.c;
     k.sph = ph.s;
@@ -452,7 +463,9 @@ __device__ __forceinline__ void solve_accel(const SrcRec &S, const Geo &g, int m
               fmax(sqrt_rough(W2), Dnow) * (INV_C * (1.0 + 1e-6)));
     double tau = fmin(fmax(Dnow * INV_C, b.lo), b.hi);
     bool ok = (b.hi == b.lo);
+    int n_it = 0;
     for (int it = 0; it < max_iter && !ok; ++it) {
+        ++n_it;
         const double tp = t - tau;
         const double s = (tp > 0.0) ? 0.5 * acc * tp * tp : 0.0;   // distance along e1
         const double vel = (tp > 0.0) ? acc * tp : 0.0;
@@ -469,6 +482,7 @@ __device__ __forceinline__ void solve_accel(const SrcRec &S, const Geo &g, int m
         tau = tn;
     }
     k.flags = ok ? 0u : FLAG_NOCONV;
+    k.iters = n_it;
     const double tp = t - tau;
     k.tp = tp;
     k.cph = 1.0;
@@ -504,6 +518,7 @@ __device__ __forceinline__ void solve_uniform(const SrcRec &S, const double x[3]
         k.a[i] = 0.0;
     }
     k.flags = 0u;
+    k.iters = 0;
 }
 
 // Mixed path, circular and linear orbits: the retarded time as a correction to
@@ -543,7 +558,9 @@ __device__ __forceinline__ bool solve_u_mixed(const SrcRec &S, const Geo &g, Kin
     const float w1f = (float)g.w1h, w2f = (float)g.w2h, Af = (float)g.Ah, kf = (float)g.kh, K0f = (float)g.K0h;
     float u = 0.f, c = c0f, s = s0f;
     bool ok = false;
+    int n32 = 0;
     for (int it = 0; it < 4; ++it) {
+        ++n32;
         float fv, fp, fpp;
         if (KIND == K_CIRCULAR) {
             const float P = fmaf(w1f, c, w2f * s), Q = fmaf(w2f, c, -w1f * s);
@@ -593,6 +610,7 @@ __device__ __forceinline__ bool solve_u_mixed(const SrcRec &S, const Geo &g, Kin
     const double cn = cd * ce - sd * e, sn = sd * ce + cd * e;
     const double tau = fma(g.tau0, ud, g.tau0);
     k.flags = 0u;
+    k.iters = n32 + 1;
     k.tp = S.t - tau;
     k.cph = cn;
     k.sph = sn;
@@ -639,7 +657,9 @@ __device__ __forceinline__ bool solve_u_accel(const SrcRec &S, const Geo &g, Kin
     const float Xf = (float)Xh, K0f = (float)K0h, gf = (float)gh, Lf = (float)Lh, tf = (float)t, t0f = (float)tau0;
     float u = 0.f;
     bool ok = false;
+    int n_it = 0;
     for (int it = 0; it < 6; ++it) {
+        ++n_it;
         const float tau = fmaf(t0f, u, t0f);
         const bool moving = tau < tf;
         const float m = moving ? gf * (1.f + u) * (2.f * tf - tau) : Lf;
@@ -664,6 +684,7 @@ __device__ __forceinline__ bool solve_u_accel(const SrcRec &S, const Geo &g, Kin
     const int n_newton = (ok && u > -0.5f) ? 1 : 30;
     bool conv = n_newton == 1;
     for (int it = 0; it < n_newton; ++it) {
+        ++n_it;
         const double tau = fma(tau0, ud, tau0);
         const bool moving = tau < t;
         const double m = moving ? gh * (1.0 + ud) * (2.0 * t - tau) : Lh;
@@ -685,6 +706,7 @@ __device__ __forceinline__ bool solve_u_accel(const SrcRec &S, const Geo &g, Kin
     const double vel = (tp > 0.0) ? acc * tp : 0.0;
     const double ac = (tp > 0.0) ? acc : 0.0;
     k.flags = conv ? 0u : FLAG_NOCONV;
+    k.iters = n_it;
     k.tp = tp;
     k.cph = 1.0;
     k.sph = 0.0;
@@ -720,11 +742,17 @@ __device__ __forceinline__ void retarded_geo(const SrcRec &S, const Geo &g, cons
     switch (S.kind) {
     case K_CIRCULAR:
         if (FULL) solve_circular<FULL>(S, g, max_iter, tol_rel, k);
-        else if (!solve_u_mixed<K_CIRCULAR>(S, g, k)) retarded_fallback_mixed(S, x, max_iter, tol_rel, k);
+        else if (!solve_u_mixed<K_CIRCULAR>(S, g, k)) {
+            retarded_fallback_mixed(S, x, max_iter, tol_rel, k);
+            k.iters |= ITER_FALLBACK;
+        }
         break;
     case K_LINEAR_OSC:
         if (FULL) solve_linear<FULL>(S, g, max_iter, tol_rel, k);
-        else if (!solve_u_mixed<K_LINEAR_OSC>(S, g, k)) retarded_fallback_mixed(S, x, max_iter, tol_rel, k);
+        else if (!solve_u_mixed<K_LINEAR_OSC>(S, g, k)) {
+            retarded_fallback_mixed(S, x, max_iter, tol_rel, k);
+            k.iters |= ITER_FALLBACK;
+        }
         break;
     case K_ACCEL:
         if (FULL) {
@@ -744,6 +772,7 @@ __device__ __forceinline__ void retarded_geo(const SrcRec &S, const Geo &g, cons
         k.cph = 1.0;
         k.sph = 0.0;
         k.flags = 0u;
+        k.iters = 0;
         break;
     }
 }

@@ -102,15 +102,30 @@ template <> __device__ __forceinline__ double qnan<double>() { return __builtin_
 // The launch tuner picks among them.
 constexpr int waves_for(bool fp64, int tch) { return tch == 1 ? 4 : (tch == 2 ? (fp64 ? 4 : 3) : 2); }
 
-template <typename F, int TCH>
+// HIST (a debugging instance, launched with TCH = 1): each workgroup also counts
+// its pairs by the iterations their retarded-time solve took, in LDS, and adds
+// the counts to hist[ITER_BINS] (bins 0..30: that many iterations, 31: more;
+// ITER_BIN_FALLBACK: mixed-path solves that fell back to the safeguarded
+// solver; ITER_BIN_NOCONV: solves flagged as not converged).  Lanes past the
+// last point stay alive to the final barrier.
+template <typename F, int TCH, bool HIST = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for(sizeof(F) == 8, TCH)))) void fields_kernel(const SrcRec *__restrict__ recs, int nch,
                                                      const double *__restrict__ pts, int64_t npts, int nt,
                                                      int t_base, int field_kind, int outputs, int nrows,
                                                      int max_iter, double tol_rel, double mask_r,
-                                                     F *__restrict__ out, uint32_t *__restrict__ flags)
+                                                     F *__restrict__ out, uint32_t *__restrict__ flags,
+                                                     unsigned long long *__restrict__ hist)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npts) return;
+    const int64_t p0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ unsigned int s_hist[HIST ? ITER_BINS : 1];
+    if constexpr (HIST) {
+        for (int i = threadIdx.x; i < ITER_BINS; i += blockDim.x) s_hist[i] = 0u;
+        __syncthreads();
+    } else {
+        if (p0 >= npts) return;
+    }
+    const bool live = p0 < npts;
+    const int64_t p = live ? p0 : 0;
     const double x[3] = {pts[p], pts[npts + p], pts[2 * npts + p]};
     const int t0 = t_base + blockIdx.y * TCH;
     const int nti = min(TCH, nt - t0);
@@ -135,6 +150,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for(s
                 F o[10];
                 const F D = lw_terms<F>(k, S.kq, field_kind, o);
                 fl[j] |= k.flags | ((D >= (F)mask_r) ? 0u : FLAG_MASKED);
+                if constexpr (HIST) {
+                    if (live) {
+                        const int bin = (k.iters & ITER_FALLBACK) ? ITER_BIN_FALLBACK : min(k.iters, ITER_BIN_FALLBACK - 1);
+                        atomicAdd(&s_hist[bin], 1u);
+                        if (k.flags & FLAG_NOCONV) atomicAdd(&s_hist[ITER_BIN_NOCONV], 1u);
+                    }
+                }
                 // the sums the requested rows need (the mask is uniform)
                 if (outputs & OUT_PHI) sum[j][0] += (double)o[0];
                 if (outputs & OUT_A)
@@ -148,6 +170,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for(s
                     for (int q = 7; q < 10; ++q) sum[j][q] += (double)o[q];
             }
         }
+    }
+    if constexpr (HIST) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < ITER_BINS; i += blockDim.x)
+            if (s_hist[i]) atomicAdd(hist + i, (unsigned long long)s_hist[i]);
+        if (!live) return;
     }
     uint32_t fl_all = 0u;
 #pragma unroll
@@ -192,10 +220,10 @@ hipError_t launch_prep(const lw_traj *d_ch, int nch, const double *d_times, int 
     return hipGetLastError();
 }
 
-template <typename F, int TCH>
+template <typename F, int TCH, bool HIST = false>
 static hipError_t launch_fields_t(const SrcRec *d_recs, int nch, const double *d_pts, int64_t npts, int nt,
                                   const lw_opts &o, double tol_rel, double mask_r, F *d_out, uint32_t *d_flags,
-                                  int block, hipStream_t s)
+                                  int block, hipStream_t s, unsigned long long *d_hist = nullptr)
 {
     const int max_iter = o.max_iter > 0 ? o.max_iter : 100;
     const unsigned gx = (unsigned)((npts + block - 1) / block);
@@ -204,9 +232,9 @@ static hipError_t launch_fields_t(const SrcRec *d_recs, int nch, const double *d
     for (int tb = 0; tb < nt; tb += per_launch) {
         const int n_here = min(per_launch, nt - tb);
         const dim3 grid(gx, (unsigned)((n_here + TCH - 1) / TCH));
-        hipLaunchKernelGGL((fields_kernel<F, TCH>), grid, dim3(block), 0, s, d_recs, nch, d_pts, npts, nt, tb,
+        hipLaunchKernelGGL((fields_kernel<F, TCH, HIST>), grid, dim3(block), 0, s, d_recs, nch, d_pts, npts, nt, tb,
                            o.field_kind, output_mask(o.outputs), output_rows(o.outputs), max_iter, tol_rel, mask_r,
-                           d_out, d_flags);
+                           d_out, d_flags, d_hist);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -216,8 +244,11 @@ static hipError_t launch_fields_t(const SrcRec *d_recs, int nch, const double *d
 template <typename F>
 static hipError_t launch_fields_f(const SrcRec *d_recs, int nch, const double *d_pts, int64_t npts, int nt,
                                   const lw_opts &o, double tol_rel, double mask_r, F *d_out, uint32_t *d_flags,
-                                  const FieldLaunch &L, hipStream_t s)
+                                  const FieldLaunch &L, hipStream_t s, unsigned long long *d_hist)
 {
+    if (d_hist)
+        return launch_fields_t<F, 1, true>(d_recs, nch, d_pts, npts, nt, o, tol_rel, mask_r, d_out, d_flags, 256, s,
+                                           d_hist);
     if (L.tchunk >= 4)
         return launch_fields_t<F, 4>(d_recs, nch, d_pts, npts, nt, o, tol_rel, mask_r, d_out, d_flags, L.block, s);
     if (L.tchunk >= 2)
@@ -227,11 +258,13 @@ static hipError_t launch_fields_f(const SrcRec *d_recs, int nch, const double *d
 
 hipError_t launch_fields(const SrcRec *d_recs, int nch, const double *d_pts, int64_t npts, int nt,
                          const lw_opts &o, double tol_rel, double mask_r, void *d_out, uint32_t *d_flags,
-                         const FieldLaunch &L, hipStream_t s)
+                         const FieldLaunch &L, hipStream_t s, unsigned long long *d_hist)
 {
     if (o.precision == LW_MIXED)
-        return launch_fields_f<float>(d_recs, nch, d_pts, npts, nt, o, tol_rel, mask_r, (float *)d_out, d_flags, L, s);
-    return launch_fields_f<double>(d_recs, nch, d_pts, npts, nt, o, tol_rel, mask_r, (double *)d_out, d_flags, L, s);
+        return launch_fields_f<float>(d_recs, nch, d_pts, npts, nt, o, tol_rel, mask_r, (float *)d_out, d_flags, L, s,
+                                      d_hist);
+    return launch_fields_f<double>(d_recs, nch, d_pts, npts, nt, o, tol_rel, mask_r, (double *)d_out, d_flags, L, s,
+                                   d_hist);
 }
 
 }  // namespace lw

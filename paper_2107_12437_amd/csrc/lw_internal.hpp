@@ -44,9 +44,12 @@ struct FieldLaunch {
 // retarded-solve / Lienard-Wiechert / superposition / store kernel.
 hipError_t launch_prep(const lw_traj *d_ch, int nch, const double *d_times, int nt, SrcRec *d_recs,
                        uint32_t *d_flags, int64_t npts, hipStream_t s);
+// d_hist non-null: the counting instance (one time per lane, 256 lanes) adds each
+// pair to the iteration histogram d_hist[ITER_BINS] (see fields_kernel).
+constexpr int ITER_BINS = LW_ITER_BINS, ITER_BIN_FALLBACK = LW_ITER_BIN_FALLBACK, ITER_BIN_NOCONV = LW_ITER_BIN_NOCONV;
 hipError_t launch_fields(const SrcRec *d_recs, int nch, const double *d_pts, int64_t npts, int nt,
                          const lw_opts &o, double tol_rel, double mask_r, void *d_out, uint32_t *d_flags,
-                         const FieldLaunch &L, hipStream_t s);
+                         const FieldLaunch &L, hipStream_t s, unsigned long long *d_hist = nullptr);
 size_t src_rec_bytes();
 // Output rows of an outputs mask (0: Phi | A | E | B).
 int output_mask(int outputs);

@@ -46,7 +46,9 @@ STATUS_NAMES = {0: "LW_OK", 1: "LW_E_INVALID", 2: "LW_E_SUPERLUMINAL", 3: "LW_E_
                 8: "LW_E_NONFINITE", 9: "LW_E_HISTORY", 10: "LW_E_STATE"}
 EXPORTS = ("lw_last_error", "lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields",
            "lw_fields_noalloc", "lw_fields_vjp", "lw_dipole_run", "lw_dipole_run_vjp", "lw_pair_modes", "lw_gamma0", "lw_gf_pair",
-           "lw_exact_modes", "lw_dipole_state_size", "lw_dipole_run_state")
+           "lw_exact_modes", "lw_dipole_state_size", "lw_dipole_run_state", "lw_set_iteration_histogram",
+           "lw_iteration_histogram")
+ITER_BINS, ITER_BIN_FALLBACK, ITER_BIN_NOCONV = 34, 32, 33
 PARAM_NAMES = ("q", "c0x", "c0y", "c0z", "amp", "omega", "phase", "accel", "vx", "vy", "vz")
 OUTPUT_NAMES = ("phi", "Ax", "Ay", "Az", "Ex", "Ey", "Ez", "Bx", "By", "Bz")
 
@@ -112,6 +114,8 @@ def load_library(path: str = LIB_PATH):
                                     ct.POINTER(RunOpts), vp, i64, ct.POINTER(dbl), i32, i32, vp, ct.POINTER(dbl), vp]
     L.lw_pair_modes.argtypes = [ct.POINTER(dbl), i64, i32, ct.POINTER(i32), i32, dbl, i64,
                                 ct.POINTER(dbl), ct.POINTER(i64), ct.POINTER(dbl)]
+    L.lw_set_iteration_histogram.argtypes = [vp, i32]
+    L.lw_iteration_histogram.argtypes = [vp, ct.POINTER(ct.c_uint64), i32, i32, vp]
     L.lw_gamma0.restype = dbl
     L.lw_gamma0.argtypes = [dbl, dbl, dbl]
     L.lw_gf_pair.argtypes = [ct.POINTER(dbl), ct.POINTER(dbl), ct.POINTER(dbl), dbl, ct.POINTER(dbl)]
@@ -119,7 +123,8 @@ def load_library(path: str = LIB_PATH):
     for name in ("lw_create", "lw_destroy", "lw_sync_status", "lw_set_autotune", "lw_fields", "lw_fields_noalloc",
                  "lw_fields_vjp",
                  "lw_dipole_run", "lw_dipole_run_vjp", "lw_pair_modes", "lw_gf_pair", "lw_exact_modes",
-                 "lw_dipole_state_size", "lw_dipole_run_state"):
+                 "lw_dipole_state_size", "lw_dipole_run_state", "lw_set_iteration_histogram",
+                 "lw_iteration_histogram"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -453,6 +458,25 @@ def sync_status(ctx: Context | None = None, device=None):
     dev = _as_device(device)
     ctx = ctx or default_context(dev.index)
     _check(load_library().lw_sync_status(ctx.handle, _stream_ptr(dev)))
+
+
+def set_iteration_histogram(enable: bool, ctx: Context | None = None, device=None):
+    """Debugging: count the retarded-time solves of later fields() calls on the context by
+    their iterations (include/lw.h, lw_set_iteration_histogram)."""
+    dev = _as_device(device)
+    ctx = ctx or default_context(dev.index)
+    _check(load_library().lw_set_iteration_histogram(ctx.handle, int(bool(enable))))
+
+
+def iteration_histogram(reset: bool = False, ctx: Context | None = None, device=None) -> np.ndarray:
+    """The context's iteration histogram, uint64 [ITER_BINS] (bins 0..31: iterations;
+    ITER_BIN_FALLBACK, ITER_BIN_NOCONV), optionally cleared after reading."""
+    dev = _as_device(device)
+    ctx = ctx or default_context(dev.index)
+    out = np.zeros(ITER_BINS, dtype=np.uint64)
+    _check(load_library().lw_iteration_histogram(ctx.handle, out.ctypes.data_as(ct.POINTER(ct.c_uint64)), ITER_BINS,
+                                                  int(bool(reset)), _stream_ptr(dev)))
+    return out
 
 
 def pair_modes(moment, inst_off, dt: float, out_stride: int, omega_ref, skip_steps):

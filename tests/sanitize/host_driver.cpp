@@ -191,6 +191,9 @@ int mode_null_ctx()
                                                          nullptr));
     print_status("dipole_run_vjp", lw_dipole_run_vjp(nullptr, dip, 2, off, 1, 1e-17, 10, &ro, nullptr, 1, &t, 1, 0,
                                                      nullptr, &J, nullptr));
+    uint64_t bins[LW_ITER_BINS];
+    print_status("set_iteration_histogram", lw_set_iteration_histogram(nullptr, 1));
+    print_status("iteration_histogram", lw_iteration_histogram(nullptr, bins, LW_ITER_BINS, 0, nullptr));
     print_status("destroy", lw_destroy(nullptr));
     return 0;
 }

@@ -335,7 +335,8 @@ def test_host_run_argument_checks(drivers, case):
 def test_host_entry_points_without_a_context(drivers):
     out = dict((ln.split()[0], ln.split()[1:]) for ln in run(drivers["host"], "null_ctx").splitlines())
     for name in ("sync_status", "set_autotune", "fields", "fields_noalloc", "fields_vjp", "dipole_run",
-                 "dipole_state_size_null_out", "dipole_run_state", "dipole_run_vjp"):
+                 "dipole_state_size_null_out", "dipole_run_state", "dipole_run_vjp", "set_iteration_histogram",
+                 "iteration_histogram"):
         assert out[name][0] == "1" and len(out[name]) > 1, (name, out[name])
     assert out["dipole_state_size"] == ["0"] and out["destroy"] == ["0"]
 
