@@ -548,17 +548,17 @@ __device__ __forceinline__ void rot_small_f32(float c0, float s0, float a, float
     s = s0 * ca + c0 * sa;
 }
 
+// The FP32 Halley steps of the correction form from u = 0, phase (c0, s0) at
+// tau0: returns whether a step fell below 2^-10; u and the step count n32.
 template <int KIND>
-__device__ __forceinline__ bool solve_u_mixed(const SrcRec &S, const Geo &g, Kin &k)
+__device__ __forceinline__ bool u_stage_f32(const Geo &g, double c0, double s0, float &u, int &n32)
 {
-    // phase at tau0 for this observation time (FP64)
-    const double c0 = S.cT * g.cw + S.sT * g.sw;
-    const double s0 = S.sT * g.cw - S.cT * g.sw;
     const float c0f = (float)c0, s0f = (float)s0;
     const float w1f = (float)g.w1h, w2f = (float)g.w2h, Af = (float)g.Ah, kf = (float)g.kh, K0f = (float)g.K0h;
-    float u = 0.f, c = c0f, s = s0f;
+    float c = c0f, s = s0f;
     bool ok = false;
-    int n32 = 0;
+    u = 0.f;
+    n32 = 0;
     for (int it = 0; it < 4; ++it) {
         ++n32;
         float fv, fp, fpp;
@@ -584,16 +584,26 @@ __device__ __forceinline__ bool solve_u_mixed(const SrcRec &S, const Geo &g, Kin
         }
         rot_small_f32(c0f, s0f, -kf * u, c, s);
     }
-    const double a = -g.kh * (double)u;
-    if (!ok || !(fabs(a) <= 0.75) || !(u > -0.5f)) return false;
-    // one Newton step in FP64 from the exact phase
+    return ok;
+}
+
+// (cos, sin) of the phase theta0 - kh u: (c0, s0) rotated by a = -kh u, |a| <= 0.75,
+// through a^11 and a^12 (truncation below 2e-17).
+__device__ __forceinline__ void rot_phase(double c0, double s0, double a, double &c, double &s)
+{
     const double a2 = a * a;
     const double sa = a * fma_k(a2, fma_k(a2, fma_k(a2, fma_k(a2, fma_k(a2, -1.0 / 39916800.0, 1.0 / 362880.0),
                                                           -1.0 / 5040.0), 1.0 / 120.0), -1.0 / 6.0), 1.0);
     const double ca = fma_k(a2, fma_k(a2, fma_k(a2, fma_k(a2, fma_k(a2, fma_k(a2, 1.0 / 479001600.0, -1.0 / 3628800.0),
                                                                    1.0 / 40320.0), -1.0 / 720.0), 1.0 / 24.0), -0.5), 1.0);
-    double cd = c0 * ca - s0 * sa, sd = s0 * ca + c0 * sa;
-    double ud = (double)u, fv, fp;
+    c = c0 * ca - s0 * sa;
+    s = s0 * ca + c0 * sa;
+}
+
+// f(u) and f'(u) of the correction form in FP64 at phase (cd, sd).
+template <int KIND>
+__device__ __forceinline__ void u_f64(const Geo &g, double ud, double cd, double sd, double &fv, double &fp)
+{
     if (KIND == K_CIRCULAR) {
         const double P = fma(g.w1h, cd, g.w2h * sd), Q = fma(g.w2h, cd, -g.w1h * sd);
         fv = fma(ud, 2.0 + ud, fma(2.0 * g.Ah, P, -g.K0h));
@@ -603,6 +613,24 @@ __device__ __forceinline__ bool solve_u_mixed(const SrcRec &S, const Geo &g, Kin
         fv = fma(ud, 2.0 + ud, fma(2.0 * g.Ah * g.w1h, cd, fma(-g.Ah * g.Ah * cd, cd, -g.K0h)));
         fp = fma(2.0 * g.Ah * g.kh * sd, gx, 2.0 + 2.0 * ud);
     }
+}
+
+template <int KIND>
+__device__ __forceinline__ bool solve_u_mixed(const SrcRec &S, const Geo &g, Kin &k)
+{
+    // phase at tau0 for this observation time (FP64)
+    const double c0 = S.cT * g.cw + S.sT * g.sw;
+    const double s0 = S.sT * g.cw - S.cT * g.sw;
+    float u;
+    int n32;
+    const bool ok = u_stage_f32<KIND>(g, c0, s0, u, n32);
+    const double a = -g.kh * (double)u;
+    if (!ok || !(fabs(a) <= 0.75) || !(u > -0.5f)) return false;
+    // one Newton step in FP64 from the exact phase
+    double cd, sd;
+    rot_phase(c0, s0, a, cd, sd);
+    double ud = (double)u, fv, fp;
+    u_f64<KIND>(g, ud, cd, sd, fv, fp);
     const double du = -fv * rcp_steer(fp);
     ud += du;
     // rotate the phase by the correction's angle e (|e| below 1e-6: second order suffices)
@@ -627,6 +655,65 @@ __device__ __forceinline__ bool solve_u_mixed(const SrcRec &S, const Geo &g, Kin
             k.R[i] = g.w[i] - A * cn * S.e1[i];
             k.bf[i] = -sf * S.bw1[i];
             k.df[i] = -cf * S.aw1[i];
+        }
+    }
+    return true;
+}
+
+// FP64 path, circular and linear orbits: the correction form with the FP32
+// steps above, then two Newton steps in FP64 (the first from the exact phase
+// rotated by the polynomial, the second from a second-order rotation by the
+// first step's angle, which is below 1e-6).  Newton squares the error, so the
+// FP32 steps' phase error of about 1e-7 rad is at rounding level after the
+// second step.  The root is accepted when Newton's bound on the remaining error,
+// |f''| du^2 / (2 |f'|) with |f''| <= 2 + 2 Ah kh^2 M (M = |(w1h, w2h)| for the
+// circular orbit, |w1h| + Ah for the linear one), is below 2^-54, about half an
+// ulp of u near 1; otherwise (and when the FP32 steps do not settle) the
+// caller takes the safeguarded Halley solver.  R, v and a come out in FP64.
+template <int KIND>
+__device__ __forceinline__ bool solve_u_full(const SrcRec &S, const Geo &g, Kin &k)
+{
+    const double c0 = S.cT * g.cw + S.sT * g.sw;
+    const double s0 = S.sT * g.cw - S.cT * g.sw;
+    float u;
+    int n32;
+    const bool ok = u_stage_f32<KIND>(g, c0, s0, u, n32);
+    const double a = -g.kh * (double)u;
+    if (!ok || !(fabs(a) <= 0.75) || !(u > -0.5f)) return false;
+    double cd, sd;
+    rot_phase(c0, s0, a, cd, sd);
+    double ud = (double)u, fv, fp;
+    double du = 0.0;
+    for (int it = 0; it < 2; ++it) {
+        u_f64<KIND>(g, ud, cd, sd, fv, fp);
+        du = -fv * rcp_steer(fp);
+        ud += du;
+        const double e = -g.kh * du, ce = fma(-0.5 * e, e, 1.0);
+        const double cn = cd * ce - sd * e, sn = sd * ce + cd * e;
+        cd = cn;
+        sd = sn;
+    }
+    const double M = KIND == K_CIRCULAR ? sqrt_rough(fma(g.w1h, g.w1h, g.w2h * g.w2h)) * (1.0 + 1e-6)
+                                        : fabs(g.w1h) + g.Ah;
+    const double f2 = fma(2.0 * g.Ah * g.kh * g.kh, M, 2.0);
+    if (!(ud > -0.5) || !(f2 * du * du <= 0x1p-53 * fabs(fp))) return false;
+    const double tau = fma(g.tau0, ud, g.tau0);
+    k.flags = 0u;
+    k.iters = n32 + 2;
+    k.tp = S.t - tau;
+    k.cph = cd;
+    k.sph = sd;
+    const double A = S.amp, om = S.omega;
+    for (int i = 0; i < 3; ++i) {
+        if (KIND == K_CIRCULAR) {
+            const double ro = A * (cd * S.e1[i] + sd * S.e2[i]);
+            k.R[i] = g.w[i] - ro;
+            k.v[i] = om * A * (-sd * S.e1[i] + cd * S.e2[i]);
+            k.a[i] = -om * om * ro;
+        } else {
+            k.R[i] = g.w[i] - A * cd * S.e1[i];
+            k.v[i] = -A * om * sd * S.e1[i];
+            k.a[i] = -A * om * om * cd * S.e1[i];
         }
     }
     return true;
@@ -741,15 +828,17 @@ __device__ __forceinline__ void retarded_geo(const SrcRec &S, const Geo &g, cons
 {
     switch (S.kind) {
     case K_CIRCULAR:
-        if (FULL) solve_circular<FULL>(S, g, max_iter, tol_rel, k);
-        else if (!solve_u_mixed<K_CIRCULAR>(S, g, k)) {
+        if (FULL) {
+            if (!solve_u_full<K_CIRCULAR>(S, g, k)) solve_circular<FULL>(S, g, max_iter, tol_rel, k);
+        } else if (!solve_u_mixed<K_CIRCULAR>(S, g, k)) {
             retarded_fallback_mixed(S, x, max_iter, tol_rel, k);
             k.iters |= ITER_FALLBACK;
         }
         break;
     case K_LINEAR_OSC:
-        if (FULL) solve_linear<FULL>(S, g, max_iter, tol_rel, k);
-        else if (!solve_u_mixed<K_LINEAR_OSC>(S, g, k)) {
+        if (FULL) {
+            if (!solve_u_full<K_LINEAR_OSC>(S, g, k)) solve_linear<FULL>(S, g, max_iter, tol_rel, k);
+        } else if (!solve_u_mixed<K_LINEAR_OSC>(S, g, k)) {
             retarded_fallback_mixed(S, x, max_iter, tol_rel, k);
             k.iters |= ITER_FALLBACK;
         }

@@ -96,11 +96,10 @@ template <> __device__ __forceinline__ double qnan<double>() { return __builtin_
 // retarded-time problem that does not depend on time (frame coordinates,
 // bracket, starting value and its sincos) is built once per (point, charge) and
 // serves all TCH times, whose sums stay in registers.  More times per lane hold
-// more sums, so the register budget grows with TCH: the mixed form runs 4 waves
-// per SIMD (128 VGPRs) at one time, 3 (168) at two and 2 (256) at four; the FP64
-// form fits two times in 4 waves (measured faster than 3 waves at 131 VGPRs).
-// The launch tuner picks among them.
-constexpr int waves_for(bool fp64, int tch) { return tch == 1 ? 4 : (tch == 2 ? (fp64 ? 4 : 3) : 2); }
+// more sums, so the register budget grows with TCH: both forms run 4 waves per
+// SIMD (128 VGPRs) at one time, 3 (168) at two and 2 (256) at four.  The launch
+// tuner picks among them.
+constexpr int waves_for(bool fp64, int tch) { return tch == 1 ? 4 : (tch == 2 ? 3 : 2); }
 
 // HIST (a debugging instance, launched with TCH = 1): each workgroup also counts
 // its pairs by the iterations their retarded-time solve took, in LDS, and adds
