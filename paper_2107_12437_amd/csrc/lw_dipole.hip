@@ -472,6 +472,60 @@ __device__ __forceinline__ float dynamic_corr_f32(float P, float X, float ix, fl
 // separations.  A moving source's origin velocity is common to both charges,
 // so its velocity terms would cancel: moving sources take the FP64 field of
 // each charge.  kq is that of the +q charge.
+// Separation of a target at X from a fixed source j for the mixed drive: |Delta|^2,
+// |Delta| and its reciprocal, Delta . p_j, and the scaled projections u . p_j,
+// p_i . u (u = Delta / |Delta|), p_i . p_j and the acceleration scale L / c^2.
+struct MixedGeo {
+    double L2, L, iL, sD, cup, ciu, pij, gsc;
+};
+
+__device__ __forceinline__ MixedGeo mixed_geo(const double X[3], const DipLds &Si, const DipLds &Sj)
+{
+    MixedGeo G;
+    const double p[3] = {Sj.px, Sj.py, Sj.pz};
+    const double dl[3] = {X[0] - Sj.ox, X[1] - Sj.oy, X[2] - Sj.oz};
+    G.L2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
+    G.sD = dl[0] * p[0] + dl[1] * p[1] + dl[2] * p[2];
+    root_rsqrt<true>(G.L2, G.L, G.iL);
+    G.cup = G.sD * G.iL;
+    G.ciu = (dl[0] * Si.px + dl[1] * Si.py + dl[2] * Si.pz) * G.iL;
+    G.pij = Si.px * p[0] + Si.py * p[1] + Si.pz * p[2];
+    G.gsc = INV_C * INV_C * G.L;                    // acceleration -> beta_dot L / c
+    return G;
+}
+
+// The mixed drive of a fixed source from its two charges' stored states hp (+q,
+// offset cfp) and hm (-q, offset cfm) at their retarded times.
+__device__ __forceinline__ double mixed_field(const MixedGeo &G, double cfp, double cfm, const double hp[3],
+                                              const double hm[3], double kq)
+{
+    const double rp = cfp * hp[0] * G.iL, rm = cfm * hm[0] * G.iL;   // scaled offsets
+    // a = u - rp p_j and b = u - rm p_j enter only through u . p_j, p_i . u,
+    // p_i . p_j and their own lengths
+    const double cup = G.cup, ciu = G.ciu, pij = G.pij;
+    // static monopole difference (FP64)
+    const double dsc = rm - rp;                     // D = dsc p_j (scaled)
+    double ra, ia, rb, ib;
+    root_rsqrt<true>(fma(rp, rp - 2.0 * cup, 1.0), ra, ia);
+    root_rsqrt<true>(fma(rm, rm - 2.0 * cup, 1.0), rb, ib);
+    const double ia3 = ia * ia * ia, ib3 = ib * ib * ib;
+    const double dab = -dsc * (2.0 * cup - (rp + rm)) * recip<double>(ra + rb);   // |b| - |a|
+    const double c3 = dab * (ra * ra + ra * rb + rb * rb) * ia3 * ib3;
+    const double st = dsc * ia3 * pij + c3 * (ciu - rm * pij);
+    // velocity and radiation terms of both charges: first order in beta in
+    // FP64, the rest in FP32
+    const double Pa = (ciu - rp * pij) * ia, Xa = (cup - rp) * ia, Pb = (ciu - rm * pij) * ib, Xb = (cup - rm) * ib;
+    const double qa = pij - Pa * Xa, qb = pij - Pb * Xb;
+    const double bea = cfp * hp[1] * INV_C, gaa = cfp * hp[2] * G.gsc;
+    const double beb = cfm * hm[1] * INV_C, gab = cfm * hm[2] * G.gsc;
+    const float fpij = (float)pij;
+    const float corr = dynamic_corr_f32((float)Pa, (float)Xa, (float)ia, (float)bea, (float)gaa, fpij, (float)qa) -
+                       dynamic_corr_f32((float)Pb, (float)Xb, (float)ib, (float)beb, (float)gab, fpij, (float)qb);
+    const double rest = dynamic_lead(Pa, Xa, ia, bea, gaa, pij, qa) - dynamic_lead(Pb, Xb, ib, beb, gab, pij, qb) +
+                        (double)corr;
+    return kq * G.iL * G.iL * (st + rest);
+}
+
 template <bool MOVING>
 __device__ double dipole_drive_mixed(const Hist &H, const DipLds &Si, const DipLds &Sj, int j, double kq,
                                      int64_t nstep, double theta, int max_iter, uint32_t &err)
@@ -488,45 +542,13 @@ __device__ double dipole_drive_mixed(const Hist &H, const DipLds &Si, const DipL
             return e + charge_field(Si, R, v, a, -kq);
         }
     }
-    const double p[3] = {Sj.px, Sj.py, Sj.pz};
-    const double dl[3] = {X[0] - Sj.ox, X[1] - Sj.oy, X[2] - Sj.oz};
-    const double L2 = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
-    const double sD = dl[0] * p[0] + dl[1] * p[1] + dl[2] * p[2];
-    double L, iL;
-    root_rsqrt<true>(L2, L, iL);
+    const MixedGeo G = mixed_geo(X, Si, Sj);
     Seg g;
     g.k = seg_none<int64_t>();
     double hp[3], hm[3];
-    charge_fixed(H, j, Sj.d0, nstep, base, L2, L, sD, Sj.cfp, max_iter, g, hp, err);
-    charge_fixed(H, j, Sj.d0, nstep, base, L2, L, sD, Sj.cfm, max_iter, g, hm, err);
-    const double rp = Sj.cfp * hp[0] * iL, rm = Sj.cfm * hm[0] * iL;   // scaled offsets
-    // a = u - rp p_j and b = u - rm p_j (u = Delta / |Delta|) enter only through
-    // u . p_j, p_i . u, p_i . p_j and their own lengths
-    const double cup = sD * iL;
-    const double ciu = (dl[0] * Si.px + dl[1] * Si.py + dl[2] * Si.pz) * iL;
-    const double pij = Si.px * p[0] + Si.py * p[1] + Si.pz * p[2];
-    // static monopole difference (FP64)
-    const double dsc = rm - rp;                     // D = dsc p_j (scaled)
-    double ra, ia, rb, ib;
-    root_rsqrt<true>(fma(rp, rp - 2.0 * cup, 1.0), ra, ia);
-    root_rsqrt<true>(fma(rm, rm - 2.0 * cup, 1.0), rb, ib);
-    const double ia3 = ia * ia * ia, ib3 = ib * ib * ib;
-    const double dab = -dsc * (2.0 * cup - (rp + rm)) * recip<double>(ra + rb);   // |b| - |a|
-    const double c3 = dab * (ra * ra + ra * rb + rb * rb) * ia3 * ib3;
-    const double st = dsc * ia3 * pij + c3 * (ciu - rm * pij);
-    // velocity and radiation terms of both charges: first order in beta in
-    // FP64, the rest in FP32
-    const double gsc = INV_C * INV_C * L;           // acceleration -> beta_dot L / c
-    const double Pa = (ciu - rp * pij) * ia, Xa = (cup - rp) * ia, Pb = (ciu - rm * pij) * ib, Xb = (cup - rm) * ib;
-    const double qa = pij - Pa * Xa, qb = pij - Pb * Xb;
-    const double bea = Sj.cfp * hp[1] * INV_C, gaa = Sj.cfp * hp[2] * gsc;
-    const double beb = Sj.cfm * hm[1] * INV_C, gab = Sj.cfm * hm[2] * gsc;
-    const float fpij = (float)pij;
-    const float corr = dynamic_corr_f32((float)Pa, (float)Xa, (float)ia, (float)bea, (float)gaa, fpij, (float)qa) -
-                       dynamic_corr_f32((float)Pb, (float)Xb, (float)ib, (float)beb, (float)gab, fpij, (float)qb);
-    const double rest = dynamic_lead(Pa, Xa, ia, bea, gaa, pij, qa) - dynamic_lead(Pb, Xb, ib, beb, gab, pij, qb) +
-                        (double)corr;
-    return kq * iL * iL * (st + rest);
+    charge_fixed(H, j, Sj.d0, nstep, base, G.L2, G.L, G.sD, Sj.cfp, max_iter, g, hp, err);
+    charge_fixed(H, j, Sj.d0, nstep, base, G.L2, G.L, G.sD, Sj.cfm, max_iter, g, hm, err);
+    return mixed_field(G, Sj.cfp, Sj.cfm, hp, hm, kq);
 }
 
 // p_i . E of both charges of source j in FP64 (Eq. (E), total field), one after
@@ -765,19 +787,26 @@ __global__ __launch_bounds__(BLOCK) void lo_instances_kernel(const DipDev *__res
 }
 
 // ---------------------------------------------------------------------------
-// Instances of at most SMALL_MAX_N fixed dipoles in FP64, one wave each.  A
-// step of such an instance is a serial chain (drive, then RK4, then the next
-// drive reads the new sample), so its time is the instructions its one wave
-// issues.  Here every lane holds one work unit of drive_all's layout for the
-// whole run (target i, stage theta, source j, charge w: 2 n (n - 1) units in
-// groups of Lg lanes), with the unit's separation and projections computed
-// once, and lanes 0..n-1 keep their dipole's state, constants and energy sums
-// in registers.  The stage sums reach the RK4 lanes by cross-lane reads.  The
-// arithmetic of every drive, sum and RK4 step is that of lo_instances_kernel,
-// in the same order, so both give the same bits.
+// Instances of at most SMALL_MAX_N fixed dipoles, one wave each.  A step of such
+// an instance is a serial chain (drive, then RK4, then the next drive reads the
+// new sample), so its time is the instructions its one wave issues.  Here
+// every lane holds one work unit for the whole run (target i, stage theta,
+// source j, charge w: 2 n (n - 1) units in groups of Lg lanes, drive_all's FP64
+// layout), with the unit's separation and projections computed once, and lanes
+// 0..n-1 keep their dipole's state, constants and energy sums in registers.
+// The stage sums reach the RK4 lanes by cross-lane reads.
+//   FP64: the arithmetic of every drive, sum and RK4 step is that of
+//         lo_instances_kernel, in the same order, so both give the same bits.
+//   MIXED: the two lanes of a source's charges each solve their charge's
+//         retarded time, swap the stored states (d, d_dot, d_ddot) there, and
+//         the +q lane evaluates the source's mixed drive (mixed_field).  The
+//         general kernel solves both charges in one lane on one cached history
+//         segment; here each lane loads its own, which finds the same root (to
+//         its last bit but for roots within rounding of a segment end).
 // ---------------------------------------------------------------------------
 constexpr int SMALL_MAX_N = 4;     // 2 n * Lg <= 64 lanes for n <= 4
 
+template <bool MIXED>
 __global__ __launch_bounds__(64) void lo_small_kernel(const DipDev *__restrict__ dev, const int32_t *__restrict__ off,
                                                       const int32_t *__restrict__ inst_list, int ring, int64_t steps,
                                                       double dt, double max_vel, int max_iter, RunOut out,
@@ -831,7 +860,7 @@ __global__ __launch_bounds__(64) void lo_small_kernel(const DipDev *__restrict__
     } else {
         {
             const double th0[1] = {0.0};
-            drive_all<BLOCK, false, false>(H, S, qv, n, 0, th0, 1, Ecur, max_iter, err);
+            drive_all<BLOCK, false, MIXED>(H, S, qv, n, 0, th0, 1, Ecur, max_iter, err);
         }
         __syncthreads();
         for (int i = tid; i < n; i += BLOCK) {
@@ -856,19 +885,31 @@ __global__ __launch_bounds__(64) void lo_small_kernel(const DipDev *__restrict__
     const int grp = tid >> lg, sub = tid & (Lg - 1);
     const bool active = grp < G && sub < M;
     int uj = 0;
-    double ucf = 0.0, ukq = 0.0, ud0 = 0.0, utheta = 0.0;
+    double ucf = 0.0, ukq = 0.0, ud0 = 0.0, utheta = 0.0, ucfp = 0.0, ucfm = 0.0;
     PairGeo P{0.0, 0.0, 0.0, 0.0, 0.0};
+    MixedGeo MG{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const bool plus = (sub & 1) == 0;           // the +q lane of its source's pair
     if (active) {
         const int th = grp >= n ? 1 : 0, i = grp - th * n;
         const int jj = sub >> 1, w = sub & 1;
         uj = jj < i ? jj : jj + 1;
         const DipLds Si = S[i], Sj = S[uj];
         ucf = w ? Sj.cfm : Sj.cfp;
-        ukq = (w ? -qv[uj] : qv[uj]) * K_COUL;
         ud0 = Sj.d0;
         utheta = th ? 1.0 : 0.5;
         const double X[3] = {Si.ox, Si.oy, Si.oz};
-        P = pair_geo(X, Si, Sj);
+        if constexpr (MIXED) {
+            ukq = qv[uj] * K_COUL;                  // the +q charge's (mixed_field)
+            ucfp = Sj.cfp;
+            ucfm = Sj.cfm;
+            MG = mixed_geo(X, Si, Sj);
+            P.L2 = MG.L2;
+            P.L = MG.L;
+            P.sD = MG.sD;
+        } else {
+            ukq = (w ? -qv[uj] : qv[uj]) * K_COUL;
+            P = pair_geo(X, Si, Sj);
+        }
     }
     // lanes 0..n-1: dipole tid's state at the run's first step, constants and sums
     const bool owner = tid < n;
@@ -900,7 +941,19 @@ __global__ __launch_bounds__(64) void lo_small_kernel(const DipDev *__restrict__
       using I = decltype(index_type);
       for (I nstep = (I)n0; nstep < (I)(n0 + steps); ++nstep) {
         double acc = 0.0;
-        if (active) acc += fixed_drive(H, P, uj, ud0, ucf, ukq, nstep, (double)nstep + utheta, max_iter, err);
+        if constexpr (MIXED) {
+            double h[3] = {0.0, 0.0, 0.0};
+            if (active) {
+                SegT<I> g;
+                g.k = seg_none<I>();
+                charge_fixed(H, uj, ud0, nstep, (double)nstep + utheta, P.L2, P.L, P.sD, ucf, max_iter, g, h, err);
+            }
+            double ho[3];
+            for (int q = 0; q < 3; ++q) ho[q] = __shfl_xor(h[q], 1, 64);
+            if (active && plus) acc += mixed_field(MG, ucfp, ucfm, h, ho, ukq);
+        } else {
+            if (active) acc += fixed_drive(H, P, uj, ud0, ucf, ukq, nstep, (double)nstep + utheta, max_iter, err);
+        }
         for (int o = 1; o < Lg; o <<= 1) acc += __shfl_xor(acc, o, 64);
         const double Em = __shfl(acc, src_mid, 64), Ee = __shfl(acc, src_end, 64);
         if (owner) {
@@ -1272,9 +1325,13 @@ hipError_t launch_dipole_instances(const DipDev *d_dev, const int32_t *d_off, co
     if (n_list <= 0) return hipSuccess;
     const size_t shmem = (size_t)ring_lds_bytes(max_n, ring_lds ? ring : 0);
     const dim3 grid((unsigned)n_list);
-    if (ring_lds && !moving && !mixed && max_n <= SMALL_MAX_N) {
-        hipLaunchKernelGGL(lo_small_kernel, grid, dim3(64), shmem, s, d_dev, d_off, d_list, ring, steps, dt, max_vel,
-                           max_iter, out, d_state, resume ? 1 : 0, d_err);
+    if (ring_lds && !moving && max_n <= SMALL_MAX_N) {
+        if (mixed)
+            hipLaunchKernelGGL(lo_small_kernel<true>, grid, dim3(64), shmem, s, d_dev, d_off, d_list, ring, steps, dt,
+                               max_vel, max_iter, out, d_state, resume ? 1 : 0, d_err);
+        else
+            hipLaunchKernelGGL(lo_small_kernel<false>, grid, dim3(64), shmem, s, d_dev, d_off, d_list, ring, steps, dt,
+                               max_vel, max_iter, out, d_state, resume ? 1 : 0, d_err);
         return hipGetLastError();
     }
     if (max_n <= 8)

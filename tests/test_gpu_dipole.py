@@ -204,14 +204,19 @@ def test_batch_equals_single_instances():
     assert np.array_equal(g["d"], full["d"][:, idx])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("resume", [False, True])
-def test_small_instance_kernel_equals_the_general_one(resume):
+def test_small_instance_kernel_equals_the_general_one(resume, precision):
     """Instances of at most 4 fixed dipoles run in a kernel of their own (each lane keeps one
-    pair unit's geometry, each target's state in registers).  Its arithmetic is the general
-    persistent kernel's, in the same order, so the outputs are the same bits.  A batch that
-    also holds a 5-dipole instance takes the general kernel, and the small instances in it
-    must come out bitwise equal to the same instances run alone.  Covers close (extrapolating)
-    and far pairs, a 3- and a 4-dipole cluster, every output, and a run resumed from its state."""
+    pair unit's geometry, each target's state in registers).  A batch that also holds a
+    5-dipole instance takes the general kernel, and the small instances in it are compared
+    with the same instances run alone.  FP64: the small kernel's arithmetic is the general
+    kernel's, in the same order, so the outputs are the same bits.  Mixed: the two charges
+    of a source solve their retarded times in two lanes, each on the history segment it
+    loads itself, where the general kernel shares one cached segment; the roots agree but for
+    the rounding of a root at a segment end, so the states agree to 1e-12 of each dipole's
+    scale and E_d to 1e-14 of the single-charge scale.  Covers close (extrapolating) and far
+    pairs, a 3- and a 4-dipole cluster, every output, and a run resumed from its state."""
     from paper_2107_12437_amd import lw
     rng = I.rng_for(91)
     pairs = I.workload_dipole_pairs(n_inst=6, steps=400, seps=[2e-9, 5e-9, 9e-9, 40e-9, 300e-9, 1e-6])
@@ -226,19 +231,27 @@ def test_small_instance_kernel_equals_the_general_one(resume):
     dt, steps = pairs["dt"], 400
 
     def run(dip, off):
+        kw = dict(policy="extrapolate", precision=precision)
         if not resume:
-            r = lw.dipole_run(dip, off, dt, steps, policy="extrapolate", energy_balance=True)
+            r = lw.dipole_run(dip, off, dt, steps, energy_balance=True, **kw)
             return {k: v.cpu().numpy() for k, v in r.items()}
         st = lw.dipole_state(dip, off, dt, policy="extrapolate")
-        lw.dipole_run(dip, off, dt, 150, policy="extrapolate", state=st)
-        r = lw.dipole_run(dip, off, dt, steps - 150, policy="extrapolate", state=st, resume=True,
-                          energy_balance=True)
+        lw.dipole_run(dip, off, dt, 150, state=st, **kw)
+        r = lw.dipole_run(dip, off, dt, steps - 150, state=st, resume=True, energy_balance=True, **kw)
         return {k: v.cpu().numpy() for k, v in r.items()}
 
     a = run(small, off_small)
     b = run(both, off_both)
-    for key in ("d", "d_dot", "energy", "Ed", "W_abs", "W_rad"):
-        assert np.array_equal(a[key], b[key][:, :n_s]), key
+    if precision == "fp64":
+        for key in ("d", "d_dot", "energy", "Ed", "W_abs", "W_rad"):
+            assert np.array_equal(a[key], b[key][:, :n_s]), key
+    else:
+        w_small = {"dipoles": small, "inst_off": off_small}
+        for key in ("d", "d_dot", "energy", "W_abs", "W_rad"):
+            scale = np.abs(a[key]).max(axis=0, keepdims=True)
+            assert (np.abs(a[key] - b[key][:, :n_s]) / scale).max() <= 1e-12, key
+        sc = single_charge_scale(w_small)[None, :]
+        assert (np.abs(a["Ed"] - b["Ed"][:, :n_s]) / sc).max() <= 1e-14
     assert np.all(np.isfinite(a["d"])) and np.abs(a["d"][-1]).max() > 0
 
 
