@@ -113,7 +113,9 @@ __global__ __launch_bounds__(256) void fields_vjp_kernel(const SrcRec *__restric
                 }
                 if (!fin) continue;
                 Kin k;
-                retarded<true>(S, x, max_iter, tol_rel, k);
+                // the safeguarded solver: the correction solve's registers would take
+                // this kernel from 3 to 2 waves per SIMD
+                retarded<true, false>(S, x, max_iter, tol_rel, k);
                 const double D2 = k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2];
                 if (!(D2 >= mask_r * mask_r) || D2 == 0.0) continue;
                 pair_param_grad(S, k, field_kind, ob, g);

@@ -530,11 +530,14 @@ __device__ __forceinline__ void solve_uniform(const SrcRec &S, const double x[3]
 //   f(u) = u (2 + u) - K0h + 2 Ah w1h cos theta - Ah^2 cos^2 theta = 0.
 // f = (c tau - D)(c tau + D) / D0^2 has the root of Eq. (ret_t) as its only root
 // with u > -1, needs no square root, and its terms are all of the size of
-// Ah, so it is solved in FP32: Halley steps until a step is below 2^-10, the
+// Ah, so it is solved in FP32: Halley steps until a step is below 2^-7, the
 // phase rotated from theta0 by -kh u with short Taylor polynomials (|kh u| is at
-// most the charge's speed over c).  FP32 rounding of f, amplified by kh, leaves
-// the root's phase good to about 1e-7 rad; one Newton step in FP64 from the FP64
+// most the charge's speed over c).  Halley's error after such a step is of the
+// order of its cube, 5e-7, and FP32 rounding of f, amplified by kh, leaves the
+// root's phase good to about 1e-7 rad; one Newton step in FP64 from the FP64
 // phase theta0 then squares the remaining error (phase error below 1e-9 rad).
+// (A stop at 2^-10 took a second FP32 step on 81 % of the benchmark's pairs for
+// no change in the outputs' error; at 2^-5 the vector potential's error grew.)
 // Returns false (the caller takes the safeguarded solver instead) when the FP32
 // steps do not settle or leave the physical range.
 __device__ __forceinline__ void rot_small_f32(float c0, float s0, float a, float &c, float &s)
@@ -549,9 +552,9 @@ __device__ __forceinline__ void rot_small_f32(float c0, float s0, float a, float
 }
 
 // The FP32 Halley steps of the correction form from u = 0, phase (c0, s0) at
-// tau0: returns whether a step fell below 2^-10; u and the step count n32.
+// tau0: returns whether a step fell below `stop`; u and the step count n32.
 template <int KIND>
-__device__ __forceinline__ bool u_stage_f32(const Geo &g, double c0, double s0, float &u, int &n32)
+__device__ __forceinline__ bool u_stage_f32(const Geo &g, double c0, double s0, float stop, float &u, int &n32)
 {
     const float c0f = (float)c0, s0f = (float)s0;
     const float w1f = (float)g.w1h, w2f = (float)g.w2h, Af = (float)g.Ah, kf = (float)g.kh, K0f = (float)g.K0h;
@@ -578,7 +581,7 @@ __device__ __forceinline__ bool u_stage_f32(const Geo &g, double c0, double s0, 
         den = den > fp2 ? den : 2.f * fp2;
         const float d = -2.f * fv * fp * __builtin_amdgcn_rcpf(den);
         u += d;
-        if (fabsf(d) <= 0x1p-10f) {
+        if (fabsf(d) <= stop) {
             ok = true;
             break;
         }
@@ -623,7 +626,7 @@ __device__ __forceinline__ bool solve_u_mixed(const SrcRec &S, const Geo &g, Kin
     const double s0 = S.sT * g.cw - S.cT * g.sw;
     float u;
     int n32;
-    const bool ok = u_stage_f32<KIND>(g, c0, s0, u, n32);
+    const bool ok = u_stage_f32<KIND>(g, c0, s0, 0x1p-7f, u, n32);
     const double a = -g.kh * (double)u;
     if (!ok || !(fabs(a) <= 0.75) || !(u > -0.5f)) return false;
     // one Newton step in FP64 from the exact phase
@@ -633,7 +636,9 @@ __device__ __forceinline__ bool solve_u_mixed(const SrcRec &S, const Geo &g, Kin
     u_f64<KIND>(g, ud, cd, sd, fv, fp);
     const double du = -fv * rcp_steer(fp);
     ud += du;
-    // rotate the phase by the correction's angle e (|e| below 1e-6: second order suffices)
+    // rotate the phase by the correction's angle e (second order: |e| is of the
+    // order of kh times the FP32 steps' error, so e^3 / 6 stays far below FP32
+    // resolution)
     const double e = -g.kh * du, ce = fma(-0.5 * e, e, 1.0);
     const double cn = cd * ce - sd * e, sn = sd * ce + cd * e;
     const double tau = fma(g.tau0, ud, g.tau0);
@@ -662,10 +667,12 @@ __device__ __forceinline__ bool solve_u_mixed(const SrcRec &S, const Geo &g, Kin
 
 // FP64 path, circular and linear orbits: the correction form with the FP32
 // steps above, then two Newton steps in FP64 (the first from the exact phase
-// rotated by the polynomial, the second from a second-order rotation by the
-// first step's angle, which is below 1e-6).  Newton squares the error, so the
-// FP32 steps' phase error of about 1e-7 rad is at rounding level after the
-// second step.  The root is accepted when Newton's bound on the remaining error,
+// rotated by the polynomial, the second from a fourth-order rotation by the
+// first step's angle e: the truncation e^5 / 120 is below 1e-17 for |e| <= 1e-3,
+// and a larger angle sends the point to the safeguarded solver).  Newton squares
+// the error, so the FP32 steps' remaining error (about their last step cubed,
+// and a phase error of about 1e-7 rad from FP32 rounding) is at rounding level
+// after the second step.  The root is accepted when Newton's bound on the remaining error,
 // |f''| du^2 / (2 |f'|) with |f''| <= 2 + 2 Ah kh^2 M (M = |(w1h, w2h)| for the
 // circular orbit, |w1h| + Ah for the linear one), is below 2^-54, about half an
 // ulp of u near 1; otherwise (and when the FP32 steps do not settle) the
@@ -677,26 +684,31 @@ __device__ __forceinline__ bool solve_u_full(const SrcRec &S, const Geo &g, Kin 
     const double s0 = S.sT * g.cw - S.cT * g.sw;
     float u;
     int n32;
-    const bool ok = u_stage_f32<KIND>(g, c0, s0, u, n32);
+    // the FP32 steps run to 2^-10 here (two FP64 Newton steps then meet the 2^-54
+    // bound below; from 2^-7 more points missed it and took the safeguarded solver)
+    const bool ok = u_stage_f32<KIND>(g, c0, s0, 0x1p-10f, u, n32);
     const double a = -g.kh * (double)u;
     if (!ok || !(fabs(a) <= 0.75) || !(u > -0.5f)) return false;
     double cd, sd;
     rot_phase(c0, s0, a, cd, sd);
     double ud = (double)u, fv, fp;
     double du = 0.0;
+    bool small = true;
     for (int it = 0; it < 2; ++it) {
         u_f64<KIND>(g, ud, cd, sd, fv, fp);
         du = -fv * rcp_steer(fp);
         ud += du;
-        const double e = -g.kh * du, ce = fma(-0.5 * e, e, 1.0);
-        const double cn = cd * ce - sd * e, sn = sd * ce + cd * e;
+        const double e = -g.kh * du, e2 = e * e;
+        small = small && fabs(e) <= 1e-3;
+        const double ce = fma(e2, fma(e2, 1.0 / 24.0, -0.5), 1.0), se = e * fma(e2, -1.0 / 6.0, 1.0);
+        const double cn = cd * ce - sd * se, sn = sd * ce + cd * se;
         cd = cn;
         sd = sn;
     }
     const double M = KIND == K_CIRCULAR ? sqrt_rough(fma(g.w1h, g.w1h, g.w2h * g.w2h)) * (1.0 + 1e-6)
                                         : fabs(g.w1h) + g.Ah;
     const double f2 = fma(2.0 * g.Ah * g.kh * g.kh, M, 2.0);
-    if (!(ud > -0.5) || !(f2 * du * du <= 0x1p-53 * fabs(fp))) return false;
+    if (!small || !(ud > -0.5) || !(f2 * du * du <= 0x1p-53 * fabs(fp))) return false;
     const double tau = fma(g.tau0, ud, g.tau0);
     k.flags = 0u;
     k.iters = n32 + 2;
@@ -761,7 +773,7 @@ __device__ __forceinline__ bool solve_u_accel(const SrcRec &S, const Geo &g, Kin
         den = den > fp2 ? den : 2.f * fp2;
         const float d = -2.f * fv * fp * __builtin_amdgcn_rcpf(den);
         u += d;
-        if (fabsf(d) <= 0x1p-10f) {
+        if (fabsf(d) <= 0x1p-7f) {
             ok = true;
             break;
         }
@@ -821,15 +833,17 @@ __device__ __forceinline__ void retarded_fallback_mixed(const SrcRec &S, const d
 // Retarded kinematics of source S (its record for the observation time) seen
 // from point x, with g = geo_prepare(record of any time of this source, x).
 // FULL: FP64 tolerance (square roots to about one ulp); otherwise the mixed
-// path's relaxed tolerance.
-template <bool FULL>
+// path's relaxed tolerance.  CORR (FULL only): the oscillating families try the
+// correction solve first; without it they take the safeguarded Halley solver
+// directly (fewer live registers, for kernels whose occupancy it would cost).
+template <bool FULL, bool CORR = true>
 __device__ __forceinline__ void retarded_geo(const SrcRec &S, const Geo &g, const double x[3], int max_iter,
                                              double tol_rel, Kin &k)
 {
     switch (S.kind) {
     case K_CIRCULAR:
         if (FULL) {
-            if (!solve_u_full<K_CIRCULAR>(S, g, k)) solve_circular<FULL>(S, g, max_iter, tol_rel, k);
+            if (!CORR || !solve_u_full<K_CIRCULAR>(S, g, k)) solve_circular<FULL>(S, g, max_iter, tol_rel, k);
         } else if (!solve_u_mixed<K_CIRCULAR>(S, g, k)) {
             retarded_fallback_mixed(S, x, max_iter, tol_rel, k);
             k.iters |= ITER_FALLBACK;
@@ -837,7 +851,7 @@ __device__ __forceinline__ void retarded_geo(const SrcRec &S, const Geo &g, cons
         break;
     case K_LINEAR_OSC:
         if (FULL) {
-            if (!solve_u_full<K_LINEAR_OSC>(S, g, k)) solve_linear<FULL>(S, g, max_iter, tol_rel, k);
+            if (!CORR || !solve_u_full<K_LINEAR_OSC>(S, g, k)) solve_linear<FULL>(S, g, max_iter, tol_rel, k);
         } else if (!solve_u_mixed<K_LINEAR_OSC>(S, g, k)) {
             retarded_fallback_mixed(S, x, max_iter, tol_rel, k);
             k.iters |= ITER_FALLBACK;
@@ -866,12 +880,12 @@ __device__ __forceinline__ void retarded_geo(const SrcRec &S, const Geo &g, cons
     }
 }
 
-template <bool FULL>
+template <bool FULL, bool CORR = true>
 __device__ __forceinline__ void retarded(const SrcRec &S, const double x[3], int max_iter, double tol_rel, Kin &k)
 {
     Geo g;
     geo_prepare(S, x, g);
-    retarded_geo<FULL>(S, g, x, max_iter, tol_rel, k);
+    retarded_geo<FULL, CORR>(S, g, x, max_iter, tol_rel, k);
 }
 
 template <typename F> __device__ __forceinline__ F recip(F x);
