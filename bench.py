@@ -42,7 +42,7 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # (profiles/fields_kernel_mixed_grid512x512x64t.md).  Valid only for the kernel
 # sources they were taken on; reported as null once those change.
 TRAFFIC_BYTES = 682.1e6
-TRAFFIC_SOURCES_SHA = "313864310f7dbbee"
+TRAFFIC_SOURCES_SHA = "53c0c0321cd432d1"
 # Algorithmic FP64 work per charge-pair drive of the oscillator step (one source
 # charge seen by one target dipole at one stage time), counted from the method's
 # definition: the retarded time on the interpolated history (30 flops, one

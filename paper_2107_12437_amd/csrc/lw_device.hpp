@@ -498,6 +498,10 @@ __device__ __forceinline__ void solve_accel(const SrcRec &S, const Geo &g, int m
 }
 
 // --- uniform velocity: |wt + v tau| = c tau has a closed-form root ---
+// FULL: correctly rounded square root and division; otherwise (the mixed path,
+// whose field is FP32) the refined v_rsq_f64 root and v_rcp_f64 reciprocal,
+// within a few ulp, which is all the mixed tolerance needs.
+template <bool FULL>
 __device__ __forceinline__ void solve_uniform(const SrcRec &S, const double x[3], Kin &k)
 {
     double wt[3];
@@ -506,9 +510,13 @@ __device__ __forceinline__ void solve_uniform(const SrcRec &S, const double x[3]
     const double wv = wt[0] * S.v[0] + wt[1] * S.v[1] + wt[2] * S.v[2];
     const double ww = wt[0] * wt[0] + wt[1] * wt[1] + wt[2] * wt[2];
     const double den = C_LIGHT * C_LIGHT - vv;
-    const double sq = sqrt(wv * wv + den * ww);
+    const double disc = wv * wv + den * ww;
+    double sq, isq;
+    if (FULL) sq = sqrt(disc);
+    else root_rsqrt<false>(fmax(disc, 1e-300), sq, isq);
     // the two algebraically equal forms, chosen to avoid cancellation
-    const double tau = (wv >= 0.0) ? (wv + sq) / den : ww / (sq - wv);
+    const double tau = FULL ? ((wv >= 0.0) ? (wv + sq) / den : ww / (sq - wv))
+                            : ((wv >= 0.0) ? (wv + sq) * rcp_steer(den) : ww * rcp_steer(sq - wv));
     k.tp = S.t - tau;
     k.cph = 1.0;
     k.sph = 0.0;
@@ -866,7 +874,7 @@ __device__ __forceinline__ void retarded_geo(const SrcRec &S, const Geo &g, cons
         }
         break;
     case K_UNIFORM_VELOCITY:
-        solve_uniform(S, x, k);
+        solve_uniform<FULL>(S, x, k);
         if (!FULL) kin_beta_from_va(k);
         break;
     default:
