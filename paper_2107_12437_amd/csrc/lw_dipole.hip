@@ -1030,8 +1030,8 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
                                                         double *__restrict__ Ecur, double *__restrict__ W,
                                                         const int64_t *__restrict__ step_ctr, int kstep,
                                                         int ring_depth, double dt, double max_vel, int max_iter,
-                                                        int init, RunOut out, const double *__restrict__ soa,
-                                                        uint32_t *__restrict__ d_err)
+                                                        int init, int wide, RunOut out,
+                                                        const double *__restrict__ soa, uint32_t *__restrict__ d_err)
 {
     __shared__ double red[2][BLOCK / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1044,14 +1044,22 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
     Hist H{rp, n, ring_depth - 1, dt, 1.0 / dt};
     uint32_t err = 0u;
     const DipLds Si = dip_lds(dev[gi]);
-    const int M = n - 1;                             // work units (source dipoles) per stage
+    const int M = n - 1;                             // source dipoles per stage
     const int nth = init ? 1 : 2;
+    // FP64 lane layout.  A launch with many targets is throughput-bound: a lane
+    // takes one source for both stage times (the fewest instructions per drive).
+    // A launch with few targets (`wide`: at most one workgroup per SIMD) is a
+    // latency chain, and the shortest chain that fits the block wins: one
+    // charge per lane (4 drives' worth of lanes per source), else one source per
+    // (stage, lane).
+    const int layout = MIXED ? 1 : (wide && 2 * nth * M <= BLOCK ? 2 : (wide && nth * M <= BLOCK ? 1 : 0));
+    const int units = layout == 2 ? 2 * nth * M : (layout == 1 ? nth * M : M);
     // the target's own state (only this workgroup writes it, and only at its
     // end): when the last lane has no pair work it reads the state into LDS
     // while the others solve, so the tail does not wait on those loads; held
     // in LDS, the values add no register pressure to the pair loop
     __shared__ double own[6];
-    const bool early = !init && (MIXED ? nth * M : M) < BLOCK;
+    const bool early = !init && units < BLOCK;
     if (early && tid == BLOCK - 1) {
         const double *h = rp + ((int64_t)(nstep & (ring_depth - 1)) * n + i) * 3;
         own[0] = h[0];
@@ -1062,7 +1070,7 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
         own[5] = W[2 * gi + 1];
     }
     double acc0 = 0.0, acc1 = 0.0;                   // stage t_n + dt/2 (or t = 0), stage t_n + dt
-    if constexpr (!MIXED) {
+    if (layout == 0) {
         // FP64: a lane takes one source for both stage times, which share its
         // constants and separation (and often the history segment)
         for (int jj = tid; jj < M; jj += BLOCK) {
@@ -1072,10 +1080,23 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             acc0 += source_drive<MOVING, MIXED>(H, Si, Sj, j, qj, nstep, init ? 0.0 : 0.5, max_iter, err);
             if (!init) acc1 += source_drive<MOVING, MIXED>(H, Si, Sj, j, qj, nstep, 1.0, max_iter, err);
         }
+    } else if (layout == 2) {
+        // FP64, few targets: a lane per (stage, source, charge)
+        for (int m = tid; m < 2 * nth * M; m += BLOCK) {
+            const int th = m >= 2 * M ? 1 : 0, r = m - th * 2 * M;
+            const int jj = r >> 1, w = r & 1;
+            const int j = jj < i ? jj : jj + 1;
+            const DipLds Sj = soa_lds(soa, out.n_dip, (uint32_t)(i0 + j));
+            const double qj = soa_get(soa, out.n_dip, SF_Q, (uint32_t)(i0 + j));
+            const double cf = w ? Sj.cfm : Sj.cfp, kq = (w ? -qj : qj) * K_COUL;
+            const double theta = init ? 0.0 : (th ? 1.0 : 0.5);
+            const double e = pair_drive<MOVING>(H, Si, Sj, j, cf, kq, nstep, theta, max_iter, err);
+            if (th) acc1 += e; else acc0 += e;
+        }
     } else {
-        // mixed: a lane per (stage, source); the mixed drive's larger state makes
-        // the merged form slower here (214 against 208 us per step on the
-        // 64-cluster workload)
+        // a lane per (stage, source): the mixed form always (its drive's larger
+        // state makes the merged form slower: 214 against 208 us per step on
+        // the 64-cluster workload), FP64 for few targets
         for (int m = tid; m < nth * M; m += BLOCK) {
             const int th = m >= M ? 1 : 0, jj = m - th * M;    // (nth <= 2 stages)
             const int j = jj < i ? jj : jj + 1;
@@ -1245,12 +1266,14 @@ hipError_t launch_dipole_steps(const DipDev *d_dev, const int32_t *d_tgt, const 
     constexpr int B = 256;
     if (n_tgt <= 0) return hipSuccess;
     const dim3 grid((unsigned)n_tgt), block(B);
+    // at most one workgroup per SIMD (256 CUs x 4): a latency-bound launch
+    const int wide = n_tgt <= 1024 ? 1 : 0;
     const double *soa = dip_soa(const_cast<DipDev *>(d_dev), out.n_dip);
     auto step = [&](hipStream_t q, int k, int init) {
         with_flags(moving, mixed, [&](auto mv, auto mx) {
             hipLaunchKernelGGL((lo_step_kernel<B, decltype(mv)::value, decltype(mx)::value>), grid, block, 0, q,
                                d_dev, d_tgt, d_tgt_lo, d_tgt_n, d_ring_base, d_ring, d_Ecur, d_W, d_step, k, ring, dt,
-                               max_vel, max_iter, init, out, soa, d_err);
+                               max_vel, max_iter, init, wide, out, soa, d_err);
         });
     };
     hipLaunchKernelGGL(step_start_kernel, dim3(1), dim3(1), 0, s, d_step, d_resume);
