@@ -67,8 +67,9 @@ def single_charge_scale(w):
 
 def assert_state_close(got, ref, w, keys=("d", "d_dot", "energy", "Ed"), tol=TOL_STATE, what=""):
     """d, d_dot, energy relative to their largest magnitude per dipole (tol, or TOL_CANCEL
-    eps times the dipole's drive cancellation ratio where that is larger); Ed relative to
-    the single-charge field scale (TOL_DRIVE)."""
+    eps times the dipole's drive cancellation ratio where that is larger; twice that for
+    the energy, which is quadratic in (d, d_dot), so its relative error is twice theirs);
+    Ed relative to the single-charge field scale (TOL_DRIVE)."""
     sc = single_charge_scale(w)
     net = np.abs(ref["Ed"]).max(axis=0)
     ratio = np.where(net > 0, sc / np.where(net > 0, net, 1.0), 0.0)
@@ -78,7 +79,8 @@ def assert_state_close(got, ref, w, keys=("d", "d_dot", "energy", "Ed"), tol=TOL
             t = TOL_DRIVE
         else:
             scale = np.abs(ref[k]).max(axis=0, keepdims=True)
-            t = np.maximum(tol, TOL_CANCEL * EPS * ratio)[None, :]
+            quad = 2.0 if k == "energy" else 1.0
+            t = np.maximum(tol, quad * TOL_CANCEL * EPS * ratio)[None, :]
         scale = np.where(scale > 0, scale, 1.0)
         err = np.abs(got[k] - ref[k]) / scale
         assert (err <= t).all(), f"{what} {k}: max relative error {err.max():.3e} at {np.unravel_index(err.argmax(), err.shape)}"
@@ -253,6 +255,34 @@ def test_small_instance_kernel_equals_the_general_one(resume, precision):
         sc = single_charge_scale(w_small)[None, :]
         assert (np.abs(a["Ed"] - b["Ed"][:, :n_s]) / sc).max() <= 1e-14
     assert np.all(np.isfinite(a["d"])) and np.abs(a["d"][-1]).max() > 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_single_dipole_instances(precision):
+    """Instances of one dipole have no source: their run is the free RK4 propagator of
+    Eq. (LO_equation) with E_d = 0.  Three of them batched with three pairs (all in the
+    small-instance kernel), against the oracle: the states at the FP64 state tolerance, or
+    at TOL_MIXED_STATE for the mixed form's pairs; the singletons' drive is exactly 0."""
+    pw = I.workload_dipole_pairs(n_inst=3, steps=400, seps=[4e-9, 30e-9, 500e-9])
+    one = I.empty_dipoles(3)
+    one["origin"][:, 0] = [2e-6, 4e-6, 6e-6]
+    one["axis"][:] = [[0.0, 0.0, 1.0], [0.0, 1.0, 0.0], [0.6, 0.8, 0.0]]
+    one["omega0"][:] = 2 * math.pi * 200e12 * np.array([1.0, 1.01, 0.99])
+    one["d0"][:] = I.E_CHARGE * 1e-12 * np.array([1.0, -0.5, 2.0])
+    w = dict(pw, dipoles=I.concat_dipoles([pw["dipoles"], one]),
+             inst_off=np.array([0, 2, 4, 6, 7, 8, 9], np.int32))
+    got = gpu_run(w, "extrapolate", precision=precision)
+    ref = oracle_run(w, "extrapolate", extended=True)
+    if precision == "fp64":
+        assert_state_close(got, ref, w, what="fp64")
+    else:
+        assert_state_close(got, ref, w, keys=("d", "d_dot", "energy"), tol=TOL_MIXED_STATE, what="mixed")
+        single = {k: v[:, 6:] for k, v in got.items()}
+        single_ref = {k: v[:, 6:] for k, v in ref.items()}
+        for k in ("d", "d_dot", "energy"):
+            scale = np.abs(single_ref[k]).max(axis=0, keepdims=True)
+            assert (np.abs(single[k] - single_ref[k]) / scale).max() <= TOL_STATE, k
+    assert np.all(got["Ed"][:, 6:] == 0.0)
 
 
 def test_error_paths():
