@@ -40,7 +40,8 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # HBM bytes per launch of fields_kernel<float, 2> on this workload from the profiler's
 # FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0) counters, calibrated on a plain 1 GiB copy
 # (profiles/fields_kernel_mixed_grid512x512x64t.md).  Valid only for the kernel
-# sources they were taken on; reported as null once those change.
+# sources and code-generation flags they were taken on; reported as null once
+# either changes.
 TRAFFIC_BYTES = 682.1e6
 TRAFFIC_SOURCES_SHA = "53c0c0321cd432d1"
 # Algorithmic FP64 work per charge-pair drive of the oscillator step (one source
@@ -58,6 +59,8 @@ def kernel_sources_sha() -> str:
     for f in ("lw_fields.hip", "lw_device.hpp"):
         with open(os.path.join(ROOT, "paper_2107_12437_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    from paper_2107_12437_amd.build import CODEGEN_FLAGS
+    h.update(" ".join(CODEGEN_FLAGS).encode())
     return h.hexdigest()[:16]
 
 

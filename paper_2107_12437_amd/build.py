@@ -3,8 +3,8 @@
     python -m paper_2107_12437_amd.build          # always rebuilds
     python -m paper_2107_12437_amd.build --if-stale
 
-All HIP code is compiled with the packed-FP32 target feature switched off:
-the kernels use ordinary scalar FP32/FP64 arithmetic only.
+All HIP code is compiled with CODEGEN_FLAGS (below): the packed-FP32 target
+feature switched off, and machine-level loop-invariant code motion off.
 """
 from __future__ import annotations
 
@@ -43,12 +43,24 @@ def is_stale() -> bool:
     return any(os.path.getmtime(p) > t for p in deps())
 
 
+# Code-generation flags of every HIP source.
+#  - packed FP32 off: the kernels use ordinary scalar FP32/FP64 arithmetic only.
+#  - no machine-level loop-invariant code motion: it hoists the 64-bit polynomial
+#    and range-reduction constants (SGPR operands of v_fma_f64) out of the kernels'
+#    charge and step loops, where they then exceed the SGPR budget and spill into
+#    VGPR lanes, and every spill or reload costs a VALU instruction.  Without it the
+#    constants are rebuilt by scalar moves next to their use (no VALU cost), the grid
+#    kernels drop from 165 to 146 VGPRs (mixed, two times per lane) with no spills,
+#    and the grid step runs 4-5 % faster with bit-identical results.
+CODEGEN_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                 "-mllvm", "-disable-machine-licm"]
+
+
 def build(force: bool = True, verbose: bool = False) -> str:
     if not force and not is_stale():
         return LIB
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared", *CODEGEN_FLAGS,
            "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
            "-I", INCLUDE, "-x", "hip", *sources(), "-o", tmp]
     if verbose:
