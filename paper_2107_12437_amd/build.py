@@ -4,7 +4,8 @@
     python -m paper_2107_12437_amd.build --if-stale
 
 All HIP code is compiled with CODEGEN_FLAGS (below): the packed-FP32 target
-feature switched off, and machine-level loop-invariant code motion off.
+feature switched off, machine-level loop-invariant code motion off, and
+multiply-add contraction within source expressions only.
 """
 from __future__ import annotations
 
@@ -52,8 +53,14 @@ def is_stale() -> bool:
 #    constants are rebuilt by scalar moves next to their use (no VALU cost), the grid
 #    kernels drop from 165 to 146 VGPRs (mixed, two times per lane) with no spills,
 #    and the grid step runs 4-5 % faster with bit-identical results.
+#  - multiply-add contraction only within one source expression (-ffp-contract=on,
+#    decided by the front end): with the default cross-statement contraction the
+#    back end fuses a product into a sum only where the product has one use, so
+#    two instances of one kernel template (say one and two times per lane, where
+#    the second shares a product between its times) round differently, and the
+#    outputs would depend on the launch shape the tuner picks.
 CODEGEN_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                 "-mllvm", "-disable-machine-licm"]
+                 "-mllvm", "-disable-machine-licm", "-ffp-contract=on"]
 
 
 def build(force: bool = True, verbose: bool = False) -> str:

@@ -68,6 +68,38 @@ __device__ __forceinline__ void pair_param_grad(const SrcRec &S, const Kin &k, i
     }
 }
 
+// The contributions of one charge of family KIND at point x over nt_here times
+// (records Rc[ti * nch], cotangent rows cot[(ti * nrows + row) * npts + p]),
+// added into g[NP]: per time the retarded kinematics (the safeguarded solver:
+// the correction solve's registers would take this kernel from 3 to 2 waves per
+// SIMD, and so would keeping the time-independent geometry live across the
+// times) and their reverse.
+template <int KIND, typename G>
+__device__ __forceinline__ void charge_grad(const SrcRec *__restrict__ Rc, int nch, int nt_here, const double x[3],
+                                            int64_t p, int64_t npts, int nrows, const int row[10], int field_kind,
+                                            int max_iter, double tol_rel, double mask_r, const G *__restrict__ cot,
+                                            double g[NP])
+{
+    for (int ti = 0; ti < nt_here; ++ti) {
+        const SrcRec &S = Rc[(int64_t)ti * nch];
+        double ob[10];
+        bool fin = true;
+#pragma unroll
+        for (int j = 0; j < 10; ++j) {
+            ob[j] = row[j] >= 0 ? (double)cot[((int64_t)ti * nrows + row[j]) * npts + p] : 0.0;
+            fin = fin && isfinite(ob[j]);
+        }
+        if (!fin) continue;
+        Geo geo;
+        geo_prepare_k<KIND>(S, x, geo);
+        Kin k;
+        retarded_kind<true, false, KIND>(S, geo, x, max_iter, tol_rel, k);
+        const double D2 = k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2];
+        if (!(D2 >= mask_r * mask_r) || D2 == 0.0) continue;
+        pair_param_grad(S, k, field_kind, ob, g);
+    }
+}
+
 template <typename G>
 __global__ __launch_bounds__(256) void fields_vjp_kernel(const SrcRec *__restrict__ recs, int nch,
                                                          const double *__restrict__ pts, int64_t npts, int nt,
@@ -102,23 +134,30 @@ __global__ __launch_bounds__(256) void fields_vjp_kernel(const SrcRec *__restric
 #pragma unroll
         for (int j = 0; j < NP; ++j) g[j] = 0.0;
         if (live) {
-            for (int ti = t0; ti < t1; ++ti) {
-                const SrcRec &S = recs[(int64_t)ti * nch + c];
-                double ob[10];
-                bool fin = true;
-#pragma unroll
-                for (int j = 0; j < 10; ++j) {
-                    ob[j] = row[j] >= 0 ? (double)cot[((int64_t)ti * nrows + row[j]) * npts + p] : 0.0;
-                    fin = fin && isfinite(ob[j]);
-                }
-                if (!fin) continue;
-                Kin k;
-                // the safeguarded solver: the correction solve's registers would take
-                // this kernel from 3 to 2 waves per SIMD
-                retarded<true, false>(S, x, max_iter, tol_rel, k);
-                const double D2 = k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2];
-                if (!(D2 >= mask_r * mask_r) || D2 == 0.0) continue;
-                pair_param_grad(S, k, field_kind, ob, g);
+            // every time's record of a charge carries the charge's family, so
+            // the solver is chosen once per charge
+            const SrcRec *Rc = recs + (int64_t)t0 * nch + c;
+            switch (Rc->kind) {
+            case K_CIRCULAR:
+                charge_grad<K_CIRCULAR>(Rc, nch, t1 - t0, x, p, npts, nrows, row, field_kind, max_iter, tol_rel,
+                                        mask_r, cot + (int64_t)t0 * nrows * npts, g);
+                break;
+            case K_LINEAR_OSC:
+                charge_grad<K_LINEAR_OSC>(Rc, nch, t1 - t0, x, p, npts, nrows, row, field_kind, max_iter, tol_rel,
+                                          mask_r, cot + (int64_t)t0 * nrows * npts, g);
+                break;
+            case K_ACCEL:
+                charge_grad<K_ACCEL>(Rc, nch, t1 - t0, x, p, npts, nrows, row, field_kind, max_iter, tol_rel,
+                                     mask_r, cot + (int64_t)t0 * nrows * npts, g);
+                break;
+            case K_UNIFORM_VELOCITY:
+                charge_grad<K_UNIFORM_VELOCITY>(Rc, nch, t1 - t0, x, p, npts, nrows, row, field_kind, max_iter,
+                                                tol_rel, mask_r, cot + (int64_t)t0 * nrows * npts, g);
+                break;
+            default:
+                charge_grad<K_STATIONARY>(Rc, nch, t1 - t0, x, p, npts, nrows, row, field_kind, max_iter, tol_rel,
+                                          mask_r, cot + (int64_t)t0 * nrows * npts, g);
+                break;
             }
         }
         // workgroup sum in a fixed order: shuffle tree per wave, then the four waves

@@ -302,13 +302,18 @@ struct Geo {
     double w1h, w2h, Ah, kh, K0h;
 };
 
-__device__ __forceinline__ void geo_prepare(const SrcRec &S, const double x[3], Geo &g)
+// The time-independent part of the retarded-time problem for a charge of family
+// KIND (the record of any observation time), seen from x.  The stationary and
+// uniform families need only w.
+template <int KIND>
+__device__ __forceinline__ void geo_prepare_k(const SrcRec &S, const double x[3], Geo &g)
 {
     for (int i = 0; i < 3; ++i) g.w[i] = x[i] - S.c0[i];
+    if constexpr (KIND != K_CIRCULAR && KIND != K_LINEAR_OSC && KIND != K_ACCEL) return;
     const double *w = g.w;
     const double A = S.amp;
     g.w1 = w[0] * S.e1[0] + w[1] * S.e1[1] + w[2] * S.e1[2];
-    if (S.kind == K_CIRCULAR) {
+    if constexpr (KIND == K_CIRCULAR) {
         const double w1 = g.w1;
         const double w2 = w[0] * S.e2[0] + w[1] * S.e2[1] + w[2] * S.e2[2];
         const double w3 = w[0] * S.e3[0] + w[1] * S.e3[1] + w[2] * S.e3[2];
@@ -328,12 +333,12 @@ __device__ __forceinline__ void geo_prepare(const SrcRec &S, const double x[3], 
         g.Ah = A * iD0;
         g.kh = S.omega * g.tau0;
         g.K0h = fma(-D0, D0, WA) * (iD0 * iD0);
-    } else if (S.kind == K_LINEAR_OSC || S.kind == K_ACCEL) {
+    } else {
         const double w1 = g.w1;
         const double p0 = w[0] - w1 * S.e1[0], p1 = w[1] - w1 * S.e1[1], p2 = w[2] - w1 * S.e1[2];
         const double perp2 = p0 * p0 + p1 * p1 + p2 * p2;     // distance^2 from the axis line
         g.w2 = perp2;
-        if (S.kind == K_LINEAR_OSC) {
+        if constexpr (KIND == K_LINEAR_OSC) {
             const double W2 = perp2 + w1 * w1;
             const double u = fmin(fmax(w1, -A), A);
             g.lo = sqrt_rough(perp2 + (w1 - u) * (w1 - u)) * (INV_C * (1.0 - 1e-6));
@@ -347,6 +352,16 @@ __device__ __forceinline__ void geo_prepare(const SrcRec &S, const double x[3], 
             g.kh = S.omega * g.tau0;
             g.K0h = fma(-D0, D0, W2) * (iD0 * iD0);
         }
+    }
+}
+
+__device__ __forceinline__ void geo_prepare(const SrcRec &S, const double x[3], Geo &g)
+{
+    switch (S.kind) {
+    case K_CIRCULAR: geo_prepare_k<K_CIRCULAR>(S, x, g); break;
+    case K_LINEAR_OSC: geo_prepare_k<K_LINEAR_OSC>(S, x, g); break;
+    case K_ACCEL: geo_prepare_k<K_ACCEL>(S, x, g); break;
+    default: geo_prepare_k<K_STATIONARY>(S, x, g); break;
     }
 }
 
@@ -829,12 +844,13 @@ __device__ __forceinline__ bool solve_u_accel(const SrcRec &S, const Geo &g, Kin
 // solve that did not settle): the safeguarded solver on a geometry rebuilt
 // here, so that its frame coordinates and bracket need not stay live across
 // the times.
+template <int KIND>
 __device__ __forceinline__ void retarded_fallback_mixed(const SrcRec &S, const double x[3], int max_iter,
                                                         double tol_rel, Kin &k)
 {
     Geo gf;
-    geo_prepare(S, x, gf);
-    if (S.kind == K_CIRCULAR) solve_circular<false>(S, gf, max_iter, tol_rel, k);
+    geo_prepare_k<KIND>(S, x, gf);
+    if constexpr (KIND == K_CIRCULAR) solve_circular<false>(S, gf, max_iter, tol_rel, k);
     else solve_linear<false>(S, gf, max_iter, tol_rel, k);
 }
 
@@ -844,47 +860,52 @@ __device__ __forceinline__ void retarded_fallback_mixed(const SrcRec &S, const d
 // path's relaxed tolerance.  CORR (FULL only): the oscillating families try the
 // correction solve first; without it they take the safeguarded Halley solver
 // directly (fewer live registers, for kernels whose occupancy it would cost).
-template <bool FULL, bool CORR = true>
-__device__ __forceinline__ void retarded_geo(const SrcRec &S, const Geo &g, const double x[3], int max_iter,
-                                             double tol_rel, Kin &k)
+// retarded_kind serves a source of family KIND (S.kind == KIND, g from
+// geo_prepare_k<KIND>); retarded_geo dispatches on S.kind.
+template <bool FULL, bool CORR, int KIND>
+__device__ __forceinline__ void retarded_kind(const SrcRec &S, const Geo &g, const double x[3], int max_iter,
+                                              double tol_rel, Kin &k)
 {
-    switch (S.kind) {
-    case K_CIRCULAR:
+    if constexpr (KIND == K_CIRCULAR || KIND == K_LINEAR_OSC) {
         if (FULL) {
-            if (!CORR || !solve_u_full<K_CIRCULAR>(S, g, k)) solve_circular<FULL>(S, g, max_iter, tol_rel, k);
-        } else if (!solve_u_mixed<K_CIRCULAR>(S, g, k)) {
-            retarded_fallback_mixed(S, x, max_iter, tol_rel, k);
+            if (!CORR || !solve_u_full<KIND>(S, g, k)) {
+                if constexpr (KIND == K_CIRCULAR) solve_circular<FULL>(S, g, max_iter, tol_rel, k);
+                else solve_linear<FULL>(S, g, max_iter, tol_rel, k);
+            }
+        } else if (!solve_u_mixed<KIND>(S, g, k)) {
+            retarded_fallback_mixed<KIND>(S, x, max_iter, tol_rel, k);
             k.iters |= ITER_FALLBACK;
         }
-        break;
-    case K_LINEAR_OSC:
-        if (FULL) {
-            if (!CORR || !solve_u_full<K_LINEAR_OSC>(S, g, k)) solve_linear<FULL>(S, g, max_iter, tol_rel, k);
-        } else if (!solve_u_mixed<K_LINEAR_OSC>(S, g, k)) {
-            retarded_fallback_mixed(S, x, max_iter, tol_rel, k);
-            k.iters |= ITER_FALLBACK;
-        }
-        break;
-    case K_ACCEL:
+    } else if constexpr (KIND == K_ACCEL) {
         if (FULL) {
             solve_accel<FULL>(S, g, max_iter, tol_rel, k);
         } else {
             solve_u_accel(S, g, k);
             kin_beta_from_va(k);
         }
-        break;
-    case K_UNIFORM_VELOCITY:
+    } else if constexpr (KIND == K_UNIFORM_VELOCITY) {
         solve_uniform<FULL>(S, x, k);
         if (!FULL) kin_beta_from_va(k);
-        break;
-    default:
+    } else {
         for (int i = 0; i < 3; ++i) { k.R[i] = g.w[i]; k.v[i] = 0.0; k.a[i] = 0.0; k.bf[i] = 0.f; k.df[i] = 0.f; }
         k.tp = S.t - sqrt(g.w[0] * g.w[0] + g.w[1] * g.w[1] + g.w[2] * g.w[2]) * INV_C;
         k.cph = 1.0;
         k.sph = 0.0;
         k.flags = 0u;
         k.iters = 0;
-        break;
+    }
+}
+
+template <bool FULL, bool CORR = true>
+__device__ __forceinline__ void retarded_geo(const SrcRec &S, const Geo &g, const double x[3], int max_iter,
+                                             double tol_rel, Kin &k)
+{
+    switch (S.kind) {
+    case K_CIRCULAR: retarded_kind<FULL, CORR, K_CIRCULAR>(S, g, x, max_iter, tol_rel, k); break;
+    case K_LINEAR_OSC: retarded_kind<FULL, CORR, K_LINEAR_OSC>(S, g, x, max_iter, tol_rel, k); break;
+    case K_ACCEL: retarded_kind<FULL, CORR, K_ACCEL>(S, g, x, max_iter, tol_rel, k); break;
+    case K_UNIFORM_VELOCITY: retarded_kind<FULL, CORR, K_UNIFORM_VELOCITY>(S, g, x, max_iter, tol_rel, k); break;
+    default: retarded_kind<FULL, CORR, K_STATIONARY>(S, g, x, max_iter, tol_rel, k); break;
     }
 }
 

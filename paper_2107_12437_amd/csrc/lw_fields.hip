@@ -96,10 +96,53 @@ template <> __device__ __forceinline__ double qnan<double>() { return __builtin_
 // retarded-time problem that does not depend on time (frame coordinates,
 // bracket, starting value and its sincos) is built once per (point, charge) and
 // serves all TCH times, whose sums stay in registers.  More times per lane hold
-// more sums, so the register budget grows with TCH: both forms run 4 waves per
-// SIMD (128 VGPRs) at one time, 3 (168) at two and 2 (256) at four.  The launch
-// tuner picks among them.
+// more sums, so the register cap grows with TCH: 4 waves per SIMD (128 VGPRs)
+// at one time, 3 (168) at two and 2 (256) at four.  At two times the mixed form
+// compiles to 127 VGPRs and so runs 4 waves (a cap of 128 made the allocator
+// spill); the FP64 form takes 144.  The launch tuner picks among them.
 constexpr int waves_for(bool fp64, int tch) { return tch == 1 ? 4 : (tch == 2 ? 3 : 2); }
+
+// One charge of family KIND at the lane's point and its nti (>= 1) times: the
+// geometry once, then per time the retarded kinematics, the terms in precision
+// F, the flags and the FP64 sums of the requested rows.
+template <typename F, int TCH, bool HIST, int KIND>
+__device__ __forceinline__ void charge_times(const SrcRec *__restrict__ R0, int nch, int c, const double x[3],
+                                             int nti, int field_kind, int outputs, int max_iter, double tol_rel,
+                                             double mask_r, bool live, double (&sum)[TCH][10],
+                                             uint32_t (&fl)[TCH], unsigned int *s_hist)
+{
+    Geo g;
+    geo_prepare_k<KIND>(R0[c], x, g);
+#pragma unroll
+    for (int j = 0; j < TCH; ++j) {
+        if (j == 0 || j < nti) {
+            const SrcRec &S = R0[(int64_t)j * nch + c];
+            Kin k;
+            retarded_kind<sizeof(F) == 8, true, KIND>(S, g, x, max_iter, tol_rel, k);
+            F o[10];
+            const F D = lw_terms<F>(k, S.kq, field_kind, o);
+            fl[j] |= k.flags | ((D >= (F)mask_r) ? 0u : FLAG_MASKED);
+            if constexpr (HIST) {
+                if (live) {
+                    const int bin = (k.iters & ITER_FALLBACK) ? ITER_BIN_FALLBACK : min(k.iters, ITER_BIN_FALLBACK - 1);
+                    atomicAdd(&s_hist[bin], 1u);
+                    if (k.flags & FLAG_NOCONV) atomicAdd(&s_hist[ITER_BIN_NOCONV], 1u);
+                }
+            }
+            // the sums the requested rows need (the mask is uniform)
+            if (outputs & OUT_PHI) sum[j][0] += (double)o[0];
+            if (outputs & OUT_A)
+#pragma unroll
+                for (int q = 1; q < 4; ++q) sum[j][q] += (double)o[q];
+            if (outputs & (OUT_E | OUT_S))
+#pragma unroll
+                for (int q = 4; q < 7; ++q) sum[j][q] += (double)o[q];
+            if (outputs & (OUT_B | OUT_S))
+#pragma unroll
+                for (int q = 7; q < 10; ++q) sum[j][q] += (double)o[q];
+        }
+    }
+}
 
 // HIST (a debugging instance, launched with TCH = 1): each workgroup also counts
 // its pairs by the iterations their retarded-time solve took, in LDS, and adds
@@ -138,36 +181,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for(s
     }
     const SrcRec *R0 = recs + (int64_t)t0 * nch;
     for (int c = 0; c < nch; ++c) {
-        Geo g;
-        geo_prepare(R0[c], x, g);
-#pragma unroll
-        for (int j = 0; j < TCH; ++j) {
-            if (j < nti) {
-                const SrcRec &S = R0[(int64_t)j * nch + c];
-                Kin k;
-                retarded_geo<sizeof(F) == 8>(S, g, x, max_iter, tol_rel, k);
-                F o[10];
-                const F D = lw_terms<F>(k, S.kq, field_kind, o);
-                fl[j] |= k.flags | ((D >= (F)mask_r) ? 0u : FLAG_MASKED);
-                if constexpr (HIST) {
-                    if (live) {
-                        const int bin = (k.iters & ITER_FALLBACK) ? ITER_BIN_FALLBACK : min(k.iters, ITER_BIN_FALLBACK - 1);
-                        atomicAdd(&s_hist[bin], 1u);
-                        if (k.flags & FLAG_NOCONV) atomicAdd(&s_hist[ITER_BIN_NOCONV], 1u);
-                    }
-                }
-                // the sums the requested rows need (the mask is uniform)
-                if (outputs & OUT_PHI) sum[j][0] += (double)o[0];
-                if (outputs & OUT_A)
-#pragma unroll
-                    for (int q = 1; q < 4; ++q) sum[j][q] += (double)o[q];
-                if (outputs & (OUT_E | OUT_S))
-#pragma unroll
-                    for (int q = 4; q < 7; ++q) sum[j][q] += (double)o[q];
-                if (outputs & (OUT_B | OUT_S))
-#pragma unroll
-                    for (int q = 7; q < 10; ++q) sum[j][q] += (double)o[q];
-            }
+        // every time's record of a charge carries the charge's family, so the
+        // solver is chosen once per charge and each family's times run as
+        // straight-line code that shares the per-charge constants
+        switch (R0[c].kind) {
+        case K_CIRCULAR:
+            charge_times<F, TCH, HIST, K_CIRCULAR>(R0, nch, c, x, nti, field_kind, outputs, max_iter, tol_rel,
+                                                   mask_r, live, sum, fl, s_hist);
+            break;
+        case K_LINEAR_OSC:
+            charge_times<F, TCH, HIST, K_LINEAR_OSC>(R0, nch, c, x, nti, field_kind, outputs, max_iter, tol_rel,
+                                                     mask_r, live, sum, fl, s_hist);
+            break;
+        case K_ACCEL:
+            charge_times<F, TCH, HIST, K_ACCEL>(R0, nch, c, x, nti, field_kind, outputs, max_iter, tol_rel,
+                                                mask_r, live, sum, fl, s_hist);
+            break;
+        case K_UNIFORM_VELOCITY:
+            charge_times<F, TCH, HIST, K_UNIFORM_VELOCITY>(R0, nch, c, x, nti, field_kind, outputs, max_iter,
+                                                           tol_rel, mask_r, live, sum, fl, s_hist);
+            break;
+        default:
+            charge_times<F, TCH, HIST, K_STATIONARY>(R0, nch, c, x, nti, field_kind, outputs, max_iter, tol_rel,
+                                                     mask_r, live, sum, fl, s_hist);
+            break;
         }
     }
     if constexpr (HIST) {
