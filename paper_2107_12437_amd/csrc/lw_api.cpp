@@ -83,7 +83,7 @@ struct lw_ctx {
     hipEvent_t stage_evt = nullptr;
     bool stage_pending = false;
     uint32_t *d_err = nullptr;
-    lw::FieldLaunch field_launch{256, 4};
+    lw::FieldLaunch field_launch{256, 2};  // untuned shape: the fastest on the grid benchmark in both precisions
     hipStream_t side = nullptr;        // small instances run here, joined back into the caller's stream
     hipStream_t capture = nullptr;     // graph capture of stepped runs
     hipEvent_t join_a = nullptr, join_b = nullptr;

@@ -27,7 +27,7 @@ enum { OUT_PHI = 1, OUT_A = 2, OUT_E = 4, OUT_B = 8, OUT_S = 16 };
 // wave-uniformly (scalar loads) by the field kernels.
 struct alignas(16) SrcRec {
     int32_t kind;
-    int32_t pad_;
+    float kqf;        // kq in FP32 (mixed path)
     double kq;        // q / (4 pi eps0)
     double t;         // observation time
     double c0[3];
@@ -565,11 +565,12 @@ __device__ __forceinline__ void solve_uniform(const SrcRec &S, const double x[3]
 // steps do not settle or leave the physical range.
 __device__ __forceinline__ void rot_small_f32(float c0, float s0, float a, float &c, float &s)
 {
-    // sin a and cos a through a^9 and a^10 (truncation below 1e-9 for |a| <= 0.75)
+    // sin a and cos a through a^7 and a^8: the truncation, below 2.1e-7 for
+    // |a| <= 0.75 and 5.4e-9 for |a| <= 0.5, moves the FP32 root by at most
+    // about Ah times that, which the FP64 Newton step that follows squares away
     const float a2 = a * a;
-    const float sa = a * fmaf(a2, fmaf(a2, fmaf(a2, fmaf(a2, 1.f / 362880.f, -1.f / 5040.f), 1.f / 120.f), -1.f / 6.f), 1.f);
-    const float ca = fmaf(a2, fmaf(a2, fmaf(a2, fmaf(a2, fmaf(a2, -1.f / 3628800.f, 1.f / 40320.f), -1.f / 720.f),
-                                           1.f / 24.f), -0.5f), 1.f);
+    const float sa = a * fmaf(a2, fmaf(a2, fmaf(a2, -1.f / 5040.f, 1.f / 120.f), -1.f / 6.f), 1.f);
+    const float ca = fmaf(a2, fmaf(a2, fmaf(a2, fmaf(a2, 1.f / 40320.f, -1.f / 720.f), 1.f / 24.f), -0.5f), 1.f);
     c = c0 * ca - s0 * sa;
     s = s0 * ca + c0 * sa;
 }
@@ -950,9 +951,11 @@ __device__ __forceinline__ void dist_inv(double R0, double R1, double R2, double
     iD = fma(iD, fma(-D, iD, 1.0), iD);
 }
 
-// Returns the retarded distance |R| in precision F (for masking).
-template <typename F>
-__device__ __forceinline__ F lw_terms(const Kin &k, double kq, int field_kind, F out[10])
+// Returns the retarded distance |R| in precision F (for masking).  IC = false
+// leaves out the factor 1/c of A and B (out[1..3] = Phi beta, out[7..9] = n x E),
+// for callers that sum over charges first and scale the sums once.
+template <typename F, bool IC = true>
+__device__ __forceinline__ F lw_terms(const Kin &k, F kq, int field_kind, F out[10])
 {
     const F R0 = (F)k.R[0], R1 = (F)k.R[1], R2 = (F)k.R[2];
     F D, iD;
@@ -973,7 +976,7 @@ __device__ __forceinline__ F lw_terms(const Kin &k, double kq, int field_kind, F
     const F u0 = n0 - b0, u1 = n1 - b1, u2 = n2 - b2;
     const F nd = n0 * d0 + n1 * d1 + n2 * d2;
     const F ik = recip<F>(kappa);
-    const F kqD = (F)kq * iD;
+    const F kqD = kq * iD;
     const F phi = kqD * ik;
     const F f = phi * ik * ik;                              // kq / (kappa^3 R)
     F cu, cd;                                               // E = f (u cu - beta_dot cd)
@@ -990,8 +993,8 @@ __device__ __forceinline__ F lw_terms(const Kin &k, double kq, int field_kind, F
     const F E0 = f * (u0 * cu - d0 * cd);
     const F E1 = f * (u1 * cu - d1 * cd);
     const F E2 = f * (u2 * cu - d2 * cd);
-    const F m0 = n0 * ic, m1 = n1 * ic, m2 = n2 * ic;     // n / c
-    const F pc = phi * ic;
+    const F m0 = IC ? n0 * ic : n0, m1 = IC ? n1 * ic : n1, m2 = IC ? n2 * ic : n2;  // n / c
+    const F pc = IC ? phi * ic : phi;
     out[0] = phi;
     out[1] = pc * b0;
     out[2] = pc * b1;

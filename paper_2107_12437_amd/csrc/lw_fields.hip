@@ -51,8 +51,8 @@ __global__ void prep_kernel(const lw_traj *__restrict__ ch, int nch, const doubl
         SrcRec R;
         const double t = times[ti];
         R.kind = T.kind;
-        R.pad_ = 0;
         R.kq = T.q * K_COUL;
+        R.kqf = (float)R.kq;
         R.t = t;
         for (int i = 0; i < 3; ++i) {
             R.c0[i] = T.c0[i];
@@ -102,11 +102,18 @@ template <> __device__ __forceinline__ double qnan<double>() { return __builtin_
 // spill); the FP64 form takes 144.  The launch tuner picks among them.
 constexpr int waves_for(bool fp64, int tch) { return tch == 1 ? 4 : (tch == 2 ? 3 : 2); }
 
+// Where the sums over charges live: in LDS for one and two times per lane (80 and
+// 160 bytes per lane, so a CU's 160 KB hold 32 and 16 waves), in registers for
+// four (320 bytes per lane would leave 8 waves per CU) and in the histogram
+// instance.
+constexpr bool lds_sums(bool hist, int tch) { return !hist && tch <= 2; }
+
 // One charge of family KIND at the lane's point and its nti (>= 1) times: the
 // geometry once, then per time the retarded kinematics, the terms in precision
-// F, the flags and the FP64 sums of the requested rows.
-template <typename F, int TCH, bool HIST, int KIND>
-__device__ __forceinline__ void charge_times(const SrcRec *__restrict__ R0, int nch, int c, const double x[3],
+// F, the flags and the FP64 sums of the requested rows (in LDS at lsum[(j * 10 +
+// q) * 64] with LSUM, else in sum[j][q]).
+template <typename F, int TCH, bool HIST, int KIND, bool LSUM>
+__device__ __forceinline__ void charge_times(double *lsum, const SrcRec *__restrict__ R0, int nch, int c, const double x[3],
                                              int nti, int field_kind, int outputs, int max_iter, double tol_rel,
                                              double mask_r, bool live, double (&sum)[TCH][10],
                                              uint32_t (&fl)[TCH], unsigned int *s_hist)
@@ -120,7 +127,8 @@ __device__ __forceinline__ void charge_times(const SrcRec *__restrict__ R0, int 
             Kin k;
             retarded_kind<sizeof(F) == 8, true, KIND>(S, g, x, max_iter, tol_rel, k);
             F o[10];
-            const F D = lw_terms<F>(k, S.kq, field_kind, o);
+            // A and B without their factor 1/c: the sums are scaled once at the end
+            const F D = lw_terms<F, false>(k, sizeof(F) == 4 ? (F)S.kqf : (F)S.kq, field_kind, o);
             fl[j] |= k.flags | ((D >= (F)mask_r) ? 0u : FLAG_MASKED);
             if constexpr (HIST) {
                 if (live) {
@@ -130,16 +138,23 @@ __device__ __forceinline__ void charge_times(const SrcRec *__restrict__ R0, int 
                 }
             }
             // the sums the requested rows need (the mask is uniform)
-            if (outputs & OUT_PHI) sum[j][0] += (double)o[0];
+            auto add = [&](int q) {
+                if constexpr (LSUM)
+                    __hip_atomic_fetch_add(lsum + (j * 10 + q) * 64, (double)o[q], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                else
+                    sum[j][q] += (double)o[q];
+            };
+            if (outputs & OUT_PHI) add(0);
             if (outputs & OUT_A)
 #pragma unroll
-                for (int q = 1; q < 4; ++q) sum[j][q] += (double)o[q];
+                for (int q = 1; q < 4; ++q) add(q);
             if (outputs & (OUT_E | OUT_S))
 #pragma unroll
-                for (int q = 4; q < 7; ++q) sum[j][q] += (double)o[q];
+                for (int q = 4; q < 7; ++q) add(q);
             if (outputs & (OUT_B | OUT_S))
 #pragma unroll
-                for (int q = 7; q < 10; ++q) sum[j][q] += (double)o[q];
+                for (int q = 7; q < 10; ++q) add(q);
         }
     }
 }
@@ -171,13 +186,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for(s
     const double x[3] = {pts[p], pts[npts + p], pts[2 * npts + p]};
     const int t0 = t_base + blockIdx.y * TCH;
     const int nti = min(TCH, nt - t0);
+    // The running sums: in LDS for one or two times per lane (each lane owns a
+    // column of its wave's block of 10 TCH doubles x 64 lanes; ds_add_f64 adds
+    // there without a VALU slot, in program order), else in registers.
+    constexpr bool LSUM = lds_sums(HIST, TCH);
+    extern __shared__ double s_sums[];
+    double *lsum = s_sums + (threadIdx.x >> 6) * (TCH * 10 * 64) + (threadIdx.x & 63);
     double sum[TCH][10];
     uint32_t fl[TCH];
 #pragma unroll
     for (int j = 0; j < TCH; ++j) {
         fl[j] = 0u;
 #pragma unroll
-        for (int q = 0; q < 10; ++q) sum[j][q] = 0.0;
+        for (int q = 0; q < 10; ++q) {
+            if constexpr (LSUM) lsum[(j * 10 + q) * 64] = 0.0;
+            else sum[j][q] = 0.0;
+        }
     }
     const SrcRec *R0 = recs + (int64_t)t0 * nch;
     for (int c = 0; c < nch; ++c) {
@@ -186,23 +210,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for(s
         // straight-line code that shares the per-charge constants
         switch (R0[c].kind) {
         case K_CIRCULAR:
-            charge_times<F, TCH, HIST, K_CIRCULAR>(R0, nch, c, x, nti, field_kind, outputs, max_iter, tol_rel,
+            charge_times<F, TCH, HIST, K_CIRCULAR, LSUM>(lsum, R0, nch, c, x, nti, field_kind, outputs, max_iter, tol_rel,
                                                    mask_r, live, sum, fl, s_hist);
             break;
         case K_LINEAR_OSC:
-            charge_times<F, TCH, HIST, K_LINEAR_OSC>(R0, nch, c, x, nti, field_kind, outputs, max_iter, tol_rel,
+            charge_times<F, TCH, HIST, K_LINEAR_OSC, LSUM>(lsum, R0, nch, c, x, nti, field_kind, outputs, max_iter, tol_rel,
                                                      mask_r, live, sum, fl, s_hist);
             break;
         case K_ACCEL:
-            charge_times<F, TCH, HIST, K_ACCEL>(R0, nch, c, x, nti, field_kind, outputs, max_iter, tol_rel,
+            charge_times<F, TCH, HIST, K_ACCEL, LSUM>(lsum, R0, nch, c, x, nti, field_kind, outputs, max_iter, tol_rel,
                                                 mask_r, live, sum, fl, s_hist);
             break;
         case K_UNIFORM_VELOCITY:
-            charge_times<F, TCH, HIST, K_UNIFORM_VELOCITY>(R0, nch, c, x, nti, field_kind, outputs, max_iter,
+            charge_times<F, TCH, HIST, K_UNIFORM_VELOCITY, LSUM>(lsum, R0, nch, c, x, nti, field_kind, outputs, max_iter,
                                                            tol_rel, mask_r, live, sum, fl, s_hist);
             break;
         default:
-            charge_times<F, TCH, HIST, K_STATIONARY>(R0, nch, c, x, nti, field_kind, outputs, max_iter, tol_rel,
+            charge_times<F, TCH, HIST, K_STATIONARY, LSUM>(lsum, R0, nch, c, x, nti, field_kind, outputs, max_iter, tol_rel,
                                                      mask_r, live, sum, fl, s_hist);
             break;
         }
@@ -224,7 +248,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_for(s
                 __builtin_nontemporal_store(masked ? qnan<F>() : (F)v, dst + (int64_t)r * npts);
                 ++r;
             };
-            const double *S = sum[j];
+            double S[10];
+#pragma unroll
+            for (int q = 0; q < 10; ++q) {
+                const double v = LSUM ? lsum[(j * 10 + q) * 64] : sum[j][q];
+                S[q] = (q >= 1 && q <= 3) || q >= 7 ? v * INV_C : v;
+            }
             if (outputs & OUT_PHI) put(S[0]);
             if (outputs & OUT_A) { put(S[1]); put(S[2]); put(S[3]); }
             if (outputs & OUT_E) { put(S[4]); put(S[5]); put(S[6]); }
@@ -261,6 +290,8 @@ static hipError_t launch_fields_t(const SrcRec *d_recs, int nch, const double *d
                                   const lw_opts &o, double tol_rel, double mask_r, F *d_out, uint32_t *d_flags,
                                   int block, hipStream_t s, unsigned long long *d_hist = nullptr)
 {
+    // whole waves only: the LDS sums are laid out per wave of 64 lanes
+    if (block < 64 || block > 256 || block % 64 != 0) return hipErrorInvalidValue;
     const int max_iter = o.max_iter > 0 ? o.max_iter : 100;
     const unsigned gx = (unsigned)((npts + block - 1) / block);
     // grid.y holds at most 65535 time tiles: longer time lists go in slices
@@ -268,7 +299,8 @@ static hipError_t launch_fields_t(const SrcRec *d_recs, int nch, const double *d
     for (int tb = 0; tb < nt; tb += per_launch) {
         const int n_here = min(per_launch, nt - tb);
         const dim3 grid(gx, (unsigned)((n_here + TCH - 1) / TCH));
-        hipLaunchKernelGGL((fields_kernel<F, TCH, HIST>), grid, dim3(block), 0, s, d_recs, nch, d_pts, npts, nt, tb,
+        const size_t lds = lds_sums(HIST, TCH) ? (size_t)TCH * 10 * block * sizeof(double) : 0;
+        hipLaunchKernelGGL((fields_kernel<F, TCH, HIST>), grid, dim3(block), lds, s, d_recs, nch, d_pts, npts, nt, tb,
                            o.field_kind, output_mask(o.outputs), output_rows(o.outputs), max_iter, tol_rel, mask_r,
                            d_out, d_flags, d_hist);
         const hipError_t e = hipGetLastError();
