@@ -77,7 +77,8 @@ lw_status lw_sync_status(lw_ctx *ctx, void *stream);
 /* Launch-shape tuning of lw_fields (on by default; LW_AUTOTUNE=0 in the
  * environment turns it off at lw_create).  While on, the first lw_fields call
  * of each shape class (precision, field kind, charge and time counts, point
- * count rounded up to a power of two) times every candidate workgroup size and
+ * count rounded up to a power of two, the set of trajectory kinds present, the
+ * output groups) times every candidate workgroup size and
  * times-per-workgroup on its own inputs and keeps the fastest: that call
  * synchronises `stream` and writes d_out several times, the last time with the
  * result.  Choices persist in the context, and across processes in the file

@@ -210,13 +210,21 @@ lw_status check_traj(const lw_traj &T, int idx, double t_max)
 
 // Shape class of a grid-field call: precision, field kind, charges, times and
 // the point count rounded up to a power of two.
-std::string field_key(const lw_opts &o, int nch, int nt, int64_t npts)
+// Shape class of a grid call: precision, field kind, charge and time counts, the
+// point count rounded up to a power of two, the set of trajectory families present
+// (bit k for kind k: each family's solver has its own cost and register needs) and
+// the output rows when not all four groups.
+std::string field_key(const lw_opts &o, const lw_traj *ch, int nch, int nt, int64_t npts)
 {
     int64_t p2 = 1;
     while (p2 < npts) p2 <<= 1;
+    unsigned fam = 0u;
+    for (int c = 0; c < nch; ++c)
+        if (ch[c].kind >= 0 && ch[c].kind < 32) fam |= 1u << ch[c].kind;
     const int om = lw::output_mask(o.outputs);
     return "fields p" + std::to_string(o.precision) + " k" + std::to_string(o.field_kind) + " c" + std::to_string(nch) +
-           " t" + std::to_string(nt) + " n" + std::to_string(p2) + (om == 15 ? "" : " o" + std::to_string(om));
+           " t" + std::to_string(nt) + " n" + std::to_string(p2) + " f" + std::to_string(fam) +
+           (om == 15 ? "" : " o" + std::to_string(om));
 }
 
 void load_tune_file(lw_ctx *ctx)
@@ -561,7 +569,7 @@ lw_status lw_fields(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, co
         return LW_OK;
     }
     lw::FieldLaunch L = ctx->field_launch;
-    const std::string key = field_key(*opts, n_charges, n_times, n_pts);
+    const std::string key = field_key(*opts, h_charges, n_charges, n_times, n_pts);
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end()) {
         L = it->second;

@@ -18,11 +18,14 @@ def _workload():
     return w
 
 
-def _key(precision_code, n_charges, n_times, n_pts):
+def _key(precision_code, n_charges, n_times, n_pts, kinds):
     p2 = 1
     while p2 < n_pts:
         p2 <<= 1
-    return f"fields p{precision_code} k0 c{n_charges} t{n_times} n{p2}"
+    fam = 0
+    for k in kinds:
+        fam |= 1 << int(k)
+    return f"fields p{precision_code} k0 c{n_charges} t{n_times} n{p2} f{fam}"
 
 
 @pytest.mark.parametrize("precision,code", [("mixed", 1), ("fp64", 0)])
@@ -36,7 +39,7 @@ def test_every_shape_gives_the_same_bits(tmp_path, monkeypatch, precision, code)
     for block in (64, 128, 256):
         for tch in (1, 2, 4):
             f = tmp_path / f"tune_{precision}_{block}_{tch}.txt"
-            f.write_text(f"{_key(code, n_ch, n_t, n_pts)} | {block} {tch}\n")
+            f.write_text(f"{_key(code, n_ch, n_t, n_pts, w['charges']['kind'])} | {block} {tch}\n")
             monkeypatch.setenv("LW_TUNE_CACHE", str(f))
             ctx = lw.Context(0)
             out, flags = lw.fields(w["charges"], pts, w["times"], precision=precision, ctx=ctx)
@@ -66,7 +69,7 @@ def test_tuned_shape_is_cached_and_reused(tmp_path, monkeypatch):
     lines = [ln for ln in f.read_text().splitlines() if ln.strip()]
     assert len(lines) == 1, lines                     # tuned once, kept in the context
     key, shape = lines[0].split("|")
-    assert key.strip() == _key(1, len(w["charges"]["kind"]), len(w["times"]), pts.shape[1])
+    assert key.strip() == _key(1, len(w["charges"]["kind"]), len(w["times"]), pts.shape[1], w["charges"]["kind"])
     block, tch = (int(v) for v in shape.split())
     assert block in (64, 128, 256) and tch in (1, 2, 4)
     assert torch.equal(out1, out2)
@@ -86,3 +89,23 @@ def test_tuned_shape_is_cached_and_reused(tmp_path, monkeypatch):
     ctx.close()
     assert torch.equal(out1, out4)
     assert not np.isnan(out1.cpu().numpy()).all()
+
+
+def test_family_set_is_part_of_the_shape_class(tmp_path, monkeypatch):
+    import torch
+    from paper_2107_12437_amd import lw
+    w = _workload()
+    pts = torch.tensor(w["points"], dtype=torch.float64, device="cuda")
+    f = tmp_path / "tune.txt"
+    monkeypatch.setenv("LW_TUNE_CACHE", str(f))
+    monkeypatch.delenv("LW_AUTOTUNE", raising=False)
+    still = dict(w["charges"])
+    still["kind"] = np.full_like(w["charges"]["kind"], I.STATIONARY)
+    ctx = lw.Context(0)
+    lw.fields(w["charges"], pts, w["times"], precision="mixed", ctx=ctx)
+    lw.fields(still, pts, w["times"], precision="mixed", ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.close()
+    keys = [ln.split("|")[0].strip() for ln in f.read_text().splitlines() if ln.strip()]
+    n_ch, n_t, n_pts = len(w["charges"]["kind"]), len(w["times"]), pts.shape[1]
+    assert keys == [_key(1, n_ch, n_t, n_pts, w["charges"]["kind"]), _key(1, n_ch, n_t, n_pts, still["kind"])]
