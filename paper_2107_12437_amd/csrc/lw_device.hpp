@@ -129,6 +129,37 @@ __device__ __forceinline__ void sincos_reduced(double x, double &s, double &c)
     c = ((q + 1) & 2) ? -b : b;
 }
 
+// sin and cos to about 1e-11 absolute (mixed path only, whose outputs are FP32):
+// the same reduction, then Taylor terms through x^11 and x^12 for |r| <= pi/4
+// (truncation below 7e-12 and 4e-13).
+__device__ __forceinline__ void sincos_reduced_short(double x, double &s, double &c)
+{
+    const double P1 = 0x1.921fb54442d18p+0;     // pi/2 = P1 + P2 + P3
+    const double P2 = 0x1.1a62633145c07p-54;
+    const double P3 = -0x1.f1976b7ed8fbcp-110;
+    const double k = rint(x * 0x1.45f306dc9c883p-1);   // x * 2/pi
+    double r = fma(-k, P1, x);
+    r = fma(-k, P2, r);
+    r = fma(-k, P3, r);
+    const double r2 = r * r;
+    double ps = fma_k(r2, -1.0 / 39916800.0, 1.0 / 362880.0);   // -1/11!, 1/9!
+    ps = fma_k(ps, r2, -1.0 / 5040.0);
+    ps = fma_k(ps, r2, 1.0 / 120.0);
+    ps = fma_k(ps, r2, -1.0 / 6.0);
+    const double sr = fma(r * r2, ps, r);
+    double pc = fma_k(r2, 1.0 / 479001600.0, -1.0 / 3628800.0);  // 1/12!, -1/10!
+    pc = fma_k(pc, r2, 1.0 / 40320.0);
+    pc = fma_k(pc, r2, -1.0 / 720.0);
+    pc = fma_k(pc, r2, 1.0 / 24.0);
+    pc = fma(pc, r2, -0.5);
+    const double cr = fma(pc, r2, 1.0);
+    const int q = (int)k & 3;
+    const double a = (q & 1) ? cr : sr;
+    const double b = (q & 1) ? sr : cr;
+    s = (q & 2) ? -a : a;
+    c = ((q + 1) & 2) ? -b : b;
+}
+
 // Square root for bounds and starting values only (v_sqrt_f64, relative error
 // near 2^-22): callers widen what they derive from it.
 __device__ __forceinline__ double sqrt_rough(double x) { return __builtin_amdgcn_sqrt(x); }
@@ -304,8 +335,13 @@ struct Geo {
 
 // The time-independent part of the retarded-time problem for a charge of family
 // KIND (the record of any observation time), seen from x.  The stationary and
-// uniform families need only w.
-template <int KIND>
+// uniform families need only w.  FULL = false (the mixed path's correction solve)
+// leaves out the bracket lo, hi, which only the safeguarded solver reads (the
+// mixed path's fallback builds its own), and takes the phase of tau0 to about
+// 1e-11.  The start tau0 is the RMS distance to the orbit over c: the mean of the
+// squared distance lies between its least and greatest values, so the clamp to
+// the bracket never moves it.
+template <int KIND, bool FULL = true>
 __device__ __forceinline__ void geo_prepare_k(const SrcRec &S, const double x[3], Geo &g)
 {
     for (int i = 0; i < 3; ++i) g.w[i] = x[i] - S.c0[i];
@@ -319,14 +355,19 @@ __device__ __forceinline__ void geo_prepare_k(const SrcRec &S, const double x[3]
         const double w3 = w[0] * S.e3[0] + w[1] * S.e3[1] + w[2] * S.e3[2];
         g.w2 = w2;
         g.w3 = w3;
-        const double rho = sqrt_rough(w1 * w1 + w2 * w2);
         const double WA = w1 * w1 + w2 * w2 + w3 * w3 + A * A;
-        // the distance to the orbit lies between these, so c tau does too
-        // (widened by 1e-6 to cover the rough square roots)
-        g.lo = sqrt_rough(w3 * w3 + (rho - A) * (rho - A)) * (INV_C * (1.0 - 1e-6));
-        g.hi = sqrt_rough(w3 * w3 + (rho + A) * (rho + A)) * (INV_C * (1.0 + 1e-6));
-        g.tau0 = fmin(fmax(sqrt_rough(WA) * INV_C, g.lo), g.hi);
-        sincos_reduced(S.omega * g.tau0, g.sw, g.cw);
+        if constexpr (FULL) {
+            const double rho = sqrt_rough(w1 * w1 + w2 * w2);
+            // the distance to the orbit lies between these, so c tau does too
+            // (widened by 1e-6 to cover the rough square roots)
+            g.lo = sqrt_rough(w3 * w3 + (rho - A) * (rho - A)) * (INV_C * (1.0 - 1e-6));
+            g.hi = sqrt_rough(w3 * w3 + (rho + A) * (rho + A)) * (INV_C * (1.0 + 1e-6));
+            g.tau0 = fmin(fmax(sqrt_rough(WA) * INV_C, g.lo), g.hi);
+            sincos_reduced(S.omega * g.tau0, g.sw, g.cw);
+        } else {
+            g.tau0 = sqrt_rough(WA) * INV_C;
+            sincos_reduced_short(S.omega * g.tau0, g.sw, g.cw);
+        }
         const double D0 = C_LIGHT * g.tau0, iD0 = rcp_steer(D0);
         g.w1h = w1 * iD0;
         g.w2h = w2 * iD0;
@@ -340,11 +381,16 @@ __device__ __forceinline__ void geo_prepare_k(const SrcRec &S, const double x[3]
         g.w2 = perp2;
         if constexpr (KIND == K_LINEAR_OSC) {
             const double W2 = perp2 + w1 * w1;
-            const double u = fmin(fmax(w1, -A), A);
-            g.lo = sqrt_rough(perp2 + (w1 - u) * (w1 - u)) * (INV_C * (1.0 - 1e-6));
-            g.hi = sqrt_rough(W2 + A * A + 2.0 * A * fabs(w1)) * (INV_C * (1.0 + 1e-6));
-            g.tau0 = fmin(fmax(sqrt_rough(W2 + 0.5 * A * A) * INV_C, g.lo), g.hi);
-            sincos_reduced(S.omega * g.tau0, g.sw, g.cw);
+            if constexpr (FULL) {
+                const double u = fmin(fmax(w1, -A), A);
+                g.lo = sqrt_rough(perp2 + (w1 - u) * (w1 - u)) * (INV_C * (1.0 - 1e-6));
+                g.hi = sqrt_rough(W2 + A * A + 2.0 * A * fabs(w1)) * (INV_C * (1.0 + 1e-6));
+                g.tau0 = fmin(fmax(sqrt_rough(W2 + 0.5 * A * A) * INV_C, g.lo), g.hi);
+                sincos_reduced(S.omega * g.tau0, g.sw, g.cw);
+            } else {
+                g.tau0 = sqrt_rough(W2 + 0.5 * A * A) * INV_C;
+                sincos_reduced_short(S.omega * g.tau0, g.sw, g.cw);
+            }
             const double D0 = C_LIGHT * g.tau0, iD0 = rcp_steer(D0);
             g.w1h = w1 * iD0;
             g.w2h = 0.0;

@@ -119,7 +119,7 @@ __device__ __forceinline__ void charge_times(double *lsum, const SrcRec *__restr
                                              uint32_t (&fl)[TCH], unsigned int *s_hist)
 {
     Geo g;
-    geo_prepare_k<KIND>(R0[c], x, g);
+    geo_prepare_k<KIND, sizeof(F) == 8>(R0[c], x, g);
 #pragma unroll
     for (int j = 0; j < TCH; ++j) {
         if (j == 0 || j < nti) {
