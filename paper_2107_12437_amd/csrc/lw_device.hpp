@@ -673,6 +673,19 @@ __device__ __forceinline__ void rot_phase(double c0, double s0, double a, double
     s = s0 * ca + c0 * sa;
 }
 
+// The same rotation for the mixed path, through a^9 and a^10 (truncation below
+// 1.1e-9 for |a| <= 0.75 and 1.3e-11 for |a| <= 0.5, against FP32 outputs).
+__device__ __forceinline__ void rot_phase_short(double c0, double s0, double a, double &c, double &s)
+{
+    const double a2 = a * a;
+    const double sa = a * fma_k(a2, fma_k(a2, fma_k(a2, fma_k(a2, 1.0 / 362880.0, -1.0 / 5040.0), 1.0 / 120.0),
+                                          -1.0 / 6.0), 1.0);
+    const double ca = fma_k(a2, fma_k(a2, fma_k(a2, fma_k(a2, fma_k(a2, -1.0 / 3628800.0, 1.0 / 40320.0),
+                                                          -1.0 / 720.0), 1.0 / 24.0), -0.5), 1.0);
+    c = c0 * ca - s0 * sa;
+    s = s0 * ca + c0 * sa;
+}
+
 // f(u) and f'(u) of the correction form in FP64 at phase (cd, sd).
 template <int KIND>
 __device__ __forceinline__ void u_f64(const Geo &g, double ud, double cd, double sd, double &fv, double &fp)
@@ -699,9 +712,11 @@ __device__ __forceinline__ bool solve_u_mixed(const SrcRec &S, const Geo &g, Kin
     const bool ok = u_stage_f32<KIND>(g, c0, s0, 0x1p-7f, u, n32);
     const double a = -g.kh * (double)u;
     if (!ok || !(fabs(a) <= 0.75) || !(u > -0.5f)) return false;
-    // one Newton step in FP64 from the exact phase
+    // one Newton step in FP64 from the exact phase (f' in FP64 too: an FP32 f' + f'' d
+    // from the last Halley step was tried, and where the terms of f' cancel its
+    // rounding left the vector potential's pointwise error 30 times larger)
     double cd, sd;
-    rot_phase(c0, s0, a, cd, sd);
+    rot_phase_short(c0, s0, a, cd, sd);
     double ud = (double)u, fv, fp;
     u_f64<KIND>(g, ud, cd, sd, fv, fp);
     const double du = -fv * rcp_steer(fp);
