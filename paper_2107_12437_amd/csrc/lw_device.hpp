@@ -719,7 +719,9 @@ __device__ __forceinline__ bool solve_u_mixed(const SrcRec &S, const Geo &g, Kin
     rot_phase_short(c0, s0, a, cd, sd);
     double ud = (double)u, fv, fp;
     u_f64<KIND>(g, ud, cd, sd, fv, fp);
-    const double du = -fv * rcp_steer(fp);
+    // v_rcp_f64 unrefined (relative error below 2^-26): the step is of the size
+    // of the FP32 stage's remaining error, so this moves u by far less than 1e-13
+    const double du = -fv * __builtin_amdgcn_rcp(fp);
     ud += du;
     // rotate the phase by the correction's angle e (second order: |e| is of the
     // order of kh times the FP32 steps' error, so e^3 / 6 stays far below FP32
