@@ -831,6 +831,11 @@ __device__ __forceinline__ bool solve_u_full(const SrcRec &S, const Geo &g, Kin 
 // so a lane whose FP32 steps did not settle continues with FP64 Newton steps
 // (up to 30) instead of a separate bracketed solver, whose registers would
 // spill the kernel; only if those fail too is the point flagged.
+// FULL (the FP64 path): the FP32 steps run to 2^-10 and the FP64 Newton steps
+// continue until a step is below 2^-50 (1 + |u|), three in the usual case (the
+// second leaves about the square of the FP32 stage's error, the third confirms);
+// returns false if they do not, and the caller takes the safeguarded solver.
+template <bool FULL = false>
 __device__ __forceinline__ bool solve_u_accel(const SrcRec &S, const Geo &g, Kin &k)
 {
     const double t = S.t, acc = S.accel, L = S.Lmax;
@@ -860,15 +865,16 @@ __device__ __forceinline__ bool solve_u_accel(const SrcRec &S, const Geo &g, Kin
         den = den > fp2 ? den : 2.f * fp2;
         const float d = -2.f * fv * fp * __builtin_amdgcn_rcpf(den);
         u += d;
-        if (fabsf(d) <= 0x1p-7f) {
+        if (fabsf(d) <= (FULL ? 0x1p-10f : 0x1p-7f)) {
             ok = true;
             break;
         }
     }
-    // FP64 Newton: one step after settled FP32 steps, else until it settles
+    // FP64 Newton: one step after settled FP32 steps (FULL: until converged, at most
+    // three), else until it settles
     double ud = (ok && u > -0.5f) ? (double)u : 0.0;
-    const int n_newton = (ok && u > -0.5f) ? 1 : 30;
-    bool conv = n_newton == 1;
+    const int n_newton = (ok && u > -0.5f) ? (FULL ? 3 : 1) : 30;
+    bool conv = !FULL && n_newton == 1;
     for (int it = 0; it < n_newton; ++it) {
         ++n_it;
         const double tau = fma(tau0, ud, tau0);
@@ -942,7 +948,7 @@ __device__ __forceinline__ void retarded_kind(const SrcRec &S, const Geo &g, con
         }
     } else if constexpr (KIND == K_ACCEL) {
         if (FULL) {
-            solve_accel<FULL>(S, g, max_iter, tol_rel, k);
+            if (!CORR || !solve_u_accel<true>(S, g, k)) solve_accel<FULL>(S, g, max_iter, tol_rel, k);
         } else {
             solve_u_accel(S, g, k);
             kin_beta_from_va(k);
