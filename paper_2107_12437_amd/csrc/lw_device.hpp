@@ -762,8 +762,9 @@ __device__ __forceinline__ bool solve_u_mixed(const SrcRec &S, const Geo &g, Kin
 // after the second step.  The root is accepted when Newton's bound on the remaining error,
 // |f''| du^2 / (2 |f'|) with |f''| <= 2 + 2 Ah kh^2 M (M = |(w1h, w2h)| for the
 // circular orbit, |w1h| + Ah for the linear one), is below 2^-54, about half an
-// ulp of u near 1; otherwise (and when the FP32 steps do not settle) the
-// caller takes the safeguarded Halley solver.  R, v and a come out in FP64.
+// ulp of u near 1, and the second step's angle is below 2^-27 (its phase follows
+// by a first-order rotation); otherwise (and when the FP32 steps do not settle)
+// the caller takes the safeguarded Halley solver.  R, v and a come out in FP64.
 template <int KIND>
 __device__ __forceinline__ bool solve_u_full(const SrcRec &S, const Geo &g, Kin &k)
 {
@@ -779,16 +780,29 @@ __device__ __forceinline__ bool solve_u_full(const SrcRec &S, const Geo &g, Kin 
     double cd, sd;
     rot_phase(c0, s0, a, cd, sd);
     double ud = (double)u, fv, fp;
-    double du = 0.0;
-    bool small = true;
-    for (int it = 0; it < 2; ++it) {
-        u_f64<KIND>(g, ud, cd, sd, fv, fp);
-        du = -fv * rcp_steer(fp);
-        ud += du;
-        const double e = -g.kh * du, e2 = e * e;
-        small = small && fabs(e) <= 1e-3;
+    // first step: the phase follows by a fourth-order rotation (its angle is below
+    // 1e-3 on acceptance, so the truncation e^5 / 120 is below 1e-17)
+    u_f64<KIND>(g, ud, cd, sd, fv, fp);
+    double du = -fv * rcp_steer(fp);
+    ud += du;
+    double e = -g.kh * du;
+    bool small = fabs(e) <= 1e-3;
+    {
+        const double e2 = e * e;
         const double ce = fma(e2, fma(e2, 1.0 / 24.0, -0.5), 1.0), se = e * fma(e2, -1.0 / 6.0, 1.0);
         const double cn = cd * ce - sd * se, sn = sd * ce + cd * se;
+        cd = cn;
+        sd = sn;
+    }
+    // second step: its angle is below 2^-27 on acceptance, so a first-order
+    // rotation is exact to e^2 / 2 < 3e-17
+    u_f64<KIND>(g, ud, cd, sd, fv, fp);
+    du = -fv * rcp_steer(fp);
+    ud += du;
+    e = -g.kh * du;
+    small = small && fabs(e) <= 0x1p-27;
+    {
+        const double cn = fma(-sd, e, cd), sn = fma(cd, e, sd);
         cd = cn;
         sd = sn;
     }
