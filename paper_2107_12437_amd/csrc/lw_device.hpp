@@ -335,13 +335,13 @@ struct Geo {
 
 // The time-independent part of the retarded-time problem for a charge of family
 // KIND (the record of any observation time), seen from x.  The stationary and
-// uniform families need only w.  FULL = false (the mixed path's correction solve)
-// leaves out the bracket lo, hi, which only the safeguarded solver reads (the
-// mixed path's fallback builds its own), and takes the phase of tau0 to about
-// 1e-11.  The start tau0 is the RMS distance to the orbit over c: the mean of the
-// squared distance lies between its least and greatest values, so the clamp to
-// the bracket never moves it.
-template <int KIND, bool FULL = true>
+// uniform families need only w.  BRACKET: also the bracket lo, hi, which only the
+// safeguarded solver reads (the correction solves' fallbacks build their own).
+// The start tau0 is the RMS distance to the orbit over c: the mean of the squared
+// distance lies between its least and greatest values, so the clamp to the
+// bracket never moves it.  PHASE64 = false (mixed path) takes the phase of tau0
+// to about 1e-11 instead of to FP64 rounding.
+template <int KIND, bool BRACKET = true, bool PHASE64 = true>
 __device__ __forceinline__ void geo_prepare_k(const SrcRec &S, const double x[3], Geo &g)
 {
     for (int i = 0; i < 3; ++i) g.w[i] = x[i] - S.c0[i];
@@ -356,18 +356,18 @@ __device__ __forceinline__ void geo_prepare_k(const SrcRec &S, const double x[3]
         g.w2 = w2;
         g.w3 = w3;
         const double WA = w1 * w1 + w2 * w2 + w3 * w3 + A * A;
-        if constexpr (FULL) {
+        if constexpr (BRACKET) {
             const double rho = sqrt_rough(w1 * w1 + w2 * w2);
             // the distance to the orbit lies between these, so c tau does too
             // (widened by 1e-6 to cover the rough square roots)
             g.lo = sqrt_rough(w3 * w3 + (rho - A) * (rho - A)) * (INV_C * (1.0 - 1e-6));
             g.hi = sqrt_rough(w3 * w3 + (rho + A) * (rho + A)) * (INV_C * (1.0 + 1e-6));
             g.tau0 = fmin(fmax(sqrt_rough(WA) * INV_C, g.lo), g.hi);
-            sincos_reduced(S.omega * g.tau0, g.sw, g.cw);
         } else {
             g.tau0 = sqrt_rough(WA) * INV_C;
-            sincos_reduced_short(S.omega * g.tau0, g.sw, g.cw);
         }
+        if constexpr (PHASE64) sincos_reduced(S.omega * g.tau0, g.sw, g.cw);
+        else sincos_reduced_short(S.omega * g.tau0, g.sw, g.cw);
         const double D0 = C_LIGHT * g.tau0, iD0 = rcp_steer(D0);
         g.w1h = w1 * iD0;
         g.w2h = w2 * iD0;
@@ -381,16 +381,16 @@ __device__ __forceinline__ void geo_prepare_k(const SrcRec &S, const double x[3]
         g.w2 = perp2;
         if constexpr (KIND == K_LINEAR_OSC) {
             const double W2 = perp2 + w1 * w1;
-            if constexpr (FULL) {
+            if constexpr (BRACKET) {
                 const double u = fmin(fmax(w1, -A), A);
                 g.lo = sqrt_rough(perp2 + (w1 - u) * (w1 - u)) * (INV_C * (1.0 - 1e-6));
                 g.hi = sqrt_rough(W2 + A * A + 2.0 * A * fabs(w1)) * (INV_C * (1.0 + 1e-6));
                 g.tau0 = fmin(fmax(sqrt_rough(W2 + 0.5 * A * A) * INV_C, g.lo), g.hi);
-                sincos_reduced(S.omega * g.tau0, g.sw, g.cw);
             } else {
                 g.tau0 = sqrt_rough(W2 + 0.5 * A * A) * INV_C;
-                sincos_reduced_short(S.omega * g.tau0, g.sw, g.cw);
             }
+            if constexpr (PHASE64) sincos_reduced(S.omega * g.tau0, g.sw, g.cw);
+            else sincos_reduced_short(S.omega * g.tau0, g.sw, g.cw);
             const double D0 = C_LIGHT * g.tau0, iD0 = rcp_steer(D0);
             g.w1h = w1 * iD0;
             g.w2h = 0.0;
@@ -398,16 +398,6 @@ __device__ __forceinline__ void geo_prepare_k(const SrcRec &S, const double x[3]
             g.kh = S.omega * g.tau0;
             g.K0h = fma(-D0, D0, W2) * (iD0 * iD0);
         }
-    }
-}
-
-__device__ __forceinline__ void geo_prepare(const SrcRec &S, const double x[3], Geo &g)
-{
-    switch (S.kind) {
-    case K_CIRCULAR: geo_prepare_k<K_CIRCULAR>(S, x, g); break;
-    case K_LINEAR_OSC: geo_prepare_k<K_LINEAR_OSC>(S, x, g); break;
-    case K_ACCEL: geo_prepare_k<K_ACCEL>(S, x, g); break;
-    default: geo_prepare_k<K_STATIONARY>(S, x, g); break;
     }
 }
 
@@ -924,40 +914,41 @@ __device__ __forceinline__ bool solve_u_accel(const SrcRec &S, const Geo &g, Kin
     return conv;
 }
 
-// The mixed path's rare fallback for the oscillating families (a correction
-// solve that did not settle): the safeguarded solver on a geometry rebuilt
-// here, so that its frame coordinates and bracket need not stay live across
-// the times.
-template <int KIND>
-__device__ __forceinline__ void retarded_fallback_mixed(const SrcRec &S, const double x[3], int max_iter,
-                                                        double tol_rel, Kin &k)
+// The rare fallback of the correction solves for the oscillating families (a
+// solve that did not settle): the safeguarded solver on a geometry rebuilt here
+// with its bracket, so that the main path neither builds the bracket nor keeps
+// the frame coordinates live across the times.
+template <bool FULL, int KIND>
+__device__ __forceinline__ void retarded_fallback(const SrcRec &S, const double x[3], int max_iter, double tol_rel,
+                                                  Kin &k)
 {
     Geo gf;
     geo_prepare_k<KIND>(S, x, gf);
-    if constexpr (KIND == K_CIRCULAR) solve_circular<false>(S, gf, max_iter, tol_rel, k);
-    else solve_linear<false>(S, gf, max_iter, tol_rel, k);
+    if constexpr (KIND == K_CIRCULAR) solve_circular<FULL>(S, gf, max_iter, tol_rel, k);
+    else solve_linear<FULL>(S, gf, max_iter, tol_rel, k);
 }
 
-// Retarded kinematics of source S (its record for the observation time) seen
-// from point x, with g = geo_prepare(record of any time of this source, x).
-// FULL: FP64 tolerance (square roots to about one ulp); otherwise the mixed
-// path's relaxed tolerance.  CORR (FULL only): the oscillating families try the
-// correction solve first; without it they take the safeguarded Halley solver
-// directly (fewer live registers, for kernels whose occupancy it would cost).
-// retarded_kind serves a source of family KIND (S.kind == KIND, g from
-// geo_prepare_k<KIND>); retarded_geo dispatches on S.kind.
+// Retarded kinematics of a source S of family KIND (its record for the
+// observation time) seen from point x, with g = geo_prepare_k<KIND, BRACKET,
+// PHASE64>(record of any time of this source, x).  FULL: FP64 tolerance (square
+// roots to about one ulp); otherwise the mixed path's relaxed tolerance.
+// CORR (FULL only): the correction solves first, their fallback on a rebuilt
+// geometry (g needs no bracket); without it the safeguarded Halley solvers on g
+// directly (g with its bracket; fewer live registers, for kernels whose occupancy
+// the correction solve would cost).  The mixed path (FULL = false) always takes
+// the correction solves, with PHASE64 = false allowed.
 template <bool FULL, bool CORR, int KIND>
 __device__ __forceinline__ void retarded_kind(const SrcRec &S, const Geo &g, const double x[3], int max_iter,
                                               double tol_rel, Kin &k)
 {
     if constexpr (KIND == K_CIRCULAR || KIND == K_LINEAR_OSC) {
-        if (FULL) {
-            if (!CORR || !solve_u_full<KIND>(S, g, k)) {
-                if constexpr (KIND == K_CIRCULAR) solve_circular<FULL>(S, g, max_iter, tol_rel, k);
-                else solve_linear<FULL>(S, g, max_iter, tol_rel, k);
-            }
+        if (FULL && !CORR) {
+            if constexpr (KIND == K_CIRCULAR) solve_circular<true>(S, g, max_iter, tol_rel, k);
+            else solve_linear<true>(S, g, max_iter, tol_rel, k);
+        } else if (FULL) {
+            if (!solve_u_full<KIND>(S, g, k)) retarded_fallback<true, KIND>(S, x, max_iter, tol_rel, k);
         } else if (!solve_u_mixed<KIND>(S, g, k)) {
-            retarded_fallback_mixed<KIND>(S, x, max_iter, tol_rel, k);
+            retarded_fallback<false, KIND>(S, x, max_iter, tol_rel, k);
             k.iters |= ITER_FALLBACK;
         }
     } else if constexpr (KIND == K_ACCEL) {
@@ -978,27 +969,6 @@ __device__ __forceinline__ void retarded_kind(const SrcRec &S, const Geo &g, con
         k.flags = 0u;
         k.iters = 0;
     }
-}
-
-template <bool FULL, bool CORR = true>
-__device__ __forceinline__ void retarded_geo(const SrcRec &S, const Geo &g, const double x[3], int max_iter,
-                                             double tol_rel, Kin &k)
-{
-    switch (S.kind) {
-    case K_CIRCULAR: retarded_kind<FULL, CORR, K_CIRCULAR>(S, g, x, max_iter, tol_rel, k); break;
-    case K_LINEAR_OSC: retarded_kind<FULL, CORR, K_LINEAR_OSC>(S, g, x, max_iter, tol_rel, k); break;
-    case K_ACCEL: retarded_kind<FULL, CORR, K_ACCEL>(S, g, x, max_iter, tol_rel, k); break;
-    case K_UNIFORM_VELOCITY: retarded_kind<FULL, CORR, K_UNIFORM_VELOCITY>(S, g, x, max_iter, tol_rel, k); break;
-    default: retarded_kind<FULL, CORR, K_STATIONARY>(S, g, x, max_iter, tol_rel, k); break;
-    }
-}
-
-template <bool FULL, bool CORR = true>
-__device__ __forceinline__ void retarded(const SrcRec &S, const double x[3], int max_iter, double tol_rel, Kin &k)
-{
-    Geo g;
-    geo_prepare(S, x, g);
-    retarded_geo<FULL, CORR>(S, g, x, max_iter, tol_rel, k);
 }
 
 template <typename F> __device__ __forceinline__ F recip(F x);

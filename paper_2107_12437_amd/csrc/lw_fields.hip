@@ -119,7 +119,9 @@ __device__ __forceinline__ void charge_times(double *lsum, const SrcRec *__restr
                                              uint32_t (&fl)[TCH], unsigned int *s_hist)
 {
     Geo g;
-    geo_prepare_k<KIND, sizeof(F) == 8>(R0[c], x, g);
+    // no bracket (the correction solves' fallback builds its own); the mixed path
+    // also takes its start phase to about 1e-11
+    geo_prepare_k<KIND, false, sizeof(F) == 8>(R0[c], x, g);
 #pragma unroll
     for (int j = 0; j < TCH; ++j) {
         if (j == 0 || j < nti) {
