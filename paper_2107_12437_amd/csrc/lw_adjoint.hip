@@ -70,10 +70,10 @@ __device__ __forceinline__ void pair_param_grad(const SrcRec &S, const Kin &k, i
 
 // The contributions of one charge of family KIND at point x over nt_here times
 // (records Rc[ti * nch], cotangent rows cot[(ti * nrows + row) * npts + p]),
-// added into g[NP]: per time the retarded kinematics (the safeguarded solver:
-// the correction solve's registers would take this kernel from 3 to 2 waves per
-// SIMD, and so would keeping the time-independent geometry live across the
-// times) and their reverse.
+// added into g[NP]: per time the retarded kinematics (the FP64 correction
+// solves, their fallback on a rebuilt geometry, so the geometry here needs no
+// bracket) and their reverse.  The geometry is rebuilt per time: keeping it live
+// across the times would take this kernel from 3 to 2 waves per SIMD.
 template <int KIND, typename G>
 __device__ __forceinline__ void charge_grad(const SrcRec *__restrict__ Rc, int nch, int nt_here, const double x[3],
                                             int64_t p, int64_t npts, int nrows, const int row[10], int field_kind,
@@ -91,9 +91,9 @@ __device__ __forceinline__ void charge_grad(const SrcRec *__restrict__ Rc, int n
         }
         if (!fin) continue;
         Geo geo;
-        geo_prepare_k<KIND>(S, x, geo);
+        geo_prepare_k<KIND, false, true>(S, x, geo);
         Kin k;
-        retarded_kind<true, false, KIND>(S, geo, x, max_iter, tol_rel, k);
+        retarded_kind<true, true, KIND>(S, geo, x, max_iter, tol_rel, k);
         const double D2 = k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2];
         if (!(D2 >= mask_r * mask_r) || D2 == 0.0) continue;
         pair_param_grad(S, k, field_kind, ob, g);
