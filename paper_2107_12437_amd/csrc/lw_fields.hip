@@ -90,16 +90,15 @@ template <> __device__ __forceinline__ float qnan<float>() { return __builtin_na
 template <> __device__ __forceinline__ double qnan<double>() { return __builtin_nan(""); }
 
 // F: working precision of the field terms and of the outputs.  The sums over
-// charges are FP64 in both (an FP32 term converts exactly, and an FP64 add costs
-// one instruction, half of a compensated FP32 add).  Each lane owns one point
-// and TCH consecutive times: the charge loop is outermost, so the part of each
-// retarded-time problem that does not depend on time (frame coordinates,
-// bracket, starting value and its sincos) is built once per (point, charge) and
-// serves all TCH times, whose sums stay in registers.  More times per lane hold
-// more sums, so the register cap grows with TCH: 4 waves per SIMD (128 VGPRs)
-// at one time, 3 (168) at two and 2 (256) at four.  At two times the mixed form
-// compiles to 127 VGPRs and so runs 4 waves (a cap of 128 made the allocator
-// spill); the FP64 form takes 144.  The launch tuner picks among them.
+// charges are FP64 in both (an FP32 term converts exactly, and an FP64 add needs
+// no compensation term).  Each lane owns one point and TCH consecutive times: the
+// charge loop is outermost, so the part of each retarded-time problem that does
+// not depend on time (frame coordinates, starting value and its sincos) is built
+// once per (point, charge) and serves all TCH times.  The register cap: 4 waves
+// per SIMD (128 VGPRs) at one time, 3 (168) at two and 2 (256) at four, whose
+// sums stay in registers.  With their sums in LDS the one- and two-time forms
+// compile to 61-83 VGPRs; LDS then holds the two-time form at 4 waves per SIMD.
+// The launch tuner picks among them.
 constexpr int waves_for(bool fp64, int tch) { return tch == 1 ? 4 : (tch == 2 ? 3 : 2); }
 
 // Where the sums over charges live: in LDS for one and two times per lane (80 and
