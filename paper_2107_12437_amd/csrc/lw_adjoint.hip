@@ -13,7 +13,7 @@
 // evaluator) and s = Rb.v - vb.a - ab.j, the cotangent of the trajectory
 // position is rb = -Rb - s n / (c kappa), and the gradient of a parameter is
 // rb . r_theta + vb . v_theta + ab . a_theta.  Sums over points and times are
-// per-workgroup partials reduced in a fixed order (bitwise reproducible).
+// per-wave partials reduced in a fixed order (bitwise reproducible).
 #include <math.h>
 
 #include "lw_device.hpp"
@@ -23,6 +23,8 @@ namespace lw {
 
 // Parameter order of the gradient rows.
 enum { P_Q = 0, P_C0 = 1, P_AMP = 4, P_OMEGA = 5, P_PHASE = 6, P_ACCEL = 7, P_V = 8, NP = 11 };
+// Waves per workgroup of the VJP kernel (256 lanes): each writes its own partials.
+constexpr int WAVES = 4;
 
 // Gradient of one (point, time, charge) contribution, added into g[NP].
 __device__ __forceinline__ void pair_param_grad(const SrcRec &S, const Kin &k, int field_kind, const double ob[10],
@@ -107,7 +109,6 @@ __global__ __launch_bounds__(256) void fields_vjp_kernel(const SrcRec *__restric
                                                          int max_iter, double tol_rel, double mask_r,
                                                          const G *__restrict__ cot, double *__restrict__ partial)
 {
-    __shared__ double red[4][NP];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t p = (int64_t)blockIdx.x * 256 + tid;
     const bool live = p < npts;
@@ -160,17 +161,16 @@ __global__ __launch_bounds__(256) void fields_vjp_kernel(const SrcRec *__restric
                 break;
             }
         }
-        // workgroup sum in a fixed order: shuffle tree per wave, then the four waves
+        // the wave's sum by a shuffle tree (every lane ends with the totals), and
+        // lane j writes parameter j's: one partial per (wave, charge), no barrier
+        double mine = 0.0;
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
             double v = g[j];
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (lane == 0) red[wave][j] = v;
+            if (lane == j) mine = v;
         }
-        __syncthreads();
-        if (tid < NP)
-            partial[(blk * nch + c) * NP + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-        __syncthreads();
+        if (lane < NP) partial[((blk * WAVES + wave) * nch + c) * NP + lane] = mine;
     }
 }
 
@@ -197,7 +197,7 @@ int vjp_params() { return NP; }
 size_t vjp_partial_doubles(int64_t npts, int nt, int nch, int tchunk)
 {
     const int64_t gx = (npts + 255) / 256, gy = (nt + tchunk - 1) / tchunk;
-    return (size_t)(gx * gy) * (size_t)nch * NP;
+    return (size_t)(gx * gy * WAVES) * (size_t)nch * NP;
 }
 
 hipError_t launch_fields_vjp(const SrcRec *d_recs, int nch, const double *d_pts, int64_t npts, int nt,
@@ -216,7 +216,7 @@ hipError_t launch_fields_vjp(const SrcRec *d_recs, int nch, const double *d_pts,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nout = nch * NP;
-    const int64_t nblk = (int64_t)grid.x * grid.y;
+    const int64_t nblk = (int64_t)grid.x * grid.y * WAVES;      // partial rows, one per wave
     hipLaunchKernelGGL(vjp_reduce_kernel, dim3(nout), dim3(256), 0, s, d_partial, nblk, nout, d_grad);
     return hipGetLastError();
 }
