@@ -154,8 +154,8 @@ lw_status lw_fields(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, co
                     void *d_out, uint32_t *d_flags, void *stream);
 
 /* Largest scratch of lw_fields_noalloc, in bytes: the charges (144 bytes each), the
- * times (8 bytes each) and one 224-byte record per (time, charge), each part
- * rounded up to 256 bytes.  For example 64 times x 280 charges fit. */
+ * times (8 bytes each) and one 272-byte record per (time, charge), each part
+ * rounded up to 256 bytes.  For example 64 times x 238 charges fit. */
 #define LW_NOALLOC_SCRATCH_BYTES (4u << 20)
 
 /* lw_fields without any allocation, for callers that cannot allocate device or

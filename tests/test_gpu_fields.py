@@ -137,6 +137,44 @@ def test_many_charges_current_loops(precision, tol):
     assert_fields_close(got, ref, tol, f"loops {precision}")
 
 
+def _dipole_pairs(charges):
+    """Each linear and circular charge followed by its partner: the opposite charge on the
+    same orbit half a period later (an oscillating dipole), so that consecutive records
+    share kind, c0, e1, e2, amp and omega."""
+    keep = [i for i, k in enumerate(charges["kind"]) if k in (I.LINEAR_OSC, I.CIRCULAR)]
+    a = I.subset_charges(charges, keep)
+    b = {k: np.array(v, copy=True) for k, v in a.items()}
+    b["q"] = -b["q"]
+    b["phase"] = b["phase"] + np.pi
+    return {k: np.stack([np.asarray(a[k]), np.asarray(b[k])], axis=1).reshape((-1,) + np.asarray(a[k]).shape[1:])
+            for k in a}
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL_FP64), ("mixed", TOL_MIXED)])
+def test_charges_sharing_an_orbit(precision, tol):
+    """Dipoles as pairs of charges on one orbit (consecutive records with the same kind,
+    c0, e1, e2, amp and omega): against the oracle, and bit for bit against the
+    iteration-counting instance (one time per lane)."""
+    import torch
+    from paper_2107_12437_amd import lw
+    w = dict(I.workload_grid_mixed(grid_n=45, n_times=5))
+    w["charges"] = _dipole_pairs(w["charges"])
+    assert len(w["charges"]["kind"]) >= 8
+    ref, rflags = run_oracle(w)
+    ctx = lw.Context(0)
+    try:
+        pts = torch.tensor(w["points"], dtype=torch.float64, device="cuda")
+        out, fl = lw.fields(w["charges"], pts, w["times"], precision=precision, ctx=ctx)
+        out, fl = out.clone(), fl.clone()
+        assert_fields_close(out.double().cpu().numpy(), ref, tol, f"orbit runs {precision}")
+        assert np.array_equal(fl.cpu().numpy().astype(np.uint32), rflags)
+        lw.set_iteration_histogram(True, ctx=ctx)
+        out2, fl2 = lw.fields(w["charges"], pts, w["times"], precision=precision, ctx=ctx)
+        assert torch.equal(out2, out) and torch.equal(fl2, fl)
+    finally:
+        ctx.close()
+
+
 def test_masking_and_flags():
     w = I.workload_tiny_orbit()
     r, *_ = O.kinematics(w["charges"], 0, w["times"][0])
