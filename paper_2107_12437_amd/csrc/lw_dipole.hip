@@ -586,6 +586,99 @@ __device__ double dipole_drive_fp64(const Hist &H, const DipLds &Si, const DipLd
     return drive_scalar(L2, sD, sI, pij, Sj.cfp, kq, hp) + drive_scalar(L2, sD, sI, pij, Sj.cfm, -kq, hm);
 }
 
+// The segments charge_fixed starts from at both stage times of a step (those
+// of tau = L/c at base_h = n + 1/2 and base_f = n + 1), with the values
+// seg_load gives each, loaded without a branch.  The two start points differ
+// by half a step (rounding is monotonic, so by less than one), so the second
+// segment is the first or the next one, and three ring rows hold both.  Rows
+// are taken modulo the ring, so every load stays in bounds, also where a
+// segment lies past the newest stored step (a row this launch may be writing):
+// that segment is marked empty and its values are not used (charge_fixed goes
+// on to the extrapolation, as it would have).
+template <typename I>
+__device__ __forceinline__ void seg_stages(const Hist &H, int j, double d0, I nstep, double base_h, double base_f,
+                                           double L, SegT<I> &gh, SegT<I> &gf, uint32_t &err)
+{
+    const double sh = base_h - L * INV_C * H.inv_dt, sf = base_f - L * INV_C * H.inv_dt;
+    const I kh = sh < 0.0 ? -1 : (I)floor(sh);
+    const I kf = sf < 0.0 ? -1 : (I)floor(sf);
+    const I k = kh < 0 ? -1 : kh;
+    const double *p0 = H.ring + ((I)(k & H.mask) * H.n + j) * 3;
+    const double *p1 = H.ring + ((I)((k + 1) & H.mask) * H.n + j) * 3;
+    const double *p2 = H.ring + ((I)((k + 2) & H.mask) * H.n + j) * 3;
+    const double r0[3] = {p0[0], p0[1], p0[2]}, r1[3] = {p1[0], p1[1], p1[2]}, r2[3] = {p2[0], p2[1], p2[2]};
+    const bool preh = kh < 0, pref = kf < 0, next = kf != kh;
+    gh.k = preh ? -1 : kh;
+    gh.d0 = preh ? d0 : r0[0];
+    gh.v0 = preh ? 0.0 : r0[1];
+    gh.a0 = preh ? 0.0 : r0[2];
+    gh.d1 = preh ? d0 : r1[0];
+    gh.v1 = preh ? 0.0 : r1[1];
+    gh.a1 = preh ? 0.0 : r1[2];
+    gf.k = pref ? -1 : kf;
+    gf.d0 = pref ? d0 : (next ? r1[0] : r0[0]);
+    gf.v0 = pref ? 0.0 : (next ? r1[1] : r0[1]);
+    gf.a0 = pref ? 0.0 : (next ? r1[2] : r0[2]);
+    gf.d1 = pref ? d0 : (next ? r2[0] : r1[0]);
+    gf.v1 = pref ? 0.0 : (next ? r2[1] : r1[1]);
+    gf.a1 = pref ? 0.0 : (next ? r2[2] : r1[2]);
+    if ((!preh && kh + H.mask < nstep) || (!pref && kf + H.mask < nstep)) err |= ERR_HISTORY;
+    if (kh >= nstep) gh.k = seg_none<I>();
+    if (kf >= nstep) gf.k = seg_none<I>();
+}
+
+// Both stage times of a step (t_n + dt/2 and t_n + dt) for both charges of a
+// fixed source, with the operations of two dipole_drive_fp64 calls (so the
+// same results).  The history rows of both stages' first segments are loaded
+// together at the start, so the second stage does not wait on memory after the
+// first stage's solves: 176 against 184 us per step on 64 clusters of 12,530
+// dipoles, although the lane then holds 147 VGPRs (3 waves per SIMD, against 4
+// at 115).  Loading each stage's two rows separately (144 VGPRs) was slower,
+// 196 us, and so was solving all four charges before their fields, 179 us.
+__device__ __forceinline__ void dipole_drive_fp64_stages(const Hist &H, const DipLds &Si, const DipLds &Sj, int j,
+                                                         double kq, int64_t nstep, int max_iter, uint32_t &err,
+                                                         double &e_half, double &e_full)
+{
+    const double dx = Si.ox - Sj.ox, dy = Si.oy - Sj.oy, dz = Si.oz - Sj.oz;
+    const double L2 = dx * dx + dy * dy + dz * dz;
+    const double sD = dx * Sj.px + dy * Sj.py + dz * Sj.pz;     // Delta . p_j
+    const double sI = dx * Si.px + dy * Si.py + dz * Si.pz;     // Delta . p_i
+    const double pij = Si.px * Sj.px + Si.py * Sj.py + Si.pz * Sj.pz;
+    const double L = sqrt(L2);
+    const double base_h = (double)nstep + 0.5, base_f = (double)nstep + 1.0;
+    Seg gh, gf;
+    seg_stages(H, j, Sj.d0, nstep, base_h, base_f, L, gh, gf, err);
+    double hp[3], hm[3];
+    charge_fixed(H, j, Sj.d0, nstep, base_h, L2, L, sD, Sj.cfp, max_iter, gh, hp, err);
+    charge_fixed(H, j, Sj.d0, nstep, base_h, L2, L, sD, Sj.cfm, max_iter, gh, hm, err);
+    e_half = drive_scalar(L2, sD, sI, pij, Sj.cfp, kq, hp) + drive_scalar(L2, sD, sI, pij, Sj.cfm, -kq, hm);
+    charge_fixed(H, j, Sj.d0, nstep, base_f, L2, L, sD, Sj.cfp, max_iter, gf, hp, err);
+    charge_fixed(H, j, Sj.d0, nstep, base_f, L2, L, sD, Sj.cfm, max_iter, gf, hm, err);
+    e_full = drive_scalar(L2, sD, sI, pij, Sj.cfp, kq, hp) + drive_scalar(L2, sD, sI, pij, Sj.cfm, -kq, hm);
+}
+
+// The mixed drive of a fixed source at both stage times of a step, with the
+// operations of two dipole_drive_mixed calls and the segment loads of
+// dipole_drive_fp64_stages: 189 against 207 us per step on 64 clusters of
+// 12,530 dipoles, against a lane per (stage, source).
+__device__ __forceinline__ void dipole_drive_mixed_stages(const Hist &H, const DipLds &Si, const DipLds &Sj, int j,
+                                                          double kq, int64_t nstep, int max_iter, uint32_t &err,
+                                                          double &e_half, double &e_full)
+{
+    const double X[3] = {Si.ox, Si.oy, Si.oz};
+    const MixedGeo G = mixed_geo(X, Si, Sj);
+    const double base_h = (double)nstep + 0.5, base_f = (double)nstep + 1.0;
+    Seg gh, gf;
+    seg_stages(H, j, Sj.d0, nstep, base_h, base_f, G.L, gh, gf, err);
+    double hp[3], hm[3];
+    charge_fixed(H, j, Sj.d0, nstep, base_h, G.L2, G.L, G.sD, Sj.cfp, max_iter, gh, hp, err);
+    charge_fixed(H, j, Sj.d0, nstep, base_h, G.L2, G.L, G.sD, Sj.cfm, max_iter, gh, hm, err);
+    e_half = mixed_field(G, Sj.cfp, Sj.cfm, hp, hm, kq);
+    charge_fixed(H, j, Sj.d0, nstep, base_f, G.L2, G.L, G.sD, Sj.cfp, max_iter, gf, hp, err);
+    charge_fixed(H, j, Sj.d0, nstep, base_f, G.L2, G.L, G.sD, Sj.cfm, max_iter, gf, hm, err);
+    e_full = mixed_field(G, Sj.cfp, Sj.cfm, hp, hm, kq);
+}
+
 // Drive contribution of work unit w of source j: in FP64 one unit per charge
 // (w = 0: +q, 1: -q), in the mixed form one unit per source dipole.
 template <bool MOVING, bool MIXED>
@@ -1046,13 +1139,15 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
     const DipLds Si = dip_lds(dev[gi]);
     const int M = n - 1;                             // source dipoles per stage
     const int nth = init ? 1 : 2;
-    // FP64 lane layout.  A launch with many targets is throughput-bound: a lane
+    // Lane layout.  A launch with many targets is throughput-bound: a lane
     // takes one source for both stage times (the fewest instructions per drive).
     // A launch with few targets (`wide`: at most one workgroup per SIMD) is a
-    // latency chain, and the shortest chain that fits the block wins: one
-    // charge per lane (4 drives' worth of lanes per source), else one source per
-    // (stage, lane).
-    const int layout = MIXED ? 1 : (wide && 2 * nth * M <= BLOCK ? 2 : (wide && nth * M <= BLOCK ? 1 : 0));
+    // latency chain, and the shortest chain that fits the block wins: in FP64
+    // one charge per lane (4 drives' worth of lanes per source), else one source
+    // per (stage, lane); the mixed form always takes one source per (stage, lane)
+    // there.
+    const int layout = MIXED ? (wide ? 1 : 0)
+                             : (wide && 2 * nth * M <= BLOCK ? 2 : (wide && nth * M <= BLOCK ? 1 : 0));
     const int units = layout == 2 ? 2 * nth * M : (layout == 1 ? nth * M : M);
     // the target's own state (only this workgroup writes it, and only at its
     // end): when the last lane has no pair work it reads the state into LDS
@@ -1071,12 +1166,24 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
     }
     double acc0 = 0.0, acc1 = 0.0;                   // stage t_n + dt/2 (or t = 0), stage t_n + dt
     if (layout == 0) {
-        // FP64: a lane takes one source for both stage times, which share its
+        // a lane takes one source for both stage times, which share its
         // constants and separation (and often the history segment)
         for (int jj = tid; jj < M; jj += BLOCK) {
             const int j = jj < i ? jj : jj + 1;
             const DipLds Sj = soa_lds(soa, out.n_dip, (uint32_t)(i0 + j));
             const double qj = soa_get(soa, out.n_dip, SF_Q, (uint32_t)(i0 + j));
+            if constexpr (!MOVING) {
+                if (!init) {
+                    double eh, ef;
+                    if constexpr (MIXED)
+                        dipole_drive_mixed_stages(H, Si, Sj, j, qj * K_COUL, nstep, max_iter, err, eh, ef);
+                    else
+                        dipole_drive_fp64_stages(H, Si, Sj, j, qj * K_COUL, nstep, max_iter, err, eh, ef);
+                    acc0 += eh;
+                    acc1 += ef;
+                    continue;
+                }
+            }
             acc0 += source_drive<MOVING, MIXED>(H, Si, Sj, j, qj, nstep, init ? 0.0 : 0.5, max_iter, err);
             if (!init) acc1 += source_drive<MOVING, MIXED>(H, Si, Sj, j, qj, nstep, 1.0, max_iter, err);
         }
@@ -1094,9 +1201,7 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             if (th) acc1 += e; else acc0 += e;
         }
     } else {
-        // a lane per (stage, source): the mixed form always (its drive's larger
-        // state makes the merged form slower: 214 against 208 us per step on
-        // the 64-cluster workload), FP64 for few targets
+        // a lane per (stage, source), for few targets
         for (int m = tid; m < nth * M; m += BLOCK) {
             const int th = m >= M ? 1 : 0, jj = m - th * M;    // (nth <= 2 stages)
             const int j = jj < i ? jj : jj + 1;
