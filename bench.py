@@ -43,7 +43,7 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # sources and code-generation flags they were taken on; reported as null once
 # either changes.
 TRAFFIC_BYTES = 682.1e6
-TRAFFIC_SOURCES_SHA = "f63d7bf3c4268232"
+TRAFFIC_SOURCES_SHA = "19c8b5fb1a8e5d18"
 # Algorithmic FP64 work per charge-pair drive of the oscillator step (one source
 # charge seen by one target dipole at one stage time), counted from the method's
 # definition: the retarded time on the interpolated history (30 flops, one
@@ -143,12 +143,11 @@ def run_part(part: str, cluster_steps: int, precision: str, ckpt_every: int, adj
     elif part == "grid-vjp":
         dw = I.workload_detector()
         dpts = torch.tensor(dw["points"], dtype=torch.float64, device="cuda")
-        dout, _ = lw.fields(dw["charges"], dpts, dw["times"], precision="fp64")
-        cot = torch.zeros_like(dout)
-        cot[:, 4:7] = 2.0 * dout[:, 4:7] / len(dw["times"])
+        dout, _ = lw.fields(dw["charges"], dpts, dw["times"], precision="fp64", outputs=("E",))
+        cot = 2.0 * dout / len(dw["times"])
 
         def call(steps):
-            lw.fields_vjp(dw["charges"], dpts, dw["times"], cot)
+            lw.fields_vjp(dw["charges"], dpts, dw["times"], cot, outputs=("E",))
         call(0)
         steps = 0
     else:
@@ -506,20 +505,22 @@ def main():
                 f"{csec * 1e3:.1f} ms for {cw['steps']} steps, "
                 f"{clusters[prec]['dipole_steps_per_s']:.3e} dipole-steps/s")
         clusters["mixed_over_fp64"] = round(clusters["fp64"]["ms"] / clusters["mixed"]["ms"], 3)
+        # J = mean over snapshots of sum |E|^2 needs E alone: the forward and the VJP
+        # take the three E rows
         dw = I.workload_detector()
         dpts = torch.tensor(dw["points"], dtype=torch.float64, device="cuda")
-        dout, _ = lw.fields(dw["charges"], dpts, dw["times"], precision="fp64")
-        cot = torch.zeros_like(dout)
-        cot[:, 4:7] = 2.0 * dout[:, 4:7] / len(dw["times"])
-        lw.fields_vjp(dw["charges"], dpts, dw["times"], cot)
+        dout, _ = lw.fields(dw["charges"], dpts, dw["times"], precision="fp64", outputs=("E",))
+        cot = 2.0 * dout / len(dw["times"])
+        lw.fields_vjp(dw["charges"], dpts, dw["times"], cot, outputs=("E",))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(3):
-            lw.fields_vjp(dw["charges"], dpts, dw["times"], cot)
+            lw.fields_vjp(dw["charges"], dpts, dw["times"], cot, outputs=("E",))
         torch.cuda.synchronize()
         vsec = (time.perf_counter() - t0) / 3
         pairs = dpts.shape[1] * len(dw["charges"]["kind"]) * len(dw["times"])
-        vjp = {"workload": dw["name"], "ms": round(vsec * 1e3, 3), "pair_vjps_per_s": pairs / vsec, "dtype": "f64"}
+        vjp = {"workload": dw["name"], "ms": round(vsec * 1e3, 3), "pair_vjps_per_s": pairs / vsec, "dtype": "f64",
+               "outputs": "E"}
         log(f"[bench] grid VJP: {vsec * 1e3:.2f} ms, {vjp['pair_vjps_per_s']:.3e} pair VJPs/s")
         # oscillator adjoint: forward run, detector VJP, backward sweep; checkpointed every
         # 250 steps (segments recomputed) and with the whole history kept

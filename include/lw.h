@@ -191,6 +191,9 @@ lw_status lw_fields_noalloc(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_cha
  *           closer than the mask radius, contribute nothing
  *   d_grad  device FP64 [n_charges][11], overwritten
  * The forward quantities are recomputed in FP64 whatever the precision.
+ * With opts->outputs = LW_OUT_E (objectives of E alone, such as |E|^2) the
+ * kernel reads and reverses only E, which is faster; the gradient is the same
+ * bits as with all outputs and zero cotangents for Phi, A and B.
  * Sums run in a fixed order: the result is bitwise reproducible.  Asynchronous. */
 lw_status lw_fields_vjp(lw_ctx *ctx, const lw_traj *h_charges, int32_t n_charges, const double *d_pts,
                         int64_t n_pts, const double *h_times, int32_t n_times, const lw_opts *opts,

@@ -27,11 +27,13 @@ enum { P_Q = 0, P_C0 = 1, P_AMP = 4, P_OMEGA = 5, P_PHASE = 6, P_ACCEL = 7, P_V 
 constexpr int WAVES = 4;
 
 // Gradient of one (point, time, charge) contribution, added into g[NP].
+// EONLY: only E has a cotangent (lw_terms_vjp<true>).
+template <bool EONLY>
 __device__ __forceinline__ void pair_param_grad(const SrcRec &S, const Kin &k, int field_kind, const double ob[10],
                                                 double g[NP])
 {
     double Rb[3], vb[3], ab[3], n[3], kqb, kappa;
-    lw_terms_vjp(k, S.kq, field_kind, ob, Rb, vb, ab, kqb, n, kappa);
+    lw_terms_vjp<EONLY>(k, S.kq, field_kind, ob, Rb, vb, ab, kqb, n, kappa);
     // jerk at t': -omega^2 v for the harmonic families, 0 otherwise
     const bool harm = (S.kind == K_CIRCULAR || S.kind == K_LINEAR_OSC);
     const double w2 = harm ? S.omega * S.omega : 0.0;
@@ -75,8 +77,9 @@ __device__ __forceinline__ void pair_param_grad(const SrcRec &S, const Kin &k, i
 // added into g[NP]: per time the retarded kinematics (the FP64 correction
 // solves, their fallback on a rebuilt geometry, so the geometry here needs no
 // bracket) and their reverse.  The geometry is rebuilt per time: keeping it live
-// across the times would take this kernel from 3 to 2 waves per SIMD.
-template <int KIND, typename G>
+// across the times would take this kernel from 3 to 2 waves per SIMD.  EONLY:
+// the cotangent holds the three E rows alone (outputs E), which are all it reads.
+template <int KIND, bool EONLY, typename G>
 __device__ __forceinline__ void charge_grad(const SrcRec *__restrict__ Rc, int nch, int nt_here, const double x[3],
                                             int64_t p, int64_t npts, int nrows, const int row[10], int field_kind,
                                             int max_iter, double tol_rel, double mask_r, const G *__restrict__ cot,
@@ -88,7 +91,11 @@ __device__ __forceinline__ void charge_grad(const SrcRec *__restrict__ Rc, int n
         bool fin = true;
 #pragma unroll
         for (int j = 0; j < 10; ++j) {
-            ob[j] = row[j] >= 0 ? (double)cot[((int64_t)ti * nrows + row[j]) * npts + p] : 0.0;
+            if (EONLY) {
+                ob[j] = (j >= 4 && j < 7) ? (double)cot[((int64_t)ti * 3 + (j - 4)) * npts + p] : 0.0;
+            } else {
+                ob[j] = row[j] >= 0 ? (double)cot[((int64_t)ti * nrows + row[j]) * npts + p] : 0.0;
+            }
             fin = fin && isfinite(ob[j]);
         }
         if (!fin) continue;
@@ -98,11 +105,11 @@ __device__ __forceinline__ void charge_grad(const SrcRec *__restrict__ Rc, int n
         retarded_kind<true, true, KIND>(S, geo, x, max_iter, tol_rel, k);
         const double D2 = k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2];
         if (!(D2 >= mask_r * mask_r) || D2 == 0.0) continue;
-        pair_param_grad(S, k, field_kind, ob, g);
+        pair_param_grad<EONLY>(S, k, field_kind, ob, g);
     }
 }
 
-template <typename G>
+template <typename G, bool EONLY>
 __global__ __launch_bounds__(256) void fields_vjp_kernel(const SrcRec *__restrict__ recs, int nch,
                                                          const double *__restrict__ pts, int64_t npts, int nt,
                                                          int tchunk, int field_kind, int outputs, int nrows,
@@ -140,23 +147,23 @@ __global__ __launch_bounds__(256) void fields_vjp_kernel(const SrcRec *__restric
             const SrcRec *Rc = recs + (int64_t)t0 * nch + c;
             switch (Rc->kind) {
             case K_CIRCULAR:
-                charge_grad<K_CIRCULAR>(Rc, nch, t1 - t0, x, p, npts, nrows, row, field_kind, max_iter, tol_rel,
+                charge_grad<K_CIRCULAR, EONLY>(Rc, nch, t1 - t0, x, p, npts, nrows, row, field_kind, max_iter, tol_rel,
                                         mask_r, cot + (int64_t)t0 * nrows * npts, g);
                 break;
             case K_LINEAR_OSC:
-                charge_grad<K_LINEAR_OSC>(Rc, nch, t1 - t0, x, p, npts, nrows, row, field_kind, max_iter, tol_rel,
+                charge_grad<K_LINEAR_OSC, EONLY>(Rc, nch, t1 - t0, x, p, npts, nrows, row, field_kind, max_iter, tol_rel,
                                           mask_r, cot + (int64_t)t0 * nrows * npts, g);
                 break;
             case K_ACCEL:
-                charge_grad<K_ACCEL>(Rc, nch, t1 - t0, x, p, npts, nrows, row, field_kind, max_iter, tol_rel,
+                charge_grad<K_ACCEL, EONLY>(Rc, nch, t1 - t0, x, p, npts, nrows, row, field_kind, max_iter, tol_rel,
                                      mask_r, cot + (int64_t)t0 * nrows * npts, g);
                 break;
             case K_UNIFORM_VELOCITY:
-                charge_grad<K_UNIFORM_VELOCITY>(Rc, nch, t1 - t0, x, p, npts, nrows, row, field_kind, max_iter,
+                charge_grad<K_UNIFORM_VELOCITY, EONLY>(Rc, nch, t1 - t0, x, p, npts, nrows, row, field_kind, max_iter,
                                                 tol_rel, mask_r, cot + (int64_t)t0 * nrows * npts, g);
                 break;
             default:
-                charge_grad<K_STATIONARY>(Rc, nch, t1 - t0, x, p, npts, nrows, row, field_kind, max_iter, tol_rel,
+                charge_grad<K_STATIONARY, EONLY>(Rc, nch, t1 - t0, x, p, npts, nrows, row, field_kind, max_iter, tol_rel,
                                           mask_r, cot + (int64_t)t0 * nrows * npts, g);
                 break;
             }
@@ -207,12 +214,28 @@ hipError_t launch_fields_vjp(const SrcRec *d_recs, int nch, const double *d_pts,
     const dim3 grid((unsigned)((npts + 255) / 256), (unsigned)((nt + tchunk - 1) / tchunk));
     const int max_iter = o.max_iter > 0 ? o.max_iter : 100;
     const int om = output_mask(o.outputs), nrows = output_rows(o.outputs);
-    if (o.precision == LW_MIXED)
-        hipLaunchKernelGGL(fields_vjp_kernel<float>, grid, dim3(256), 0, s, d_recs, nch, d_pts, npts, nt, tchunk,
-                           o.field_kind, om, nrows, max_iter, tol_rel, mask_r, (const float *)d_cot, d_partial);
-    else
-        hipLaunchKernelGGL(fields_vjp_kernel<double>, grid, dim3(256), 0, s, d_recs, nch, d_pts, npts, nt, tchunk,
-                           o.field_kind, om, nrows, max_iter, tol_rel, mask_r, (const double *)d_cot, d_partial);
+    // a cotangent of E alone (objectives of |E|^2) takes the kernel that reads
+    // and reverses only E
+    const bool eonly = om == OUT_E;
+    if (o.precision == LW_MIXED) {
+        if (eonly)
+            hipLaunchKernelGGL((fields_vjp_kernel<float, true>), grid, dim3(256), 0, s, d_recs, nch, d_pts, npts, nt,
+                               tchunk, o.field_kind, om, nrows, max_iter, tol_rel, mask_r, (const float *)d_cot,
+                               d_partial);
+        else
+            hipLaunchKernelGGL((fields_vjp_kernel<float, false>), grid, dim3(256), 0, s, d_recs, nch, d_pts, npts,
+                               nt, tchunk, o.field_kind, om, nrows, max_iter, tol_rel, mask_r, (const float *)d_cot,
+                               d_partial);
+    } else {
+        if (eonly)
+            hipLaunchKernelGGL((fields_vjp_kernel<double, true>), grid, dim3(256), 0, s, d_recs, nch, d_pts, npts,
+                               nt, tchunk, o.field_kind, om, nrows, max_iter, tol_rel, mask_r, (const double *)d_cot,
+                               d_partial);
+        else
+            hipLaunchKernelGGL((fields_vjp_kernel<double, false>), grid, dim3(256), 0, s, d_recs, nch, d_pts, npts,
+                               nt, tchunk, o.field_kind, om, nrows, max_iter, tol_rel, mask_r, (const double *)d_cot,
+                               d_partial);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nout = nch * NP;

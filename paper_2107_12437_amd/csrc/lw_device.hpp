@@ -1062,7 +1062,11 @@ __device__ __forceinline__ F lw_terms(const Kin &k, F kq, int field_kind, F out[
 }
 
 // Reverse of lw_terms<double>: given the cotangent ob of (Phi, A, E, B), the
-// cotangents of R, v, a and of kq = q / (4 pi eps0).
+// cotangents of R, v, a and of kq = q / (4 pi eps0).  EONLY: only E has a
+// cotangent (ob[4..6]; the other entries are not read), as for objectives of
+// |E|^2.  The reverses of Phi, A and B are then left out, which gives the
+// values of the general form with zero cotangents there (it adds only zeros).
+template <bool EONLY = false>
 __device__ __forceinline__ void lw_terms_vjp(const Kin &k, double kq, int field_kind, const double ob[10],
                                              double Rb[3], double vb[3], double ab[3], double &kqb, double n[3],
                                              double &kappa_out)
@@ -1096,21 +1100,24 @@ __device__ __forceinline__ void lw_terms_vjp(const Kin &k, double kq, int field_
     }
     const double pc = phi * ic;
     // ---- reverse ----
-    const double Phib = ob[0];
-    const double Ab[3] = {ob[1], ob[2], ob[3]};
     const double Eb[3] = {ob[4], ob[5], ob[6]};
-    const double Bb[3] = {ob[7], ob[8], ob[9]};
-    // B = m x E
-    double mb[3], Et[3];
-    mb[0] = E[1] * Bb[2] - E[2] * Bb[1];
-    mb[1] = E[2] * Bb[0] - E[0] * Bb[2];
-    mb[2] = E[0] * Bb[1] - E[1] * Bb[0];
-    Et[0] = Eb[0] + (Bb[1] * m[2] - Bb[2] * m[1]);
-    Et[1] = Eb[1] + (Bb[2] * m[0] - Bb[0] * m[2]);
-    Et[2] = Eb[2] + (Bb[0] * m[1] - Bb[1] * m[0]);
-    // A = pc b
-    const double pcb = Ab[0] * b[0] + Ab[1] * b[1] + Ab[2] * b[2];
-    double bbar[3] = {pc * Ab[0], pc * Ab[1], pc * Ab[2]};
+    double mb[3] = {0.0, 0.0, 0.0}, Et[3] = {Eb[0], Eb[1], Eb[2]};
+    double Phib = 0.0, pcb = 0.0, bbar[3] = {0.0, 0.0, 0.0};
+    if constexpr (!EONLY) {
+        Phib = ob[0];
+        const double Ab[3] = {ob[1], ob[2], ob[3]};
+        const double Bb[3] = {ob[7], ob[8], ob[9]};
+        // B = m x E
+        mb[0] = E[1] * Bb[2] - E[2] * Bb[1];
+        mb[1] = E[2] * Bb[0] - E[0] * Bb[2];
+        mb[2] = E[0] * Bb[1] - E[1] * Bb[0];
+        Et[0] = Eb[0] + (Bb[1] * m[2] - Bb[2] * m[1]);
+        Et[1] = Eb[1] + (Bb[2] * m[0] - Bb[0] * m[2]);
+        Et[2] = Eb[2] + (Bb[0] * m[1] - Bb[1] * m[0]);
+        // A = pc b
+        pcb = Ab[0] * b[0] + Ab[1] * b[1] + Ab[2] * b[2];
+        for (int i = 0; i < 3; ++i) bbar[i] = pc * Ab[i];
+    }
     // E = f W, W = u cu - d cd
     const double fb = Et[0] * W[0] + Et[1] * W[1] + Et[2] * W[2];
     double ub[3], dbar[3];
@@ -1123,7 +1130,7 @@ __device__ __forceinline__ void lw_terms_vjp(const Kin &k, double kq, int field_
         cdb -= Wb * d[i];
     }
     // phi = kqD ik feeds Phi, pc and f
-    const double phib = Phib + pcb * ic + fb * ik * ik;
+    const double phib = EONLY ? fb * ik * ik : Phib + pcb * ic + fb * ik * ik;
     const double ikb_f = fb * 2.0 * phi * ik;
     double ikb = ikb_f + phib * kqD;
     const double kqDb = phib * ik;
@@ -1133,7 +1140,9 @@ __device__ __forceinline__ void lw_terms_vjp(const Kin &k, double kq, int field_
     const double ndb = rad ? cub * ic : 0.0;
     double kappab = rad ? cdb * ic : 0.0;
     // m = n / c
-    double nbar[3] = {mb[0] * ic, mb[1] * ic, mb[2] * ic};
+    double nbar[3] = {0.0, 0.0, 0.0};
+    if constexpr (!EONLY)
+        for (int i = 0; i < 3; ++i) nbar[i] = mb[i] * ic;
     // kqD = kq iD
     iDb += kqDb * kq;
     kqb = kqDb * iD;

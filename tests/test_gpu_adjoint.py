@@ -112,6 +112,34 @@ def test_vjp_linear_functional_all_outputs_all_families():
 
 
 @pytest.mark.parametrize("cot_dtype", ["float64", "float32"])
+def test_e_only_cotangent_equals_all_rows(cot_dtype):
+    """A cotangent of E alone (outputs ("E",)) takes the kernel instance that reads and
+    reverses only E. Its gradient must equal, bit for bit, that of the ten-row cotangent
+    with zero Phi, A and B rows, which the general reverse only adds as zeros. The case
+    covers all five families, 289 points (a ragged last workgroup) and 5 times (a ragged
+    last time chunk)."""
+    import torch
+    from paper_2107_12437_amd import lw
+    st = I.empty_charges(1)
+    st["kind"][0] = I.STATIONARY
+    st["q"][0] = I.E_CHARGE
+    st["c0"][0] = [-4e-9, 2e-9, 3e-9]
+    ch = I.concat_charges([mixed_families(), st])
+    pts = I.plane_grid(30e-9, 17, z=25e-9)
+    times = np.array([0.2e-15, 0.35e-15, 0.6e-15, 0.75e-15, 0.9e-15])
+    dt = torch.float64 if cot_dtype == "float64" else torch.float32
+    rng = np.random.default_rng(5)
+    cot_e = torch.tensor(rng.normal(size=(len(times), 3, pts.shape[1])), dtype=dt, device="cuda")
+    cot_all = torch.zeros((len(times), 10, pts.shape[1]), dtype=dt, device="cuda")
+    cot_all[:, 4:7] = cot_e
+    dpts = torch.tensor(pts, dtype=torch.float64, device="cuda")
+    g_e = lw.fields_vjp(ch, dpts, times, cot_e, outputs=("E",)).cpu().numpy()
+    g_all = lw.fields_vjp(ch, dpts, times, cot_all).cpu().numpy()
+    assert np.abs(g_all).max() > 0
+    assert np.array_equal(g_e, g_all), np.abs(g_e - g_all).max() / np.abs(g_all).max()
+
+
+@pytest.mark.parametrize("cot_dtype", ["float64", "float32"])
 def test_detector_objective_gradient(cot_dtype):
     """J = (1/n_t) sum |E|^2 on a 16x16 detector at z = 200 nm, 4 snapshots, 64 circular
     charges: gradient with respect to (R, omega, phase) of 8 seeded charges; the
