@@ -1212,6 +1212,30 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             if (th) acc1 += e; else acc0 += e;
         }
     }
+    // lane 0 reads the target's constants here, and its state too without the
+    // early read, so that the loads are in flight during the block sums (read
+    // after the barrier they added one memory round trip to every workgroup)
+    double st[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double om = 0.0, gm = 0.0, fq = 0.0, dd0 = 0.0, eh = 0.0, ms = 0.0, vf = 0.0;
+    if (tid == 0) {
+        const DipDev &D = dev[gi];
+        om = D.omega0;
+        gm = D.gamma0;
+        fq = D.f;
+        dd0 = D.d0;
+        eh = D.ehalf;
+        ms = D.mspeed;
+        vf = D.vfac;
+        if (!init && !early) {
+            const double *h = rp + ((int64_t)(nstep & (ring_depth - 1)) * n + i) * 3;
+            st[0] = h[0];
+            st[1] = h[1];
+            st[2] = h[2];
+            st[3] = Ecur[gi];
+            st[4] = W[2 * gi];
+            st[5] = W[2 * gi + 1];
+        }
+    }
     // block sums in a fixed order: within each wave, then over the waves
     for (int o = 32; o > 0; o >>= 1) {
         acc0 += __shfl_xor(acc0, o, 64);
@@ -1228,19 +1252,18 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             s0 += red[0][v];
             s1 += red[1][v];
         }
-        const DipDev &D = dev[gi];
-        const double w2 = D.omega0 * D.omega0, g = D.gamma0, f = D.f;
+        const double w2 = om * om, g = gm, f = fq;
         if (init) {
             // t = 0: drive from the static pre-history, sample 0 = (d0, 0, d_ddot(0))
             const double E0 = s0;
             double *h = rp + (int64_t)i * 3;
-            h[0] = D.d0;
+            h[0] = dd0;
             h[1] = 0.0;
-            h[2] = f * E0 - w2 * D.d0;
+            h[2] = f * E0 - w2 * dd0;
             Ecur[gi] = E0;
             W[2 * gi] = 0.0;
             W[2 * gi + 1] = 0.0;
-            put_row(out, 0, gi, D.d0, 0.0, run_energy(w2, D.ehalf, D.d0, 0.0), E0, 0.0, 0.0);
+            put_row(out, 0, gi, dd0, 0.0, run_energy(w2, eh, dd0, 0.0), E0, 0.0, 0.0);
         } else {
             const double Em = s0, Ee = s1;
             double y0, y1, a0, Ec, W0, W1;
@@ -1252,13 +1275,12 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
                 W0 = own[4];
                 W1 = own[5];
             } else {
-                const double *h = rp + ((int64_t)(nstep & (ring_depth - 1)) * n + i) * 3;
-                y0 = h[0];
-                y1 = h[1];
-                a0 = h[2];
-                Ec = Ecur[gi];
-                W0 = W[2 * gi];
-                W1 = W[2 * gi + 1];
+                y0 = st[0];
+                y1 = st[1];
+                a0 = st[2];
+                Ec = st[3];
+                W0 = st[4];
+                W1 = st[5];
             }
             const double k1d = y1, k1v = f * Ec - g * y1 - w2 * y0;
             const double y0b = y0 + 0.5 * dt * k1d, y1b = y1 + 0.5 * dt * k1v;
@@ -1276,7 +1298,7 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             hn[2] = an;
             Ecur[gi] = Ee;
             if (!(isfinite(dn) && isfinite(vn) && isfinite(an))) err |= ERR_NONFINITE;
-            if (max_vel > 0.0 && D.mspeed + D.vfac * fabs(vn) > max_vel) err |= ERR_VELOCITY;
+            if (max_vel > 0.0 && ms + vf * fabs(vn) > max_vel) err |= ERR_VELOCITY;
             // energy bookkeeping (Sec. 2.5), trapezoid rule over the step
             const double wa = W0 + 0.5 * dt * (y1 * Ec + vn * Ee);
             const double wr = W1 + 0.5 * dt * K_LARMOR * (a0 * a0 + an * an);
@@ -1284,7 +1306,7 @@ __global__ __launch_bounds__(BLOCK) void lo_step_kernel(const DipDev *__restrict
             W[2 * gi + 1] = wr;
             const int64_t rel = nstep + 1 - step_ctr[1];       // steps since the run's first
             const int64_t row = out_row(rel, out.stride);
-            if (row >= 0) put_row(out, row, gi, dn, vn, run_energy(w2, D.ehalf, dn, vn), Ee, wa, wr);
+            if (row >= 0) put_row(out, row, gi, dn, vn, run_energy(w2, eh, dn, vn), Ee, wa, wr);
         }
     }
     if (err) atomicOr(d_err, err);
