@@ -98,13 +98,14 @@ __device__ __forceinline__ void charge_grad(const SrcRec *__restrict__ Rc, int n
             }
             fin = fin && isfinite(ob[j]);
         }
-        if (!fin) continue;
+        // the cotangent is tested after the solve, which does not depend on it,
+        // so that its loads are in flight during the solve
         Geo geo;
         geo_prepare_k<KIND, false, true>(S, x, geo);
         Kin k;
         retarded_kind<true, true, KIND>(S, geo, x, max_iter, tol_rel, k);
         const double D2 = k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2];
-        if (!(D2 >= mask_r * mask_r) || D2 == 0.0) continue;
+        if (!fin || !(D2 >= mask_r * mask_r) || D2 == 0.0) continue;
         pair_param_grad<EONLY>(S, k, field_kind, ob, g);
     }
 }
