@@ -43,7 +43,7 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # sources and code-generation flags they were taken on; reported as null once
 # either changes.
 TRAFFIC_BYTES = 682.1e6
-TRAFFIC_SOURCES_SHA = "19c8b5fb1a8e5d18"
+TRAFFIC_SOURCES_SHA = "743b9fce60fa5dfc"
 # Algorithmic FP64 work per charge-pair drive of the oscillator step (one source
 # charge seen by one target dipole at one stage time), counted from the method's
 # definition: the retarded time on the interpolated history (30 flops, one

@@ -34,7 +34,7 @@ struct alignas(16) SrcRec {
     double e1[3];
     double e2[3];
     double e3[3];     // e1 x e2
-    double amp, omega;
+    double amp, omega;  // uniform velocity: c^2 - |v|^2 and its reciprocal (rcp_steer)
     double cT, sT;    // cos, sin of Theta = omega t + phase
     double accel;
     double Lmax;      // accel: distance travelled along e1 by time t
@@ -43,7 +43,7 @@ struct alignas(16) SrcRec {
     // FP32 coefficients of beta and beta_dot (mixed path) in the orbit frame:
     // circular  beta = -s bw1 + c bw2,  beta_dot = -(c aw1 + s aw2);
     // linear    beta = -s bw1,          beta_dot = -c aw1;
-    // bw = amp omega / c * e, aw = amp omega^2 / c * e
+    // bw = amp omega / c * e, aw = amp omega^2 / c * e; uniform velocity: bw1 = beta
     float bw1[3], bw2[3], aw1[3], aw2[3];
 };
 
@@ -552,22 +552,23 @@ __device__ __forceinline__ void solve_accel(const SrcRec &S, const Geo &g, int m
 // FULL: correctly rounded square root and division; otherwise (the mixed path,
 // whose field is FP32) the refined v_rsq_f64 root and v_rcp_f64 reciprocal,
 // within a few ulp, which is all the mixed tolerance needs.
+// The record holds den = c^2 - |v|^2 (amp) and its reciprocal (omega), which
+// do not depend on the point.
 template <bool FULL>
 __device__ __forceinline__ void solve_uniform(const SrcRec &S, const double x[3], Kin &k)
 {
     double wt[3];
     for (int i = 0; i < 3; ++i) wt[i] = x[i] - S.rt[i];
-    const double vv = S.v[0] * S.v[0] + S.v[1] * S.v[1] + S.v[2] * S.v[2];
     const double wv = wt[0] * S.v[0] + wt[1] * S.v[1] + wt[2] * S.v[2];
     const double ww = wt[0] * wt[0] + wt[1] * wt[1] + wt[2] * wt[2];
-    const double den = C_LIGHT * C_LIGHT - vv;
+    const double den = S.amp;
     const double disc = wv * wv + den * ww;
     double sq, isq;
     if (FULL) sq = sqrt(disc);
     else root_rsqrt<false>(fmax(disc, 1e-300), sq, isq);
     // the two algebraically equal forms, chosen to avoid cancellation
     const double tau = FULL ? ((wv >= 0.0) ? (wv + sq) / den : ww / (sq - wv))
-                            : ((wv >= 0.0) ? (wv + sq) * rcp_steer(den) : ww * rcp_steer(sq - wv));
+                            : ((wv >= 0.0) ? (wv + sq) * S.omega : ww * rcp_steer(sq - wv));
     k.tp = S.t - tau;
     k.cph = 1.0;
     k.sph = 0.0;
@@ -960,7 +961,11 @@ __device__ __forceinline__ void retarded_kind(const SrcRec &S, const Geo &g, con
         }
     } else if constexpr (KIND == K_UNIFORM_VELOCITY) {
         solve_uniform<FULL>(S, x, k);
-        if (!FULL) kin_beta_from_va(k);
+        if (!FULL)
+            for (int i = 0; i < 3; ++i) {     // kin_beta_from_va's values, from the record
+                k.bf[i] = S.bw1[i];
+                k.df[i] = 0.f;
+            }
     } else {
         for (int i = 0; i < 3; ++i) { k.R[i] = g.w[i]; k.v[i] = 0.0; k.a[i] = 0.0; k.bf[i] = 0.f; k.df[i] = 0.f; }
         k.tp = S.t - sqrt(g.w[0] * g.w[0] + g.w[1] * g.w[1] + g.w[2] * g.w[2]) * INV_C;

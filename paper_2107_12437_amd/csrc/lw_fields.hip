@@ -79,6 +79,14 @@ __global__ void prep_kernel(const lw_traj *__restrict__ ch, int nch, const doubl
             R.aw1[i] = (float)(aw * T.e1[i]);
             R.aw2[i] = (float)(aw * T.e2[i]);
         }
+        if (T.kind == K_UNIFORM_VELOCITY) {
+            // the closed form's constants (solve_uniform) and beta in FP32, once
+            // per record instead of once per point
+            const double vv = T.v[0] * T.v[0] + T.v[1] * T.v[1] + T.v[2] * T.v[2];
+            R.amp = C_LIGHT * C_LIGHT - vv;
+            R.omega = rcp_steer(R.amp);
+            for (int i = 0; i < 3; ++i) R.bw1[i] = (float)(T.v[i] * INV_C);
+        }
         recs[r] = R;
     }
     if (flags)
