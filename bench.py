@@ -43,7 +43,7 @@ PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # sources and code-generation flags they were taken on; reported as null once
 # either changes.
 TRAFFIC_BYTES = 682.1e6
-TRAFFIC_SOURCES_SHA = "743b9fce60fa5dfc"
+TRAFFIC_SOURCES_SHA = "a857de27d0f7cbc7"
 # Algorithmic FP64 work per charge-pair drive of the oscillator step (one source
 # charge seen by one target dipole at one stage time), counted from the method's
 # definition: the retarded time on the interpolated history (30 flops, one

@@ -33,13 +33,13 @@ __device__ __forceinline__ void pair_param_grad(const SrcRec &S, const Kin &k, i
                                                 double g[NP])
 {
     double Rb[3], vb[3], ab[3], n[3], kqb, kappa;
-    lw_terms_vjp<EONLY>(k, S.kq, field_kind, ob, Rb, vb, ab, kqb, n, kappa);
+    lw_terms_vjp<EONLY, true>(k, S.kq, field_kind, ob, Rb, vb, ab, kqb, n, kappa);
     // jerk at t': -omega^2 v for the harmonic families, 0 otherwise
     const bool harm = (S.kind == K_CIRCULAR || S.kind == K_LINEAR_OSC);
     const double w2 = harm ? S.omega * S.omega : 0.0;
     double sres = 0.0;
     for (int i = 0; i < 3; ++i) sres += Rb[i] * k.v[i] - vb[i] * k.a[i] + ab[i] * w2 * k.v[i];
-    const double fac = sres / (C_LIGHT - (n[0] * k.v[0] + n[1] * k.v[1] + n[2] * k.v[2]));
+    const double fac = sres * recip<double>(C_LIGHT - (n[0] * k.v[0] + n[1] * k.v[1] + n[2] * k.v[2]));
     double rb[3];
     for (int i = 0; i < 3; ++i) rb[i] = -Rb[i] - fac * n[i];
     g[P_Q] += kqb * K_COUL;

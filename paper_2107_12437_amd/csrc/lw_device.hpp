@@ -1071,14 +1071,22 @@ __device__ __forceinline__ F lw_terms(const Kin &k, F kq, int field_kind, F out[
 // cotangent (ob[4..6]; the other entries are not read), as for objectives of
 // |E|^2.  The reverses of Phi, A and B are then left out, which gives the
 // values of the general form with zero cotangents there (it adds only zeros).
-template <bool EONLY = false>
+// FAST: 1/|R| and 1/kappa from the refined hardware reciprocal square root and
+// reciprocal (within an ulp or two) instead of the correctly rounded square
+// root and divisions, as the forward FP64 evaluator takes them.
+template <bool EONLY = false, bool FAST = false>
 __device__ __forceinline__ void lw_terms_vjp(const Kin &k, double kq, int field_kind, const double ob[10],
                                              double Rb[3], double vb[3], double ab[3], double &kqb, double n[3],
                                              double &kappa_out)
 {
     const double ic = INV_C;
-    const double D = sqrt(k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2]);
-    const double iD = 1.0 / D;
+    double D, iD;
+    if constexpr (FAST) {
+        dist_inv(k.R[0], k.R[1], k.R[2], D, iD);
+    } else {
+        D = sqrt(k.R[0] * k.R[0] + k.R[1] * k.R[1] + k.R[2] * k.R[2]);
+        iD = 1.0 / D;
+    }
     double b[3], d[3], u[3];
     for (int i = 0; i < 3; ++i) {
         n[i] = k.R[i] * iD;
@@ -1090,7 +1098,7 @@ __device__ __forceinline__ void lw_terms_vjp(const Kin &k, double kq, int field_
     const double kappa = 1.0 - nb;
     const double bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
     const double nd = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
-    const double ik = 1.0 / kappa;
+    const double ik = FAST ? recip<double>(kappa) : 1.0 / kappa;
     const double kqD = kq * iD;
     const double phi = kqD * ik;
     const double f = phi * ik * ik;
