@@ -336,6 +336,24 @@ def test_stepped_matches_persistent_through_graph_replays():
     assert (np.abs(a["Ed"] - b["Ed"]) / sc).max() <= 1e-14
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_throughput_layout_close_pairs_match_persistent(precision):
+    """600 pair instances of the pair recipe (log-uniform 1 nm - 1 um, dt = T0/200) on the
+    stepped path: 1,200 targets take its throughput layout, one lane per source for both
+    stage times, with both stages' history rows loaded together. A third of the pairs are
+    closer than c dt, so under the extrapolating policy the end-of-step stage reads past
+    the newest stored sample; the first steps read the static pre-history. 300 steps,
+    against the same instances on the persistent path, to rounding."""
+    w = I.workload_dipole_pairs(n_inst=600, steps=300)
+    sep = np.linalg.norm(w["dipoles"]["origin"][0::2] - w["dipoles"]["origin"][1::2], axis=1)
+    assert (sep < 299792458.0 * w["dt"]).sum() > 100
+    a = gpu_run(w, "extrapolate", stepped_min_n=2, precision=precision)
+    b = gpu_run(w, "extrapolate", stepped_min_n=-1, precision=precision)
+    for k in ("d", "d_dot", "energy"):
+        scale = np.abs(b[k]).max(axis=0, keepdims=True)
+        assert (np.abs(a[k] - b[k]) / scale).max() <= 1e-12, k
+
+
 def moving_workload(n, steps, seed, extra_static_pair=True):
     """A cluster of n dipoles whose origins oscillate (amplitudes 0.1-0.5 nm along seeded
     directions, 10-100 THz, seeded phases; Sec. 4.3), plus a fixed pair as a second
